@@ -1,0 +1,524 @@
+"""Plain FP64 CPU oracle for the robust block LOBPCG of Nottoli, Gianni,
+Levitt and Lipparini, "A robust, open-source implementation of the locally
+optimal block preconditioned conjugate gradient for large eigenvalue problems
+in quantum chemistry" (arXiv:2305.06668).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  It shares no code with
+the GPU library: it uses numpy / scipy (LAPACK, OpenBLAS, scipy.sparse) for
+every step, in float64, in the order the paper states them.
+
+What is computed (paper Sec. 2 and Sec. 3):
+  * ``ortho``          Alg. 2 (Cholesky orthonormalisation with repetition and
+                       a diagonal shift when the factorisation fails, after
+                       Fukaya et al.'s shifted CholeskyQR; Sec. 3.2);
+  * ``ortho_against``  Alg. 3 (project out Y, re-orthonormalise, loop);
+  * ``rayleigh_ritz``  the RR step of Sec. 2 on an orthonormal basis;
+  * ``lobpcg``         Alg. 1 with the orthonormal (X, W, P) basis, P built
+                       implicitly from the RR coefficients (eq. a_block and
+                       neweigv), operator applications reused only through
+                       orthonormal coefficient matrices, and locking
+                       (Sec. 3.1, paragraphs "Basis selection", "Reuse of
+                       applications", "Locking").
+
+Readings taken where the paper is silent or ambiguous (each is also listed in
+the design notes of the repository):
+  R1  Alg. 1 writes the residual with the old iterate right after forming the
+      new one; the residual is taken for the *new* Ritz pairs.
+  R2  The initial RR of Alg. 1 needs an orthonormal X0, so X0 is passed
+      through ``ortho`` first.
+  R3  Alg. 3 is read as a do-while: normalise the columns, always project and
+      orthonormalise once, then test ||Y^T X|| on the orthonormal X.
+  R4  The norms in ||X^T X - I|| and ||Y^T X|| are max-abs entries; pass caps
+      6 (Alg. 2) and 4 (Alg. 3); hitting a cap is counted as "stalled".
+  R5  Shift: eps = 2^-52, ||X|| = ||X||_F = sqrt(trace(X^T X)) taken after
+      column normalisation, sigma = alpha * eps * ||X||_F starting at
+      alpha = 100 and growing 10x per retry, at most 20 retries, then the
+      SVQB orthonormalisation of Stathopoulos and Wu as a last resort.
+  R6  Columns are scaled to unit 2-norm before the first factorisation; a
+      column of exact zeros is replaced by a deterministic SplitMix64 vector.
+  R7  Jacobi preconditioner.  Sec. 2 gives T = (diag(A) - rho I)^-1 as an
+      example for diagonally dominant A.  LOBPCG's convergence theory wants a
+      positive definite T, and from a random start (rho in the middle of the
+      diagonal) the indefinite form stalls, so the default is the absolute
+      value T_j = |diag(A) - theta_j I|^-1, which equals the paper's form
+      wherever diag(A) > theta_j.  The signed form is kept as an option
+      ("diag_signed").  Either way a denominator x with |x| < delta_j =
+      1e-8 max(1, |theta_j|) is replaced by copysign(delta_j, x), sign(0) = +.
+  R8  Locking: m_conv is the number of *leading* columns whose residual
+      2-norm is <= tol, never decreasing; locked columns stay in X and are
+      still rotated by the RR; W and P are built for the active columns only.
+  R9  Convergence is the per-column residual 2-norm ||A x - theta x|| <= tol
+      with ||x|| = 1.  When the RR residuals say "converged", the residual is
+      recomputed from an explicit product A X (the true residual); if that
+      check fails, AX is replaced by the explicit product, P is dropped and
+      the iteration continues.
+  R10 The reduced matrix is symmetrised, a <- (a + a^T) / 2, before eigh.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+EPS = 2.0 ** -52  # double precision unit roundoff used for the shift (R5)
+TAU_ORTHO = 1e-14  # Sec. 4: the only ortho parameter used in all experiments
+SHIFT_ALPHA0 = 100.0  # Sec. 3.2: start at 100 x norm(X) x machine precision
+SHIFT_GROWTH = 10.0  # R5
+SHIFT_RETRIES = 20  # R5
+ORTHO_MAX_PASSES = 6  # R4 (Alg. 2)
+ORTHO_Y_MAX_PASSES = 4  # R4 (Alg. 3)
+PRECOND_GUARD = 1e-8  # R7
+ZERO_COLUMN_SEED = 0x2305066680000000  # R6
+
+Operator = Callable[[np.ndarray], np.ndarray]
+
+
+# ---------------------------------------------------------------------------
+# bookkeeping
+
+
+@dataclasses.dataclass
+class OrthoStats:
+    grams: int = 0  # overlap matrices formed (checks included)
+    factorizations: int = 0  # Cholesky attempts, failed ones included
+    failed_factorizations: int = 0
+    shifted: int = 0  # successful factorisations that needed a shift
+    updates: int = 0  # X <- X L^-T applications
+    ortho_calls: int = 0
+    against_calls: int = 0
+    against_passes: int = 0  # project+ortho passes of Alg. 3
+    stalled: int = 0
+    svqb: int = 0
+    zero_columns: int = 0
+
+    def merge(self, o: "OrthoStats") -> None:
+        for f in dataclasses.fields(self):
+            setattr(self, f.name, getattr(self, f.name) + getattr(o, f.name))
+
+
+class OrthoFailed(RuntimeError):
+    pass
+
+
+# ---------------------------------------------------------------------------
+# a counter-based generator for the zero-column replacement (R6)
+
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 finaliser (Steele, Lea, Flood 2014) on a 64-bit counter."""
+    z = (x + 0x9E3779B97F4A7C15) & _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def splitmix_column(n: int, col: int, seed: int = ZERO_COLUMN_SEED) -> np.ndarray:
+    """Entry i is (splitmix64(seed + col*n + i) >> 11) * 2^-53 - 0.5."""
+    out = np.empty(n, dtype=np.float64)
+    base = seed + col * n
+    for i in range(n):
+        out[i] = (splitmix64((base + i) & _MASK64) >> 11) * (2.0 ** -53) - 0.5
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.2, Alg. 2 and Alg. 3
+
+
+def max_abs(M: np.ndarray) -> float:
+    return float(np.max(np.abs(M))) if M.size else 0.0
+
+
+def normalize_columns(X: np.ndarray, stats: Optional[OrthoStats] = None) -> np.ndarray:
+    """Scale every column to unit 2-norm (R6)."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    norms = np.sqrt(np.einsum("ij,ij->j", X, X))
+    for j in np.nonzero(norms == 0.0)[0]:
+        X[:, j] = splitmix_column(X.shape[0], int(j))
+        norms[j] = math.sqrt(float(X[:, j] @ X[:, j]))
+        if stats is not None:
+            stats.zero_columns += 1
+    return X / norms
+
+
+def _potrf(M: np.ndarray) -> Optional[np.ndarray]:
+    """Lower Cholesky factor, or None when the factorisation breaks down."""
+    try:
+        L = np.linalg.cholesky(M)
+    except np.linalg.LinAlgError:
+        return None
+    if not np.all(np.isfinite(L)):
+        return None
+    return L
+
+
+def shifted_cholesky(M: np.ndarray, stats: OrthoStats) -> Optional[np.ndarray]:
+    """Cholesky of M; on failure add alpha*eps*||X||_F to the diagonal and
+    increase alpha until it succeeds (Sec. 3.2, Alg. 2; reading R5).
+
+    Returns None when every retry failed (the caller then uses SVQB)."""
+    stats.factorizations += 1
+    L = _potrf(M)
+    if L is not None:
+        return L
+    stats.failed_factorizations += 1
+    norm_x = math.sqrt(max(float(np.trace(M)), 0.0))
+    alpha = SHIFT_ALPHA0
+    eye = np.eye(M.shape[0])
+    for _ in range(SHIFT_RETRIES):
+        sigma = alpha * EPS * norm_x
+        stats.factorizations += 1
+        L = _potrf(M + sigma * eye)
+        if L is not None:
+            stats.shifted += 1
+            return L
+        stats.failed_factorizations += 1
+        alpha *= SHIFT_GROWTH
+    return None
+
+
+def svqb(X: np.ndarray, M: np.ndarray, stats: OrthoStats) -> np.ndarray:
+    """Stathopoulos-Wu SVQB: X <- X U Sigma^-1/2 with small eigenvalues of
+    the overlap clamped to eps * max(Sigma); no column is dropped."""
+    stats.svqb += 1
+    s, U = np.linalg.eigh(M)
+    s = np.maximum(s, EPS * max(float(s.max()), 0.0))
+    if not np.all(s > 0.0):
+        raise OrthoFailed("overlap matrix has no positive eigenvalue")
+    return (X @ U) / np.sqrt(s)
+
+
+def ortho(
+    X: np.ndarray,
+    tau: float = TAU_ORTHO,
+    stats: Optional[OrthoStats] = None,
+    max_passes: int = ORTHO_MAX_PASSES,
+) -> np.ndarray:
+    """Alg. 2: while ||X^T X - I|| > tau, factor M = X^T X = L L^T (shifting
+    the diagonal when the factorisation fails) and set X <- X L^-T."""
+    st = stats if stats is not None else OrthoStats()
+    st.ortho_calls += 1
+    X = normalize_columns(X, st)
+    if X.shape[1] == 0:
+        return X
+    eye = np.eye(X.shape[1])
+    for p in range(max_passes):
+        M = X.T @ X
+        M = 0.5 * (M + M.T)
+        st.grams += 1
+        if max_abs(M - eye) <= tau:
+            return X
+        if p == max_passes - 1:
+            st.stalled += 1
+            return X
+        L = shifted_cholesky(M, st)
+        if L is None:
+            X = svqb(X, M, st)
+        else:
+            # X L^-T  ==  (L^-1 X^T)^T
+            X = sla.solve_triangular(L, X.T, lower=True, check_finite=False).T
+        st.updates += 1
+    return X
+
+
+def ortho_against(
+    X: np.ndarray,
+    Y: np.ndarray,
+    tau: float = TAU_ORTHO,
+    stats: Optional[OrthoStats] = None,
+    max_passes: int = ORTHO_Y_MAX_PASSES,
+) -> np.ndarray:
+    """Alg. 3 (reading R3): X <- X - Y (Y^T X); X <- ortho(X); repeat until
+    ||Y^T X|| <= tau.  Y must have orthonormal columns."""
+    st = stats if stats is not None else OrthoStats()
+    st.against_calls += 1
+    X = normalize_columns(X, st)
+    if Y is None or Y.shape[1] == 0:
+        return ortho(X, tau, st)
+    C = Y.T @ X
+    for p in range(max_passes):
+        st.against_passes += 1
+        X = X - Y @ C
+        X = ortho(X, tau, st)
+        C = Y.T @ X
+        if max_abs(C) <= tau:
+            return X
+    st.stalled += 1
+    return X
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2: Rayleigh-Ritz, residuals, the Jacobi preconditioner
+
+
+def symmetrize(a: np.ndarray) -> np.ndarray:
+    return 0.5 * (a + a.T)
+
+
+def rayleigh_ritz(V: np.ndarray, AV: np.ndarray):
+    """RR on an orthonormal basis V: eigen-decompose a = V^T A V (R10);
+    returns all Ritz values (ascending) and the coefficient matrix."""
+    a = symmetrize(V.T @ AV)
+    theta, U = np.linalg.eigh(a)
+    return theta, U
+
+
+def precondition_diag(
+    R: np.ndarray, diag: np.ndarray, theta: np.ndarray, signed: bool = False
+) -> np.ndarray:
+    """W~[:, j] = R[:, j] / g(|diag - theta_j|)  (Sec. 2, reading R7);
+    ``signed=True`` drops the absolute value (the paper's literal example)."""
+    out = np.empty_like(R)
+    for j in range(R.shape[1]):
+        delta = PRECOND_GUARD * max(1.0, abs(float(theta[j])))
+        den = diag - theta[j]
+        if not signed:
+            den = np.abs(den)
+        small = np.abs(den) < delta
+        den = np.where(small, np.where(den < 0.0, -delta, delta), den)
+        out[:, j] = R[:, j] / den
+    return out
+
+
+def ritz_residual(AX: np.ndarray, X: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    """R = A X - X diag(theta) for Ritz pairs (Sec. 2, reading R1)."""
+    return AX - X * theta
+
+
+def leading_converged(rnorm: np.ndarray, tol: float) -> int:
+    c = 0
+    for r in rnorm:
+        if r <= tol:
+            c += 1
+        else:
+            break
+    return c
+
+
+def true_residuals(op: Operator, X: np.ndarray):
+    """Explicit A X, Rayleigh quotients x^T A x / x^T x and residual 2-norms."""
+    AX = op(X)
+    xx = np.einsum("ij,ij->j", X, X)
+    theta = np.einsum("ij,ij->j", X, AX) / xx
+    R = AX - X * theta
+    return theta, np.linalg.norm(R, axis=0), AX
+
+
+def normalize_signs(X: np.ndarray) -> np.ndarray:
+    """Largest-|.| entry of each column made positive (first index on ties)."""
+    X = np.array(X, copy=True)
+    for j in range(X.shape[1]):
+        i = int(np.argmax(np.abs(X[:, j])))
+        if X[i, j] < 0:
+            X[:, j] = -X[:, j]
+    return X
+
+
+# ---------------------------------------------------------------------------
+# operators (the paper's method is matrix-free; these are its inputs)
+
+
+def csr_operator(row_ptr, col, val, n: int) -> Operator:
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix((np.asarray(val, np.float64), np.asarray(col), np.asarray(row_ptr)), shape=(n, n))
+
+    def apply(X):
+        return np.asarray(A @ X)
+
+    return apply
+
+
+def dense_operator(A: np.ndarray) -> Operator:
+    def apply(X):
+        return A @ X
+
+    return apply
+
+
+def kronsum_operator(A: np.ndarray, V: np.ndarray) -> Operator:
+    """H = A (x) I + I (x) A + diag(vec V) on row-major vectorised na x na
+    blocks: H vec(Z) = vec(A Z + Z A + V o Z)."""
+    na = A.shape[0]
+
+    def apply(X):
+        out = np.empty_like(X)
+        for b in range(X.shape[1]):
+            Z = X[:, b].reshape(na, na)
+            out[:, b] = (A @ Z + Z @ A + V * Z).reshape(-1)
+        return out
+
+    return apply
+
+
+def kronsum_diagonal(A: np.ndarray, V: np.ndarray) -> np.ndarray:
+    d = np.diag(A)
+    return (d[:, None] + d[None, :] + V).reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# Alg. 1
+
+
+@dataclasses.dataclass
+class LobpcgResult:
+    evals: np.ndarray
+    evecs: np.ndarray
+    resnorms: np.ndarray  # true residual 2-norms of the returned pairs
+    converged: bool
+    iterations: int
+    matvec_columns: int
+    ortho: OrthoStats
+    history_theta: list  # Ritz values (first m) after every RR
+    history_resid: list  # RR residual norms (all m) after every RR
+    history_active: list  # m_act used for the matvec of every iteration
+    true_checks: int
+    rms: np.ndarray  # ||r||_2 / sqrt(n), the paper's RMS measure
+    maxabs: np.ndarray  # max |r_i|, the paper's second measure
+    X_all: np.ndarray = None  # the whole final block
+    theta_all: np.ndarray = None
+
+
+def lobpcg(
+    op: Operator,
+    X0: np.ndarray,
+    k: int,
+    tol: float = 1e-8,
+    diag: Optional[np.ndarray] = None,
+    precond: str = "diag",
+    tau: float = TAU_ORTHO,
+    max_iter: int = 1000,
+    callback: Optional[Callable[[dict], None]] = None,
+) -> LobpcgResult:
+    """Alg. 1: the lowest k eigenpairs of the symmetric operator ``op``.
+
+    X0 is the n x m initial block (m >= k, the block may hold extra vectors,
+    Sec. 2).  ``precond`` is "diag" (|Jacobi|, needs ``diag``),
+    "diag_signed" (the paper's signed Jacobi) or "none"."""
+    X0 = np.asarray(X0, dtype=np.float64)
+    n, m = X0.shape
+    if not (1 <= k <= m):
+        raise ValueError("need 1 <= k <= block size")
+    if precond.startswith("diag") and diag is None:
+        raise ValueError("the Jacobi preconditioner needs diag(A)")
+    st = OrthoStats()
+    hist_theta, hist_resid, hist_active = [], [], []
+    matvecs = 0
+    true_checks = 0
+
+    def tprec(R, theta):
+        if precond == "diag":
+            return precondition_diag(R, diag, theta)
+        if precond == "diag_signed":
+            return precondition_diag(R, diag, theta, signed=True)
+        if precond == "none":
+            return R.copy()
+        raise ValueError(precond)
+
+    # Alg. 1 initial Rayleigh-Ritz (reading R2: orthonormalise X0 first)
+    X = ortho(X0, tau, st)
+    AX = op(X)
+    matvecs += m
+    theta_all, U = rayleigh_ritz(X, AX)
+    X = X @ U
+    AX = AX @ U
+    theta = theta_all[:m]
+    R = ritz_residual(AX, X, theta)  # reading R1
+    rnorm = np.linalg.norm(R, axis=0)
+    hist_theta.append(theta.copy())
+    hist_resid.append(rnorm.copy())
+    m_conv = 0
+    P = AP = None
+    it = 0
+    converged = False
+    while True:
+        m_conv = max(m_conv, leading_converged(rnorm, tol))  # reading R8
+        if m_conv >= k:
+            # reading R9: judge with the true residual of an explicit product
+            true_checks += 1
+            th_t, r_t, AX_t = true_residuals(op, X)
+            matvecs += m
+            if float(np.max(r_t[:k])) <= tol:
+                converged = True
+                break
+            AX = AX_t
+            theta = th_t
+            R = ritz_residual(AX, X, theta)
+            rnorm = np.linalg.norm(R, axis=0)
+            m_conv = leading_converged(rnorm, tol)
+            P = AP = None
+            if m_conv >= k:
+                converged = True
+                break
+        if it >= max_iter:
+            break
+        it += 1
+        act = np.arange(m_conv, m)
+        # Alg. 1: preconditioned residuals, orthogonalised against (X, P)
+        Wt = tprec(R[:, act], theta[act])
+        Y = X if P is None else np.hstack([X, P])
+        W = ortho_against(Wt, Y, tau, st)
+        AW = op(W)
+        matvecs += W.shape[1]
+        hist_active.append(W.shape[1])
+        if P is None:
+            V = np.hstack([X, W])
+            AV = np.hstack([AX, AW])
+        else:
+            V = np.hstack([X, W, P])
+            AV = np.hstack([AX, AW, AP])
+        # Rayleigh-Ritz in V
+        theta_all, U = rayleigh_ritz(V, AV)
+        ux = U[:, :m]
+        theta = theta_all[:m]
+        # eq. neweigv and "Reuse of applications": X and AX through u_x
+        Xn = V @ ux
+        AXn = AV @ ux
+        R = ritz_residual(AXn, Xn, theta)  # reading R1
+        rnorm = np.linalg.norm(R, axis=0)
+        hist_theta.append(theta.copy())
+        hist_resid.append(rnorm.copy())
+        if callback is not None:
+            callback(dict(it=it, theta=theta, rnorm=rnorm, m_conv=m_conv, X=Xn, AX=AXn))
+        m_conv = max(m_conv, leading_converged(rnorm, tol))
+        act = np.arange(m_conv, m)
+        if m_conv < k:
+            # P from u_x: subtract the identity on the X block from the
+            # unconverged columns, orthonormalise against u_x in R^p, and
+            # rotate V and AV with the orthonormal u_p
+            p = V.shape[1]
+            up_t = ux[:, act].copy()
+            up_t[act, np.arange(act.size)] -= 1.0
+            up = ortho_against(up_t, ux, tau, st)
+            P = V @ up
+            AP = AV @ up
+        X, AX = Xn, AXn
+
+    if not converged:
+        true_checks += 1
+        th_t, r_t, AX_t = true_residuals(op, X)
+    Rt = AX_t[:, :k] - X[:, :k] * th_t[:k]
+    res = LobpcgResult(
+        evals=th_t[:k].copy(),
+        evecs=normalize_signs(X[:, :k]),
+        resnorms=r_t[:k].copy(),
+        converged=converged,
+        iterations=it,
+        matvec_columns=matvecs,
+        ortho=st,
+        history_theta=hist_theta,
+        history_resid=hist_resid,
+        history_active=hist_active,
+        true_checks=true_checks,
+        rms=r_t[:k] / math.sqrt(n),
+        maxabs=np.max(np.abs(Rt), axis=0),
+        X_all=X,
+        theta_all=th_t,
+    )
+    return res

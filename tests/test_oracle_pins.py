@@ -1,0 +1,445 @@
+"""Pins for the CPU oracle: each test checks the oracle against something other
+than itself -- a library special case, a closed form, brute force on a tiny
+input, an invariant the mathematics fixes, or a value the paper states.
+
+The ``test_planted_*`` tests plant a plausible mistake in the oracle (on the
+CPU) and show that one of the pins catches it.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import lobpcg_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def graded(n, m, cond, seed):
+    """n x m matrix with singular values logspaced over [1/cond, 1]."""
+    g = synth.rng(seed)
+    U, _ = np.linalg.qr(g.standard_normal((n, m)))
+    V, _ = np.linalg.qr(g.standard_normal((m, m)))
+    s = np.logspace(0, -math.log10(cond), m)
+    return (U * s) @ V.T
+
+
+def householder_q(X):
+    Q, R = np.linalg.qr(X)
+    return Q * np.sign(np.diag(R))
+
+
+def projector_distance(A, B):
+    """|| P_A - P_B ||_2 for column spaces (sine of largest principal angle)."""
+    QA = np.linalg.qr(A)[0]
+    QB = np.linalg.qr(B)[0]
+    return float(np.linalg.norm(QA @ QA.T - QB @ QB.T, 2))
+
+
+# ---------------------------------------------------------------------------
+# paper-stated constants
+
+
+def test_paper_constants():
+    c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    assert O.TAU_ORTHO == c["tau_ortho"]["value"]
+    assert O.SHIFT_ALPHA0 == c["shift_alpha0"]["value"]
+
+
+def test_splitmix64_published_sequence():
+    # SplitMix64 seeded with 0: the first three outputs of the reference
+    # generator (Steele, Lea, Flood 2014; also Vigna's splitmix64.c).
+    gamma = 0x9E3779B97F4A7C15
+    assert O.splitmix64(0) == 0xE220A8397B1DCDAF
+    assert O.splitmix64(gamma) == 0x6E789E6AA1B965F4
+    assert O.splitmix64((2 * gamma) % (1 << 64)) == 0x06C45D188009454F
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2: ortho(X)
+
+
+def check_ortho_vs_qr(ortho_fn):
+    worst = 0.0
+    for seed, cond in [(1, 10.0), (2, 1e3), (3, 1e3)]:
+        X = graded(400, 8, cond, seed) * synth.rng(seed + 10).uniform(0.5, 50, 8)
+        Q = ortho_fn(X)
+        worst = max(worst, float(np.max(np.abs(Q - householder_q(X)))))
+    return worst
+
+
+def test_ortho_equals_householder_q():
+    # Without a shift, Cholesky QR and Householder QR give the same Q once
+    # R has a positive diagonal (a library special case of Alg. 2).
+    assert check_ortho_vs_qr(O.ortho) < 1e-12
+
+
+@pytest.mark.parametrize("cond", [1.0, 1e4, 1e7])
+def test_ortho_orthonormal(cond):
+    st = O.OrthoStats()
+    Q = O.ortho(graded(1000, 12, cond, 7), stats=st)
+    assert O.max_abs(Q.T @ Q - np.eye(12)) <= O.TAU_ORTHO
+    assert st.stalled == 0
+
+
+def test_cholesky_breakdown_near_1e8():
+    # Sec. 3.2: the unshifted factorisation of the overlap fails once
+    # cond(X) is past ~1e8; well below it, it succeeds.
+    c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    edge = c["cholesky_breakdown_condition"]["value"]
+    ok = O._potrf(O.normalize_columns(graded(500, 6, edge / 1e3, 3)).T @ O.normalize_columns(graded(500, 6, edge / 1e3, 3)))
+    assert ok is not None
+    fails = 0
+    for seed in range(5):
+        X = O.normalize_columns(graded(500, 6, edge * 1e3, seed))
+        if O._potrf(X.T @ X) is None:
+            fails += 1
+    assert fails >= 4
+
+
+def test_ortho_forced_shift_at_most_four_factorizations():
+    # Columns [x, x + 1e-10 y, z...]: cond ~ 1e10, the first Cholesky must
+    # fail; Sec. 3.2 says one failed + one shifted + two unshifted suffice.
+    g = synth.rng(5)
+    x, y = g.standard_normal(800), g.standard_normal(800)
+    Z = g.standard_normal((800, 3))
+    X = np.column_stack([x, x + 1e-10 * y, Z])
+    st = O.OrthoStats()
+    Q = O.ortho(X, stats=st)
+    c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    assert st.failed_factorizations >= 1
+    assert st.shifted == 1
+    assert st.factorizations <= c["max_cholesky_factorizations"]["value"]
+    assert O.max_abs(Q.T @ Q - np.eye(5)) <= O.TAU_ORTHO
+    # the span keeps x, the part of y that survived rounding, and Z
+    assert projector_distance(Q, np.column_stack([x, y, Z])) < 1e-5
+
+
+def test_shift_value_is_alpha_eps_normX():
+    # Force a failure and read the shift back from L L^T - M (Alg. 2).
+    X = O.normalize_columns(np.column_stack([np.ones(50), np.ones(50), np.arange(50.0)]))
+    M = X.T @ X
+    st = O.OrthoStats()
+    L = O.shifted_cholesky(M, st)
+    assert st.failed_factorizations >= 1 and L is not None
+    sigma = np.diag(L @ L.T - M).mean()
+    k = st.factorizations - 2  # retries before the successful one
+    expected = O.SHIFT_ALPHA0 * (O.SHIFT_GROWTH ** k) * O.EPS * math.sqrt(np.trace(M))
+    # rounding in M + sigma I leaves sigma known to ~1e-16 absolute; a wrong
+    # alpha (10x off) or norm (||X||^2 vs ||X||) would miss by far more
+    assert abs(sigma - expected) <= 0.02 * expected
+
+
+def test_zero_column_replaced():
+    X = np.zeros((64, 3))
+    X[:, 0] = 1.0
+    X[:, 2] = np.arange(64.0)
+    st = O.OrthoStats()
+    Q = O.ortho(X, stats=st)
+    assert st.zero_columns == 1
+    assert O.max_abs(Q.T @ Q - np.eye(3)) <= O.TAU_ORTHO
+
+
+# ---------------------------------------------------------------------------
+# Alg. 3: ortho(X, Y)
+
+
+def check_ortho_against(fn):
+    g = synth.rng(11)
+    n = 600
+    Y = np.linalg.qr(g.standard_normal((n, 6)))[0]
+    Xt = Y @ g.standard_normal((6, 4)) + 1e-10 * g.standard_normal((n, 4))
+    st = O.OrthoStats()
+    Q = fn(Xt, Y, stats=st)
+    return Y, Xt, Q, st
+
+
+def test_ortho_against_pins():
+    Y, Xt, Q, st = check_ortho_against(O.ortho_against)
+    assert O.max_abs(Y.T @ Q) <= O.TAU_ORTHO
+    assert O.max_abs(Q.T @ Q - np.eye(4)) <= O.TAU_ORTHO
+    # span([Y Q]) == span([Y X~]) up to what rounding left of the 1e-10 part
+    assert projector_distance(np.hstack([Y, Q]), np.hstack([Y, Xt])) < 1e-5
+    # Sec. 3.2: about two passes are usually enough
+    assert st.against_passes <= 3
+
+
+def test_ortho_against_single_projection_is_not_enough():
+    # The paper's argument for the loop: one projection + ortho leaves
+    # Y^T Q of order eps/delta.  Check the oracle really needed > 1 pass.
+    Y, Xt, Q, st = check_ortho_against(O.ortho_against)
+    one = O.ortho(Xt - Y @ (Y.T @ Xt))
+    assert O.max_abs(Y.T @ one) > 1e3 * O.TAU_ORTHO
+    assert st.against_passes >= 2
+
+
+# ---------------------------------------------------------------------------
+# Rayleigh-Ritz and the preconditioner
+
+
+def test_rayleigh_ritz_interlacing():
+    A = synth.random_symmetric(300, 4)
+    lam = np.linalg.eigvalsh(A)
+    V = np.linalg.qr(synth.rng(5).standard_normal((300, 12)))[0]
+    theta, U = O.rayleigh_ritz(V, A @ V)
+    # Cauchy interlacing: lam_j <= theta_j <= lam_{n-p+j}
+    assert np.all(theta >= lam[:12] - 1e-12)
+    assert np.all(theta <= lam[-12:] + 1e-12)
+    assert np.all(np.diff(theta) >= 0)
+    # U diagonalises the projected matrix
+    a = V.T @ A @ V
+    assert np.allclose(U.T @ (0.5 * (a + a.T)) @ U, np.diag(theta), atol=1e-12)
+
+
+def test_preconditioner_guard_by_hand():
+    R = np.array([[1.0, 2.0], [1.0, 2.0], [1.0, 2.0]])
+    d = np.array([3.0, 1.0, 1.0 + 5e-9])
+    theta = np.array([1.0, 2.0])
+    W = O.precondition_diag(R, d, theta)
+    # column 0: |3-1| = 2; |0| -> guard 1e-8 (positive); |5e-9| -> 1e-8
+    assert np.allclose(W[:, 0], [0.5, 1e8, 1e8], rtol=1e-15)
+    # column 1: |3-2| = 1, |1-2| = 1, |1+5e-9-2| ~ 1
+    assert np.allclose(W[:, 1], [2.0, 2.0, 2.0 / (1.0 - 5e-9)], rtol=1e-15)
+    Ws = O.precondition_diag(R, d, theta, signed=True)
+    assert np.allclose(Ws[:, 1], [2.0, -2.0, -2.0 / (1.0 - 5e-9)], rtol=1e-15)
+    assert Ws[1, 0] == 1e8  # sign(0) taken as +
+
+
+# ---------------------------------------------------------------------------
+# full solves against closed forms and brute force
+
+
+def assert_eigs(res, lam, tol=1e-8, rel=1e-9):
+    assert res.converged
+    assert np.all(res.resnorms <= tol)
+    scale = np.maximum(np.abs(lam), 1e-3 * max(1.0, float(np.max(np.abs(lam)))))
+    assert np.all(np.abs(res.evals - lam) <= rel * scale), (res.evals, lam)
+
+
+def test_closed_form_laplacian_1d():
+    n, k = 120, 4
+    L = synth.laplacian_1d(n)
+    op = O.csr_operator(L.row_ptr, L.col, L.val, n)
+    res = O.lobpcg(op, synth.start_block(n, 6, 1), k, 1e-9, diag=L.diag, max_iter=2000)
+    j = np.arange(1, k + 1)
+    lam = 2.0 - 2.0 * np.cos(j * np.pi / (n + 1))
+    assert_eigs(res, lam, tol=1e-9)
+    # eigenvectors sin(i j pi/(n+1)) (up to sign)
+    i = np.arange(1, n + 1)[:, None]
+    ex = np.sin(i * j[None, :] * np.pi / (n + 1))
+    ex /= np.linalg.norm(ex, axis=0)
+    assert np.all(np.abs(np.abs(np.sum(ex * res.evecs, axis=0)) - 1.0) < 1e-8)
+
+
+def test_closed_form_diagonal():
+    d = synth.rng(3).permutation(np.linspace(1.0, 9.0, 150))
+    A = np.diag(d)
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(150, 5, 2), 5, 1e-9, diag=d)
+    lam = np.sort(d)[:5]
+    assert_eigs(res, lam, tol=1e-9)
+    idx = np.argsort(d)[:5]
+    for c in range(5):
+        e = np.zeros(150)
+        e[idx[c]] = 1.0
+        assert np.allclose(res.evecs[:, c], e, atol=1e-8)
+
+
+def test_closed_form_kronsum():
+    na = 24
+    A, _ = synth.kronsum(na=na, seed=9)
+    V = np.zeros((na, na))
+    alpha = np.linalg.eigvalsh(A)
+    sums = np.sort((alpha[:, None] + alpha[None, :]).reshape(-1))
+    k = 6
+    assert sums[k] - sums[k - 1] > 1e-6  # the block does not cut a cluster
+    op = O.kronsum_operator(A, V)
+    res = O.lobpcg(op, synth.start_block(na * na, k, 3), k, 1e-9, diag=O.kronsum_diagonal(A, V))
+    assert_eigs(res, sums[:k], tol=1e-9)
+
+
+def test_kronsum_operator_matches_kron():
+    na = 5
+    A, V = synth.kronsum(na=na, seed=2)
+    H = np.kron(A, np.eye(na)) + np.kron(np.eye(na), A) + np.diag(V.reshape(-1))
+    X = synth.start_block(na * na, 3, 1)
+    assert np.allclose(O.kronsum_operator(A, V)(X), H @ X, atol=1e-13)
+    assert np.allclose(O.kronsum_diagonal(A, V), np.diag(H), atol=1e-15)
+
+
+@pytest.mark.parametrize(
+    "kind",
+    ["random", "clustered", "degenerate"],
+)
+def test_brute_force_dense(kind):
+    n = 160
+    if kind == "random":
+        A = synth.random_symmetric(n, 21)
+    elif kind == "clustered":
+        lam = np.concatenate([[1.0, 1.0 + 1e-6, 1.0 + 2e-6, 2.0], np.linspace(3.0, 10.0, n - 4)])
+        A, _ = synth.prescribed_spectrum(lam, 22)
+    else:
+        lam = np.concatenate([[-1.0, 0.5, 0.5, 2.0], np.linspace(3.0, 10.0, n - 4)])
+        A, _ = synth.prescribed_spectrum(lam, 23)
+    k = 4
+    w, Vx = np.linalg.eigh(A)
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(n, k, 5), k, 1e-9, diag=np.diag(A).copy(), max_iter=3000)
+    assert_eigs(res, w[:k], tol=1e-9)
+    # spectral projector of the whole computed block vs brute force
+    assert projector_distance(res.evecs, Vx[:, :k]) < 1e-6
+
+
+def test_invariants_and_ritz_monotone():
+    n, m = 400, 6
+    A = synth.dense_dd(n, seed=77)
+    lam = np.linalg.eigvalsh(A)
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(n, m, 8), m, 1e-9, diag=np.diag(A).copy())
+    assert res.converged
+    X = res.X_all
+    assert O.max_abs(X.T @ X - np.eye(m)) < 1e-12
+    H = np.array(res.history_theta)
+    # X^(k) is inside the next subspace, so Ritz values never increase
+    assert np.all(np.diff(H, axis=0) <= 10 * np.finfo(float).eps * np.abs(lam).max())
+    # Courant-Fischer: theta_j >= lambda_j at every iteration
+    assert np.all(H >= lam[:m] - 1e-12)
+    assert np.all(np.diff(res.evals) >= 0)
+
+
+def test_reuse_keeps_ax_accurate():
+    # Sec. 3.1 "Reuse of applications": AX reached through orthonormal
+    # coefficients only stays within a few ulps of an explicit A X.
+    n, m = 300, 4
+    A = synth.dense_dd(n, seed=5)
+    normA = np.abs(A).sum(1).max()
+    worst = []
+
+    def cb(d):
+        worst.append(O.max_abs(d["AX"] - A @ d["X"]))
+
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(n, m, 1), m, 1e-10, diag=np.diag(A).copy(), callback=cb)
+    assert res.converged and len(worst) > 5
+    assert max(worst) <= 1e3 * np.finfo(float).eps * normA
+
+
+def test_locking_matvec_count():
+    # Widely separated leading eigenvalues converge one after another.
+    n, m = 200, 4
+    d = np.concatenate([[1.0, 2.0, 4.0, 8.0], np.linspace(20.0, 40.0, n - 4)])
+    A = np.diag(d) + 1e-3 * synth.random_symmetric(n, 3)
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(n, m, 4), m, 1e-9, diag=np.diag(A).copy())
+    assert res.converged
+    act = res.history_active
+    assert all(a >= b for a, b in zip(act, act[1:]))  # m_conv never decreases
+    assert min(act) < m  # locking happened
+    assert res.matvec_columns == m + sum(act) + m * res.true_checks
+
+
+def test_extra_block_vectors():
+    n = 300
+    A = synth.dense_dd(n, seed=31)
+    lam = np.linalg.eigvalsh(A)
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(n, 6, 2), 2, 1e-9, diag=np.diag(A).copy())
+    assert_eigs(res, lam[:2], tol=1e-9)
+    assert res.evecs.shape == (n, 2)
+
+
+def test_max_iter_reports_not_converged():
+    A = synth.dense_dd(300, seed=31)
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(300, 4, 2), 4, 1e-12, diag=np.diag(A).copy(), max_iter=2)
+    assert not res.converged
+    assert res.iterations == 2
+    assert np.all(np.isfinite(res.evals)) and np.all(res.resnorms > 0)
+
+
+def test_signed_preconditioner_also_converges_from_unit_guess():
+    n, m = 400, 4
+    A = synth.dense_dd(n, seed=12)
+    d = np.diag(A).copy()
+    X0 = np.zeros((n, m))
+    X0[np.argsort(d)[:m], np.arange(m)] = 1.0
+    X0 += 1e-3 * synth.start_block(n, m, 1)
+    res = O.lobpcg(O.dense_operator(A), X0, m, 1e-9, diag=d, precond="diag_signed")
+    assert_eigs(res, np.linalg.eigvalsh(A)[:m], tol=1e-9)
+
+
+def test_output_signs_normalised():
+    A = synth.dense_dd(200, seed=2)
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(200, 3, 9), 3, 1e-9, diag=np.diag(A).copy())
+    for j in range(3):
+        i = np.argmax(np.abs(res.evecs[:, j]))
+        assert res.evecs[i, j] > 0
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes (in the oracle, on the CPU): the pins above must catch them
+
+
+def test_planted_transposed_triangular_factor():
+    def bad_ortho(X):
+        X = O.normalize_columns(X)
+        for _ in range(3):
+            M = X.T @ X
+            L = np.linalg.cholesky(M)
+            X = X @ np.linalg.inv(L)  # should be L^-T
+        return X
+
+    try:
+        worst = check_ortho_vs_qr(bad_ortho)
+    except np.linalg.LinAlgError:
+        worst = np.inf
+    assert worst > 1e-6
+
+
+def test_planted_missing_projection():
+    def bad_against(X, Y, stats=None):
+        return O.ortho(X, stats=stats)
+
+    Y, Xt, Q, st = check_ortho_against(bad_against)
+    assert O.max_abs(Y.T @ Q) > O.TAU_ORTHO
+
+
+def test_planted_residual_sign_error(monkeypatch):
+    monkeypatch.setattr(O, "ritz_residual", lambda AX, X, th: AX + X * th)
+    A = synth.dense_dd(150, seed=1)
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(150, 3, 1), 3, 1e-9, diag=np.diag(A).copy(), max_iter=60)
+    with pytest.raises(AssertionError):
+        assert_eigs(res, np.linalg.eigvalsh(A)[:3], tol=1e-9)
+
+
+def test_planted_wrong_end_of_spectrum(monkeypatch):
+    def rr_top(V, AV):
+        th, U = np.linalg.eigh(O.symmetrize(V.T @ AV))
+        return th[::-1].copy(), U[:, ::-1].copy()
+
+    monkeypatch.setattr(O, "rayleigh_ritz", rr_top)
+    A = synth.dense_dd(150, seed=1)
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(150, 3, 1), 3, 1e-9, diag=np.diag(A).copy(), max_iter=60)
+    with pytest.raises(AssertionError):
+        assert_eigs(res, np.linalg.eigvalsh(A)[:3], tol=1e-9)
+
+
+def run_invariants(A, m, seed):
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(A.shape[0], m, seed), m, 1e-9, diag=np.diag(A).copy(), max_iter=200)
+    X = res.X_all
+    assert res.converged
+    assert O.max_abs(X.T @ X - np.eye(m)) < 1e-12
+
+
+def test_planted_unorthogonalised_p(monkeypatch):
+    # u_p used without its ortho against u_x: V is no longer orthonormal and
+    # the standard RR is invalid; the invariants catch it.
+    A = synth.dense_dd(300, seed=6)
+    run_invariants(A, 4, 1)
+    orig = O.ortho_against
+
+    def skip_small(X, Y, tau=O.TAU_ORTHO, stats=None, max_passes=O.ORTHO_Y_MAX_PASSES):
+        if Y is not None and Y.shape[0] < 100:  # the R^p call that builds u_p
+            return O.normalize_columns(X)
+        return orig(X, Y, tau, stats, max_passes)
+
+    monkeypatch.setattr(O, "ortho_against", skip_small)
+    with pytest.raises(AssertionError):
+        run_invariants(A, 4, 1)
