@@ -1,0 +1,241 @@
+/*
+ * lobpcg.h -- C ABI of an MI355X (gfx950) block LOBPCG eigensolver.
+ *
+ * Method: Nottoli, Gianni, Levitt, Lipparini, "A robust, open-source
+ * implementation of the locally optimal block preconditioned conjugate
+ * gradient for large eigenvalue problems in quantum chemistry",
+ * arXiv:2305.06668.  The problem (Sec. 2): for a real symmetric A of order n,
+ * find the m << n lowest eigenpairs.  Alg. 1 gives the iteration; Alg. 2 and
+ * Alg. 3 the Cholesky-based orthonormalisations it relies on (Sec. 3.2).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns an int status (LOBPCG_OK = 0, >0 warnings, <0
+ *    errors); nothing is thrown across this boundary.  A per-handle message
+ *    for the last error is available from lobpcg_last_error().
+ *  - Blocks of vectors are ROW-MAJOR: an n x c block with leading dimension
+ *    ld >= c stores entry (i, j) at ptr[i * ld + j].  Small matrices are
+ *    row-major and dense (ld = number of columns).
+ *  - "device" pointers are HIP device memory on the handle's device, owned by
+ *    the caller, and must stay valid until the handle is destroyed or the
+ *    setter is called again.  "host" pointers are ordinary host memory.
+ *  - All device work runs on the handle's stream (lobpcg_set_stream; the
+ *    null stream by default).  Entry points that return host data synchronise
+ *    that stream before returning; the step entry points (lobpcg_apply_operator,
+ *    lobpcg_gram, ...) are asynchronous unless stated otherwise.
+ *  - Device scratch comes from a caller-provided workspace
+ *    (lobpcg_workspace_size / lobpcg_set_workspace); the library itself only
+ *    allocates a few KB of pinned host memory for read-backs.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LOBPCG_MI355X_H
+#define LOBPCG_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lobpcg_ctx* lobpcg_t;
+
+/* ---- status codes ------------------------------------------------------ */
+#define LOBPCG_OK 0
+#define LOBPCG_NOT_CONVERGED 1     /* max_iter reached; results are readable */
+#define LOBPCG_ERR_INVALID_ARG -1
+#define LOBPCG_ERR_BAD_STATE -2    /* call order violated (e.g. solve before set_operator) */
+#define LOBPCG_ERR_DEVICE -3       /* a HIP runtime call failed */
+#define LOBPCG_ERR_WORKSPACE -4    /* no workspace, or smaller than lobpcg_workspace_size */
+#define LOBPCG_ERR_ORTHO_FAILED -5 /* shifted Cholesky and SVQB both failed */
+#define LOBPCG_ERR_NONFINITE -6    /* NaN or Inf met in residuals or overlaps */
+#define LOBPCG_ERR_UNSUPPORTED -7  /* size or mode outside what this build implements */
+
+/* ---- preconditioners (Sec. 2, T in w = T r) ---------------------------- */
+#define LOBPCG_PRECOND_NONE 0        /* T = I */
+#define LOBPCG_PRECOND_DIAG 1        /* T_j = |diag(A) - theta_j I|^-1 (default) */
+#define LOBPCG_PRECOND_DIAG_SIGNED 2 /* T_j = (diag(A) - theta_j I)^-1, Sec. 2's example */
+
+/* ---- precision modes --------------------------------------------------- */
+#define LOBPCG_PREC_FP64 0 /* every step in fp64 */
+#define LOBPCG_PREC_FP32 1 /* operator, Grams and blocks in fp32 until the
+                              residual nears the fp32 floor, then fp64 */
+
+/* ---- option keys for lobpcg_set_option --------------------------------- */
+#define LOBPCG_OPT_TAU_ORTHO 0        /* ortho threshold, default 1e-14 (Sec. 4) */
+#define LOBPCG_OPT_MAX_ITER 1         /* default 1000 */
+#define LOBPCG_OPT_PRECISION 2        /* LOBPCG_PREC_*, default FP64 */
+#define LOBPCG_OPT_ORTHO_MAX_PASSES 3 /* Alg. 2 overlap evaluations, default 6 */
+#define LOBPCG_OPT_ORTHO_Y_MAX_PASSES 4 /* Alg. 3 passes, default 4 */
+#define LOBPCG_OPT_TRACE 5            /* 1: time phases with HIP events */
+
+/* ---- statistics --------------------------------------------------------- */
+typedef struct lobpcg_stats {
+  int32_t iterations;          /* Alg. 1 loop iterations */
+  int32_t converged;           /* 1 when all k pairs met tol on the true residual */
+  int64_t matvec_columns;      /* columns the operator was applied to */
+  int32_t ortho_grams;         /* overlap matrices formed in ortho calls */
+  int32_t ortho_factorizations;/* Cholesky attempts (failed ones included) */
+  int32_t ortho_failed;        /* failed Cholesky attempts */
+  int32_t ortho_shifted;       /* factorizations that needed the diagonal shift */
+  int32_t ortho_stalled;       /* ortho loops stopped at their pass cap */
+  int32_t ortho_svqb;          /* SVQB fallbacks */
+  int32_t against_passes;      /* Alg. 3 project+ortho passes */
+  int32_t true_checks;         /* explicit A X residual checks */
+  int32_t relocks;             /* iterations where locking changed the active set */
+  int32_t precision_switch_iter; /* iteration of the fp32 -> fp64 switch, -1 if none */
+  int32_t m_conv;              /* locked (converged) leading columns */
+  double ms_total;             /* wall time of lobpcg_solve */
+  double ms_operator;          /* the phase times below need LOBPCG_OPT_TRACE */
+  double ms_rr;                /* RR Gram + small eigensolve + rotation */
+  double ms_ortho;             /* ortho(W~; [X P]) */
+  double ms_sync;              /* host waits for per-iteration read-backs */
+} lobpcg_stats;
+
+/* ---- ortho report for the step entry points ---------------------------- */
+typedef struct lobpcg_ortho_info {
+  int32_t grams, factorizations, failed, shifted, updates, passes, stalled, svqb;
+} lobpcg_ortho_info;
+
+/* ======================================================================== */
+/* Handle life cycle                                                         */
+/* ======================================================================== */
+
+/* Create a solver for a symmetric operator of order n (Sec. 2) on HIP device
+ * `device`.  n >= 1.  *out receives the handle (NULL on error). */
+int lobpcg_create(int64_t n, int device, lobpcg_t* out);
+/* Release the handle and its pinned host buffers (never the caller's memory). */
+int lobpcg_destroy(lobpcg_t h);
+/* Run all device work of this handle on `hip_stream` (a hipStream_t). */
+int lobpcg_set_stream(lobpcg_t h, void* hip_stream);
+/* Set an option (LOBPCG_OPT_*); integer options take integral values. */
+int lobpcg_set_option(lobpcg_t h, int key, double value);
+
+/* Bytes of device workspace needed for a block of `block` columns under the
+ * current options and operator (call after the operator is set).  The block
+ * is the RR block m (Sec. 2: m >= number of pairs sought); 1 <= block <= 32
+ * and 3 * block <= n in this build. */
+int lobpcg_workspace_size(lobpcg_t h, int block, size_t* bytes);
+/* Hand over a device buffer of `bytes` bytes (256-byte aligned) used for all
+ * blocks and partial results.  Borrowed, not freed by the library. */
+int lobpcg_set_workspace(lobpcg_t h, void* dev_ptr, size_t bytes);
+
+/* ======================================================================== */
+/* Operator and preconditioner (the method is matrix-free, Sec. 3.1)          */
+/* ======================================================================== */
+
+/* Sparse symmetric A in CSR: row_ptr (n+1, int32), col (nnz, int32, any
+ * order within a row), val (nnz, fp64); all device, borrowed.  Both
+ * triangles must be stored. */
+int lobpcg_set_operator_csr(lobpcg_t h, const int32_t* row_ptr, const int32_t* col,
+                            const double* val, int64_t nnz);
+/* Dense symmetric A, row-major with leading dimension lda >= n; device,
+ * borrowed. */
+int lobpcg_set_operator_dense(lobpcg_t h, const double* A, int64_t lda);
+/* Matrix-free H = A (x) I + I (x) A + diag(vec V) of order n = na^2, with A
+ * (na x na, symmetric, row-major) and V (na x na, row-major); vector entry
+ * i * na + j pairs with V[i][j].  Device, borrowed. */
+int lobpcg_set_operator_kronsum(lobpcg_t h, int64_t na, const double* A, const double* V);
+
+/* Preconditioner T (Sec. 2).  kind: LOBPCG_PRECOND_*.  diag: device array of
+ * n values of diag(A), or NULL to take it from the operator (CSR: the stored
+ * diagonal entries; dense: A_ii; kronsum: A_ii + A_jj + V_ij).  A diagonal
+ * entry x with |x - theta_j| < 1e-8 max(1, |theta_j|) is clamped to that
+ * bound (sign kept, 0 taken as +). */
+int lobpcg_set_preconditioner(lobpcg_t h, int kind, const double* diag);
+
+/* Initial block X0 (Alg. 1 input): device, row-major n x block with leading
+ * dimension ld.  Copied when lobpcg_solve starts.  Without it the solver
+ * fills X0 with SplitMix64 uniforms in [-0.5, 0.5). */
+int lobpcg_set_initial_guess(lobpcg_t h, const double* X0, int64_t ld, int block);
+
+/* ======================================================================== */
+/* Solve and results                                                          */
+/* ======================================================================== */
+
+/* Alg. 1: iterate until the k lowest pairs have true residual 2-norms
+ * ||A x - theta x|| <= tol (||x|| = 1), or max_iter.  1 <= k <= block.
+ * Blocking: returns after the stream is synchronised.  Returns LOBPCG_OK,
+ * LOBPCG_NOT_CONVERGED, or an error. */
+int lobpcg_solve(lobpcg_t h, int k, double tol);
+
+/* Results of the last solve.  evals, resnorms: host arrays of k doubles (may
+ * be NULL); evecs: device, row-major n x k with leading dimension ldv >= k
+ * (may be NULL).  Pairs are in ascending order; each eigenvector's entry of
+ * largest magnitude is positive (lowest index on ties).  resnorms are true
+ * residual 2-norms from an explicit product A X.  Blocking. */
+int lobpcg_get_eigenpairs(lobpcg_t h, int k, double* evals, double* evecs, int64_t ldv,
+                          double* resnorms);
+/* Counters and phase times of the last solve (host struct). */
+int lobpcg_get_stats(lobpcg_t h, lobpcg_stats* out);
+
+const char* lobpcg_status_string(int status);
+const char* lobpcg_last_error(lobpcg_t h);
+
+/* ======================================================================== */
+/* Step entry points: one step of the hot path each, on caller buffers.       */
+/* They need the operator (for apply/rotate) and a workspace set.             */
+/* ======================================================================== */
+
+/* Operator application Y = A W (Alg. 1, the products A X^[0] and A W^[k]).
+ * W: device n x ncols (ldw), Y: device n x ncols (ldy), 1 <= ncols <= 64.
+ * Asynchronous. */
+int lobpcg_apply_operator(lobpcg_t h, const double* W, int64_t ldw, int ncols, double* Y,
+                          int64_t ldy);
+
+/* Overlap / projection product C = A^T B over the handle's n rows (the
+ * a = V^T AV of Alg. 1, the X^T X of Alg. 2, the Y^T X of Alg. 3).
+ * A: device n x p (lda), B: device n x q (ldb), C: device p x q row-major.
+ * 1 <= p, q <= 128.  The n-reduction is fixed-order (deterministic).
+ * Asynchronous. */
+int lobpcg_gram(lobpcg_t h, const double* A, int64_t lda, int p, const double* B, int64_t ldb,
+                int q, double* C);
+
+/* Alg. 2, ortho(X): orthonormalise the ncols columns of X in place (device,
+ * n x ncols, ldx), 1 <= ncols <= 32.  Columns are scaled to unit norm first;
+ * a failed Cholesky of the overlap is retried with the diagonal shift
+ * alpha * eps * ||X||_F, alpha = 100, 1000, ... (Sec. 3.2).  info (host,
+ * may be NULL) receives the counters.  Blocking. */
+int lobpcg_ortho(lobpcg_t h, double* X, int64_t ldx, int ncols, lobpcg_ortho_info* info);
+
+/* Alg. 3, ortho(X, Y): make X (device n x ncols, ldx, in place) orthonormal
+ * and orthogonal to the orthonormal Y (device n x ycols, ldy).  Y must sit
+ * immediately left of X in the same row-major buffer: X == Y + ycols and
+ * ldx == ldy (the layout the solver keeps [X P | W] in).  ncols <= 32,
+ * ycols + ncols <= 96.  Blocking. */
+int lobpcg_ortho_against(lobpcg_t h, double* X, int64_t ldx, int ncols, const double* Y,
+                         int64_t ldy, int ycols, lobpcg_ortho_info* info);
+
+/* Small symmetric eigensolve of the RR matrix (Alg. 1, "solve a u = lambda
+ * u"): a (device p x p, symmetrised as (a + a^T)/2 first) -> evals (device,
+ * p, ascending) and evecs (device p x p row-major, column j pairs with
+ * evals[j]).  2 <= p <= 96.  Cyclic parallel-order Jacobi in fp64.
+ * Asynchronous. */
+int lobpcg_small_eigh(lobpcg_t h, const double* a, int p, double* evals, double* evecs);
+
+/* Shifted Cholesky of a small overlap M (device p x p, p <= 64): L (device,
+ * lower triangular p x p) with L L^T = M + sigma I, sigma = 0 when the plain
+ * factorisation succeeds, else alpha * eps * sqrt(trace M) with alpha =
+ * 100, 1000, ... (Sec. 3.2, Alg. 2).  *shifts (host, may be NULL) receives
+ * the number of failed attempts.  Blocking.  LOBPCG_ERR_ORTHO_FAILED when
+ * all retries fail. */
+int lobpcg_small_cholesky(lobpcg_t h, const double* M, int p, double* L, int* shifts);
+
+/* Block rotation with residual and preconditioner (Alg. 1 lines forming
+ * X^[k+1], AX^[k+1], P^[k+1], AP^[k+1], R and W~ = T R; eq. neweigv and the
+ * "Reuse of applications" paragraph, Sec. 3.1):
+ *   [X' P'] = V U,  [AX' AP'] = AV U    with U = [u_x u_p] (device p x q,
+ *                                       q = m + np), V, AV device n x p (ldv)
+ *   R = AX' - X' diag(theta)            theta: device m
+ *   W~[:, j - a0] = T_j R[:, j] for j in [a0, m)   (T from the handle)
+ * Outputs go to Vout / AVout (device n x ldo): columns [0, q) hold [X' P'] /
+ * [AX' AP'], columns [q, q + m - a0) of Vout hold W~.  resnorm2 (device m)
+ * receives ||R[:, j]||^2.  Vout must not alias V.  p <= 96, q <= 64.
+ * Asynchronous. */
+int lobpcg_rotate(lobpcg_t h, const double* V, const double* AV, int64_t ldv, int p,
+                  const double* U, int m, int q, const double* theta, int a0, double* Vout,
+                  double* AVout, int64_t ldo, double* resnorm2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOBPCG_MI355X_H */

@@ -1,0 +1,136 @@
+// Internal declarations shared by the kernels and the host driver.
+// Layout conventions: blocks of vectors are row-major (entry (i, j) of an
+// n x c block with leading dimension ld is at ptr[i * ld + j]); small
+// matrices are dense row-major.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace lobpcg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxBlock = 32;            // RR block m
+constexpr int kMaxP = 3 * kMaxBlock;     // RR subspace m + 2 m_act
+constexpr int kGramMaxCols = 128;        // p, q limit of the Gram kernel
+constexpr int kGramBlocks = 512;         // stage-1 workgroups of the Gram
+constexpr int kStreamBlocks = 1024;      // persistent grid of streaming kernels
+constexpr double kPrecondGuard = 1e-8;   // |d - theta| floor, relative to max(1, |theta|)
+constexpr uint64_t kZeroColumnSeed = 0x2305066680000000ull;
+constexpr uint64_t kDefaultX0Seed = 0x2305066600000001ull;
+
+enum PrecondKind { kPrecNone = 0, kPrecDiag = 1, kPrecDiagSigned = 2 };
+
+// Device-side state of one ortho(W; Y) call (Alg. 2 nested in Alg. 3).
+// Written only by the one-workgroup controller kernel; the streaming kernels
+// read `done` and return at once when it is set.
+struct OrthoState {
+  int state;    // OrthoPhase
+  int done;     // 1: nothing left to apply
+  int inner;    // overlap evaluations in the current Alg. 2 loop
+  int outer;    // Alg. 3 passes
+  int w_only;   // the pending coefficient has no Y part
+  int error;    // 0, kOrthoErrZero (zero column met), kOrthoErrNonfinite, kOrthoErrFailed
+  int zero_mask;  // bit j: column j of W was exactly zero
+  int grams, factorizations, failed, shifted, updates, stalled, svqb, passes;
+  int ny, nw;   // current shape
+  int max_inner, max_outer;
+  double tau;
+};
+enum OrthoPhase { kPhStart = 0, kPhBegin = 1, kPhLoop = 2, kPhOuter = 3, kPhDone = 4 };
+enum { kOrthoErrZero = 1, kOrthoErrNonfinite = 2, kOrthoErrFailed = 3 };
+
+// ---- streaming kernels (k_blas.hip) -------------------------------------
+// C (p x q) = A^T B over n rows, fp64 result; `part` needs kGramBlocks*p*q.
+hipError_t gram_f64(const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
+                    int64_t n, double* part, double* C, const int* skip, hipStream_t s);
+hipError_t gram_f32(const float* A, int64_t lda, int p, const float* B, int64_t ldb, int q,
+                    int64_t n, double* part, double* C, const int* skip, hipStream_t s);
+
+// Out (n x q) = In (n x p) Coef (p x q); Out may alias columns of In when
+// every row of Out lies inside the same row of In.  skip: optional flag.
+hipError_t tsmm_f64(const double* In, int64_t ldi, int p, const double* Coef, int q, double* Out,
+                    int64_t ldo, int64_t n, const int* skip, hipStream_t s);
+hipError_t tsmm_f32(const float* In, int64_t ldi, int p, const double* Coef, int q, float* Out,
+                    int64_t ldo, int64_t n, const int* skip, hipStream_t s);
+
+// Rotation + residual + preconditioner (one pass over V and AV).
+struct RotateArgs {
+  int64_t n, ldv, ldo;
+  int p, m, q, a0, precond;
+  const double* U;      // p x q
+  const double* theta;  // m
+  const double* diag;   // n (may be null for kPrecNone)
+  double* part;         // kStreamBlocks * m partial norms
+  double* resnorm2;     // m
+};
+hipError_t rotate_f64(const double* V, const double* AV, double* Vout, double* AVout,
+                      const RotateArgs& a, hipStream_t s);
+hipError_t rotate_f32(const float* V, const float* AV, float* Vout, float* AVout,
+                      const RotateArgs& a, hipStream_t s);
+
+// Column statistics for the true residual: out[0:m] = x^T x, out[m:2m] =
+// x^T (Ax), out[2m:3m] = ||Ax - theta x||^2.
+hipError_t colstats_f64(const double* X, int64_t ldx, const double* AX, int64_t ldax, int m,
+                        const double* theta, int64_t n, double* part, double* out, hipStream_t s);
+
+// Fill column `col` of an n x * block with SplitMix64 uniforms in [-0.5, 0.5):
+// entry i = (splitmix64(seed + col_id * n + i) >> 11) * 2^-53 - 0.5.
+hipError_t fill_splitmix(double* X, int64_t ld, int col, int col_id, int64_t n, uint64_t seed,
+                         hipStream_t s);
+
+// Copy the first k columns of X to out (ld_out) with each column's sign set so
+// its largest-magnitude entry (lowest index on ties) is positive.
+hipError_t copy_signfix(const double* X, int64_t ldx, int k, int64_t n, double* out,
+                        int64_t ldout, int64_t* part_idx, double* part_val, hipStream_t s);
+
+// Precision conversions of an n x c block.
+hipError_t convert_f64_to_f32(const double* in, int64_t ldi, float* out, int64_t ldo, int c,
+                              int64_t n, hipStream_t s);
+hipError_t convert_f32_to_f64(const float* in, int64_t ldi, double* out, int64_t ldo, int c,
+                              int64_t n, hipStream_t s);
+hipError_t convert_vec_f64_to_f32(const double* in, float* out, int64_t len, hipStream_t s);
+
+// ---- operators (k_op.hip) -----------------------------------------------
+hipError_t spmm_csr_f64(const int32_t* rp, const int32_t* ci, const double* val, const double* W,
+                        int64_t ldw, double* Y, int64_t ldy, int ncols, int64_t n, hipStream_t s);
+hipError_t spmm_csr_f32(const int32_t* rp, const int32_t* ci, const float* val, const float* W,
+                        int64_t ldw, float* Y, int64_t ldy, int ncols, int64_t n, hipStream_t s);
+hipError_t dense_apply_f64(const double* A, int64_t lda, const double* W, int64_t ldw, double* Y,
+                           int64_t ldy, int ncols, int64_t n, hipStream_t s);
+hipError_t dense_apply_f32(const float* A, int64_t lda, const float* W, int64_t ldw, float* Y,
+                           int64_t ldy, int ncols, int64_t n, hipStream_t s);
+hipError_t kronsum_apply_f64(const double* A, const double* Vp, int64_t na, const double* W,
+                             int64_t ldw, double* Y, int64_t ldy, int ncols, hipStream_t s);
+hipError_t kronsum_apply_f32(const float* A, const float* Vp, int64_t na, const float* W,
+                             int64_t ldw, float* Y, int64_t ldy, int ncols, hipStream_t s);
+// Sets bits of *bad (device int, zeroed by the caller) on a malformed CSR.
+hipError_t csr_check(const int32_t* rp, const int32_t* ci, int64_t n, int64_t nnz, int* bad,
+                     hipStream_t s);
+hipError_t csr_diag(const int32_t* rp, const int32_t* ci, const double* val, int64_t n,
+                    double* diag, hipStream_t s);
+hipError_t dense_diag(const double* A, int64_t lda, int64_t n, double* diag, hipStream_t s);
+hipError_t kronsum_diag(const double* A, const double* Vp, int64_t na, double* diag,
+                        hipStream_t s);
+
+// ---- small dense fp64 kernels (k_small.hip) -----------------------------
+// Eigen-decomposition of sym(a) (p x p): evals ascending, evecs p x p.
+hipError_t small_eigh(const double* a, int p, double* evals, double* evecs, int* sweeps,
+                      hipStream_t s);
+// Rayleigh-Ritz coefficients: eig of sym(a) (p x p); theta = lowest m
+// values; U (p x q) = [u_x | u_p] where u_p = ortho(u_x[:, a0:m] - E[:, a0:m]; u_x)
+// (q = m + (want_up ? m - a0 : 0)).  info[0] = Jacobi sweeps, info[1] = 0 ok,
+// info[2..] ortho counters for the R^p orthonormalisation.
+hipError_t small_rr(const double* a, int p, int m, int a0, int want_up, double tau,
+                    double* theta_all, double* U, int* info, hipStream_t s);
+// Shifted Cholesky (p x p, p <= 64): L lower with L L^T = M + sigma I.
+hipError_t small_cholesky(const double* M, int p, double* L, int* info, hipStream_t s);
+// One controller step of ortho(W; Y): reads G = [Y W]^T W ((ny+nw) x nw),
+// updates the state and writes the next coefficient ((ny+nw) x nw).
+hipError_t ortho_ctl(const double* G, OrthoState* st, double* coef, hipStream_t s);
+hipError_t ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner, int max_outer,
+                      hipStream_t s);
+
+}  // namespace lobpcg

@@ -1,0 +1,269 @@
+// Operator application Y = A W for the matrix kinds the solver accepts
+// (Alg. 1: the products A X^[0] and A W^[k]; the method is matrix-free,
+// Sec. 3.1, so the operator is an input, not part of the method).
+//
+//   * CSR SpMM: HBM-bound on the (col, val) stream.  A group of G lanes
+//     (G = next power of two >= number of block columns) owns one row: the
+//     group loads G (col, val) pairs coalesced, broadcasts them with
+//     __shfl, and every lane gathers one column of the W row (the group
+//     reads the whole W row, ncols*8 contiguous bytes).  Row blocks are
+//     remapped so that each XCD (hardware dispatches block b to XCD b % 8)
+//     walks one contiguous range of rows: a banded matrix then keeps its W
+//     window inside that XCD's L2.
+//   * dense: HBM-bound on A; a wave owns R rows, lanes stride the columns,
+//     and the ncols partial sums are reduced across the wave at the end.
+#include "internal.h"
+
+namespace lobpcg {
+
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+template <typename TV, typename TW, int G>
+__global__ __launch_bounds__(256) void k_spmm_csr(const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci,
+                                                  const TV* __restrict__ val,
+                                                  const TW* __restrict__ W, int64_t ldw,
+                                                  TW* __restrict__ Y, int64_t ldy, int ncols,
+                                                  int64_t n, int per_xcd) {
+  constexpr int RPB = 256 / G;
+  const int b = blockIdx.x;
+  const int lb = (b & 7) * per_xcd + (b >> 3);
+  const int64_t row = (int64_t)lb * RPB + threadIdx.x / G;
+  const int c = threadIdx.x & (G - 1);
+  const int gbase = (threadIdx.x & 63) & ~(G - 1);
+  if (row >= n) return;  // the whole group shares the row
+  const bool active = c < ncols;
+  const int e0 = rp[row], e1 = rp[row + 1];
+  TW acc = TW(0);
+  for (int e = e0; e < e1; e += G) {
+    const int my = e + c;
+    int col = 0;
+    TV v = TV(0);
+    if (my < e1) {
+      col = ci[my];
+      v = val[my];
+    }
+    const int cnt = min(G, e1 - e);
+    int t = 0;
+    for (; t + 4 <= cnt; t += 4) {
+      const int c0 = __shfl(col, gbase + t, 64);
+      const int c1 = __shfl(col, gbase + t + 1, 64);
+      const int c2 = __shfl(col, gbase + t + 2, 64);
+      const int c3 = __shfl(col, gbase + t + 3, 64);
+      const TV v0 = __shfl(v, gbase + t, 64);
+      const TV v1 = __shfl(v, gbase + t + 1, 64);
+      const TV v2 = __shfl(v, gbase + t + 2, 64);
+      const TV v3 = __shfl(v, gbase + t + 3, 64);
+      TW w0 = TW(0), w1 = TW(0), w2 = TW(0), w3 = TW(0);
+      if (active) {
+        w0 = W[(int64_t)c0 * ldw + c];
+        w1 = W[(int64_t)c1 * ldw + c];
+        w2 = W[(int64_t)c2 * ldw + c];
+        w3 = W[(int64_t)c3 * ldw + c];
+      }
+      acc += (TW)v0 * w0;
+      acc += (TW)v1 * w1;
+      acc += (TW)v2 * w2;
+      acc += (TW)v3 * w3;
+    }
+    for (; t < cnt; ++t) {
+      const int c0 = __shfl(col, gbase + t, 64);
+      const TV v0 = __shfl(v, gbase + t, 64);
+      if (active) acc += (TW)v0 * W[(int64_t)c0 * ldw + c];
+    }
+  }
+  if (active) Y[row * ldy + c] = acc;
+}
+
+template <typename TV, typename TW, int G>
+static hipError_t spmm_launch(const int32_t* rp, const int32_t* ci, const TV* val, const TW* W,
+                              int64_t ldw, TW* Y, int64_t ldy, int ncols, int64_t n,
+                              hipStream_t s) {
+  constexpr int RPB = 256 / G;
+  const int64_t nb = (n + RPB - 1) / RPB;
+  const int64_t nbp = (nb + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_spmm_csr<TV, TW, G>), dim3((unsigned)nbp), dim3(256), 0, s, rp, ci, val,
+                     W, ldw, Y, ldy, ncols, n, (int)(nbp / 8));
+  return hipGetLastError();
+}
+
+template <typename TV, typename TW>
+static hipError_t spmm_any(const int32_t* rp, const int32_t* ci, const TV* val, const TW* W,
+                           int64_t ldw, TW* Y, int64_t ldy, int ncols, int64_t n, hipStream_t s) {
+  if (n < 1 || ncols < 1) return hipErrorInvalidValue;
+  // columns beyond 64 are processed in slices of 64
+  for (int c0 = 0; c0 < ncols; c0 += 64) {
+    const int nc = std::min(64, ncols - c0);
+    hipError_t e;
+    if (nc <= 1) e = spmm_launch<TV, TW, 1>(rp, ci, val, W + c0, ldw, Y + c0, ldy, nc, n, s);
+    else if (nc <= 2) e = spmm_launch<TV, TW, 2>(rp, ci, val, W + c0, ldw, Y + c0, ldy, nc, n, s);
+    else if (nc <= 4) e = spmm_launch<TV, TW, 4>(rp, ci, val, W + c0, ldw, Y + c0, ldy, nc, n, s);
+    else if (nc <= 8) e = spmm_launch<TV, TW, 8>(rp, ci, val, W + c0, ldw, Y + c0, ldy, nc, n, s);
+    else if (nc <= 16) e = spmm_launch<TV, TW, 16>(rp, ci, val, W + c0, ldw, Y + c0, ldy, nc, n, s);
+    else if (nc <= 32) e = spmm_launch<TV, TW, 32>(rp, ci, val, W + c0, ldw, Y + c0, ldy, nc, n, s);
+    else e = spmm_launch<TV, TW, 64>(rp, ci, val, W + c0, ldw, Y + c0, ldy, nc, n, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t spmm_csr_f64(const int32_t* rp, const int32_t* ci, const double* val, const double* W,
+                        int64_t ldw, double* Y, int64_t ldy, int ncols, int64_t n, hipStream_t s) {
+  return spmm_any<double, double>(rp, ci, val, W, ldw, Y, ldy, ncols, n, s);
+}
+hipError_t spmm_csr_f32(const int32_t* rp, const int32_t* ci, const float* val, const float* W,
+                        int64_t ldw, float* Y, int64_t ldy, int ncols, int64_t n, hipStream_t s) {
+  return spmm_any<float, float>(rp, ci, val, W, ldw, Y, ldy, ncols, n, s);
+}
+
+// ---------------------------------------------------------------------------
+// dense: Y (n x ncols) = A (n x n, lda) W (n x ncols), R rows per wave,
+// up to MC columns per launch.
+
+template <typename T, int R, int MC>
+__global__ __launch_bounds__(256) void k_dense(const T* __restrict__ A, int64_t lda,
+                                               const T* __restrict__ W, int64_t ldw,
+                                               T* __restrict__ Y, int64_t ldy, int ncols,
+                                               int64_t n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t r0 = gw * R;
+  if (r0 >= n) return;
+  T acc[R][MC];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < MC; ++j) acc[r][j] = T(0);
+  const T* arow[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) arow[r] = A + min(r0 + r, n - 1) * lda;
+  for (int64_t c = lane; c < n; c += 64) {
+    T w[MC];
+#pragma unroll
+    for (int j = 0; j < MC; ++j) w[j] = (j < ncols) ? W[c * ldw + j] : T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T a = arow[r][c];
+#pragma unroll
+      for (int j = 0; j < MC; ++j) acc[r][j] += a * w[j];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+      T v = acc[r][j];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+      acc[r][j] = v;
+    }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r0 + r < n)
+#pragma unroll
+        for (int j = 0; j < MC; ++j)
+          if (j < ncols) Y[(r0 + r) * ldy + j] = acc[r][j];
+  }
+}
+
+template <typename T>
+static hipError_t dense_any(const T* A, int64_t lda, const T* W, int64_t ldw, T* Y, int64_t ldy,
+                            int ncols, int64_t n, hipStream_t s) {
+  if (n < 1 || ncols < 1) return hipErrorInvalidValue;
+  constexpr int R = 4;
+  const int64_t waves = (n + R - 1) / R;
+  const int grid = cdiv(waves, 4);
+  for (int c0 = 0; c0 < ncols; c0 += 8) {
+    const int nc = std::min(8, ncols - c0);
+    if (nc <= 4)
+      hipLaunchKernelGGL((k_dense<T, R, 4>), dim3(grid), dim3(256), 0, s, A, lda, W + c0, ldw,
+                         Y + c0, ldy, nc, n);
+    else
+      hipLaunchKernelGGL((k_dense<T, R, 8>), dim3(grid), dim3(256), 0, s, A, lda, W + c0, ldw,
+                         Y + c0, ldy, nc, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t dense_apply_f64(const double* A, int64_t lda, const double* W, int64_t ldw, double* Y,
+                           int64_t ldy, int ncols, int64_t n, hipStream_t s) {
+  return dense_any<double>(A, lda, W, ldw, Y, ldy, ncols, n, s);
+}
+hipError_t dense_apply_f32(const float* A, int64_t lda, const float* W, int64_t ldw, float* Y,
+                           int64_t ldy, int ncols, int64_t n, hipStream_t s) {
+  return dense_any<float>(A, lda, W, ldw, Y, ldy, ncols, n, s);
+}
+
+// ---------------------------------------------------------------------------
+// CSR structure check (run once when the operator is set): row pointers
+// non-decreasing from 0 to nnz, every column index inside [0, n).
+
+__global__ void k_csr_check(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            int64_t n, int64_t nnz, int* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) atomicOr(bad, 1);
+  if (i >= n) return;
+  const int32_t e0 = rp[i], e1 = rp[i + 1];
+  if (e1 < e0 || e0 < 0 || (int64_t)e1 > nnz) {
+    atomicOr(bad, 2);
+    return;
+  }
+  for (int32_t e = e0; e < e1; ++e) {
+    const int32_t c = ci[e];
+    if (c < 0 || (int64_t)c >= n) {
+      atomicOr(bad, 4);
+      return;
+    }
+  }
+}
+hipError_t csr_check(const int32_t* rp, const int32_t* ci, int64_t n, int64_t nnz, int* bad,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_csr_check, dim3(cdiv(n, 256)), dim3(256), 0, s, rp, ci, n, nnz, bad);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// diagonals (inputs of the Jacobi preconditioner)
+
+__global__ void k_csr_diag(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ val, int64_t n, double* __restrict__ d) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double v = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] == i) v += val[e];
+  d[i] = v;
+}
+hipError_t csr_diag(const int32_t* rp, const int32_t* ci, const double* val, int64_t n,
+                    double* diag, hipStream_t s) {
+  hipLaunchKernelGGL(k_csr_diag, dim3(cdiv(n, 256)), dim3(256), 0, s, rp, ci, val, n, diag);
+  return hipGetLastError();
+}
+
+__global__ void k_dense_diag(const double* __restrict__ A, int64_t lda, int64_t n,
+                             double* __restrict__ d) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i] = A[i * lda + i];
+}
+hipError_t dense_diag(const double* A, int64_t lda, int64_t n, double* diag, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_diag, dim3(cdiv(n, 256)), dim3(256), 0, s, A, lda, n, diag);
+  return hipGetLastError();
+}
+
+__global__ void k_kron_diag(const double* __restrict__ A, const double* __restrict__ Vp,
+                            int64_t na, double* __restrict__ d) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= na * na) return;
+  const int64_t i = idx / na, j = idx - i * na;
+  d[idx] = A[i * na + i] + A[j * na + j] + Vp[idx];
+}
+hipError_t kronsum_diag(const double* A, const double* Vp, int64_t na, double* diag,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_kron_diag, dim3(cdiv(na * na, 256)), dim3(256), 0, s, A, Vp, na, diag);
+  return hipGetLastError();
+}
+
+}  // namespace lobpcg

@@ -1,0 +1,852 @@
+// Small dense fp64 linear algebra of the LOBPCG step, one workgroup each,
+// everything resident in LDS (gfx950: 160 KB per workgroup):
+//   * cyclic Jacobi eigensolver in parallel (round-robin) order for the
+//     p x p Rayleigh-Ritz matrix, p <= 96 (Alg. 1, "solve a u = lambda u";
+//     the paper calls LAPACK dsyev, Sec. 3.1);
+//   * shifted Cholesky of an overlap matrix (Sec. 3.2: retry with
+//     alpha * eps * ||X|| added to the diagonal, alpha = 100, 1000, ...);
+//   * the implicit P coefficients u_p = ortho(u_x[:, act] - E[:, act]; u_x)
+//     in R^p (Alg. 1 and the "Basis selection" paragraph of Sec. 3.1);
+//   * the controller of ortho(W; Y) on n-vectors (Alg. 2 inside Alg. 3): it
+//     reads the overlap G = [Y W]^T W of the current W and emits the small
+//     coefficient matrix that the streaming kernel applies next.
+#include "internal.h"
+
+namespace lobpcg {
+
+constexpr double kEps = 0x1.0p-52;  // double precision machine epsilon
+constexpr double kShiftAlpha0 = 100.0;
+constexpr double kShiftGrowth = 10.0;
+constexpr int kShiftRetries = 20;
+constexpr int kJacobiMaxSweeps = 40;
+
+__device__ __forceinline__ uint64_t sm64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// block-wide helpers (every thread of the block calls them)
+
+__device__ double blk_reduce_max(double v, double* scratch) {
+  // scratch: blockDim.x / 64 doubles
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[w] = v;
+  __syncthreads();
+  double r = scratch[0];
+  for (int i = 1; i < nw; ++i) r = fmax(r, scratch[i]);
+  __syncthreads();
+  return r;
+}
+
+__device__ double blk_reduce_sum_ordered(double v, double* scratch) {
+  // deterministic: each wave reduces by a fixed xor tree, waves in order
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[w] = v;
+  __syncthreads();
+  double r = scratch[0];
+  for (int i = 1; i < nw; ++i) r += scratch[i];
+  __syncthreads();
+  return r;
+}
+
+// C (p x q) = A^T B, A: n x p, B: n x q
+__device__ void blk_gemm_tn(const double* A, int lda, const double* B, int ldb, int n, int p,
+                            int q, double* C, int ldc) {
+  for (int idx = threadIdx.x; idx < p * q; idx += blockDim.x) {
+    const int i = idx / q, j = idx - i * q;
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) s += A[r * lda + i] * B[r * ldb + j];
+    C[i * ldc + j] = s;
+  }
+  __syncthreads();
+}
+
+// X (n x q) -= Y (n x p) C (p x q)
+__device__ void blk_sub_mm(double* X, int ldx, const double* Y, int ldy, const double* C, int ldc,
+                           int n, int p, int q) {
+  for (int idx = threadIdx.x; idx < n * q; idx += blockDim.x) {
+    const int r = idx / q, j = idx - r * q;
+    double s = 0.0;
+    for (int k = 0; k < p; ++k) s += Y[r * ldy + k] * C[k * ldc + j];
+    X[r * ldx + j] -= s;
+  }
+  __syncthreads();
+}
+
+// scale columns of X (n x q) to unit norm; exact-zero columns are replaced
+// by SplitMix64 columns (entry i of column j: splitmix64(seed + j n + i)).
+__device__ void blk_normalize(double* X, int ldx, int n, int q, double* tmp, int* zeros) {
+  for (int j = threadIdx.x; j < q; j += blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) s += X[r * ldx + j] * X[r * ldx + j];
+    if (s == 0.0) {
+      for (int r = 0; r < n; ++r) {
+        const uint64_t z = sm64(kZeroColumnSeed + (uint64_t)j * (uint64_t)n + (uint64_t)r);
+        X[r * ldx + j] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
+      }
+      s = 0.0;
+      for (int r = 0; r < n; ++r) s += X[r * ldx + j] * X[r * ldx + j];
+      atomicAdd(zeros, 1);
+    }
+    tmp[j] = sqrt(s);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * q; idx += blockDim.x) {
+    const int j = idx % q;
+    X[idx / q * ldx + j] /= tmp[j];
+  }
+  __syncthreads();
+}
+
+// Cholesky L L^T = M + shift I (lower, n x n); returns true on success.
+// Breaks down when a pivot is not > 0 (NaN included), like LAPACK potrf.
+__device__ bool blk_chol(const double* M, int ldm, int n, double shift, double* L, int ldl,
+                         int* flag) {
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx - i * n;
+    L[i * ldl + j] = (j <= i) ? (M[i * ldm + j] + (i == j ? shift : 0.0)) : 0.0;
+  }
+  if (threadIdx.x == 0) *flag = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = L[j * ldl + j];
+      if (!(d > 0.0)) *flag = 1;
+      else L[j * ldl + j] = sqrt(d);
+    }
+    __syncthreads();
+    if (*flag) return false;
+    const double ljj = L[j * ldl + j];
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) L[i * ldl + j] /= ljj;
+    __syncthreads();
+    const int rem = n - j - 1;
+    for (int idx = threadIdx.x; idx < rem * rem; idx += blockDim.x) {
+      const int i = j + 1 + idx / rem, k = j + 1 + idx % rem;
+      if (k <= i) L[i * ldl + k] -= L[i * ldl + j] * L[k * ldl + j];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+struct ShiftCount {
+  int factorizations, failed, shifted, svqb;
+};
+
+// Sec. 3.2 / Alg. 2: plain Cholesky, then shifts alpha*eps*||X||_F with
+// ||X||_F = sqrt(trace M), alpha = 100, x10 per retry.
+__device__ bool blk_shifted_chol(const double* M, int ldm, int n, double* L, int ldl, int* flag,
+                                 ShiftCount* c, double* scratch) {
+  if (threadIdx.x == 0) c->factorizations++;
+  if (blk_chol(M, ldm, n, 0.0, L, ldl, flag)) return true;
+  if (threadIdx.x == 0) c->failed++;
+  double tr = 0.0;
+  for (int i = 0; i < n; ++i) tr += M[i * ldm + i];
+  const double normx = sqrt(fmax(tr, 0.0));
+  double alpha = kShiftAlpha0;
+  for (int t = 0; t < kShiftRetries; ++t) {
+    if (threadIdx.x == 0) c->factorizations++;
+    if (blk_chol(M, ldm, n, alpha * kEps * normx, L, ldl, flag)) {
+      if (threadIdx.x == 0) c->shifted++;
+      return true;
+    }
+    if (threadIdx.x == 0) c->failed++;
+    alpha *= kShiftGrowth;
+  }
+  return false;
+}
+
+// Linv = L^-1 (lower), one column per thread by forward substitution.
+__device__ void blk_tri_inv(const double* L, int ldl, int n, double* Li, int ldi) {
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int i = 0; i < n; ++i) {
+      if (i < j) {
+        Li[i * ldi + j] = 0.0;
+        continue;
+      }
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) s -= L[i * ldl + k] * Li[k * ldi + j];
+      Li[i * ldi + j] = s / L[i * ldl + i];
+    }
+  }
+  __syncthreads();
+}
+
+// X (n x q) <- X L^-T, one row per thread: z_j = (x_j - sum_{k<j} z_k L_jk) / L_jj
+__device__ void blk_trsm_rt(double* X, int ldx, int n, int q, const double* L, int ldl) {
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    for (int j = 0; j < q; ++j) {
+      double s = X[r * ldx + j];
+      for (int k = 0; k < j; ++k) s -= X[r * ldx + k] * L[j * ldl + k];
+      X[r * ldx + j] = s / L[j * ldl + j];
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Parallel cyclic Jacobi on the symmetric n x n matrix A (LDS, stride lda),
+// accumulating V (stride ldv, initialised here to I).  Round-robin pairing:
+// in round r the pairs are {pp-1, r} and {(r+k) mod (pp-1), (r-k) mod (pp-1)}
+// for k = 1 .. pp/2-1, with pp = n rounded up to even (index n is a dummy).
+// A rotation is skipped when |a_pq| <= 2^-53 sqrt(|a_pp a_qq|) or
+// |a_pq| <= 2^-60 ||A||_F; the sweep loop stops after a sweep without any
+// rotation.  Returns the number of sweeps.
+
+__device__ int blk_jacobi(double* A, int lda, double* V, int ldv, int n, double* cs, int* pr,
+                          int* rot_flag, double* scratch) {
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx - i * n;
+    V[i * ldv + j] = (i == j) ? 1.0 : 0.0;
+  }
+  double fro = 0.0;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const double v = A[(idx / n) * lda + idx % n];
+    fro += v * v;
+  }
+  fro = sqrt(blk_reduce_sum_ordered(fro, scratch));
+  const double abs_tol = 0x1.0p-60 * fro;
+  if (n < 2) return 0;
+  const int pp = n + (n & 1);
+  const int npairs = pp / 2;
+  int sweep = 0;
+  for (; sweep < kJacobiMaxSweeps; ++sweep) {
+    if (threadIdx.x == 0) *rot_flag = 0;
+    __syncthreads();
+    for (int r = 0; r < pp - 1; ++r) {
+      // pairs and angles
+      for (int k = threadIdx.x; k < npairs; k += blockDim.x) {
+        int i, j;
+        if (k == 0) {
+          i = pp - 1;
+          j = r;
+        } else {
+          i = (r + k) % (pp - 1);
+          j = (r - k + (pp - 1)) % (pp - 1);
+        }
+        if (i > j) {
+          const int t = i;
+          i = j;
+          j = t;
+        }
+        double c = 1.0, s = 0.0;
+        if (j < n) {
+          const double apq = A[i * lda + j];
+          const double app = A[i * lda + i], aqq = A[j * lda + j];
+          if (fabs(apq) > 0x1.0p-53 * sqrt(fabs(app * aqq)) && fabs(apq) > abs_tol) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                          : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            *rot_flag = 1;
+          }
+        }
+        pr[2 * k] = i;
+        pr[2 * k + 1] = j;
+        cs[2 * k] = c;
+        cs[2 * k + 1] = s;
+      }
+      __syncthreads();
+      // rows: A <- J^T A  (row i' = c row_i - s row_j, row j' = s row_i + c row_j)
+      for (int idx = threadIdx.x; idx < npairs * n; idx += blockDim.x) {
+        const int k = idx / n, col = idx - k * n;
+        const int i = pr[2 * k], j = pr[2 * k + 1];
+        const double s = cs[2 * k + 1];
+        if (j >= n || s == 0.0) continue;
+        const double c = cs[2 * k];
+        const double ai = A[i * lda + col], aj = A[j * lda + col];
+        A[i * lda + col] = c * ai - s * aj;
+        A[j * lda + col] = s * ai + c * aj;
+      }
+      __syncthreads();
+      // columns: A <- A J and V <- V J
+      for (int idx = threadIdx.x; idx < npairs * n; idx += blockDim.x) {
+        const int k = idx % npairs, row = idx / npairs;
+        const int i = pr[2 * k], j = pr[2 * k + 1];
+        const double s = cs[2 * k + 1];
+        if (j >= n || s == 0.0) continue;
+        const double c = cs[2 * k];
+        const double ai = A[row * lda + i], aj = A[row * lda + j];
+        A[row * lda + i] = c * ai - s * aj;
+        A[row * lda + j] = s * ai + c * aj;
+        const double vi = V[row * ldv + i], vj = V[row * ldv + j];
+        V[row * ldv + i] = c * vi - s * vj;
+        V[row * ldv + j] = s * vi + c * vj;
+      }
+      __syncthreads();
+      // the annihilated pair is exactly zero
+      for (int k = threadIdx.x; k < npairs; k += blockDim.x) {
+        const int i = pr[2 * k], j = pr[2 * k + 1];
+        if (j < n && cs[2 * k + 1] != 0.0) {
+          A[i * lda + j] = 0.0;
+          A[j * lda + i] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = *rot_flag;
+    __syncthreads();
+    if (!any) break;
+  }
+  return sweep + 1;
+}
+
+// evals ascending (ties by index) -> perm[rank] = index
+__device__ void blk_sort_evals(const double* A, int lda, int n, int* perm) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double li = A[i * lda + i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = A[j * lda + j];
+      if (lj < li || (lj == li && j < i)) ++rank;
+    }
+    perm[rank] = i;
+  }
+  __syncthreads();
+}
+
+// LDS layout shared by the eig-based kernels
+struct EigLds {
+  double* A;  // p x (p+1)
+  double* V;  // p x (p+1)
+  double* cs;
+  int* pr;
+  int* perm;
+  double* scratch;
+  int* flags;
+};
+
+// The second area holds V during the Jacobi sweeps and, in k_small_rr, the
+// R^p orthonormalisation work arrays afterwards (X p x na, C m x na, M, L and
+// an SVQB workspace), hence its size max(p (p+1), p m + 5 m^2 + 2 m).
+__host__ __device__ inline int eig_area2(int p, int m) {
+  const int a = p * (p + 1), b = p * m + 5 * m * m + 2 * m;
+  return a > b ? a : b;
+}
+__device__ EigLds eig_lds(double* smem, int p, int m) {
+  EigLds L;
+  const int ld = p + 1;
+  L.A = smem;
+  L.V = L.A + p * ld;
+  L.cs = L.V + eig_area2(p, m);   // 2 * 64
+  L.scratch = L.cs + 2 * 64;      // 16
+  L.pr = (int*)(L.scratch + 16);  // 2 * 64
+  L.perm = L.pr + 2 * 64;         // 128
+  L.flags = L.perm + 128;         // 8
+  return L;
+}
+static size_t eig_lds_bytes(int p, int m) {
+  return sizeof(double) * (size_t)(p * (p + 1) + eig_area2(p, m) + 2 * 64 + 16) +
+         sizeof(int) * (2 * 64 + 128 + 8);
+}
+
+__device__ void load_sym(const double* a, int p, double* A, int lda) {
+  for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
+    const int i = idx / p, j = idx - i * p;
+    A[i * lda + j] = 0.5 * (a[i * p + j] + a[j * p + i]);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(512) void k_small_eigh(const double* __restrict__ a, int p,
+                                                    double* __restrict__ evals,
+                                                    double* __restrict__ evecs, int* sweeps) {
+  extern __shared__ double smem[];
+  EigLds L = eig_lds(smem, p, 1);
+  const int ld = p + 1;
+  load_sym(a, p, L.A, ld);
+  const int sw = blk_jacobi(L.A, ld, L.V, ld, p, L.cs, L.pr, L.flags, L.scratch);
+  blk_sort_evals(L.A, ld, p, L.perm);
+  for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
+    const int i = idx / p, j = idx - i * p;
+    evecs[i * p + j] = L.V[i * ld + L.perm[j]];
+  }
+  for (int j = threadIdx.x; j < p; j += blockDim.x) evals[j] = L.A[L.perm[j] * ld + L.perm[j]];
+  if (threadIdx.x == 0 && sweeps != nullptr) *sweeps = sw;
+}
+
+hipError_t small_eigh(const double* a, int p, double* evals, double* evecs, int* sweeps,
+                      hipStream_t s) {
+  if (p < 1 || p > kMaxP) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_small_eigh, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              152 * 1024);
+    (void)hipGetLastError();
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_small_eigh, dim3(1), dim3(512), eig_lds_bytes(p, 1), s, a, p, evals, evecs,
+                     sweeps);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// SVQB (Stathopoulos-Wu) coefficient for an n x n overlap M: X <- X U S^-1/2,
+// eigenvalues clamped below eps * max.  Writes the n x n coefficient to Cf.
+// Uses Ws (2 * n * (n+1) doubles) as Jacobi workspace.
+__device__ bool blk_svqb_coef(const double* M, int ldm, int n, double* Cf, int ldc, double* Ws,
+                              double* cs, int* pr, int* flag, int* perm, double* scratch) {
+  const int ld = n + 1;
+  double* A = Ws;
+  double* U = Ws + n * ld;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx - i * n;
+    A[i * ld + j] = M[i * ldm + j];
+  }
+  __syncthreads();
+  blk_jacobi(A, ld, U, ld, n, cs, pr, flag, scratch);
+  double smax = 0.0;
+  for (int i = 0; i < n; ++i) smax = fmax(smax, A[i * ld + i]);
+  if (!(smax > 0.0)) return false;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx - i * n;
+    const double sj = fmax(A[j * ld + j], kEps * smax);
+    Cf[i * ldc + j] = U[i * ld + j] / sqrt(sj);
+  }
+  __syncthreads();
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Rayleigh-Ritz coefficients (Alg. 1): eig of sym(a); u_x = lowest m
+// eigenvectors; optionally u_p = ortho(u_x[:, a0:m] - E[:, a0:m]; u_x) in R^p
+// by Alg. 3 / Alg. 2 (the same readings as on n-vectors).
+
+__global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ a, int p, int m,
+                                                  int a0, int want_up, double tau,
+                                                  double* __restrict__ theta_all,
+                                                  double* __restrict__ U, int* __restrict__ info) {
+  extern __shared__ double smem[];
+  EigLds L = eig_lds(smem, p, m);
+  const int ld = p + 1;
+  __shared__ ShiftCount cnt;
+  __shared__ int zeros;
+  __shared__ int stalled, passes, grams, updates;
+  if (threadIdx.x == 0) {
+    cnt.factorizations = cnt.failed = cnt.shifted = cnt.svqb = 0;
+    zeros = stalled = passes = grams = updates = 0;
+  }
+  load_sym(a, p, L.A, ld);
+  const int sw = blk_jacobi(L.A, ld, L.V, ld, p, L.cs, L.pr, L.flags, L.scratch);
+  blk_sort_evals(L.A, ld, p, L.perm);
+  for (int j = threadIdx.x; j < p; j += blockDim.x) theta_all[j] = L.A[L.perm[j] * ld + L.perm[j]];
+  __syncthreads();
+  // sorted eigenvectors into the A area (stride ld): Us[:, j] = V[:, perm[j]]
+  double* Us = L.A;
+  for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
+    const int i = idx / p, j = idx - i * p;
+    Us[i * ld + j] = L.V[i * ld + L.perm[j]];
+  }
+  __syncthreads();
+  const int na = want_up ? (m - a0) : 0;
+  const int q = m + na;
+  // u_x
+  for (int idx = threadIdx.x; idx < p * m; idx += blockDim.x) {
+    const int i = idx / m, j = idx - i * m;
+    U[i * q + j] = Us[i * ld + j];
+  }
+  int bad = 0;
+  if (na > 0) {
+    // V area becomes: X (p x na), C (m x na), M (na x na), Lc (na x na), Li, svqb workspace
+    double* X = L.V;
+    const int ldx = na;
+    double* C = X + p * na;
+    double* M = C + m * na;
+    double* Lc = M + na * na;
+    double* Ws = Lc + na * na;
+    // u~_p = u_x[:, a0:m] - E[:, a0:m]
+    for (int idx = threadIdx.x; idx < p * na; idx += blockDim.x) {
+      const int i = idx / na, j = idx - i * na;
+      X[i * ldx + j] = Us[i * ld + a0 + j] - ((i == a0 + j) ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    blk_normalize(X, ldx, p, na, L.cs, &zeros);
+    blk_gemm_tn(Us, ld, X, ldx, p, m, na, C, na);  // C = u_x^T X
+    for (int pass = 0; pass < 4; ++pass) {
+      if (threadIdx.x == 0) passes++;
+      blk_sub_mm(X, ldx, Us, ld, C, na, p, m, na);
+      // ortho(X): normalise, then Gram / check / shifted Cholesky / X L^-T
+      blk_normalize(X, ldx, p, na, L.cs, &zeros);
+      for (int it = 0; it < 6; ++it) {
+        blk_gemm_tn(X, ldx, X, ldx, p, na, na, M, na);
+        if (threadIdx.x == 0) grams++;
+        double dev = 0.0;
+        for (int idx = threadIdx.x; idx < na * na; idx += blockDim.x) {
+          const int i = idx / na, j = idx - i * na;
+          const double v = 0.5 * (M[i * na + j] + M[j * na + i]) - (i == j ? 1.0 : 0.0);
+          dev = fmax(dev, fabs(v));
+        }
+        dev = blk_reduce_max(dev, L.scratch);
+        if (dev <= tau) break;
+        if (it == 5) {
+          if (threadIdx.x == 0) stalled++;
+          break;
+        }
+        for (int idx = threadIdx.x; idx < na * na; idx += blockDim.x) {
+          const int i = idx / na, j = idx - i * na;
+          M[idx] = 0.5 * (M[i * na + j] + M[j * na + i]);
+        }
+        __syncthreads();
+        // symmetrised copy is in place; compute Cholesky
+        if (blk_shifted_chol(M, na, na, Lc, na, L.flags, &cnt, L.scratch)) {
+          blk_trsm_rt(X, ldx, p, na, Lc, na);
+        } else {
+          if (threadIdx.x == 0) cnt.svqb++;
+          if (!blk_svqb_coef(M, na, na, Lc, na, Ws, L.cs, L.pr, L.flags, L.perm, L.scratch)) {
+            bad = 1;
+            break;
+          }
+          // X <- X Cf (Cf in Lc); use Ws as row buffer
+          for (int r = threadIdx.x; r < p; r += blockDim.x) {
+            double row[kMaxBlock];
+            for (int j = 0; j < na; ++j) row[j] = X[r * ldx + j];
+            for (int j = 0; j < na; ++j) {
+              double s = 0.0;
+              for (int k = 0; k < na; ++k) s += row[k] * Lc[k * na + j];
+              X[r * ldx + j] = s;
+            }
+          }
+          __syncthreads();
+        }
+        if (threadIdx.x == 0) updates++;
+      }
+      if (bad) break;
+      blk_gemm_tn(Us, ld, X, ldx, p, m, na, C, na);
+      double cm = 0.0;
+      for (int idx = threadIdx.x; idx < m * na; idx += blockDim.x) cm = fmax(cm, fabs(C[idx]));
+      cm = blk_reduce_max(cm, L.scratch);
+      if (cm <= tau) break;
+      if (pass == 3 && threadIdx.x == 0) stalled++;
+    }
+    for (int idx = threadIdx.x; idx < p * na; idx += blockDim.x) {
+      const int i = idx / na, j = idx - i * na;
+      U[i * q + m + j] = X[i * ldx + j];
+    }
+  }
+  if (threadIdx.x == 0) {
+    info[0] = sw;
+    info[1] = bad;
+    info[2] = grams;
+    info[3] = cnt.factorizations;
+    info[4] = cnt.failed;
+    info[5] = cnt.shifted;
+    info[6] = updates;
+    info[7] = passes;
+    info[8] = stalled;
+    info[9] = cnt.svqb;
+    info[10] = zeros;
+  }
+}
+
+hipError_t small_rr(const double* a, int p, int m, int a0, int want_up, double tau,
+                    double* theta_all, double* U, int* info, hipStream_t s) {
+  if (p < 1 || p > kMaxP || m < 1 || m > p || a0 < 0 || a0 > m) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    // dynamic + static LDS must stay within the 160 KB of a workgroup
+    (void)hipFuncSetAttribute((const void*)k_small_rr, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              152 * 1024);
+    (void)hipGetLastError();
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(512), eig_lds_bytes(p, m), s, a, p, m, a0, want_up, tau,
+                     theta_all, U, info);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// standalone shifted Cholesky (p <= 64)
+
+__global__ __launch_bounds__(256) void k_small_chol(const double* __restrict__ M, int p,
+                                                    double* __restrict__ Lout, int* info) {
+  __shared__ double Ms[64 * 65];
+  __shared__ double Ls[64 * 65];
+  __shared__ double scratch[16];
+  __shared__ int flag;
+  __shared__ ShiftCount cnt;
+  if (threadIdx.x == 0) cnt.factorizations = cnt.failed = cnt.shifted = cnt.svqb = 0;
+  for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
+    const int i = idx / p, j = idx - i * p;
+    Ms[i * 65 + j] = 0.5 * (M[i * p + j] + M[j * p + i]);
+  }
+  __syncthreads();
+  const bool ok = blk_shifted_chol(Ms, 65, p, Ls, 65, &flag, &cnt, scratch);
+  for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
+    const int i = idx / p, j = idx - i * p;
+    Lout[idx] = ok ? Ls[i * 65 + j] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    info[0] = ok ? 0 : 1;
+    info[1] = cnt.factorizations;
+    info[2] = cnt.failed;
+    info[3] = cnt.shifted;
+  }
+}
+
+hipError_t small_cholesky(const double* M, int p, double* L, int* info, hipStream_t s) {
+  if (p < 1 || p > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(256), 0, s, M, p, L, info);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ortho(W; Y) controller.  G = [Y W]^T W, (ny + nw) x nw: rows [0, ny) are
+// C = Y^T W, rows [ny, ny+nw) are M = W^T W.  The coefficient written to
+// `coef` ((ny+nw) x nw) is applied by the streaming kernel as
+// W <- [Y W] coef, after which G is recomputed and this kernel runs again.
+//
+// Phases (reading of Alg. 3 as a do-while around Alg. 2, both with column
+// normalisation first):
+//   START  raw W~: normalise (D0) and project: coef = [-C D0; D0]
+//          (no Y: behave as BEGIN)
+//   BEGIN  start of ortho(X): D = diag(M)^-1/2, M' = D M D;
+//          ||M' - I|| <= tau -> ortho done on X = W D: Alg. 3 check on C D;
+//          else shifted Cholesky M' = L L^T, coef = [0; D L^-T] -> LOOP
+//   LOOP   ||M - I|| <= tau (or pass cap) -> Alg. 3 check on C;
+//          else shifted Cholesky, coef = [0; L^-T]
+//   Alg. 3 check: ||C|| <= tau (or no Y) -> finished; else project
+//          coef = [-C; I] (scaled by the pending D) -> BEGIN
+//   FINAL  a pending diagonal scaling was applied: finished.
+
+enum { kPhFinal = 5 };
+
+__global__ __launch_bounds__(256) void k_ortho_ctl(const double* __restrict__ G,
+                                                   OrthoState* __restrict__ gst,
+                                                   double* __restrict__ coef) {
+  __shared__ OrthoState st;
+  __shared__ double Gs[kMaxP * kMaxBlock];
+  __shared__ double Ms[kMaxBlock * (kMaxBlock + 1)];
+  __shared__ double Ls[kMaxBlock * (kMaxBlock + 1)];
+  __shared__ double Li[kMaxBlock * (kMaxBlock + 1)];
+  __shared__ double Ws[2 * kMaxBlock * (kMaxBlock + 1)];
+  __shared__ double D[kMaxBlock];
+  __shared__ double cs[2 * 64];
+  __shared__ int pr[2 * 64];
+  __shared__ int perm[64];
+  __shared__ double scratch[16];
+  __shared__ int flag, nonfinite, zero_mask;
+  __shared__ ShiftCount cnt;
+  if (threadIdx.x == 0) {
+    st = *gst;
+    nonfinite = 0;
+    zero_mask = 0;
+    cnt.factorizations = cnt.failed = cnt.shifted = cnt.svqb = 0;
+  }
+  __syncthreads();
+  if (st.done) return;
+  const int ny = st.ny, nw = st.nw, nr = ny + nw;
+  const int ldm = kMaxBlock + 1;
+  for (int idx = threadIdx.x; idx < nr * nw; idx += blockDim.x) {
+    const double v = G[idx];
+    Gs[idx] = v;
+    if (!isfinite(v)) nonfinite = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) st.grams++;
+  if (st.state == kPhFinal) {
+    if (threadIdx.x == 0) {
+      st.done = 1;
+      st.state = kPhDone;
+      *gst = st;
+    }
+    return;
+  }
+  if (nonfinite) {
+    if (threadIdx.x == 0) {
+      st.error = kOrthoErrNonfinite;
+      st.done = 1;
+      *gst = st;
+    }
+    return;
+  }
+  // symmetrised M
+  for (int idx = threadIdx.x; idx < nw * nw; idx += blockDim.x) {
+    const int i = idx / nw, j = idx - i * nw;
+    Ms[i * ldm + j] = 0.5 * (Gs[(ny + i) * nw + j] + Gs[(ny + j) * nw + i]);
+  }
+  __syncthreads();
+  int phase = st.state;
+  if (phase == kPhStart && ny == 0) phase = kPhBegin;
+
+  // helper lambdas are avoided: explicit code per phase
+  bool check_outer = false;
+  bool have_scale = false;  // D pending (BEGIN passed its check)
+  if (phase == kPhStart || phase == kPhBegin) {
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+      const double d = Ms[j * ldm + j];
+      if (d == 0.0) atomicOr(&zero_mask, 1 << j);
+      D[j] = (d > 0.0) ? 1.0 / sqrt(d) : 0.0;
+    }
+    __syncthreads();
+    if (zero_mask) {
+      if (threadIdx.x == 0) {
+        st.error = kOrthoErrZero;
+        st.zero_mask = zero_mask;
+        st.done = 1;
+        *gst = st;
+      }
+      return;
+    }
+  }
+  if (phase == kPhStart) {
+    // normalise + first projection (Alg. 3, first pass)
+    for (int idx = threadIdx.x; idx < nr * nw; idx += blockDim.x) {
+      const int i = idx / nw, j = idx - i * nw;
+      coef[idx] = (i < ny) ? -Gs[i * nw + j] * D[j] : ((i - ny == j) ? D[j] : 0.0);
+    }
+    if (threadIdx.x == 0) {
+      st.passes++;
+      st.outer = 1;
+      st.w_only = 0;
+      st.state = kPhBegin;
+      *gst = st;
+    }
+    return;
+  }
+  if (phase == kPhBegin) {
+    // M' = D M D, Alg. 2 check on the normalised X
+    for (int idx = threadIdx.x; idx < nw * nw; idx += blockDim.x) {
+      const int i = idx / nw, j = idx - i * nw;
+      Ms[i * ldm + j] *= D[i] * D[j];
+    }
+    if (threadIdx.x == 0) st.inner = 1;
+    __syncthreads();
+  } else if (phase == kPhLoop) {
+    if (threadIdx.x == 0) st.inner++;
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) D[j] = 1.0;
+    __syncthreads();
+  }
+  double dev = 0.0;
+  for (int idx = threadIdx.x; idx < nw * nw; idx += blockDim.x) {
+    const int i = idx / nw, j = idx - i * nw;
+    dev = fmax(dev, fabs(Ms[i * ldm + j] - (i == j ? 1.0 : 0.0)));
+  }
+  dev = blk_reduce_max(dev, scratch);
+  const bool ortho_ok = dev <= st.tau;
+  const bool capped = !ortho_ok && st.inner >= st.max_inner;
+  if (ortho_ok || capped) {
+    if (capped && threadIdx.x == 0) st.stalled++;
+    check_outer = true;
+    have_scale = (phase == kPhBegin);
+  } else {
+    // shifted Cholesky of M (= M' in BEGIN)
+    const bool ok = blk_shifted_chol(Ms, ldm, nw, Ls, ldm, &flag, &cnt, scratch);
+    if (ok) {
+      blk_tri_inv(Ls, ldm, nw, Li, ldm);
+      // coef W part: D L^-T, i.e. coef[ny+i][j] = D_i Linv[j][i]
+      for (int idx = threadIdx.x; idx < nr * nw; idx += blockDim.x) {
+        const int i = idx / nw, j = idx - i * nw;
+        coef[idx] = (i < ny) ? 0.0 : D[i - ny] * Li[j * ldm + (i - ny)];
+      }
+    } else {
+      if (threadIdx.x == 0) cnt.svqb++;
+      const bool sv = blk_svqb_coef(Ms, ldm, nw, Li, ldm, Ws, cs, pr, &flag, perm, scratch);
+      if (!sv) {
+        if (threadIdx.x == 0) {
+          st.error = kOrthoErrFailed;
+          st.done = 1;
+          st.factorizations += cnt.factorizations;
+          st.failed += cnt.failed;
+          *gst = st;
+        }
+        return;
+      }
+      for (int idx = threadIdx.x; idx < nr * nw; idx += blockDim.x) {
+        const int i = idx / nw, j = idx - i * nw;
+        coef[idx] = (i < ny) ? 0.0 : D[i - ny] * Li[(i - ny) * ldm + j];
+      }
+    }
+    if (threadIdx.x == 0) {
+      st.factorizations += cnt.factorizations;
+      st.failed += cnt.failed;
+      st.shifted += cnt.shifted;
+      st.svqb += cnt.svqb;
+      st.updates++;
+      st.w_only = 1;
+      st.state = kPhLoop;
+      *gst = st;
+    }
+    return;
+  }
+  // Alg. 3 check on C D (D = 1 unless BEGIN's normalisation is pending)
+  double cm = 0.0;
+  for (int idx = threadIdx.x; idx < ny * nw; idx += blockDim.x) {
+    const int j = idx % nw;
+    cm = fmax(cm, fabs(Gs[idx] * D[j]));
+  }
+  cm = blk_reduce_max(cm, scratch);
+  const bool y_ok = (ny == 0) || (cm <= st.tau);
+  if (y_ok || st.outer >= st.max_outer) {
+    if (!y_ok && threadIdx.x == 0) st.stalled++;
+    if (have_scale) {
+      // apply the pending normalisation, then finish
+      for (int idx = threadIdx.x; idx < nr * nw; idx += blockDim.x) {
+        const int i = idx / nw, j = idx - i * nw;
+        coef[idx] = (i < ny) ? 0.0 : ((i - ny == j) ? D[j] : 0.0);
+      }
+      if (threadIdx.x == 0) {
+        st.w_only = 1;
+        st.state = kPhFinal;
+        *gst = st;
+      }
+    } else if (threadIdx.x == 0) {
+      st.done = 1;
+      st.state = kPhDone;
+      *gst = st;
+    }
+    return;
+  }
+  // project again: W <- W D - Y (C D)
+  for (int idx = threadIdx.x; idx < nr * nw; idx += blockDim.x) {
+    const int i = idx / nw, j = idx - i * nw;
+    coef[idx] = (i < ny) ? -Gs[i * nw + j] * D[j] : ((i - ny == j) ? D[j] : 0.0);
+  }
+  if (threadIdx.x == 0) {
+    st.passes++;
+    st.outer++;
+    st.w_only = 0;
+    st.state = kPhBegin;
+    *gst = st;
+  }
+}
+
+__global__ void k_ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner,
+                             int max_outer) {
+  OrthoState s;
+  s.state = kPhStart;
+  s.done = 0;
+  s.inner = 0;
+  s.outer = 0;
+  s.w_only = 0;
+  s.error = 0;
+  s.zero_mask = 0;
+  s.grams = s.factorizations = s.failed = s.shifted = s.updates = s.stalled = s.svqb = s.passes = 0;
+  s.ny = ny;
+  s.nw = nw;
+  s.max_inner = max_inner;
+  s.max_outer = max_outer;
+  s.tau = tau;
+  *st = s;
+}
+
+hipError_t ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner, int max_outer,
+                      hipStream_t s) {
+  if (nw < 1 || nw > kMaxBlock || ny < 0 || ny + nw > kMaxP) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ortho_init, dim3(1), dim3(1), 0, s, st, ny, nw, tau, max_inner, max_outer);
+  return hipGetLastError();
+}
+
+hipError_t ortho_ctl(const double* G, OrthoState* st, double* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_ortho_ctl, dim3(1), dim3(256), 0, s, G, st, coef);
+  return hipGetLastError();
+}
+
+}  // namespace lobpcg

@@ -1,0 +1,782 @@
+// Host driver of the block LOBPCG (Alg. 1 of arXiv:2305.06668) and the C ABI
+// declared in include/lobpcg.h.
+//
+// Per iteration the host launches, on one stream:
+//   Gram a = V^T AV -> small RR kernel (Jacobi eig + u_p) -> rotate (X, AX,
+//   P, AP, R, W~ in one pass) -> [read back the m residual norms: the one
+//   per-iteration host sync] -> ortho(W~; [X P]) as rounds of
+//   (controller, block update, Gram) driven by device-side state -> the
+//   operator on W.
+// V = [X | P | W] and AV = [AX | AP | AW] are row-major blocks with leading
+// dimension m + np + nw, double-buffered; Y = [X | P] is a column prefix so
+// that ortho(W; Y) works on one buffer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lobpcg.h"
+#include "internal.h"
+
+using namespace lobpcg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kOrthoRounds = 6;     // controller rounds launched before the first check
+constexpr int kOrthoHardCap = 64;   // rounds before giving up
+constexpr size_t kPinnedBytes = 1 << 16;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+enum OpKind { kOpNone = 0, kOpCsr = 1, kOpDense = 2, kOpKron = 3 };
+
+struct Layout {
+  size_t V[2], AV[2], diag, part, small, total;
+  // inside small (byte offsets)
+  size_t a, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye;
+};
+
+}  // namespace
+
+struct lobpcg_ctx {
+  int64_t n = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // options
+  double tau = 1e-14;
+  int max_iter = 1000;
+  int precision = LOBPCG_PREC_FP64;
+  int ortho_max_inner = 6;
+  int ortho_max_outer = 4;
+  int trace = 0;
+  // operator
+  int op = kOpNone;
+  const int32_t* rp = nullptr;
+  const int32_t* ci = nullptr;
+  const double* val = nullptr;
+  int64_t nnz = 0;
+  const double* A = nullptr;
+  int64_t lda = 0;
+  int64_t na = 0;
+  const double* Vpot = nullptr;
+  // preconditioner
+  int pkind = LOBPCG_PRECOND_DIAG;
+  const double* user_diag = nullptr;
+  bool diag_ready = false;
+  // initial guess
+  const double* X0 = nullptr;
+  int64_t ldx0 = 0;
+  int block = 0;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout lay{};
+  int lay_block = -1;
+  // pinned host buffer
+  char* pinned = nullptr;
+  // results
+  bool have_result = false;
+  int res_k = 0;
+  const double* res_X = nullptr;
+  int64_t res_ld = 0;
+  std::vector<double> res_evals, res_resn;
+  lobpcg_stats stats{};
+  std::string err;
+
+  // ---- helpers ----
+  double* dptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
+  template <typename T> T* small_ptr(size_t off) const {
+    return reinterpret_cast<T*>(ws + lay.small + off);
+  }
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* where) {
+    err = std::string(where) + ": " + hipGetErrorString(e);
+    return LOBPCG_ERR_DEVICE;
+  }
+  Layout plan(int m) const;
+  int ensure_layout(int m);
+  int apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy);
+  int ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info);
+  int ensure_diag();
+  int true_residuals(const double* X, int64_t ldx, int m, double* scratch, const double* theta_rr,
+                     std::vector<double>& th, std::vector<double>& rn);
+  int solve(int k, double tol);
+};
+
+#define HIPCHK(expr)                                  \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+Layout lobpcg_ctx::plan(int m) const {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const size_t blk = (size_t)n * 3 * m * sizeof(double);
+  L.V[0] = take(blk);
+  L.V[1] = take(blk);
+  L.AV[0] = take(blk);
+  L.AV[1] = take(blk);
+  L.diag = take((size_t)n * sizeof(double));
+  const size_t gblk = (size_t)std::min<int64_t>(kGramBlocks, (n + 63) / 64) + 1;
+  const size_t part = std::max(gblk * kGramMaxCols * kGramMaxCols, (size_t)kStreamBlocks * 3 * 64);
+  L.part = take(part * sizeof(double));
+  // small area
+  size_t so = 0;
+  auto stake = [&](size_t bytes) {
+    const size_t o = so;
+    so = align_up(so + bytes);
+    return o;
+  };
+  L.a = stake(sizeof(double) * kGramMaxCols * kGramMaxCols);
+  L.theta = stake(sizeof(double) * kGramMaxCols);
+  L.U = stake(sizeof(double) * kMaxP * 64);
+  L.G = stake(sizeof(double) * kMaxP * kMaxBlock);
+  L.coef = stake(sizeof(double) * kMaxP * kMaxBlock);
+  L.resn2 = stake(sizeof(double) * 64);
+  L.cols = stake(sizeof(double) * 3 * 64);
+  L.info = stake(sizeof(int) * 64);
+  L.ost = stake(sizeof(OrthoState));
+  L.pidx = stake(sizeof(int64_t) * 256 * 64);
+  L.pval = stake(sizeof(double) * 256 * 64);
+  L.eye = stake(sizeof(double) * 64 * 64);
+  L.small = take(so);
+  L.total = off;
+  return L;
+}
+
+int lobpcg_ctx::ensure_layout(int m) {
+  if (ws == nullptr) return fail(LOBPCG_ERR_WORKSPACE, "no workspace set");
+  if (lay_block != m) {
+    Layout L = plan(m);
+    if (L.total > ws_bytes)
+      return fail(LOBPCG_ERR_WORKSPACE, "workspace smaller than lobpcg_workspace_size");
+    lay = L;
+    lay_block = m;
+    diag_ready = false;
+  }
+  return LOBPCG_OK;
+}
+
+int lobpcg_ctx::apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy) {
+  hipError_t e = hipSuccess;
+  switch (op) {
+    case kOpCsr: e = spmm_csr_f64(rp, ci, val, W, ldw, Y, ldy, nc, n, stream); break;
+    case kOpDense: e = dense_apply_f64(A, lda, W, ldw, Y, ldy, nc, n, stream); break;
+    case kOpKron: e = kronsum_apply_f64(A, Vpot, na, W, ldw, Y, ldy, nc, stream); break;
+    default: return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+  }
+  if (e != hipSuccess) return hip_fail(e, "operator");
+  stats.matvec_columns += nc;
+  return LOBPCG_OK;
+}
+
+int lobpcg_ctx::ensure_diag() {
+  if (diag_ready) return LOBPCG_OK;
+  double* d = dptr(lay.diag);
+  if (user_diag != nullptr) {
+    HIPCHK(hipMemcpyAsync(d, user_diag, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+  } else {
+    switch (op) {
+      case kOpCsr: HIPCHK(csr_diag(rp, ci, val, n, d, stream)); break;
+      case kOpDense: HIPCHK(dense_diag(A, lda, n, d, stream)); break;
+      case kOpKron: HIPCHK(kronsum_diag(A, Vpot, na, d, stream)); break;
+      default: return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+    }
+  }
+  diag_ready = true;
+  return LOBPCG_OK;
+}
+
+// ortho(W; Y) (Alg. 3 around Alg. 2) on base = [Y | W] rows, ld.
+int lobpcg_ctx::ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info) {
+  OrthoState* st = small_ptr<OrthoState>(lay.ost);
+  double* G = small_ptr<double>(lay.G);
+  double* coef = small_ptr<double>(lay.coef);
+  double* part = dptr(lay.part);
+  OrthoState* hst = reinterpret_cast<OrthoState*>(pinned);
+  const int nr = ny + nw;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    HIPCHK(ortho_init(st, ny, nw, tau, ortho_max_inner, ortho_max_outer, stream));
+    HIPCHK(gram_f64(base, ld, nr, base + ny, ld, nw, n, part, G, nullptr, stream));
+    int rounds = 0;
+    bool finished = false;
+    while (!finished) {
+      const int batch = (rounds == 0) ? kOrthoRounds : 2;
+      for (int r = 0; r < batch; ++r) {
+        HIPCHK(ortho_ctl(G, st, coef, stream));
+        HIPCHK(tsmm_f64(base, ld, nr, coef, nw, base + ny, ld, n, &st->done, stream));
+        HIPCHK(gram_f64(base, ld, nr, base + ny, ld, nw, n, part, G, &st->done, stream));
+      }
+      rounds += batch;
+      HIPCHK(hipMemcpyAsync(hst, st, sizeof(OrthoState), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      if (hst->done) finished = true;
+      else if (rounds >= kOrthoHardCap) return fail(LOBPCG_ERR_ORTHO_FAILED, "ortho did not finish");
+    }
+    OrthoState s = *hst;
+    stats.ortho_grams += s.grams;
+    stats.ortho_factorizations += s.factorizations;
+    stats.ortho_failed += s.failed;
+    stats.ortho_shifted += s.shifted;
+    stats.ortho_stalled += s.stalled;
+    stats.ortho_svqb += s.svqb;
+    stats.against_passes += s.passes;
+    if (info != nullptr) {
+      info->grams += s.grams;
+      info->factorizations += s.factorizations;
+      info->failed += s.failed;
+      info->shifted += s.shifted;
+      info->updates += s.updates;
+      info->passes += s.passes;
+      info->stalled += s.stalled;
+      info->svqb += s.svqb;
+    }
+    if (s.error == 0) return LOBPCG_OK;
+    if (s.error == kOrthoErrNonfinite) return fail(LOBPCG_ERR_NONFINITE, "non-finite overlap");
+    if (s.error == kOrthoErrFailed) return fail(LOBPCG_ERR_ORTHO_FAILED, "shifted Cholesky and SVQB failed");
+    // exact zero columns: replace by SplitMix64 columns and start again
+    for (int j = 0; j < nw; ++j)
+      if (s.zero_mask & (1 << j))
+        HIPCHK(fill_splitmix(base + ny, ld, j, j, n, kZeroColumnSeed, stream));
+  }
+  return fail(LOBPCG_ERR_ORTHO_FAILED, "zero columns persist");
+}
+
+int lobpcg_ctx::true_residuals(const double* X, int64_t ldx, int m, double* scratch,
+                               const double* theta_rr, std::vector<double>& th,
+                               std::vector<double>& rn) {
+  int rc = apply_op(X, ldx, m, scratch, m);
+  if (rc) return rc;
+  double* cols = small_ptr<double>(lay.cols);
+  double* thd = small_ptr<double>(lay.theta) + 64;  // second theta slot
+  double* part = dptr(lay.part);
+  double* h = reinterpret_cast<double*>(pinned);
+  HIPCHK(colstats_f64(X, ldx, scratch, m, m, theta_rr, n, part, cols, stream));
+  HIPCHK(hipMemcpyAsync(h, cols, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  th.assign(m, 0.0);
+  for (int j = 0; j < m; ++j) th[j] = h[m + j] / h[j];
+  std::vector<double> tmp(th);
+  HIPCHK(hipMemcpyAsync(thd, tmp.data(), sizeof(double) * m, hipMemcpyHostToDevice, stream));
+  HIPCHK(colstats_f64(X, ldx, scratch, m, m, thd, n, part, cols, stream));
+  HIPCHK(hipMemcpyAsync(h, cols, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  rn.assign(m, 0.0);
+  for (int j = 0; j < m; ++j) rn[j] = std::sqrt(h[2 * m + j]);
+  stats.true_checks++;
+  return LOBPCG_OK;
+}
+
+static int leading_converged(const std::vector<double>& r, double tol) {
+  int c = 0;
+  for (double v : r) {
+    if (v <= tol) ++c;
+    else break;
+  }
+  return c;
+}
+
+int lobpcg_ctx::solve(int k, double tol) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (op == kOpNone) return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+  const int m = block;
+  if (m < 1) return fail(LOBPCG_ERR_BAD_STATE, "block size unknown: set an initial guess or query the workspace");
+  if (k < 1 || k > m) return fail(LOBPCG_ERR_INVALID_ARG, "need 1 <= k <= block");
+  if (!(tol > 0.0)) return fail(LOBPCG_ERR_INVALID_ARG, "tol must be > 0");
+  if (precision != LOBPCG_PREC_FP64) return fail(LOBPCG_ERR_UNSUPPORTED, "precision mode not built");
+  int rc = ensure_layout(m);
+  if (rc) return rc;
+  std::memset(&stats, 0, sizeof(stats));
+  stats.precision_switch_iter = -1;
+  have_result = false;
+  if (pkind != LOBPCG_PRECOND_NONE) {
+    rc = ensure_diag();
+    if (rc) return rc;
+  }
+  double* V[2] = {dptr(lay.V[0]), dptr(lay.V[1])};
+  double* AV[2] = {dptr(lay.AV[0]), dptr(lay.AV[1])};
+  double* a = small_ptr<double>(lay.a);
+  double* theta = small_ptr<double>(lay.theta);
+  double* U = small_ptr<double>(lay.U);
+  double* resn2 = small_ptr<double>(lay.resn2);
+  int* info = small_ptr<int>(lay.info);
+  double* part = dptr(lay.part);
+  double* h = reinterpret_cast<double*>(pinned);
+
+  // ---- initial block (Alg. 1 input; reading: orthonormalise X0 first) ----
+  if (X0 != nullptr) {
+    HIPCHK(hipMemcpy2DAsync(V[0], sizeof(double) * m, X0, sizeof(double) * ldx0,
+                            sizeof(double) * m, n, hipMemcpyDeviceToDevice, stream));
+  } else {
+    for (int j = 0; j < m; ++j) HIPCHK(fill_splitmix(V[0], m, j, j, n, kDefaultX0Seed, stream));
+  }
+  rc = ortho_run(V[0], m, 0, m, nullptr);
+  if (rc) return rc;
+  rc = apply_op(V[0], m, m, AV[0], m);
+  if (rc) return rc;
+
+  int c = 0;           // current buffer
+  int L = m;           // its leading dimension (= number of columns in V)
+  bool first = true;   // V = [X] only (initial RR, or restart after a true check)
+  int m_conv = 0;
+  int iter = 0;
+  bool converged = false;
+  std::vector<double> rnorm(m), th_rr(m), th_t, rn_t;
+  const double* Xres = nullptr;
+  int64_t Xld = 0;
+  for (;;) {
+    // ---- Rayleigh-Ritz in V (Alg. 1) ----
+    HIPCHK(gram_f64(V[c], L, L, AV[c], L, L, n, part, a, nullptr, stream));
+    const int want_up = first ? 0 : 1;
+    int a0 = m_conv;
+    int nact = m - a0;
+    HIPCHK(small_rr(a, L, m, a0, want_up, tau, theta, U, info, stream));
+    int q = m + (want_up ? nact : 0);
+    int ldo = q + nact;
+    RotateArgs ra{};
+    ra.n = n;
+    ra.ldv = L;
+    ra.ldo = ldo;
+    ra.p = L;
+    ra.m = m;
+    ra.q = q;
+    ra.a0 = a0;
+    ra.precond = pkind;
+    ra.U = U;
+    ra.theta = theta;
+    ra.diag = dptr(lay.diag);
+    ra.part = part;
+    ra.resnorm2 = resn2;
+    HIPCHK(rotate_f64(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
+    HIPCHK(hipMemcpyAsync(h, resn2, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(h + 64, theta, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(h + 128, info, sizeof(int) * 16, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    const int* hinfo = reinterpret_cast<const int*>(h + 128);
+    if (hinfo[1] != 0) return fail(LOBPCG_ERR_ORTHO_FAILED, "R^p orthonormalisation of u_p failed");
+    for (int j = 0; j < m; ++j) {
+      rnorm[j] = std::sqrt(h[j]);
+      th_rr[j] = h[64 + j];
+      if (!std::isfinite(rnorm[j]) || !std::isfinite(th_rr[j]))
+        return fail(LOBPCG_ERR_NONFINITE, "non-finite Ritz value or residual");
+    }
+    const int newc = std::max(m_conv, leading_converged(rnorm, tol));
+    if (newc >= k) {
+      // reading R9: judge with an explicit product A X
+      rc = true_residuals(V[1 - c], ldo, m, AV[c], theta, th_t, rn_t);
+      if (rc) return rc;
+      double worst = 0.0;
+      for (int j = 0; j < k; ++j) worst = std::max(worst, rn_t[j]);
+      if (worst <= tol) {
+        converged = true;
+        Xres = V[1 - c];
+        Xld = ldo;
+        break;
+      }
+      // restart from X with the explicit product: V = [X], AV = [A X]
+      HIPCHK(hipMemcpy2DAsync(V[c], sizeof(double) * m, V[1 - c], sizeof(double) * ldo,
+                              sizeof(double) * m, n, hipMemcpyDeviceToDevice, stream));
+      L = m;
+      first = true;
+      m_conv = 0;
+      continue;
+    }
+    if (newc != m_conv) {
+      // locking changed the active set: rebuild u_p, P and W~ for it
+      stats.relocks++;
+      m_conv = newc;
+      a0 = m_conv;
+      nact = m - a0;
+      HIPCHK(small_rr(a, L, m, a0, want_up, tau, theta, U, info, stream));
+      q = m + (want_up ? nact : 0);
+      ldo = q + nact;
+      ra.ldo = ldo;
+      ra.q = q;
+      ra.a0 = a0;
+      HIPCHK(rotate_f64(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
+    }
+    if (iter >= max_iter) {
+      rc = true_residuals(V[1 - c], ldo, m, AV[c], theta, th_t, rn_t);
+      if (rc) return rc;
+      Xres = V[1 - c];
+      Xld = ldo;
+      break;
+    }
+    ++iter;
+    // ---- W = ortho(T R; [X P]) and AW = A W (Alg. 1) ----
+    rc = ortho_run(V[1 - c], ldo, q, nact, nullptr);
+    if (rc) return rc;
+    rc = apply_op(V[1 - c] + q, ldo, nact, AV[1 - c] + q, ldo);
+    if (rc) return rc;
+    c = 1 - c;
+    L = ldo;
+    first = false;
+  }
+  res_k = k;
+  res_X = Xres;
+  res_ld = Xld;
+  res_evals.assign(th_t.begin(), th_t.begin() + m);
+  res_resn.assign(rn_t.begin(), rn_t.begin() + m);
+  have_result = true;
+  stats.iterations = iter;
+  stats.converged = converged ? 1 : 0;
+  stats.m_conv = m_conv;
+  stats.ms_total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return converged ? LOBPCG_OK : LOBPCG_NOT_CONVERGED;
+}
+
+// ===========================================================================
+// C ABI
+
+#define GUARD(h)                                          \
+  if ((h) == nullptr) return LOBPCG_ERR_INVALID_ARG;      \
+  hipError_t dev_e_ = hipSetDevice((h)->device);          \
+  if (dev_e_ != hipSuccess) return (h)->hip_fail(dev_e_, "hipSetDevice");
+
+extern "C" {
+
+int lobpcg_create(int64_t n, int device, lobpcg_t* out) {
+  if (out == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n < 1) return LOBPCG_ERR_INVALID_ARG;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return LOBPCG_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return LOBPCG_ERR_DEVICE;
+  lobpcg_ctx* h = new (std::nothrow) lobpcg_ctx();
+  if (h == nullptr) return LOBPCG_ERR_DEVICE;
+  h->n = n;
+  h->device = device;
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->pinned), kPinnedBytes, hipHostMallocDefault) !=
+      hipSuccess) {
+    delete h;
+    return LOBPCG_ERR_DEVICE;
+  }
+  *out = h;
+  return LOBPCG_OK;
+}
+
+int lobpcg_destroy(lobpcg_t h) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  hipSetDevice(h->device);
+  if (h->pinned) hipHostFree(h->pinned);
+  delete h;
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_stream(lobpcg_t h, void* s) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  h->stream = reinterpret_cast<hipStream_t>(s);
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_option(lobpcg_t h, int key, double v) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  switch (key) {
+    case LOBPCG_OPT_TAU_ORTHO:
+      if (!(v > 0.0)) return h->fail(LOBPCG_ERR_INVALID_ARG, "tau must be > 0");
+      h->tau = v;
+      return LOBPCG_OK;
+    case LOBPCG_OPT_MAX_ITER:
+      if (v < 0 || v > 1e9) return h->fail(LOBPCG_ERR_INVALID_ARG, "bad max_iter");
+      h->max_iter = (int)v;
+      return LOBPCG_OK;
+    case LOBPCG_OPT_PRECISION:
+      if (v != LOBPCG_PREC_FP64 && v != LOBPCG_PREC_FP32)
+        return h->fail(LOBPCG_ERR_INVALID_ARG, "bad precision");
+      h->precision = (int)v;
+      return LOBPCG_OK;
+    case LOBPCG_OPT_ORTHO_MAX_PASSES:
+      if (v < 1 || v > 50) return h->fail(LOBPCG_ERR_INVALID_ARG, "bad pass cap");
+      h->ortho_max_inner = (int)v;
+      return LOBPCG_OK;
+    case LOBPCG_OPT_ORTHO_Y_MAX_PASSES:
+      if (v < 1 || v > 50) return h->fail(LOBPCG_ERR_INVALID_ARG, "bad pass cap");
+      h->ortho_max_outer = (int)v;
+      return LOBPCG_OK;
+    case LOBPCG_OPT_TRACE:
+      h->trace = (v != 0.0);
+      return LOBPCG_OK;
+    default: return h->fail(LOBPCG_ERR_INVALID_ARG, "unknown option");
+  }
+}
+
+int lobpcg_workspace_size(lobpcg_t h, int block, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  if (block < 1 || block > kMaxBlock || 3 * (int64_t)block > h->n)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "need 1 <= block <= 32 and 3*block <= n");
+  *bytes = h->plan(block).total;
+  if (h->X0 == nullptr) h->block = block;
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_workspace(lobpcg_t h, void* p, size_t bytes) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  if (p == nullptr || (reinterpret_cast<uintptr_t>(p) % kAlign) != 0)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
+  h->ws = reinterpret_cast<char*>(p);
+  h->ws_bytes = bytes;
+  h->lay_block = -1;
+  h->diag_ready = false;
+  h->have_result = false;
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_operator_csr(lobpcg_t h, const int32_t* row_ptr, const int32_t* col,
+                            const double* val, int64_t nnz) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  if (row_ptr == nullptr || (nnz > 0 && (col == nullptr || val == nullptr)) || nnz < 0 ||
+      nnz > INT32_MAX)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad CSR arrays");
+  {
+    // validate the structure on the device before any kernel indexes with it
+    hipError_t e = hipSetDevice(h->device);
+    int* bad = nullptr;
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&bad), sizeof(int));
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), h->stream);
+    if (e == hipSuccess) e = csr_check(row_ptr, col, h->n, nnz, bad, h->stream);
+    int hb = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (bad != nullptr) (void)hipFree(bad);
+    if (e != hipSuccess) return h->hip_fail(e, "CSR check");
+    if (hb != 0)
+      return h->fail(LOBPCG_ERR_INVALID_ARG,
+                     "malformed CSR (row_ptr must rise from 0 to nnz, columns in [0, n))");
+  }
+  h->op = kOpCsr;
+  h->rp = row_ptr;
+  h->ci = col;
+  h->val = val;
+  h->nnz = nnz;
+  h->diag_ready = false;
+  h->have_result = false;
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_operator_dense(lobpcg_t h, const double* A, int64_t lda) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  if (A == nullptr || lda < h->n) return h->fail(LOBPCG_ERR_INVALID_ARG, "bad dense operator");
+  h->op = kOpDense;
+  h->A = A;
+  h->lda = lda;
+  h->diag_ready = false;
+  h->have_result = false;
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_operator_kronsum(lobpcg_t h, int64_t na, const double* A, const double* V) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  if (A == nullptr || V == nullptr || na < 1 || na * na != h->n)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad Kronecker-sum operator (need na*na == n)");
+  h->op = kOpKron;
+  h->A = A;
+  h->na = na;
+  h->Vpot = V;
+  h->diag_ready = false;
+  h->have_result = false;
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_preconditioner(lobpcg_t h, int kind, const double* diag) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  if (kind != LOBPCG_PRECOND_NONE && kind != LOBPCG_PRECOND_DIAG &&
+      kind != LOBPCG_PRECOND_DIAG_SIGNED)
+    return h->fail(LOBPCG_ERR_UNSUPPORTED, "preconditioner kind not available");
+  h->pkind = kind;
+  h->user_diag = diag;
+  h->diag_ready = false;
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_initial_guess(lobpcg_t h, const double* X0, int64_t ld, int block) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  if (X0 == nullptr || block < 1 || block > kMaxBlock || ld < block || 3 * (int64_t)block > h->n)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad initial guess (block <= 32, 3*block <= n)");
+  h->X0 = X0;
+  h->ldx0 = ld;
+  h->block = block;
+  return LOBPCG_OK;
+}
+
+int lobpcg_solve(lobpcg_t h, int k, double tol) {
+  GUARD(h);
+  return h->solve(k, tol);
+}
+
+int lobpcg_get_eigenpairs(lobpcg_t h, int k, double* evals, double* evecs, int64_t ldv,
+                          double* resnorms) {
+  GUARD(h);
+  if (!h->have_result) return h->fail(LOBPCG_ERR_BAD_STATE, "no solve result");
+  if (k < 1 || k > (int)h->res_evals.size()) return h->fail(LOBPCG_ERR_INVALID_ARG, "bad k");
+  for (int j = 0; j < k; ++j) {
+    if (evals) evals[j] = h->res_evals[j];
+    if (resnorms) resnorms[j] = h->res_resn[j];
+  }
+  if (evecs != nullptr) {
+    if (ldv < k) return h->fail(LOBPCG_ERR_INVALID_ARG, "ldv < k");
+    hipError_t e = copy_signfix(h->res_X, h->res_ld, k, h->n, evecs, ldv,
+                                h->small_ptr<int64_t>(h->lay.pidx),
+                                h->small_ptr<double>(h->lay.pval), h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "copy_signfix");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "sync");
+  }
+  return LOBPCG_OK;
+}
+
+int lobpcg_get_stats(lobpcg_t h, lobpcg_stats* out) {
+  if (h == nullptr || out == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  *out = h->stats;
+  return LOBPCG_OK;
+}
+
+const char* lobpcg_status_string(int s) {
+  switch (s) {
+    case LOBPCG_OK: return "ok";
+    case LOBPCG_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case LOBPCG_ERR_INVALID_ARG: return "invalid argument";
+    case LOBPCG_ERR_BAD_STATE: return "bad call order";
+    case LOBPCG_ERR_DEVICE: return "HIP device error";
+    case LOBPCG_ERR_WORKSPACE: return "workspace missing or too small";
+    case LOBPCG_ERR_ORTHO_FAILED: return "orthonormalisation failed";
+    case LOBPCG_ERR_NONFINITE: return "non-finite values";
+    case LOBPCG_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* lobpcg_last_error(lobpcg_t h) {
+  if (h == nullptr) return "null handle";
+  return h->err.c_str();
+}
+
+// ---- step entry points ----------------------------------------------------
+
+int lobpcg_apply_operator(lobpcg_t h, const double* W, int64_t ldw, int ncols, double* Y,
+                          int64_t ldy) {
+  GUARD(h);
+  if (W == nullptr || Y == nullptr || ncols < 1 || ncols > 64 || ldw < ncols || ldy < ncols)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad apply arguments");
+  return h->apply_op(W, ldw, ncols, Y, ldy);
+}
+
+static int need_ws(lobpcg_t h) {
+  if (h->ws == nullptr) return h->fail(LOBPCG_ERR_WORKSPACE, "no workspace set");
+  const int m = h->lay_block > 0 ? h->lay_block : (h->block > 0 ? h->block : 1);
+  return h->ensure_layout(m);
+}
+
+int lobpcg_gram(lobpcg_t h, const double* A, int64_t lda, int p, const double* B, int64_t ldb,
+                int q, double* C) {
+  GUARD(h);
+  if (A == nullptr || B == nullptr || C == nullptr || p < 1 || q < 1 || p > kGramMaxCols ||
+      q > kGramMaxCols || lda < p || ldb < q)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad gram arguments");
+  int rc = need_ws(h);
+  if (rc) return rc;
+  hipError_t e = gram_f64(A, lda, p, B, ldb, q, h->n, h->dptr(h->lay.part), C, nullptr, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "gram");
+  return LOBPCG_OK;
+}
+
+int lobpcg_ortho(lobpcg_t h, double* X, int64_t ldx, int ncols, lobpcg_ortho_info* info) {
+  GUARD(h);
+  if (X == nullptr || ncols < 1 || ncols > kMaxBlock || ldx < ncols)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad ortho arguments");
+  int rc = need_ws(h);
+  if (rc) return rc;
+  if (info) std::memset(info, 0, sizeof(*info));
+  return h->ortho_run(X, ldx, 0, ncols, info);
+}
+
+int lobpcg_ortho_against(lobpcg_t h, double* X, int64_t ldx, int ncols, const double* Y,
+                         int64_t ldy, int ycols, lobpcg_ortho_info* info) {
+  GUARD(h);
+  if (X == nullptr || Y == nullptr || ncols < 1 || ncols > kMaxBlock || ycols < 0 ||
+      ycols + ncols > kMaxP || ldx < ycols + ncols || ldx != ldy || X != Y + ycols)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "ortho_against needs X == Y + ycols in one buffer");
+  int rc = need_ws(h);
+  if (rc) return rc;
+  if (info) std::memset(info, 0, sizeof(*info));
+  return h->ortho_run(const_cast<double*>(Y), ldx, ycols, ncols, info);
+}
+
+int lobpcg_small_eigh(lobpcg_t h, const double* a, int p, double* evals, double* evecs) {
+  GUARD(h);
+  if (a == nullptr || evals == nullptr || evecs == nullptr || p < 1 || p > kMaxP)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad small_eigh arguments");
+  hipError_t e = small_eigh(a, p, evals, evecs, nullptr, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "small_eigh");
+  return LOBPCG_OK;
+}
+
+int lobpcg_small_cholesky(lobpcg_t h, const double* M, int p, double* L, int* shifts) {
+  GUARD(h);
+  if (M == nullptr || L == nullptr || p < 1 || p > 64)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad small_cholesky arguments");
+  int rc = need_ws(h);
+  if (rc) return rc;
+  int* info = h->small_ptr<int>(h->lay.info);
+  hipError_t e = small_cholesky(M, p, L, info, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "small_cholesky");
+  int hi[4];
+  e = hipMemcpyAsync(hi, info, sizeof(hi), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "small_cholesky readback");
+  if (shifts) *shifts = hi[2];
+  return hi[0] == 0 ? LOBPCG_OK : h->fail(LOBPCG_ERR_ORTHO_FAILED, "all shifted retries failed");
+}
+
+int lobpcg_rotate(lobpcg_t h, const double* V, const double* AV, int64_t ldv, int p,
+                  const double* U, int m, int q, const double* theta, int a0, double* Vout,
+                  double* AVout, int64_t ldo, double* resnorm2) {
+  GUARD(h);
+  if (V == nullptr || AV == nullptr || U == nullptr || theta == nullptr || Vout == nullptr ||
+      AVout == nullptr || resnorm2 == nullptr || p < 1 || p > kMaxP || m < 1 || q < m || q > 64 ||
+      a0 < 0 || a0 > m || ldv < p || ldo < q + (m - a0))
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad rotate arguments");
+  int rc = need_ws(h);
+  if (rc) return rc;
+  if (h->pkind != LOBPCG_PRECOND_NONE) {
+    if (h->op == kOpNone && h->user_diag == nullptr)
+      return h->fail(LOBPCG_ERR_BAD_STATE, "preconditioner needs diag(A)");
+    rc = h->ensure_diag();
+    if (rc) return rc;
+  }
+  RotateArgs ra{};
+  ra.n = h->n;
+  ra.ldv = ldv;
+  ra.ldo = ldo;
+  ra.p = p;
+  ra.m = m;
+  ra.q = q;
+  ra.a0 = a0;
+  ra.precond = h->pkind;
+  ra.U = U;
+  ra.theta = theta;
+  ra.diag = h->dptr(h->lay.diag);
+  ra.part = h->dptr(h->lay.part);
+  ra.resnorm2 = resnorm2;
+  hipError_t e = rotate_f64(V, AV, Vout, AVout, ra, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "rotate");
+  return LOBPCG_OK;
+}
+
+}  // extern "C"

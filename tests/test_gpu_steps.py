@@ -1,0 +1,319 @@
+"""GPU parity of the individual steps (through the C ABI) against the CPU
+oracle or against the plain mathematical definition of the step.
+
+Tolerances: every step here is fp64.  A product or overlap over n rows is
+compared entry-wise within 1e-13 of the scale sum_k |a_ik| |b_kj| (the
+standard forward error bound ~ n eps times that scale, with the tree
+reduction's log2(n) factor well inside it for the sizes used); small dense
+results within 1e-12 of their norm.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import lobpcg_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_06668_amd as P
+
+    return P
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def make_solver(P, n, block=8):
+    s = P.Solver(n)
+    s.ensure_workspace(block)
+    return s
+
+
+@pytest.mark.parametrize("n,p,q", [(1000, 1, 1), (4097, 5, 17), (100003, 48, 48), (20011, 96, 32), (7, 3, 2), (333, 128, 128)])
+def test_gram(P, n, p, q):
+    say("gram", n, p, q)
+    g = synth.rng(n + p + q)
+    A = g.standard_normal((n, p))
+    B = g.standard_normal((n, q))
+    s = make_solver(P, max(n, 24))
+    # operate on the handle's n: pad to the handle size if needed
+    nn = s.n
+    Ap = np.zeros((nn, p)); Ap[:n] = A
+    Bp = np.zeros((nn, q)); Bp[:n] = B
+    C = torch.zeros((p, q), dtype=torch.float64, device="cuda")
+    P.lobpcg_gram(s.h, cu(Ap), cu(Bp), C)
+    ref = A.T @ B
+    scale = np.abs(A).T @ np.abs(B)
+    assert np.all(np.abs(host(C) - ref) <= 1e-13 * scale + 1e-300)
+
+
+def test_gram_strided_views(P):
+    n = 5003
+    g = synth.rng(3)
+    Vb = g.standard_normal((n, 40))
+    s = make_solver(P, n)
+    V = cu(Vb)
+    C = torch.zeros((30, 10), dtype=torch.float64, device="cuda")
+    P.lobpcg_gram(s.h, V[:, :30], V[:, 30:], C)
+    ref = Vb[:, :30].T @ Vb[:, 30:]
+    assert np.allclose(host(C), ref, rtol=0, atol=1e-11)
+
+
+def test_gram_deterministic(P):
+    n = 65537
+    g = synth.rng(9)
+    A = cu(g.standard_normal((n, 24)))
+    s = make_solver(P, n)
+    C1 = torch.zeros((24, 24), dtype=torch.float64, device="cuda")
+    C2 = torch.zeros_like(C1)
+    P.lobpcg_gram(s.h, A, A, C1)
+    P.lobpcg_gram(s.h, A, A, C2)
+    assert torch.equal(C1, C2)
+
+
+@pytest.mark.parametrize("m", [1, 3, 4, 8, 16, 17, 32, 40])
+def test_apply_csr(P, m):
+    say("apply_csr", m)
+    n = 30011
+    C = synth.csr_banded(n=n, seed=5, band=700, diag_slope=1e-3)
+    S = C.to_scipy()
+    W = synth.start_block(n, m, 7)
+    s = P.Solver(n)
+    s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val))
+    s.ensure_workspace(1)
+    Y = torch.zeros((n, m), dtype=torch.float64, device="cuda")
+    P.lobpcg_apply_operator(s.h, cu(W), Y)
+    ref = S @ W
+    scale = abs(S) @ np.abs(W)
+    assert np.all(np.abs(host(Y) - ref) <= 1e-14 * scale + 1e-300)
+
+
+def test_apply_csr_strided_and_empty_rows(P):
+    n = 4099
+    A = np.zeros((n, n))
+    idx = np.arange(0, n, 3)
+    A[idx, idx] = 1.0 + idx
+    A[idx[:-1], idx[1:]] = 0.5
+    A[idx[1:], idx[:-1]] = 0.5
+    C = synth.csr_from_dense(A)
+    # rows with only an explicit zero diagonal exist (csr_from_dense keeps them)
+    s = P.Solver(n)
+    s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val))
+    s.ensure_workspace(1)
+    Wb = synth.start_block(n, 12, 1)
+    W = cu(Wb)
+    Y = torch.zeros((n, 20), dtype=torch.float64, device="cuda")
+    P.lobpcg_apply_operator(s.h, W[:, 2:9], Y[:, 5:12])
+    out = host(Y)
+    assert np.allclose(out[:, 5:12], A @ Wb[:, 2:9], atol=1e-13)
+    assert np.all(out[:, :5] == 0) and np.all(out[:, 12:] == 0)
+
+
+@pytest.mark.parametrize("n,m", [(777, 1), (2000, 4), (1031, 8), (515, 11)])
+def test_apply_dense(P, n, m):
+    A = synth.dense_dd(n, seed=n)
+    W = synth.start_block(n, m, 2)
+    s = P.Solver(n)
+    s.set_operator_dense(cu(A))
+    s.ensure_workspace(1)
+    Y = torch.zeros((n, m), dtype=torch.float64, device="cuda")
+    P.lobpcg_apply_operator(s.h, cu(W), Y)
+    ref = A @ W
+    scale = np.abs(A) @ np.abs(W)
+    assert np.all(np.abs(host(Y) - ref) <= 1e-13 * scale)
+
+
+def test_apply_kronsum(P):
+    na, m = 19, 5
+    A, V = synth.kronsum(na=na, seed=4)
+    W = synth.start_block(na * na, m, 1)
+    s = P.Solver(na * na)
+    s.set_operator_kronsum(cu(A), cu(V))
+    s.ensure_workspace(1)
+    Y = torch.zeros((na * na, m), dtype=torch.float64, device="cuda")
+    P.lobpcg_apply_operator(s.h, cu(W), Y)
+    H = np.kron(A, np.eye(na)) + np.kron(np.eye(na), A) + np.diag(V.reshape(-1))
+    assert np.allclose(host(Y), H @ W, atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [2, 7, 24, 48, 96])
+def test_small_eigh(P, p):
+    say("small_eigh", p)
+    a = synth.random_symmetric(p, p) + 3.0 * np.diag(np.arange(p))
+    a[0, 1] += 1e-9  # not exactly symmetric: the kernel symmetrises
+    s = make_solver(P, 300)
+    ev = torch.zeros(p, dtype=torch.float64, device="cuda")
+    U = torch.zeros((p, p), dtype=torch.float64, device="cuda")
+    P.lobpcg_small_eigh(s.h, cu(a), ev, U)
+    lam, Uh = host(ev), host(U)
+    asym = 0.5 * (a + a.T)
+    ref = np.linalg.eigvalsh(asym)
+    nrm = np.linalg.norm(asym, 2)
+    assert np.all(np.abs(lam - ref) <= 1e-13 * nrm)
+    assert np.all(np.diff(lam) >= 0)
+    assert np.abs(Uh.T @ Uh - np.eye(p)).max() <= 1e-13
+    assert np.abs(asym @ Uh - Uh * lam).max() <= 1e-13 * nrm
+
+
+def test_small_eigh_degenerate(P):
+    p = 12
+    lam = np.array([1.0, 1.0, 1.0, 2.0, 2.0] + list(np.linspace(3, 9, p - 5)))
+    a, _ = synth.prescribed_spectrum(lam, 3)
+    s = make_solver(P, 300)
+    ev = torch.zeros(p, dtype=torch.float64, device="cuda")
+    U = torch.zeros((p, p), dtype=torch.float64, device="cuda")
+    P.lobpcg_small_eigh(s.h, cu(a), ev, U)
+    assert np.allclose(host(ev), lam, atol=1e-13 * 9)
+    Uh = host(U)
+    assert np.abs(Uh.T @ Uh - np.eye(p)).max() <= 1e-13
+
+
+def test_small_cholesky(P):
+    g = synth.rng(1)
+    G = g.standard_normal((50, 20))
+    M = G.T @ G
+    s = make_solver(P, 300)
+    L = torch.zeros((20, 20), dtype=torch.float64, device="cuda")
+    shifts = P.lobpcg_small_cholesky(s.h, cu(M), L)
+    Lh = host(L)
+    assert shifts == 0
+    assert np.allclose(Lh, np.linalg.cholesky(M), atol=1e-12)
+    # singular overlap: the plain factorisation fails, the shifted one works
+    X = O.normalize_columns(np.column_stack([np.ones(50), np.ones(50), np.arange(50.0)]))
+    M2 = X.T @ X
+    L2 = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+    shifts = P.lobpcg_small_cholesky(s.h, cu(M2), L2)
+    st = O.OrthoStats()
+    Lo = O.shifted_cholesky(M2, st)
+    assert shifts == st.failed_factorizations >= 1
+    # same shift as the oracle: L L^T - M is sigma I on both sides; entries
+    # below a pivot of size sqrt(sigma) carry rounding of order eps/sqrt(sigma)
+    Lg = host(L2)
+    sig_g = np.diag(Lg @ Lg.T - M2)
+    sig_o = np.diag(Lo @ Lo.T - M2)
+    assert np.allclose(sig_g, sig_o, rtol=0.02)
+    assert np.abs(Lg @ Lg.T - M2 - np.diag(sig_g)).max() <= 1e-15
+    assert np.abs(Lg - Lo).max() <= 8 * np.finfo(float).eps / np.sqrt(sig_o.mean())
+
+
+def graded(n, m, cond, seed):
+    g = synth.rng(seed)
+    U, _ = np.linalg.qr(g.standard_normal((n, m)))
+    V, _ = np.linalg.qr(g.standard_normal((m, m)))
+    return (U * np.logspace(0, -math.log10(cond), m)) @ V.T
+
+
+@pytest.mark.parametrize("n,m,cond", [(5000, 8, 10.0), (20011, 16, 1e3), (3001, 32, 1e5), (1000, 1, 1.0)])
+def test_ortho_vs_oracle(P, n, m, cond):
+    say("ortho", n, m, cond)
+    X = graded(n, m, cond, 3) * synth.rng(4).uniform(0.5, 10, m)
+    s = make_solver(P, n)
+    Xd = cu(X)
+    info = P.lobpcg_ortho(s.h, Xd)
+    Q = host(Xd)
+    Qo = O.ortho(X)
+    assert np.abs(Q.T @ Q - np.eye(m)).max() <= 1e-14
+    assert np.abs(Q - Qo).max() <= 1e-15 * cond * 50
+    assert info["stalled"] == 0
+
+
+def test_ortho_forced_shift(P):
+    g = synth.rng(5)
+    n = 800
+    x, y = g.standard_normal(n), g.standard_normal(n)
+    Z = g.standard_normal((n, 3))
+    X = np.column_stack([x, x + 1e-10 * y, Z])
+    s = make_solver(P, n)
+    Xd = cu(X)
+    info = P.lobpcg_ortho(s.h, Xd)
+    Q = host(Xd)
+    assert info["failed"] >= 1 and info["shifted"] == 1 and info["factorizations"] <= 4
+    assert np.abs(Q.T @ Q - np.eye(5)).max() <= 1e-14
+
+
+def test_ortho_against_vs_oracle(P):
+    g = synth.rng(11)
+    n = 6000
+    Y = np.linalg.qr(g.standard_normal((n, 6)))[0]
+    Xt = Y @ g.standard_normal((6, 4)) + 1e-10 * g.standard_normal((n, 4))
+    buf = cu(np.hstack([Y, Xt]))
+    s = make_solver(P, n)
+    info = P.lobpcg_ortho_against(s.h, buf[:, 6:], buf[:, :6])
+    out = host(buf)
+    Q = out[:, 6:]
+    assert np.array_equal(out[:, :6], Y)
+    assert np.abs(Y.T @ Q).max() <= 1e-14
+    assert np.abs(Q.T @ Q - np.eye(4)).max() <= 1e-14
+    assert info["passes"] <= 3
+    Qo = O.ortho_against(Xt, Y)
+    PQ = Q @ Q.T
+    PO = Qo @ Qo.T
+    assert np.linalg.norm(PQ - PO, 2) < 1e-5  # the 1e-10 part survives to ~1e-6
+
+
+def test_ortho_zero_column(P):
+    n = 1000
+    X = synth.start_block(n, 3, 2)
+    X[:, 1] = 0.0
+    s = make_solver(P, n)
+    Xd = cu(X)
+    P.lobpcg_ortho(s.h, Xd)
+    Q = host(Xd)
+    assert np.abs(Q.T @ Q - np.eye(3)).max() <= 1e-14
+    # the replacement is the oracle's SplitMix64 column, orthonormalised
+    Qo = O.ortho(X)
+    assert np.abs(Q - Qo).max() < 1e-12
+
+
+@pytest.mark.parametrize("precond", [0, 1, 2])
+def test_rotate_definition(P, precond):
+    n, m, a0 = 10007, 6, 2
+    p = m + 2 * 4
+    q = m + (m - a0)
+    g = synth.rng(precond)
+    V = g.standard_normal((n, p))
+    AV = g.standard_normal((n, p))
+    U = g.standard_normal((p, q))
+    theta = np.sort(g.uniform(0.5, 2.0, m))
+    d = g.uniform(0.0, 3.0, n)
+    d[:5] = theta[a0]  # exercise the guard
+    s = P.Solver(n)
+    s.ensure_workspace(m)
+    s.set_preconditioner(precond, cu(d))
+    ldo = q + (m - a0) + 3
+    Vo = torch.zeros((n, ldo), dtype=torch.float64, device="cuda")
+    AVo = torch.zeros((n, ldo), dtype=torch.float64, device="cuda")
+    r2 = torch.zeros(m, dtype=torch.float64, device="cuda")
+    P.lobpcg_rotate(s.h, cu(V), cu(AV), p, cu(U), m, q, cu(theta), a0, Vo, AVo, r2)
+    Xn = V @ U
+    AXn = AV @ U
+    R = AXn[:, :m] - Xn[:, :m] * theta
+    if precond == 0:
+        Wt = R[:, a0:]
+    else:
+        Wt = O.precondition_diag(R[:, a0:], d, theta[a0:], signed=(precond == 2))
+    vo, avo = host(Vo), host(AVo)
+    scale = np.abs(V) @ np.abs(U)
+    assert np.all(np.abs(vo[:, :q] - Xn) <= 1e-13 * scale)
+    assert np.all(np.abs(avo[:, :q] - AXn) <= 1e-13 * (np.abs(AV) @ np.abs(U)))
+    assert np.allclose(vo[:, q:q + m - a0], Wt, rtol=1e-12, atol=1e-12 * np.abs(Wt).max())
+    assert np.allclose(host(r2), (R ** 2).sum(0), rtol=1e-12)
