@@ -56,6 +56,12 @@ hipError_t tsmm_f64(const double* In, int64_t ldi, int p, const double* Coef, in
 hipError_t tsmm_f32(const float* In, int64_t ldi, int p, const double* Coef, int q, float* Out,
                     int64_t ldo, int64_t n, const int* skip, hipStream_t s);
 
+// One pass of ortho(W; Y) on base = [Y | W]: W <- [Y W] coef in place and
+// G = [Y W]^T W of the new W (skipped when st->done).
+hipError_t ortho_apply_f64(double* base, int64_t ld, int ny, int nw, const double* coef,
+                           const OrthoState* st, int64_t n, double* part, double* G,
+                           hipStream_t s);
+
 // Rotation + residual + preconditioner (one pass over V and AV).
 struct RotateArgs {
   int64_t n, ldv, ldo;

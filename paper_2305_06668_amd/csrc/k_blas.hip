@@ -79,7 +79,27 @@ __global__ __launch_bounds__(256) void k_gram_part(const T* __restrict__ A, int6
     for (int tj = 0; tj < MTJ; ++tj) acc[ti][tj] = AccT{0, 0, 0, 0};
 
   int64_t base = r0 + wave * 4;
-  // steps whose 4 rows all exist: no row checks
+  // four steps at a time: all fragments of the four steps are loaded before
+  // their MFMAs, which keeps 4 (MTI + MTJ) loads in flight per lane
+  constexpr int U = 4;
+  for (; base + 16 * (U - 1) + 4 <= r1; base += 16 * U) {
+    T a[U][MTI], b[U][MTJ];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = base + 16 * u + kr;
+#pragma unroll
+      for (int ti = 0; ti < MTI; ++ti) a[u][ti] = va[ti] ? A[row * lda + ca[ti]] : T(0);
+#pragma unroll
+      for (int tj = 0; tj < MTJ; ++tj) b[u][tj] = vb[tj] ? B[row * ldb + cb[tj]] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int ti = 0; ti < MTI; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < MTJ; ++tj) acc[ti][tj] = mma(a[u][ti], b[u][tj], acc[ti][tj]);
+  }
+  // remaining steps whose 4 rows all exist: no row checks
   for (; base + 4 <= r1; base += 16) {
     const int64_t row = base + kr;
     T a[MTI], b[MTJ];
@@ -132,21 +152,45 @@ __global__ __launch_bounds__(256) void k_gram_part(const T* __restrict__ A, int6
   }
 }
 
-// Stage 2: C[idx] = sum over blocks, in two fixed-order levels (groups of 32).
+// Stage 2: C[o] = sum over blocks b of part[b][o], fixed order: block x owns
+// 16 consecutive outputs; thread (s, o) with s = tid / 16 sums the blocks
+// b = s, s + 16, s + 32, ... in order; the 16 slice sums are added in slice
+// order.  Loads of one b are 16 consecutive doubles (coalesced).
 __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int nblk,
                                                    int pq, double* __restrict__ C,
                                                    const int* __restrict__ skip) {
   if (skip != nullptr && *skip) return;
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= pq) return;
-  double total = 0.0;
-  for (int g = 0; g < nblk; g += 32) {
-    double s = 0.0;
-    const int e = min(nblk, g + 32);
-    for (int b = g; b < e; ++b) s += part[(int64_t)b * pq + idx];
-    total += s;
+  __shared__ double red[16][17];
+  const int o = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int sl = threadIdx.x >> 4;
+  double acc = 0.0;
+  if (o < pq) {
+    int b = sl;
+    for (; b + 48 < nblk; b += 64) {
+      const double v0 = part[(int64_t)b * pq + o];
+      const double v1 = part[(int64_t)(b + 16) * pq + o];
+      const double v2 = part[(int64_t)(b + 32) * pq + o];
+      const double v3 = part[(int64_t)(b + 48) * pq + o];
+      acc += v0;
+      acc += v1;
+      acc += v2;
+      acc += v3;
+    }
+    for (; b < nblk; b += 16) acc += part[(int64_t)b * pq + o];
   }
-  C[idx] = total;
+  red[sl][threadIdx.x & 15] = acc;
+  __syncthreads();
+  if (threadIdx.x < 16 && o < pq) {
+    double t = 0.0;
+    for (int i = 0; i < 16; ++i) t += red[i][threadIdx.x];
+    C[o] = t;
+  }
+}
+
+static hipError_t sum_parts(const double* part, int nblk, int pq, double* C, const int* skip,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(cdiv(pq, 16)), dim3(256), 0, s, part, nblk, pq, C, skip);
+  return hipGetLastError();
 }
 
 template <typename T, int MTI, int MTJ>
@@ -162,25 +206,77 @@ static hipError_t gram_launch(const T* A, int64_t lda, int p, const T* B, int64_
   dim3 grid(nblk, (TI + MTI - 1) / MTI);
   hipLaunchKernelGGL((k_gram_part<T, MTI, MTJ>), grid, dim3(256), 0, s, A, lda, p, B, ldb, q, n,
                      rpb, part, skip);
-  hipLaunchKernelGGL(k_sum_parts, dim3(cdiv(p * q, 256)), dim3(256), 0, s, part, nblk, p * q, C,
-                     skip);
-  return hipGetLastError();
+  return sum_parts(part, nblk, p * q, C, skip, s);
 }
 
 template <typename T>
 static hipError_t gram_any(const T* A, int64_t lda, int p, const T* B, int64_t ldb, int q,
                            int64_t n, double* part, double* C, const int* skip, hipStream_t s) {
   if (p < 1 || q < 1 || p > kGramMaxCols || q > kGramMaxCols || n < 1) return hipErrorInvalidValue;
+  // row-tile group size: every row tile when the accumulators fit (<= 16
+  // 16x16 tiles per wave), else groups of 16 / TJ row tiles
+  const int TI = (p + 15) / 16;
   switch ((q + 15) / 16) {
-    case 1: return gram_launch<T, 8, 1>(A, lda, p, B, ldb, q, n, part, C, skip, s);
-    case 2: return gram_launch<T, 8, 2>(A, lda, p, B, ldb, q, n, part, C, skip, s);
-    case 3: return gram_launch<T, 5, 3>(A, lda, p, B, ldb, q, n, part, C, skip, s);
-    case 4: return gram_launch<T, 4, 4>(A, lda, p, B, ldb, q, n, part, C, skip, s);
-    case 5: return gram_launch<T, 3, 5>(A, lda, p, B, ldb, q, n, part, C, skip, s);
-    case 6: return gram_launch<T, 2, 6>(A, lda, p, B, ldb, q, n, part, C, skip, s);
-    case 7: return gram_launch<T, 2, 7>(A, lda, p, B, ldb, q, n, part, C, skip, s);
-    default: return gram_launch<T, 2, 8>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+    case 1:
+      switch (std::min(TI, 8)) {
+        case 1: return gram_launch<T, 1, 1>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 2: return gram_launch<T, 2, 1>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 3: return gram_launch<T, 3, 1>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 4: return gram_launch<T, 4, 1>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 5: return gram_launch<T, 5, 1>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 6: return gram_launch<T, 6, 1>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 7: return gram_launch<T, 7, 1>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        default: return gram_launch<T, 8, 1>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+      }
+    case 2:
+      switch (std::min(TI, 8)) {
+        case 1: return gram_launch<T, 1, 2>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 2: return gram_launch<T, 2, 2>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 3: return gram_launch<T, 3, 2>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 4: return gram_launch<T, 4, 2>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 5: return gram_launch<T, 5, 2>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 6: return gram_launch<T, 6, 2>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 7: return gram_launch<T, 7, 2>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        default: return gram_launch<T, 8, 2>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+      }
+    case 3:
+      switch (std::min(TI, 5)) {
+        case 1: return gram_launch<T, 1, 3>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 2: return gram_launch<T, 2, 3>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 3: return gram_launch<T, 3, 3>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 4: return gram_launch<T, 4, 3>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        default: return gram_launch<T, 5, 3>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+      }
+    case 4:
+      switch (std::min(TI, 4)) {
+        case 1: return gram_launch<T, 1, 4>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 2: return gram_launch<T, 2, 4>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 3: return gram_launch<T, 3, 4>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        default: return gram_launch<T, 4, 4>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+      }
+    case 5:
+      switch (std::min(TI, 3)) {
+        case 1: return gram_launch<T, 1, 5>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        case 2: return gram_launch<T, 2, 5>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        default: return gram_launch<T, 3, 5>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+      }
+    case 6:
+      switch (std::min(TI, 2)) {
+        case 1: return gram_launch<T, 1, 6>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        default: return gram_launch<T, 2, 6>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+      }
+    case 7:
+      switch (std::min(TI, 2)) {
+        case 1: return gram_launch<T, 1, 7>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        default: return gram_launch<T, 2, 7>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+      }
+    case 8:
+      switch (std::min(TI, 2)) {
+        case 1: return gram_launch<T, 1, 8>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+        default: return gram_launch<T, 2, 8>(A, lda, p, B, ldb, q, n, part, C, skip, s);
+      }
   }
+  return hipErrorInvalidValue;
 }
 
 hipError_t gram_f64(const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
@@ -200,10 +296,181 @@ hipError_t gram_f32(const float* A, int64_t lda, int p, const float* B, int64_t 
 template <typename T>
 __device__ __forceinline__ void stage_rows(const T* __restrict__ In, int64_t ld, int p,
                                            int64_t row0, int rows, T* __restrict__ tile) {
+  // batches of 12 independent loads per thread before their LDS stores, so
+  // that many global loads are in flight per thread
   const int ldt = p + 1;
-  for (int idx = threadIdx.x; idx < 64 * p; idx += 256) {
-    const int r = idx / p, c = idx - r * p;
-    tile[r * ldt + c] = (r < rows) ? In[(row0 + r) * ld + c] : T(0);
+  const int total = 64 * p;
+  constexpr int B = 12;
+  for (int base = threadIdx.x; base < total; base += 256 * B) {
+    T v[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int idx = base + 256 * i;
+      const int r = idx / p;
+      v[i] = (idx < total && r < rows) ? In[(row0 + r) * ld + (idx - r * p)] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int idx = base + 256 * i;
+      if (idx < total) {
+        const int r = idx / p;
+        tile[r * ldt + (idx - r * p)] = v[i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// ortho apply: one streaming pass of ortho(W; Y) (Alg. 2 / Alg. 3).  With
+// base = [Y | W] (nr = ny + nw columns, leading dimension ld):
+//   W <- [Y W] coef                (in place; coef is (ny + nw) x nw)
+//   part[block] = [Y W]^T W        (of the NEW W, per-block partial)
+// The new W rows are written back into the LDS tile so that the overlap is
+// accumulated with MFMA straight from LDS (K = 4 rows per MFMA).  Skips
+// itself when the controller has finished (st->done).
+
+template <int MTI, int MTJ>
+__global__ __launch_bounds__(256) void k_ortho_apply(double* base, int64_t ld, int ny, int nw,
+                                                     const double* __restrict__ coef,
+                                                     const OrthoState* __restrict__ st, int64_t n,
+                                                     double* __restrict__ part) {
+  if (st->done) return;
+  const int w_only = st->w_only;
+  const int nr = ny + nw;
+  extern __shared__ double smem_d[];
+  double* cf = smem_d;
+  double* tile = cf + ((nr * nw + 1) & ~1);
+  double* red = tile + 64 * (nr + 1);
+  const int ldt = nr + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, cc = lane & 15;
+  for (int i = threadIdx.x; i < nr * nw; i += 256) cf[i] = coef[i];
+  d4 G[MTI][MTJ];
+#pragma unroll
+  for (int I = 0; I < MTI; ++I)
+#pragma unroll
+    for (int J = 0; J < MTJ; ++J) G[I][J] = d4{0, 0, 0, 0};
+  const int kbeg = w_only ? (ny & ~3) : 0;  // coefficient rows < ny are zero then
+  const int64_t nchunks = (n + 63) / 64;
+  for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    __syncthreads();
+    const int64_t row0 = chunk * 64;
+    const int rows = (int)min<int64_t>(64, n - row0);
+    stage_rows<double>(base, ld, nr, row0, rows, tile);
+    __syncthreads();
+    d4 acc[MTJ];
+#pragma unroll
+    for (int J = 0; J < MTJ; ++J) acc[J] = d4{0, 0, 0, 0};
+    const int arow = wave * 16 + cc;
+    for (int k = kbeg; k < nr; k += 4) {
+      const int kk = k + g;
+      const bool kv = kk < nr;
+      const double a = kv ? tile[arow * ldt + kk] : 0.0;
+#pragma unroll
+      for (int J = 0; J < MTJ; ++J) {
+        const int col = J * 16 + cc;
+        const double b = (kv && col < nw) ? cf[kk * nw + col] : 0.0;
+        acc[J] = mma(a, b, acc[J]);
+      }
+    }
+    __syncthreads();  // every wave is done reading the old W columns
+#pragma unroll
+    for (int J = 0; J < MTJ; ++J) {
+      const int col = J * 16 + cc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rl = wave * 16 + 4 * r + g;
+        if (rl < rows && col < nw) {
+          base[(row0 + rl) * ld + ny + col] = acc[J][r];
+          tile[rl * ldt + ny + col] = acc[J][r];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rl = wave * 16 + 4 * r + g;
+      double bj[MTJ];
+#pragma unroll
+      for (int J = 0; J < MTJ; ++J) {
+        const int cj = J * 16 + cc;
+        bj[J] = (cj < nw) ? tile[rl * ldt + ny + cj] : 0.0;
+      }
+#pragma unroll
+      for (int I = 0; I < MTI; ++I) {
+        const int ci = I * 16 + cc;
+        const double ai = (ci < nr) ? tile[rl * ldt + ci] : 0.0;
+#pragma unroll
+        for (int J = 0; J < MTJ; ++J) G[I][J] = mma(ai, bj[J], G[I][J]);
+      }
+    }
+  }
+  // fixed-order reduction over the waves, then the block partial
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int I = 0; I < MTI; ++I)
+#pragma unroll
+        for (int J = 0; J < MTJ; ++J)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int idx = (I * MTJ + J) * 256 + (4 * r + g) * 16 + cc;
+            red[idx] = (w == 0) ? G[I][J][r] : red[idx] + G[I][J][r];
+          }
+    }
+    __syncthreads();
+  }
+  double* dst = part + (int64_t)blockIdx.x * nr * nw;
+  for (int idx = threadIdx.x; idx < nr * nw; idx += 256) {
+    const int i = idx / nw, j = idx - i * nw;
+    dst[idx] = red[((i >> 4) * MTJ + (j >> 4)) * 256 + (i & 15) * 16 + (j & 15)];
+  }
+}
+
+template <int MTI, int MTJ>
+static hipError_t ortho_apply_launch(double* base, int64_t ld, int ny, int nw, const double* coef,
+                                     const OrthoState* st, int64_t n, double* part, double* G,
+                                     hipStream_t s) {
+  static bool attr = false;
+  const int nr = ny + nw;
+  const size_t sm = sizeof(double) * (size_t)(((nr * nw + 1) & ~1) + 64 * (nr + 1) + MTI * MTJ * 256);
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_ortho_apply<MTI, MTJ>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
+    (void)hipGetLastError();
+    attr = true;
+  }
+  const int64_t nchunks = (n + 63) / 64;
+  const int grid = (int)std::min<int64_t>(nchunks, kGramBlocks);
+  hipLaunchKernelGGL((k_ortho_apply<MTI, MTJ>), dim3(grid), dim3(256), sm, s, base, ld, ny, nw,
+                     coef, st, n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return sum_parts(part, grid, nr * nw, G, &st->done, s);
+}
+
+hipError_t ortho_apply_f64(double* base, int64_t ld, int ny, int nw, const double* coef,
+                           const OrthoState* st, int64_t n, double* part, double* G,
+                           hipStream_t s) {
+  const int nr = ny + nw;
+  if (nw < 1 || nw > kMaxBlock || ny < 0 || nr > kMaxP || n < 1) return hipErrorInvalidValue;
+  const int TI = (nr + 15) / 16;
+  if (nw <= 16) {
+    switch (TI) {
+      case 1: return ortho_apply_launch<1, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      case 2: return ortho_apply_launch<2, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      case 3: return ortho_apply_launch<3, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      case 4: return ortho_apply_launch<4, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      case 5: return ortho_apply_launch<5, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      default: return ortho_apply_launch<6, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+    }
+  }
+  switch (TI) {
+    case 2: return ortho_apply_launch<2, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
+    case 3: return ortho_apply_launch<3, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
+    case 4: return ortho_apply_launch<4, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
+    case 5: return ortho_apply_launch<5, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
+    default: return ortho_apply_launch<6, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
   }
 }
 
@@ -435,9 +702,9 @@ static hipError_t rotate_launch(const T* V, const T* AV, T* Vout, T* AVout, cons
   const int grid = (int)std::min<int64_t>(nchunks, kStreamBlocks);
   hipLaunchKernelGGL((k_rotate<T, MTJ>), dim3(grid), dim3(256), rotate_smem<T>(a.p, a.q), s, V, AV,
                      Vout, AVout, a);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, a.part, grid, a.m, a.resnorm2,
-                     (const int*)nullptr);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return sum_parts(a.part, grid, a.m, a.resnorm2, nullptr, s);
 }
 
 template <typename T>
@@ -500,9 +767,9 @@ hipError_t colstats_f64(const double* X, int64_t ldx, const double* AX, int64_t 
   if (m < 1 || m > 64) return hipErrorInvalidValue;
   const int grid = (int)std::min<int64_t>(kStreamBlocks, (n + 3) / 4);
   hipLaunchKernelGGL(k_colstats, dim3(grid), dim3(256), 0, s, X, ldx, AX, ldax, m, theta, n, part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, grid, 3 * m, out,
-                     (const int*)nullptr);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return sum_parts(part, grid, 3 * m, out, nullptr, s);
 }
 
 // ---------------------------------------------------------------------------

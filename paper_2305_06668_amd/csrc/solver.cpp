@@ -219,8 +219,7 @@ int lobpcg_ctx::ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho
       const int batch = (rounds == 0) ? kOrthoRounds : 2;
       for (int r = 0; r < batch; ++r) {
         HIPCHK(ortho_ctl(G, st, coef, stream));
-        HIPCHK(tsmm_f64(base, ld, nr, coef, nw, base + ny, ld, n, &st->done, stream));
-        HIPCHK(gram_f64(base, ld, nr, base + ny, ld, nw, n, part, G, &st->done, stream));
+        HIPCHK(ortho_apply_f64(base, ld, ny, nw, coef, st, n, part, G, stream));
       }
       rounds += batch;
       HIPCHK(hipMemcpyAsync(hst, st, sizeof(OrthoState), hipMemcpyDeviceToHost, stream));
