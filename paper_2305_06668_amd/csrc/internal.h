@@ -37,7 +37,10 @@ struct OrthoState {
   int grams, factorizations, failed, shifted, updates, stalled, svqb, passes;
   int ny, nw;   // current shape
   int max_inner, max_outer;
+  int fold_scale;     // input: a final diagonal column scaling may be left pending
+  int pending_scale;  // output: W must still be scaled by dscale (folded into the next RR)
   double tau;
+  double dscale[kMaxBlock];
 };
 enum OrthoPhase { kPhStart = 0, kPhBegin = 1, kPhLoop = 2, kPhOuter = 3, kPhDone = 4 };
 enum { kOrthoErrZero = 1, kOrthoErrNonfinite = 2, kOrthoErrFailed = 3 };
@@ -71,6 +74,8 @@ struct RotateArgs {
   const double* diag;   // n (may be null for kPrecNone)
   double* part;         // kStreamBlocks * m partial norms
   double* resnorm2;     // m
+  double* gpart;        // optional: kStreamBlocks * (q + m - a0) * (m - a0) partials
+  double* G0;           // optional: [X' P' W~]^T W~ ((q + m - a0) x (m - a0))
 };
 hipError_t rotate_f64(const double* V, const double* AV, double* Vout, double* AVout,
                       const RotateArgs& a, hipStream_t s);
@@ -129,14 +134,19 @@ hipError_t small_eigh(const double* a, int p, double* evals, double* evecs, int*
 // values; U (p x q) = [u_x | u_p] where u_p = ortho(u_x[:, a0:m] - E[:, a0:m]; u_x)
 // (q = m + (want_up ? m - a0 : 0)).  info[0] = Jacobi sweeps, info[1] = 0 ok,
 // info[2..] ortho counters for the R^p orthonormalisation.
+// `pend` (may be null): when pend->pending_scale is set, the columns
+// [woff, woff + pend->nw) of V are taken as scaled by pend->dscale: a is
+// scaled as D a D and the rows of U as D U, so the scaling never needs its
+// own pass over V.
 hipError_t small_rr(const double* a, int p, int m, int a0, int want_up, double tau,
-                    double* theta_all, double* U, int* info, hipStream_t s);
+                    const OrthoState* pend, int woff, double* theta_all, double* U, int* info,
+                    hipStream_t s);
 // Shifted Cholesky (p x p, p <= 64): L lower with L L^T = M + sigma I.
 hipError_t small_cholesky(const double* M, int p, double* L, int* info, hipStream_t s);
 // One controller step of ortho(W; Y): reads G = [Y W]^T W ((ny+nw) x nw),
 // updates the state and writes the next coefficient ((ny+nw) x nw).
 hipError_t ortho_ctl(const double* G, OrthoState* st, double* coef, hipStream_t s);
 hipError_t ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner, int max_outer,
-                      hipStream_t s);
+                      int fold_scale, hipStream_t s);
 
 }  // namespace lobpcg

@@ -595,10 +595,14 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
   extern __shared__ double smem_d[];
   __shared__ double nred[4][64];
   const int p = a.p, q = a.q, m = a.m;
+  const int na = m - a.a0;
+  const int no = q + na;  // output columns [X' P' W~]
+  const bool want_g = a.gpart != nullptr && na > 0;
   T* cf = reinterpret_cast<T*>(smem_d);
   T* tV = cf + ((p * q + 1) & ~1);
   T* tA = tV + 64 * (p + 1);
-  const int ldt = p + 1;
+  T* tO = tV;  // output tile, reuses the staging area: 64 x (no + 1) <= 2 * 64 * (p + 1)
+  const int ldt = p + 1, ldto = no + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kr = lane >> 4, cc = lane & 15;
   for (int i = threadIdx.x; i < p * q; i += 256) cf[i] = (T)a.U[i];
@@ -610,6 +614,13 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
     th[tj] = (col < m) ? a.theta[col] : 0.0;
     nacc[tj] = 0.0;
   }
+  // G0 = [X' P' W~]^T W~ accumulators: up to 6 x 2 tiles
+  const int tig = (no + 15) >> 4, tjg = (na + 15) >> 4;
+  typename AccOf<T>::type gacc[6][2];
+#pragma unroll
+  for (int I = 0; I < 6; ++I)
+#pragma unroll
+    for (int J = 0; J < 2; ++J) gacc[I][J] = AccT{0, 0, 0, 0};
   const int64_t n = a.n;
   const int64_t nchunks = (n + 63) / 64;
   for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
@@ -639,31 +650,62 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
         aa[tj] = mma(av, b, aa[tj]);
       }
     }
+    if (want_g) __syncthreads();  // staging area becomes the output tile
 #pragma unroll
     for (int tj = 0; tj < MTJ; ++tj) {
       const int col = tj * 16 + cc;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rr = wave * 16 + acc_row<T>(r, lane);
-        if (rr < rows && col < q) {
-          const int64_t g = row0 + rr;
+        if (col < q) {
           const T xo = (T)ax[tj][r];
           const T ao = (T)aa[tj][r];
-          Vout[g * a.ldo + col] = xo;
-          AVout[g * a.ldo + col] = ao;
-          if (col < m) {
-            const double res = (double)ao - th[tj] * (double)xo;
-            nacc[tj] += res * res;
-            if (col >= a.a0) {
-              const double d = (a.precond == kPrecNone) ? 0.0 : a.diag[g];
-              Vout[g * a.ldo + q + (col - a.a0)] = (T)precond_apply(res, d, th[tj], a.precond);
+          if (rr < rows) {
+            const int64_t g = row0 + rr;
+            Vout[g * a.ldo + col] = xo;
+            AVout[g * a.ldo + col] = ao;
+            if (col < m) {
+              const double res = (double)ao - th[tj] * (double)xo;
+              nacc[tj] += res * res;
+              if (col >= a.a0) {
+                const double d = (a.precond == kPrecNone) ? 0.0 : a.diag[g];
+                const T w = (T)precond_apply(res, d, th[tj], a.precond);
+                Vout[g * a.ldo + q + (col - a.a0)] = w;
+                if (want_g) tO[rr * ldto + q + (col - a.a0)] = w;
+              }
             }
+          } else if (want_g && col >= a.a0 && col < m) {
+            tO[rr * ldto + q + (col - a.a0)] = T(0);
+          }
+          if (want_g) tO[rr * ldto + col] = (rr < rows) ? xo : T(0);
+        }
+      }
+    }
+    if (want_g) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rl = wave * 16 + 4 * r + kr;  // K = 4 rows per MFMA, any row order
+        T bj[2];
+#pragma unroll
+        for (int J = 0; J < 2; ++J) {
+          const int cj = J * 16 + cc;
+          bj[J] = (J < tjg && cj < na) ? tO[rl * ldto + q + cj] : T(0);
+        }
+#pragma unroll
+        for (int I = 0; I < 6; ++I) {
+          if (I < tig) {
+            const int ci = I * 16 + cc;
+            const T ai = (ci < no) ? tO[rl * ldto + ci] : T(0);
+#pragma unroll
+            for (int J = 0; J < 2; ++J)
+              if (J < tjg) gacc[I][J] = mma(ai, bj[J], gacc[I][J]);
           }
         }
       }
     }
   }
-  // per-column partial: sum the 4 lane groups (fixed xor order), then waves
+  // per-column residual partial: sum the 4 lane groups (fixed xor order), then waves
 #pragma unroll
   for (int tj = 0; tj < MTJ; ++tj) {
     double v = nacc[tj];
@@ -681,11 +723,38 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
     const int c = threadIdx.x;
     a.part[(int64_t)blockIdx.x * m + c] = ((nred[0][c] + nred[1][c]) + nred[2][c]) + nred[3][c];
   }
+  if (want_g) {
+    // fixed-order reduction of G0 over the waves (reusing the staging area)
+    double* red = reinterpret_cast<double*>(cf + ((p * q + 1) & ~1));
+    for (int w = 0; w < 4; ++w) {
+      if (wave == w) {
+#pragma unroll
+        for (int I = 0; I < 6; ++I)
+#pragma unroll
+          for (int J = 0; J < 2; ++J)
+            if (I < tig && J < tjg)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int idx = (I * 2 + J) * 256 + acc_row<T>(r, lane) * 16 + cc;
+                const double v = (double)gacc[I][J][r];
+                red[idx] = (w == 0) ? v : red[idx] + v;
+              }
+      }
+      __syncthreads();
+    }
+    double* dst = a.gpart + (int64_t)blockIdx.x * no * na;
+    for (int idx = threadIdx.x; idx < no * na; idx += 256) {
+      const int i = idx / na, j = idx - i * na;
+      dst[idx] = red[((i >> 4) * 2 + (j >> 4)) * 256 + (i & 15) * 16 + (j & 15)];
+    }
+  }
 }
 
 template <typename T>
 static size_t rotate_smem(int p, int q) {
-  return sizeof(T) * (size_t)(((p * q + 1) & ~1) + 2 * 64 * (p + 1));
+  // the G0 reduction needs 12 * 256 doubles after the coefficient block
+  const size_t tiles = std::max<size_t>(2 * 64 * (p + 1) * sizeof(T), 12 * 256 * sizeof(double));
+  return sizeof(T) * (size_t)((p * q + 1) & ~1) + tiles;
 }
 
 template <typename T, int MTJ>
@@ -704,7 +773,10 @@ static hipError_t rotate_launch(const T* V, const T* AV, T* Vout, T* AVout, cons
                      Vout, AVout, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return sum_parts(a.part, grid, a.m, a.resnorm2, nullptr, s);
+  e = sum_parts(a.part, grid, a.m, a.resnorm2, nullptr, s);
+  if (e != hipSuccess || a.gpart == nullptr || a.m == a.a0) return e;
+  const int na = a.m - a.a0;
+  return sum_parts(a.gpart, grid, (a.q + na) * na, a.G0, nullptr, s);
 }
 
 template <typename T>

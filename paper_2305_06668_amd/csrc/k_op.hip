@@ -18,6 +18,12 @@ namespace lobpcg {
 
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// G = lanes per stored entry (next power of two >= ncols); a row is owned by a
+// group of GS = max(G, 16) lanes, which holds NP = GS / G "slots" that take
+// stored entries in turn.  The group loads its row's (col, val) pairs in
+// chunks of GS (one per lane, coalesced), four chunks up front, broadcasts
+// them with __shfl, and issues all gathers of a chunk before accumulating.
+// Slot partial sums are combined with xor shuffles at the end.
 template <typename TV, typename TW, int G>
 __global__ __launch_bounds__(256) void k_spmm_csr(const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci,
@@ -25,61 +31,63 @@ __global__ __launch_bounds__(256) void k_spmm_csr(const int32_t* __restrict__ rp
                                                   const TW* __restrict__ W, int64_t ldw,
                                                   TW* __restrict__ Y, int64_t ldy, int ncols,
                                                   int64_t n, int per_xcd) {
-  constexpr int RPB = 256 / G;
+  constexpr int GS = (G < 16) ? 16 : G;
+  constexpr int NP = GS / G;
+  constexpr int RPB = 256 / GS;
+  constexpr int NCH = 2;
   const int b = blockIdx.x;
   const int lb = (b & 7) * per_xcd + (b >> 3);
-  const int64_t row = (int64_t)lb * RPB + threadIdx.x / G;
-  const int c = threadIdx.x & (G - 1);
-  const int gbase = (threadIdx.x & 63) & ~(G - 1);
+  const int64_t row = (int64_t)lb * RPB + threadIdx.x / GS;
+  const int lg = threadIdx.x & (GS - 1);
+  const int slot = lg / G;
+  const int c = lg & (G - 1);
+  const int gbase = (threadIdx.x & 63) & ~(GS - 1);
   if (row >= n) return;  // the whole group shares the row
   const bool active = c < ncols;
   const int e0 = rp[row], e1 = rp[row + 1];
   TW acc = TW(0);
-  for (int e = e0; e < e1; e += G) {
-    const int my = e + c;
-    int col = 0;
-    TV v = TV(0);
-    if (my < e1) {
-      col = ci[my];
-      v = val[my];
+  for (int e = e0; e < e1; e += NCH * GS) {
+    int colr[NCH];
+    TV vr[NCH];
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+      const int ee = e + k * GS + lg;
+      const bool ok = ee < e1;
+      colr[k] = ok ? ci[ee] : 0;
+      vr[k] = ok ? val[ee] : TV(0);
     }
-    const int cnt = min(G, e1 - e);
-    int t = 0;
-    for (; t + 4 <= cnt; t += 4) {
-      const int c0 = __shfl(col, gbase + t, 64);
-      const int c1 = __shfl(col, gbase + t + 1, 64);
-      const int c2 = __shfl(col, gbase + t + 2, 64);
-      const int c3 = __shfl(col, gbase + t + 3, 64);
-      const TV v0 = __shfl(v, gbase + t, 64);
-      const TV v1 = __shfl(v, gbase + t + 1, 64);
-      const TV v2 = __shfl(v, gbase + t + 2, 64);
-      const TV v3 = __shfl(v, gbase + t + 3, 64);
-      TW w0 = TW(0), w1 = TW(0), w2 = TW(0), w3 = TW(0);
-      if (active) {
-        w0 = W[(int64_t)c0 * ldw + c];
-        w1 = W[(int64_t)c1 * ldw + c];
-        w2 = W[(int64_t)c2 * ldw + c];
-        w3 = W[(int64_t)c3 * ldw + c];
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+      const int base_e = e + k * GS;
+      if (base_e >= e1) break;
+      constexpr int UB = (G < 8) ? G : 8;  // gathers in flight per batch
+#pragma unroll
+      for (int u0 = 0; u0 < G; u0 += UB) {
+        TW w[UB];
+        TV vv[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          const int t = slot + NP * (u0 + u);
+          const int cidx = __shfl(colr[k], gbase + t, 64);
+          vv[u] = __shfl(vr[k], gbase + t, 64);
+          w[u] = (active && base_e + t < e1) ? W[(int64_t)cidx * ldw + c] : TW(0);
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) acc += (TW)vv[u] * w[u];
       }
-      acc += (TW)v0 * w0;
-      acc += (TW)v1 * w1;
-      acc += (TW)v2 * w2;
-      acc += (TW)v3 * w3;
-    }
-    for (; t < cnt; ++t) {
-      const int c0 = __shfl(col, gbase + t, 64);
-      const TV v0 = __shfl(v, gbase + t, 64);
-      if (active) acc += (TW)v0 * W[(int64_t)c0 * ldw + c];
     }
   }
-  if (active) Y[row * ldy + c] = acc;
+#pragma unroll
+  for (int off = G; off < GS; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  if (slot == 0 && active) Y[row * ldy + c] = acc;
 }
 
 template <typename TV, typename TW, int G>
 static hipError_t spmm_launch(const int32_t* rp, const int32_t* ci, const TV* val, const TW* W,
                               int64_t ldw, TW* Y, int64_t ldy, int ncols, int64_t n,
                               hipStream_t s) {
-  constexpr int RPB = 256 / G;
+  constexpr int GS = (G < 16) ? 16 : G;
+  constexpr int RPB = 256 / GS;
   const int64_t nb = (n + RPB - 1) / RPB;
   const int64_t nbp = (nb + 7) / 8 * 8;
   hipLaunchKernelGGL((k_spmm_csr<TV, TW, G>), dim3((unsigned)nbp), dim3(256), 0, s, rp, ci, val,

@@ -30,7 +30,7 @@ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
 // ---------------------------------------------------------------------------
 // block-wide helpers (every thread of the block calls them)
 
-__device__ double blk_reduce_max(double v, double* scratch) {
+__device__ __forceinline__ double blk_reduce_max(double v, double* scratch) {
   // scratch: blockDim.x / 64 doubles
   for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -43,7 +43,7 @@ __device__ double blk_reduce_max(double v, double* scratch) {
   return r;
 }
 
-__device__ double blk_reduce_sum_ordered(double v, double* scratch) {
+__device__ __forceinline__ double blk_reduce_sum_ordered(double v, double* scratch) {
   // deterministic: each wave reduces by a fixed xor tree, waves in order
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -57,7 +57,7 @@ __device__ double blk_reduce_sum_ordered(double v, double* scratch) {
 }
 
 // C (p x q) = A^T B, A: n x p, B: n x q
-__device__ void blk_gemm_tn(const double* A, int lda, const double* B, int ldb, int n, int p,
+__device__ __forceinline__ void blk_gemm_tn(const double* A, int lda, const double* B, int ldb, int n, int p,
                             int q, double* C, int ldc) {
   for (int idx = threadIdx.x; idx < p * q; idx += blockDim.x) {
     const int i = idx / q, j = idx - i * q;
@@ -69,7 +69,7 @@ __device__ void blk_gemm_tn(const double* A, int lda, const double* B, int ldb, 
 }
 
 // X (n x q) -= Y (n x p) C (p x q)
-__device__ void blk_sub_mm(double* X, int ldx, const double* Y, int ldy, const double* C, int ldc,
+__device__ __forceinline__ void blk_sub_mm(double* X, int ldx, const double* Y, int ldy, const double* C, int ldc,
                            int n, int p, int q) {
   for (int idx = threadIdx.x; idx < n * q; idx += blockDim.x) {
     const int r = idx / q, j = idx - r * q;
@@ -82,7 +82,7 @@ __device__ void blk_sub_mm(double* X, int ldx, const double* Y, int ldy, const d
 
 // scale columns of X (n x q) to unit norm; exact-zero columns are replaced
 // by SplitMix64 columns (entry i of column j: splitmix64(seed + j n + i)).
-__device__ void blk_normalize(double* X, int ldx, int n, int q, double* tmp, int* zeros) {
+__device__ __forceinline__ void blk_normalize(double* X, int ldx, int n, int q, double* tmp, int* zeros) {
   for (int j = threadIdx.x; j < q; j += blockDim.x) {
     double s = 0.0;
     for (int r = 0; r < n; ++r) s += X[r * ldx + j] * X[r * ldx + j];
@@ -107,7 +107,7 @@ __device__ void blk_normalize(double* X, int ldx, int n, int q, double* tmp, int
 
 // Cholesky L L^T = M + shift I (lower, n x n); returns true on success.
 // Breaks down when a pivot is not > 0 (NaN included), like LAPACK potrf.
-__device__ bool blk_chol(const double* M, int ldm, int n, double shift, double* L, int ldl,
+__device__ __forceinline__ bool blk_chol(const double* M, int ldm, int n, double shift, double* L, int ldl,
                          int* flag) {
   for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
     const int i = idx / n, j = idx - i * n;
@@ -142,7 +142,7 @@ struct ShiftCount {
 
 // Sec. 3.2 / Alg. 2: plain Cholesky, then shifts alpha*eps*||X||_F with
 // ||X||_F = sqrt(trace M), alpha = 100, x10 per retry.
-__device__ bool blk_shifted_chol(const double* M, int ldm, int n, double* L, int ldl, int* flag,
+__device__ __forceinline__ bool blk_shifted_chol(const double* M, int ldm, int n, double* L, int ldl, int* flag,
                                  ShiftCount* c, double* scratch) {
   if (threadIdx.x == 0) c->factorizations++;
   if (blk_chol(M, ldm, n, 0.0, L, ldl, flag)) return true;
@@ -164,7 +164,7 @@ __device__ bool blk_shifted_chol(const double* M, int ldm, int n, double* L, int
 }
 
 // Linv = L^-1 (lower), one column per thread by forward substitution.
-__device__ void blk_tri_inv(const double* L, int ldl, int n, double* Li, int ldi) {
+__device__ __forceinline__ void blk_tri_inv(const double* L, int ldl, int n, double* Li, int ldi) {
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     for (int i = 0; i < n; ++i) {
       if (i < j) {
@@ -180,7 +180,7 @@ __device__ void blk_tri_inv(const double* L, int ldl, int n, double* Li, int ldi
 }
 
 // X (n x q) <- X L^-T, one row per thread: z_j = (x_j - sum_{k<j} z_k L_jk) / L_jj
-__device__ void blk_trsm_rt(double* X, int ldx, int n, int q, const double* L, int ldl) {
+__device__ __forceinline__ void blk_trsm_rt(double* X, int ldx, int n, int q, const double* L, int ldl) {
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
     for (int j = 0; j < q; ++j) {
       double s = X[r * ldx + j];
@@ -196,11 +196,15 @@ __device__ void blk_trsm_rt(double* X, int ldx, int n, int q, const double* L, i
 // accumulating V (stride ldv, initialised here to I).  Round-robin pairing:
 // in round r the pairs are {pp-1, r} and {(r+k) mod (pp-1), (r-k) mod (pp-1)}
 // for k = 1 .. pp/2-1, with pp = n rounded up to even (index n is a dummy).
+// Two phases per round: (1) one thread per pair computes its rotation from
+// the current 2x2 block; (2) every 2x2 block {i0,i1} x {j0,j1} of two pairs
+// is rotated in place from both sides by one thread (it is closed under
+// J^T A J, so no double buffer is needed), and V's column pairs likewise.
 // A rotation is skipped when |a_pq| <= 2^-53 sqrt(|a_pp a_qq|) or
 // |a_pq| <= 2^-60 ||A||_F; the sweep loop stops after a sweep without any
-// rotation.  Returns the number of sweeps.
+// rotation.  Returns the number of sweeps.  Must run with blockDim.x == 1024.
 
-__device__ int blk_jacobi(double* A, int lda, double* V, int ldv, int n, double* cs, int* pr,
+__device__ __forceinline__ int blk_jacobi(double* A, int lda, double* V, int ldv, int n, double* cs, int* pr,
                           int* rot_flag, double* scratch) {
   for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
     const int i = idx / n, j = idx - i * n;
@@ -216,78 +220,124 @@ __device__ int blk_jacobi(double* A, int lda, double* V, int ldv, int n, double*
   if (n < 2) return 0;
   const int pp = n + (n & 1);
   const int npairs = pp / 2;
+  double* cc = cs;            // cos per pair
+  double* ss = cs + 64;       // sin per pair
+  double* tt = cs + 128;      // tan per pair
   int sweep = 0;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (; sweep < kJacobiMaxSweeps; ++sweep) {
     if (threadIdx.x == 0) *rot_flag = 0;
     __syncthreads();
     for (int r = 0; r < pp - 1; ++r) {
-      // pairs and angles
       for (int k = threadIdx.x; k < npairs; k += blockDim.x) {
         int i, j;
         if (k == 0) {
           i = pp - 1;
           j = r;
         } else {
-          i = (r + k) % (pp - 1);
-          j = (r - k + (pp - 1)) % (pp - 1);
+          i = r + k;
+          if (i >= pp - 1) i -= pp - 1;
+          j = r - k;
+          if (j < 0) j += pp - 1;
         }
         if (i > j) {
           const int t = i;
           i = j;
           j = t;
         }
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sn = 0.0, tn = 0.0;
         if (j < n) {
           const double apq = A[i * lda + j];
           const double app = A[i * lda + i], aqq = A[j * lda + j];
           if (fabs(apq) > 0x1.0p-53 * sqrt(fabs(app * aqq)) && fabs(apq) > abs_tol) {
             const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                          : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            tn = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                              : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tn * tn);
+            sn = tn * c;
             *rot_flag = 1;
           }
         }
         pr[2 * k] = i;
         pr[2 * k + 1] = j;
-        cs[2 * k] = c;
-        cs[2 * k + 1] = s;
+        cc[k] = c;
+        ss[k] = sn;
+        tt[k] = tn;
       }
       __syncthreads();
-      // rows: A <- J^T A  (row i' = c row_i - s row_j, row j' = s row_i + c row_j)
-      for (int idx = threadIdx.x; idx < npairs * n; idx += blockDim.x) {
-        const int k = idx / n, col = idx - k * n;
-        const int i = pr[2 * k], j = pr[2 * k + 1];
-        const double s = cs[2 * k + 1];
-        if (j >= n || s == 0.0) continue;
-        const double c = cs[2 * k];
-        const double ai = A[i * lda + col], aj = A[j * lda + col];
-        A[i * lda + col] = c * ai - s * aj;
-        A[j * lda + col] = s * ai + c * aj;
-      }
-      __syncthreads();
-      // columns: A <- A J and V <- V J
-      for (int idx = threadIdx.x; idx < npairs * n; idx += blockDim.x) {
-        const int k = idx % npairs, row = idx / npairs;
-        const int i = pr[2 * k], j = pr[2 * k + 1];
-        const double s = cs[2 * k + 1];
-        if (j >= n || s == 0.0) continue;
-        const double c = cs[2 * k];
-        const double ai = A[row * lda + i], aj = A[row * lda + j];
-        A[row * lda + i] = c * ai - s * aj;
-        A[row * lda + j] = s * ai + c * aj;
-        const double vi = V[row * ldv + i], vj = V[row * ldv + j];
-        V[row * ldv + i] = c * vi - s * vj;
-        V[row * ldv + j] = s * vi + c * vj;
-      }
-      __syncthreads();
-      // the annihilated pair is exactly zero
-      for (int k = threadIdx.x; k < npairs; k += blockDim.x) {
-        const int i = pr[2 * k], j = pr[2 * k + 1];
-        if (j < n && cs[2 * k + 1] != 0.0) {
-          A[i * lda + j] = 0.0;
-          A[j * lda + i] = 0.0;
+      // Phase 2 (needs blockDim == 1024: a 32 x 32 thread grid).  Thread
+      // (ty, tx) owns the 2x2 blocks (P, Q) for P in {ty, ty+32}, Q in
+      // {tx, tx+32} with P <= Q, and V's column pair Q on the rows ty,
+      // ty+32, ty+64; every load of an item is issued before its arithmetic.
+#pragma unroll
+      for (int hq = 0; hq < 2; ++hq) {
+        const int Q = tx + 32 * hq;
+        if (Q >= npairs) continue;
+        const double cQ = cc[Q], sQ = ss[Q], tQ = tt[Q];
+        const int j0 = pr[2 * Q], j1 = pr[2 * Q + 1];
+        const bool vj1 = j1 < n;
+#pragma unroll
+        for (int hp = 0; hp < 2; ++hp) {
+          const int P = ty + 32 * hp;
+          if (P >= npairs || P > Q) continue;
+          if (P == Q) {
+            if (sQ == 0.0) continue;  // skipped or dummy pair
+            const double a01 = A[j0 * lda + j1];
+            const double a00 = A[j0 * lda + j0], a11 = A[j1 * lda + j1];
+            A[j0 * lda + j0] = a00 - tQ * a01;
+            A[j1 * lda + j1] = a11 + tQ * a01;
+            A[j0 * lda + j1] = 0.0;
+            A[j1 * lda + j0] = 0.0;
+            continue;
+          }
+          const double cP = cc[P], sP = ss[P];
+          if (sP == 0.0 && sQ == 0.0) continue;
+          const int i0 = pr[2 * P], i1 = pr[2 * P + 1];
+          const bool vi1 = i1 < n;
+          const double b00 = A[i0 * lda + j0];
+          const double b01 = vj1 ? A[i0 * lda + j1] : 0.0;
+          const double b10 = vi1 ? A[i1 * lda + j0] : 0.0;
+          const double b11 = (vi1 && vj1) ? A[i1 * lda + j1] : 0.0;
+          // rows (J^T A): i0' = c i0 - s i1, i1' = s i0 + c i1
+          const double t00 = cP * b00 - sP * b10, t01 = cP * b01 - sP * b11;
+          const double t10 = sP * b00 + cP * b10, t11 = sP * b01 + cP * b11;
+          // columns (A J): j0' = c j0 - s j1, j1' = s j0 + c j1
+          const double n00 = cQ * t00 - sQ * t01, n01 = sQ * t00 + cQ * t01;
+          const double n10 = cQ * t10 - sQ * t11, n11 = sQ * t10 + cQ * t11;
+          A[i0 * lda + j0] = n00;
+          A[j0 * lda + i0] = n00;
+          if (vj1) {
+            A[i0 * lda + j1] = n01;
+            A[j1 * lda + i0] = n01;
+          }
+          if (vi1) {
+            A[i1 * lda + j0] = n10;
+            A[j0 * lda + i1] = n10;
+          }
+          if (vi1 && vj1) {
+            A[i1 * lda + j1] = n11;
+            A[j1 * lda + i1] = n11;
+          }
+        }
+        if (sQ != 0.0) {
+          // rows ty, ty + 32, ty + 64 (clamped reads, guarded writes)
+          const int r0 = ty, r1 = ty + 32, r2 = ty + 64;
+          const int q1 = (r1 < n) ? r1 : r0, q2 = (r2 < n) ? r2 : r0;
+          const double a0 = V[r0 * ldv + j0], b0 = V[r0 * ldv + j1];
+          const double a1 = V[q1 * ldv + j0], b1 = V[q1 * ldv + j1];
+          const double a2 = V[q2 * ldv + j0], b2 = V[q2 * ldv + j1];
+          if (r0 < n) {
+            V[r0 * ldv + j0] = cQ * a0 - sQ * b0;
+            V[r0 * ldv + j1] = sQ * a0 + cQ * b0;
+          }
+          if (r1 < n) {
+            V[r1 * ldv + j0] = cQ * a1 - sQ * b1;
+            V[r1 * ldv + j1] = sQ * a1 + cQ * b1;
+          }
+          if (r2 < n) {
+            V[r2 * ldv + j0] = cQ * a2 - sQ * b2;
+            V[r2 * ldv + j1] = sQ * a2 + cQ * b2;
+          }
         }
       }
       __syncthreads();
@@ -295,12 +345,26 @@ __device__ int blk_jacobi(double* A, int lda, double* V, int ldv, int n, double*
     const int any = *rot_flag;
     __syncthreads();
     if (!any) break;
+    // stop without a confirming sweep when no pair would rotate any more
+    if (threadIdx.x == 0) *rot_flag = 0;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+      const int i = idx / n, j = idx - i * n;
+      if (j <= i) continue;
+      const double apq = A[i * lda + j];
+      if (fabs(apq) > 0x1.0p-53 * sqrt(fabs(A[i * lda + i] * A[j * lda + j])) && fabs(apq) > abs_tol)
+        *rot_flag = 1;
+    }
+    __syncthreads();
+    const int more = *rot_flag;
+    __syncthreads();
+    if (!more) break;
   }
   return sweep + 1;
 }
 
 // evals ascending (ties by index) -> perm[rank] = index
-__device__ void blk_sort_evals(const double* A, int lda, int n, int* perm) {
+__device__ __forceinline__ void blk_sort_evals(const double* A, int lda, int n, int* perm) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const double li = A[i * lda + i];
     int rank = 0;
@@ -326,29 +390,29 @@ struct EigLds {
 
 // The second area holds V during the Jacobi sweeps and, in k_small_rr, the
 // R^p orthonormalisation work arrays afterwards (X p x na, C m x na, M, L and
-// an SVQB workspace), hence its size max(p (p+1), p m + 5 m^2 + 2 m).
+// an SVQB workspace), hence its size max(p (p+1), 2 p m + 3 m^2 + 2 m).
 __host__ __device__ inline int eig_area2(int p, int m) {
-  const int a = p * (p + 1), b = p * m + 5 * m * m + 2 * m;
+  const int a = p * (p + 1), b = 2 * p * m + 3 * m * m + 2 * m;
   return a > b ? a : b;
 }
-__device__ EigLds eig_lds(double* smem, int p, int m) {
+__device__ __forceinline__ EigLds eig_lds(double* smem, int p, int m) {
   EigLds L;
   const int ld = p + 1;
   L.A = smem;
   L.V = L.A + p * ld;
-  L.cs = L.V + eig_area2(p, m);   // 2 * 64
-  L.scratch = L.cs + 2 * 64;      // 16
+  L.cs = L.V + eig_area2(p, m);   // 3 * 64
+  L.scratch = L.cs + 3 * 64;      // 16
   L.pr = (int*)(L.scratch + 16);  // 2 * 64
   L.perm = L.pr + 2 * 64;         // 128
   L.flags = L.perm + 128;         // 8
   return L;
 }
 static size_t eig_lds_bytes(int p, int m) {
-  return sizeof(double) * (size_t)(p * (p + 1) + eig_area2(p, m) + 2 * 64 + 16) +
+  return sizeof(double) * (size_t)(p * (p + 1) + eig_area2(p, m) + 3 * 64 + 16) +
          sizeof(int) * (2 * 64 + 128 + 8);
 }
 
-__device__ void load_sym(const double* a, int p, double* A, int lda) {
+__device__ __forceinline__ void load_sym(const double* a, int p, double* A, int lda) {
   for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
     const int i = idx / p, j = idx - i * p;
     A[i * lda + j] = 0.5 * (a[i * p + j] + a[j * p + i]);
@@ -356,7 +420,7 @@ __device__ void load_sym(const double* a, int p, double* A, int lda) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(512) void k_small_eigh(const double* __restrict__ a, int p,
+__global__ __launch_bounds__(1024) void k_small_eigh(const double* __restrict__ a, int p,
                                                     double* __restrict__ evals,
                                                     double* __restrict__ evecs, int* sweeps) {
   extern __shared__ double smem[];
@@ -383,7 +447,7 @@ hipError_t small_eigh(const double* a, int p, double* evals, double* evecs, int*
     (void)hipGetLastError();
     attr = true;
   }
-  hipLaunchKernelGGL(k_small_eigh, dim3(1), dim3(512), eig_lds_bytes(p, 1), s, a, p, evals, evecs,
+  hipLaunchKernelGGL(k_small_eigh, dim3(1), dim3(1024), eig_lds_bytes(p, 1), s, a, p, evals, evecs,
                      sweeps);
   return hipGetLastError();
 }
@@ -392,7 +456,7 @@ hipError_t small_eigh(const double* a, int p, double* evals, double* evecs, int*
 // SVQB (Stathopoulos-Wu) coefficient for an n x n overlap M: X <- X U S^-1/2,
 // eigenvalues clamped below eps * max.  Writes the n x n coefficient to Cf.
 // Uses Ws (2 * n * (n+1) doubles) as Jacobi workspace.
-__device__ bool blk_svqb_coef(const double* M, int ldm, int n, double* Cf, int ldc, double* Ws,
+__device__ __forceinline__ bool blk_svqb_coef(const double* M, int ldm, int n, double* Cf, int ldc, double* Ws,
                               double* cs, int* pr, int* flag, int* perm, double* scratch) {
   const int ld = n + 1;
   double* A = Ws;
@@ -420,8 +484,9 @@ __device__ bool blk_svqb_coef(const double* M, int ldm, int n, double* Cf, int l
 // eigenvectors; optionally u_p = ortho(u_x[:, a0:m] - E[:, a0:m]; u_x) in R^p
 // by Alg. 3 / Alg. 2 (the same readings as on n-vectors).
 
-__global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ a, int p, int m,
+__global__ __launch_bounds__(1024) void k_small_rr(const double* __restrict__ a, int p, int m,
                                                   int a0, int want_up, double tau,
+                                                  const OrthoState* __restrict__ pend, int woff,
                                                   double* __restrict__ theta_all,
                                                   double* __restrict__ U, int* __restrict__ info) {
   extern __shared__ double smem[];
@@ -435,6 +500,20 @@ __global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ a, 
     zeros = stalled = passes = grams = updates = 0;
   }
   load_sym(a, p, L.A, ld);
+  // pending column scaling of the W block (see small_rr in internal.h)
+  double* dsc = L.scratch + 0;  // not used by load_sym; only read below
+  const bool scaled = (pend != nullptr) && pend->pending_scale;
+  if (scaled) {
+    const int nws = pend->nw;
+    for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
+      const int i = idx / p, j = idx - i * p;
+      const double di = (i >= woff && i < woff + nws) ? pend->dscale[i - woff] : 1.0;
+      const double dj = (j >= woff && j < woff + nws) ? pend->dscale[j - woff] : 1.0;
+      L.A[i * ld + j] *= di * dj;
+    }
+    __syncthreads();
+  }
+  (void)dsc;
   const int sw = blk_jacobi(L.A, ld, L.V, ld, p, L.cs, L.pr, L.flags, L.scratch);
   blk_sort_evals(L.A, ld, p, L.perm);
   for (int j = threadIdx.x; j < p; j += blockDim.x) theta_all[j] = L.A[L.perm[j] * ld + L.perm[j]];
@@ -448,10 +527,11 @@ __global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ a, 
   __syncthreads();
   const int na = want_up ? (m - a0) : 0;
   const int q = m + na;
-  // u_x
+  // u_x (row scaling for a pending W scaling is applied when U is written)
   for (int idx = threadIdx.x; idx < p * m; idx += blockDim.x) {
     const int i = idx / m, j = idx - i * m;
-    U[i * q + j] = Us[i * ld + j];
+    const double di = (scaled && i >= woff && i < woff + pend->nw) ? pend->dscale[i - woff] : 1.0;
+    U[i * q + j] = di * Us[i * ld + j];
   }
   int bad = 0;
   if (na > 0) {
@@ -504,15 +584,14 @@ __global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ a, 
             bad = 1;
             break;
           }
-          // X <- X Cf (Cf in Lc); use Ws as row buffer
-          for (int r = threadIdx.x; r < p; r += blockDim.x) {
-            double row[kMaxBlock];
-            for (int j = 0; j < na; ++j) row[j] = X[r * ldx + j];
-            for (int j = 0; j < na; ++j) {
-              double s = 0.0;
-              for (int k = 0; k < na; ++k) s += row[k] * Lc[k * na + j];
-              X[r * ldx + j] = s;
-            }
+          // X <- X Cf (Cf in Lc), through the Ws area as a copy of X
+          for (int idx = threadIdx.x; idx < p * na; idx += blockDim.x) Ws[idx] = X[idx];
+          __syncthreads();
+          for (int idx = threadIdx.x; idx < p * na; idx += blockDim.x) {
+            const int r = idx / na, j = idx - r * na;
+            double acc = 0.0;
+            for (int k = 0; k < na; ++k) acc += Ws[r * na + k] * Lc[k * na + j];
+            X[r * ldx + j] = acc;
           }
           __syncthreads();
         }
@@ -528,7 +607,8 @@ __global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ a, 
     }
     for (int idx = threadIdx.x; idx < p * na; idx += blockDim.x) {
       const int i = idx / na, j = idx - i * na;
-      U[i * q + m + j] = X[i * ldx + j];
+      const double di = (scaled && i >= woff && i < woff + pend->nw) ? pend->dscale[i - woff] : 1.0;
+      U[i * q + m + j] = di * X[i * ldx + j];
     }
   }
   if (threadIdx.x == 0) {
@@ -547,7 +627,8 @@ __global__ __launch_bounds__(512) void k_small_rr(const double* __restrict__ a, 
 }
 
 hipError_t small_rr(const double* a, int p, int m, int a0, int want_up, double tau,
-                    double* theta_all, double* U, int* info, hipStream_t s) {
+                    const OrthoState* pend, int woff, double* theta_all, double* U, int* info,
+                    hipStream_t s) {
   if (p < 1 || p > kMaxP || m < 1 || m > p || a0 < 0 || a0 > m) return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
@@ -557,8 +638,8 @@ hipError_t small_rr(const double* a, int p, int m, int a0, int want_up, double t
     (void)hipGetLastError();
     attr = true;
   }
-  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(512), eig_lds_bytes(p, m), s, a, p, m, a0, want_up, tau,
-                     theta_all, U, info);
+  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(1024), eig_lds_bytes(p, m), s, a, p, m, a0, want_up, tau,
+                     pend, woff, theta_all, U, info);
   return hipGetLastError();
 }
 
@@ -618,7 +699,7 @@ hipError_t small_cholesky(const double* M, int p, double* L, int* info, hipStrea
 
 enum { kPhFinal = 5 };
 
-__global__ __launch_bounds__(256) void k_ortho_ctl(const double* __restrict__ G,
+__global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G,
                                                    OrthoState* __restrict__ gst,
                                                    double* __restrict__ coef) {
   __shared__ OrthoState st;
@@ -628,7 +709,7 @@ __global__ __launch_bounds__(256) void k_ortho_ctl(const double* __restrict__ G,
   __shared__ double Li[kMaxBlock * (kMaxBlock + 1)];
   __shared__ double Ws[2 * kMaxBlock * (kMaxBlock + 1)];
   __shared__ double D[kMaxBlock];
-  __shared__ double cs[2 * 64];
+  __shared__ double cs[3 * 64];
   __shared__ int pr[2 * 64];
   __shared__ int perm[64];
   __shared__ double scratch[16];
@@ -786,7 +867,17 @@ __global__ __launch_bounds__(256) void k_ortho_ctl(const double* __restrict__ G,
   const bool y_ok = (ny == 0) || (cm <= st.tau);
   if (y_ok || st.outer >= st.max_outer) {
     if (!y_ok && threadIdx.x == 0) st.stalled++;
-    if (have_scale) {
+    if (have_scale && st.fold_scale) {
+      // leave the normalisation pending: the caller folds it into the next
+      // Rayleigh-Ritz coefficients instead of spending a pass on it
+      if (threadIdx.x == 0) {
+        for (int j = 0; j < nw; ++j) st.dscale[j] = D[j];
+        st.pending_scale = 1;
+        st.done = 1;
+        st.state = kPhDone;
+        *gst = st;
+      }
+    } else if (have_scale) {
       // apply the pending normalisation, then finish
       for (int idx = threadIdx.x; idx < nr * nw; idx += blockDim.x) {
         const int i = idx / nw, j = idx - i * nw;
@@ -819,7 +910,7 @@ __global__ __launch_bounds__(256) void k_ortho_ctl(const double* __restrict__ G,
 }
 
 __global__ void k_ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner,
-                             int max_outer) {
+                             int max_outer, int fold_scale) {
   OrthoState s;
   s.state = kPhStart;
   s.done = 0;
@@ -833,19 +924,24 @@ __global__ void k_ortho_init(OrthoState* st, int ny, int nw, double tau, int max
   s.nw = nw;
   s.max_inner = max_inner;
   s.max_outer = max_outer;
+  s.fold_scale = fold_scale;
+  s.pending_scale = 0;
   s.tau = tau;
+  for (int j = 0; j < kMaxBlock; ++j) s.dscale[j] = 1.0;
   *st = s;
 }
 
 hipError_t ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner, int max_outer,
-                      hipStream_t s) {
+                      int fold_scale, hipStream_t s) {
   if (nw < 1 || nw > kMaxBlock || ny < 0 || ny + nw > kMaxP) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_ortho_init, dim3(1), dim3(1), 0, s, st, ny, nw, tau, max_inner, max_outer);
+  hipLaunchKernelGGL(k_ortho_init, dim3(1), dim3(1), 0, s, st, ny, nw, tau, max_inner, max_outer,
+                     fold_scale);
   return hipGetLastError();
 }
 
 hipError_t ortho_ctl(const double* G, OrthoState* st, double* coef, hipStream_t s) {
-  hipLaunchKernelGGL(k_ortho_ctl, dim3(1), dim3(256), 0, s, G, st, coef);
+  // 1024 threads: the SVQB fallback runs the Jacobi sweep, which assumes them
+  hipLaunchKernelGGL(k_ortho_ctl, dim3(1), dim3(1024), 0, s, G, st, coef);
   return hipGetLastError();
 }
 

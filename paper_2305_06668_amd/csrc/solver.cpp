@@ -31,6 +31,7 @@ constexpr size_t kAlign = 256;
 constexpr int kOrthoRounds = 6;     // controller rounds launched before the first check
 constexpr int kOrthoHardCap = 64;   // rounds before giving up
 constexpr size_t kPinnedBytes = 1 << 16;
+constexpr size_t kGPartOffset = 1 << 16;  // doubles: rotation's overlap partials inside `part`
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -105,7 +106,8 @@ struct lobpcg_ctx {
   Layout plan(int m) const;
   int ensure_layout(int m);
   int apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy);
-  int ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info);
+  int ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info,
+                bool have_g0 = false, bool fold = false);
   int ensure_diag();
   int true_residuals(const double* X, int64_t ldx, int m, double* scratch, const double* theta_rr,
                      std::vector<double>& th, std::vector<double>& rn);
@@ -133,7 +135,9 @@ Layout lobpcg_ctx::plan(int m) const {
   L.AV[1] = take(blk);
   L.diag = take((size_t)n * sizeof(double));
   const size_t gblk = (size_t)std::min<int64_t>(kGramBlocks, (n + 63) / 64) + 1;
-  const size_t part = std::max(gblk * kGramMaxCols * kGramMaxCols, (size_t)kStreamBlocks * 3 * 64);
+  const size_t part =
+      std::max({gblk * kGramMaxCols * kGramMaxCols, (size_t)kStreamBlocks * 3 * 64,
+                kGPartOffset + (size_t)kStreamBlocks * kMaxP * kMaxBlock});
   L.part = take(part * sizeof(double));
   // small area
   size_t so = 0;
@@ -203,7 +207,8 @@ int lobpcg_ctx::ensure_diag() {
 }
 
 // ortho(W; Y) (Alg. 3 around Alg. 2) on base = [Y | W] rows, ld.
-int lobpcg_ctx::ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info) {
+int lobpcg_ctx::ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info,
+                          bool have_g0, bool fold) {
   OrthoState* st = small_ptr<OrthoState>(lay.ost);
   double* G = small_ptr<double>(lay.G);
   double* coef = small_ptr<double>(lay.coef);
@@ -211,8 +216,10 @@ int lobpcg_ctx::ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho
   OrthoState* hst = reinterpret_cast<OrthoState*>(pinned);
   const int nr = ny + nw;
   for (int attempt = 0; attempt < 3; ++attempt) {
-    HIPCHK(ortho_init(st, ny, nw, tau, ortho_max_inner, ortho_max_outer, stream));
-    HIPCHK(gram_f64(base, ld, nr, base + ny, ld, nw, n, part, G, nullptr, stream));
+    HIPCHK(ortho_init(st, ny, nw, tau, ortho_max_inner, ortho_max_outer, fold ? 1 : 0, stream));
+    // the overlap of the raw W~ may come fused from the rotation kernel
+    if (!(have_g0 && attempt == 0))
+      HIPCHK(gram_f64(base, ld, nr, base + ny, ld, nw, n, part, G, nullptr, stream));
     int rounds = 0;
     bool finished = false;
     while (!finished) {
@@ -324,10 +331,15 @@ int lobpcg_ctx::solve(int k, double tol) {
   } else {
     for (int j = 0; j < m; ++j) HIPCHK(fill_splitmix(V[0], m, j, j, n, kDefaultX0Seed, stream));
   }
-  rc = ortho_run(V[0], m, 0, m, nullptr);
+  rc = ortho_run(V[0], m, 0, m, nullptr, false, true);
   if (rc) return rc;
   rc = apply_op(V[0], m, m, AV[0], m);
   if (rc) return rc;
+  // a column scaling left pending by the last ortho of W (or of X0) is
+  // folded into the next Rayleigh-Ritz coefficients
+  const OrthoState* pend = small_ptr<OrthoState>(lay.ost);
+  int pend_woff = 0;
+  bool pend_valid = true;
 
   int c = 0;           // current buffer
   int L = m;           // its leading dimension (= number of columns in V)
@@ -344,7 +356,8 @@ int lobpcg_ctx::solve(int k, double tol) {
     const int want_up = first ? 0 : 1;
     int a0 = m_conv;
     int nact = m - a0;
-    HIPCHK(small_rr(a, L, m, a0, want_up, tau, theta, U, info, stream));
+    HIPCHK(small_rr(a, L, m, a0, want_up, tau, pend_valid ? pend : nullptr, pend_woff, theta, U,
+                    info, stream));
     int q = m + (want_up ? nact : 0);
     int ldo = q + nact;
     RotateArgs ra{};
@@ -361,6 +374,8 @@ int lobpcg_ctx::solve(int k, double tol) {
     ra.diag = dptr(lay.diag);
     ra.part = part;
     ra.resnorm2 = resn2;
+    ra.gpart = part + kGPartOffset;
+    ra.G0 = small_ptr<double>(lay.G);
     HIPCHK(rotate_f64(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
     HIPCHK(hipMemcpyAsync(h, resn2, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipMemcpyAsync(h + 64, theta, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
@@ -393,6 +408,7 @@ int lobpcg_ctx::solve(int k, double tol) {
       L = m;
       first = true;
       m_conv = 0;
+      pend_valid = false;  // the copied X is fully scaled
       continue;
     }
     if (newc != m_conv) {
@@ -401,7 +417,8 @@ int lobpcg_ctx::solve(int k, double tol) {
       m_conv = newc;
       a0 = m_conv;
       nact = m - a0;
-      HIPCHK(small_rr(a, L, m, a0, want_up, tau, theta, U, info, stream));
+      HIPCHK(small_rr(a, L, m, a0, want_up, tau, pend_valid ? pend : nullptr, pend_woff, theta, U,
+                      info, stream));
       q = m + (want_up ? nact : 0);
       ldo = q + nact;
       ra.ldo = ldo;
@@ -418,8 +435,10 @@ int lobpcg_ctx::solve(int k, double tol) {
     }
     ++iter;
     // ---- W = ortho(T R; [X P]) and AW = A W (Alg. 1) ----
-    rc = ortho_run(V[1 - c], ldo, q, nact, nullptr);
+    rc = ortho_run(V[1 - c], ldo, q, nact, nullptr, true, true);
     if (rc) return rc;
+    pend_valid = true;
+    pend_woff = q;
     rc = apply_op(V[1 - c] + q, ldo, nact, AV[1 - c] + q, ldo);
     if (rc) return rc;
     c = 1 - c;
