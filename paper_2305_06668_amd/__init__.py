@@ -435,6 +435,8 @@ class Solver:
 
     def set_option(self, key, value):
         lobpcg_set_option(self.h, key, value)
+        if key == OPT_PRECISION and self._block is not None:
+            self.ensure_workspace(self._block)  # the fp32 phase needs more workspace
 
     def set_initial_guess(self, X0):
         self._keep["X0"] = X0

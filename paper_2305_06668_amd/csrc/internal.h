@@ -64,6 +64,9 @@ hipError_t tsmm_f32(const float* In, int64_t ldi, int p, const double* Coef, int
 hipError_t ortho_apply_f64(double* base, int64_t ld, int ny, int nw, const double* coef,
                            const OrthoState* st, int64_t n, double* part, double* G,
                            hipStream_t s);
+hipError_t ortho_apply_f32(float* base, int64_t ld, int ny, int nw, const double* coef,
+                           const OrthoState* st, int64_t n, double* part, double* G,
+                           hipStream_t s);
 
 // Rotation + residual + preconditioner (one pass over V and AV).
 struct RotateArgs {
@@ -91,6 +94,9 @@ hipError_t colstats_f64(const double* X, int64_t ldx, const double* AX, int64_t 
 // entry i = (splitmix64(seed + col_id * n + i) >> 11) * 2^-53 - 0.5.
 hipError_t fill_splitmix(double* X, int64_t ld, int col, int col_id, int64_t n, uint64_t seed,
                          hipStream_t s);
+
+hipError_t fill_splitmix_f32(float* X, int64_t ld, int col, int col_id, int64_t n, uint64_t seed,
+                             hipStream_t s);
 
 // Copy the first k columns of X to out (ld_out) with each column's sign set so
 // its largest-magnitude entry (lowest index on ties) is positive.
@@ -125,6 +131,12 @@ hipError_t csr_diag(const int32_t* rp, const int32_t* ci, const double* val, int
 hipError_t dense_diag(const double* A, int64_t lda, int64_t n, double* diag, hipStream_t s);
 hipError_t kronsum_diag(const double* A, const double* Vp, int64_t na, double* diag,
                         hipStream_t s);
+// Gershgorin bound max_i sum_j |a_ij| of the operator (device result in *out,
+// via `part` partials of kStreamBlocks doubles).
+hipError_t csr_norm_bound(const int32_t* rp, const double* val, int64_t n, double* part,
+                          double* out, hipStream_t s);
+hipError_t dense_norm_bound(const double* A, int64_t lda, int64_t n, double* part, double* out,
+                            hipStream_t s);
 
 // ---- small dense fp64 kernels (k_small.hip) -----------------------------
 // Eigen-decomposition of sym(a) (p x p): evals ascending, evecs p x p.

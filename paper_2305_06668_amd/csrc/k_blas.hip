@@ -329,47 +329,48 @@ __device__ __forceinline__ void stage_rows(const T* __restrict__ In, int64_t ld,
 // accumulated with MFMA straight from LDS (K = 4 rows per MFMA).  Skips
 // itself when the controller has finished (st->done).
 
-template <int MTI, int MTJ>
-__global__ __launch_bounds__(256) void k_ortho_apply(double* base, int64_t ld, int ny, int nw,
+template <typename T, int MTI, int MTJ>
+__global__ __launch_bounds__(256) void k_ortho_apply(T* base, int64_t ld, int ny, int nw,
                                                      const double* __restrict__ coef,
                                                      const OrthoState* __restrict__ st, int64_t n,
                                                      double* __restrict__ part) {
+  typedef typename AccOf<T>::type AccT;
   if (st->done) return;
   const int w_only = st->w_only;
   const int nr = ny + nw;
   extern __shared__ double smem_d[];
-  double* cf = smem_d;
-  double* tile = cf + ((nr * nw + 1) & ~1);
-  double* red = tile + 64 * (nr + 1);
+  double* red = smem_d;                          // MTI * MTJ * 256 doubles
+  T* cf = reinterpret_cast<T*>(red + MTI * MTJ * 256);
+  T* tile = cf + ((nr * nw + 1) & ~1);
   const int ldt = nr + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, cc = lane & 15;
-  for (int i = threadIdx.x; i < nr * nw; i += 256) cf[i] = coef[i];
-  d4 G[MTI][MTJ];
+  for (int i = threadIdx.x; i < nr * nw; i += 256) cf[i] = (T)coef[i];
+  AccT G[MTI][MTJ];
 #pragma unroll
   for (int I = 0; I < MTI; ++I)
 #pragma unroll
-    for (int J = 0; J < MTJ; ++J) G[I][J] = d4{0, 0, 0, 0};
+    for (int J = 0; J < MTJ; ++J) G[I][J] = AccT{0, 0, 0, 0};
   const int kbeg = w_only ? (ny & ~3) : 0;  // coefficient rows < ny are zero then
   const int64_t nchunks = (n + 63) / 64;
   for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
     __syncthreads();
     const int64_t row0 = chunk * 64;
     const int rows = (int)min<int64_t>(64, n - row0);
-    stage_rows<double>(base, ld, nr, row0, rows, tile);
+    stage_rows<T>(base, ld, nr, row0, rows, tile);
     __syncthreads();
-    d4 acc[MTJ];
+    AccT acc[MTJ];
 #pragma unroll
-    for (int J = 0; J < MTJ; ++J) acc[J] = d4{0, 0, 0, 0};
+    for (int J = 0; J < MTJ; ++J) acc[J] = AccT{0, 0, 0, 0};
     const int arow = wave * 16 + cc;
     for (int k = kbeg; k < nr; k += 4) {
       const int kk = k + g;
       const bool kv = kk < nr;
-      const double a = kv ? tile[arow * ldt + kk] : 0.0;
+      const T a = kv ? tile[arow * ldt + kk] : T(0);
 #pragma unroll
       for (int J = 0; J < MTJ; ++J) {
         const int col = J * 16 + cc;
-        const double b = (kv && col < nw) ? cf[kk * nw + col] : 0.0;
+        const T b = (kv && col < nw) ? cf[kk * nw + col] : T(0);
         acc[J] = mma(a, b, acc[J]);
       }
     }
@@ -379,27 +380,28 @@ __global__ __launch_bounds__(256) void k_ortho_apply(double* base, int64_t ld, i
       const int col = J * 16 + cc;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int rl = wave * 16 + 4 * r + g;
+        const int rl = wave * 16 + acc_row<T>(r, lane);
         if (rl < rows && col < nw) {
-          base[(row0 + rl) * ld + ny + col] = acc[J][r];
-          tile[rl * ldt + ny + col] = acc[J][r];
+          const T v = (T)acc[J][r];
+          base[(row0 + rl) * ld + ny + col] = v;
+          tile[rl * ldt + ny + col] = v;
         }
       }
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int rl = wave * 16 + 4 * r + g;
-      double bj[MTJ];
+      const int rl = wave * 16 + 4 * r + g;  // K = 4 rows per MFMA, any row order
+      T bj[MTJ];
 #pragma unroll
       for (int J = 0; J < MTJ; ++J) {
         const int cj = J * 16 + cc;
-        bj[J] = (cj < nw) ? tile[rl * ldt + ny + cj] : 0.0;
+        bj[J] = (cj < nw) ? tile[rl * ldt + ny + cj] : T(0);
       }
 #pragma unroll
       for (int I = 0; I < MTI; ++I) {
         const int ci = I * 16 + cc;
-        const double ai = (ci < nr) ? tile[rl * ldt + ci] : 0.0;
+        const T ai = (ci < nr) ? tile[rl * ldt + ci] : T(0);
 #pragma unroll
         for (int J = 0; J < MTJ; ++J) G[I][J] = mma(ai, bj[J], G[I][J]);
       }
@@ -414,8 +416,9 @@ __global__ __launch_bounds__(256) void k_ortho_apply(double* base, int64_t ld, i
         for (int J = 0; J < MTJ; ++J)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int idx = (I * MTJ + J) * 256 + (4 * r + g) * 16 + cc;
-            red[idx] = (w == 0) ? G[I][J][r] : red[idx] + G[I][J][r];
+            const int idx = (I * MTJ + J) * 256 + acc_row<T>(r, lane) * 16 + cc;
+            const double v = (double)G[I][J][r];
+            red[idx] = (w == 0) ? v : red[idx] + v;
           }
     }
     __syncthreads();
@@ -427,51 +430,64 @@ __global__ __launch_bounds__(256) void k_ortho_apply(double* base, int64_t ld, i
   }
 }
 
-template <int MTI, int MTJ>
-static hipError_t ortho_apply_launch(double* base, int64_t ld, int ny, int nw, const double* coef,
+template <typename T, int MTI, int MTJ>
+static hipError_t ortho_apply_launch(T* base, int64_t ld, int ny, int nw, const double* coef,
                                      const OrthoState* st, int64_t n, double* part, double* G,
                                      hipStream_t s) {
   static bool attr = false;
   const int nr = ny + nw;
-  const size_t sm = sizeof(double) * (size_t)(((nr * nw + 1) & ~1) + 64 * (nr + 1) + MTI * MTJ * 256);
+  const size_t sm = sizeof(double) * (size_t)(MTI * MTJ * 256) +
+                    sizeof(T) * (size_t)(((nr * nw + 1) & ~1) + 64 * (nr + 1));
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_ortho_apply<MTI, MTJ>,
+    (void)hipFuncSetAttribute((const void*)k_ortho_apply<T, MTI, MTJ>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
     (void)hipGetLastError();
     attr = true;
   }
   const int64_t nchunks = (n + 63) / 64;
   const int grid = (int)std::min<int64_t>(nchunks, kGramBlocks);
-  hipLaunchKernelGGL((k_ortho_apply<MTI, MTJ>), dim3(grid), dim3(256), sm, s, base, ld, ny, nw,
+  hipLaunchKernelGGL((k_ortho_apply<T, MTI, MTJ>), dim3(grid), dim3(256), sm, s, base, ld, ny, nw,
                      coef, st, n, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return sum_parts(part, grid, nr * nw, G, &st->done, s);
 }
 
-hipError_t ortho_apply_f64(double* base, int64_t ld, int ny, int nw, const double* coef,
-                           const OrthoState* st, int64_t n, double* part, double* G,
-                           hipStream_t s) {
+template <typename T>
+static hipError_t ortho_apply_any(T* base, int64_t ld, int ny, int nw, const double* coef,
+                                  const OrthoState* st, int64_t n, double* part, double* G,
+                                  hipStream_t s) {
   const int nr = ny + nw;
   if (nw < 1 || nw > kMaxBlock || ny < 0 || nr > kMaxP || n < 1) return hipErrorInvalidValue;
   const int TI = (nr + 15) / 16;
   if (nw <= 16) {
     switch (TI) {
-      case 1: return ortho_apply_launch<1, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
-      case 2: return ortho_apply_launch<2, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
-      case 3: return ortho_apply_launch<3, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
-      case 4: return ortho_apply_launch<4, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
-      case 5: return ortho_apply_launch<5, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
-      default: return ortho_apply_launch<6, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      case 1: return ortho_apply_launch<T, 1, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      case 2: return ortho_apply_launch<T, 2, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      case 3: return ortho_apply_launch<T, 3, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      case 4: return ortho_apply_launch<T, 4, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      case 5: return ortho_apply_launch<T, 5, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
+      default: return ortho_apply_launch<T, 6, 1>(base, ld, ny, nw, coef, st, n, part, G, s);
     }
   }
   switch (TI) {
-    case 2: return ortho_apply_launch<2, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
-    case 3: return ortho_apply_launch<3, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
-    case 4: return ortho_apply_launch<4, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
-    case 5: return ortho_apply_launch<5, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
-    default: return ortho_apply_launch<6, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
+    case 2: return ortho_apply_launch<T, 2, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
+    case 3: return ortho_apply_launch<T, 3, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
+    case 4: return ortho_apply_launch<T, 4, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
+    case 5: return ortho_apply_launch<T, 5, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
+    default: return ortho_apply_launch<T, 6, 2>(base, ld, ny, nw, coef, st, n, part, G, s);
   }
+}
+
+hipError_t ortho_apply_f64(double* base, int64_t ld, int ny, int nw, const double* coef,
+                           const OrthoState* st, int64_t n, double* part, double* G,
+                           hipStream_t s) {
+  return ortho_apply_any<double>(base, ld, ny, nw, coef, st, n, part, G, s);
+}
+hipError_t ortho_apply_f32(float* base, int64_t ld, int ny, int nw, const double* coef,
+                           const OrthoState* st, int64_t n, double* part, double* G,
+                           hipStream_t s) {
+  return ortho_apply_any<float>(base, ld, ny, nw, coef, st, n, part, G, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -866,6 +882,21 @@ hipError_t fill_splitmix(double* X, int64_t ld, int col, int col_id, int64_t n, 
                          hipStream_t s) {
   hipLaunchKernelGGL(k_fill_splitmix, dim3(cdiv(n, 256)), dim3(256), 0, s, X, ld, col, col_id, n,
                      seed);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_splitmix_f32(float* X, int64_t ld, int col, int col_id, int64_t n,
+                                    uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t z = splitmix64(seed + (uint64_t)col_id * (uint64_t)n + (uint64_t)i);
+  X[i * ld + col] = (float)((double)(z >> 11) * 0x1.0p-53 - 0.5);
+}
+
+hipError_t fill_splitmix_f32(float* X, int64_t ld, int col, int col_id, int64_t n, uint64_t seed,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_splitmix_f32, dim3(cdiv(n, 256)), dim3(256), 0, s, X, ld, col, col_id,
+                     n, seed);
   return hipGetLastError();
 }
 

@@ -234,6 +234,72 @@ hipError_t csr_check(const int32_t* rp, const int32_t* ci, int64_t n, int64_t nn
 }
 
 // ---------------------------------------------------------------------------
+// Gershgorin bound max_i sum_j |a_ij| (used by the precision switch)
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = fmax(r, sh[i]);
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_csr_rowabs(const int32_t* __restrict__ rp,
+                                                    const double* __restrict__ val, int64_t n,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[4];
+  double best = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) s += fabs(val[e]);
+    best = fmax(best, s);
+  }
+  best = block_max(best, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = best;
+}
+
+__global__ __launch_bounds__(256) void k_dense_rowabs(const double* __restrict__ A, int64_t lda,
+                                                      int64_t n, double* __restrict__ part) {
+  __shared__ double sh[4];
+  double best = 0.0;
+  // one wave per row
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+    double s = 0.0;
+    for (int64_t j = lane; j < n; j += 64) s += fabs(A[i * lda + j]);
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    best = fmax(best, s);
+  }
+  best = block_max(best, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = best;
+}
+
+__global__ void k_max_final(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+  __shared__ double sh[4];
+  double best = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) best = fmax(best, part[i]);
+  best = block_max(best, sh);
+  if (threadIdx.x == 0) *out = best;
+}
+
+hipError_t csr_norm_bound(const int32_t* rp, const double* val, int64_t n, double* part,
+                          double* out, hipStream_t s) {
+  const int grid = (int)std::min<int64_t>(kStreamBlocks, cdiv(n, 256));
+  hipLaunchKernelGGL(k_csr_rowabs, dim3(grid), dim3(256), 0, s, rp, val, n, part);
+  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, part, grid, out);
+  return hipGetLastError();
+}
+
+hipError_t dense_norm_bound(const double* A, int64_t lda, int64_t n, double* part, double* out,
+                            hipStream_t s) {
+  const int grid = (int)std::min<int64_t>(kStreamBlocks, cdiv(n, 4));
+  hipLaunchKernelGGL(k_dense_rowabs, dim3(grid), dim3(256), 0, s, A, lda, n, part);
+  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, part, grid, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // diagonals (inputs of the Jacobi preconditioner)
 
 __global__ void k_csr_diag(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,

@@ -39,6 +39,7 @@ enum OpKind { kOpNone = 0, kOpCsr = 1, kOpDense = 2, kOpKron = 3 };
 
 struct Layout {
   size_t V[2], AV[2], diag, part, small, total;
+  size_t V32[2], AV32[2], op32;  // mixed precision only (0 otherwise)
   // inside small (byte offsets)
   size_t a, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye;
 };
@@ -89,6 +90,9 @@ struct lobpcg_ctx {
   std::vector<double> res_evals, res_resn;
   lobpcg_stats stats{};
   std::string err;
+  // fp32 operator copies (mixed precision) and the operator norm bound
+  bool op32_ready = false;
+  double norm_bound = -1.0;
 
   // ---- helpers ----
   double* dptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
@@ -104,13 +108,25 @@ struct lobpcg_ctx {
     return LOBPCG_ERR_DEVICE;
   }
   Layout plan(int m) const;
+  size_t op32_elems() const;
   int ensure_layout(int m);
   int apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy);
-  int ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info,
-                bool have_g0 = false, bool fold = false);
+  int apply_op(const float* W, int64_t ldw, int nc, float* Y, int64_t ldy);
+  template <typename T>
+  int ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info, bool have_g0 = false,
+                bool fold = false, double tau_run = -1.0);
   int ensure_diag();
+  int ensure_op32();
   int true_residuals(const double* X, int64_t ldx, int m, double* scratch, const double* theta_rr,
                      std::vector<double>& th, std::vector<double>& rn);
+  struct PhaseOut {
+    const void* X;  // final Ritz vectors of the phase (first m columns)
+    int64_t ld;
+    bool converged;
+  };
+  template <typename T>
+  int run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool low, int& iter,
+                PhaseOut& out);
   int solve(int k, double tol);
 };
 
@@ -119,6 +135,15 @@ struct lobpcg_ctx {
     hipError_t e_ = (expr);                           \
     if (e_ != hipSuccess) return hip_fail(e_, #expr); \
   } while (0)
+
+size_t lobpcg_ctx::op32_elems() const {
+  switch (op) {
+    case kOpCsr: return (size_t)nnz;
+    case kOpDense: return (size_t)n * (size_t)n;
+    case kOpKron: return 2 * (size_t)na * (size_t)na;
+    default: return 0;
+  }
+}
 
 Layout lobpcg_ctx::plan(int m) const {
   Layout L{};
@@ -159,19 +184,28 @@ Layout lobpcg_ctx::plan(int m) const {
   L.pval = stake(sizeof(double) * 256 * 64);
   L.eye = stake(sizeof(double) * 64 * 64);
   L.small = take(so);
+  if (precision == LOBPCG_PREC_FP32) {
+    const size_t blk32 = (size_t)n * 3 * m * sizeof(float);
+    L.V32[0] = take(blk32);
+    L.V32[1] = take(blk32);
+    L.AV32[0] = take(blk32);
+    L.AV32[1] = take(blk32);
+    L.op32 = take(op32_elems() * sizeof(float));
+  }
   L.total = off;
   return L;
 }
 
 int lobpcg_ctx::ensure_layout(int m) {
   if (ws == nullptr) return fail(LOBPCG_ERR_WORKSPACE, "no workspace set");
-  if (lay_block != m) {
-    Layout L = plan(m);
+  Layout L = plan(m);
+  if (lay_block != m || L.total != lay.total) {
     if (L.total > ws_bytes)
       return fail(LOBPCG_ERR_WORKSPACE, "workspace smaller than lobpcg_workspace_size");
     lay = L;
     lay_block = m;
     diag_ready = false;
+    op32_ready = false;
   }
   return LOBPCG_OK;
 }
@@ -186,6 +220,53 @@ int lobpcg_ctx::apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_
   }
   if (e != hipSuccess) return hip_fail(e, "operator");
   stats.matvec_columns += nc;
+  return LOBPCG_OK;
+}
+
+// fp32 operator (mixed-precision phase): copies made by ensure_op32
+int lobpcg_ctx::apply_op(const float* W, int64_t ldw, int nc, float* Y, int64_t ldy) {
+  const float* o32 = reinterpret_cast<const float*>(ws + lay.op32);
+  hipError_t e = hipSuccess;
+  switch (op) {
+    case kOpCsr: e = spmm_csr_f32(rp, ci, o32, W, ldw, Y, ldy, nc, n, stream); break;
+    case kOpDense: e = dense_apply_f32(o32, n, W, ldw, Y, ldy, nc, n, stream); break;
+    case kOpKron:
+      e = kronsum_apply_f32(o32, o32 + na * na, na, W, ldw, Y, ldy, nc, stream);
+      break;
+    default: return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+  }
+  if (e != hipSuccess) return hip_fail(e, "operator (fp32)");
+  stats.matvec_columns += nc;
+  return LOBPCG_OK;
+}
+
+int lobpcg_ctx::ensure_op32() {
+  if (op32_ready) return LOBPCG_OK;
+  float* o32 = reinterpret_cast<float*>(ws + lay.op32);
+  double* part = dptr(lay.part);
+  double* nb = small_ptr<double>(lay.cols);
+  double* h = reinterpret_cast<double*>(pinned);
+  switch (op) {
+    case kOpCsr:
+      HIPCHK(convert_vec_f64_to_f32(val, o32, nnz, stream));
+      HIPCHK(csr_norm_bound(rp, val, n, part, nb, stream));
+      break;
+    case kOpDense:
+      HIPCHK(convert_f64_to_f32(A, lda, o32, n, (int)n, n, stream));
+      HIPCHK(dense_norm_bound(A, lda, n, part, nb, stream));
+      break;
+    case kOpKron:
+      HIPCHK(convert_vec_f64_to_f32(A, o32, na * na, stream));
+      HIPCHK(convert_vec_f64_to_f32(Vpot, o32 + na * na, na * na, stream));
+      HIPCHK(dense_norm_bound(A, na, na, part, nb, stream));
+      HIPCHK(dense_norm_bound(Vpot, na, na, part, nb + 1, stream));
+      break;
+    default: return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+  }
+  HIPCHK(hipMemcpyAsync(h, nb, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  norm_bound = (op == kOpKron) ? 2.0 * h[0] + h[1] : h[0];
+  op32_ready = true;
   return LOBPCG_OK;
 }
 
@@ -206,27 +287,65 @@ int lobpcg_ctx::ensure_diag() {
   return LOBPCG_OK;
 }
 
+// typed dispatch of the streaming kernels
+static hipError_t gram_t(const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
+                         int64_t n, double* part, double* C, const int* skip, hipStream_t s) {
+  return gram_f64(A, lda, p, B, ldb, q, n, part, C, skip, s);
+}
+static hipError_t gram_t(const float* A, int64_t lda, int p, const float* B, int64_t ldb, int q,
+                         int64_t n, double* part, double* C, const int* skip, hipStream_t s) {
+  return gram_f32(A, lda, p, B, ldb, q, n, part, C, skip, s);
+}
+static hipError_t rotate_t(const double* V, const double* AV, double* Vo, double* AVo,
+                           const RotateArgs& a, hipStream_t s) {
+  return rotate_f64(V, AV, Vo, AVo, a, s);
+}
+static hipError_t rotate_t(const float* V, const float* AV, float* Vo, float* AVo,
+                           const RotateArgs& a, hipStream_t s) {
+  return rotate_f32(V, AV, Vo, AVo, a, s);
+}
+static hipError_t ortho_apply_t(double* b, int64_t ld, int ny, int nw, const double* coef,
+                                const OrthoState* st, int64_t n, double* part, double* G,
+                                hipStream_t s) {
+  return ortho_apply_f64(b, ld, ny, nw, coef, st, n, part, G, s);
+}
+static hipError_t ortho_apply_t(float* b, int64_t ld, int ny, int nw, const double* coef,
+                                const OrthoState* st, int64_t n, double* part, double* G,
+                                hipStream_t s) {
+  return ortho_apply_f32(b, ld, ny, nw, coef, st, n, part, G, s);
+}
+static hipError_t fill_t(double* X, int64_t ld, int col, int id, int64_t n, uint64_t seed,
+                         hipStream_t s) {
+  return fill_splitmix(X, ld, col, id, n, seed, s);
+}
+static hipError_t fill_t(float* X, int64_t ld, int col, int id, int64_t n, uint64_t seed,
+                         hipStream_t s) {
+  return fill_splitmix_f32(X, ld, col, id, n, seed, s);
+}
+
 // ortho(W; Y) (Alg. 3 around Alg. 2) on base = [Y | W] rows, ld.
-int lobpcg_ctx::ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info,
-                          bool have_g0, bool fold) {
+template <typename T>
+int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info,
+                          bool have_g0, bool fold, double tau_run) {
   OrthoState* st = small_ptr<OrthoState>(lay.ost);
   double* G = small_ptr<double>(lay.G);
   double* coef = small_ptr<double>(lay.coef);
   double* part = dptr(lay.part);
   OrthoState* hst = reinterpret_cast<OrthoState*>(pinned);
   const int nr = ny + nw;
+  const double t = (tau_run > 0.0) ? tau_run : tau;
   for (int attempt = 0; attempt < 3; ++attempt) {
-    HIPCHK(ortho_init(st, ny, nw, tau, ortho_max_inner, ortho_max_outer, fold ? 1 : 0, stream));
+    HIPCHK(ortho_init(st, ny, nw, t, ortho_max_inner, ortho_max_outer, fold ? 1 : 0, stream));
     // the overlap of the raw W~ may come fused from the rotation kernel
     if (!(have_g0 && attempt == 0))
-      HIPCHK(gram_f64(base, ld, nr, base + ny, ld, nw, n, part, G, nullptr, stream));
+      HIPCHK(gram_t(base, ld, nr, base + ny, ld, nw, n, part, G, nullptr, stream));
     int rounds = 0;
     bool finished = false;
     while (!finished) {
       const int batch = (rounds == 0) ? kOrthoRounds : 2;
       for (int r = 0; r < batch; ++r) {
         HIPCHK(ortho_ctl(G, st, coef, stream));
-        HIPCHK(ortho_apply_f64(base, ld, ny, nw, coef, st, n, part, G, stream));
+        HIPCHK(ortho_apply_t(base, ld, ny, nw, coef, st, n, part, G, stream));
       }
       rounds += batch;
       HIPCHK(hipMemcpyAsync(hst, st, sizeof(OrthoState), hipMemcpyDeviceToHost, stream));
@@ -257,8 +376,7 @@ int lobpcg_ctx::ortho_run(double* base, int64_t ld, int ny, int nw, lobpcg_ortho
     if (s.error == kOrthoErrFailed) return fail(LOBPCG_ERR_ORTHO_FAILED, "shifted Cholesky and SVQB failed");
     // exact zero columns: replace by SplitMix64 columns and start again
     for (int j = 0; j < nw; ++j)
-      if (s.zero_mask & (1 << j))
-        HIPCHK(fill_splitmix(base + ny, ld, j, j, n, kZeroColumnSeed, stream));
+      if (s.zero_mask & (1 << j)) HIPCHK(fill_t(base + ny, ld, j, j, n, kZeroColumnSeed, stream));
   }
   return fail(LOBPCG_ERR_ORTHO_FAILED, "zero columns persist");
 }
@@ -297,25 +415,18 @@ static int leading_converged(const std::vector<double>& r, double tol) {
   return c;
 }
 
-int lobpcg_ctx::solve(int k, double tol) {
-  const auto t0 = std::chrono::steady_clock::now();
-  if (op == kOpNone) return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+// One precision phase of Alg. 1, starting from the block X stored in V0
+// (leading dimension m, not yet orthonormal).  `low` selects the fp32 phase
+// (reading of the mixed-precision extension): no locking, ortho threshold
+// 1e-6, and the phase ends when every residual is within 100 fp32 roundoffs
+// of ||A|| or has stalled (no 10% decrease over 3 iterations).  The fp64
+// phase ends on the true-residual check (reading R9) or max_iter.
+template <typename T>
+int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool low, int& iter,
+                          PhaseOut& out) {
   const int m = block;
-  if (m < 1) return fail(LOBPCG_ERR_BAD_STATE, "block size unknown: set an initial guess or query the workspace");
-  if (k < 1 || k > m) return fail(LOBPCG_ERR_INVALID_ARG, "need 1 <= k <= block");
-  if (!(tol > 0.0)) return fail(LOBPCG_ERR_INVALID_ARG, "tol must be > 0");
-  if (precision != LOBPCG_PREC_FP64) return fail(LOBPCG_ERR_UNSUPPORTED, "precision mode not built");
-  int rc = ensure_layout(m);
-  if (rc) return rc;
-  std::memset(&stats, 0, sizeof(stats));
-  stats.precision_switch_iter = -1;
-  have_result = false;
-  if (pkind != LOBPCG_PRECOND_NONE) {
-    rc = ensure_diag();
-    if (rc) return rc;
-  }
-  double* V[2] = {dptr(lay.V[0]), dptr(lay.V[1])};
-  double* AV[2] = {dptr(lay.AV[0]), dptr(lay.AV[1])};
+  T* V[2] = {V0, V1};
+  T* AV[2] = {AV0, AV1};
   double* a = small_ptr<double>(lay.a);
   double* theta = small_ptr<double>(lay.theta);
   double* U = small_ptr<double>(lay.U);
@@ -323,15 +434,10 @@ int lobpcg_ctx::solve(int k, double tol) {
   int* info = small_ptr<int>(lay.info);
   double* part = dptr(lay.part);
   double* h = reinterpret_cast<double*>(pinned);
-
-  // ---- initial block (Alg. 1 input; reading: orthonormalise X0 first) ----
-  if (X0 != nullptr) {
-    HIPCHK(hipMemcpy2DAsync(V[0], sizeof(double) * m, X0, sizeof(double) * ldx0,
-                            sizeof(double) * m, n, hipMemcpyDeviceToDevice, stream));
-  } else {
-    for (int j = 0; j < m; ++j) HIPCHK(fill_splitmix(V[0], m, j, j, n, kDefaultX0Seed, stream));
-  }
-  rc = ortho_run(V[0], m, 0, m, nullptr, false, true);
+  const double tau_phase = low ? 1e-6 : tau;
+  const double lock_tol = low ? -1.0 : tol;  // nothing locks in the fp32 phase
+  const double switch_level = 100.0 * 0x1.0p-24 * (norm_bound > 0.0 ? norm_bound : 1.0);
+  int rc = ortho_run<T>(V[0], m, 0, m, nullptr, false, true, tau_phase);
   if (rc) return rc;
   rc = apply_op(V[0], m, m, AV[0], m);
   if (rc) return rc;
@@ -345,19 +451,18 @@ int lobpcg_ctx::solve(int k, double tol) {
   int L = m;           // its leading dimension (= number of columns in V)
   bool first = true;   // V = [X] only (initial RR, or restart after a true check)
   int m_conv = 0;
-  int iter = 0;
-  bool converged = false;
+  double prev_max = INFINITY;
+  int stall = 0;
   std::vector<double> rnorm(m), th_rr(m), th_t, rn_t;
-  const double* Xres = nullptr;
-  int64_t Xld = 0;
+  out.converged = false;
   for (;;) {
     // ---- Rayleigh-Ritz in V (Alg. 1) ----
-    HIPCHK(gram_f64(V[c], L, L, AV[c], L, L, n, part, a, nullptr, stream));
+    HIPCHK(gram_t(V[c], L, L, AV[c], L, L, n, part, a, nullptr, stream));
     const int want_up = first ? 0 : 1;
     int a0 = m_conv;
     int nact = m - a0;
-    HIPCHK(small_rr(a, L, m, a0, want_up, tau, pend_valid ? pend : nullptr, pend_woff, theta, U,
-                    info, stream));
+    HIPCHK(small_rr(a, L, m, a0, want_up, tau_phase, pend_valid ? pend : nullptr, pend_woff, theta,
+                    U, info, stream));
     int q = m + (want_up ? nact : 0);
     int ldo = q + nact;
     RotateArgs ra{};
@@ -376,35 +481,48 @@ int lobpcg_ctx::solve(int k, double tol) {
     ra.resnorm2 = resn2;
     ra.gpart = part + kGPartOffset;
     ra.G0 = small_ptr<double>(lay.G);
-    HIPCHK(rotate_f64(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
+    HIPCHK(rotate_t(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
     HIPCHK(hipMemcpyAsync(h, resn2, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipMemcpyAsync(h + 64, theta, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipMemcpyAsync(h + 128, info, sizeof(int) * 16, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     const int* hinfo = reinterpret_cast<const int*>(h + 128);
     if (hinfo[1] != 0) return fail(LOBPCG_ERR_ORTHO_FAILED, "R^p orthonormalisation of u_p failed");
+    double rmax = 0.0;
     for (int j = 0; j < m; ++j) {
       rnorm[j] = std::sqrt(h[j]);
       th_rr[j] = h[64 + j];
       if (!std::isfinite(rnorm[j]) || !std::isfinite(th_rr[j]))
         return fail(LOBPCG_ERR_NONFINITE, "non-finite Ritz value or residual");
+      rmax = std::max(rmax, rnorm[j]);
     }
-    const int newc = std::max(m_conv, leading_converged(rnorm, tol));
-    if (newc >= k) {
+    if (low) {
+      stall = (rmax > 0.9 * prev_max) ? stall + 1 : 0;
+      prev_max = std::min(prev_max, rmax);
+      if (rmax <= switch_level || stall >= 3 || iter >= max_iter) {
+        out.X = V[1 - c];
+        out.ld = ldo;
+        return LOBPCG_OK;
+      }
+    }
+    const int newc = std::max(m_conv, leading_converged(rnorm, lock_tol));
+    if (!low && newc >= k) {
       // reading R9: judge with an explicit product A X
-      rc = true_residuals(V[1 - c], ldo, m, AV[c], theta, th_t, rn_t);
+      const double* Xd = reinterpret_cast<const double*>(V[1 - c]);
+      double* scratch = reinterpret_cast<double*>(AV[c]);
+      rc = true_residuals(Xd, ldo, m, scratch, theta, th_t, rn_t);
       if (rc) return rc;
       double worst = 0.0;
       for (int j = 0; j < k; ++j) worst = std::max(worst, rn_t[j]);
       if (worst <= tol) {
-        converged = true;
-        Xres = V[1 - c];
-        Xld = ldo;
+        out.converged = true;
+        out.X = V[1 - c];
+        out.ld = ldo;
         break;
       }
       // restart from X with the explicit product: V = [X], AV = [A X]
-      HIPCHK(hipMemcpy2DAsync(V[c], sizeof(double) * m, V[1 - c], sizeof(double) * ldo,
-                              sizeof(double) * m, n, hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipMemcpy2DAsync(V[c], sizeof(T) * m, V[1 - c], sizeof(T) * ldo, sizeof(T) * m, n,
+                              hipMemcpyDeviceToDevice, stream));
       L = m;
       first = true;
       m_conv = 0;
@@ -417,25 +535,26 @@ int lobpcg_ctx::solve(int k, double tol) {
       m_conv = newc;
       a0 = m_conv;
       nact = m - a0;
-      HIPCHK(small_rr(a, L, m, a0, want_up, tau, pend_valid ? pend : nullptr, pend_woff, theta, U,
-                      info, stream));
+      HIPCHK(small_rr(a, L, m, a0, want_up, tau_phase, pend_valid ? pend : nullptr, pend_woff,
+                      theta, U, info, stream));
       q = m + (want_up ? nact : 0);
       ldo = q + nact;
       ra.ldo = ldo;
       ra.q = q;
       ra.a0 = a0;
-      HIPCHK(rotate_f64(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
+      HIPCHK(rotate_t(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
     }
     if (iter >= max_iter) {
-      rc = true_residuals(V[1 - c], ldo, m, AV[c], theta, th_t, rn_t);
+      const double* Xd = reinterpret_cast<const double*>(V[1 - c]);
+      rc = true_residuals(Xd, ldo, m, reinterpret_cast<double*>(AV[c]), theta, th_t, rn_t);
       if (rc) return rc;
-      Xres = V[1 - c];
-      Xld = ldo;
+      out.X = V[1 - c];
+      out.ld = ldo;
       break;
     }
     ++iter;
     // ---- W = ortho(T R; [X P]) and AW = A W (Alg. 1) ----
-    rc = ortho_run(V[1 - c], ldo, q, nact, nullptr, true, true);
+    rc = ortho_run<T>(V[1 - c], ldo, q, nact, nullptr, true, true, tau_phase);
     if (rc) return rc;
     pend_valid = true;
     pend_woff = q;
@@ -445,18 +564,67 @@ int lobpcg_ctx::solve(int k, double tol) {
     L = ldo;
     first = false;
   }
+  if (!low) {
+    res_evals.assign(th_t.begin(), th_t.begin() + m);
+    res_resn.assign(rn_t.begin(), rn_t.begin() + m);
+    stats.m_conv = m_conv;
+  }
+  return LOBPCG_OK;
+}
+
+int lobpcg_ctx::solve(int k, double tol) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (op == kOpNone) return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+  const int m = block;
+  if (m < 1) return fail(LOBPCG_ERR_BAD_STATE, "block size unknown: set an initial guess or query the workspace");
+  if (k < 1 || k > m) return fail(LOBPCG_ERR_INVALID_ARG, "need 1 <= k <= block");
+  if (!(tol > 0.0)) return fail(LOBPCG_ERR_INVALID_ARG, "tol must be > 0");
+  int rc = ensure_layout(m);
+  if (rc) return rc;
+  std::memset(&stats, 0, sizeof(stats));
+  stats.precision_switch_iter = -1;
+  have_result = false;
+  if (pkind != LOBPCG_PRECOND_NONE) {
+    rc = ensure_diag();
+    if (rc) return rc;
+  }
+  double* V[2] = {dptr(lay.V[0]), dptr(lay.V[1])};
+  double* AV[2] = {dptr(lay.AV[0]), dptr(lay.AV[1])};
+
+  // ---- initial block (Alg. 1 input) ----
+  if (X0 != nullptr) {
+    HIPCHK(hipMemcpy2DAsync(V[0], sizeof(double) * m, X0, sizeof(double) * ldx0,
+                            sizeof(double) * m, n, hipMemcpyDeviceToDevice, stream));
+  } else {
+    for (int j = 0; j < m; ++j) HIPCHK(fill_splitmix(V[0], m, j, j, n, kDefaultX0Seed, stream));
+  }
+  int iter = 0;
+  PhaseOut po{};
+  if (precision == LOBPCG_PREC_FP32) {
+    rc = ensure_op32();
+    if (rc) return rc;
+    float* V32[2] = {reinterpret_cast<float*>(ws + lay.V32[0]), reinterpret_cast<float*>(ws + lay.V32[1])};
+    float* AV32[2] = {reinterpret_cast<float*>(ws + lay.AV32[0]),
+                      reinterpret_cast<float*>(ws + lay.AV32[1])};
+    HIPCHK(convert_f64_to_f32(V[0], m, V32[0], m, m, n, stream));
+    rc = run_phase<float>(V32[0], V32[1], AV32[0], AV32[1], k, tol, true, iter, po);
+    if (rc) return rc;
+    // switch: promote the fp32 Ritz vectors; phase 2 re-orthonormalises them
+    // in fp64 and recomputes A X explicitly (P is dropped)
+    HIPCHK(convert_f32_to_f64(reinterpret_cast<const float*>(po.X), po.ld, V[0], m, m, n, stream));
+    stats.precision_switch_iter = iter;
+  }
+  rc = run_phase<double>(V[0], V[1], AV[0], AV[1], k, tol, false, iter, po);
+  if (rc) return rc;
   res_k = k;
-  res_X = Xres;
-  res_ld = Xld;
-  res_evals.assign(th_t.begin(), th_t.begin() + m);
-  res_resn.assign(rn_t.begin(), rn_t.begin() + m);
+  res_X = reinterpret_cast<const double*>(po.X);
+  res_ld = po.ld;
   have_result = true;
   stats.iterations = iter;
-  stats.converged = converged ? 1 : 0;
-  stats.m_conv = m_conv;
+  stats.converged = po.converged ? 1 : 0;
   stats.ms_total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  return converged ? LOBPCG_OK : LOBPCG_NOT_CONVERGED;
+  return po.converged ? LOBPCG_OK : LOBPCG_NOT_CONVERGED;
 }
 
 // ===========================================================================
@@ -584,6 +752,7 @@ int lobpcg_set_operator_csr(lobpcg_t h, const int32_t* row_ptr, const int32_t* c
   h->val = val;
   h->nnz = nnz;
   h->diag_ready = false;
+  h->op32_ready = false;
   h->have_result = false;
   return LOBPCG_OK;
 }
@@ -595,6 +764,7 @@ int lobpcg_set_operator_dense(lobpcg_t h, const double* A, int64_t lda) {
   h->A = A;
   h->lda = lda;
   h->diag_ready = false;
+  h->op32_ready = false;
   h->have_result = false;
   return LOBPCG_OK;
 }
@@ -608,6 +778,7 @@ int lobpcg_set_operator_kronsum(lobpcg_t h, int64_t na, const double* A, const d
   h->na = na;
   h->Vpot = V;
   h->diag_ready = false;
+  h->op32_ready = false;
   h->have_result = false;
   return LOBPCG_OK;
 }
@@ -721,7 +892,7 @@ int lobpcg_ortho(lobpcg_t h, double* X, int64_t ldx, int ncols, lobpcg_ortho_inf
   int rc = need_ws(h);
   if (rc) return rc;
   if (info) std::memset(info, 0, sizeof(*info));
-  return h->ortho_run(X, ldx, 0, ncols, info);
+  return h->ortho_run<double>(X, ldx, 0, ncols, info);
 }
 
 int lobpcg_ortho_against(lobpcg_t h, double* X, int64_t ldx, int ncols, const double* Y,
@@ -733,7 +904,7 @@ int lobpcg_ortho_against(lobpcg_t h, double* X, int64_t ldx, int ncols, const do
   int rc = need_ws(h);
   if (rc) return rc;
   if (info) std::memset(info, 0, sizeof(*info));
-  return h->ortho_run(const_cast<double*>(Y), ldx, ycols, ncols, info);
+  return h->ortho_run<double>(const_cast<double*>(Y), ldx, ycols, ncols, info);
 }
 
 int lobpcg_small_eigh(lobpcg_t h, const double* a, int p, double* evals, double* evecs) {

@@ -211,3 +211,54 @@ def test_invalid_calls(P):
         P.lobpcg_workspace_size(s.h, 40)
     with pytest.raises(P.LobpcgError):
         P.lobpcg_set_option(s.h, 99, 1.0)
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: fp32 operator / Grams / blocks, fp64 small dense kernels,
+# then an fp64 phase to the same tolerance (reading of the precision extension)
+
+
+def mixed_solve(P, n, setop, X0, k, tol, max_iter=None):
+    s = P.Solver(n)
+    setop(s)
+    s.set_preconditioner(P.PRECOND_DIAG)
+    s.set_initial_guess(cu(X0))
+    s.set_option(P.OPT_PRECISION, P.PREC_FP32)
+    if max_iter is not None:
+        s.set_option(P.OPT_MAX_ITER, max_iter)
+    res = s.solve(k, tol)
+    res.evecs_np = res.evecs.cpu().numpy()
+    return s, res
+
+
+def test_mixed_dense_dd_full_size(P):
+    n, k = 2000, 4
+    A = synth.dense_dd(n)
+    X0 = synth.start_block(n, k, synth.SEEDS["dense_dd"][1])
+    s, res = mixed_solve(P, n, lambda s: s.set_operator_dense(cu(A)), X0, k, 1e-8)
+    lam_all = np.linalg.eigvalsh(A)
+    ora = O.lobpcg(O.dense_operator(A), X0, k, 1e-8, diag=np.diag(A).copy())
+    check_pairs(res, O.dense_operator(A), lam_all[:k], 1e-8, gaps_of(lam_all, k), ora.evecs, ora.resnorms, normA=abs(lam_all).max())
+    assert res.stats["precision_switch_iter"] >= 1
+    say("mixed dense: switch at", res.stats["precision_switch_iter"], "of", res.stats["iterations"])
+
+
+def test_mixed_csr_banded_scaled(P):
+    n, k = 20000, 8
+    C = synth.csr_banded(n=n, seed=21, band=600, diag_slope=10.0 / n)
+    X0 = synth.start_block(n, k, 22)
+    op = O.csr_operator(C.row_ptr, C.col, C.val, n)
+    s, res = mixed_solve(P, n, lambda s: s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val)), X0, k, 1e-8)
+    ora = O.lobpcg(op, X0, k, 1e-8, diag=C.diag)
+    check_pairs(res, op, ora.evals, 1e-8, normA=11.0)
+    assert res.stats["precision_switch_iter"] >= 1
+
+
+def test_mixed_kronsum(P):
+    na, k = 32, 8
+    A, V = synth.kronsum(na=na, seed=5)
+    X0 = synth.start_block(na * na, k, 4)
+    s, res = mixed_solve(P, na * na, lambda s: s.set_operator_kronsum(cu(A), cu(V)), X0, k, 1e-8)
+    H = np.kron(A, np.eye(na)) + np.kron(np.eye(na), A) + np.diag(V.reshape(-1))
+    lam_all = np.linalg.eigvalsh(H)
+    check_pairs(res, O.kronsum_operator(A, V), lam_all[:k], 1e-8, normA=40.0)
