@@ -391,7 +391,7 @@ def lobpcg(
     k: int,
     tol: float = 1e-8,
     diag: Optional[np.ndarray] = None,
-    precond: str = "diag",
+    precond="diag",
     tau: float = TAU_ORTHO,
     max_iter: int = 1000,
     callback: Optional[Callable[[dict], None]] = None,
@@ -400,19 +400,22 @@ def lobpcg(
 
     X0 is the n x m initial block (m >= k, the block may hold extra vectors,
     Sec. 2).  ``precond`` is "diag" (|Jacobi|, needs ``diag``),
-    "diag_signed" (the paper's signed Jacobi) or "none"."""
+    "diag_signed" (the paper's signed Jacobi), "none", or a callable
+    f(R_act, theta_act, X_act) returning the preconditioned columns."""
     X0 = np.asarray(X0, dtype=np.float64)
     n, m = X0.shape
     if not (1 <= k <= m):
         raise ValueError("need 1 <= k <= block size")
-    if precond.startswith("diag") and diag is None:
+    if isinstance(precond, str) and precond.startswith("diag") and diag is None:
         raise ValueError("the Jacobi preconditioner needs diag(A)")
     st = OrthoStats()
     hist_theta, hist_resid, hist_active = [], [], []
     matvecs = 0
     true_checks = 0
 
-    def tprec(R, theta):
+    def tprec(R, theta, Xa):
+        if callable(precond):
+            return np.asarray(precond(R, theta, Xa), dtype=np.float64)
         if precond == "diag":
             return precondition_diag(R, diag, theta)
         if precond == "diag_signed":
@@ -461,7 +464,7 @@ def lobpcg(
         it += 1
         act = np.arange(m_conv, m)
         # Alg. 1: preconditioned residuals, orthogonalised against (X, P)
-        Wt = tprec(R[:, act], theta[act])
+        Wt = tprec(R[:, act], theta[act], X[:, act])
         Y = X if P is None else np.hstack([X, P])
         W = ortho_against(Wt, Y, tau, st)
         AW = op(W)

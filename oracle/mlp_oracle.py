@@ -1,25 +1,41 @@
-"""CPU fp64 oracle for the learned preconditioner (test infrastructure only).
+"""CPU fp64 oracle for the learned preconditioner (test infrastructure only:
+imported by tests, the smoke check and the CPU baseline, never by the GPU
+library).
 
-The learned preconditioner is an extension beside the paper's method (the
-paper's own study of better preconditioners is Sec. 4.4; its default is the
-Jacobi preconditioner of Sec. 2).  Reading used here:
+The learned preconditioner is an extension beside the paper's method; the
+paper's default preconditioner is the Jacobi one of Sec. 2 and its study of
+better preconditioners is Sec. 4.4.  Reading used here:
 
-  * a per-entry MLP 4 -> 128 -> 128 -> 1 with SiLU activations maps, for an
-    active residual column r (Ritz value theta) and the operator diagonal d,
-    the features
-        f1 = r_i / rms(r)
-        f2 = (d_i - theta) / s
-        f3 = theta / s
-        f4 = r_i / (rms(r) (|d_i - theta| / s + 1e-3))
-    (s = mean |d|) to a correction c_i; the preconditioned column is c;
-  * training targets are the Jacobi-Davidson corrections t solving
-        (I - x x^T)(A - theta I)(I - x x^T) t = -r,  t orthogonal to x
-    (MINRES, relative residual 1e-6), scaled to unit RMS per column;
-  * loss: mean squared error over the sampled entries; Adam.
+Preconditioned column.  For an active residual column r (Ritz value theta)
+of an operator with diagonal d and off-diagonal absolute row sums
+rho_i = sum_{l != i} |a_il|, with s = mean_i |d_i|,
 
-Functions: ``features``, ``forward``, ``backward`` (analytic gradients),
-``loss``, ``adam_step``, ``jd_targets`` (scipy MINRES on the projected
-operator).  Everything in float64.
+    w_i = r_i / sqrt((d_i - theta)^2 + c_i^2),     c_i = s * softplus(y_i),
+
+where y_i is the output of a per-entry MLP 3 -> 128 -> 128 -> 1 (SiLU) on
+the features
+    phi_1 = log(|d_i - theta| / s + 1e-6),
+    phi_2 = theta / s,
+    phi_3 = log(rho_i / s + 1e-6).
+c -> 0 gives the absolute Jacobi preconditioner; the net learns how much to
+regularise it where d_i is close to theta relative to the coupling rho_i.
+The denominator is floored at delta = 1e-8 max(1, |theta|), the Jacobi guard.
+
+Training objective.  For a column j with Ritz vector x_j in the orthonormal
+block X, let u = (I - X X^T) w.  The Rayleigh-Ritz step on span{x_j, u}
+lowers the Ritz value by
+    Delta(w) = sqrt(h^2 + b^2) - h,   b = r^T u / |u|,  h = (u^T A u / |u|^2 - theta) / 2
+(the smaller eigenvalue of the 2 x 2 projected matrix [[theta, b], [b, 2h + theta]]).
+The loss is the mean over columns of log(Delta(t) / Delta(w)), where t is
+the near-exact Jacobi-Davidson correction of the same column (``jd_targets``):
+it is the log of the factor by which the learned step falls short of the
+near-exact solve's step, and its gradient does not depend on t.
+
+Functions: ``features``, ``forward``, ``backward_dy`` (generic MLP backward
+for an output gradient), ``precondition``, ``decrease`` (Delta),
+``objective`` (loss and analytic gradient with respect to the flat
+parameters), ``adam_step``, ``init_params``, ``jd_targets``.  Everything in
+float64.
 """
 from __future__ import annotations
 
@@ -28,8 +44,9 @@ import dataclasses
 import numpy as np
 
 HIDDEN = 128
-NFEAT = 4
-FEAT_EPS = 1e-3
+NFEAT = 3
+FEAT_FLOOR = 1e-6
+GUARD = 1e-8  # Jacobi guard, relative to max(1, |theta|)
 
 
 @dataclasses.dataclass
@@ -65,21 +82,36 @@ def n_params(H: int = HIDDEN, F: int = NFEAT) -> int:
     return H * F + H + H * H + H + H + 1
 
 
+def sigmoid(z):
+    return 0.5 * (1.0 + np.tanh(0.5 * z))
+
+
 def silu(z):
-    return z / (1.0 + np.exp(-z))
+    return z * sigmoid(z)
 
 
 def dsilu(z):
-    s = 1.0 / (1.0 + np.exp(-z))
+    s = sigmoid(z)
     return s * (1.0 + z * (1.0 - s))
 
 
-def features(r: np.ndarray, d: np.ndarray, theta: float, s: float) -> np.ndarray:
-    """Per-entry features of one residual column (n x 4)."""
-    rms = np.sqrt(np.mean(r * r))
-    rn = r / rms
-    dm = (d - theta) / s
-    return np.column_stack([rn, dm, np.full_like(r, theta / s), rn / (np.abs(dm) + FEAT_EPS)])
+def softplus(y):
+    return np.logaddexp(0.0, y)
+
+
+def scale_of(d: np.ndarray) -> float:
+    return float(np.mean(np.abs(d)))
+
+
+def features(d: np.ndarray, theta: float, rho: np.ndarray, s: float) -> np.ndarray:
+    """Per-entry features of one column (n x 3)."""
+    return np.column_stack(
+        [
+            np.log(np.abs(d - theta) / s + FEAT_FLOOR),
+            np.full(d.shape, theta / s),
+            np.log(rho / s + FEAT_FLOOR),
+        ]
+    )
 
 
 def forward(p: Params, X: np.ndarray):
@@ -92,26 +124,73 @@ def forward(p: Params, X: np.ndarray):
     return y, (X, z1, h1, z2, h2)
 
 
-def loss(y: np.ndarray, t: np.ndarray) -> float:
-    return float(np.mean((y - t) ** 2))
-
-
-def backward(p: Params, cache, y: np.ndarray, t: np.ndarray) -> Params:
-    """Analytic gradient of the mean squared error."""
+def backward_dy(p: Params, cache, dy: np.ndarray) -> Params:
+    """Gradient of sum_i dy_i * y_i with respect to the parameters."""
     X, z1, h1, z2, h2 = cache
-    B = X.shape[0]
-    dy = (2.0 / B) * (y - t)  # (B,)
-    dW3 = dy[None, :] @ h2  # (1, H)
+    dW3 = dy[None, :] @ h2
     db3 = np.array([dy.sum()])
-    dh2 = dy[:, None] * p.W3  # (B, H)
-    dz2 = dh2 * dsilu(z2)
+    dz2 = (dy[:, None] * p.W3) * dsilu(z2)
     dW2 = dz2.T @ h1
     db2 = dz2.sum(0)
-    dh1 = dz2 @ p.W2
-    dz1 = dh1 * dsilu(z1)
+    dz1 = (dz2 @ p.W2) * dsilu(z1)
     dW1 = dz1.T @ X
     db1 = dz1.sum(0)
     return Params(dW1, db1, dW2, db2, dW3, db3)
+
+
+def precondition(p: Params, r: np.ndarray, d: np.ndarray, theta: float, rho: np.ndarray, s: float):
+    """The learned preconditioned column w (and the pieces the gradient needs)."""
+    F = features(d, theta, rho, s)
+    y, cache = forward(p, F)
+    c = s * softplus(y)
+    dm = d - theta
+    delta = GUARD * max(1.0, abs(theta))
+    q = np.maximum(dm * dm + c * c, delta * delta)
+    w = r / np.sqrt(q)
+    return w, dict(y=y, c=c, q=q, floored=(dm * dm + c * c) < delta * delta, cache=cache)
+
+
+def decrease(A, X: np.ndarray, x: np.ndarray, r: np.ndarray, theta: float, w: np.ndarray) -> float:
+    """Delta(w): how far the Rayleigh-Ritz step on span{x, (I - X X^T) w}
+    lowers theta."""
+    u = w - X @ (X.T @ w)
+    nu2 = float(u @ u)
+    b = float(r @ u) / np.sqrt(nu2)
+    h = (float(u @ (A @ u)) / nu2 - theta) / 2.0
+    return float(np.sqrt(h * h + b * b) - h)
+
+
+def objective(p: Params, A, X: np.ndarray, R: np.ndarray, theta: np.ndarray, cols, d, rho, s, ref=None):
+    """Mean over the columns `cols` of log(ref_j / Delta_j(w_j)) and its
+    gradient with respect to the flat parameters (ref_j = 1 when None)."""
+    g = np.zeros(n_params(p.W2.shape[0], p.W1.shape[1]))
+    L = 0.0
+    nc = len(cols)
+    for k, j in enumerate(cols):
+        r = R[:, j]
+        th = float(theta[j])
+        w, aux = precondition(p, r, d, th, rho, s)
+        u = w - X @ (X.T @ w)
+        Au = A @ u
+        nu2 = float(u @ u)
+        nu = np.sqrt(nu2)
+        b = float(r @ u) / nu
+        cq = float(u @ Au) / nu2
+        h = (cq - th) / 2.0
+        S = np.sqrt(h * h + b * b)
+        D = S - h
+        L += (np.log(1.0 if ref is None else ref[k]) - np.log(D)) / nc
+        dLdD = -1.0 / (D * nc)
+        dDb = b / S
+        dDc = (h / S - 1.0) / 2.0
+        gu = dLdD * (dDb * (r / nu - b * u / nu2) + dDc * 2.0 * (Au - cq * u) / nu2)
+        gw = gu - X @ (X.T @ gu)
+        # w = r q^-1/2, q = dm^2 + c^2 (not floored), c = s softplus(y)
+        dq = gw * r * (-0.5) * aux["q"] ** -1.5
+        dq = np.where(aux["floored"], 0.0, dq)
+        dy = dq * 2.0 * aux["c"] * s * sigmoid(aux["y"])
+        g += backward_dy(p, aux["cache"], dy).flat()
+    return L, g
 
 
 def adam_step(theta: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
@@ -123,21 +202,21 @@ def adam_step(theta: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, t:
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def init_params(seed: int, H: int = HIDDEN, F: int = NFEAT) -> Params:
+def init_params(seed: int, H: int = HIDDEN, F: int = NFEAT, out_bias: float = -3.0) -> Params:
     g = np.random.Generator(np.random.PCG64(seed))
     return Params(
         g.normal(0, 1 / np.sqrt(F), (H, F)),
         np.zeros(H),
         g.normal(0, 1 / np.sqrt(H), (H, H)),
         np.zeros(H),
-        g.normal(0, 1 / np.sqrt(H), (1, H)),
-        np.zeros(1),
+        0.1 * g.normal(0, 1 / np.sqrt(H), (1, H)),
+        np.full(1, out_bias),
     )
 
 
 def jd_targets(A, X: np.ndarray, theta: np.ndarray, R: np.ndarray, rtol: float = 1e-6, maxiter: int = 500) -> np.ndarray:
     """Jacobi-Davidson corrections t_j: (I - x x^T)(A - theta_j I)(I - x x^T) t = -r_j,
-    t orthogonal to x_j, by MINRES; each column scaled to unit RMS."""
+    t orthogonal to x_j, by MINRES from a zero start."""
     import scipy.sparse.linalg as spla
 
     n = X.shape[0]
@@ -154,6 +233,5 @@ def jd_targets(A, X: np.ndarray, theta: np.ndarray, R: np.ndarray, rtol: float =
         op = spla.LinearOperator((n, n), matvec=mv, dtype=np.float64)
         b = -(R[:, j] - x * (x @ R[:, j]))
         t, _ = spla.minres(op, b, rtol=rtol, maxiter=maxiter)
-        t = t - x * (x @ t)
-        out[:, j] = t / np.sqrt(np.mean(t * t))
+        out[:, j] = t - x * (x @ t)
     return out
