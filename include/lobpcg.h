@@ -54,6 +54,11 @@ typedef struct lobpcg_ctx* lobpcg_t;
 #define LOBPCG_PRECOND_NONE 0        /* T = I */
 #define LOBPCG_PRECOND_DIAG 1        /* T_j = |diag(A) - theta_j I|^-1 (default) */
 #define LOBPCG_PRECOND_DIAG_SIGNED 2 /* T_j = (diag(A) - theta_j I)^-1, Sec. 2's example */
+#define LOBPCG_PRECOND_LEARNED 3     /* learned regularised Jacobi step (see
+                                        lobpcg_set_learned_weights); Jacobi fallback */
+
+/* Parameters of the learned preconditioner's MLP (3 -> 128 -> 128 -> 1). */
+#define LOBPCG_LEARNED_NPARAMS 17153
 
 /* ---- precision modes --------------------------------------------------- */
 #define LOBPCG_PREC_FP64 0 /* every step in fp64 */
@@ -89,6 +94,9 @@ typedef struct lobpcg_stats {
   double ms_rr;                /* RR Gram + small eigensolve + rotation */
   double ms_ortho;             /* ortho(W~; [X P]) */
   double ms_sync;              /* host waits for per-iteration read-backs */
+  int32_t learned_fallbacks;   /* learned steps that did not lower the residual
+                                  (the column then takes 3 Jacobi steps) */
+  int32_t learned_nonfinite;   /* learned applications with a non-finite net output */
 } lobpcg_stats;
 
 /* ---- ortho report for the step entry points ---------------------------- */
@@ -142,6 +150,22 @@ int lobpcg_set_operator_kronsum(lobpcg_t h, int64_t na, const double* A, const d
  * entry x with |x - theta_j| < 1e-8 max(1, |theta_j|) is clamped to that
  * bound (sign kept, 0 taken as +). */
 int lobpcg_set_preconditioner(lobpcg_t h, int kind, const double* diag);
+
+/* Weights of the learned preconditioner (an extension beside Sec. 2's
+ * Jacobi T; Sec. 4.4 studies other preconditioners).  w: host, the
+ * LOBPCG_LEARNED_NPARAMS fp32 parameters in the order W1 (128 x 3 row-major),
+ * b1 (128), W2 (128 x 128), b2 (128), W3 (128), b3 (1); copied to a
+ * library-owned device buffer.  With kind LOBPCG_PRECOND_LEARNED the active
+ * column j of W~ becomes
+ *   w_i = r_i / sqrt((d_i - theta_j)^2 + c_i^2),  c_i = s softplus(y_i),
+ * y_i = MLP(log(|d_i - theta_j| / s + 1e-6), theta_j / s,
+ *           log(rho_i / s + 1e-6)),
+ * d = diag(A), rho_i = sum_{l != i} |a_il|, s = mean |d|; the denominator is
+ * floored at the Jacobi guard.  A column whose residual did not decrease
+ * over the step that used its learned column takes the Jacobi step for the
+ * next 3 iterations; an entry with a non-finite net output takes the Jacobi
+ * step.  INVALID_ARG unless count == LOBPCG_LEARNED_NPARAMS. */
+int lobpcg_set_learned_weights(lobpcg_t h, const float* w, int64_t count);
 
 /* Initial block X0 (Alg. 1 input): device, row-major n x block with leading
  * dimension ld.  Copied when lobpcg_solve starts.  Without it the solver
@@ -234,6 +258,65 @@ int lobpcg_small_cholesky(lobpcg_t h, const double* M, int p, double* L, int* sh
 int lobpcg_rotate(lobpcg_t h, const double* V, const double* AV, int64_t ldv, int p,
                   const double* U, int m, int q, const double* theta, int a0, double* Vout,
                   double* AVout, int64_t ldo, double* resnorm2);
+
+/* The learned preconditioner's transform (see lobpcg_set_learned_weights) on
+ * caller buffers: R (device n x nact, ldr) is replaced in place by the
+ * learned columns for the Ritz values theta (device, nact); mask (device,
+ * nact ints, may be NULL): nonzero selects the Jacobi step for that column.
+ * Needs weights and the operator.  1 <= nact <= 64.  Asynchronous. */
+int lobpcg_learned_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const double* theta,
+                         const int* mask);
+
+/* ======================================================================== */
+/* Training the learned preconditioner                                        */
+/* ======================================================================== */
+/* A learner holds fp32 weights with Adam state and a set of snapshots.  A
+ * snapshot is an orthonormal Ritz block X of some operator (for example the
+ * eigenvectors of a solve stopped early with LOBPCG_OPT_MAX_ITER); the
+ * learner forms R = A X - X diag(theta) and, for each column, the near-exact
+ * Jacobi-Davidson correction t_j solving
+ *   (I - x_j x_j^T)(A - theta_j I)(I - x_j x_j^T) t = -r_j,  t orthogonal to x_j
+ * by MINRES.  The training loss of a column is log(Delta(t_j) / Delta(w_j)),
+ * Delta(v) being the decrease of theta_j achieved by the Rayleigh-Ritz step on
+ * span{x_j, (I - X X^T) v}, and w_j the learned column; the loss of a step is
+ * its mean over the step's columns.  Device buffers are library-owned. */
+typedef struct lobpcg_learner* lobpcg_learner_t;
+
+/* Create a learner on `device` with weights drawn from `seed` (layer l
+ * weights N(0, 1/fan_in) from SplitMix64 + Box-Muller, output layer scaled by
+ * 0.1, biases 0 except b3 = -3). */
+int lobpcg_learner_create(int device, uint64_t seed, lobpcg_learner_t* out);
+int lobpcg_learner_destroy(lobpcg_learner_t L);
+int lobpcg_learner_set_stream(lobpcg_learner_t L, void* hip_stream);
+/* Host fp32 weights in, out (LOBPCG_LEARNED_NPARAMS); set resets Adam. */
+int lobpcg_learner_set_weights(lobpcg_learner_t L, const float* w, int64_t count);
+int lobpcg_learner_get_weights(lobpcg_learner_t L, float* w, int64_t count);
+/* Add a snapshot: X device n x m (ldx), orthonormal columns, of the operator
+ * set in solver handle h (which must stay alive and unchanged while the
+ * learner uses it and must have a workspace for block >= m); m <= 32.
+ * MINRES runs at most minres_maxiter iterations or to relative residual
+ * minres_rtol.  *index receives the snapshot number.  Blocking. */
+int lobpcg_learner_add_snapshot(lobpcg_learner_t L, lobpcg_t h, const double* X, int64_t ldx,
+                                int m, int minres_maxiter, double minres_rtol, int* index);
+/* Per-column data of snapshot `snap` (host arrays of m doubles, any may be
+ * NULL): Ritz values, residual norms, Delta(t_j) of the MINRES corrections and
+ * MINRES relative residual estimates. */
+int lobpcg_learner_snapshot_info(lobpcg_learner_t L, int snap, double* theta, double* resnorm,
+                                 double* ref_decrease, double* minres_relres);
+/* Loss of the current weights on columns cols[0..ncols) (host) of snapshot
+ * `snap`, and optionally its gradient (host, LOBPCG_LEARNED_NPARAMS doubles)
+ * and the learned and Jacobi decreases per column (host, ncols each; may be
+ * NULL).  Blocking. */
+int lobpcg_learner_objective(lobpcg_learner_t L, int snap, const int* cols, int ncols,
+                             double* loss, double* grad, double* learned_decrease,
+                             double* jacobi_decrease);
+/* `steps` Adam steps (learning rate lr), each on a snapshot and
+ * cols_per_step distinct columns drawn with SplitMix64 from `seed`.
+ * loss_first / loss_last (host, may be NULL): mean loss of the first and
+ * last 10% of the steps.  Blocking. */
+int lobpcg_learner_train(lobpcg_learner_t L, int steps, int cols_per_step, double lr,
+                         uint64_t seed, double* loss_first, double* loss_last);
+const char* lobpcg_learner_last_error(lobpcg_learner_t L);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,9 @@ Training objective.  For a column j with Ritz vector x_j in the orthonormal
 block X, let u = (I - X X^T) w.  The Rayleigh-Ritz step on span{x_j, u}
 lowers the Ritz value by
     Delta(w) = sqrt(h^2 + b^2) - h,   b = r^T u / |u|,  h = (u^T A u / |u|^2 - theta) / 2
-(the smaller eigenvalue of the 2 x 2 projected matrix [[theta, b], [b, 2h + theta]]).
+(theta minus the smaller eigenvalue of the 2 x 2 projected matrix
+[[theta, b], [b, 2h + theta]]), evaluated as b^2 / (S + h) with
+S = sqrt(h^2 + b^2) when h > 0, where the difference form cancels.
 The loss is the mean over columns of log(Delta(t) / Delta(w)), where t is
 the near-exact Jacobi-Davidson correction of the same column (``jd_targets``):
 it is the log of the factor by which the learned step falls short of the
@@ -150,6 +152,13 @@ def precondition(p: Params, r: np.ndarray, d: np.ndarray, theta: float, rho: np.
     return w, dict(y=y, c=c, q=q, floored=(dm * dm + c * c) < delta * delta, cache=cache)
 
 
+def _delta(h: float, b: float):
+    """(Delta, S) for Delta = sqrt(h^2 + b^2) - h without cancellation."""
+    S = float(np.hypot(h, b))
+    D = b * b / (S + h) if h > 0.0 else S - h
+    return D, S
+
+
 def decrease(A, X: np.ndarray, x: np.ndarray, r: np.ndarray, theta: float, w: np.ndarray) -> float:
     """Delta(w): how far the Rayleigh-Ritz step on span{x, (I - X X^T) w}
     lowers theta."""
@@ -157,7 +166,7 @@ def decrease(A, X: np.ndarray, x: np.ndarray, r: np.ndarray, theta: float, w: np
     nu2 = float(u @ u)
     b = float(r @ u) / np.sqrt(nu2)
     h = (float(u @ (A @ u)) / nu2 - theta) / 2.0
-    return float(np.sqrt(h * h + b * b) - h)
+    return _delta(h, b)[0]
 
 
 def objective(p: Params, A, X: np.ndarray, R: np.ndarray, theta: np.ndarray, cols, d, rho, s, ref=None):
@@ -177,13 +186,13 @@ def objective(p: Params, A, X: np.ndarray, R: np.ndarray, theta: np.ndarray, col
         b = float(r @ u) / nu
         cq = float(u @ Au) / nu2
         h = (cq - th) / 2.0
-        S = np.sqrt(h * h + b * b)
-        D = S - h
+        D, S = _delta(h, b)
         L += (np.log(1.0 if ref is None else ref[k]) - np.log(D)) / nc
-        dLdD = -1.0 / (D * nc)
-        dDb = b / S
-        dDc = (h / S - 1.0) / 2.0
-        gu = dLdD * (dDb * (r / nu - b * u / nu2) + dDc * 2.0 * (Au - cq * u) / nu2)
+        # dD/db = b / S, dD/dcq = (h / S - 1) / 2 = -D / (2 S); the products
+        # with dL/dD = -1 / (D nc) are formed without dividing by a tiny D
+        cb = -b / (S * D * nc)
+        cc = 1.0 / (2.0 * S * nc)
+        gu = cb * (r / nu - b * u / nu2) + cc * 2.0 * (Au - cq * u) / nu2
         gw = gu - X @ (X.T @ gu)
         # w = r q^-1/2, q = dm^2 + c^2 (not floored), c = s softplus(y)
         dq = gw * r * (-0.5) * aux["q"] ** -1.5

@@ -41,6 +41,8 @@ ERR_UNSUPPORTED = -7
 PRECOND_NONE = 0
 PRECOND_DIAG = 1
 PRECOND_DIAG_SIGNED = 2
+PRECOND_LEARNED = 3
+LEARNED_NPARAMS = 17153
 
 PREC_FP64 = 0
 PREC_FP32 = 1
@@ -76,6 +78,8 @@ class lobpcg_stats(ctypes.Structure):
         ("ms_rr", _dbl),
         ("ms_ortho", _dbl),
         ("ms_sync", _dbl),
+        ("learned_fallbacks", _i32),
+        ("learned_nonfinite", _i32),
     ]
 
     def as_dict(self) -> dict:
@@ -125,6 +129,26 @@ _c = {
         "lobpcg_rotate",
         [_vp, _vp, _vp, _i64, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _i64, _vp],
     ),
+    "set_learned_weights": _sig("lobpcg_set_learned_weights", [_vp, _vp, _i64]),
+    "learned_apply": _sig("lobpcg_learned_apply", [_vp, _vp, _i64, ctypes.c_int, _vp, _vp]),
+    "learner_create": _sig("lobpcg_learner_create", [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    "learner_destroy": _sig("lobpcg_learner_destroy", [_vp]),
+    "learner_set_stream": _sig("lobpcg_learner_set_stream", [_vp, _vp]),
+    "learner_set_weights": _sig("lobpcg_learner_set_weights", [_vp, _vp, _i64]),
+    "learner_get_weights": _sig("lobpcg_learner_get_weights", [_vp, _vp, _i64]),
+    "learner_add_snapshot": _sig(
+        "lobpcg_learner_add_snapshot",
+        [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, _dbl, ctypes.POINTER(ctypes.c_int)],
+    ),
+    "learner_snapshot_info": _sig("lobpcg_learner_snapshot_info", [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "learner_objective": _sig(
+        "lobpcg_learner_objective", [_vp, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]
+    ),
+    "learner_train": _sig(
+        "lobpcg_learner_train",
+        [_vp, ctypes.c_int, ctypes.c_int, _dbl, ctypes.c_uint64, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)],
+    ),
+    "learner_last_error": _sig("lobpcg_learner_last_error", [_vp], ctypes.c_char_p),
 }
 
 EXPORTED = [
@@ -134,7 +158,11 @@ EXPORTED = [
     "lobpcg_set_initial_guess", "lobpcg_solve", "lobpcg_get_eigenpairs", "lobpcg_get_stats",
     "lobpcg_status_string", "lobpcg_last_error", "lobpcg_apply_operator", "lobpcg_gram",
     "lobpcg_ortho", "lobpcg_ortho_against", "lobpcg_small_eigh", "lobpcg_small_cholesky",
-    "lobpcg_rotate",
+    "lobpcg_rotate", "lobpcg_set_learned_weights", "lobpcg_learned_apply",
+    "lobpcg_learner_create", "lobpcg_learner_destroy", "lobpcg_learner_set_stream",
+    "lobpcg_learner_set_weights", "lobpcg_learner_get_weights", "lobpcg_learner_add_snapshot",
+    "lobpcg_learner_snapshot_info", "lobpcg_learner_objective", "lobpcg_learner_train",
+    "lobpcg_learner_last_error",
 ]
 
 
@@ -379,6 +407,108 @@ def lobpcg_rotate(h, V, AV, p, U, m, q, theta, a0, Vout, AVout, resnorm2) -> Non
     )
 
 
+def _host_f32(w, name="weights"):
+    a = np.ascontiguousarray(np.asarray(w, dtype=np.float32))
+    if a.ndim != 1 or a.size != LEARNED_NPARAMS:
+        raise ValueError(f"{name}: need {LEARNED_NPARAMS} float32 values")
+    return a
+
+
+def lobpcg_set_learned_weights(h, w) -> None:
+    a = _host_f32(w)
+    _check(h, _c["set_learned_weights"](h, a.ctypes.data_as(_vp), a.size))
+
+
+def lobpcg_learned_apply(h, R, theta, mask=None) -> None:
+    torch = _torch()
+    nact = R.shape[1]
+    if theta.numel() != nact:
+        raise ValueError("theta: one value per column")
+    mp = None
+    if mask is not None:
+        if mask.dtype != torch.int32 or mask.numel() != nact or not mask.is_cuda:
+            raise ValueError("mask: int32 cuda tensor, one value per column")
+        mp = ctypes.c_void_p(mask.data_ptr())
+    _check(h, _c["learned_apply"](h, _dev_ptr(R, torch.float64, "R"), _ld(R, "R"), nact, _dev_ptr(theta, torch.float64, "theta"), mp))
+
+
+def lobpcg_learner_last_error(L) -> str:
+    return (_c["learner_last_error"](L) or b"").decode()
+
+
+def _lcheck(L, rc: int) -> int:
+    if rc != OK:
+        raise LobpcgError(rc, f"{lobpcg_status_string(rc)}: {lobpcg_learner_last_error(L)}")
+    return rc
+
+
+def lobpcg_learner_create(device: int = 0, seed: int = 1):
+    out = _vp()
+    rc = _c["learner_create"](device, ctypes.c_uint64(seed), ctypes.byref(out))
+    if rc != OK:
+        raise LobpcgError(rc, f"lobpcg_learner_create: {lobpcg_status_string(rc)}")
+    return out
+
+
+def lobpcg_learner_destroy(L) -> None:
+    _c["learner_destroy"](L)
+
+
+def lobpcg_learner_set_stream(L, stream_ptr=None) -> None:
+    _lcheck(L, _c["learner_set_stream"](L, stream_ptr if stream_ptr is not None else _stream_ptr()))
+
+
+def lobpcg_learner_set_weights(L, w) -> None:
+    a = _host_f32(w)
+    _lcheck(L, _c["learner_set_weights"](L, a.ctypes.data_as(_vp), a.size))
+
+
+def lobpcg_learner_get_weights(L) -> np.ndarray:
+    a = np.empty(LEARNED_NPARAMS, dtype=np.float32)
+    _lcheck(L, _c["learner_get_weights"](L, a.ctypes.data_as(_vp), a.size))
+    return a
+
+
+def lobpcg_learner_add_snapshot(L, h, X, minres_maxiter: int = 300, minres_rtol: float = 1e-6) -> int:
+    torch = _torch()
+    idx = ctypes.c_int(-1)
+    _lcheck(
+        L,
+        _c["learner_add_snapshot"](
+            L, h, _dev_ptr(X, torch.float64, "X"), _ld(X, "X"), X.shape[1], int(minres_maxiter), float(minres_rtol), ctypes.byref(idx)
+        ),
+    )
+    return idx.value
+
+
+def lobpcg_learner_snapshot_info(L, snap: int, m: int) -> dict:
+    out = {k: np.empty(m) for k in ("theta", "resnorm", "ref_decrease", "minres_relres")}
+    _lcheck(
+        L,
+        _c["learner_snapshot_info"](
+            L, snap, *(out[k].ctypes.data_as(_vp) for k in ("theta", "resnorm", "ref_decrease", "minres_relres"))
+        ),
+    )
+    return out
+
+
+def lobpcg_learner_objective(L, snap: int, cols, want_grad: bool = False, want_decreases: bool = False):
+    c = np.ascontiguousarray(np.asarray(cols, dtype=np.int32))
+    loss = ctypes.c_double()
+    g = np.empty(LEARNED_NPARAMS) if want_grad else None
+    dl = np.empty(c.size) if want_decreases else None
+    dj = np.empty(c.size) if want_decreases else None
+    ptr = lambda a: a.ctypes.data_as(_vp) if a is not None else None
+    _lcheck(L, _c["learner_objective"](L, snap, c.ctypes.data_as(_vp), c.size, ctypes.byref(loss), ptr(g), ptr(dl), ptr(dj)))
+    return dict(loss=loss.value, grad=g, learned_decrease=dl, jacobi_decrease=dj)
+
+
+def lobpcg_learner_train(L, steps: int, cols_per_step: int, lr: float, seed: int = 1):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _lcheck(L, _c["learner_train"](L, steps, cols_per_step, lr, ctypes.c_uint64(seed), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
 # ---- convenience object ----------------------------------------------------
 
 
@@ -432,6 +562,9 @@ class Solver:
     def set_preconditioner(self, kind=PRECOND_DIAG, diag=None):
         self._keep["diag"] = diag
         lobpcg_set_preconditioner(self.h, kind, diag)
+
+    def set_learned_weights(self, w):
+        lobpcg_set_learned_weights(self.h, w)
 
     def set_option(self, key, value):
         lobpcg_set_option(self.h, key, value)

@@ -12,7 +12,16 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblobpcg.so")
-SOURCES = ["k_blas.hip", "k_op.hip", "k_kron.hip", "k_small.hip", "solver.cpp"]
+SOURCES = [
+    "k_blas.hip",
+    "k_op.hip",
+    "k_kron.hip",
+    "k_small.hip",
+    "k_mlp.hip",
+    "k_learn.hip",
+    "solver.cpp",
+    "learner.cpp",
+]
 ARCH = "gfx950"
 
 

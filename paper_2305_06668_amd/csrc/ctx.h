@@ -1,0 +1,128 @@
+// Solver handle shared by the host driver (solver.cpp) and the training
+// driver of the learned preconditioner (learner.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lobpcg.h"
+#include "internal.h"
+
+namespace lobpcg {
+
+constexpr size_t kAlign = 256;
+constexpr int kOrthoRounds = 6;     // controller rounds launched before the first check
+constexpr int kOrthoHardCap = 64;   // rounds before giving up
+constexpr size_t kPinnedBytes = 1 << 16;
+constexpr size_t kGPartOffset = 1 << 16;  // doubles: rotation's overlap partials inside `part`
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+enum OpKind { kOpNone = 0, kOpCsr = 1, kOpDense = 2, kOpKron = 3 };
+
+struct Layout {
+  size_t V[2], AV[2], diag, rho, part, small, total;
+  size_t V32[2], AV32[2], op32;  // mixed precision only (0 otherwise)
+  // inside small (byte offsets)
+  size_t a, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye, lmask, lflags, lscale;
+};
+
+}  // namespace lobpcg
+
+using lobpcg::Layout;
+
+struct lobpcg_ctx {
+  int64_t n = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // options
+  double tau = 1e-14;
+  int max_iter = 1000;
+  int precision = LOBPCG_PREC_FP64;
+  int ortho_max_inner = 6;
+  int ortho_max_outer = 4;
+  int trace = 0;
+  // operator
+  int op = lobpcg::kOpNone;
+  const int32_t* rp = nullptr;
+  const int32_t* ci = nullptr;
+  const double* val = nullptr;
+  int64_t nnz = 0;
+  const double* A = nullptr;
+  int64_t lda = 0;
+  int64_t na = 0;
+  const double* Vpot = nullptr;
+  // preconditioner
+  int pkind = LOBPCG_PRECOND_DIAG;
+  const double* user_diag = nullptr;
+  bool diag_ready = false;
+  float* lweights = nullptr;     // learned preconditioner weights (library-owned device copy)
+  bool lfeat_ready = false;      // off-diagonal row sums and mean |diag| computed
+  double lscale_host = 0.0;
+  // initial guess
+  const double* X0 = nullptr;
+  int64_t ldx0 = 0;
+  int block = 0;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout lay{};
+  int lay_block = -1;
+  // pinned host buffer
+  char* pinned = nullptr;
+  // results
+  bool have_result = false;
+  int res_k = 0;
+  const double* res_X = nullptr;
+  int64_t res_ld = 0;
+  std::vector<double> res_evals, res_resn;
+  lobpcg_stats stats{};
+  std::string err;
+  // fp32 operator copies (mixed precision) and the operator norm bound
+  bool op32_ready = false;
+  double norm_bound = -1.0;
+
+  // ---- helpers ----
+  double* dptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
+  template <typename T> T* small_ptr(size_t off) const {
+    return reinterpret_cast<T*>(ws + lay.small + off);
+  }
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* where) {
+    err = std::string(where) + ": " + hipGetErrorString(e);
+    return LOBPCG_ERR_DEVICE;
+  }
+  Layout plan(int m) const;
+  size_t op32_elems() const;
+  int ensure_layout(int m);
+  int apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy);
+  int apply_op(const float* W, int64_t ldw, int nc, float* Y, int64_t ldy);
+  template <typename T>
+  int ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info, bool have_g0 = false,
+                bool fold = false, double tau_run = -1.0);
+  int ensure_diag();
+  int ensure_learned_features();
+  int ensure_op32();
+  int true_residuals(const double* X, int64_t ldx, int m, double* scratch, const double* theta_rr,
+                     std::vector<double>& th, std::vector<double>& rn);
+  struct PhaseOut {
+    const void* X;  // final Ritz vectors of the phase (first m columns)
+    int64_t ld;
+    bool converged;
+  };
+  template <typename T>
+  int run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool low, int& iter,
+                PhaseOut& out);
+  int solve(int k, double tol);
+};
+
+#define HIPCHK(expr)                                  \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)

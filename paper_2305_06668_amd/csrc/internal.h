@@ -21,7 +21,14 @@ constexpr double kPrecondGuard = 1e-8;   // |d - theta| floor, relative to max(1
 constexpr uint64_t kZeroColumnSeed = 0x2305066680000000ull;
 constexpr uint64_t kDefaultX0Seed = 0x2305066600000001ull;
 
-enum PrecondKind { kPrecNone = 0, kPrecDiag = 1, kPrecDiagSigned = 2 };
+enum PrecondKind { kPrecNone = 0, kPrecDiag = 1, kPrecDiagSigned = 2, kPrecLearned = 3 };
+
+// learned preconditioner: per-entry MLP 3 -> 128 -> 128 -> 1
+constexpr int kMlpHidden = 128;
+constexpr int kMlpFeat = 3;
+constexpr int kMlpParams = kMlpHidden * kMlpFeat + kMlpHidden + kMlpHidden * kMlpHidden +
+                           kMlpHidden + kMlpHidden + 1;
+constexpr int kMlpBlocks = 256;  // persistent grid of the MLP kernels
 
 // Device-side state of one ortho(W; Y) call (Alg. 2 nested in Alg. 3).
 // Written only by the one-workgroup controller kernel; the streaming kernels
@@ -160,5 +167,35 @@ hipError_t small_cholesky(const double* M, int p, double* L, int* info, hipStrea
 hipError_t ortho_ctl(const double* G, OrthoState* st, double* coef, hipStream_t s);
 hipError_t ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner, int max_outer,
                       int fold_scale, hipStream_t s);
+
+// ---- learned preconditioner (k_mlp.hip) ---------------------------------
+// In place: R[:, 0:nact] (n rows, leading dimension ld) <- learned
+// preconditioned columns for Ritz values theta[0:nact]; diag, rho (off-
+// diagonal absolute row sums) and *s (mean |diag|) describe the operator;
+// w holds kMlpParams fp32 weights; mask[j] != 0 (optional) selects the
+// Jacobi step for column j; flags[j] (optional) is set to 1 where a net
+// output was not finite (that entry then takes the Jacobi step).
+hipError_t mlp_apply_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
+                         const double* diag, const double* rho, const double* s, const float* w,
+                         const int* mask, int* flags, hipStream_t st);
+hipError_t mlp_apply_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
+                         const double* diag, const double* rho, const double* s, const float* w,
+                         const int* mask, int* flags, hipStream_t st);
+// grad (kMlpParams doubles) = d/dweights of sum_e G_e w_e(weights), with w
+// the learned columns of R; part needs kMlpBlocks * kMlpParams doubles.
+hipError_t mlp_grad(const double* R, const double* G, int64_t ld, int nact, int64_t n,
+                    const double* theta, const double* diag, const double* rho, const double* s,
+                    const float* w, double* part, double* grad, hipStream_t st);
+// One Adam step (step count t >= 1) on the fp32 weights.
+hipError_t mlp_adam(float* w, float* m, float* v, const double* g, int t, double lr,
+                    hipStream_t st);
+hipError_t offdiag_abs_csr(const int32_t* rp, const int32_t* ci, const double* val, int64_t n,
+                           double* rho, hipStream_t st);
+hipError_t offdiag_abs_dense(const double* A, int64_t lda, int64_t n, double* rho,
+                             hipStream_t st);
+hipError_t offdiag_abs_kron(const double* A, int64_t na, double* ra_tmp, double* rho,
+                            hipStream_t st);
+// *out = mean |d| (part: 1024 doubles)
+hipError_t abs_mean(const double* d, int64_t n, double* part, double* out, hipStream_t st);
 
 }  // namespace lobpcg

@@ -1,0 +1,323 @@
+// Streaming kernels of the learned preconditioner's training driver: column
+// gathers, block projections, column dot products, the per-column scalars of
+// the training objective, and the vector updates of the block MINRES that
+// produces the near-exact Jacobi-Davidson corrections.  All fp64, one row
+// per thread; the column dots reduce in two fixed-order stages.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace lobpcg {
+
+namespace {
+
+constexpr int kDotBlocks = 1024;
+
+inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Out[:, j] = In[:, cols[j]]
+__global__ void k_gather_cols(const double* __restrict__ In, int64_t ldi,
+                              const int* __restrict__ cols, int nc, int64_t n,
+                              double* __restrict__ Out, int64_t ldo) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < nc; ++j) Out[i * ldo + j] = In[i * ldi + cols[j]];
+}
+
+// Out = In - X C  (X: n x m, C: m x nc row-major)
+__global__ void k_project(const double* __restrict__ In, int64_t ldi, const double* __restrict__ X,
+                          int64_t ldx, int m, const double* __restrict__ C, int nc, int64_t n,
+                          double* __restrict__ Out, int64_t ldo) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double x[kMaxBlock];
+  for (int t = 0; t < m; ++t) x[t] = X[i * ldx + t];
+  for (int j = 0; j < nc; ++j) {
+    double s = In[i * ldi + j];
+    for (int t = 0; t < m; ++t) s -= x[t] * C[t * nc + j];
+    Out[i * ldo + j] = s;
+  }
+}
+
+struct DotArgs {
+  const double* P[3];
+  const double* Q[3];
+  int64_t ldp[3], ldq[3];
+  int npairs, nc;
+  int64_t n;
+};
+
+// part[b][pair][col] = sum over this block's rows of P[i][col] Q[i][col]
+__global__ __launch_bounds__(256) void k_coldots_part(DotArgs a, double* __restrict__ part) {
+  __shared__ double red[256];
+  for (int pr = 0; pr < a.npairs; ++pr) {
+    for (int j = 0; j < a.nc; ++j) {
+      double s = 0.0;
+      for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n;
+           i += (int64_t)gridDim.x * 256)
+        s += a.P[pr][i * a.ldp[pr] + j] * a.Q[pr][i * a.ldq[pr] + j];
+      red[threadIdx.x] = s;
+      __syncthreads();
+      for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) part[((size_t)blockIdx.x * a.npairs + pr) * a.nc + j] = red[0];
+      __syncthreads();
+    }
+  }
+}
+__global__ void k_coldots_final(const double* __restrict__ part, int nblk, int count,
+                                double* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * count + idx];
+  out[idx] = s;
+}
+
+// Training objective per column (see mlp_objective_scalars).
+__global__ void k_obj_scalars(const double* __restrict__ dots, const double* __restrict__ theta,
+                              const double* __restrict__ ref, int nc, double* __restrict__ coef,
+                              double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= nc) return;
+  const double uu = dots[j], ru = dots[nc + j], uau = dots[2 * nc + j];
+  const double nu2 = uu, nu = sqrt(uu);
+  const double b = ru / nu;
+  const double cq = uau / nu2;
+  const double h = 0.5 * (cq - theta[j]);
+  const double S = hypot(h, b);
+  // Delta = S - h, written b^2 / (S + h) when h > 0 (the difference cancels)
+  const double D = h > 0.0 ? b * b / (S + h) : S - h;
+  // dL/db = -(b / S) / (D nc); dL/dcq = (D / (2 S)) / (D nc) = 1 / (2 S nc)
+  const double cb = -b / (S * D * nc);
+  const double cc = 1.0 / (2.0 * S * nc);
+  coef[j] = cb / nu;                                    // r
+  coef[nc + j] = -cb * b / nu2 - cc * 2.0 * cq / nu2;   // u
+  coef[2 * nc + j] = cc * 2.0 / nu2;                    // P A u
+  out[j] = D;
+  out[nc + j] = (ref ? log(ref[j]) : 0.0) - log(D);
+}
+
+// Out = a R + b U + c Z  (per-column coefficients)
+__global__ void k_combine3(const double* __restrict__ R, const double* __restrict__ U,
+                           const double* __restrict__ Z, const double* __restrict__ coef, int nc,
+                           int64_t n, double* __restrict__ Out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < nc; ++j)
+    Out[i * nc + j] = coef[j] * R[i * nc + j] + coef[nc + j] * U[i * nc + j] +
+                      coef[2 * nc + j] * Z[i * nc + j];
+}
+
+// R = AX - X diag(theta)
+__global__ void k_residual(const double* __restrict__ X, const double* __restrict__ AX,
+                           const double* __restrict__ theta, int m, int64_t n,
+                           double* __restrict__ R) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < m; ++j) R[i * m + j] = AX[i * m + j] - theta[j] * X[i * m + j];
+}
+
+// ---- block MINRES (Paige-Saunders recurrence, one system per column) ----
+// Per-column state, updated by k_mr_scalars.
+struct MrState {
+  double beta1, beta, oldb, dbar, epsln, oldeps, phibar, cs, sn, phi, delta, denom, alfa;
+  int done;
+};
+
+// V = Y / beta
+__global__ void k_mr_scale(const double* __restrict__ Y, const MrState* __restrict__ st, int nc,
+                           int64_t n, double* __restrict__ V) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < nc; ++j) V[i * nc + j] = st[j].done ? 0.0 : Y[i * nc + j] / st[j].beta;
+}
+
+// Y = (AV - theta V) - x (x^T (AV - theta V)) - (beta / oldb) R1 [itn > 1]
+__global__ void k_mr_y(const double* __restrict__ AV, const double* __restrict__ V,
+                       const double* __restrict__ Xc, const double* __restrict__ theta,
+                       const double* __restrict__ dots, const double* __restrict__ R1,
+                       const MrState* __restrict__ st, int first, int nc, int64_t n,
+                       double* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < nc; ++j) {
+    const double xd = dots[j] - theta[j] * dots[nc + j];  // x^T (A v - theta v)
+    double y = AV[i * nc + j] - theta[j] * V[i * nc + j] - xd * Xc[i * nc + j];
+    if (!first && !st[j].done) y -= (st[j].beta / st[j].oldb) * R1[i * nc + j];
+    Y[i * nc + j] = y;
+  }
+}
+
+// Y -= (alfa / beta) R2   (alfa = dots[j] stored into the state)
+__global__ void k_mr_y2(const double* __restrict__ dots, const double* __restrict__ R2,
+                        MrState* __restrict__ st, int nc, int64_t n, double* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < nc; ++j)
+    if (!st[j].done) Y[i * nc + j] -= (dots[j] / st[j].beta) * R2[i * nc + j];
+}
+
+__global__ void k_mr_init(const double* __restrict__ bnorm2, int nc, MrState* __restrict__ st) {
+  const int j = threadIdx.x;
+  if (j >= nc) return;
+  MrState s{};
+  s.beta1 = sqrt(bnorm2[j]);
+  s.beta = s.beta1;
+  s.oldb = 0.0;
+  s.phibar = s.beta1;
+  s.cs = -1.0;
+  s.sn = 0.0;
+  s.done = !(s.beta1 > 0.0);
+  st[j] = s;
+}
+
+// Givens recurrence of one MINRES step; alfa = dots_a[j], new beta^2 = dots_b[j].
+__global__ void k_mr_scalars(const double* __restrict__ alfa, const double* __restrict__ beta2,
+                             int nc, MrState* __restrict__ st) {
+  const int j = threadIdx.x;
+  if (j >= nc) return;
+  MrState s = st[j];
+  if (s.done) {
+    s.phi = 0.0;
+    s.denom = 0.0;
+    st[j] = s;
+    return;
+  }
+  s.alfa = alfa[j];
+  s.oldb = s.beta;
+  s.beta = sqrt(beta2[j]);
+  s.oldeps = s.epsln;
+  s.delta = s.cs * s.dbar + s.sn * s.alfa;
+  const double gbar = s.sn * s.dbar - s.cs * s.alfa;
+  s.epsln = s.sn * s.beta;
+  s.dbar = -s.cs * s.beta;
+  double gamma = sqrt(gbar * gbar + s.beta * s.beta);
+  gamma = fmax(gamma, 1e-300);
+  s.cs = gbar / gamma;
+  s.sn = s.beta / gamma;
+  s.phi = s.cs * s.phibar;
+  s.phibar = s.sn * s.phibar;
+  s.denom = 1.0 / gamma;
+  if (!(s.beta > 1e-300 * s.beta1)) s.done = 1;  // exact invariant subspace: stop this column
+  st[j] = s;
+}
+
+// Wn = (V - oldeps W1 - delta W2) denom ; T += phi Wn
+__global__ void k_mr_update(const double* __restrict__ V, const double* __restrict__ W1,
+                            const double* __restrict__ W2, const MrState* __restrict__ st, int nc,
+                            int64_t n, double* __restrict__ Wn, double* __restrict__ T) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < nc; ++j) {
+    const MrState& s = st[j];
+    const double w = (V[i * nc + j] - s.oldeps * W1[i * nc + j] - s.delta * W2[i * nc + j]) * s.denom;
+    Wn[i * nc + j] = w;
+    T[i * nc + j] += s.phi * w;
+  }
+}
+
+// Y = -(r - x (x^T r)) given dots = x^T r
+__global__ void k_mr_rhs(const double* __restrict__ Rc, const double* __restrict__ Xc,
+                         const double* __restrict__ dots, int nc, int64_t n,
+                         double* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < nc; ++j) Y[i * nc + j] = -(Rc[i * nc + j] - dots[j] * Xc[i * nc + j]);
+}
+
+}  // namespace
+
+size_t mr_state_bytes() { return sizeof(MrState); }
+
+hipError_t gather_cols(const double* In, int64_t ldi, const int* cols, int nc, int64_t n,
+                       double* Out, int64_t ldo, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_cols, dim3(cdiv64(n, 256)), dim3(256), 0, s, In, ldi, cols, nc, n,
+                     Out, ldo);
+  return hipGetLastError();
+}
+hipError_t project_block(const double* In, int64_t ldi, const double* X, int64_t ldx, int m,
+                         const double* C, int nc, int64_t n, double* Out, int64_t ldo,
+                         hipStream_t s) {
+  if (m > kMaxBlock) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_project, dim3(cdiv64(n, 256)), dim3(256), 0, s, In, ldi, X, ldx, m, C, nc,
+                     n, Out, ldo);
+  return hipGetLastError();
+}
+hipError_t coldots(int npairs, const double* const* P, const int64_t* ldp, const double* const* Q,
+                   const int64_t* ldq, int nc, int64_t n, double* part, double* out,
+                   hipStream_t s) {
+  DotArgs a{};
+  for (int k = 0; k < npairs; ++k) {
+    a.P[k] = P[k];
+    a.Q[k] = Q[k];
+    a.ldp[k] = ldp[k];
+    a.ldq[k] = ldq[k];
+  }
+  a.npairs = npairs;
+  a.nc = nc;
+  a.n = n;
+  const int grid = std::max(1, std::min(kDotBlocks, cdiv64(n, 256)));
+  hipLaunchKernelGGL(k_coldots_part, dim3(grid), dim3(256), 0, s, a, part);
+  const int count = npairs * nc;
+  hipLaunchKernelGGL(k_coldots_final, dim3(cdiv64(count, 64)), dim3(64), 0, s, part, grid, count,
+                     out);
+  return hipGetLastError();
+}
+hipError_t objective_scalars(const double* dots, const double* theta, const double* ref, int nc,
+                             double* coef, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_obj_scalars, dim3(1), dim3(64), 0, s, dots, theta, ref, nc, coef, out);
+  return hipGetLastError();
+}
+hipError_t combine3(const double* R, const double* U, const double* Z, const double* coef, int nc,
+                    int64_t n, double* Out, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine3, dim3(cdiv64(n, 256)), dim3(256), 0, s, R, U, Z, coef, nc, n, Out);
+  return hipGetLastError();
+}
+hipError_t residual_block(const double* X, const double* AX, const double* theta, int m,
+                          int64_t n, double* R, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(cdiv64(n, 256)), dim3(256), 0, s, X, AX, theta, m, n, R);
+  return hipGetLastError();
+}
+hipError_t mr_init(const double* bnorm2, int nc, void* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_mr_init, dim3(1), dim3(64), 0, s, bnorm2, nc, static_cast<MrState*>(st));
+  return hipGetLastError();
+}
+hipError_t mr_rhs(const double* Rc, const double* Xc, const double* dots, int nc, int64_t n,
+                  double* Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_mr_rhs, dim3(cdiv64(n, 256)), dim3(256), 0, s, Rc, Xc, dots, nc, n, Y);
+  return hipGetLastError();
+}
+hipError_t mr_scale(const double* Y, const void* st, int nc, int64_t n, double* V, hipStream_t s) {
+  hipLaunchKernelGGL(k_mr_scale, dim3(cdiv64(n, 256)), dim3(256), 0, s, Y,
+                     static_cast<const MrState*>(st), nc, n, V);
+  return hipGetLastError();
+}
+hipError_t mr_y(const double* AV, const double* V, const double* Xc, const double* theta,
+                const double* dots, const double* R1, const void* st, int first, int nc, int64_t n,
+                double* Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_mr_y, dim3(cdiv64(n, 256)), dim3(256), 0, s, AV, V, Xc, theta, dots, R1,
+                     static_cast<const MrState*>(st), first, nc, n, Y);
+  return hipGetLastError();
+}
+hipError_t mr_y2(const double* dots, const double* R2, void* st, int nc, int64_t n, double* Y,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_mr_y2, dim3(cdiv64(n, 256)), dim3(256), 0, s, dots, R2,
+                     static_cast<MrState*>(st), nc, n, Y);
+  return hipGetLastError();
+}
+hipError_t mr_scalars(const double* alfa, const double* beta2, int nc, void* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_mr_scalars, dim3(1), dim3(64), 0, s, alfa, beta2, nc,
+                     static_cast<MrState*>(st));
+  return hipGetLastError();
+}
+hipError_t mr_update(const double* V, const double* W1, const double* W2, const void* st, int nc,
+                     int64_t n, double* Wn, double* T, hipStream_t s) {
+  hipLaunchKernelGGL(k_mr_update, dim3(cdiv64(n, 256)), dim3(256), 0, s, V, W1, W2,
+                     static_cast<const MrState*>(st), nc, n, Wn, T);
+  return hipGetLastError();
+}
+
+}  // namespace lobpcg

@@ -1,0 +1,602 @@
+// Learned preconditioner: inference and training kernels.
+//
+// The preconditioned column is w_i = r_i / sqrt((d_i - theta)^2 + c_i^2)
+// with c_i = s softplus(y_i), y_i the output of a per-entry MLP
+// 3 -> 128 -> 128 -> 1 (SiLU) on the features
+//   phi = (log(|d_i - theta| / s + 1e-6), theta / s, log(rho_i / s + 1e-6)),
+// rho_i the off-diagonal absolute row sum and s = mean |d|.  The denominator
+// is floored at the Jacobi guard delta = 1e-8 max(1, |theta|).  A column
+// flagged in `mask`, and any entry whose net output is not finite, takes
+// c = 0: the guarded absolute Jacobi step (the diagonal fallback).
+//
+// Work layout: a workgroup of 256 threads holds W2^T (128 x 128 fp32, rows
+// padded to 132 floats) and the small layers in LDS and walks tiles of 64
+// entries (entry e = row * nact + column, contiguous in the row-major
+// block).  Layer 2 is a 64 x 128 x 128 product per tile: thread (eg, kg)
+// owns entries 4eg..4eg+3 and neurons 8kg..8kg+7 in 32 fp32 accumulators,
+// reading one float4 of h1 and two float4 of W2^T per step of the inner
+// dimension; LDS reads are broadcasts (16 distinct h1 chunks and 4 distinct
+// W2^T chunks per wave).  The layer-3 dot is reduced over the 16 neuron
+// groups through LDS in a fixed order.
+//
+// Training (k_mlp_grad): the same forward pass per tile, then the analytic
+// backward pass for an output gradient dL/dw given per entry; per-tile sums
+// are formed in fp32 and accumulated across tiles in fp64 per workgroup;
+// k_grad_reduce adds the workgroup partials in a fixed order, k_adam updates
+// the fp32 master weights.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace lobpcg {
+
+namespace {
+
+constexpr int kH = kMlpHidden;
+constexpr int kTE = 64;          // entries per tile
+constexpr int kW2S = 132;        // padded row stride of W2^T
+constexpr int kHS = kTE + 4;     // padded row stride of h1 / dz2 ([neuron][entry])
+constexpr int oW1 = 0, oB1 = kH * kMlpFeat, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH,
+              oB3 = oW3 + kH;
+static_assert(oB3 + 1 == kMlpParams, "parameter layout");
+
+// LDS layout (floats)
+constexpr int sW2T = 0;
+constexpr int sW1 = sW2T + kH * kW2S;
+constexpr int sB1 = sW1 + kH * 4;  // W1 rows padded to 4
+constexpr int sB2 = sB1 + kH;
+constexpr int sW3 = sB2 + kH;
+constexpr int sB3 = sW3 + kH;
+constexpr int sPhi = sB3 + 4;            // [e][4]
+constexpr int sH1 = sPhi + kTE * 4;      // [j][kHS]
+constexpr int sYP = sH1 + kH * kHS;      // [kg][kTE] layer-3 partials
+constexpr int sY = sYP + 16 * kTE;       // [e]
+constexpr int kFwdFloats = sY + kTE;
+// training extras
+constexpr int sDZ2 = kFwdFloats;         // [k][kHS]
+constexpr int sDY = sDZ2 + kH * kHS;     // [e]
+constexpr int sGA = sDY + kTE;           // [j][8]: dW1 (3), db1, db2, dW3
+constexpr int sDEnd = sGA + kH * 8;      // then 2 kTE doubles (r, dL/dw)
+constexpr size_t kFwdBytes = sizeof(float) * kFwdFloats;
+constexpr size_t kGradBytes = sizeof(float) * sDEnd + sizeof(double) * 2 * kTE;
+static_assert(kGradBytes <= 152 * 1024, "LDS budget");
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = sigm(z);
+  return s * (1.0f + z * (1.0f - s));
+}
+__device__ __forceinline__ double softplus_d(double y) {
+  return fmax(y, 0.0) + log1p(exp(-fabs(y)));
+}
+
+__device__ __forceinline__ void load_weights(const float* __restrict__ wts, float* L) {
+  for (int idx = threadIdx.x; idx < kH * kH; idx += blockDim.x) {
+    const int k = idx / kH, j = idx - k * kH;  // W2[k][j]
+    L[sW2T + j * kW2S + k] = wts[oW2 + idx];
+  }
+  for (int idx = threadIdx.x; idx < kH; idx += blockDim.x) {
+    L[sW1 + idx * 4 + 0] = wts[oW1 + idx * 3 + 0];
+    L[sW1 + idx * 4 + 1] = wts[oW1 + idx * 3 + 1];
+    L[sW1 + idx * 4 + 2] = wts[oW1 + idx * 3 + 2];
+    L[sW1 + idx * 4 + 3] = 0.0f;
+    L[sB1 + idx] = wts[oB1 + idx];
+    L[sB2 + idx] = wts[oB2 + idx];
+    L[sW3 + idx] = wts[oW3 + idx];
+  }
+  if (threadIdx.x == 0) L[sB3] = wts[oB3];
+}
+
+// Per-entry inputs of one tile entry.
+struct EntryIn {
+  bool valid;
+  int64_t row;
+  int col;
+  double dm;     // d_i - theta_j
+  double theta;
+};
+
+// Features of tile entry e into LDS (threads 0..kTE-1).
+__device__ __forceinline__ EntryIn entry_features(float* L, int e, int64_t ent, int64_t total,
+                                                  int nact, const double* __restrict__ diag,
+                                                  const double* __restrict__ rho,
+                                                  const double* __restrict__ theta, double s) {
+  EntryIn in{};
+  in.valid = ent < total;
+  float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+  if (in.valid) {
+    in.row = ent / nact;
+    in.col = (int)(ent - in.row * nact);
+    in.theta = theta[in.col];
+    in.dm = diag[in.row] - in.theta;
+    f0 = (float)log(fabs(in.dm) / s + 1e-6);
+    f1 = (float)(in.theta / s);
+    f2 = (float)log(rho[in.row] / s + 1e-6);
+  }
+  L[sPhi + e * 4 + 0] = f0;
+  L[sPhi + e * 4 + 1] = f1;
+  L[sPhi + e * 4 + 2] = f2;
+  return in;
+}
+
+// Layer 1 into h1 (all threads), then layer 2 into z2 registers and the
+// layer-3 partials; y of each tile entry lands in L[sY + e].  Two barriers.
+__device__ __forceinline__ void forward_tile(float* L, float (&z2)[4][8], int eg, int kg) {
+  for (int idx = threadIdx.x; idx < kH * kTE; idx += blockDim.x) {
+    const int j = idx / kTE, e = idx - j * kTE;
+    const float* w1 = L + sW1 + j * 4;
+    const float* ph = L + sPhi + e * 4;
+    const float z = L[sB1 + j] + w1[0] * ph[0] + w1[1] * ph[1] + w1[2] * ph[2];
+    L[sH1 + j * kHS + e] = silu(z);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) z2[e][k] = L[sB2 + 8 * kg + k];
+  const float* h1 = L + sH1 + 4 * eg;
+  const float* w2 = L + sW2T + 8 * kg;
+#pragma unroll 4
+  for (int j = 0; j < kH; ++j) {
+    const float4 hv = *reinterpret_cast<const float4*>(h1 + j * kHS);
+    const float4 wa = *reinterpret_cast<const float4*>(w2 + j * kW2S);
+    const float4 wb = *reinterpret_cast<const float4*>(w2 + j * kW2S + 4);
+    const float hh[4] = {hv.x, hv.y, hv.z, hv.w};
+    const float ww[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) z2[e][k] = fmaf(hh[e], ww[k], z2[e][k]);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc = fmaf(L[sW3 + 8 * kg + k], silu(z2[e][k]), acc);
+    L[sYP + kg * kTE + 4 * eg + e] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < kTE) {
+    float y = L[sB3];
+    for (int g = 0; g < 16; ++g) y += L[sYP + g * kTE + threadIdx.x];
+    L[sY + threadIdx.x] = y;
+  }
+}
+
+struct EntryOut {
+  double c;      // regulariser (0 on fallback)
+  double q;      // dm^2 + c^2, floored
+  bool floored;
+};
+
+__device__ __forceinline__ EntryOut regularise(const EntryIn& in, float y, double s, bool jacobi,
+                                               int* flags) {
+  EntryOut o{};
+  double c = s * softplus_d((double)y);
+  if (!jacobi && !isfinite(c)) {
+    if (flags) flags[in.col] = 1;
+    jacobi = true;
+  }
+  if (jacobi) c = 0.0;
+  const double delta = kPrecondGuard * fmax(1.0, fabs(in.theta));
+  const double q = in.dm * in.dm + c * c;
+  o.floored = q < delta * delta;
+  o.q = o.floored ? delta * delta : q;
+  o.c = c;
+  return o;
+}
+
+// Inference: R (n x nact, leading dimension ld) is replaced by the learned
+// preconditioned columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mlp_apply(T* __restrict__ R, int64_t ld, int nact,
+                                                   int64_t n, const double* __restrict__ theta,
+                                                   const double* __restrict__ diag,
+                                                   const double* __restrict__ rho,
+                                                   const double* __restrict__ sptr,
+                                                   const float* __restrict__ wts,
+                                                   const int* __restrict__ mask,
+                                                   int* __restrict__ flags) {
+  extern __shared__ float L[];
+  load_weights(wts, L);
+  const double s = *sptr;
+  const int eg = threadIdx.x & 15, kg = threadIdx.x >> 4;
+  const int64_t total = n * nact;
+  const int64_t ntiles = (total + kTE - 1) / kTE;
+  float z2[4][8];
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    EntryIn in{};
+    __syncthreads();  // weights loaded / previous tile's LDS reads done
+    if (threadIdx.x < kTE)
+      in = entry_features(L, threadIdx.x, tile * kTE + threadIdx.x, total, nact, diag, rho, theta,
+                          s);
+    __syncthreads();
+    forward_tile(L, z2, eg, kg);
+    if (threadIdx.x < kTE && in.valid) {
+      const bool jac = mask != nullptr && mask[in.col] != 0;
+      const EntryOut o = regularise(in, L[sY + threadIdx.x], s, jac, flags);
+      T* p = R + in.row * ld + in.col;
+      *p = (T)((double)*p / sqrt(o.q));
+    }
+  }
+}
+
+// Training: per-workgroup partial gradients (kMlpParams doubles each) of
+// sum_e G_e w_e, where w is the learned column of R and G = dL/dw is given
+// (same layout as R).
+__global__ __launch_bounds__(256) void k_mlp_grad(const double* __restrict__ R,
+                                                  const double* __restrict__ G, int64_t ld,
+                                                  int nact, int64_t n,
+                                                  const double* __restrict__ theta,
+                                                  const double* __restrict__ diag,
+                                                  const double* __restrict__ rho,
+                                                  const double* __restrict__ sptr,
+                                                  const float* __restrict__ wts,
+                                                  double* __restrict__ part) {
+  extern __shared__ float L[];
+  double* Ld = reinterpret_cast<double*>(L + sDEnd);  // [r(kTE) | g(kTE)]
+  load_weights(wts, L);
+  const double s = *sptr;
+  const int tid = threadIdx.x;
+  const int eg = tid & 15, kg = tid >> 4;
+  const int64_t total = n * nact;
+  const int64_t ntiles = (total + kTE - 1) / kTE;
+  // fp64 accumulators: dW2 block (8 k x 8 j) of this thread, per-neuron rows
+  double aW2[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) aW2[a][b] = 0.0;
+  double aRow[6] = {0, 0, 0, 0, 0, 0};  // neuron tid (< 128): dW1[0..2], db1, db2, dW3
+  double aB3 = 0.0;
+  float z2[4][8];
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    EntryIn in{};
+    __syncthreads();
+    if (tid < kTE) {
+      in = entry_features(L, tid, tile * kTE + tid, total, nact, diag, rho, theta, s);
+      Ld[tid] = in.valid ? R[in.row * ld + in.col] : 0.0;
+      Ld[kTE + tid] = in.valid ? G[in.row * ld + in.col] : 0.0;
+    }
+    for (int idx = tid; idx < kH * 8; idx += blockDim.x) L[sGA + idx] = 0.0f;
+    __syncthreads();
+    forward_tile(L, z2, eg, kg);
+    // dL/dy per entry: w = r q^-1/2, q = dm^2 + c^2, c = s softplus(y)
+    if (tid < kTE) {
+      float dy = 0.0f;
+      if (in.valid) {
+        const float y = L[sY + tid];
+        const EntryOut o = regularise(in, y, s, false, nullptr);
+        if (!o.floored && o.c > 0.0) {
+          const double sg = 1.0 / (1.0 + exp(-(double)y));
+          dy = (float)(-Ld[kTE + tid] * Ld[tid] * o.c * s * sg / (o.q * sqrt(o.q)));
+        }
+      }
+      L[sDY + tid] = dy;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      float t = 0.0f;
+      for (int e = 0; e < kTE; ++e) t += L[sDY + e];
+      aB3 += (double)t;
+    }
+    // dz2 = dy w3 silu'(z2); dW3 += dy h2; db2 += dz2
+    {
+      float pW3[8], pB2[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pW3[k] = pB2[k] = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float dy = L[sDY + 4 * eg + e];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float z = z2[e][k];
+          const float dz = dy * L[sW3 + 8 * kg + k] * dsilu(z);
+          L[sDZ2 + (8 * kg + k) * kHS + 4 * eg + e] = dz;
+          pW3[k] = fmaf(dy, silu(z), pW3[k]);
+          pB2[k] += dz;
+        }
+      }
+      // reduce over the 16 entry groups (lanes with equal kg are one
+      // 16-lane segment of a wave)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) {
+          pW3[k] += __shfl_xor(pW3[k], off, 16);
+          pB2[k] += __shfl_xor(pB2[k], off, 16);
+        }
+      }
+      if (eg == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          L[sGA + (8 * kg + k) * 8 + 4] = pB2[k];
+          L[sGA + (8 * kg + k) * 8 + 5] = pW3[k];
+        }
+      }
+    }
+    __syncthreads();
+    // dW2[k][j] += sum_e dz2[k][e] h1[j][e]; thread: k = 8 kg .., j = 8 eg ..
+    {
+      float t[8][8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) t[a][b] = 0.0f;
+      for (int e = 0; e < kTE; e += 4) {
+        float4 dz[8], hv[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+          dz[a] = *reinterpret_cast<const float4*>(L + sDZ2 + (8 * kg + a) * kHS + e);
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+          hv[b] = *reinterpret_cast<const float4*>(L + sH1 + (8 * eg + b) * kHS + e);
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            float v = t[a][b];
+            v = fmaf(dz[a].x, hv[b].x, v);
+            v = fmaf(dz[a].y, hv[b].y, v);
+            v = fmaf(dz[a].z, hv[b].z, v);
+            v = fmaf(dz[a].w, hv[b].w, v);
+            t[a][b] = v;
+          }
+      }
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) aW2[a][b] += (double)t[a][b];
+    }
+    // dh1[e][j] = sum_k dz2[k][e] W2[k][j]; thread: e = 4 eg .., j = 8 kg ..
+    {
+      float dh[4][8];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) dh[e][b] = 0.0f;
+      for (int k = 0; k < kH; ++k) {
+        const float4 dz = *reinterpret_cast<const float4*>(L + sDZ2 + k * kHS + 4 * eg);
+        const float dd[4] = {dz.x, dz.y, dz.z, dz.w};
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const float w = L[sW2T + (8 * kg + b) * kW2S + k];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) dh[e][b] = fmaf(dd[e], w, dh[e][b]);
+        }
+      }
+      // dz1 = dh1 silu'(z1); dW1 += dz1 phi; db1 += dz1
+      float p0[8], p1[8], p2[8], pb[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) p0[b] = p1[b] = p2[b] = pb[b] = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float* ph = L + sPhi + (4 * eg + e) * 4;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int j = 8 * kg + b;
+          const float* w1 = L + sW1 + j * 4;
+          const float z1 = L[sB1 + j] + w1[0] * ph[0] + w1[1] * ph[1] + w1[2] * ph[2];
+          const float dz1 = dh[e][b] * dsilu(z1);
+          p0[b] = fmaf(dz1, ph[0], p0[b]);
+          p1[b] = fmaf(dz1, ph[1], p1[b]);
+          p2[b] = fmaf(dz1, ph[2], p2[b]);
+          pb[b] += dz1;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) {
+          p0[b] += __shfl_xor(p0[b], off, 16);
+          p1[b] += __shfl_xor(p1[b], off, 16);
+          p2[b] += __shfl_xor(p2[b], off, 16);
+          pb[b] += __shfl_xor(pb[b], off, 16);
+        }
+      }
+      if (eg == 0) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          float* g = L + sGA + (8 * kg + b) * 8;
+          g[0] = p0[b];
+          g[1] = p1[b];
+          g[2] = p2[b];
+          g[3] = pb[b];
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < kH) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) aRow[c] += (double)L[sGA + tid * 8 + c];
+    }
+  }
+  double* out = part + (size_t)blockIdx.x * kMlpParams;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) out[oW2 + (8 * kg + a) * kH + 8 * eg + b] = aW2[a][b];
+  if (tid < kH) {
+    out[oW1 + tid * 3 + 0] = aRow[0];
+    out[oW1 + tid * 3 + 1] = aRow[1];
+    out[oW1 + tid * 3 + 2] = aRow[2];
+    out[oB1 + tid] = aRow[3];
+    out[oB2 + tid] = aRow[4];
+    out[oW3 + tid] = aRow[5];
+  }
+  if (tid == 0) out[oB3] = aB3;
+}
+
+__global__ void k_grad_reduce(const double* __restrict__ part, int nblk, double* __restrict__ g) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kMlpParams) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * kMlpParams + idx];
+  g[idx] = s;
+}
+
+__global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                       const double* __restrict__ g, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kMlpParams) return;
+  const float gi = (float)g[idx];
+  const float mi = b1 * m[idx] + (1.0f - b1) * gi;
+  const float vi = b2 * v[idx] + (1.0f - b2) * gi * gi;
+  m[idx] = mi;
+  v[idx] = vi;
+  w[idx] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---- features of the operator ------------------------------------------
+__global__ void k_csr_offdiag_abs(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                  const double* __restrict__ val, int64_t n,
+                                  double* __restrict__ rho) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] != i) s += fabs(val[e]);
+  rho[i] = s;
+}
+
+// one wave per row
+__global__ void k_dense_offdiag_abs(const double* __restrict__ A, int64_t lda, int64_t n,
+                                    double* __restrict__ rho) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t j = lane; j < n; j += 64)
+    if (j != i) s += fabs(A[i * lda + j]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) rho[i] = s;
+}
+
+// H = A (x) I + I (x) A + diag(V): rho_(i,j) = ra_i + ra_j with ra the
+// off-diagonal absolute row sums of A (computed first into rho[0..na)).
+__global__ void k_kron_offdiag_abs(const double* __restrict__ ra, int64_t na,
+                                   double* __restrict__ rho) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= na * na) return;
+  const int64_t i = idx / na, j = idx - i * na;
+  rho[idx] = ra[i] + ra[j];
+}
+
+// mean |d| in two fixed-order stages
+__global__ void k_absmean_part(const double* __restrict__ d, int64_t n, double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += fabs(d[i]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void k_absmean_final(const double* __restrict__ part, int nblk, int64_t n,
+                                double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[b];
+  *out = s / (double)n;
+}
+
+inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+int mlp_grid(int64_t total) {
+  const int64_t tiles = (total + kTE - 1) / kTE;
+  return (int)std::min<int64_t>(tiles, kMlpBlocks);
+}
+
+}  // namespace
+
+template <typename T>
+static hipError_t mlp_apply_t(T* R, int64_t ld, int nact, int64_t n, const double* theta,
+                              const double* diag, const double* rho, const double* s,
+                              const float* w, const int* mask, int* flags, hipStream_t st) {
+  if (n <= 0 || nact <= 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_apply<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdBytes);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_mlp_apply<T>, dim3(mlp_grid(n * nact)), dim3(256), kFwdBytes, st, R, ld,
+                     nact, n, theta, diag, rho, s, w, mask, flags);
+  return hipGetLastError();
+}
+
+hipError_t mlp_apply_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
+                         const double* diag, const double* rho, const double* s, const float* w,
+                         const int* mask, int* flags, hipStream_t st) {
+  return mlp_apply_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+}
+hipError_t mlp_apply_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
+                         const double* diag, const double* rho, const double* s, const float* w,
+                         const int* mask, int* flags, hipStream_t st) {
+  return mlp_apply_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+}
+
+hipError_t mlp_grad(const double* R, const double* G, int64_t ld, int nact, int64_t n,
+                    const double* theta, const double* diag, const double* rho, const double* s,
+                    const float* w, double* part, double* grad, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_grad),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGradBytes);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int grid = (n > 0 && nact > 0) ? mlp_grid(n * nact) : 0;
+  if (grid > 0)
+    hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(256), kGradBytes, st, R, G, ld, nact, n,
+                       theta, diag, rho, s, w, part);
+  hipLaunchKernelGGL(k_grad_reduce, dim3(cdiv64(kMlpParams, 256)), dim3(256), 0, st, part, grid,
+                     grad);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam(float* w, float* m, float* v, const double* g, int t, double lr,
+                    hipStream_t st) {
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  const float c1 = (float)(1.0 - std::pow(b1, t)), c2 = (float)(1.0 - std::pow(b2, t));
+  hipLaunchKernelGGL(k_adam, dim3(cdiv64(kMlpParams, 256)), dim3(256), 0, st, w, m, v, g,
+                     (float)lr, (float)b1, (float)b2, (float)eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t offdiag_abs_csr(const int32_t* rp, const int32_t* ci, const double* val, int64_t n,
+                           double* rho, hipStream_t st) {
+  hipLaunchKernelGGL(k_csr_offdiag_abs, dim3(cdiv64(n, 256)), dim3(256), 0, st, rp, ci, val, n,
+                     rho);
+  return hipGetLastError();
+}
+hipError_t offdiag_abs_dense(const double* A, int64_t lda, int64_t n, double* rho,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_offdiag_abs, dim3(cdiv64(n, 4)), dim3(256), 0, st, A, lda, n, rho);
+  return hipGetLastError();
+}
+hipError_t offdiag_abs_kron(const double* A, int64_t na, double* ra_tmp, double* rho,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_offdiag_abs, dim3(cdiv64(na, 4)), dim3(256), 0, st, A, na, na,
+                     ra_tmp);
+  hipLaunchKernelGGL(k_kron_offdiag_abs, dim3(cdiv64(na * na, 256)), dim3(256), 0, st, ra_tmp, na,
+                     rho);
+  return hipGetLastError();
+}
+hipError_t abs_mean(const double* d, int64_t n, double* part, double* out, hipStream_t st) {
+  const int grid = (int)std::min<int64_t>(std::max<int64_t>(cdiv64(n, 256), 1), 1024);
+  hipLaunchKernelGGL(k_absmean_part, dim3(grid), dim3(256), 0, st, d, n, part);
+  hipLaunchKernelGGL(k_absmean_final, dim3(1), dim3(64), 0, st, part, grid, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace lobpcg

@@ -20,121 +20,9 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lobpcg.h"
-#include "internal.h"
+#include "ctx.h"
 
 using namespace lobpcg;
-
-namespace {
-
-constexpr size_t kAlign = 256;
-constexpr int kOrthoRounds = 6;     // controller rounds launched before the first check
-constexpr int kOrthoHardCap = 64;   // rounds before giving up
-constexpr size_t kPinnedBytes = 1 << 16;
-constexpr size_t kGPartOffset = 1 << 16;  // doubles: rotation's overlap partials inside `part`
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-enum OpKind { kOpNone = 0, kOpCsr = 1, kOpDense = 2, kOpKron = 3 };
-
-struct Layout {
-  size_t V[2], AV[2], diag, part, small, total;
-  size_t V32[2], AV32[2], op32;  // mixed precision only (0 otherwise)
-  // inside small (byte offsets)
-  size_t a, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye;
-};
-
-}  // namespace
-
-struct lobpcg_ctx {
-  int64_t n = 0;
-  int device = 0;
-  hipStream_t stream = nullptr;
-  // options
-  double tau = 1e-14;
-  int max_iter = 1000;
-  int precision = LOBPCG_PREC_FP64;
-  int ortho_max_inner = 6;
-  int ortho_max_outer = 4;
-  int trace = 0;
-  // operator
-  int op = kOpNone;
-  const int32_t* rp = nullptr;
-  const int32_t* ci = nullptr;
-  const double* val = nullptr;
-  int64_t nnz = 0;
-  const double* A = nullptr;
-  int64_t lda = 0;
-  int64_t na = 0;
-  const double* Vpot = nullptr;
-  // preconditioner
-  int pkind = LOBPCG_PRECOND_DIAG;
-  const double* user_diag = nullptr;
-  bool diag_ready = false;
-  // initial guess
-  const double* X0 = nullptr;
-  int64_t ldx0 = 0;
-  int block = 0;
-  // workspace
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  Layout lay{};
-  int lay_block = -1;
-  // pinned host buffer
-  char* pinned = nullptr;
-  // results
-  bool have_result = false;
-  int res_k = 0;
-  const double* res_X = nullptr;
-  int64_t res_ld = 0;
-  std::vector<double> res_evals, res_resn;
-  lobpcg_stats stats{};
-  std::string err;
-  // fp32 operator copies (mixed precision) and the operator norm bound
-  bool op32_ready = false;
-  double norm_bound = -1.0;
-
-  // ---- helpers ----
-  double* dptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
-  template <typename T> T* small_ptr(size_t off) const {
-    return reinterpret_cast<T*>(ws + lay.small + off);
-  }
-  int fail(int code, const std::string& msg) {
-    err = msg;
-    return code;
-  }
-  int hip_fail(hipError_t e, const char* where) {
-    err = std::string(where) + ": " + hipGetErrorString(e);
-    return LOBPCG_ERR_DEVICE;
-  }
-  Layout plan(int m) const;
-  size_t op32_elems() const;
-  int ensure_layout(int m);
-  int apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy);
-  int apply_op(const float* W, int64_t ldw, int nc, float* Y, int64_t ldy);
-  template <typename T>
-  int ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info, bool have_g0 = false,
-                bool fold = false, double tau_run = -1.0);
-  int ensure_diag();
-  int ensure_op32();
-  int true_residuals(const double* X, int64_t ldx, int m, double* scratch, const double* theta_rr,
-                     std::vector<double>& th, std::vector<double>& rn);
-  struct PhaseOut {
-    const void* X;  // final Ritz vectors of the phase (first m columns)
-    int64_t ld;
-    bool converged;
-  };
-  template <typename T>
-  int run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool low, int& iter,
-                PhaseOut& out);
-  int solve(int k, double tol);
-};
-
-#define HIPCHK(expr)                                  \
-  do {                                                \
-    hipError_t e_ = (expr);                           \
-    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
-  } while (0)
 
 size_t lobpcg_ctx::op32_elems() const {
   switch (op) {
@@ -159,6 +47,7 @@ Layout lobpcg_ctx::plan(int m) const {
   L.AV[0] = take(blk);
   L.AV[1] = take(blk);
   L.diag = take((size_t)n * sizeof(double));
+  L.rho = take((size_t)n * sizeof(double));
   const size_t gblk = (size_t)std::min<int64_t>(kGramBlocks, (n + 63) / 64) + 1;
   const size_t part =
       std::max({gblk * kGramMaxCols * kGramMaxCols, (size_t)kStreamBlocks * 3 * 64,
@@ -183,6 +72,9 @@ Layout lobpcg_ctx::plan(int m) const {
   L.pidx = stake(sizeof(int64_t) * 256 * 64);
   L.pval = stake(sizeof(double) * 256 * 64);
   L.eye = stake(sizeof(double) * 64 * 64);
+  L.lmask = stake(sizeof(int) * 64);
+  L.lflags = stake(sizeof(int) * 64);
+  L.lscale = stake(sizeof(double) * 4);
   L.small = take(so);
   if (precision == LOBPCG_PREC_FP32) {
     const size_t blk32 = (size_t)n * 3 * m * sizeof(float);
@@ -205,6 +97,7 @@ int lobpcg_ctx::ensure_layout(int m) {
     lay = L;
     lay_block = m;
     diag_ready = false;
+    lfeat_ready = false;
     op32_ready = false;
   }
   return LOBPCG_OK;
@@ -287,6 +180,31 @@ int lobpcg_ctx::ensure_diag() {
   return LOBPCG_OK;
 }
 
+// Inputs of the learned preconditioner besides diag(A): the off-diagonal
+// absolute row sums and s = mean |diag|.
+int lobpcg_ctx::ensure_learned_features() {
+  if (lfeat_ready) return LOBPCG_OK;
+  int rc = ensure_diag();
+  if (rc) return rc;
+  double* rho = dptr(lay.rho);
+  switch (op) {
+    case kOpCsr: HIPCHK(offdiag_abs_csr(rp, ci, val, n, rho, stream)); break;
+    case kOpDense: HIPCHK(offdiag_abs_dense(A, lda, n, rho, stream)); break;
+    case kOpKron: HIPCHK(offdiag_abs_kron(A, na, dptr(lay.part), rho, stream)); break;
+    default: return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+  }
+  double* sc = small_ptr<double>(lay.lscale);
+  HIPCHK(abs_mean(dptr(lay.diag), n, dptr(lay.part) + (op == kOpKron ? na : 0), sc, stream));
+  double* hp = reinterpret_cast<double*>(pinned);
+  HIPCHK(hipMemcpyAsync(hp, sc, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  lscale_host = hp[0];
+  if (!(lscale_host > 0.0) || !std::isfinite(lscale_host))
+    return fail(LOBPCG_ERR_INVALID_ARG, "learned preconditioner needs a nonzero diagonal");
+  lfeat_ready = true;
+  return LOBPCG_OK;
+}
+
 // typed dispatch of the streaming kernels
 static hipError_t gram_t(const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
                          int64_t n, double* part, double* C, const int* skip, hipStream_t s) {
@@ -295,6 +213,16 @@ static hipError_t gram_t(const double* A, int64_t lda, int p, const double* B, i
 static hipError_t gram_t(const float* A, int64_t lda, int p, const float* B, int64_t ldb, int q,
                          int64_t n, double* part, double* C, const int* skip, hipStream_t s) {
   return gram_f32(A, lda, p, B, ldb, q, n, part, C, skip, s);
+}
+static hipError_t mlp_apply_t(double* R, int64_t ld, int nact, int64_t n, const double* theta,
+                              const double* diag, const double* rho, const double* s,
+                              const float* w, const int* mask, int* flags, hipStream_t st) {
+  return mlp_apply_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+}
+static hipError_t mlp_apply_t(float* R, int64_t ld, int nact, int64_t n, const double* theta,
+                              const double* diag, const double* rho, const double* s,
+                              const float* w, const int* mask, int* flags, hipStream_t st) {
+  return mlp_apply_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
 }
 static hipError_t rotate_t(const double* V, const double* AV, double* Vo, double* AVo,
                            const RotateArgs& a, hipStream_t s) {
@@ -437,6 +365,18 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
   const double tau_phase = low ? 1e-6 : tau;
   const double lock_tol = low ? -1.0 : tol;  // nothing locks in the fp32 phase
   const double switch_level = 100.0 * 0x1.0p-24 * (norm_bound > 0.0 ? norm_bound : 1.0);
+  // learned preconditioner: a column whose residual did not decrease over
+  // the step that used its learned W takes the Jacobi step for the next 3
+  // iterations (so does a column where the net produced a non-finite value)
+  const bool learned = (pkind == LOBPCG_PRECOND_LEARNED);
+  std::vector<int> fb_left(m, 0);
+  std::vector<char> used_learned(m, 0);
+  std::vector<double> r_before(m, 0.0);
+  int prev_a0 = 0, prev_nact = 0;
+  int* lmask = small_ptr<int>(lay.lmask);
+  int* lflags = small_ptr<int>(lay.lflags);
+  int* hmask = reinterpret_cast<int*>(pinned + kPinnedBytes / 2);
+  if (learned) HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
   int rc = ortho_run<T>(V[0], m, 0, m, nullptr, false, true, tau_phase);
   if (rc) return rc;
   rc = apply_op(V[0], m, m, AV[0], m);
@@ -473,18 +413,20 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     ra.m = m;
     ra.q = q;
     ra.a0 = a0;
-    ra.precond = pkind;
+    ra.precond = learned ? kPrecNone : pkind;  // learned: W~ = R, transformed below
     ra.U = U;
     ra.theta = theta;
     ra.diag = dptr(lay.diag);
     ra.part = part;
     ra.resnorm2 = resn2;
-    ra.gpart = part + kGPartOffset;
+    ra.gpart = learned ? nullptr : part + kGPartOffset;
     ra.G0 = small_ptr<double>(lay.G);
     HIPCHK(rotate_t(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
     HIPCHK(hipMemcpyAsync(h, resn2, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipMemcpyAsync(h + 64, theta, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipMemcpyAsync(h + 128, info, sizeof(int) * 16, hipMemcpyDeviceToHost, stream));
+    if (learned)
+      HIPCHK(hipMemcpyAsync(h + 192, lflags, sizeof(int) * 64, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     const int* hinfo = reinterpret_cast<const int*>(h + 128);
     if (hinfo[1] != 0) return fail(LOBPCG_ERR_ORTHO_FAILED, "R^p orthonormalisation of u_p failed");
@@ -495,6 +437,23 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       if (!std::isfinite(rnorm[j]) || !std::isfinite(th_rr[j]))
         return fail(LOBPCG_ERR_NONFINITE, "non-finite Ritz value or residual");
       rmax = std::max(rmax, rnorm[j]);
+    }
+    if (learned) {
+      const int* hfl = reinterpret_cast<const int*>(h + 192);
+      for (int j = 0; j < prev_nact; ++j)
+        if (hfl[j]) {
+          stats.learned_nonfinite++;
+          fb_left[prev_a0 + j] = 3;
+          used_learned[prev_a0 + j] = 0;
+        }
+      for (int j = 0; j < m; ++j) {
+        if (used_learned[j] && !(rnorm[j] < r_before[j])) {
+          fb_left[j] = 3;
+          stats.learned_fallbacks++;
+        }
+        used_learned[j] = 0;
+      }
+      prev_nact = 0;
     }
     if (low) {
       stall = (rmax > 0.9 * prev_max) ? stall + 1 : 0;
@@ -554,7 +513,22 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     }
     ++iter;
     // ---- W = ortho(T R; [X P]) and AW = A W (Alg. 1) ----
-    rc = ortho_run<T>(V[1 - c], ldo, q, nact, nullptr, true, true, tau_phase);
+    if (learned) {
+      for (int j = a0; j < m; ++j) {
+        const bool jac = fb_left[j] > 0;
+        if (jac) --fb_left[j];
+        hmask[j - a0] = jac ? 1 : 0;
+        used_learned[j] = jac ? 0 : 1;
+        r_before[j] = rnorm[j];
+      }
+      HIPCHK(hipMemcpyAsync(lmask, hmask, sizeof(int) * nact, hipMemcpyHostToDevice, stream));
+      HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
+      HIPCHK(mlp_apply_t(V[1 - c] + q, ldo, nact, n, theta + a0, dptr(lay.diag), dptr(lay.rho),
+                         small_ptr<double>(lay.lscale), lweights, lmask, lflags, stream));
+      prev_a0 = a0;
+      prev_nact = nact;
+    }
+    rc = ortho_run<T>(V[1 - c], ldo, q, nact, nullptr, !learned, true, tau_phase);
     if (rc) return rc;
     pend_valid = true;
     pend_woff = q;
@@ -586,6 +560,12 @@ int lobpcg_ctx::solve(int k, double tol) {
   have_result = false;
   if (pkind != LOBPCG_PRECOND_NONE) {
     rc = ensure_diag();
+    if (rc) return rc;
+  }
+  if (pkind == LOBPCG_PRECOND_LEARNED) {
+    if (lweights == nullptr)
+      return fail(LOBPCG_ERR_BAD_STATE, "learned preconditioner selected but no weights set");
+    rc = ensure_learned_features();
     if (rc) return rc;
   }
   double* V[2] = {dptr(lay.V[0]), dptr(lay.V[1])};
@@ -661,7 +641,8 @@ int lobpcg_create(int64_t n, int device, lobpcg_t* out) {
 int lobpcg_destroy(lobpcg_t h) {
   if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
   hipSetDevice(h->device);
-  if (h->pinned) hipHostFree(h->pinned);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->lweights) (void)hipFree(h->lweights);
   delete h;
   return LOBPCG_OK;
 }
@@ -720,6 +701,7 @@ int lobpcg_set_workspace(lobpcg_t h, void* p, size_t bytes) {
   h->ws_bytes = bytes;
   h->lay_block = -1;
   h->diag_ready = false;
+  h->lfeat_ready = false;
   h->have_result = false;
   return LOBPCG_OK;
 }
@@ -752,6 +734,7 @@ int lobpcg_set_operator_csr(lobpcg_t h, const int32_t* row_ptr, const int32_t* c
   h->val = val;
   h->nnz = nnz;
   h->diag_ready = false;
+  h->lfeat_ready = false;
   h->op32_ready = false;
   h->have_result = false;
   return LOBPCG_OK;
@@ -764,6 +747,7 @@ int lobpcg_set_operator_dense(lobpcg_t h, const double* A, int64_t lda) {
   h->A = A;
   h->lda = lda;
   h->diag_ready = false;
+  h->lfeat_ready = false;
   h->op32_ready = false;
   h->have_result = false;
   return LOBPCG_OK;
@@ -778,6 +762,7 @@ int lobpcg_set_operator_kronsum(lobpcg_t h, int64_t na, const double* A, const d
   h->na = na;
   h->Vpot = V;
   h->diag_ready = false;
+  h->lfeat_ready = false;
   h->op32_ready = false;
   h->have_result = false;
   return LOBPCG_OK;
@@ -786,11 +771,28 @@ int lobpcg_set_operator_kronsum(lobpcg_t h, int64_t na, const double* A, const d
 int lobpcg_set_preconditioner(lobpcg_t h, int kind, const double* diag) {
   if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
   if (kind != LOBPCG_PRECOND_NONE && kind != LOBPCG_PRECOND_DIAG &&
-      kind != LOBPCG_PRECOND_DIAG_SIGNED)
+      kind != LOBPCG_PRECOND_DIAG_SIGNED && kind != LOBPCG_PRECOND_LEARNED)
     return h->fail(LOBPCG_ERR_UNSUPPORTED, "preconditioner kind not available");
   h->pkind = kind;
   h->user_diag = diag;
   h->diag_ready = false;
+  h->lfeat_ready = false;
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_learned_weights(lobpcg_t h, const float* w, int64_t count) {
+  GUARD(h);
+  if (w == nullptr || count != kMlpParams)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "learned weights: need LOBPCG_LEARNED_NPARAMS floats");
+  if (h->lweights == nullptr) {
+    hipError_t e = hipMalloc(&h->lweights, sizeof(float) * kMlpParams);
+    if (e != hipSuccess) {
+      h->lweights = nullptr;
+      return h->hip_fail(e, "hipMalloc(weights)");
+    }
+  }
+  hipError_t e = hipMemcpy(h->lweights, w, sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return h->hip_fail(e, "hipMemcpy(weights)");
   return LOBPCG_OK;
 }
 
@@ -870,6 +872,24 @@ static int need_ws(lobpcg_t h) {
   if (h->ws == nullptr) return h->fail(LOBPCG_ERR_WORKSPACE, "no workspace set");
   const int m = h->lay_block > 0 ? h->lay_block : (h->block > 0 ? h->block : 1);
   return h->ensure_layout(m);
+}
+
+int lobpcg_learned_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const double* theta,
+                         const int* mask) {
+  GUARD(h);
+  if (R == nullptr || theta == nullptr || nact < 1 || nact > 64 || ldr < nact)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad learned_apply arguments");
+  if (h->lweights == nullptr) return h->fail(LOBPCG_ERR_BAD_STATE, "no learned weights set");
+  if (h->op == kOpNone) return h->fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+  int rc = need_ws(h);
+  if (rc) return rc;
+  rc = h->ensure_learned_features();
+  if (rc) return rc;
+  hipError_t e = mlp_apply_f64(R, ldr, nact, h->n, theta, h->dptr(h->lay.diag),
+                               h->dptr(h->lay.rho), h->small_ptr<double>(h->lay.lscale),
+                               h->lweights, mask, nullptr, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "learned apply");
+  return LOBPCG_OK;
 }
 
 int lobpcg_gram(lobpcg_t h, const double* A, int64_t lda, int p, const double* B, int64_t ldb,

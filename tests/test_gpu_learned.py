@@ -1,0 +1,246 @@
+"""GPU parity of the learned preconditioner against its CPU fp64 oracle
+(oracle/mlp_oracle.py), through the C ABI.
+
+Bars: the learned column (fp32 MLP, fp64 epilogue) within 1e-4 relative of
+the oracle per entry (the net runs in fp32: features and activations carry
+about 1e-6 relative error, amplified at most by c^2 / q <= 1 in w); the
+training loss within 1e-5 relative and its gradient within 1e-4 relative in
+norm (fp32 products, fp64 accumulation across tiles); the MINRES corrections'
+decreases within 1e-6 relative of scipy's MINRES on the same projected
+systems solved to 1e-12.  Solves with the learned preconditioner are judged
+on their eigenpairs, like any other preconditioner.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lobpcg_oracle as O
+from oracle import mlp_oracle as M
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_06668_amd as P
+
+    return P
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def f32_params(seed, out_bias=-1.0, w3_scale=10.0):
+    """Oracle parameters rounded to fp32 (what the GPU holds)."""
+    p = M.init_params(seed, out_bias=out_bias)
+    p.W3 *= w3_scale
+    w = p.flat().astype(np.float32)
+    return w, M.Params.from_flat(w.astype(np.float64))
+
+
+def family_problem(n=3000, idx=3, seed=11, m=6):
+    C, _ = synth.csr_family(idx, n=n, band=400)
+    A = O.csr_operator(C.row_ptr, C.col, C.val, n)
+    import scipy.sparse as sp
+
+    As = sp.csr_matrix((C.val, C.col, C.row_ptr), shape=(n, n))
+    rho = np.asarray(abs(As).sum(1)).ravel() - np.abs(C.diag)
+    # an orthonormal Ritz block after a few oracle iterations
+    X0 = synth.start_block(n, m, seed)
+    r = O.lobpcg(A, X0, m, 1e-8, diag=C.diag, max_iter=3)
+    X = r.X_all
+    return C, As, X, rho
+
+
+def solver_for(P, C, block):
+    s = P.Solver(C.n)
+    s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val))
+    s.ensure_workspace(block)
+    return s
+
+
+def test_learned_apply_matches_oracle(P):
+    C, As, X, rho = family_problem()
+    n, m = X.shape
+    d = C.diag
+    s_ = M.scale_of(d)
+    w32, p = f32_params(5)
+    s = solver_for(P, C, m)
+    s.set_learned_weights(w32)
+    g = synth.rng(7)
+    R = g.standard_normal((n, m))
+    theta = np.sort(d)[[0, 3, 10, 50, 200, 999]] + np.array([0.0, 1e-3, -2e-3, 0.1, 0.0, 5.0])
+    theta[4] = d[17]  # an exact hit of a diagonal entry: the guard floor
+    mask = np.array([0, 1, 0, 0, 1, 0], dtype=np.int32)
+    Rd = cu(R)
+    P.lobpcg_learned_apply(s.h, Rd, cu(theta), cu(mask))
+    Wg = Rd.cpu().numpy()
+    for j in range(m):
+        if mask[j]:
+            ref = O.precondition_diag(R[:, [j]], d, theta[[j]])[:, 0]
+            assert np.allclose(Wg[:, j], ref, rtol=1e-14, atol=0), j
+        else:
+            ref, _ = M.precondition(p, R[:, j], d, theta[j], rho, s_)
+            err = np.abs(Wg[:, j] - ref) / np.abs(ref)
+            say(f"col {j}: max rel err {err.max():.2e}")
+            assert err.max() <= 1e-4, j
+
+
+def test_learned_apply_nonfinite_weights_fall_back(P):
+    C, As, X, rho = family_problem(n=1200)
+    n, m = X.shape
+    w32, _ = f32_params(5)
+    w32[M.n_params() - 1] = np.nan
+    s = solver_for(P, C, m)
+    s.set_learned_weights(w32)
+    R = synth.rng(8).standard_normal((n, 4))
+    theta = np.sort(C.diag)[:4] + 1e-3
+    Rd = cu(R)
+    P.lobpcg_learned_apply(s.h, Rd, cu(theta))
+    ref = O.precondition_diag(R, C.diag, theta)
+    assert np.allclose(Rd.cpu().numpy(), ref, rtol=1e-14, atol=0)
+
+
+def test_learner_objective_and_gradient_match_oracle(P):
+    C, As, X, rho = family_problem()
+    n, m = X.shape
+    s = solver_for(P, C, m)
+    L = P.lobpcg_learner_create(0, 3)
+    try:
+        w32, p = f32_params(9)
+        P.lobpcg_learner_set_weights(L, w32)
+        snap = P.lobpcg_learner_add_snapshot(L, s.h, cu(X), minres_maxiter=50, minres_rtol=1e-6)
+        info = P.lobpcg_learner_snapshot_info(L, snap, m)
+        th = np.einsum("ij,ij->j", X, As @ X)
+        assert np.allclose(info["theta"], th, rtol=1e-13)
+        R = As @ X - X * th
+        assert np.allclose(info["resnorm"], np.linalg.norm(R, axis=0), rtol=1e-10)
+        cols = [0, 2, 5]
+        out = P.lobpcg_learner_objective(L, snap, cols, want_grad=True, want_decreases=True)
+        ref = info["ref_decrease"][cols]
+        Lo, go = M.objective(p, As, X, R, th, cols, C.diag, rho, M.scale_of(C.diag), ref=ref)
+        gg = out["grad"]
+        rel_l = abs(out["loss"] - Lo) / abs(Lo)
+        rel_g = np.linalg.norm(gg - go) / np.linalg.norm(go)
+        say(f"loss gpu {out['loss']:.10f} oracle {Lo:.10f} rel {rel_l:.2e}; grad rel {rel_g:.2e}")
+        assert rel_l <= 1e-5
+        assert rel_g <= 1e-4
+        # per-block agreement (every layer's gradient, not only the dominant one)
+        gp, op = M.Params.from_flat(gg), M.Params.from_flat(go)
+        for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            a, b = getattr(gp, name), getattr(op, name)
+            assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b) + 1e-12 * np.linalg.norm(go), name
+        # decreases: learned and Jacobi, against the oracle's definition
+        for k, j in enumerate(cols):
+            w, _ = M.precondition(p, R[:, j], C.diag, th[j], rho, M.scale_of(C.diag))
+            Dl = M.decrease(As, X, X[:, j], R[:, j], th[j], w)
+            wj = O.precondition_diag(R[:, [j]], C.diag, th[[j]])[:, 0]
+            Dj = M.decrease(As, X, X[:, j], R[:, j], th[j], wj)
+            assert abs(out["learned_decrease"][k] - Dl) <= 1e-4 * Dl
+            assert abs(out["jacobi_decrease"][k] - Dj) <= 1e-9 * Dj
+    finally:
+        P.lobpcg_learner_destroy(L)
+
+
+def test_minres_corrections_match_oracle(P):
+    # a Ritz block near the lowest eigenvectors: the projected systems are
+    # then well enough conditioned for MINRES to reach 1e-10 in a few hundred
+    # steps (from a random block theta sits mid-spectrum and it needs > 700)
+    n, m = 500, 4
+    A = synth.dense_dd(n, seed=12)
+    V = np.linalg.eigh(A)[1]
+    Xb = np.linalg.qr(V[:, :m] + 1e-2 * synth.rng(13).standard_normal((n, m)))[0]
+    th0, U = np.linalg.eigh(Xb.T @ A @ Xb)
+    X = Xb @ U
+    s = P.Solver(n)
+    s.set_operator_dense(cu(A))
+    s.ensure_workspace(m)
+    L = P.lobpcg_learner_create(0, 1)
+    try:
+        snap = P.lobpcg_learner_add_snapshot(L, s.h, cu(X), minres_maxiter=600, minres_rtol=1e-10)
+        info = P.lobpcg_learner_snapshot_info(L, snap, m)
+        th = np.einsum("ij,ij->j", X, A @ X)
+        R = A @ X - X * th
+        T = M.jd_targets(A, X, th, R, rtol=1e-12, maxiter=2000)
+        say("minres relres", info["minres_relres"])
+        assert np.all(info["minres_relres"] <= 1e-10)
+        for j in range(m):
+            D = M.decrease(A, X, X[:, j], R[:, j], th[j], T[:, j])
+            assert abs(info["ref_decrease"][j] - D) <= 1e-6 * D, (j, info["ref_decrease"][j], D)
+    finally:
+        P.lobpcg_learner_destroy(L)
+
+
+def test_training_lowers_loss(P):
+    C, As, X, rho = family_problem(n=4000, m=8)
+    s = solver_for(P, C, 8)
+    L = P.lobpcg_learner_create(0, 4)
+    try:
+        for it in (2, 6):
+            Xs = O.lobpcg(O.csr_operator(C.row_ptr, C.col, C.val, C.n), synth.start_block(C.n, 8, it), 8, 1e-8,
+                          diag=C.diag, max_iter=it).X_all
+            P.lobpcg_learner_add_snapshot(L, s.h, cu(Xs), minres_maxiter=60)
+        first, last = P.lobpcg_learner_train(L, 120, 4, 3e-3, seed=2)
+        say(f"training loss {first:.4f} -> {last:.4f}")
+        assert np.isfinite(first) and np.isfinite(last)
+        assert last < first
+    finally:
+        P.lobpcg_learner_destroy(L)
+
+
+def _eig_ref(A, k):
+    w, V = np.linalg.eigh(A)
+    return w, V[:, :k]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_learned_solve_eigenpairs(P, precision):
+    n, k = 1500, 6
+    A = synth.dense_dd(n, seed=21)
+    w_all, V = _eig_ref(A, k)
+    X0 = synth.start_block(n, k, 22)
+    w32, _ = f32_params(3, out_bias=-2.0, w3_scale=1.0)
+    s = P.Solver(n)
+    s.set_operator_dense(cu(A))
+    s.set_learned_weights(w32)
+    s.set_preconditioner(P.PRECOND_LEARNED)
+    if precision == "mixed":
+        s.set_option(P.OPT_PRECISION, P.PREC_FP32)
+    s.set_initial_guess(cu(X0))
+    res = s.solve(k, 1e-8)
+    say(precision, res.stats["iterations"], res.stats["learned_fallbacks"], res.resnorms.max())
+    assert res.status == 0
+    X = res.evecs.cpu().numpy()
+    AX = A @ X
+    th = np.einsum("ij,ij->j", X, AX)
+    assert np.all(np.linalg.norm(AX - X * th, axis=0) <= 1e-8 * 1.0001)
+    assert np.all(np.abs(res.evals - w_all[:k]) <= 1e-9 * np.maximum(np.abs(w_all[:k]), 1e-3 * 101))
+    assert np.abs(X.T @ X - np.eye(k)).max() < 1e-12
+
+
+def test_learned_solve_with_nan_weights_still_converges(P):
+    n, k = 1200, 4
+    C = synth.csr_banded(n=n, band=200, seed=31)
+    X0 = synth.start_block(n, k, 32)
+    w32, _ = f32_params(3)
+    w32[:] = np.nan
+    s = P.Solver(n)
+    s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val))
+    s.set_learned_weights(w32)
+    s.set_preconditioner(P.PRECOND_LEARNED)
+    s.set_initial_guess(cu(X0))
+    res = s.solve(k, 1e-8)
+    say("nan weights:", res.stats["iterations"], res.stats["learned_nonfinite"])
+    assert res.status == 0
+    assert res.stats["learned_nonfinite"] > 0
+    op = O.csr_operator(C.row_ptr, C.col, C.val, n)
+    ref = O.lobpcg(op, X0, k, 1e-8, diag=C.diag)
+    assert np.all(np.abs(res.evals - ref.evals) <= 1e-9 * np.abs(ref.evals))

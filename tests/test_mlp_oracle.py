@@ -159,3 +159,16 @@ def test_jd_targets_solve_projected_system():
     t_ref = Q @ np.linalg.solve(Q.T @ (A - th * np.eye(n)) @ Q, -(Q.T @ r))
     assert abs(T[:, 0] @ x) < 1e-10
     assert np.allclose(T[:, 0], t_ref, atol=1e-7 * np.abs(t_ref).max())
+
+
+def test_decrease_formula_has_no_cancellation():
+    # Delta = sqrt(h^2 + b^2) - h: for b << h it is b^2 / (2h) to first order
+    # (the smaller root of the 2 x 2 problem), never 0 for b != 0
+    for h, b in [(1.0, 1e-9), (3.0, 1e-12), (1e3, 1e-5)]:
+        D, S = M._delta(h, b)
+        assert D > 0.0
+        assert abs(D - b * b / (2 * h)) <= 1e-6 * b * b / (2 * h)
+    for h, b in [(-2.0, 0.5), (0.3, 0.4), (0.0, 1.0)]:
+        D, S = M._delta(h, b)
+        lam = np.linalg.eigvalsh(np.array([[0.0, b], [b, 2 * h]]))[0]
+        assert abs(D - (0.0 - lam)) <= 1e-14 * max(1.0, abs(lam))
