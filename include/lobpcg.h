@@ -72,6 +72,9 @@ typedef struct lobpcg_ctx* lobpcg_t;
 #define LOBPCG_OPT_ORTHO_MAX_PASSES 3 /* Alg. 2 overlap evaluations, default 6 */
 #define LOBPCG_OPT_ORTHO_Y_MAX_PASSES 4 /* Alg. 3 passes, default 4 */
 #define LOBPCG_OPT_TRACE 5            /* 1: time phases with HIP events */
+#define LOBPCG_OPT_LEARNED_BF16 6     /* learned preconditioner inference: 1 (default)
+                                         = hidden layer on bf16 MFMA with fp32
+                                         accumulation, 0 = fp32 throughout */
 
 /* ---- statistics --------------------------------------------------------- */
 typedef struct lobpcg_stats {
@@ -260,7 +263,7 @@ int lobpcg_rotate(lobpcg_t h, const double* V, const double* AV, int64_t ldv, in
                   double* AVout, int64_t ldo, double* resnorm2);
 
 /* The learned preconditioner's transform (see lobpcg_set_learned_weights) on
- * caller buffers: R (device n x nact, ldr) is replaced in place by the
+ * caller buffers, in the precision LOBPCG_OPT_LEARNED_BF16 selects: R (device n x nact, ldr) is replaced in place by the
  * learned columns for the Ritz values theta (device, nact); mask (device,
  * nact ints, may be NULL): nonzero selects the Jacobi step for that column.
  * Needs weights and the operator.  1 <= nact <= 64.  Asynchronous. */

@@ -53,6 +53,7 @@ OPT_PRECISION = 2
 OPT_ORTHO_MAX_PASSES = 3
 OPT_ORTHO_Y_MAX_PASSES = 4
 OPT_TRACE = 5
+OPT_LEARNED_BF16 = 6
 
 _i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 

@@ -181,6 +181,14 @@ hipError_t mlp_apply_f64(double* R, int64_t ld, int nact, int64_t n, const doubl
 hipError_t mlp_apply_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
                          const double* diag, const double* rho, const double* s, const float* w,
                          const int* mask, int* flags, hipStream_t st);
+// The same transform with layer 2 on bf16 MFMA (fp32 accumulate): the
+// solver's inference path.
+hipError_t mlp_apply_bf16_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
+                              const double* diag, const double* rho, const double* s,
+                              const float* w, const int* mask, int* flags, hipStream_t st);
+hipError_t mlp_apply_bf16_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
+                              const double* diag, const double* rho, const double* s,
+                              const float* w, const int* mask, int* flags, hipStream_t st);
 // grad (kMlpParams doubles) = d/dweights of sum_e G_e w_e(weights), with w
 // the learned columns of R; part needs kMlpBlocks * kMlpParams doubles.
 hipError_t mlp_grad(const double* R, const double* G, int64_t ld, int nact, int64_t n,

@@ -429,6 +429,128 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const double* __restrict__ R,
   if (tid == 0) out[oB3] = aB3;
 }
 
+// Inference with layer 2 on bf16 MFMA (v_mfma_f32_16x16x32_bf16, fp32
+// accumulate); layers 1 and 3, the features and the epilogue stay fp32 /
+// fp64.  One wave computes 32 entries (two 16-row M tiles) against all 128
+// neurons (eight 16-column N tiles); the B fragments of W2^T (8 x 4 x 8 bf16
+// per lane) are read from LDS (W2 as bf16, rows padded to 136 values) once
+// per K step and shared by both M tiles.  Lane (g = lane / 16,
+// r = lane % 16) evaluates layer 1 for entry r of each M tile at the hidden
+// units 32 ks + 8 g + [0, 8) -- exactly its A fragments, so every h1 value is
+// computed once.  The accumulator row of lane (g, r), element i, is entry
+// 4 g + i and its column is neuron r of the N tile; layer 3 sums over the
+// 16 lanes of a segment with xor shuffles.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float silu_fast(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64_t ld, int nact,
+                                                        int64_t n,
+                                                        const double* __restrict__ theta,
+                                                        const double* __restrict__ diag,
+                                                        const double* __restrict__ rho,
+                                                        const double* __restrict__ sptr,
+                                                        const float* __restrict__ wts,
+                                                        const int* __restrict__ mask,
+                                                        int* __restrict__ flags) {
+  constexpr int kBS = kH + 8;  // padded row stride of the bf16 W2 copy
+  __shared__ float4 w1s[kH];  // (W1[k][0..2], b1[k])
+  __shared__ __attribute__((aligned(16))) __bf16 w2s[kH * kBS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  for (int k = threadIdx.x; k < kH; k += blockDim.x)
+    w1s[k] = make_float4(wts[oW1 + 3 * k], wts[oW1 + 3 * k + 1], wts[oW1 + 3 * k + 2], wts[oB1 + k]);
+  for (int idx = threadIdx.x; idx < kH * kH; idx += blockDim.x)
+    w2s[(idx / kH) * kBS + (idx % kH)] = (__bf16)wts[oW2 + idx];
+  float b2r[8], w3r[8];
+#pragma unroll
+  for (int nt = 0; nt < 8; ++nt) {
+    b2r[nt] = wts[oB2 + 16 * nt + r];
+    w3r[nt] = wts[oW3 + 16 * nt + r];
+  }
+  const float b3 = wts[oB3];
+  const double s = *sptr;
+  __syncthreads();
+  const int64_t total = n * nact;
+  const int64_t nwt = (total + 31) / 32;
+  for (int64_t wt = (int64_t)blockIdx.x * 4 + wave; wt < nwt; wt += (int64_t)gridDim.x * 4) {
+    // keep the weight reads inside the loop (LDS re-reads are cheap; holding
+    // every fragment in registers for the whole kernel would cap occupancy)
+    asm volatile("" ::: "memory");
+    float ph[2][3];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int64_t ent = wt * 32 + 16 * t + r;
+      ph[t][0] = ph[t][1] = ph[t][2] = 0.0f;
+      if (ent < total) {
+        const int64_t row = ent / nact;
+        const int col = (int)(ent - row * nact);
+        const double th = theta[col];
+        ph[t][0] = (float)log(fabs(diag[row] - th) / s + 1e-6);
+        ph[t][1] = (float)(th / s);
+        ph[t][2] = (float)log(rho[row] / s + 1e-6);
+      }
+    }
+    f32x4 acc[2][8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int nt = 0; nt < 8; ++nt) acc[t][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      bf16x8 bq[8];
+#pragma unroll
+      for (int nt = 0; nt < 8; ++nt)
+        bq[nt] = *reinterpret_cast<const bf16x8*>(w2s + (16 * nt + r) * kBS + 32 * ks + 8 * g);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        bf16x8 a;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float4 w = w1s[32 * ks + 8 * g + j];
+          const float z = w.w + w.x * ph[t][0] + w.y * ph[t][1] + w.z * ph[t][2];
+          a[j] = (__bf16)silu_fast(z);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt)
+          acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[nt], acc[t][nt], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int nt = 0; nt < 8; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] = fmaf(w3r[nt], silu_fast(acc[t][nt][i] + b2r[nt]), y[i]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) y[i] += __shfl_xor(y[i], off, 16);
+      if (r < 4) {
+        const int64_t ent = wt * 32 + 16 * t + 4 * g + r;
+        if (ent < total) {
+          const float yv = b3 + (r == 0 ? y[0] : r == 1 ? y[1] : r == 2 ? y[2] : y[3]);
+          EntryIn in{};
+          in.valid = true;
+          in.row = ent / nact;
+          in.col = (int)(ent - in.row * nact);
+          in.theta = theta[in.col];
+          in.dm = diag[in.row] - in.theta;
+          const bool jac = mask != nullptr && mask[in.col] != 0;
+          const EntryOut o = regularise(in, yv, s, jac, flags);
+          T* p = R + in.row * ld + in.col;
+          *p = (T)((double)*p / sqrt(o.q));
+        }
+      }
+    }
+  }
+}
+
 __global__ void k_grad_reduce(const double* __restrict__ part, int nblk, double* __restrict__ g) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= kMlpParams) return;
@@ -516,6 +638,29 @@ int mlp_grid(int64_t total) {
 }
 
 }  // namespace
+
+template <typename T>
+static hipError_t mlp_apply_bf16_t(T* R, int64_t ld, int nact, int64_t n, const double* theta,
+                                   const double* diag, const double* rho, const double* s,
+                                   const float* w, const int* mask, int* flags, hipStream_t st) {
+  if (n <= 0 || nact <= 0) return hipSuccess;
+  const int64_t nwt = (n * nact + 31) / 32;
+  const int grid = (int)std::min<int64_t>((nwt + 3) / 4, 1024);
+  hipLaunchKernelGGL(k_mlp_apply_bf16<T>, dim3(grid), dim3(256), 0, st, R, ld, nact, n, theta,
+                     diag, rho, s, w, mask, flags);
+  return hipGetLastError();
+}
+
+hipError_t mlp_apply_bf16_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
+                              const double* diag, const double* rho, const double* s,
+                              const float* w, const int* mask, int* flags, hipStream_t st) {
+  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+}
+hipError_t mlp_apply_bf16_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
+                              const double* diag, const double* rho, const double* s,
+                              const float* w, const int* mask, int* flags, hipStream_t st) {
+  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+}
 
 template <typename T>
 static hipError_t mlp_apply_t(T* R, int64_t ld, int nact, int64_t n, const double* theta,

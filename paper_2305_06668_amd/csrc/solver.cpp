@@ -214,15 +214,19 @@ static hipError_t gram_t(const float* A, int64_t lda, int p, const float* B, int
                          int64_t n, double* part, double* C, const int* skip, hipStream_t s) {
   return gram_f32(A, lda, p, B, ldb, q, n, part, C, skip, s);
 }
-static hipError_t mlp_apply_t(double* R, int64_t ld, int nact, int64_t n, const double* theta,
-                              const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, hipStream_t st) {
-  return mlp_apply_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+static hipError_t mlp_apply_t(bool bf16, double* R, int64_t ld, int nact, int64_t n,
+                              const double* theta, const double* diag, const double* rho,
+                              const double* s, const float* w, const int* mask, int* flags,
+                              hipStream_t st) {
+  return bf16 ? mlp_apply_bf16_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st)
+              : mlp_apply_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
 }
-static hipError_t mlp_apply_t(float* R, int64_t ld, int nact, int64_t n, const double* theta,
-                              const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, hipStream_t st) {
-  return mlp_apply_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+static hipError_t mlp_apply_t(bool bf16, float* R, int64_t ld, int nact, int64_t n,
+                              const double* theta, const double* diag, const double* rho,
+                              const double* s, const float* w, const int* mask, int* flags,
+                              hipStream_t st) {
+  return bf16 ? mlp_apply_bf16_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st)
+              : mlp_apply_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
 }
 static hipError_t rotate_t(const double* V, const double* AV, double* Vo, double* AVo,
                            const RotateArgs& a, hipStream_t s) {
@@ -523,8 +527,9 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       }
       HIPCHK(hipMemcpyAsync(lmask, hmask, sizeof(int) * nact, hipMemcpyHostToDevice, stream));
       HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
-      HIPCHK(mlp_apply_t(V[1 - c] + q, ldo, nact, n, theta + a0, dptr(lay.diag), dptr(lay.rho),
-                         small_ptr<double>(lay.lscale), lweights, lmask, lflags, stream));
+      HIPCHK(mlp_apply_t(learned_bf16 != 0, V[1 - c] + q, ldo, nact, n, theta + a0,
+                         dptr(lay.diag), dptr(lay.rho), small_ptr<double>(lay.lscale), lweights,
+                         lmask, lflags, stream));
       prev_a0 = a0;
       prev_nact = nact;
     }
@@ -679,6 +684,9 @@ int lobpcg_set_option(lobpcg_t h, int key, double v) {
       return LOBPCG_OK;
     case LOBPCG_OPT_TRACE:
       h->trace = (v != 0.0);
+      return LOBPCG_OK;
+    case LOBPCG_OPT_LEARNED_BF16:
+      h->learned_bf16 = (v != 0.0);
       return LOBPCG_OK;
     default: return h->fail(LOBPCG_ERR_INVALID_ARG, "unknown option");
   }
@@ -885,9 +893,10 @@ int lobpcg_learned_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const dou
   if (rc) return rc;
   rc = h->ensure_learned_features();
   if (rc) return rc;
-  hipError_t e = mlp_apply_f64(R, ldr, nact, h->n, theta, h->dptr(h->lay.diag),
-                               h->dptr(h->lay.rho), h->small_ptr<double>(h->lay.lscale),
-                               h->lweights, mask, nullptr, h->stream);
+  hipError_t e = mlp_apply_t(h->learned_bf16 != 0, R, ldr, nact, h->n, theta,
+                             h->dptr(h->lay.diag), h->dptr(h->lay.rho),
+                             h->small_ptr<double>(h->lay.lscale), h->lweights, mask, nullptr,
+                             h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "learned apply");
   return LOBPCG_OK;
 }

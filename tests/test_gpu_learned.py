@@ -75,6 +75,7 @@ def test_learned_apply_matches_oracle(P):
     w32, p = f32_params(5)
     s = solver_for(P, C, m)
     s.set_learned_weights(w32)
+    s.set_option(P.OPT_LEARNED_BF16, 0)
     g = synth.rng(7)
     R = g.standard_normal((n, m))
     theta = np.sort(d)[[0, 3, 10, 50, 200, 999]] + np.array([0.0, 1e-3, -2e-3, 0.1, 0.0, 5.0])
@@ -92,6 +93,32 @@ def test_learned_apply_matches_oracle(P):
             err = np.abs(Wg[:, j] - ref) / np.abs(ref)
             say(f"col {j}: max rel err {err.max():.2e}")
             assert err.max() <= 1e-4, j
+
+
+@pytest.mark.parametrize("n", [3000, 1777])
+def test_learned_apply_bf16_matches_oracle(P, n):
+    # the solver's inference path: layer 2 on bf16 MFMA.  bf16 rounding of
+    # h1 and W2 (2^-9 relative) moves y by O(1e-3 |y|); w moves by at most the
+    # relative change of c, so entries agree to 3e-2 and typically to 1e-3
+    C, As, X, rho = family_problem(n=n)
+    d = C.diag
+    m = 5
+    w32, p = f32_params(5)
+    s = solver_for(P, C, 6)
+    s.set_learned_weights(w32)
+    R = synth.rng(17).standard_normal((n, m))
+    theta = np.sort(d)[[0, 2, 9, 40, 300]] + np.array([0.0, 1e-3, -2e-3, 0.1, 0.0])
+    Rd = cu(R)
+    P.lobpcg_learned_apply(s.h, Rd, cu(theta))
+    Wg = Rd.cpu().numpy()
+    errs = []
+    for j in range(m):
+        ref, _ = M.precondition(p, R[:, j], d, theta[j], rho, M.scale_of(d))
+        errs.append(np.abs(Wg[:, j] - ref) / np.abs(ref))
+    errs = np.concatenate(errs)
+    say(f"bf16 apply: max rel err {errs.max():.2e}, median {np.median(errs):.2e}")
+    assert errs.max() <= 3e-2
+    assert np.median(errs) <= 2e-3
 
 
 def test_learned_apply_nonfinite_weights_fall_back(P):
