@@ -15,6 +15,7 @@ LIB = os.path.join(HERE, "liblobpcg.so")
 SOURCES = [
     "k_blas.hip",
     "k_op.hip",
+    "k_spmm.hip",
     "k_kron.hip",
     "k_small.hip",
     "k_mlp.hip",

@@ -474,6 +474,7 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
   }
   const float b3 = wts[oB3];
   const double s = *sptr;
+  const double inv_s = 1.0 / s;
   __syncthreads();
   const int64_t total = n * nact;
   const int64_t nwt = (total + 31) / 32;
@@ -481,19 +482,27 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
     // keep the weight reads inside the loop (LDS re-reads are cheap; holding
     // every fragment in registers for the whole kernel would cap occupancy)
     asm volatile("" ::: "memory");
-    float ph[2][3];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int64_t ent = wt * 32 + 16 * t + r;
-      ph[t][0] = ph[t][1] = ph[t][2] = 0.0f;
-      if (ent < total) {
+    // features: lane l < 32 evaluates entry l of the tile once (fp32 logs of
+    // the fp64 difference d - theta); the four lanes that hold an entry's A
+    // rows read them with shuffles
+    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+    {
+      const int64_t ent = wt * 32 + (lane & 31);
+      if (lane < 32 && ent < total) {
         const int64_t row = ent / nact;
         const int col = (int)(ent - row * nact);
         const double th = theta[col];
-        ph[t][0] = (float)log(fabs(diag[row] - th) / s + 1e-6);
-        ph[t][1] = (float)(th / s);
-        ph[t][2] = (float)log(rho[row] / s + 1e-6);
+        f0 = __logf((float)(fabs(diag[row] - th) * inv_s) + 1e-6f);
+        f1 = (float)(th * inv_s);
+        f2 = __logf((float)(rho[row] * inv_s) + 1e-6f);
       }
+    }
+    float ph[2][3];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      ph[t][0] = __shfl(f0, 16 * t + r, 64);
+      ph[t][1] = __shfl(f1, 16 * t + r, 64);
+      ph[t][2] = __shfl(f2, 16 * t + r, 64);
     }
     f32x4 acc[2][8];
 #pragma unroll
@@ -520,32 +529,53 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
           acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[nt], acc[t][nt], 0, 0, 0);
       }
     }
+    // layer 3: y of entry 16 t + 4 g + i, summed over the 16 lanes of segment g
+    float y[2][4];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) y[t][i] = 0.0f;
 #pragma unroll
       for (int nt = 0; nt < 8; ++nt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) y[i] = fmaf(w3r[nt], silu_fast(acc[t][nt][i] + b2r[nt]), y[i]);
+        for (int i = 0; i < 4; ++i)
+          y[t][i] = fmaf(w3r[nt], silu_fast(acc[t][nt][i] + b2r[nt]), y[t][i]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) y[i] += __shfl_xor(y[i], off, 16);
-      if (r < 4) {
-        const int64_t ent = wt * 32 + 16 * t + 4 * g + r;
-        if (ent < total) {
-          const float yv = b3 + (r == 0 ? y[0] : r == 1 ? y[1] : r == 2 ? y[2] : y[3]);
-          EntryIn in{};
-          in.valid = true;
-          in.row = ent / nact;
-          in.col = (int)(ent - in.row * nact);
-          in.theta = theta[in.col];
-          in.dm = diag[in.row] - in.theta;
-          const bool jac = mask != nullptr && mask[in.col] != 0;
-          const EntryOut o = regularise(in, yv, s, jac, flags);
-          T* p = R + in.row * ld + in.col;
-          *p = (T)((double)*p / sqrt(o.q));
+        for (int off = 8; off >= 1; off >>= 1) y[t][i] += __shfl_xor(y[t][i], off, 16);
+    }
+    // epilogue on 32 lanes: lane L < 32 finishes entry L of the tile (its y
+    // sits in segment (L % 16) / 4, slot (t = L / 16, i = L % 4))
+    {
+      const int src = 16 * ((lane & 15) >> 2);
+      float yv = 0.0f;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float v = __shfl(y[t][i], src, 64);
+          if ((lane >> 4) == t && (lane & 3) == i) yv = v;
         }
+      const int64_t ent = wt * 32 + lane;
+      if (lane < 32 && ent < total) {
+        const int64_t row = ent / nact;
+        const int col = (int)(ent - row * nact);
+        const double th = theta[col];
+        const float dm = (float)(diag[row] - th);
+        yv += b3;
+        bool jac = mask != nullptr && mask[col] != 0;
+        // c = s softplus(y), fp32 (the net itself ran in bf16)
+        const float cf = (float)s * (fmaxf(yv, 0.0f) + __logf(1.0f + __expf(-fabsf(yv))));
+        if (!jac && !isfinite(cf)) {
+          if (flags) flags[col] = 1;
+          jac = true;
+        }
+        const float c = jac ? 0.0f : cf;
+        const float delta = (float)(kPrecondGuard * fmax(1.0, fabs(th)));
+        const float q = fmaxf(dm * dm + c * c, delta * delta);
+        T* p = R + row * ld + col;
+        *p = (T)((double)*p * (double)__frsqrt_rn(q));
       }
     }
   }

@@ -4,7 +4,9 @@ Every computation runs in the HIP library: the solver produces Ritz blocks
 (solves stopped early at the given iteration counts), the learner turns each
 into a snapshot (residuals, near-exact Jacobi-Davidson corrections by block
 MINRES) and trains the MLP with its own forward, backward and Adam kernels.
-This module only sequences those calls.
+This module only sequences those calls, and keeps the weights that did best
+on a caller-supplied validation solve (the objective is a one-step decrease,
+so its value is a noisy guide to the iteration count of whole solves).
 """
 from __future__ import annotations
 
@@ -35,24 +37,32 @@ class TrainReport:
     seconds_train: float
     minres_relres_max: float
     log: list = field(default_factory=list)
+    best_chunk: int = -1
+    best_score: float = float("nan")
 
 
 def train(
     solvers,
     block: int,
-    snapshot_iters=(2, 5, 10, 20, 40),
+    snapshot_iters=(1, 3, 8, 20, 50),
     minres_maxiter: int = 100,
     minres_rtol: float = 1e-6,
-    steps: int = 400,
+    steps: int = 300,
     cols_per_step: int = 8,
-    lr: float = 3e-3,
+    lr: float = 1e-3,
     seed: int = 1,
     device: int = 0,
+    chunks: int = 1,
+    validate=None,
 ) -> TrainReport:
     """Train on the operators held by `solvers` (paper_2305_06668_amd.Solver
     objects with an operator, a preconditioner and an initial block of
     `block` columns set).  Each solver is run up to every count in
-    `snapshot_iters` (stopping early) and its Ritz block becomes a snapshot."""
+    `snapshot_iters` (stopping early) and its Ritz block becomes a snapshot.
+
+    The `steps` Adam steps run in `chunks` equal parts; with `validate`
+    (weights -> score, lower is better) the weights after each part are
+    scored and the best are returned."""
     L = lobpcg_learner_create(device, seed)
     lobpcg_learner_set_stream(L)
     log = []
@@ -70,10 +80,20 @@ def train(
                 nsnap += 1
             s.set_option(OPT_MAX_ITER, 1000)
         t1 = time.perf_counter()
-        first, last = lobpcg_learner_train(L, steps, cols_per_step, lr, seed)
+        per = max(1, steps // max(1, chunks))
+        best_w, best_score, best_chunk = None, float("inf"), -1
+        first = last = float("nan")
+        for c in range(max(1, chunks)):
+            a, b = lobpcg_learner_train(L, per, cols_per_step, lr, seed * 1000003 + c)
+            if c == 0:
+                first = a
+            last = b
+            w = lobpcg_learner_get_weights(L)
+            score = float(validate(w)) if validate is not None else float(c)
+            log.append(dict(chunk=c, steps=per * (c + 1), loss_first=a, loss_last=b, score=score))
+            if validate is None or score < best_score:
+                best_w, best_score, best_chunk = w, score, c
         t2 = time.perf_counter()
-        w = lobpcg_learner_get_weights(L)
-        log.append(dict(snapshots=nsnap, loss_first=first, loss_last=last))
-        return TrainReport(w, nsnap, first, last, t1 - t0, t2 - t1, relres, log)
+        return TrainReport(best_w, nsnap, first, last, t1 - t0, t2 - t1, relres, log, best_chunk, best_score)
     finally:
         lobpcg_learner_destroy(L)
