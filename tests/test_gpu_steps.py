@@ -142,17 +142,24 @@ def test_apply_dense(P, n, m):
     assert np.all(np.abs(host(Y) - ref) <= 1e-13 * scale)
 
 
-def test_apply_kronsum(P):
-    na, m = 19, 5
+@pytest.mark.parametrize("na,m,ldw", [(19, 5, 5), (64, 8, 8), (45, 13, 16), (96, 17, 20)])
+def test_apply_kronsum(P, na, m, ldw):
+    # tiles of 32 x 32 x 8 with ragged i/j/column edges and strided blocks
+    say("kronsum", na, m, ldw)
     A, V = synth.kronsum(na=na, seed=4)
-    W = synth.start_block(na * na, m, 1)
+    W = synth.start_block(na * na, ldw, 1)
     s = P.Solver(na * na)
     s.set_operator_kronsum(cu(A), cu(V))
     s.ensure_workspace(1)
-    Y = torch.zeros((na * na, m), dtype=torch.float64, device="cuda")
-    P.lobpcg_apply_operator(s.h, cu(W), Y)
+    Wd = cu(W)
+    Y = torch.full((na * na, ldw), 7.0, dtype=torch.float64, device="cuda")
+    P.lobpcg_apply_operator(s.h, Wd[:, :m], Y[:, :m])
     H = np.kron(A, np.eye(na)) + np.kron(np.eye(na), A) + np.diag(V.reshape(-1))
-    assert np.allclose(host(Y), H @ W, atol=1e-12)
+    ref = H @ W[:, :m]
+    scale = np.abs(H) @ np.abs(W[:, :m])
+    Yh = host(Y)
+    assert np.all(np.abs(Yh[:, :m] - ref) <= 1e-13 * scale + 1e-300)
+    assert np.all(Yh[:, m:] == 7.0)  # columns past ncols untouched
 
 
 @pytest.mark.parametrize("p", [2, 7, 24, 48, 96])
