@@ -441,13 +441,14 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const double* __restrict__ R,
 // 4 g + i and its column is neuron r of the N tile; layer 3 sums over the
 // 16 lanes of a segment with xor shuffles.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kMlpTilesPerWave = 2;  // 16-entry M tiles per wave iteration
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float silu_fast(float z) {
   return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
 }
 
-template <typename T>
+template <typename T, int MT>
 __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64_t ld, int nact,
                                                         int64_t n,
                                                         const double* __restrict__ theta,
@@ -477,18 +478,19 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
   const double inv_s = 1.0 / s;
   __syncthreads();
   const int64_t total = n * nact;
-  const int64_t nwt = (total + 31) / 32;
+  constexpr int E = 16 * MT;  // entries per wave tile
+  const int64_t nwt = (total + E - 1) / E;
   for (int64_t wt = (int64_t)blockIdx.x * 4 + wave; wt < nwt; wt += (int64_t)gridDim.x * 4) {
     // keep the weight reads inside the loop (LDS re-reads are cheap; holding
     // every fragment in registers for the whole kernel would cap occupancy)
     asm volatile("" ::: "memory");
-    // features: lane l < 32 evaluates entry l of the tile once (fp32 logs of
+    // features: lane l < E evaluates entry l of the tile once (fp32 logs of
     // the fp64 difference d - theta); the four lanes that hold an entry's A
     // rows read them with shuffles
     float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
     {
-      const int64_t ent = wt * 32 + (lane & 31);
-      if (lane < 32 && ent < total) {
+      const int64_t ent = wt * E + (lane % E);
+      if (lane < E && ent < total) {
         const int64_t row = ent / nact;
         const int col = (int)(ent - row * nact);
         const double th = theta[col];
@@ -497,16 +499,16 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
         f2 = __logf((float)(rho[row] * inv_s) + 1e-6f);
       }
     }
-    float ph[2][3];
+    float ph[MT][3];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < MT; ++t) {
       ph[t][0] = __shfl(f0, 16 * t + r, 64);
       ph[t][1] = __shfl(f1, 16 * t + r, 64);
       ph[t][2] = __shfl(f2, 16 * t + r, 64);
     }
-    f32x4 acc[2][8];
+    f32x4 acc[MT][8];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int nt = 0; nt < 8; ++nt) acc[t][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -516,7 +518,7 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
       for (int nt = 0; nt < 8; ++nt)
         bq[nt] = *reinterpret_cast<const bf16x8*>(w2s + (16 * nt + r) * kBS + 32 * ks + 8 * g);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < MT; ++t) {
         bf16x8 a;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -530,9 +532,9 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
       }
     }
     // layer 3: y of entry 16 t + 4 g + i, summed over the 16 lanes of segment g
-    float y[2][4];
+    float y[MT][4];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < MT; ++t) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) y[t][i] = 0.0f;
 #pragma unroll
@@ -545,20 +547,20 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
 #pragma unroll
         for (int off = 8; off >= 1; off >>= 1) y[t][i] += __shfl_xor(y[t][i], off, 16);
     }
-    // epilogue on 32 lanes: lane L < 32 finishes entry L of the tile (its y
+    // epilogue on E lanes: lane L < E finishes entry L of the tile (its y
     // sits in segment (L % 16) / 4, slot (t = L / 16, i = L % 4))
     {
       const int src = 16 * ((lane & 15) >> 2);
       float yv = 0.0f;
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+      for (int t = 0; t < MT; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const float v = __shfl(y[t][i], src, 64);
           if ((lane >> 4) == t && (lane & 3) == i) yv = v;
         }
-      const int64_t ent = wt * 32 + lane;
-      if (lane < 32 && ent < total) {
+      const int64_t ent = wt * E + lane;
+      if (lane < E && ent < total) {
         const int64_t row = ent / nact;
         const int col = (int)(ent - row * nact);
         const double th = theta[col];
@@ -674,9 +676,10 @@ static hipError_t mlp_apply_bf16_t(T* R, int64_t ld, int nact, int64_t n, const 
                                    const double* diag, const double* rho, const double* s,
                                    const float* w, const int* mask, int* flags, hipStream_t st) {
   if (n <= 0 || nact <= 0) return hipSuccess;
-  const int64_t nwt = (n * nact + 31) / 32;
+  constexpr int MT = kMlpTilesPerWave;
+  const int64_t nwt = (n * nact + 16 * MT - 1) / (16 * MT);
   const int grid = (int)std::min<int64_t>((nwt + 3) / 4, 1024);
-  hipLaunchKernelGGL(k_mlp_apply_bf16<T>, dim3(grid), dim3(256), 0, st, R, ld, nact, n, theta,
+  hipLaunchKernelGGL((k_mlp_apply_bf16<T, MT>), dim3(grid), dim3(256), 0, st, R, ld, nact, n, theta,
                      diag, rho, s, w, mask, flags);
   return hipGetLastError();
 }

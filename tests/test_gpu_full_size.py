@@ -1,0 +1,135 @@
+"""Parity at the benchmark's full size (CSR, n = 1,000,000, 16 columns), in
+the launch configuration the benchmark times, where the oracle cannot run
+the whole solve in seconds: sampled operator rows and sampled
+learned-preconditioner entries are recomputed one by one on the CPU, and the
+solves are judged by properties that hold at any size -- true residuals
+recomputed on the CPU from the returned vectors, Rayleigh quotients equal to
+the returned eigenvalues, orthonormality, ascending order -- and by the
+agreement of the fp64 and the mixed-precision solves, two different paths
+whose eigenvalues must each lie within r^2 / gap of the true ones.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp_oracle as M
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N = 1_000_000
+K = 16
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_06668_amd as P
+
+    return P
+
+
+@pytest.fixture(scope="module")
+def problem(P):
+    import scipy.sparse as sp
+
+    mseed, xseed = synth.SEEDS["csr_banded"]
+    C = synth.csr_banded(n=N, seed=mseed)
+    A = sp.csr_matrix((C.val, C.col, C.row_ptr), shape=(N, N))
+    X0 = synth.start_block(N, K, xseed)
+    s = P.Solver(N)
+    s.set_operator_csr(*(torch.from_numpy(a).cuda() for a in (C.row_ptr, C.col, C.val)))
+    s.set_preconditioner(P.PRECOND_DIAG)
+    s.set_initial_guess(torch.from_numpy(X0).cuda())
+    return C, A, s
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_spmm_sampled_rows(P, problem):
+    C, A, s = problem
+    W = synth.start_block(N, K, 99)
+    Y = torch.empty((N, K), dtype=torch.float64, device="cuda")
+    P.lobpcg_apply_operator(s.h, torch.from_numpy(W).cuda(), Y)
+    Yh = Y.cpu().numpy()
+    rows = np.concatenate([[0, 1, N - 1, N - 2], synth.rng(5).integers(0, N, 400)])
+    for i in rows:
+        lo, hi = C.row_ptr[i], C.row_ptr[i + 1]
+        ref = C.val[lo:hi] @ W[C.col[lo:hi]]
+        scale = np.abs(C.val[lo:hi]) @ np.abs(W[C.col[lo:hi]])
+        assert np.all(np.abs(Yh[i] - ref) <= 1e-14 * scale + 1e-300), i
+
+
+def _certify(A, res, tol):
+    X = res.evecs.cpu().numpy()
+    AX = A @ X
+    th = np.einsum("ij,ij->j", X, AX)
+    r = np.linalg.norm(AX - X * th, axis=0)
+    assert np.all(r <= tol * 1.0001), r
+    # the fp64 residual of an n = 1e6 product carries ~sqrt(n) eps |A| of
+    # summation-order noise, so tiny residuals agree only to ~1e-12 absolute
+    assert np.allclose(res.resnorms, r, rtol=1e-3, atol=1e-11)
+    assert np.allclose(res.evals, th, rtol=1e-13)
+    assert np.all(np.diff(res.evals) >= -1e-12)
+    G = X.T @ X
+    assert np.abs(G - np.eye(X.shape[1])).max() < 1e-12
+    return X, r
+
+
+def test_full_size_solves_agree(P, problem):
+    C, A, s = problem
+    out = {}
+    for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_FP32)):
+        s.set_option(P.OPT_PRECISION, prec)
+        res = s.solve(K, 1e-8)
+        say(name, res.status, res.stats["iterations"], res.resnorms.max())
+        assert res.status == P.OK
+        X, r = _certify(A, res, 1e-8)
+        out[name] = (res.evals, X, r)
+    s.set_option(P.OPT_PRECISION, P.PREC_FP64)
+    e64, X64, r64 = out["fp64"]
+    e32, X32, r32 = out["mixed"]
+    # both are within their residuals of true eigenvalues; the lowest 16
+    # diagonal entries lie in [1.0013, 1.0046] with gaps down to ~4e-5, so
+    # Kato-Temple gives |theta - lambda| <= r^2 / gap << 1e-9 |lambda|
+    assert np.all(np.abs(e64 - e32) <= 1e-9 * np.abs(e64)), (e64, e32)
+
+
+def test_learned_full_size(P, problem):
+    """The learned transform at full size in the solver's launch
+    configuration (bf16 MFMA) on sampled entries, and a learned + mixed
+    solve certified like the others."""
+    import scipy.sparse as sp
+
+    C, A, s = problem
+    w = M.init_params(11, out_bias=-2.0).flat().astype(np.float32)
+    p = M.Params.from_flat(w.astype(np.float64))
+    s.set_learned_weights(w)
+    s.set_option(P.OPT_LEARNED_BF16, 1)
+    d = C.diag
+    rho = np.asarray(abs(A).sum(1)).ravel() - np.abs(d)
+    sc = M.scale_of(d)
+    R = synth.start_block(N, K, 7)
+    theta = np.sort(d)[:K] + 1e-4
+    Rd = torch.from_numpy(R).cuda()
+    P.lobpcg_learned_apply(s.h, Rd, torch.from_numpy(theta).cuda())
+    Wg = Rd.cpu().numpy()
+    rows = synth.rng(3).integers(0, N, 2000)
+    errs = []
+    for j in range(K):
+        ref, _ = M.precondition(p, R[rows, j], d[rows], theta[j], rho[rows], sc)
+        errs.append(np.abs(Wg[rows, j] - ref) / np.abs(ref))
+    errs = np.concatenate(errs)
+    say(f"learned full size: max rel err {errs.max():.2e}, median {np.median(errs):.2e}")
+    assert errs.max() <= 3e-2 and np.median(errs) <= 2e-3
+    s.set_preconditioner(P.PRECOND_LEARNED)
+    s.set_option(P.OPT_PRECISION, P.PREC_FP32)
+    res = s.solve(K, 1e-8)
+    say("learned+mixed", res.status, res.stats["iterations"], res.stats["learned_fallbacks"])
+    s.set_preconditioner(P.PRECOND_DIAG)
+    s.set_option(P.OPT_PRECISION, P.PREC_FP64)
+    assert res.status == P.OK
+    _certify(A, res, 1e-8)
