@@ -111,8 +111,8 @@ def main():
     ap.add_argument("--spmm-reps", type=int, default=20)
     ap.add_argument("--train-matrices", type=int, default=4)
     ap.add_argument("--train-n", type=int, default=200_000)
-    ap.add_argument("--train-steps", type=int, default=1500)
-    ap.add_argument("--train-chunks", type=int, default=5)
+    ap.add_argument("--train-steps", type=int, default=600)
+    ap.add_argument("--train-chunks", type=int, default=12)
     ap.add_argument(
         "--kernels-only",
         action="store_true",
