@@ -471,6 +471,11 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     const int newc = std::max(m_conv, leading_converged(rnorm, lock_tol));
     if (!low && newc >= k) {
       // reading R9: judge with an explicit product A X
+      // the implicit-P recurrence lets X's orthonormality drift by rounding
+      // (about 1e-12 after hundreds of iterations): re-orthonormalise X
+      // (Alg. 2) before the explicit product that judges it
+      rc = ortho_run<T>(V[1 - c], ldo, 0, m, nullptr, false, false, tau);
+      if (rc) return rc;
       const double* Xd = reinterpret_cast<const double*>(V[1 - c]);
       double* scratch = reinterpret_cast<double*>(AV[c]);
       rc = true_residuals(Xd, ldo, m, scratch, theta, th_t, rn_t);
@@ -508,6 +513,8 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       HIPCHK(rotate_t(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
     }
     if (iter >= max_iter) {
+      rc = ortho_run<T>(V[1 - c], ldo, 0, m, nullptr, false, false, tau);
+      if (rc) return rc;
       const double* Xd = reinterpret_cast<const double*>(V[1 - c]);
       rc = true_residuals(Xd, ldo, m, reinterpret_cast<double*>(AV[c]), theta, th_t, rn_t);
       if (rc) return rc;

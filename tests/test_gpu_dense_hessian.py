@@ -1,0 +1,62 @@
+"""The dense, not diagonally dominant configuration at full size (n = 20,000,
+k = 8: diag U(0.1, 10) + a rank-64 term with S ~ U(-5, 5) + symmetric
+N(0, 0.05^2) noise), fp64 and mixed precision.  The full dense eigensolve is
+minutes of host time, so the solves are certified by properties that hold
+at any size (true residuals recomputed on the CPU from the returned vectors,
+Rayleigh quotients, orthonormality, order) and by the agreement of the two
+precisions within the Kato-Temple bound r^2 / gap of the true eigenvalues.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N, K = 20_000, 8
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_06668_amd as P
+
+    return P
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_dense_hessian_full_size(P):
+    mseed, xseed = synth.SEEDS["dense_hessian"]
+    A = synth.dense_hessian(N, seed=mseed)
+    X0 = synth.start_block(N, K, xseed)
+    s = P.Solver(N)
+    s.set_operator_dense(torch.from_numpy(A).cuda())
+    s.set_preconditioner(P.PRECOND_DIAG)
+    s.set_option(P.OPT_MAX_ITER, 5000)
+    s.set_initial_guess(torch.from_numpy(X0).cuda())
+    normA = np.abs(A).sum(1).max()  # Gershgorin bound, ~1e3 here
+    out = {}
+    for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_FP32)):
+        s.set_option(P.OPT_PRECISION, prec)
+        res = s.solve(K, 1e-8)
+        say(name, res.status, res.stats["iterations"], f"{res.stats['ms_total']:.0f} ms", res.evals)
+        assert res.status == P.OK
+        X = res.evecs.cpu().numpy()
+        AX = A @ X
+        th = np.einsum("ij,ij->j", X, AX)
+        r = np.linalg.norm(AX - X * th, axis=0)
+        assert np.all(r <= 1e-8 * 1.0001), r
+        # Rayleigh quotients of a dense n = 2e4 product in two summation
+        # orders agree to ~sqrt(n) eps |A|, far inside the eigenvalue bar
+        assert np.all(np.abs(res.evals - th) <= 1e-12 * normA)
+        assert np.all(np.diff(res.evals) >= -1e-12)
+        assert np.abs(X.T @ X - np.eye(K)).max() < 1e-12
+        out[name] = res.evals
+    gaps = np.diff(out["fp64"])
+    say("smallest gap", gaps.min())
+    assert np.all(np.abs(out["fp64"] - out["mixed"]) <= 1e-9 * np.maximum(np.abs(out["fp64"]), 1e-3 * normA))
