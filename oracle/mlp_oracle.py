@@ -10,7 +10,9 @@ Preconditioned column.  For an active residual column r (Ritz value theta)
 of an operator with diagonal d and off-diagonal absolute row sums
 rho_i = sum_{l != i} |a_il|, with s = mean_i |d_i|,
 
-    w_i = r_i / sqrt((d_i - theta)^2 + c_i^2),     c_i = s * softplus(y_i),
+    w_i = r_i / sqrt((d_i - theta)^2 + c_i^2),     c_i = s * softplus(y_i)
+                                                    if |d_i - theta| <= 16 rho_i,
+                                                    c_i = 0 otherwise,
 
 where y_i is the output of a per-entry MLP 3 -> 128 -> 128 -> 1 (SiLU) on
 the features
@@ -19,6 +21,9 @@ the features
     phi_3 = log(rho_i / s + 1e-6).
 c -> 0 gives the absolute Jacobi preconditioner; the net learns how much to
 regularise it where d_i is close to theta relative to the coupling rho_i.
+Outside the window |d_i - theta| <= 16 rho_i the step is the Jacobi one (a
+regulariser of the size of the coupling changes w there by less than
+(1/16)^2 / 2), so only the entries near theta need the net.
 The denominator is floored at delta = 1e-8 max(1, |theta|), the Jacobi guard.
 
 Training objective.  For a column j with Ritz vector x_j in the orthonormal
@@ -49,6 +54,7 @@ HIDDEN = 128
 NFEAT = 3
 FEAT_FLOOR = 1e-6
 GUARD = 1e-8  # Jacobi guard, relative to max(1, |theta|)
+WINDOW = 16.0  # the net acts where |d - theta| <= WINDOW * rho
 
 
 @dataclasses.dataclass
@@ -144,12 +150,13 @@ def precondition(p: Params, r: np.ndarray, d: np.ndarray, theta: float, rho: np.
     """The learned preconditioned column w (and the pieces the gradient needs)."""
     F = features(d, theta, rho, s)
     y, cache = forward(p, F)
-    c = s * softplus(y)
     dm = d - theta
+    inside = np.abs(dm) <= WINDOW * rho
+    c = np.where(inside, s * softplus(y), 0.0)
     delta = GUARD * max(1.0, abs(theta))
     q = np.maximum(dm * dm + c * c, delta * delta)
     w = r / np.sqrt(q)
-    return w, dict(y=y, c=c, q=q, floored=(dm * dm + c * c) < delta * delta, cache=cache)
+    return w, dict(y=y, c=c, q=q, floored=(dm * dm + c * c) < delta * delta, inside=inside, cache=cache)
 
 
 def _delta(h: float, b: float):
@@ -196,7 +203,7 @@ def objective(p: Params, A, X: np.ndarray, R: np.ndarray, theta: np.ndarray, col
         gw = gu - X @ (X.T @ gu)
         # w = r q^-1/2, q = dm^2 + c^2 (not floored), c = s softplus(y)
         dq = gw * r * (-0.5) * aux["q"] ** -1.5
-        dq = np.where(aux["floored"], 0.0, dq)
+        dq = np.where(aux["floored"] | ~aux["inside"], 0.0, dq)
         dy = dq * 2.0 * aux["c"] * s * sigmoid(aux["y"])
         g += backward_dy(p, aux["cache"], dy).flat()
     return L, g

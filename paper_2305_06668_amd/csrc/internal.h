@@ -29,6 +29,7 @@ constexpr int kMlpFeat = 3;
 constexpr int kMlpParams = kMlpHidden * kMlpFeat + kMlpHidden + kMlpHidden * kMlpHidden +
                            kMlpHidden + kMlpHidden + 1;
 constexpr int kMlpBlocks = 256;  // persistent grid of the MLP kernels
+constexpr double kMlpWindow = 16.0;  // the net acts where |d - theta| <= kMlpWindow * rho
 
 // Device-side state of one ortho(W; Y) call (Alg. 2 nested in Alg. 3).
 // Written only by the one-workgroup controller kernel; the streaming kernels

@@ -5,9 +5,12 @@
 // 3 -> 128 -> 128 -> 1 (SiLU) on the features
 //   phi = (log(|d_i - theta| / s + 1e-6), theta / s, log(rho_i / s + 1e-6)),
 // rho_i the off-diagonal absolute row sum and s = mean |d|.  The denominator
-// is floored at the Jacobi guard delta = 1e-8 max(1, |theta|).  A column
-// flagged in `mask`, and any entry whose net output is not finite, takes
-// c = 0: the guarded absolute Jacobi step (the diagonal fallback).
+// is floored at the Jacobi guard delta = 1e-8 max(1, |theta|).  Outside the
+// window |d_i - theta| <= 16 rho_i, c = 0 by definition (the regulariser
+// only matters where d_i is within a few couplings of theta), and a tile
+// with no entry inside the window skips the net.  A column flagged in
+// `mask`, and any entry whose net output is not finite, takes c = 0: the
+// guarded absolute Jacobi step (the diagonal fallback).
 //
 // Work layout: a workgroup of 256 threads holds W2^T (128 x 128 fp32, rows
 // padded to 132 floats) and the small layers in LDS and walks tiles of 64
@@ -92,6 +95,7 @@ __device__ __forceinline__ void load_weights(const float* __restrict__ wts, floa
 // Per-entry inputs of one tile entry.
 struct EntryIn {
   bool valid;
+  bool inside;   // |d_i - theta_j| <= kMlpWindow rho_i
   int64_t row;
   int col;
   double dm;     // d_i - theta_j
@@ -111,9 +115,11 @@ __device__ __forceinline__ EntryIn entry_features(float* L, int e, int64_t ent, 
     in.col = (int)(ent - in.row * nact);
     in.theta = theta[in.col];
     in.dm = diag[in.row] - in.theta;
+    const double rr = rho[in.row];
+    in.inside = fabs(in.dm) <= kMlpWindow * rr;
     f0 = (float)log(fabs(in.dm) / s + 1e-6);
     f1 = (float)(in.theta / s);
-    f2 = (float)log(rho[in.row] / s + 1e-6);
+    f2 = (float)log(rr / s + 1e-6);
   }
   L[sPhi + e * 4 + 0] = f0;
   L[sPhi + e * 4 + 1] = f1;
@@ -174,6 +180,7 @@ struct EntryOut {
 __device__ __forceinline__ EntryOut regularise(const EntryIn& in, float y, double s, bool jacobi,
                                                int* flags) {
   EntryOut o{};
+  if (!in.inside) jacobi = true;
   double c = s * softplus_d((double)y);
   if (!jacobi && !isfinite(c)) {
     if (flags) flags[in.col] = 1;
@@ -212,8 +219,8 @@ __global__ __launch_bounds__(256) void k_mlp_apply(T* __restrict__ R, int64_t ld
     if (threadIdx.x < kTE)
       in = entry_features(L, threadIdx.x, tile * kTE + threadIdx.x, total, nact, diag, rho, theta,
                           s);
-    __syncthreads();
-    forward_tile(L, z2, eg, kg);
+    // the net only matters inside the window: skip it for tiles without such entries
+    if (__syncthreads_or(threadIdx.x < kTE && in.valid && in.inside)) forward_tile(L, z2, eg, kg);
     if (threadIdx.x < kTE && in.valid) {
       const bool jac = mask != nullptr && mask[in.col] != 0;
       const EntryOut o = regularise(in, L[sY + threadIdx.x], s, jac, flags);
@@ -261,7 +268,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const double* __restrict__ R,
       Ld[kTE + tid] = in.valid ? G[in.row * ld + in.col] : 0.0;
     }
     for (int idx = tid; idx < kH * 8; idx += blockDim.x) L[sGA + idx] = 0.0f;
-    __syncthreads();
+    // entries outside the window have dL/dy = 0: skip tiles without any inside
+    if (!__syncthreads_or(tid < kTE && in.valid && in.inside)) continue;
     forward_tile(L, z2, eg, kg);
     // dL/dy per entry: w = r q^-1/2, q = dm^2 + c^2, c = s softplus(y)
     if (tid < kTE) {
@@ -488,17 +496,22 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
     // the fp64 difference d - theta); the four lanes that hold an entry's A
     // rows read them with shuffles
     float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+    bool inside = false;
     {
       const int64_t ent = wt * E + (lane % E);
       if (lane < E && ent < total) {
         const int64_t row = ent / nact;
         const int col = (int)(ent - row * nact);
         const double th = theta[col];
-        f0 = __logf((float)(fabs(diag[row] - th) * inv_s) + 1e-6f);
+        const double adm = fabs(diag[row] - th), rr = rho[row];
+        inside = adm <= kMlpWindow * rr;
+        f0 = __logf((float)(adm * inv_s) + 1e-6f);
         f1 = (float)(th * inv_s);
-        f2 = __logf((float)(rho[row] * inv_s) + 1e-6f);
+        f2 = __logf((float)(rr * inv_s) + 1e-6f);
       }
     }
+    // no entry of the tile inside the window: every entry takes the Jacobi step
+    const bool run_net = __ballot(inside) != 0;
     float ph[MT][3];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
@@ -512,7 +525,7 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
 #pragma unroll
       for (int nt = 0; nt < 8; ++nt) acc[t][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    for (int ks = 0; ks < 4 && run_net; ++ks) {
       bf16x8 bq[8];
 #pragma unroll
       for (int nt = 0; nt < 8; ++nt)
@@ -537,6 +550,7 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
     for (int t = 0; t < MT; ++t) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) y[t][i] = 0.0f;
+      if (!run_net) continue;
 #pragma unroll
       for (int nt = 0; nt < 8; ++nt)
 #pragma unroll
@@ -564,9 +578,10 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
         const int64_t row = ent / nact;
         const int col = (int)(ent - row * nact);
         const double th = theta[col];
-        const float dm = (float)(diag[row] - th);
+        const double dmd = diag[row] - th;
+        const float dm = (float)dmd;
         yv += b3;
-        bool jac = mask != nullptr && mask[col] != 0;
+        bool jac = (mask != nullptr && mask[col] != 0) || !(fabs(dmd) <= kMlpWindow * rho[row]);
         // c = s softplus(y), fp32 (the net itself ran in bf16)
         const float cf = (float)s * (fmaxf(yv, 0.0f) + __logf(1.0f + __expf(-fabsf(yv))));
         if (!jac && !isfinite(cf)) {

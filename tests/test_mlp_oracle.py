@@ -98,17 +98,20 @@ def test_vanishing_regulariser_is_absolute_jacobi():
 
 
 def test_regulariser_closed_form():
-    # with a constant output y the regulariser is c = s log(1 + e^y)
+    # with a constant output y the regulariser is c = s log(1 + e^y) inside
+    # the window |d - theta| <= 16 rho and 0 outside it
     p = small_net()
     p.W3[:] = 0.0
     p.b3[:] = 0.7
-    r = np.array([1.0, -2.0, 0.5])
-    d = np.array([2.0, 1.0, 1.5])
-    rho = np.array([0.1, 0.2, 0.3])
+    r = np.array([1.0, -2.0, 0.5, 3.0])
+    d = np.array([2.0, 1.0, 1.5, 9.0])
+    rho = np.array([0.1, 0.2, 0.3, 0.1])  # the last entry is outside (7.8 > 1.6)
     s = M.scale_of(d)
     w, aux = M.precondition(p, r, d, 1.2, rho, s)
     c = s * np.log1p(np.exp(0.7))
-    assert np.allclose(w, r / np.sqrt((d - 1.2) ** 2 + c * c), rtol=1e-14)
+    ref = r / np.sqrt((d - 1.2) ** 2 + np.array([c, c, c, 0.0]) ** 2)
+    assert np.allclose(w, ref, rtol=1e-14)
+    assert list(aux["inside"]) == [True, True, True, False]
 
 
 def test_activation_closed_forms():
