@@ -269,7 +269,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"csr_banded n={n} nnz={C.nnz} band=+-5000 k={k} block={k} precond=jacobi tol={args.tol:g}",
+            "workload": f"csr_banded n={n} nnz={C.nnz} band=+-5000 k={k} block={k} tol={args.tol:g}",
             "variant": "learned+mixed: fp32 operator/Grams/blocks then fp64 to tol, learned preconditioner",
             "iterations": stats["iterations"],
             "precision_switch_iter": stats["precision_switch_iter"],
