@@ -492,80 +492,82 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
     // keep the weight reads inside the loop (LDS re-reads are cheap; holding
     // every fragment in registers for the whole kernel would cap occupancy)
     asm volatile("" ::: "memory");
-    // features: lane l < E evaluates entry l of the tile once (fp32 logs of
-    // the fp64 difference d - theta); the four lanes that hold an entry's A
-    // rows read them with shuffles
-    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
-    bool inside = false;
-    {
-      const int64_t ent = wt * E + (lane % E);
-      if (lane < E && ent < total) {
-        const int64_t row = ent / nact;
-        const int col = (int)(ent - row * nact);
-        const double th = theta[col];
-        const double adm = fabs(diag[row] - th), rr = rho[row];
-        inside = adm <= kMlpWindow * rr;
-        f0 = __logf((float)(adm * inv_s) + 1e-6f);
+    // lane l < E owns entry l of the tile: its operands are loaded once
+    const int64_t ent = wt * E + lane;
+    const bool valid = lane < E && ent < total;
+    int64_t row = 0;
+    int col = 0;
+    double th = 0.0, dmd = 0.0, rr = 0.0;
+    if (valid) {
+      row = ent / nact;
+      col = (int)(ent - row * nact);
+      th = theta[col];
+      dmd = diag[row] - th;
+      rr = rho[row];
+    }
+    const bool inside = valid && fabs(dmd) <= kMlpWindow * rr;
+    // the net only acts inside the window: a tile without such entries takes
+    // the Jacobi step everywhere and skips it
+    float yv = 0.0f;
+    if (__ballot(inside) != 0) {
+      // features (fp32 logs of the fp64 difference d - theta); the four
+      // lanes that hold an entry's A rows read them with shuffles
+      float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+      if (valid) {
+        f0 = __logf((float)(fabs(dmd) * inv_s) + 1e-6f);
         f1 = (float)(th * inv_s);
         f2 = __logf((float)(rr * inv_s) + 1e-6f);
       }
-    }
-    // no entry of the tile inside the window: every entry takes the Jacobi step
-    const bool run_net = __ballot(inside) != 0;
-    float ph[MT][3];
-#pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      ph[t][0] = __shfl(f0, 16 * t + r, 64);
-      ph[t][1] = __shfl(f1, 16 * t + r, 64);
-      ph[t][2] = __shfl(f2, 16 * t + r, 64);
-    }
-    f32x4 acc[MT][8];
-#pragma unroll
-    for (int t = 0; t < MT; ++t)
-#pragma unroll
-      for (int nt = 0; nt < 8; ++nt) acc[t][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int ks = 0; ks < 4 && run_net; ++ks) {
-      bf16x8 bq[8];
-#pragma unroll
-      for (int nt = 0; nt < 8; ++nt)
-        bq[nt] = *reinterpret_cast<const bf16x8*>(w2s + (16 * nt + r) * kBS + 32 * ks + 8 * g);
+      float ph[MT][3];
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
-        bf16x8 a;
+        ph[t][0] = __shfl(f0, 16 * t + r, 64);
+        ph[t][1] = __shfl(f1, 16 * t + r, 64);
+        ph[t][2] = __shfl(f2, 16 * t + r, 64);
+      }
+      f32x4 acc[MT][8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float4 w = w1s[32 * ks + 8 * g + j];
-          const float z = w.w + w.x * ph[t][0] + w.y * ph[t][1] + w.z * ph[t][2];
-          a[j] = (__bf16)silu_fast(z);
-        }
+      for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) acc[t][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        bf16x8 bq[8];
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt)
-          acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[nt], acc[t][nt], 0, 0, 0);
+          bq[nt] = *reinterpret_cast<const bf16x8*>(w2s + (16 * nt + r) * kBS + 32 * ks + 8 * g);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          bf16x8 a;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float4 w = w1s[32 * ks + 8 * g + j];
+            const float z = w.w + w.x * ph[t][0] + w.y * ph[t][1] + w.z * ph[t][2];
+            a[j] = (__bf16)silu_fast(z);
+          }
+#pragma unroll
+          for (int nt = 0; nt < 8; ++nt)
+            acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[nt], acc[t][nt], 0, 0, 0);
+        }
       }
-    }
-    // layer 3: y of entry 16 t + 4 g + i, summed over the 16 lanes of segment g
-    float y[MT][4];
+      // layer 3: y of entry 16 t + 4 g + i, summed over the 16 lanes of segment g
+      float y[MT][4];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
+      for (int t = 0; t < MT; ++t) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) y[t][i] = 0.0f;
-      if (!run_net) continue;
+        for (int i = 0; i < 4; ++i) y[t][i] = 0.0f;
 #pragma unroll
-      for (int nt = 0; nt < 8; ++nt)
+        for (int nt = 0; nt < 8; ++nt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            y[t][i] = fmaf(w3r[nt], silu_fast(acc[t][nt][i] + b2r[nt]), y[t][i]);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          y[t][i] = fmaf(w3r[nt], silu_fast(acc[t][nt][i] + b2r[nt]), y[t][i]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) y[t][i] += __shfl_xor(y[t][i], off, 16);
-    }
-    // epilogue on E lanes: lane L < E finishes entry L of the tile (its y
-    // sits in segment (L % 16) / 4, slot (t = L / 16, i = L % 4))
-    {
+          for (int off = 8; off >= 1; off >>= 1) y[t][i] += __shfl_xor(y[t][i], off, 16);
+      }
+      // entry L's y sits in segment (L % 16) / 4, slot (t = L / 16, i = L % 4)
       const int src = 16 * ((lane & 15) >> 2);
-      float yv = 0.0f;
 #pragma unroll
       for (int t = 0; t < MT; ++t)
 #pragma unroll
@@ -573,27 +575,25 @@ __global__ __launch_bounds__(256) void k_mlp_apply_bf16(T* __restrict__ R, int64
           const float v = __shfl(y[t][i], src, 64);
           if ((lane >> 4) == t && (lane & 3) == i) yv = v;
         }
-      const int64_t ent = wt * E + lane;
-      if (lane < E && ent < total) {
-        const int64_t row = ent / nact;
-        const int col = (int)(ent - row * nact);
-        const double th = theta[col];
-        const double dmd = diag[row] - th;
-        const float dm = (float)dmd;
-        yv += b3;
-        bool jac = (mask != nullptr && mask[col] != 0) || !(fabs(dmd) <= kMlpWindow * rho[row]);
+      yv += b3;
+    }
+    // epilogue: w = r / sqrt((d - theta)^2 + c^2), floored at the guard
+    if (valid) {
+      bool jac = !inside || (mask != nullptr && mask[col] != 0);
+      float c = 0.0f;
+      if (!jac) {
         // c = s softplus(y), fp32 (the net itself ran in bf16)
-        const float cf = (float)s * (fmaxf(yv, 0.0f) + __logf(1.0f + __expf(-fabsf(yv))));
-        if (!jac && !isfinite(cf)) {
+        c = (float)s * (fmaxf(yv, 0.0f) + __logf(1.0f + __expf(-fabsf(yv))));
+        if (!isfinite(c)) {
           if (flags) flags[col] = 1;
-          jac = true;
+          c = 0.0f;
         }
-        const float c = jac ? 0.0f : cf;
-        const float delta = (float)(kPrecondGuard * fmax(1.0, fabs(th)));
-        const float q = fmaxf(dm * dm + c * c, delta * delta);
-        T* p = R + row * ld + col;
-        *p = (T)((double)*p * (double)__frsqrt_rn(q));
       }
+      const float dm = (float)dmd;
+      const float delta = (float)(kPrecondGuard * fmax(1.0, fabs(th)));
+      const float q = fmaxf(dm * dm + c * c, delta * delta);
+      T* p = R + row * ld + col;
+      *p = (T)((double)*p * (double)__frsqrt_rn(q));
     }
   }
 }
