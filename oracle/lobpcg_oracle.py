@@ -54,6 +54,14 @@ the design notes of the repository):
       check fails, AX is replaced by the explicit product, P is dropped and
       the iteration continues.
   R10 The reduced matrix is symmetrised, a <- (a + a^T) / 2, before eigh.
+  R16 Eigenvectors of the reduced matrix are oriented so that the diagonal
+      entry u[j, j] is >= 0 (for the X block: the new Ritz vector continues
+      the old one).  The "Basis selection" paragraph forms P from the
+      coefficients of X^{k+1} - X^k by subtracting the identity from u_xx,
+      which presumes that orientation; an eigensolver's signs are otherwise
+      arbitrary, and a flipped column turns the small difference into
+      2 x_j minus the difference, which the ortho against u_x then recovers
+      only to eps / ||difference||.
 """
 from __future__ import annotations
 
@@ -263,10 +271,17 @@ def symmetrize(a: np.ndarray) -> np.ndarray:
 
 def rayleigh_ritz(V: np.ndarray, AV: np.ndarray):
     """RR on an orthonormal basis V: eigen-decompose a = V^T A V (R10);
-    returns all Ritz values (ascending) and the coefficient matrix."""
+    returns all Ritz values (ascending) and the coefficient matrix, its
+    columns oriented by R16."""
     a = symmetrize(V.T @ AV)
     theta, U = np.linalg.eigh(a)
-    return theta, U
+    return theta, orient_columns(U)
+
+
+def orient_columns(U: np.ndarray) -> np.ndarray:
+    """R16: flip column j when U[j, j] < 0."""
+    s = np.where(np.diag(U) < 0.0, -1.0, 1.0)
+    return U * s
 
 
 def precondition_diag(

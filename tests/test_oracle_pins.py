@@ -195,6 +195,48 @@ def test_rayleigh_ritz_interlacing():
     assert np.allclose(U.T @ (0.5 * (a + a.T)) @ U, np.diag(theta), atol=1e-12)
 
 
+def test_rayleigh_ritz_orientation_and_p_accuracy():
+    # R16: every coefficient column has a nonnegative diagonal entry and is
+    # still an eigenvector; with it, u_x - E is the small update, and the
+    # P coefficients built from it match those built from the flipped
+    # column only up to eps / ||update|| (the cancellation R16 avoids)
+    g = synth.rng(21)
+    n, m = 400, 4
+    A = synth.dense_dd(n, seed=21)
+    w, V = np.linalg.eigh(A)
+    X = np.linalg.qr(V[:, :m] + 1e-9 * g.standard_normal((n, m)))[0]
+    W = np.linalg.qr(g.standard_normal((n, m)) - X @ (X.T @ g.standard_normal((n, m))))[0]
+    W = np.linalg.qr(W - X @ (X.T @ W))[0]
+    Vb = np.hstack([X, W])
+    th, U = O.rayleigh_ritz(Vb, A @ Vb)
+    a = O.symmetrize(Vb.T @ A @ Vb)
+    assert np.all(np.diag(U) >= 0.0)
+    assert np.abs(a @ U - U * th).max() <= 1e-12 * np.abs(a).max()
+    # flipping basis vector k flips row k of every eigenvector and so the
+    # sign of diagonal entry k: the oriented result is exactly D U D, with
+    # u_xx ~ I, whatever signs the eigensolver picks
+    for k in range(m):
+        D = np.ones(2 * m)
+        D[k] = -1.0
+        th2, U2 = O.rayleigh_ritz(Vb * D, (A @ Vb) * D)
+        assert np.all(np.diag(U2) >= 0.0)
+        assert np.allclose(U2, D[:, None] * U * D[None, :], atol=1e-10)
+        assert np.linalg.norm(U2[:, :m] - np.eye(2 * m)[:, :m], axis=0).max() < 1e-6
+    ux = U[:, :m]
+    upd = ux - np.eye(2 * m)[:, :m]
+    assert np.linalg.norm(upd, axis=0).max() < 1e-6  # the update is small
+    flip = ux * np.array([1.0, -1.0, 1.0, -1.0])
+    upd_f = flip - np.eye(2 * m)[:, :m]
+    # both project to the same direction; the flipped one loses digits
+    def proj(Y):
+        Y = Y - ux @ (ux.T @ Y)
+        return Y / np.linalg.norm(Y, axis=0)
+    p0, p1 = proj(upd), proj(upd_f)
+    cos = np.abs(np.sum(p0 * p1, axis=0))
+    assert np.all(cos > 0.99)
+    assert np.max(1.0 - cos) > 1e-12  # measurable loss on the flipped columns
+
+
 def test_preconditioner_guard_by_hand():
     R = np.array([[1.0, 2.0], [1.0, 2.0], [1.0, 2.0]])
     d = np.array([3.0, 1.0, 1.0 + 5e-9])
