@@ -113,6 +113,7 @@ def main():
     ap.add_argument("--train-n", type=int, default=200_000)
     ap.add_argument("--train-steps", type=int, default=600)
     ap.add_argument("--train-chunks", type=int, default=12)
+    ap.add_argument("--rr-jacobi", action="store_true", help="Rayleigh-Ritz eigensolves by Jacobi")
     ap.add_argument(
         "--kernels-only",
         action="store_true",
@@ -147,6 +148,7 @@ def main():
     X0d = torch.from_numpy(X0).to(dev)
 
     s = P.Solver(n)
+    s.set_option(P.OPT_RR_JACOBI, 1 if args.rr_jacobi else 0)
     s.set_operator_csr(rp, ci, va)
     s.set_preconditioner(P.PRECOND_DIAG)
     s.set_initial_guess(X0d)
@@ -181,6 +183,7 @@ def main():
     def family_solver(seed_m, seed_x):
         Ct = synth.csr_banded(n=ntr, seed=seed_m, diag_slope=slope)
         st = P.Solver(ntr)
+        st.set_option(P.OPT_RR_JACOBI, 1 if args.rr_jacobi else 0)
         st.set_operator_csr(
             torch.from_numpy(Ct.row_ptr).to(dev), torch.from_numpy(Ct.col).to(dev), torch.from_numpy(Ct.val).to(dev)
         )

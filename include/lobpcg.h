@@ -72,6 +72,10 @@ typedef struct lobpcg_ctx* lobpcg_t;
 #define LOBPCG_OPT_ORTHO_MAX_PASSES 3 /* Alg. 2 overlap evaluations, default 6 */
 #define LOBPCG_OPT_ORTHO_Y_MAX_PASSES 4 /* Alg. 3 passes, default 4 */
 #define LOBPCG_OPT_TRACE 5            /* 1: time phases with HIP events */
+#define LOBPCG_OPT_RR_JACOBI 7         /* Rayleigh-Ritz eigensolver: 0 (default) =
+                                         Householder tridiagonalisation, Sturm
+                                         multisection and inverse iteration;
+                                         1 = parallel cyclic Jacobi */
 #define LOBPCG_OPT_LEARNED_BF16 6     /* learned preconditioner inference: 1 (default)
                                          = hidden layer on bf16 MFMA with fp32
                                          accumulation, 0 = fp32 throughout */
@@ -100,6 +104,8 @@ typedef struct lobpcg_stats {
   int32_t learned_fallbacks;   /* learned steps that did not lower the residual
                                   (the column then takes 3 Jacobi steps) */
   int32_t learned_nonfinite;   /* learned applications with a non-finite net output */
+  int32_t rr_eig_fallbacks;    /* Rayleigh-Ritz eigensolves that fell back from the
+                                  tridiagonal path to Jacobi */
 } lobpcg_stats;
 
 /* ---- ortho report for the step entry points ---------------------------- */

@@ -54,6 +54,7 @@ OPT_ORTHO_MAX_PASSES = 3
 OPT_ORTHO_Y_MAX_PASSES = 4
 OPT_TRACE = 5
 OPT_LEARNED_BF16 = 6
+OPT_RR_JACOBI = 7
 
 _i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -81,6 +82,7 @@ class lobpcg_stats(ctypes.Structure):
         ("ms_sync", _dbl),
         ("learned_fallbacks", _i32),
         ("learned_nonfinite", _i32),
+        ("rr_eig_fallbacks", _i32),
     ]
 
     def as_dict(self) -> dict:

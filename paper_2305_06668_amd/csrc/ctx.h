@@ -44,6 +44,7 @@ struct lobpcg_ctx {
   int ortho_max_inner = 6;
   int ortho_max_outer = 4;
   int trace = 0;
+  int rr_jacobi = 0;     // Rayleigh-Ritz eigensolver: 0 tridiagonal, 1 Jacobi
   int learned_bf16 = 1;  // learned preconditioner inference: layer 2 on bf16 MFMA
   // operator
   int op = lobpcg::kOpNone;

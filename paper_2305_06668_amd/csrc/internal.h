@@ -160,7 +160,7 @@ hipError_t small_eigh(const double* a, int p, double* evals, double* evecs, int*
 // own pass over V.
 hipError_t small_rr(const double* a, int p, int m, int a0, int want_up, double tau,
                     const OrthoState* pend, int woff, double* theta_all, double* U, int* info,
-                    hipStream_t s);
+                    int jacobi, hipStream_t s);
 // Shifted Cholesky (p x p, p <= 64): L lower with L L^T = M + sigma I.
 hipError_t small_cholesky(const double* M, int p, double* L, int* info, hipStream_t s);
 // One controller step of ortho(W; Y): reads G = [Y W]^T W ((ny+nw) x nw),

@@ -420,18 +420,593 @@ __device__ __forceinline__ void load_sym(const double* a, int p, double* A, int 
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Lowest nev eigenpairs of a symmetric p x p matrix by the tridiagonal
+// route (the Rayleigh-Ritz solve of Alg. 1; the paper calls LAPACK for it,
+// Sec. 3.1).  Jacobi needs p - 1 dependent rounds per sweep, each a chain
+// of square roots and divisions followed by a full-matrix update; this path
+// has one short chain per reflector and per Sturm count instead:
+//   1. Householder reduction A = Q T Q^T by one wave: reflector k,
+//      H_k = I - beta_k v_k v_k^T, maps column k below the diagonal to
+//      alpha_k e_{k+1} (v_k kept in that column, Q = H_0 H_1 ... H_{p-3});
+//   2. the nev lowest eigenvalues of T by multisection on Sturm counts
+//      (counts of negative pivots of T - x I with LAPACK's pivmin guard),
+//      G points per eigenvalue and round;
+//   3. their vectors by block inverse iteration: a solve with the
+//      partial-pivoting LU of T - lambda_j I from a SplitMix64 start
+//      (pivots below eps ||T|| raised to eps ||T||, one thread per vector),
+//      Cholesky-QR of the nev vectors, a second solve;
+//   4. back-transformation u = Q z, one wave per vector;
+//   5. Cholesky-QR, twice, of the nev vectors.
+// Inverse iteration returns the vectors of a cluster of close or repeated
+// eigenvalues as independent mixtures of the cluster's eigenvectors, which
+// drift towards each other with further solves; orthonormalising them in
+// ascending order between and after the solves keeps them an orthonormal
+// eigenbasis of the cluster (residuals and orthogonality ~1e-15 ||A|| on
+// repeated and 1e-14-separated eigenvalues, where three plain solves
+// followed by Cholesky-QR lose two digits).
+// Returns false when a Cholesky-QR breaks down (A is destroyed); the
+// callers then reload A and run Jacobi.
+
+constexpr int kEigLdsBytes = 152 * 1024;  // dynamic LDS of the eigensolver kernels
+constexpr int kMsPoints = 32;              // multisection points per eigenvalue
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+// Sum over the 64 lanes (all active), the same bits in every lane: within
+// each row of 16 by DPP (swap neighbours, swap pairs, mirror 8, mirror 16;
+// each step adds the same two operands on both partners), then the four row
+// sums in a fixed order.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// LDS layout after the p x (p+1) A area, in doubles
+struct TriLayout {
+  int ldz, nb;
+  int d, e, inve, e2, beta, vv, ww, ev, linv, G, Z, ws, sw, total;
+};
+__host__ __device__ inline TriLayout tri_layout(int p, int nev) {
+  TriLayout t;
+  t.ldz = nev + 1;
+  int o = 0;
+  t.d = o; o += p;
+  t.e = o; o += p;
+  t.inve = o; o += p;
+  t.e2 = o; o += p;
+  t.beta = o; o += p;
+  t.vv = o; o += p;
+  t.ww = o; o += p;
+  t.ev = o; o += nev;
+  t.linv = o; o += nev;
+  t.G = o; o += nev * (nev + 1);
+  t.Z = o; o += p * t.ldz;
+  t.ws = o;
+  const int avail = kEigLdsBytes / 8 - p * (p + 1) - o;
+  const int per = 4 * p + (p + 7) / 8 + 1;  // U0^-1, U1, U2, multipliers + pivot flags
+  int nb = avail / per;
+  if (nb > nev) nb = nev;
+  t.nb = nb;
+  if (nb < 1) {
+    t.sw = o;
+    t.total = o;
+    return t;
+  }
+  o += 4 * p * nb;
+  t.sw = o;
+  o += (p * nb + 7) / 8;
+  t.total = o;
+  return t;
+}
+
+// NR = rows per lane (1 for p <= 64, else 2)
+template <int NR>
+__device__ void wave_tridiag(double* A, int lda, int p, double* d, double* e, double* beta, double* vv,
+                             double* ww) {
+  const int l = threadIdx.x & 63;
+  for (int k = 0; k + 2 < p; ++k) {
+    const int k1 = k + 1;
+    double x[NR];
+    bool act[NR];
+    int ic[NR];
+    double tail = 0.0;
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+      const int i = l + 64 * h;
+      act[h] = i > k && i < p;
+      ic[h] = min(i, p - 1);
+      x[h] = act[h] ? A[i * lda + k] : 0.0;
+      if (i > k1) tail += x[h] * x[h];
+    }
+    const double x1 = A[k1 * lda + k];
+    tail = wave_sum(tail);
+    double alpha = x1, b = 0.0;
+    if (tail > 0.0) {
+      const double nrm = sqrt(x1 * x1 + tail);
+      alpha = (x1 >= 0.0) ? -nrm : nrm;
+      b = 1.0 / (nrm * (nrm + fabs(x1)));  // 2 / v^T v for v = x - alpha e_1
+#pragma unroll
+      for (int h = 0; h < NR; ++h) {
+        const int i = l + 64 * h;
+        if (act[h]) {
+          const double v = (i == k1) ? x1 - alpha : x[h];
+          A[i * lda + k] = v;
+          vv[i] = v;
+        }
+      }
+    }
+    if (l == 0) {
+      d[k] = A[k * lda + k];
+      e[k] = alpha;
+      beta[k] = b;
+    }
+    wave_sync();
+    if (b == 0.0) continue;  // H_k = I
+    // p = beta A v on the trailing block (A[i][j] read as A[j][i])
+    double pv[NR], vi[NR];
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+      pv[h] = 0.0;
+      vi[h] = act[h] ? vv[l + 64 * h] : 0.0;
+    }
+    for (int j0 = k1; j0 < p; j0 += 8) {
+      double vj[8], aj[8][NR];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = min(j0 + u, p - 1);
+        vj[u] = (j0 + u < p) ? vv[j] : 0.0;
+#pragma unroll
+        for (int h = 0; h < NR; ++h) aj[u][h] = A[j * lda + ic[h]];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int h = 0; h < NR; ++h) pv[h] += aj[u][h] * vj[u];
+    }
+    double kp = 0.0;
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+      pv[h] = act[h] ? b * pv[h] : 0.0;
+      kp += pv[h] * vi[h];
+    }
+    const double K = 0.5 * b * wave_sum(kp);
+    double wv[NR];
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+      wv[h] = pv[h] - K * vi[h];
+      if (act[h]) ww[l + 64 * h] = wv[h];
+    }
+    wave_sync();
+    // A <- A - v w^T - w v^T on the trailing block, lane i owning column i;
+    // chunks of 8 rows with every load issued before the chunk's stores
+    for (int j0 = k1; j0 < p; j0 += 8) {
+      double vj[8], wj[8], aj[8][NR];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = min(j0 + u, p - 1);
+        vj[u] = vv[j];
+        wj[u] = ww[j];
+#pragma unroll
+        for (int h = 0; h < NR; ++h) aj[u][h] = A[j * lda + ic[h]];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (j0 + u < p) {
+#pragma unroll
+          for (int h = 0; h < NR; ++h)
+            if (act[h]) A[(j0 + u) * lda + ic[h]] = aj[u][h] - (vj[u] * wv[h] + wj[u] * vi[h]);
+        }
+      }
+    }
+    wave_sync();
+  }
+  if (l == 0) {
+    if (p >= 2) {
+      d[p - 2] = A[(p - 2) * lda + p - 2];
+      e[p - 2] = A[(p - 1) * lda + p - 2];
+    }
+    d[p - 1] = A[(p - 1) * lda + p - 1];
+  }
+  wave_sync();
+}
+
+// 1 / q to ~1 ulp: the hardware reciprocal and one Newton step (the Sturm
+// count only needs each step to a few ulps, Kahan's backward-error argument)
+__device__ __forceinline__ double rcp_nr(double q) {
+  const double r = __builtin_amdgcn_rcp(q);
+  return fma(r, fma(-q, r, 1.0), r);
+}
+
+// number of eigenvalues of T below x (negative pivots of T - x I)
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int p, double x,
+                                           double pivmin) {
+  double q = d[0] - x;
+  int c = 0;
+  if (q <= pivmin) {
+    ++c;
+    q = fmin(q, -pivmin);
+  }
+#pragma unroll 4
+  for (int i = 1; i < p; ++i) {
+    q = (d[i] - x) - e2[i - 1] * rcp_nr(q);
+    if (q <= pivmin) {
+      ++c;
+      q = fmin(q, -pivmin);
+    }
+  }
+  return c;
+}
+
+// eigenvalues 0 .. nev-1 (ascending) of T into ev; every thread calls it
+__device__ void blk_multisection(const double* d, const double* e2, int p, int nev, double gl, double gu,
+                                 double tnorm, double pivmin, double* ev) {
+  int G = kMsPoints;
+  while (G > 1 && G * nev > (int)blockDim.x) G >>= 1;
+  const int t = threadIdx.x & (G - 1);
+  const int gi = threadIdx.x / G, ngroups = blockDim.x / G;
+  const int lane = threadIdx.x & 63;
+  const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane & ~(G - 1)));
+  for (int j = gi; j < nev; j += ngroups) {
+    double lo = gl, hi = gu;
+    for (int round = 0; round < 256; ++round) {
+      const double w = hi - lo;
+      if (w <= 2.0 * kEps * fmax(fabs(lo), fabs(hi)) || w <= kEps * tnorm) break;
+      const double h = w / (double)(G + 1);
+      const double x = lo + (double)(t + 1) * h;
+      const int c = sturm_count(d, e2, p, x, pivmin);
+      const int k = __popcll(__ballot(c <= j) & gmask);
+      const double nlo = (k > 0) ? lo + (double)k * h : lo;
+      const double nhi = (k < G) ? lo + (double)(k + 1) * h : hi;
+      if (nlo == lo && nhi == hi) break;
+      lo = nlo;
+      hi = nhi;
+    }
+    if (t == 0) ev[j] = lo + 0.5 * (hi - lo);
+  }
+}
+
+// one inverse-iteration solve of (T - lam I) z = Z[:, j] for the vectors
+// j = j0 + t, t < nb (thread t); factor = true builds the LU, else reuses it.
+// The loads of the next step are issued before the current step's stores.
+__device__ void tri_invit_solve(const double* __restrict__ d, const double* __restrict__ e,
+                                const double* __restrict__ inve, int p, double lam, double tol, double* Z,
+                                int ldz, int j, double* ws, uint8_t* sw, int nb, int t, bool factor) {
+  double* U0 = ws;
+  double* U1 = ws + p * nb;
+  double* U2 = ws + 2 * p * nb;
+  double* LM = ws + 3 * p * nb;
+  double y = Z[j];
+  double bnx = (p > 1) ? Z[ldz + j] : 0.0;
+  if (factor) {
+    double c0 = d[0] - lam, c1 = (p > 1) ? e[0] : 0.0;
+    for (int i = 0; i + 1 < p; ++i) {
+      const double ei = e[i];
+      const double dn = d[i + 1] - lam;
+      const double en = (i + 2 < p) ? e[i + 1] : 0.0;
+      const double ie = inve[i];
+      const double bn = bnx;
+      if (i + 2 < p) bnx = Z[(i + 2) * ldz + j];
+      if (fabs(c0) >= fabs(ei)) {
+        if (fabs(c0) < tol) c0 = (c0 < 0.0) ? -tol : tol;
+        const double li = ei / c0;
+        U0[i * nb + t] = 1.0 / c0;
+        U1[i * nb + t] = c1;
+        U2[i * nb + t] = 0.0;
+        LM[i * nb + t] = li;
+        sw[i * nb + t] = 0;
+        Z[i * ldz + j] = y;
+        y = bn - li * y;
+        c0 = dn - li * c1;
+        c1 = en;
+      } else {
+        const double li = c0 * ie;
+        U0[i * nb + t] = ie;
+        U1[i * nb + t] = dn;
+        U2[i * nb + t] = en;
+        LM[i * nb + t] = li;
+        sw[i * nb + t] = 1;
+        Z[i * ldz + j] = bn;
+        y = y - li * bn;
+        const double nc0 = c1 - li * dn;
+        c1 = -li * en;
+        c0 = nc0;
+      }
+    }
+    if (fabs(c0) < tol) c0 = (c0 < 0.0) ? -tol : tol;
+    U0[(p - 1) * nb + t] = 1.0 / c0;
+    U1[(p - 1) * nb + t] = 0.0;
+    U2[(p - 1) * nb + t] = 0.0;
+  } else {
+    double lmx = LM[t];
+    uint8_t swx = sw[t];
+    for (int i = 0; i + 1 < p; ++i) {
+      const double bn = bnx, li = lmx;
+      const uint8_t si = swx;
+      if (i + 2 < p) bnx = Z[(i + 2) * ldz + j];
+      if (i + 1 < p) {
+        lmx = LM[(i + 1) * nb + t];
+        swx = sw[(i + 1) * nb + t];
+      }
+      if (si == 0) {
+        Z[i * ldz + j] = y;
+        y = bn - li * y;
+      } else {
+        Z[i * ldz + j] = bn;
+        y = y - li * bn;
+      }
+    }
+  }
+  Z[(p - 1) * ldz + j] = y;
+  double z1 = 0.0, z2 = 0.0, zmax = 0.0;
+  double zx = Z[(p - 1) * ldz + j], u0x = U0[(p - 1) * nb + t], u1x = U1[(p - 1) * nb + t],
+         u2x = U2[(p - 1) * nb + t];
+  for (int i = p - 1; i >= 0; --i) {
+    const double zr = zx, u0 = u0x, u1 = u1x, u2 = u2x;
+    if (i > 0) {
+      zx = Z[(i - 1) * ldz + j];
+      u0x = U0[(i - 1) * nb + t];
+      u1x = U1[(i - 1) * nb + t];
+      u2x = U2[(i - 1) * nb + t];
+    }
+    const double zi = (zr - u1 * z1 - u2 * z2) * u0;
+    Z[i * ldz + j] = zi;
+    zmax = fmax(zmax, fabs(zi));
+    z2 = z1;
+    z1 = zi;
+  }
+  const double sc = (zmax > 0.0 && zmax < INFINITY) ? 1.0 / zmax : 1.0;
+#pragma unroll 4
+  for (int i = 0; i < p; ++i) Z[i * ldz + j] *= sc;
+}
+
+// Z (p x n, n <= p) <- Z L^-T with L L^T = Z^T Z, by one wave; G (n x n,
+// stride ldg) and linv are scratch.  False when a pivot is not > 0.
+template <int NR>
+__device__ bool wave_cholqr(double* Z, int ldz, int p, int n, double* G, int ldg, double* linv) {
+  const int l = threadIdx.x & 63;
+  for (int idx = l; idx < n * n; idx += 64) {
+    const int r = idx / n, c = idx - r * n;
+    if (c > r) continue;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = 0;
+    for (; i + 4 <= p; i += 4) {
+      s0 += Z[i * ldz + r] * Z[i * ldz + c];
+      s1 += Z[(i + 1) * ldz + r] * Z[(i + 1) * ldz + c];
+      s2 += Z[(i + 2) * ldz + r] * Z[(i + 2) * ldz + c];
+      s3 += Z[(i + 3) * ldz + r] * Z[(i + 3) * ldz + c];
+    }
+    for (; i < p; ++i) s0 += Z[i * ldz + r] * Z[i * ldz + c];
+    G[r * ldg + c] = (s0 + s1) + (s2 + s3);
+  }
+  wave_sync();
+  for (int k = 0; k < n; ++k) {
+    const double gkk = G[k * ldg + k];
+    if (!(gkk > 0.0) || !(gkk < INFINITY)) return false;
+    const double lkk = sqrt(gkk), inv = 1.0 / lkk;
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+      const int r = l + 64 * h;
+      if (r > k && r < n) G[r * ldg + k] *= inv;
+    }
+    if (l == 0) {
+      G[k * ldg + k] = lkk;
+      linv[k] = inv;
+    }
+    wave_sync();
+    // trailing update, lane c owning column c: G[r][c] -= L[r][k] L[c][k], r >= c > k
+#pragma unroll
+    for (int h = 0; h < NR; ++h) {
+      const int c = l + 64 * h;
+      if (c > k && c < n) {
+        const double lck = G[c * ldg + k];
+        for (int r0 = c; r0 < n; r0 += 4) {
+          double lk[4], gc[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = min(r0 + u, n - 1);
+            lk[u] = G[r * ldg + k];
+            gc[u] = G[r * ldg + c];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (r0 + u < n) G[(r0 + u) * ldg + c] = gc[u] - lk[u] * lck;
+        }
+      }
+    }
+    wave_sync();
+  }
+#pragma unroll
+  for (int h = 0; h < NR; ++h) {
+    const int i = l + 64 * h;
+    if (i < p) {
+      for (int jj = 0; jj < n; ++jj) {
+        double s0 = Z[i * ldz + jj], s1 = 0.0;
+        int k = 0;
+        for (; k + 2 <= jj; k += 2) {
+          s0 -= Z[i * ldz + k] * G[jj * ldg + k];
+          s1 -= Z[i * ldz + k + 1] * G[jj * ldg + k + 1];
+        }
+        if (k < jj) s0 -= Z[i * ldz + k] * G[jj * ldg + k];
+        Z[i * ldz + jj] = (s0 + s1) * linv[jj];
+      }
+    }
+  }
+  wave_sync();
+  return true;
+}
+
+// The whole path (1-5).  A: p x lda in LDS (destroyed); base: the area after
+// A laid out by tri_layout(p, nev), whose ev and Z receive the result.  Every
+// thread calls it; the return value is uniform.
+__device__ bool blk_tri_eigh(double* A, int lda, int p, int nev, double* base, const TriLayout& L,
+                             int* flag) {
+  double* d = base + L.d;
+  double* e = base + L.e;
+  double* inve = base + L.inve;
+  double* e2 = base + L.e2;
+  double* beta = base + L.beta;
+  double* ev = base + L.ev;
+  double* Z = base + L.Z;
+  const int ldz = L.ldz;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave == 0) {
+    if (p <= 64) wave_tridiag<1>(A, lda, p, d, e, beta, base + L.vv, base + L.ww);
+    else wave_tridiag<2>(A, lda, p, d, e, beta, base + L.vv, base + L.ww);
+  }
+  __syncthreads();
+  // Gershgorin interval, ||T||, pivmin (every thread, same order)
+  double gl = INFINITY, gu = -INFINITY, emax2 = 0.0;
+  for (int i = 0; i < p; ++i) {
+    const double r = ((i > 0) ? fabs(e[i - 1]) : 0.0) + ((i + 1 < p) ? fabs(e[i]) : 0.0);
+    gl = fmin(gl, d[i] - r);
+    gu = fmax(gu, d[i] + r);
+    if (i + 1 < p) emax2 = fmax(emax2, e[i] * e[i]);
+  }
+  const double tnorm = fmax(fabs(gl), fabs(gu));
+  if (!(tnorm < INFINITY)) return false;
+  if (tnorm == 0.0) {  // the zero matrix
+    for (int idx = threadIdx.x; idx < p * nev; idx += blockDim.x) {
+      const int i = idx / nev, j = idx - i * nev;
+      Z[i * ldz + j] = (i == j) ? 1.0 : 0.0;
+    }
+    for (int j = threadIdx.x; j < nev; j += blockDim.x) ev[j] = 0.0;
+    __syncthreads();
+    return true;
+  }
+  const double pivmin = 0x1.0p-1022 * fmax(1.0, emax2);
+  const double tol = kEps * tnorm;
+  const double widen = 2.1 * (kEps * tnorm * p + 2.0 * pivmin);
+  gl -= widen;
+  gu += widen;
+  for (int i = threadIdx.x; i + 1 < p; i += blockDim.x) {
+    e2[i] = e[i] * e[i];
+    const double piv = (fabs(e[i]) < tol) ? ((e[i] < 0.0) ? -tol : tol) : e[i];
+    inve[i] = (e[i] == 0.0) ? 0.0 : 1.0 / piv;
+  }
+  __syncthreads();
+  blk_multisection(d, e2, p, nev, gl, gu, tnorm, pivmin, ev);
+  // start vectors
+  for (int idx = threadIdx.x; idx < p * nev; idx += blockDim.x) {
+    const int i = idx / nev, j = idx - i * nev;
+    const uint64_t z = sm64(kZeroColumnSeed ^ (0x5EEDull << 32) ^ ((uint64_t)j * (uint64_t)p + (uint64_t)i));
+    Z[i * ldz + j] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+  }
+  __syncthreads();
+  // two solves with a Cholesky-QR between them (block inverse iteration);
+  // with several batches the LU is rebuilt for the second solve
+  const int nb = L.nb;
+  for (int it = 0; it < 2; ++it) {
+    for (int j0 = 0; j0 < nev; j0 += nb) {
+      const int t = threadIdx.x;
+      if (t < nb && j0 + t < nev) {
+        const int j = j0 + t;
+        tri_invit_solve(d, e, inve, p, ev[j], tol, Z, ldz, j, base + L.ws,
+                        reinterpret_cast<uint8_t*>(base + L.sw), nb, t, it == 0 || nb < nev);
+      }
+      __syncthreads();
+    }
+    if (it == 0) {
+      if (wave == 0) {
+        const bool ok = (p <= 64) ? wave_cholqr<1>(Z, ldz, p, nev, base + L.G, nev + 1, base + L.linv)
+                                  : wave_cholqr<2>(Z, ldz, p, nev, base + L.G, nev + 1, base + L.linv);
+        if (lane == 0) *flag = ok ? 1 : 0;
+      }
+      __syncthreads();
+      const bool ok = *flag != 0;
+      __syncthreads();
+      if (!ok) return false;
+    }
+  }
+  // u = H_0 H_1 ... H_{p-3} z, one wave per vector
+  const int nw = blockDim.x >> 6;
+  for (int j = wave; j < nev; j += nw) {
+    double z[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      z[h] = (i < p) ? Z[i * ldz + j] : 0.0;
+    }
+#pragma unroll 2
+    for (int k = p - 3; k >= 0; --k) {
+      const double b = beta[k];  // 0 for H_k = I: then s = 0
+      double v[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        v[h] = (i > k && i < p) ? A[i * lda + k] : 0.0;
+      }
+      const double s = b * wave_sum(v[0] * z[0] + v[1] * z[1]);
+      z[0] -= s * v[0];
+      z[1] -= s * v[1];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      if (i < p) Z[i * ldz + j] = z[h];
+    }
+  }
+  __syncthreads();
+  // Cholesky-QR twice, with the A area as Gram scratch
+  if (wave == 0) {
+    bool ok = true;
+    for (int pass = 0; pass < 2 && ok; ++pass)
+      ok = (p <= 64) ? wave_cholqr<1>(Z, ldz, p, nev, A, lda, base + L.linv)
+                     : wave_cholqr<2>(Z, ldz, p, nev, A, lda, base + L.linv);
+    if (lane == 0) *flag = ok ? 1 : 0;
+  }
+  __syncthreads();
+  const bool ok = *flag != 0;
+  __syncthreads();
+  return ok;
+}
+
 __global__ __launch_bounds__(1024) void k_small_eigh(const double* __restrict__ a, int p,
                                                     double* __restrict__ evals,
                                                     double* __restrict__ evecs, int* sweeps) {
   extern __shared__ double smem[];
-  EigLds L = eig_lds(smem, p, 1);
+  __shared__ int tflag;
   const int ld = p + 1;
+  const TriLayout T = tri_layout(p, p);
+  if (T.nb >= 1) {
+    load_sym(a, p, smem, ld);
+    double* base = smem + p * ld;
+    if (blk_tri_eigh(smem, ld, p, p, base, T, &tflag)) {
+      for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
+        const int i = idx / p, j = idx - i * p;
+        const double sg = (base[T.Z + j * T.ldz + j] < 0.0) ? -1.0 : 1.0;
+        evecs[i * p + j] = sg * base[T.Z + i * T.ldz + j];
+      }
+      for (int j = threadIdx.x; j < p; j += blockDim.x) evals[j] = base[T.ev + j];
+      if (threadIdx.x == 0 && sweeps != nullptr) *sweeps = 0;
+      return;
+    }
+  }
+  EigLds L = eig_lds(smem, p, 1);
   load_sym(a, p, L.A, ld);
   const int sw = blk_jacobi(L.A, ld, L.V, ld, p, L.cs, L.pr, L.flags, L.scratch);
   blk_sort_evals(L.A, ld, p, L.perm);
   for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
     const int i = idx / p, j = idx - i * p;
-    evecs[i * p + j] = L.V[i * ld + L.perm[j]];
+    const double sg = (L.V[j * ld + L.perm[j]] < 0.0) ? -1.0 : 1.0;
+    evecs[i * p + j] = sg * L.V[i * ld + L.perm[j]];
   }
   for (int j = threadIdx.x; j < p; j += blockDim.x) evals[j] = L.A[L.perm[j] * ld + L.perm[j]];
   if (threadIdx.x == 0 && sweeps != nullptr) *sweeps = sw;
@@ -447,8 +1022,7 @@ hipError_t small_eigh(const double* a, int p, double* evals, double* evecs, int*
     (void)hipGetLastError();
     attr = true;
   }
-  hipLaunchKernelGGL(k_small_eigh, dim3(1), dim3(1024), eig_lds_bytes(p, 1), s, a, p, evals, evecs,
-                     sweeps);
+  hipLaunchKernelGGL(k_small_eigh, dim3(1), dim3(1024), kEigLdsBytes, s, a, p, evals, evecs, sweeps);
   return hipGetLastError();
 }
 
@@ -484,47 +1058,72 @@ __device__ __forceinline__ bool blk_svqb_coef(const double* M, int ldm, int n, d
 // eigenvectors; optionally u_p = ortho(u_x[:, a0:m] - E[:, a0:m]; u_x) in R^p
 // by Alg. 3 / Alg. 2 (the same readings as on n-vectors).
 
-__global__ __launch_bounds__(1024) void k_small_rr(const double* __restrict__ a, int p, int m,
-                                                  int a0, int want_up, double tau,
-                                                  const OrthoState* __restrict__ pend, int woff,
-                                                  double* __restrict__ theta_all,
-                                                  double* __restrict__ U, int* __restrict__ info) {
-  extern __shared__ double smem[];
-  EigLds L = eig_lds(smem, p, m);
-  const int ld = p + 1;
-  __shared__ ShiftCount cnt;
-  __shared__ int zeros;
-  __shared__ int stalled, passes, grams, updates;
-  if (threadIdx.x == 0) {
-    cnt.factorizations = cnt.failed = cnt.shifted = cnt.svqb = 0;
-    zeros = stalled = passes = grams = updates = 0;
-  }
-  load_sym(a, p, L.A, ld);
-  // pending column scaling of the W block (see small_rr in internal.h)
-  double* dsc = L.scratch + 0;  // not used by load_sym; only read below
-  const bool scaled = (pend != nullptr) && pend->pending_scale;
-  if (scaled) {
+// sym(a) into A (stride lda), with the pending column scaling of the W block
+// (see small_rr in internal.h) applied from both sides when pend != nullptr
+__device__ void load_rr_matrix(const double* a, int p, double* A, int lda, const OrthoState* pend,
+                               int woff) {
+  load_sym(a, p, A, lda);
+  if (pend != nullptr) {
     const int nws = pend->nw;
     for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
       const int i = idx / p, j = idx - i * p;
       const double di = (i >= woff && i < woff + nws) ? pend->dscale[i - woff] : 1.0;
       const double dj = (j >= woff && j < woff + nws) ? pend->dscale[j - woff] : 1.0;
-      L.A[i * ld + j] *= di * dj;
+      A[i * lda + j] *= di * dj;
     }
     __syncthreads();
   }
-  (void)dsc;
-  const int sw = blk_jacobi(L.A, ld, L.V, ld, p, L.cs, L.pr, L.flags, L.scratch);
-  blk_sort_evals(L.A, ld, p, L.perm);
-  for (int j = threadIdx.x; j < p; j += blockDim.x) theta_all[j] = L.A[L.perm[j] * ld + L.perm[j]];
-  __syncthreads();
-  // sorted eigenvectors into the A area (stride ld): Us[:, j] = V[:, perm[j]]
-  double* Us = L.A;
-  for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
-    const int i = idx / p, j = idx - i * p;
-    Us[i * ld + j] = L.V[i * ld + L.perm[j]];
+}
+
+__global__ __launch_bounds__(1024) void k_small_rr(const double* __restrict__ a, int p, int m,
+                                                  int a0, int want_up, double tau,
+                                                  const OrthoState* __restrict__ pend, int woff,
+                                                  double* __restrict__ theta_all,
+                                                  double* __restrict__ U, int* __restrict__ info,
+                                                  int jacobi) {
+  extern __shared__ double smem[];
+  EigLds L = eig_lds(smem, p, m);
+  const int ld = p + 1;
+  __shared__ ShiftCount cnt;
+  __shared__ int zeros;
+  __shared__ int stalled, passes, grams, updates, tflag;
+  if (threadIdx.x == 0) {
+    cnt.factorizations = cnt.failed = cnt.shifted = cnt.svqb = 0;
+    zeros = stalled = passes = grams = updates = 0;
   }
-  __syncthreads();
+  const bool scaled = (pend != nullptr) && pend->pending_scale;
+  double* Us = L.A;  // sorted eigenvectors u_x (first m columns), stride ld
+  int sw = 0;
+  const TriLayout T = tri_layout(p, m);
+  bool tri = false;
+  if (!jacobi && T.nb >= 1) {
+    load_rr_matrix(a, p, L.A, ld, scaled ? pend : nullptr, woff);
+    double* base = L.A + p * ld;
+    tri = blk_tri_eigh(L.A, ld, p, m, base, T, &tflag);
+    if (tri) {
+      for (int j = threadIdx.x; j < m; j += blockDim.x) theta_all[j] = base[T.ev + j];
+      // orientation: u[j][j] >= 0, so that u_x - E is the small update X_new - X_old
+      for (int idx = threadIdx.x; idx < p * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx - i * m;
+        const double sg = (base[T.Z + j * T.ldz + j] < 0.0) ? -1.0 : 1.0;
+        Us[i * ld + j] = sg * base[T.Z + i * T.ldz + j];
+      }
+      __syncthreads();
+    }
+  }
+  if (!tri) {
+    load_rr_matrix(a, p, L.A, ld, scaled ? pend : nullptr, woff);
+    sw = blk_jacobi(L.A, ld, L.V, ld, p, L.cs, L.pr, L.flags, L.scratch);
+    blk_sort_evals(L.A, ld, p, L.perm);
+    for (int j = threadIdx.x; j < m; j += blockDim.x) theta_all[j] = L.A[L.perm[j] * ld + L.perm[j]];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
+      const int i = idx / p, j = idx - i * p;
+      const double sg = (L.V[j * ld + L.perm[j]] < 0.0) ? -1.0 : 1.0;
+      Us[i * ld + j] = sg * L.V[i * ld + L.perm[j]];
+    }
+    __syncthreads();
+  }
   const int na = want_up ? (m - a0) : 0;
   const int q = m + na;
   // u_x (row scaling for a pending W scaling is applied when U is written)
@@ -623,12 +1222,13 @@ __global__ __launch_bounds__(1024) void k_small_rr(const double* __restrict__ a,
     info[8] = stalled;
     info[9] = cnt.svqb;
     info[10] = zeros;
+    info[11] = (tri || jacobi) ? 0 : 1;  // Jacobi fallback of the eigensolve
   }
 }
 
 hipError_t small_rr(const double* a, int p, int m, int a0, int want_up, double tau,
                     const OrthoState* pend, int woff, double* theta_all, double* U, int* info,
-                    hipStream_t s) {
+                    int jacobi, hipStream_t s) {
   if (p < 1 || p > kMaxP || m < 1 || m > p || a0 < 0 || a0 > m) return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
@@ -638,8 +1238,8 @@ hipError_t small_rr(const double* a, int p, int m, int a0, int want_up, double t
     (void)hipGetLastError();
     attr = true;
   }
-  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(1024), eig_lds_bytes(p, m), s, a, p, m, a0, want_up, tau,
-                     pend, woff, theta_all, U, info);
+  hipLaunchKernelGGL(k_small_rr, dim3(1), dim3(1024), kEigLdsBytes, s, a, p, m, a0, want_up, tau,
+                     pend, woff, theta_all, U, info, jacobi);
   return hipGetLastError();
 }
 

@@ -508,21 +508,37 @@ int lobpcg_learner_objective(lobpcg_learner_t L, int snap, const int* cols, int 
   return L->objective(S, cols, ncols, loss, grad, learned_decrease, jacobi_decrease);
 }
 
+constexpr double kTrainResidualFloor = 1e-9;
+
 int lobpcg_learner_train(lobpcg_learner_t L, int steps, int cols_per_step, double lr,
                          uint64_t seed, double* loss_first, double* loss_last) {
   LGUARD(L);
   if (L->snaps.empty()) return L->fail(LOBPCG_ERR_BAD_STATE, "no snapshots");
   if (steps < 1 || cols_per_step < 1 || !(lr > 0.0))
     return L->fail(LOBPCG_ERR_INVALID_ARG, "bad training arguments");
+  // Columns whose residual is at rounding level carry no training signal:
+  // their R (and so the learned step and the MINRES correction) is the
+  // rounding of the product A X, ~eps sqrt(n) ||A||.  Only columns with
+  // ||r_j|| > kTrainResidualFloor max(1, |theta_j|) are sampled.
+  std::vector<std::vector<int>> elig(L->snaps.size());
+  std::vector<int> usable;
+  for (size_t q = 0; q < L->snaps.size(); ++q) {
+    const Snapshot& S = L->snaps[q];
+    for (int j = 0; j < S.m; ++j)
+      if (S.rn_h[j] > kTrainResidualFloor * std::max(1.0, std::fabs(S.th_h[j]))) elig[q].push_back(j);
+    if (!elig[q].empty()) usable.push_back((int)q);
+  }
+  if (usable.empty()) return L->fail(LOBPCG_ERR_BAD_STATE, "no snapshot column above the residual floor");
   uint64_t s = seed;
   const int tail = std::max(1, steps / 10);
   double first = 0.0, last = 0.0;
   for (int t = 0; t < steps; ++t) {
-    Snapshot& S = L->snaps[splitmix(s) % L->snaps.size()];
-    const int nc = std::min(cols_per_step, S.m);
-    std::vector<int> perm(S.m);
-    for (int j = 0; j < S.m; ++j) perm[j] = j;
-    for (int j = 0; j < nc; ++j) std::swap(perm[j], perm[j + splitmix(s) % (S.m - j)]);
+    const int q = usable[splitmix(s) % usable.size()];
+    Snapshot& S = L->snaps[q];
+    std::vector<int> perm(elig[q]);
+    const int ne = (int)perm.size();
+    const int nc = std::min(cols_per_step, ne);
+    for (int j = 0; j < nc; ++j) std::swap(perm[j], perm[j + splitmix(s) % (ne - j)]);
     std::sort(perm.begin(), perm.begin() + nc);
     double loss = 0.0;
     int rc = L->objective(S, perm.data(), nc, &loss, nullptr, nullptr, nullptr, true);

@@ -406,7 +406,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     int a0 = m_conv;
     int nact = m - a0;
     HIPCHK(small_rr(a, L, m, a0, want_up, tau_phase, pend_valid ? pend : nullptr, pend_woff, theta,
-                    U, info, stream));
+                    U, info, rr_jacobi, stream));
     int q = m + (want_up ? nact : 0);
     int ldo = q + nact;
     RotateArgs ra{};
@@ -434,6 +434,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     HIPCHK(hipStreamSynchronize(stream));
     const int* hinfo = reinterpret_cast<const int*>(h + 128);
     if (hinfo[1] != 0) return fail(LOBPCG_ERR_ORTHO_FAILED, "R^p orthonormalisation of u_p failed");
+    stats.rr_eig_fallbacks += hinfo[11];
     double rmax = 0.0;
     for (int j = 0; j < m; ++j) {
       rnorm[j] = std::sqrt(h[j]);
@@ -504,7 +505,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       a0 = m_conv;
       nact = m - a0;
       HIPCHK(small_rr(a, L, m, a0, want_up, tau_phase, pend_valid ? pend : nullptr, pend_woff,
-                      theta, U, info, stream));
+                      theta, U, info, rr_jacobi, stream));
       q = m + (want_up ? nact : 0);
       ldo = q + nact;
       ra.ldo = ldo;
@@ -694,6 +695,9 @@ int lobpcg_set_option(lobpcg_t h, int key, double v) {
       return LOBPCG_OK;
     case LOBPCG_OPT_LEARNED_BF16:
       h->learned_bf16 = (v != 0.0);
+      return LOBPCG_OK;
+    case LOBPCG_OPT_RR_JACOBI:
+      h->rr_jacobi = (v != 0.0);
       return LOBPCG_OK;
     default: return h->fail(LOBPCG_ERR_INVALID_ARG, "unknown option");
   }

@@ -168,6 +168,46 @@ def test_brute_force_dense(P, kind):
     check_pairs(res, O.dense_operator(A), w[:k], 1e-9, normA=abs(w).max())
 
 
+@pytest.mark.parametrize("kind", ["random", "degenerate", "kronsum"])
+def test_rr_eigensolvers_agree(P, kind):
+    """The two Rayleigh-Ritz eigensolvers (tridiagonal path, the default,
+    and Jacobi) reach the same pairs; the tridiagonal path never falls back.
+    The degenerate and Kronecker-sum cases have repeated eigenvalues, where
+    the tridiagonal path orthonormalises inverse-iteration mixtures."""
+    if kind == "kronsum":
+        na = 24
+        g = synth.rng(41)
+        B = g.standard_normal((na, na))
+        A1 = 0.5 * (B + B.T) + 6.0 * np.eye(na)
+        n = na * na
+        A = np.kron(A1, np.eye(na)) + np.kron(np.eye(na), A1)  # eigenvalues l_i + l_j: pairs repeat
+    elif kind == "degenerate":
+        n = 200
+        lam = np.concatenate([[-1.0, 0.5, 0.5, 0.5, 2.0, 2.0], np.linspace(3.0, 10.0, n - 6)])
+        A, _ = synth.prescribed_spectrum(lam, 43)
+    else:
+        n = 300
+        A = synth.dense_dd(n, seed=44)
+    k = 6
+    w = np.linalg.eigvalsh(A)
+    X0 = synth.start_block(n, k, 45)
+    out = {}
+    for jac in (0, 1):
+        s = P.Solver(n)
+        s.set_operator_dense(cu(A))
+        s.set_preconditioner(1)
+        s.set_option(P.OPT_RR_JACOBI, jac)
+        s.set_option(P.OPT_MAX_ITER, 3000)
+        s.set_initial_guess(cu(X0))
+        res = s.solve(k, 1e-9)
+        res.evecs_np = res.evecs.cpu().numpy()
+        check_pairs(res, O.dense_operator(A), w[:k], 1e-9, normA=abs(w).max())
+        out[jac] = res
+        say(kind, "jacobi" if jac else "tridiagonal", res.stats["iterations"], res.stats["rr_eig_fallbacks"])
+    assert out[0].stats["rr_eig_fallbacks"] == 0
+    assert np.allclose(out[0].evals, out[1].evals, rtol=0, atol=1e-9 * abs(w).max())
+
+
 def test_extra_block_vectors_and_locking(P):
     n = 400
     d = np.concatenate([[1.0, 2.0, 4.0, 8.0], np.linspace(20.0, 40.0, n - 4)])
