@@ -23,7 +23,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 enum OpKind { kOpNone = 0, kOpCsr = 1, kOpDense = 2, kOpKron = 3 };
 
 struct Layout {
-  size_t V[2], AV[2], diag, rho, part, small, total;
+  size_t V[2], AV[2], diag, rho, ltiles, part, small, total;
   size_t V32[2], AV32[2], op32;  // mixed precision only (0 otherwise)
   // inside small (byte offsets)
   size_t a, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye, lmask, lflags, lscale;
@@ -88,6 +88,8 @@ struct lobpcg_ctx {
 
   // ---- helpers ----
   double* dptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
+  // super-tile list of the bf16 learned transform: up to 64 columns
+  int64_t ltiles_cap() const { return (n * 64 + lobpcg::kMlpSuper - 1) / lobpcg::kMlpSuper; }
   template <typename T> T* small_ptr(size_t off) const {
     return reinterpret_cast<T*>(ws + lay.small + off);
   }

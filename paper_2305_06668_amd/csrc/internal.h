@@ -29,6 +29,7 @@ constexpr int kMlpFeat = 3;
 constexpr int kMlpParams = kMlpHidden * kMlpFeat + kMlpHidden + kMlpHidden * kMlpHidden +
                            kMlpHidden + kMlpHidden + 1;
 constexpr int kMlpBlocks = 256;  // persistent grid of the MLP kernels
+constexpr int kMlpSuper = 256;   // entries per screened super tile of the bf16 transform
 constexpr double kMlpWindow = 16.0;  // the net acts where |d - theta| <= kMlpWindow * rho
 
 // Device-side state of one ortho(W; Y) call (Alg. 2 nested in Alg. 3).
@@ -184,12 +185,17 @@ hipError_t mlp_apply_f32(float* R, int64_t ld, int nact, int64_t n, const double
                          const int* mask, int* flags, hipStream_t st);
 // The same transform with layer 2 on bf16 MFMA (fp32 accumulate): the
 // solver's inference path.
+// tiles: device scratch of 1 + tiles_cap ints (count, then the list of
+// super tiles of kMlpSuper entries that hold window entries); tiles_cap must
+// be >= ceil(n nact / kMlpSuper)
 hipError_t mlp_apply_bf16_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, hipStream_t st);
+                              const float* w, const int* mask, int* flags, int* tiles,
+                              int64_t tiles_cap, hipStream_t st);
 hipError_t mlp_apply_bf16_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, hipStream_t st);
+                              const float* w, const int* mask, int* flags, int* tiles,
+                              int64_t tiles_cap, hipStream_t st);
 // grad (kMlpParams doubles) = d/dweights of sum_e G_e w_e(weights), with w
 // the learned columns of R; part needs kMlpBlocks * kMlpParams doubles.
 hipError_t mlp_grad(const double* R, const double* G, int64_t ld, int nact, int64_t n,

@@ -517,115 +517,86 @@ __host__ __device__ inline TriLayout tri_layout(int p, int nev) {
   return t;
 }
 
-// NR = rows per lane (1 for p <= 64, else 2)
-template <int NR>
-__device__ void wave_tridiag(double* A, int lda, int p, double* d, double* e, double* beta, double* vv,
-                             double* ww) {
-  const int l = threadIdx.x & 63;
+// Householder reduction by the whole workgroup, three barriers per step:
+// wave 0 forms reflector k from row k (= column k, the trailing block is
+// kept symmetric); each wave takes rows i of p = beta A v, its lanes
+// splitting the row; every thread then updates trailing entries with
+// w = p - K v, K = beta/2 p^T v (formed by every wave in the same order).
+__device__ void blk_tridiag(double* A, int lda, int p, double* d, double* e, double* beta, double* vv,
+                            double* pp) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
   for (int k = 0; k + 2 < p; ++k) {
-    const int k1 = k + 1;
-    double x[NR];
-    bool act[NR];
-    int ic[NR];
-    double tail = 0.0;
+    const int k1 = k + 1, s = p - k1;
+    if (wave == 0) {
+      double x[2];
+      double tail = 0.0;
 #pragma unroll
-    for (int h = 0; h < NR; ++h) {
-      const int i = l + 64 * h;
-      act[h] = i > k && i < p;
-      ic[h] = min(i, p - 1);
-      x[h] = act[h] ? A[i * lda + k] : 0.0;
-      if (i > k1) tail += x[h] * x[h];
-    }
-    const double x1 = A[k1 * lda + k];
-    tail = wave_sum(tail);
-    double alpha = x1, b = 0.0;
-    if (tail > 0.0) {
-      const double nrm = sqrt(x1 * x1 + tail);
-      alpha = (x1 >= 0.0) ? -nrm : nrm;
-      b = 1.0 / (nrm * (nrm + fabs(x1)));  // 2 / v^T v for v = x - alpha e_1
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        x[h] = (i > k && i < p) ? A[k * lda + i] : 0.0;
+        if (i > k1) tail += x[h] * x[h];
+      }
+      const double x1 = A[k * lda + k1];
+      tail = wave_sum(tail);
+      double alpha = x1, b = 0.0;
+      if (tail > 0.0) {
+        const double nrm = sqrt(x1 * x1 + tail);
+        alpha = (x1 >= 0.0) ? -nrm : nrm;
+        b = 1.0 / (nrm * (nrm + fabs(x1)));  // 2 / v^T v for v = x - alpha e_1
+      }
 #pragma unroll
-      for (int h = 0; h < NR; ++h) {
-        const int i = l + 64 * h;
-        if (act[h]) {
-          const double v = (i == k1) ? x1 - alpha : x[h];
-          A[i * lda + k] = v;
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        if (i > k && i < p) {
+          const double v = (b != 0.0 && i == k1) ? x1 - alpha : x[h];
+          A[i * lda + k] = v;  // reflector k, kept for the back-transformation
           vv[i] = v;
         }
       }
-    }
-    if (l == 0) {
-      d[k] = A[k * lda + k];
-      e[k] = alpha;
-      beta[k] = b;
-    }
-    wave_sync();
-    if (b == 0.0) continue;  // H_k = I
-    // p = beta A v on the trailing block (A[i][j] read as A[j][i])
-    double pv[NR], vi[NR];
-#pragma unroll
-    for (int h = 0; h < NR; ++h) {
-      pv[h] = 0.0;
-      vi[h] = act[h] ? vv[l + 64 * h] : 0.0;
-    }
-    for (int j0 = k1; j0 < p; j0 += 8) {
-      double vj[8], aj[8][NR];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int j = min(j0 + u, p - 1);
-        vj[u] = (j0 + u < p) ? vv[j] : 0.0;
-#pragma unroll
-        for (int h = 0; h < NR; ++h) aj[u][h] = A[j * lda + ic[h]];
+      if (lane == 0) {
+        d[k] = A[k * lda + k];
+        e[k] = alpha;
+        beta[k] = b;
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int h = 0; h < NR; ++h) pv[h] += aj[u][h] * vj[u];
     }
+    __syncthreads();
+    const double b = beta[k];
+    if (b == 0.0) continue;  // H_k = I (uniform)
+    for (int i = k1 + wave; i < p; i += nw) {
+      double acc = 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = k1 + lane + 64 * h;
+        if (j < p) acc += A[i * lda + j] * vv[j];
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) pp[i] = b * acc;
+    }
+    __syncthreads();
     double kp = 0.0;
 #pragma unroll
-    for (int h = 0; h < NR; ++h) {
-      pv[h] = act[h] ? b * pv[h] : 0.0;
-      kp += pv[h] * vi[h];
+    for (int h = 0; h < 2; ++h) {
+      const int i = k1 + lane + 64 * h;
+      if (i < p) kp += pp[i] * vv[i];
     }
     const double K = 0.5 * b * wave_sum(kp);
-    double wv[NR];
-#pragma unroll
-    for (int h = 0; h < NR; ++h) {
-      wv[h] = pv[h] - K * vi[h];
-      if (act[h]) ww[l + 64 * h] = wv[h];
+    for (int idx = tid; idx < s * s; idx += blockDim.x) {
+      const int jj = idx / s, ii = idx - jj * s;
+      const int j = k1 + jj, i = k1 + ii;
+      const double vj = vv[j], vi = vv[i];
+      const double wi = pp[i] - K * vi, wj = pp[j] - K * vj;
+      A[j * lda + i] -= vj * wi + wj * vi;
     }
-    wave_sync();
-    // A <- A - v w^T - w v^T on the trailing block, lane i owning column i;
-    // chunks of 8 rows with every load issued before the chunk's stores
-    for (int j0 = k1; j0 < p; j0 += 8) {
-      double vj[8], wj[8], aj[8][NR];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int j = min(j0 + u, p - 1);
-        vj[u] = vv[j];
-        wj[u] = ww[j];
-#pragma unroll
-        for (int h = 0; h < NR; ++h) aj[u][h] = A[j * lda + ic[h]];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (j0 + u < p) {
-#pragma unroll
-          for (int h = 0; h < NR; ++h)
-            if (act[h]) A[(j0 + u) * lda + ic[h]] = aj[u][h] - (vj[u] * wv[h] + wj[u] * vi[h]);
-        }
-      }
-    }
-    wave_sync();
+    __syncthreads();
   }
-  if (l == 0) {
+  if (tid == 0) {
     if (p >= 2) {
       d[p - 2] = A[(p - 2) * lda + p - 2];
       e[p - 2] = A[(p - 1) * lda + p - 2];
     }
     d[p - 1] = A[(p - 1) * lda + p - 1];
   }
-  wave_sync();
+  __syncthreads();
 }
 
 // 1 / q to ~1 ulp: the hardware reciprocal and one Newton step (the Sturm
@@ -777,12 +748,10 @@ __device__ void tri_invit_solve(const double* __restrict__ d, const double* __re
   for (int i = 0; i < p; ++i) Z[i * ldz + j] *= sc;
 }
 
-// Z (p x n, n <= p) <- Z L^-T with L L^T = Z^T Z, by one wave; G (n x n,
-// stride ldg) and linv are scratch.  False when a pivot is not > 0.
-template <int NR>
-__device__ bool wave_cholqr(double* Z, int ldz, int p, int n, double* G, int ldg, double* linv) {
-  const int l = threadIdx.x & 63;
-  for (int idx = l; idx < n * n; idx += 64) {
+// G (lower, n x n, stride ldg) <- Z^T Z for Z (p x n, stride ldz), every
+// thread; ends with a barrier
+__device__ void blk_gram_lower(const double* Z, int ldz, int p, int n, double* G, int ldg) {
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
     const int r = idx / n, c = idx - r * n;
     if (c > r) continue;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -796,6 +765,14 @@ __device__ bool wave_cholqr(double* Z, int ldz, int p, int n, double* G, int ldg
     for (; i < p; ++i) s0 += Z[i * ldz + r] * Z[i * ldz + c];
     G[r * ldg + c] = (s0 + s1) + (s2 + s3);
   }
+  __syncthreads();
+}
+
+// Z <- Z L^-T with L L^T = G (the Gram Z^T Z from blk_gram_lower), by one
+// wave; G is overwritten by L.  False when a pivot is not > 0.
+template <int NR>
+__device__ bool wave_cholqr(double* Z, int ldz, int p, int n, double* G, int ldg, double* linv) {
+  const int l = threadIdx.x & 63;
   wave_sync();
   for (int k = 0; k < n; ++k) {
     const double gkk = G[k * ldg + k];
@@ -867,11 +844,7 @@ __device__ bool blk_tri_eigh(double* A, int lda, int p, int nev, double* base, c
   double* Z = base + L.Z;
   const int ldz = L.ldz;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (wave == 0) {
-    if (p <= 64) wave_tridiag<1>(A, lda, p, d, e, beta, base + L.vv, base + L.ww);
-    else wave_tridiag<2>(A, lda, p, d, e, beta, base + L.vv, base + L.ww);
-  }
-  __syncthreads();
+  blk_tridiag(A, lda, p, d, e, beta, base + L.vv, base + L.ww);
   // Gershgorin interval, ||T||, pivmin (every thread, same order)
   double gl = INFINITY, gu = -INFINITY, emax2 = 0.0;
   for (int i = 0; i < p; ++i) {
@@ -924,6 +897,7 @@ __device__ bool blk_tri_eigh(double* A, int lda, int p, int nev, double* base, c
       __syncthreads();
     }
     if (it == 0) {
+      blk_gram_lower(Z, ldz, p, nev, base + L.G, nev + 1);
       if (wave == 0) {
         const bool ok = (p <= 64) ? wave_cholqr<1>(Z, ldz, p, nev, base + L.G, nev + 1, base + L.linv)
                                   : wave_cholqr<2>(Z, ldz, p, nev, base + L.G, nev + 1, base + L.linv);
@@ -965,17 +939,19 @@ __device__ bool blk_tri_eigh(double* A, int lda, int p, int nev, double* base, c
   }
   __syncthreads();
   // Cholesky-QR twice, with the A area as Gram scratch
-  if (wave == 0) {
-    bool ok = true;
-    for (int pass = 0; pass < 2 && ok; ++pass)
-      ok = (p <= 64) ? wave_cholqr<1>(Z, ldz, p, nev, A, lda, base + L.linv)
-                     : wave_cholqr<2>(Z, ldz, p, nev, A, lda, base + L.linv);
-    if (lane == 0) *flag = ok ? 1 : 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    blk_gram_lower(Z, ldz, p, nev, A, lda);
+    if (wave == 0) {
+      const bool ok = (p <= 64) ? wave_cholqr<1>(Z, ldz, p, nev, A, lda, base + L.linv)
+                                : wave_cholqr<2>(Z, ldz, p, nev, A, lda, base + L.linv);
+      if (lane == 0) *flag = ok ? 1 : 0;
+    }
+    __syncthreads();
+    const bool ok = *flag != 0;
+    __syncthreads();
+    if (!ok) return false;
   }
-  __syncthreads();
-  const bool ok = *flag != 0;
-  __syncthreads();
-  return ok;
+  return true;
 }
 
 __global__ __launch_bounds__(1024) void k_small_eigh(const double* __restrict__ a, int p,

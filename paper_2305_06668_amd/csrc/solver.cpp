@@ -48,6 +48,7 @@ Layout lobpcg_ctx::plan(int m) const {
   L.AV[1] = take(blk);
   L.diag = take((size_t)n * sizeof(double));
   L.rho = take((size_t)n * sizeof(double));
+  L.ltiles = take((size_t)(ltiles_cap() + 1) * sizeof(int));
   const size_t gblk = (size_t)std::min<int64_t>(kGramBlocks, (n + 63) / 64) + 1;
   const size_t part =
       std::max({gblk * kGramMaxCols * kGramMaxCols, (size_t)kStreamBlocks * 3 * 64,
@@ -217,15 +218,17 @@ static hipError_t gram_t(const float* A, int64_t lda, int p, const float* B, int
 static hipError_t mlp_apply_t(bool bf16, double* R, int64_t ld, int nact, int64_t n,
                               const double* theta, const double* diag, const double* rho,
                               const double* s, const float* w, const int* mask, int* flags,
-                              hipStream_t st) {
-  return bf16 ? mlp_apply_bf16_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st)
+                              int* tiles, int64_t tiles_cap, hipStream_t st) {
+  return bf16 ? mlp_apply_bf16_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tiles,
+                                   tiles_cap, st)
               : mlp_apply_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
 }
 static hipError_t mlp_apply_t(bool bf16, float* R, int64_t ld, int nact, int64_t n,
                               const double* theta, const double* diag, const double* rho,
                               const double* s, const float* w, const int* mask, int* flags,
-                              hipStream_t st) {
-  return bf16 ? mlp_apply_bf16_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st)
+                              int* tiles, int64_t tiles_cap, hipStream_t st) {
+  return bf16 ? mlp_apply_bf16_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tiles,
+                                   tiles_cap, st)
               : mlp_apply_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
 }
 static hipError_t rotate_t(const double* V, const double* AV, double* Vo, double* AVo,
@@ -537,7 +540,8 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
       HIPCHK(mlp_apply_t(learned_bf16 != 0, V[1 - c] + q, ldo, nact, n, theta + a0,
                          dptr(lay.diag), dptr(lay.rho), small_ptr<double>(lay.lscale), lweights,
-                         lmask, lflags, stream));
+                         lmask, lflags, reinterpret_cast<int*>(ws + lay.ltiles), ltiles_cap(),
+                         stream));
       prev_a0 = a0;
       prev_nact = nact;
     }
@@ -907,6 +911,7 @@ int lobpcg_learned_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const dou
   hipError_t e = mlp_apply_t(h->learned_bf16 != 0, R, ldr, nact, h->n, theta,
                              h->dptr(h->lay.diag), h->dptr(h->lay.rho),
                              h->small_ptr<double>(h->lay.lscale), h->lweights, mask, nullptr,
+                             reinterpret_cast<int*>(h->ws + h->lay.ltiles), h->ltiles_cap(),
                              h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "learned apply");
   return LOBPCG_OK;
