@@ -603,6 +603,20 @@ __device__ __forceinline__ double precond_apply(double r, double d, double th, i
   return r / den;
 }
 
+// dynamic LDS of k_rotate for a coefficient stride ldc; the stride is padded
+// to 16 (mod 32) when that still fits in 150 KB (it does for every shape
+// but the largest fp64 ones)
+__host__ __device__ inline size_t rotate_smem_bytes(int p, int ldc, size_t tsize) {
+  const size_t tiles = 2 * 64 * (size_t)(p + 1) * tsize > 12 * 256 * sizeof(double)
+                           ? 2 * 64 * (size_t)(p + 1) * tsize
+                           : 12 * 256 * sizeof(double);
+  return tsize * (size_t)((p * ldc + 1) & ~1) + tiles;
+}
+__host__ __device__ inline int rotate_ldc(int p, int q, size_t tsize) {
+  const int padded = q + ((16 - q % 32) + 32) % 32;
+  return rotate_smem_bytes(p, padded, tsize) <= 150 * 1024 ? padded : q;
+}
+
 template <typename T, int MTJ>
 __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T* __restrict__ AV,
                                                 T* __restrict__ Vout, T* __restrict__ AVout,
@@ -614,14 +628,17 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
   const int na = m - a.a0;
   const int no = q + na;  // output columns [X' P' W~]
   const bool want_g = a.gpart != nullptr && na > 0;
+  // coefficient stride = 16 (mod 32): the four k rows a wave reads per MFMA
+  // step fall in different LDS banks
+  const int ldc = rotate_ldc(p, q, sizeof(T));
   T* cf = reinterpret_cast<T*>(smem_d);
-  T* tV = cf + ((p * q + 1) & ~1);
+  T* tV = cf + ((p * ldc + 1) & ~1);
   T* tA = tV + 64 * (p + 1);
   T* tO = tV;  // output tile, reuses the staging area: 64 x (no + 1) <= 2 * 64 * (p + 1)
   const int ldt = p + 1, ldto = no + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kr = lane >> 4, cc = lane & 15;
-  for (int i = threadIdx.x; i < p * q; i += 256) cf[i] = (T)a.U[i];
+  for (int i = threadIdx.x; i < p * q; i += 256) cf[(i / q) * ldc + i % q] = (T)a.U[i];
   double th[MTJ];
   double nacc[MTJ];
 #pragma unroll
@@ -661,7 +678,7 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
 #pragma unroll
       for (int tj = 0; tj < MTJ; ++tj) {
         const int col = tj * 16 + cc;
-        const T b = (kv && col < q) ? cf[kk * q + col] : T(0);
+        const T b = (kv && col < q) ? cf[kk * ldc + col] : T(0);
         ax[tj] = mma(xv, b, ax[tj]);
         aa[tj] = mma(av, b, aa[tj]);
       }
@@ -741,7 +758,7 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
   }
   if (want_g) {
     // fixed-order reduction of G0 over the waves (reusing the staging area)
-    double* red = reinterpret_cast<double*>(cf + ((p * q + 1) & ~1));
+    double* red = reinterpret_cast<double*>(cf + ((p * ldc + 1) & ~1));
     for (int w = 0; w < 4; ++w) {
       if (wave == w) {
 #pragma unroll
@@ -769,8 +786,7 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
 template <typename T>
 static size_t rotate_smem(int p, int q) {
   // the G0 reduction needs 12 * 256 doubles after the coefficient block
-  const size_t tiles = std::max<size_t>(2 * 64 * (p + 1) * sizeof(T), 12 * 256 * sizeof(double));
-  return sizeof(T) * (size_t)((p * q + 1) & ~1) + tiles;
+  return rotate_smem_bytes(p, rotate_ldc(p, q, sizeof(T)), sizeof(T));
 }
 
 template <typename T, int MTJ>

@@ -29,7 +29,9 @@ __global__ __launch_bounds__(256) void k_spmm_csr(const int32_t* __restrict__ rp
   constexpr int GS = (G < 16) ? 16 : G;
   constexpr int NP = GS / G;
   constexpr int RPB = 256 / GS;
-  constexpr int NCH = 2;
+  // narrow blocks (G <= 2) take four chunks per pass: a row's entries then
+  // fit one pass, and every gather of the pass is in flight together
+  constexpr int NCH = (G <= 2) ? 4 : 2;
   const int b = blockIdx.x;
   const int lb = (b & 7) * per_xcd + (b >> 3);
   const int64_t row = (int64_t)lb * RPB + threadIdx.x / GS;
@@ -50,6 +52,28 @@ __global__ __launch_bounds__(256) void k_spmm_csr(const int32_t* __restrict__ rp
       const bool ok = ee < e1;
       colr[k] = ok ? ci[ee] : 0;
       vr[k] = ok ? val[ee] : TV(0);
+    }
+    if constexpr (G <= 4) {
+      // all gathers of the pass first, then the products in the same order
+      // as below (entries past the row end contribute 0 * 0)
+      TW w[NCH][G];
+      TV vv[NCH][G];
+#pragma unroll
+      for (int k = 0; k < NCH; ++k) {
+        const int base_e = e + k * GS;
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const int t = slot + NP * u;
+          const int cidx = __shfl(colr[k], gbase + t, 64);
+          vv[k][u] = __shfl(vr[k], gbase + t, 64);
+          w[k][u] = (active && base_e + t < e1) ? W[(int64_t)cidx * ldw + c] : TW(0);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NCH; ++k)
+#pragma unroll
+        for (int u = 0; u < G; ++u) acc += (TW)vv[k][u] * w[k][u];
+      continue;
     }
 #pragma unroll
     for (int k = 0; k < NCH; ++k) {
