@@ -297,25 +297,35 @@ template <typename T>
 __device__ __forceinline__ void stage_rows(const T* __restrict__ In, int64_t ld, int p,
                                            int64_t row0, int rows, T* __restrict__ tile) {
   // batches of 12 independent loads per thread before their LDS stores, so
-  // that many global loads are in flight per thread
+  // that many global loads are in flight per thread.  Element idx of the
+  // tile is (idx / p, idx % p); the thread's (row, column) is divided out
+  // once and then advanced by 256 elements (dr rows and dc columns, with a
+  // carry) per step, so no division sits in the loop.
   const int ldt = p + 1;
   const int total = 64 * p;
   constexpr int B = 12;
+  const int dr = 256 / p, dc = 256 - dr * p;
+  int r = threadIdx.x / p, c = threadIdx.x - (threadIdx.x / p) * p;
   for (int base = threadIdx.x; base < total; base += 256 * B) {
     T v[B];
+    int rr[B], cc[B];
 #pragma unroll
     for (int i = 0; i < B; ++i) {
+      rr[i] = r;
+      cc[i] = c;
       const int idx = base + 256 * i;
-      const int r = idx / p;
-      v[i] = (idx < total && r < rows) ? In[(row0 + r) * ld + (idx - r * p)] : T(0);
+      v[i] = (idx < total && r < rows) ? In[(row0 + r) * ld + c] : T(0);
+      r += dr;
+      c += dc;
+      if (c >= p) {
+        c -= p;
+        ++r;
+      }
     }
 #pragma unroll
     for (int i = 0; i < B; ++i) {
       const int idx = base + 256 * i;
-      if (idx < total) {
-        const int r = idx / p;
-        tile[r * ldt + (idx - r * p)] = v[i];
-      }
+      if (idx < total) tile[rr[i] * ldt + cc[i]] = v[i];
     }
   }
 }
