@@ -293,9 +293,78 @@ hipError_t gram_f32(const float* A, int64_t lda, int p, const float* B, int64_t 
 // with an odd row stride p+1 (no bank conflicts on the column-wise fragment
 // reads).
 
+// 16-byte vector of T
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { typedef double __attribute__((ext_vector_type(2))) type; };
+template <> struct Vec16<float> { typedef float __attribute__((ext_vector_type(4))) type; };
+
+// Rows of p elements at stride ld starting at a 16-byte aligned address
+// with p and ld multiples of the vector width: the chunk is then read as
+// 16-byte vectors (6 per thread for 64 x 48 fp64), all issued before the
+// LDS stores.  Rows past `rows` are zero-filled like the scalar path.
+template <typename T>
+__device__ __forceinline__ bool stage_rows_vec(const T* __restrict__ In, int64_t ld, int p,
+                                               int64_t row0, int rows, T* __restrict__ tile) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VE = 16 / sizeof(T);
+  constexpr int B = 8;
+  if (p % VE != 0 || ld % VE != 0 || (reinterpret_cast<uintptr_t>(In) & 15) != 0) return false;
+  const int ldt = p + 1;
+  const int pv = p / VE;
+  const int total = 64 * pv;
+  for (int base = threadIdx.x; base < total; base += 256 * B) {
+    V v[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int idx = base + 256 * i;
+      const int r = idx / pv, cv = idx - r * pv;
+      if (idx < total && r < rows)
+        v[i] = *reinterpret_cast<const V*>(In + (row0 + r) * ld + cv * VE);
+      else
+        for (int e = 0; e < VE; ++e) v[i][e] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int idx = base + 256 * i;
+      if (idx < total) {
+        const int r = idx / pv, cv = idx - r * pv;
+#pragma unroll
+        for (int e = 0; e < VE; ++e) tile[r * ldt + cv * VE + e] = v[i][e];
+      }
+    }
+  }
+  return true;
+}
+
+// Rows 0 .. rows-1 of an LDS tile (ncols elements at stride ldt) to global
+// rows row0.. at stride ld: 16-byte vector stores when the global rows are
+// aligned for them, else one element per thread and step.
+template <typename T>
+__device__ __forceinline__ void write_rows(const T* __restrict__ tile, int ldt, int ncols, int rows,
+                                           T* __restrict__ Out, int64_t ld, int64_t row0) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VE = 16 / sizeof(T);
+  if (ncols % VE == 0 && ld % VE == 0 && (reinterpret_cast<uintptr_t>(Out) & 15) == 0) {
+    const int cvn = ncols / VE;
+    for (int idx = threadIdx.x; idx < rows * cvn; idx += 256) {
+      const int r = idx / cvn, cv = idx - r * cvn;
+      V v;
+#pragma unroll
+      for (int e = 0; e < VE; ++e) v[e] = tile[r * ldt + cv * VE + e];
+      *reinterpret_cast<V*>(Out + (row0 + r) * ld + cv * VE) = v;
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < rows * ncols; idx += 256) {
+      const int r = idx / ncols, c = idx - r * ncols;
+      Out[(row0 + r) * ld + c] = tile[r * ldt + c];
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void stage_rows(const T* __restrict__ In, int64_t ld, int p,
                                            int64_t row0, int rows, T* __restrict__ tile) {
+  if (stage_rows_vec<T>(In, ld, p, row0, rows, tile)) return;
   // batches of 12 independent loads per thread before their LDS stores, so
   // that many global loads are in flight per thread.  Element idx of the
   // tile is (idx / p, idx % p); the thread's (row, column) is divided out
@@ -616,15 +685,18 @@ __device__ __forceinline__ double precond_apply(double r, double d, double th, i
 // dynamic LDS of k_rotate for a coefficient stride ldc; the stride is padded
 // to 16 (mod 32) when that still fits in 150 KB (it does for every shape
 // but the largest fp64 ones)
-__host__ __device__ inline size_t rotate_smem_bytes(int p, int ldc, size_t tsize) {
-  const size_t tiles = 2 * 64 * (size_t)(p + 1) * tsize > 12 * 256 * sizeof(double)
-                           ? 2 * 64 * (size_t)(p + 1) * tsize
-                           : 12 * 256 * sizeof(double);
+// The tile area holds the two staged input tiles (64 x (p+1) each), the
+// output tile (64 x (no+1), no = q + m - a0 <= 2q) and the G0 reduction.
+__host__ __device__ inline size_t rotate_smem_bytes(int p, int q, int ldc, size_t tsize) {
+  size_t tiles = 2 * 64 * (size_t)(p + 1) * tsize;
+  const size_t out = 64 * (size_t)(2 * q + 1) * tsize;
+  if (out > tiles) tiles = out;
+  if (12 * 256 * sizeof(double) > tiles) tiles = 12 * 256 * sizeof(double);
   return tsize * (size_t)((p * ldc + 1) & ~1) + tiles;
 }
 __host__ __device__ inline int rotate_ldc(int p, int q, size_t tsize) {
   const int padded = q + ((16 - q % 32) + 32) % 32;
-  return rotate_smem_bytes(p, padded, tsize) <= 150 * 1024 ? padded : q;
+  return rotate_smem_bytes(p, q, padded, tsize) <= 150 * 1024 ? padded : q;
 }
 
 template <typename T, int MTJ>
@@ -693,7 +765,10 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
         aa[tj] = mma(av, b, aa[tj]);
       }
     }
-    if (want_g) __syncthreads();  // staging area becomes the output tile
+    // The outputs go through LDS (the staging area becomes the output tile)
+    // and leave as 16-byte vectors along contiguous rows: first
+    // [X' P' W~] (no columns), then [AX' AP'] (q columns).
+    __syncthreads();
 #pragma unroll
     for (int tj = 0; tj < MTJ; ++tj) {
       const int col = tj * 16 + cc;
@@ -703,29 +778,26 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
         if (col < q) {
           const T xo = (T)ax[tj][r];
           const T ao = (T)aa[tj][r];
-          if (rr < rows) {
-            const int64_t g = row0 + rr;
-            Vout[g * a.ldo + col] = xo;
-            AVout[g * a.ldo + col] = ao;
-            if (col < m) {
+          const bool live = rr < rows;
+          tO[rr * ldto + col] = live ? xo : T(0);
+          if (col < m) {
+            T w = T(0);
+            if (live) {
               const double res = (double)ao - th[tj] * (double)xo;
               nacc[tj] += res * res;
               if (col >= a.a0) {
-                const double d = (a.precond == kPrecNone) ? 0.0 : a.diag[g];
-                const T w = (T)precond_apply(res, d, th[tj], a.precond);
-                Vout[g * a.ldo + q + (col - a.a0)] = w;
-                if (want_g) tO[rr * ldto + q + (col - a.a0)] = w;
+                const double d = (a.precond == kPrecNone) ? 0.0 : a.diag[row0 + rr];
+                w = (T)precond_apply(res, d, th[tj], a.precond);
               }
             }
-          } else if (want_g && col >= a.a0 && col < m) {
-            tO[rr * ldto + q + (col - a.a0)] = T(0);
+            if (col >= a.a0) tO[rr * ldto + q + (col - a.a0)] = w;
           }
-          if (want_g) tO[rr * ldto + col] = (rr < rows) ? xo : T(0);
         }
       }
     }
+    __syncthreads();
+    write_rows<T>(tO, ldto, no, rows, Vout, a.ldo, row0);
     if (want_g) {
-      __syncthreads();
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rl = wave * 16 + 4 * r + kr;  // K = 4 rows per MFMA, any row order
@@ -747,6 +819,19 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
         }
       }
     }
+    __syncthreads();
+    const int ldtq = q + 1;
+#pragma unroll
+    for (int tj = 0; tj < MTJ; ++tj) {
+      const int col = tj * 16 + cc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = wave * 16 + acc_row<T>(r, lane);
+        if (col < q) tO[rr * ldtq + col] = (rr < rows) ? (T)aa[tj][r] : T(0);
+      }
+    }
+    __syncthreads();
+    write_rows<T>(tO, ldtq, q, rows, AVout, a.ldo, row0);
   }
   // per-column residual partial: sum the 4 lane groups (fixed xor order), then waves
 #pragma unroll
@@ -796,7 +881,7 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
 template <typename T>
 static size_t rotate_smem(int p, int q) {
   // the G0 reduction needs 12 * 256 doubles after the coefficient block
-  return rotate_smem_bytes(p, rotate_ldc(p, q, sizeof(T)), sizeof(T));
+  return rotate_smem_bytes(p, q, rotate_ldc(p, q, sizeof(T)), sizeof(T));
 }
 
 template <typename T, int MTJ>
