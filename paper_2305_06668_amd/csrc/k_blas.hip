@@ -45,7 +45,10 @@ static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // Each of the 4 waves takes every 4th 4-row step of the block's rows.
 
 template <typename T, int MTI, int MTJ>
-__global__ __launch_bounds__(256) void k_gram_part(const T* __restrict__ A, int64_t lda, int p,
+// occupancy bound for up to 3 x 3 tiles (the Rayleigh-Ritz Gram at m = 16):
+// 3 waves per SIMD without spills (fp64 240 -> 168 registers); larger tile
+// counts would spill, so they keep the default
+__global__ __launch_bounds__(256, (MTI <= 3 && MTJ <= 3) ? 3 : 1) void k_gram_part(const T* __restrict__ A, int64_t lda, int p,
                                                    const T* __restrict__ B, int64_t ldb, int q,
                                                    int64_t n, int64_t rpb,
                                                    double* __restrict__ part,
@@ -409,7 +412,9 @@ __device__ __forceinline__ void stage_rows(const T* __restrict__ In, int64_t ld,
 // itself when the controller has finished (st->done).
 
 template <typename T, int MTI, int MTJ>
-__global__ __launch_bounds__(256) void k_ortho_apply(T* base, int64_t ld, int ny, int nw,
+// 4 waves per SIMD for one column tile and up to 5 row tiles (fp64 136 -> 108
+// registers, no spills); wider instances would spill and keep the default
+__global__ __launch_bounds__(256, (MTJ == 1 && MTI <= 5) ? 4 : 1) void k_ortho_apply(T* base, int64_t ld, int ny, int nw,
                                                      const double* __restrict__ coef,
                                                      const OrthoState* __restrict__ st, int64_t n,
                                                      double* __restrict__ part) {
