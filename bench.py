@@ -199,10 +199,12 @@ def main():
         # +-10 % iteration noise, and the one-step objective drifts away from
         # whole-solve speed after a few hundred steps, so the weights are
         # chosen after every 25-step chunk
+        # (in the benchmark's own mode: learned + mixed precision)
         total = 0
         for val in vals:
             val.set_learned_weights(w)
             val.set_preconditioner(P.PRECOND_LEARNED)
+            val.set_option(P.OPT_PRECISION, P.PREC_FP32)
             r = val.solve(k, args.tol, want_vectors=False)
             total += r.stats["iterations"] if r.status == P.OK else 10**6
         return total / len(vals)

@@ -16,7 +16,6 @@ constexpr size_t kAlign = 256;
 constexpr int kOrthoRounds = 6;     // controller rounds launched before the first check
 constexpr int kOrthoHardCap = 64;   // rounds before giving up
 constexpr size_t kPinnedBytes = 1 << 16;
-constexpr size_t kGPartOffset = 1 << 16;  // doubles: rotation's overlap partials inside `part`
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -107,8 +106,8 @@ struct lobpcg_ctx {
   int apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy);
   int apply_op(const float* W, int64_t ldw, int nc, float* Y, int64_t ldy);
   template <typename T>
-  int ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info, bool have_g0 = false,
-                bool fold = false, double tau_run = -1.0);
+  int ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info, bool fold = false,
+                double tau_run = -1.0);
   int ensure_diag();
   int ensure_learned_features();
   int ensure_op32();

@@ -86,8 +86,6 @@ struct RotateArgs {
   const double* diag;   // n (may be null for kPrecNone)
   double* part;         // kStreamBlocks * m partial norms
   double* resnorm2;     // m
-  double* gpart;        // optional: kStreamBlocks * (q + m - a0) * (m - a0) partials
-  double* G0;           // optional: [X' P' W~]^T W~ ((q + m - a0) x (m - a0))
 };
 hipError_t rotate_f64(const double* V, const double* AV, double* Vout, double* AVout,
                       const RotateArgs& a, hipStream_t s);

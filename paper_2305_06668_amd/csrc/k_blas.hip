@@ -690,13 +690,12 @@ __device__ __forceinline__ double precond_apply(double r, double d, double th, i
 // dynamic LDS of k_rotate for a coefficient stride ldc; the stride is padded
 // to 16 (mod 32) when that still fits in 150 KB (it does for every shape
 // but the largest fp64 ones)
-// The tile area holds the two staged input tiles (64 x (p+1) each), the
-// output tile (64 x (no+1), no = q + m - a0 <= 2q) and the G0 reduction.
+// The tile area holds the two staged input tiles (64 x (p+1) each) and,
+// after them, the output tile (64 x (no+1), no = q + m - a0 <= 2q).
 __host__ __device__ inline size_t rotate_smem_bytes(int p, int q, int ldc, size_t tsize) {
   size_t tiles = 2 * 64 * (size_t)(p + 1) * tsize;
   const size_t out = 64 * (size_t)(2 * q + 1) * tsize;
   if (out > tiles) tiles = out;
-  if (12 * 256 * sizeof(double) > tiles) tiles = 12 * 256 * sizeof(double);
   return tsize * (size_t)((p * ldc + 1) & ~1) + tiles;
 }
 __host__ __device__ inline int rotate_ldc(int p, int q, size_t tsize) {
@@ -704,22 +703,19 @@ __host__ __device__ inline int rotate_ldc(int p, int q, size_t tsize) {
   return rotate_smem_bytes(p, q, padded, tsize) <= 150 * 1024 ? padded : q;
 }
 
-// WG: the fused overlap G0 = [X' P' W~]^T W~ is formed (its accumulators,
-// GI x GJ tiles with GI <= 2 MTJ and GJ <= MTJ since no <= 2q and na <= q,
-// exist only then: they would otherwise hold registers that cap occupancy)
-template <typename T, int MTJ, bool WG>
-__global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T* __restrict__ AV,
-                                                T* __restrict__ Vout, T* __restrict__ AVout,
-                                                RotateArgs a) {
-  constexpr int GI = WG ? (2 * MTJ < 6 ? 2 * MTJ : 6) : 1;
-  constexpr int GJ = WG ? (MTJ < 2 ? MTJ : 2) : 1;
+// 4 waves per SIMD for every instance (fp64 MTJ = 4: 3), without spills
+template <typename T, int MTJ>
+__global__ __launch_bounds__(256, (MTJ <= 3 ? 4 : 3)) void k_rotate(const T* __restrict__ V,
+                                                                   const T* __restrict__ AV,
+                                                                   T* __restrict__ Vout,
+                                                                   T* __restrict__ AVout,
+                                                                   RotateArgs a) {
   typedef typename AccOf<T>::type AccT;
   extern __shared__ double smem_d[];
   __shared__ double nred[4][64];
   const int p = a.p, q = a.q, m = a.m;
   const int na = m - a.a0;
   const int no = q + na;  // output columns [X' P' W~]
-  const bool want_g = WG && na > 0;
   // coefficient stride = 16 (mod 32): the four k rows a wave reads per MFMA
   // step fall in different LDS banks
   const int ldc = rotate_ldc(p, q, sizeof(T));
@@ -739,13 +735,6 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
     th[tj] = (col < m) ? a.theta[col] : 0.0;
     nacc[tj] = 0.0;
   }
-  // G0 = [X' P' W~]^T W~ accumulators: tig x tjg <= GI x GJ tiles
-  const int tig = (no + 15) >> 4, tjg = (na + 15) >> 4;
-  typename AccOf<T>::type gacc[GI][GJ];
-#pragma unroll
-  for (int I = 0; I < GI; ++I)
-#pragma unroll
-    for (int J = 0; J < GJ; ++J) gacc[I][J] = AccT{0, 0, 0, 0};
   const int64_t n = a.n;
   const int64_t nchunks = (n + 63) / 64;
   for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
@@ -807,28 +796,6 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
     }
     __syncthreads();
     write_rows<T>(tO, ldto, no, rows, Vout, a.ldo, row0);
-    if (want_g) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rl = wave * 16 + 4 * r + kr;  // K = 4 rows per MFMA, any row order
-        T bj[GJ];
-#pragma unroll
-        for (int J = 0; J < GJ; ++J) {
-          const int cj = J * 16 + cc;
-          bj[J] = (J < tjg && cj < na) ? tO[rl * ldto + q + cj] : T(0);
-        }
-#pragma unroll
-        for (int I = 0; I < GI; ++I) {
-          if (I < tig) {
-            const int ci = I * 16 + cc;
-            const T ai = (ci < no) ? tO[rl * ldto + ci] : T(0);
-#pragma unroll
-            for (int J = 0; J < GJ; ++J)
-              if (J < tjg) gacc[I][J] = mma(ai, bj[J], gacc[I][J]);
-          }
-        }
-      }
-    }
     __syncthreads();
     const int ldtq = q + 1;
 #pragma unroll
@@ -861,64 +828,30 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ V, const T
     const int c = threadIdx.x;
     a.part[(int64_t)blockIdx.x * m + c] = ((nred[0][c] + nred[1][c]) + nred[2][c]) + nred[3][c];
   }
-  if (want_g) {
-    // fixed-order reduction of G0 over the waves (reusing the staging area)
-    double* red = reinterpret_cast<double*>(cf + ((p * ldc + 1) & ~1));
-    for (int w = 0; w < 4; ++w) {
-      if (wave == w) {
-#pragma unroll
-        for (int I = 0; I < GI; ++I)
-#pragma unroll
-          for (int J = 0; J < GJ; ++J)
-            if (I < tig && J < tjg)
-#pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int idx = (I * 2 + J) * 256 + acc_row<T>(r, lane) * 16 + cc;
-                const double v = (double)gacc[I][J][r];
-                red[idx] = (w == 0) ? v : red[idx] + v;
-              }
-      }
-      __syncthreads();
-    }
-    double* dst = a.gpart + (int64_t)blockIdx.x * no * na;
-    for (int idx = threadIdx.x; idx < no * na; idx += 256) {
-      const int i = idx / na, j = idx - i * na;
-      dst[idx] = red[((i >> 4) * 2 + (j >> 4)) * 256 + (i & 15) * 16 + (j & 15)];
-    }
-  }
 }
 
 template <typename T>
 static size_t rotate_smem(int p, int q) {
-  // the G0 reduction needs 12 * 256 doubles after the coefficient block
   return rotate_smem_bytes(p, q, rotate_ldc(p, q, sizeof(T)), sizeof(T));
 }
 
-template <typename T, int MTJ, bool WG>
+template <typename T, int MTJ>
 static hipError_t rotate_launch(const T* V, const T* AV, T* Vout, T* AVout, const RotateArgs& a,
                                 hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_rotate<T, MTJ, WG>,
+    (void)hipFuncSetAttribute((const void*)k_rotate<T, MTJ>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     (void)hipGetLastError();
     attr = true;
   }
-  if (WG) {
-    const int na = a.m - a.a0, no = a.q + na;
-    const int gi = (2 * MTJ < 6) ? 2 * MTJ : 6, gj = (MTJ < 2) ? MTJ : 2;
-    if ((no + 15) / 16 > gi || (na + 15) / 16 > gj) return hipErrorInvalidValue;
-  }
   const int64_t nchunks = (a.n + 63) / 64;
   const int grid = (int)std::min<int64_t>(nchunks, kStreamBlocks);
-  hipLaunchKernelGGL((k_rotate<T, MTJ, WG>), dim3(grid), dim3(256), rotate_smem<T>(a.p, a.q), s, V,
-                     AV, Vout, AVout, a);
+  hipLaunchKernelGGL((k_rotate<T, MTJ>), dim3(grid), dim3(256), rotate_smem<T>(a.p, a.q), s, V, AV,
+                     Vout, AVout, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = sum_parts(a.part, grid, a.m, a.resnorm2, nullptr, s);
-  if (e != hipSuccess || a.gpart == nullptr || a.m == a.a0) return e;
-  const int na = a.m - a.a0;
-  return sum_parts(a.gpart, grid, (a.q + na) * na, a.G0, nullptr, s);
+  return sum_parts(a.part, grid, a.m, a.resnorm2, nullptr, s);
 }
 
 template <typename T>
@@ -927,16 +860,11 @@ static hipError_t rotate_any(const T* V, const T* AV, T* Vout, T* AVout, const R
   if (a.p < 1 || a.p > kMaxP || a.q < a.m || a.q > 64 || a.m < 1 || a.m > 64 || a.a0 < 0 ||
       a.a0 > a.m || a.n < 1 || a.ldo < a.q + (a.m - a.a0) || a.ldv < a.p)
     return hipErrorInvalidValue;
-  const bool wg = a.gpart != nullptr && a.m > a.a0;
   switch ((a.q + 15) / 16) {
-    case 1: return wg ? rotate_launch<T, 1, true>(V, AV, Vout, AVout, a, s)
-                      : rotate_launch<T, 1, false>(V, AV, Vout, AVout, a, s);
-    case 2: return wg ? rotate_launch<T, 2, true>(V, AV, Vout, AVout, a, s)
-                      : rotate_launch<T, 2, false>(V, AV, Vout, AVout, a, s);
-    case 3: return wg ? rotate_launch<T, 3, true>(V, AV, Vout, AVout, a, s)
-                      : rotate_launch<T, 3, false>(V, AV, Vout, AVout, a, s);
-    default: return wg ? rotate_launch<T, 4, true>(V, AV, Vout, AVout, a, s)
-                       : rotate_launch<T, 4, false>(V, AV, Vout, AVout, a, s);
+    case 1: return rotate_launch<T, 1>(V, AV, Vout, AVout, a, s);
+    case 2: return rotate_launch<T, 2>(V, AV, Vout, AVout, a, s);
+    case 3: return rotate_launch<T, 3>(V, AV, Vout, AVout, a, s);
+    default: return rotate_launch<T, 4>(V, AV, Vout, AVout, a, s);
   }
 }
 

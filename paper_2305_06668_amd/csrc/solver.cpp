@@ -52,7 +52,7 @@ Layout lobpcg_ctx::plan(int m) const {
   const size_t gblk = (size_t)std::min<int64_t>(kGramBlocks, (n + 63) / 64) + 1;
   const size_t part =
       std::max({gblk * kGramMaxCols * kGramMaxCols, (size_t)kStreamBlocks * 3 * 64,
-                kGPartOffset + (size_t)kStreamBlocks * kMaxP * kMaxBlock});
+                (size_t)kStreamBlocks * kMaxP * kMaxBlock});
   L.part = take(part * sizeof(double));
   // small area
   size_t so = 0;
@@ -261,7 +261,7 @@ static hipError_t fill_t(float* X, int64_t ld, int col, int id, int64_t n, uint6
 // ortho(W; Y) (Alg. 3 around Alg. 2) on base = [Y | W] rows, ld.
 template <typename T>
 int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info,
-                          bool have_g0, bool fold, double tau_run) {
+                          bool fold, double tau_run) {
   OrthoState* st = small_ptr<OrthoState>(lay.ost);
   double* G = small_ptr<double>(lay.G);
   double* coef = small_ptr<double>(lay.coef);
@@ -271,9 +271,11 @@ int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info
   const double t = (tau_run > 0.0) ? tau_run : tau;
   for (int attempt = 0; attempt < 3; ++attempt) {
     HIPCHK(ortho_init(st, ny, nw, t, ortho_max_inner, ortho_max_outer, fold ? 1 : 0, stream));
-    // the overlap of the raw W~ may come fused from the rotation kernel
-    if (!(have_g0 && attempt == 0))
-      HIPCHK(gram_t(base, ld, nr, base + ny, ld, nw, n, part, G, nullptr, stream));
+    // the overlap [Y W~]^T W~ of the raw W~, by its own kernel: fused into
+    // the rotation it held the rotation at two waves per SIMD (fp64), which
+    // cost more than the separate pass (434 us against 328 + 91 us per
+    // iteration at n = 1e6, m = 16)
+    HIPCHK(gram_t(base, ld, nr, base + ny, ld, nw, n, part, G, nullptr, stream));
     int rounds = 0;
     bool finished = false;
     while (!finished) {
@@ -384,7 +386,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
   int* lflags = small_ptr<int>(lay.lflags);
   int* hmask = reinterpret_cast<int*>(pinned + kPinnedBytes / 2);
   if (learned) HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
-  int rc = ortho_run<T>(V[0], m, 0, m, nullptr, false, true, tau_phase);
+  int rc = ortho_run<T>(V[0], m, 0, m, nullptr, true, tau_phase);
   if (rc) return rc;
   rc = apply_op(V[0], m, m, AV[0], m);
   if (rc) return rc;
@@ -426,8 +428,6 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     ra.diag = dptr(lay.diag);
     ra.part = part;
     ra.resnorm2 = resn2;
-    ra.gpart = learned ? nullptr : part + kGPartOffset;
-    ra.G0 = small_ptr<double>(lay.G);
     HIPCHK(rotate_t(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
     HIPCHK(hipMemcpyAsync(h, resn2, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipMemcpyAsync(h + 64, theta, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
@@ -478,7 +478,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       // the implicit-P recurrence lets X's orthonormality drift by rounding
       // (about 1e-12 after hundreds of iterations): re-orthonormalise X
       // (Alg. 2) before the explicit product that judges it
-      rc = ortho_run<T>(V[1 - c], ldo, 0, m, nullptr, false, false, tau);
+      rc = ortho_run<T>(V[1 - c], ldo, 0, m, nullptr, false, tau);
       if (rc) return rc;
       const double* Xd = reinterpret_cast<const double*>(V[1 - c]);
       double* scratch = reinterpret_cast<double*>(AV[c]);
@@ -517,7 +517,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       HIPCHK(rotate_t(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
     }
     if (iter >= max_iter) {
-      rc = ortho_run<T>(V[1 - c], ldo, 0, m, nullptr, false, false, tau);
+      rc = ortho_run<T>(V[1 - c], ldo, 0, m, nullptr, false, tau);
       if (rc) return rc;
       const double* Xd = reinterpret_cast<const double*>(V[1 - c]);
       rc = true_residuals(Xd, ldo, m, reinterpret_cast<double*>(AV[c]), theta, th_t, rn_t);
@@ -545,7 +545,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       prev_a0 = a0;
       prev_nact = nact;
     }
-    rc = ortho_run<T>(V[1 - c], ldo, q, nact, nullptr, !learned, true, tau_phase);
+    rc = ortho_run<T>(V[1 - c], ldo, q, nact, nullptr, true, tau_phase);
     if (rc) return rc;
     pend_valid = true;
     pend_woff = q;
