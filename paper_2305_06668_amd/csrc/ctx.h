@@ -13,7 +13,10 @@
 namespace lobpcg {
 
 constexpr size_t kAlign = 256;
-constexpr int kOrthoRounds = 6;     // controller rounds launched before the first check
+// controller rounds launched before the first check: two applications and
+// the deciding controller round cover most calls (a no-op round still costs
+// ~13 us of launches; a further check costs a ~30 us read-back)
+constexpr int kOrthoRounds = 3;
 constexpr int kOrthoHardCap = 64;   // rounds before giving up
 constexpr size_t kPinnedBytes = 1 << 16;
 
