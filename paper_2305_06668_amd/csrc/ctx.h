@@ -17,6 +17,7 @@ constexpr size_t kAlign = 256;
 // the deciding controller round cover most calls (a no-op round still costs
 // ~13 us of launches; a further check costs a ~30 us read-back)
 constexpr int kOrthoRounds = 3;
+constexpr size_t kReadbackBytes = 2048;  // resn2, theta (2 slots), info, learned flags
 constexpr int kOrthoHardCap = 64;   // rounds before giving up
 constexpr size_t kPinnedBytes = 1 << 16;
 
@@ -28,7 +29,8 @@ struct Layout {
   size_t V[2], AV[2], diag, rho, ltiles, part, small, total;
   size_t V32[2], AV32[2], op32;  // mixed precision only (0 otherwise)
   // inside small (byte offsets)
-  size_t a, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye, lmask, lflags, lscale;
+  size_t a, rb, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye, lmask, lflags, ltcount,
+      lscale;
 };
 
 }  // namespace lobpcg

@@ -460,15 +460,16 @@ __device__ __forceinline__ float silu_fast(float z) {
 // kMlpSuper entries (4 per lane, loaded together) and, when none of them is
 // inside the window, takes the Jacobi step for all of them (the formula of
 // the tile epilogue with c = 0); super tiles with an entry inside are
-// appended to tiles[1..] (count in tiles[0], cleared by the caller) for the
-// MFMA kernel.  The order of the list depends on timing; every super tile
+// appended to tlist (count in *tcount, zero on entry) for the MFMA
+// kernel.  The order of the list depends on timing; every super tile
 // is processed the same way wherever it sits, so results do not.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mlp_screen(T* __restrict__ R, int64_t ld, int nact, int64_t n,
                                                     const double* __restrict__ theta,
                                                     const double* __restrict__ diag,
                                                     const double* __restrict__ rho,
-                                                    int* __restrict__ tiles) {
+                                                    int* __restrict__ tcount,
+                                                    int* __restrict__ tlist) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t total = n * nact;
   const int64_t nst = (total + kMlpSuper - 1) / kMlpSuper;
@@ -510,7 +511,7 @@ __global__ __launch_bounds__(256) void k_mlp_screen(T* __restrict__ R, int64_t l
       any |= sval[q] && fabs(sdm[q]) <= kMlpWindow * srr[q];
     }
     if (__ballot(any) != 0) {
-      if (lane == 0) tiles[1 + atomicAdd(tiles, 1)] = (int)st;
+      if (lane == 0) tlist[atomicAdd(tcount, 1)] = (int)st;
       continue;
     }
 #pragma unroll
@@ -534,7 +535,8 @@ __global__ __launch_bounds__(256, 2) void k_mlp_apply_bf16(T* __restrict__ R, in
                                                         const float* __restrict__ wts,
                                                         const int* __restrict__ mask,
                                                         int* __restrict__ flags,
-                                                        const int* __restrict__ tiles) {
+                                                        const int* __restrict__ tcount,
+                                                        const int* __restrict__ tlist) {
   constexpr int kBS = kH + 8;  // padded row stride of the bf16 W2 copy
   __shared__ float4 w1s[kH];  // (W1[k][0..2], b1[k])
   __shared__ __attribute__((aligned(16))) __bf16 w2s[kH * kBS];
@@ -560,9 +562,9 @@ __global__ __launch_bounds__(256, 2) void k_mlp_apply_bf16(T* __restrict__ R, in
   // the super tiles (kSE entries) that k_mlp_screen found to hold entries
   // inside the window, one per wave iteration, each as kSE / E tiles
   constexpr int kSE = kMlpSuper, kTS = kSE / E;
-  const int nlist = tiles[0];
+  const int nlist = *tcount;
   for (int li = blockIdx.x * 4 + wave; li < nlist; li += gridDim.x * 4) {
-    const int64_t st = tiles[1 + li];
+    const int64_t st = tlist[li];
     for (int u = 0; u < kTS; ++u) {
       const int64_t wt = st * kTS + u;
       if (wt >= nwt) break;
@@ -767,36 +769,43 @@ int mlp_grid(int64_t total) {
 template <typename T>
 static hipError_t mlp_apply_bf16_t(T* R, int64_t ld, int nact, int64_t n, const double* theta,
                                    const double* diag, const double* rho, const double* s,
-                                   const float* w, const int* mask, int* flags, int* tiles,
-                                   int64_t tiles_cap, hipStream_t st) {
+                                   const float* w, const int* mask, int* flags, int* tcount,
+                                   int* tlist, int64_t tiles_cap, bool zero_count,
+                                   hipStream_t st) {
   if (n <= 0 || nact <= 0) return hipSuccess;
   constexpr int MT = kMlpTilesPerWave;
   const int64_t nst = (n * nact + kMlpSuper - 1) / kMlpSuper;
-  if (tiles == nullptr || nst > tiles_cap || nst > INT32_MAX) return hipErrorInvalidValue;
-  hipError_t e = hipMemsetAsync(tiles, 0, sizeof(int), st);
-  if (e != hipSuccess) return e;
+  if (tcount == nullptr || tlist == nullptr || nst > tiles_cap || nst > INT32_MAX)
+    return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
+  if (zero_count) {
+    e = hipMemsetAsync(tcount, 0, sizeof(int), st);
+    if (e != hipSuccess) return e;
+  }
   const int sgrid = (int)std::min<int64_t>((nst + 3) / 4, 4096);
   hipLaunchKernelGGL((k_mlp_screen<T>), dim3(sgrid), dim3(256), 0, st, R, ld, nact, n, theta, diag,
-                     rho, tiles);
+                     rho, tcount, tlist);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // two waves per SIMD (the MFMA path holds ~240 registers): 2 blocks per CU
   hipLaunchKernelGGL((k_mlp_apply_bf16<T, MT>), dim3(512), dim3(256), 0, st, R, ld, nact, n, theta,
-                     diag, rho, s, w, mask, flags, tiles);
+                     diag, rho, s, w, mask, flags, tcount, tlist);
   return hipGetLastError();
 }
 
 hipError_t mlp_apply_bf16_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, int* tiles,
-                              int64_t tiles_cap, hipStream_t st) {
-  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tiles, tiles_cap, st);
+                              const float* w, const int* mask, int* flags, int* tcount, int* tlist,
+                              int64_t tiles_cap, bool zero_count, hipStream_t st) {
+  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tcount, tlist,
+                          tiles_cap, zero_count, st);
 }
 hipError_t mlp_apply_bf16_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, int* tiles,
-                              int64_t tiles_cap, hipStream_t st) {
-  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tiles, tiles_cap, st);
+                              const float* w, const int* mask, int* flags, int* tcount, int* tlist,
+                              int64_t tiles_cap, bool zero_count, hipStream_t st) {
+  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tcount, tlist,
+                          tiles_cap, zero_count, st);
 }
 
 template <typename T>

@@ -48,7 +48,7 @@ Layout lobpcg_ctx::plan(int m) const {
   L.AV[1] = take(blk);
   L.diag = take((size_t)n * sizeof(double));
   L.rho = take((size_t)n * sizeof(double));
-  L.ltiles = take((size_t)(ltiles_cap() + 1) * sizeof(int));
+  L.ltiles = take((size_t)ltiles_cap() * sizeof(int));
   const size_t gblk = (size_t)std::min<int64_t>(kGramBlocks, (n + 63) / 64) + 1;
   const size_t part =
       std::max({gblk * kGramMaxCols * kGramMaxCols, (size_t)kStreamBlocks * 3 * 64,
@@ -62,19 +62,24 @@ Layout lobpcg_ctx::plan(int m) const {
     return o;
   };
   L.a = stake(sizeof(double) * kGramMaxCols * kGramMaxCols);
-  L.theta = stake(sizeof(double) * kGramMaxCols);
+  // read back once per iteration as one block: residual norms (64),
+  // Ritz values (two slots of 64), RR info (64 ints), learned-path flags
+  // (64 ints) and the learned transform's super-tile counter
+  L.rb = stake(kReadbackBytes + 256);
+  L.resn2 = L.rb;
+  L.theta = L.rb + 512;
+  L.info = L.rb + 1536;
+  L.lflags = L.rb + 1792;
+  L.ltcount = L.rb + 2048;
   L.U = stake(sizeof(double) * kMaxP * 64);
   L.G = stake(sizeof(double) * kMaxP * kMaxBlock);
   L.coef = stake(sizeof(double) * kMaxP * kMaxBlock);
-  L.resn2 = stake(sizeof(double) * 64);
   L.cols = stake(sizeof(double) * 3 * 64);
-  L.info = stake(sizeof(int) * 64);
   L.ost = stake(sizeof(OrthoState));
   L.pidx = stake(sizeof(int64_t) * 256 * 64);
   L.pval = stake(sizeof(double) * 256 * 64);
   L.eye = stake(sizeof(double) * 64 * 64);
   L.lmask = stake(sizeof(int) * 64);
-  L.lflags = stake(sizeof(int) * 64);
   L.lscale = stake(sizeof(double) * 4);
   L.small = take(so);
   if (precision == LOBPCG_PREC_FP32) {
@@ -218,17 +223,19 @@ static hipError_t gram_t(const float* A, int64_t lda, int p, const float* B, int
 static hipError_t mlp_apply_t(bool bf16, double* R, int64_t ld, int nact, int64_t n,
                               const double* theta, const double* diag, const double* rho,
                               const double* s, const float* w, const int* mask, int* flags,
-                              int* tiles, int64_t tiles_cap, hipStream_t st) {
-  return bf16 ? mlp_apply_bf16_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tiles,
-                                   tiles_cap, st)
+                              int* tcount, int* tlist, int64_t tiles_cap, bool zero_count,
+                              hipStream_t st) {
+  return bf16 ? mlp_apply_bf16_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tcount, tlist,
+                                   tiles_cap, zero_count, st)
               : mlp_apply_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
 }
 static hipError_t mlp_apply_t(bool bf16, float* R, int64_t ld, int nact, int64_t n,
                               const double* theta, const double* diag, const double* rho,
                               const double* s, const float* w, const int* mask, int* flags,
-                              int* tiles, int64_t tiles_cap, hipStream_t st) {
-  return bf16 ? mlp_apply_bf16_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tiles,
-                                   tiles_cap, st)
+                              int* tcount, int* tlist, int64_t tiles_cap, bool zero_count,
+                              hipStream_t st) {
+  return bf16 ? mlp_apply_bf16_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tcount, tlist,
+                                   tiles_cap, zero_count, st)
               : mlp_apply_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
 }
 static hipError_t rotate_t(const double* V, const double* AV, double* Vo, double* AVo,
@@ -385,7 +392,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
   int* lmask = small_ptr<int>(lay.lmask);
   int* lflags = small_ptr<int>(lay.lflags);
   int* hmask = reinterpret_cast<int*>(pinned + kPinnedBytes / 2);
-  if (learned) HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
+  if (learned) HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 65, stream));  // flags + tile counter
   int rc = ortho_run<T>(V[0], m, 0, m, nullptr, true, tau_phase);
   if (rc) return rc;
   rc = apply_op(V[0], m, m, AV[0], m);
@@ -429,13 +436,10 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     ra.part = part;
     ra.resnorm2 = resn2;
     HIPCHK(rotate_t(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
-    HIPCHK(hipMemcpyAsync(h, resn2, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipMemcpyAsync(h + 64, theta, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipMemcpyAsync(h + 128, info, sizeof(int) * 16, hipMemcpyDeviceToHost, stream));
-    if (learned)
-      HIPCHK(hipMemcpyAsync(h + 192, lflags, sizeof(int) * 64, hipMemcpyDeviceToHost, stream));
+    // one read-back: resn2 at h[0], theta at h[64], info at h[192], flags at h[224]
+    HIPCHK(hipMemcpyAsync(h, resn2, kReadbackBytes, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
-    const int* hinfo = reinterpret_cast<const int*>(h + 128);
+    const int* hinfo = reinterpret_cast<const int*>(h + 192);
     if (hinfo[1] != 0) return fail(LOBPCG_ERR_ORTHO_FAILED, "R^p orthonormalisation of u_p failed");
     stats.rr_eig_fallbacks += hinfo[11];
     double rmax = 0.0;
@@ -447,7 +451,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       rmax = std::max(rmax, rnorm[j]);
     }
     if (learned) {
-      const int* hfl = reinterpret_cast<const int*>(h + 192);
+      const int* hfl = reinterpret_cast<const int*>(h + 224);
       for (int j = 0; j < prev_nact; ++j)
         if (hfl[j]) {
           stats.learned_nonfinite++;
@@ -537,11 +541,11 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
         r_before[j] = rnorm[j];
       }
       HIPCHK(hipMemcpyAsync(lmask, hmask, sizeof(int) * nact, hipMemcpyHostToDevice, stream));
-      HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
+      HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 65, stream));  // flags + tile counter
       HIPCHK(mlp_apply_t(learned_bf16 != 0, V[1 - c] + q, ldo, nact, n, theta + a0,
                          dptr(lay.diag), dptr(lay.rho), small_ptr<double>(lay.lscale), lweights,
-                         lmask, lflags, reinterpret_cast<int*>(ws + lay.ltiles), ltiles_cap(),
-                         stream));
+                         lmask, lflags, small_ptr<int>(lay.ltcount),
+                         reinterpret_cast<int*>(ws + lay.ltiles), ltiles_cap(), false, stream));
       prev_a0 = a0;
       prev_nact = nact;
     }
@@ -911,7 +915,8 @@ int lobpcg_learned_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const dou
   hipError_t e = mlp_apply_t(h->learned_bf16 != 0, R, ldr, nact, h->n, theta,
                              h->dptr(h->lay.diag), h->dptr(h->lay.rho),
                              h->small_ptr<double>(h->lay.lscale), h->lweights, mask, nullptr,
-                             reinterpret_cast<int*>(h->ws + h->lay.ltiles), h->ltiles_cap(),
+                             h->small_ptr<int>(h->lay.ltcount),
+                             reinterpret_cast<int*>(h->ws + h->lay.ltiles), h->ltiles_cap(), true,
                              h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "learned apply");
   return LOBPCG_OK;
