@@ -1,0 +1,98 @@
+"""Kronecker-sum operator at its full size: na = 4096 (n = 16.8M), 8 fp64
+columns, through the C ABI in the launch configuration the solver uses.
+
+H = A (x) I + I (x) A + diag(vec V) (the matrix-free CI sigma of the
+paper's Full CI experiments, Sec. 4).  The oracle cannot form H at this
+size, so the check is twofold:
+* sampled outputs: 48 (i, j) rows (all columns) recomputed on the host
+  from the definition Y[i][j] = A[i,:] W[:, j] + A[j,:] W[i, :] + V[i][j]
+  W[i][j], within 1e-13 of the scale |A[i,:]| |W[:, j]| + |A[j,:]| |W[i, :]|
+  + |V W| (fp64 forward error of a 4096-term sum, with room for the
+  accumulation order);
+* a property of every output: the column sums of Y equal
+  colsum(A) . (sum_j W[:, j]) + colsum(A) . (sum_i W[i, :]) + sum V o W,
+  within 1e-12 of the sum of absolute values, which a missing, repeated or
+  misplaced tile breaks (the bound sums |A| |W| over every output).
+Both a compact block (ld = 8) and a strided one (ld = 24, 7 columns, the
+solver's [X P W] buffer after a lock) are checked.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_06668_amd as P
+
+    return P
+
+
+@pytest.fixture(scope="module")
+def problem():
+    na = 4096
+    A, V = synth.kronsum(na=na, seed=synth.SEEDS["kronsum"][0])
+    W = synth.start_block(na * na, 8, synth.SEEDS["kronsum"][1])
+    return na, A, V, W
+
+
+@pytest.mark.parametrize("ldw,off,m", [(8, 0, 8), (24, 16, 7)])
+def test_kronsum_full_size(P, problem, ldw, off, m):
+    na, A, V, Wh = problem
+    print(f"kron full na={na} ldw={ldw} off={off} m={m}", flush=True)
+    n = na * na
+    dev = "cuda"
+    s = P.Solver(n)
+    s.set_operator_kronsum(torch.from_numpy(A).to(dev), torch.from_numpy(V).to(dev))
+    s.ensure_workspace(8)
+    Wbuf = torch.zeros((n, ldw), dtype=torch.float64, device=dev)
+    Wbuf[:, off : off + m] = torch.from_numpy(Wh[:, :m]).to(dev)
+    Ybuf = torch.full((n, ldw), 3.0, dtype=torch.float64, device=dev)
+    W = Wbuf[:, off : off + m]
+    Y = Ybuf[:, off : off + m]
+    P.lobpcg_apply_operator(s.h, W, Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.lobpcg_apply_operator(s.h, W, Y)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    print(f"  one apply {ms:.1f} ms ({4.0 * na**3 * m / (ms * 1e-3) / 1e12:.1f} TFLOP/s)", flush=True)
+
+    W3 = Wh[:, :m].reshape(na, na, m)
+    g = synth.rng(77)
+    ii = g.integers(0, na, 48)
+    jj = g.integers(0, na, 48)
+    # edges of the 32 x 32 tiles and of the operator
+    ii[:4] = [0, 31, 32, na - 1]
+    jj[:4] = [na - 1, 32, 31, 0]
+    rows = torch.from_numpy(ii * na + jj).to(dev)
+    Ys = Y.index_select(0, rows).cpu().numpy()
+    for t in range(len(ii)):
+        i, j = int(ii[t]), int(jj[t])
+        ref = A[i, :] @ W3[:, j, :] + A[j, :] @ W3[i, :, :] + V[i, j] * W3[i, j, :]
+        scale = (
+            np.abs(A[i, :]) @ np.abs(W3[:, j, :])
+            + np.abs(A[j, :]) @ np.abs(W3[i, :, :])
+            + abs(V[i, j]) * np.abs(W3[i, j, :])
+        )
+        assert np.all(np.abs(Ys[t] - ref) <= 1e-13 * scale), (i, j)
+
+    cs = A.sum(axis=0)
+    ref_sum = cs @ W3.sum(axis=1) + cs @ W3.sum(axis=0) + np.einsum("ij,ijb->b", V, W3)
+    ca = np.abs(A).sum(axis=0)
+    aW = np.abs(W3)
+    abs_sum = ca @ aW.sum(axis=1) + ca @ aW.sum(axis=0) + np.einsum("ij,ijb->b", np.abs(V), aW)
+    got = Y.sum(dim=0).cpu().numpy()
+    assert np.all(np.abs(got - ref_sum) <= 1e-12 * abs_sum)
+    # columns outside the block untouched
+    rest = torch.cat([Ybuf[:, :off], Ybuf[:, off + m :]], dim=1)
+    assert bool((rest == 3.0).all())
