@@ -44,13 +44,20 @@ template <typename T> __device__ __forceinline__ int krow(int r, int lane);
 template <> __device__ __forceinline__ int krow<double>(int r, int lane) { return 4 * r + (lane >> 4); }
 template <> __device__ __forceinline__ int krow<float>(int r, int lane) { return 4 * (lane >> 4) + r; }
 
-// position of element x of LDS row k: rows of 32 values, swizzled so that
-// the rows k4 .. k4 + 3 read together by one MFMA operand load do not share
-// banks (fp64: 256-byte rows, halves swapped on odd k; fp32: 128-byte rows,
-// halves swapped on k = 2, 3 mod 4)
-template <typename T> __device__ __forceinline__ int kswz(int x, int k);
-template <> __device__ __forceinline__ int kswz<double>(int x, int k) { return x ^ ((k & 1) << 4); }
-template <> __device__ __forceinline__ int kswz<float>(int x, int k) { return x ^ ((k & 2) << 3); }
+// position of element x of LDS row k (of the tile of column b): rows of 32
+// values, swizzled so that (1) the rows k4 .. k4 + 3 read together by one
+// MFMA operand load fall in different banks (fp64: 256-byte rows, halves
+// swapped on odd k; fp32: 128-byte rows, halves swapped on k = 2, 3 mod 4)
+// and (2) the staging stores, whose 16-lane groups span 4 column pairs and
+// 4 k rows, spread over the banks (bits 1-3 permuted by b and k, which keeps
+// the 16 values one MFMA operand row reads contiguous and pairs adjacent)
+template <typename T> __device__ __forceinline__ int kswz(int x, int k, int b);
+template <> __device__ __forceinline__ int kswz<double>(int x, int k, int b) {
+  return x ^ ((k & 1) << 4) ^ (((k >> 1) & 1) << 1) ^ ((b >> 1) << 2);
+}
+template <> __device__ __forceinline__ int kswz<float>(int x, int k, int b) {
+  return x ^ (((k >> 1) & 1) << 4) ^ ((b >> 1) << 2);
+}
 
 template <typename T>
 struct alignas(16) KronSmem {
@@ -128,7 +135,7 @@ struct KronStage {
     for (int u = 0; u < kPXK; ++u) {
       const int q = t + 256 * u;
       const int bp = q & 3, jj = (q >> 2) & (kTJ - 1), kk = q >> 7;
-      const int x = kswz<T>(jj, kk);
+      const int x = kswz<T>(jj, kk, 2 * bp);
       sm.xk[2 * bp][kk][x] = xk[u].x;
       sm.xk[2 * bp + 1][kk][x] = xk[u].y;
     }
@@ -136,19 +143,19 @@ struct KronStage {
     for (int u = 0; u < kPXI; ++u) {
       const int q = t + 256 * u;
       const int bp = q & 3, kk = (q >> 2) & (kKC - 1), ii = q >> 6;
-      const int x = kswz<T>(ii, kk);
+      const int x = kswz<T>(ii, kk, 2 * bp);
       sm.xi[2 * bp][kk][x] = xi[u].x;
       sm.xi[2 * bp + 1][kk][x] = xi[u].y;
     }
     {
       const int kp = t & 7, ii = t >> 3;
-      sm.ai[2 * kp][kswz<T>(ii, 2 * kp)] = ai.x;
-      sm.ai[2 * kp + 1][kswz<T>(ii, 2 * kp + 1)] = ai.y;
+      sm.ai[2 * kp][kswz<T>(ii, 2 * kp, 0)] = ai.x;
+      sm.ai[2 * kp + 1][kswz<T>(ii, 2 * kp + 1, 0)] = ai.y;
     }
     {
       const int jp = t & 15, kk = t >> 4;
-      // the swizzle flips bit 4 only, so the pair stays adjacent and aligned
-      *reinterpret_cast<Pair<T>*>(&sm.aj[kk][kswz<T>(2 * jp, kk)]) = aj;
+      // the swizzle leaves bit 0 alone, so the pair stays adjacent and aligned
+      *reinterpret_cast<Pair<T>*>(&sm.aj[kk][kswz<T>(2 * jp, kk, 0)]) = aj;
     }
   }
 };
@@ -182,20 +189,22 @@ __global__ __launch_bounds__(256, 2) void k_kron_mfma(const T* __restrict__ A,
     // the next chunk's loads are in flight while this chunk's MFMAs run
     const bool more = k0 + kKC < na;
     if (more) st.load(A, W, na, ldw, nc, i0, j0, b0, k0 + kKC, t);
-    // two of the four k steps unrolled: all four hold 256 registers and spill
-#pragma unroll 2
+    // k steps not unrolled: 228 registers (all four unrolled hold 256 and
+    // spill, two unrolled run 2 % slower)
+#pragma unroll 1
     for (int k4 = 0; k4 < kKC; k4 += 4) {
       const int kk = k4 + g;
       T ai[2], aj[2], xk[2][2], xi[2][2];
 #pragma unroll
       for (int s2 = 0; s2 < 2; ++s2) {
-        const int x = kswz<T>(16 * s2 + r, kk);
+        const int x = kswz<T>(16 * s2 + r, kk, 0);
         ai[s2] = sm.ai[kk][x];
         aj[s2] = sm.aj[kk][x];
 #pragma unroll
         for (int bw = 0; bw < 2; ++bw) {
-          xk[bw][s2] = sm.xk[2 * wave + bw][kk][x];
-          xi[bw][s2] = sm.xi[2 * wave + bw][kk][x];
+          const int xb = kswz<T>(16 * s2 + r, kk, 2 * wave + bw);
+          xk[bw][s2] = sm.xk[2 * wave + bw][kk][xb];
+          xi[bw][s2] = sm.xi[2 * wave + bw][kk][xb];
         }
       }
       // A W_b: A-operand A[i][k], B-operand W_b[k][j]
