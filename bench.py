@@ -124,6 +124,32 @@ def kron_only(P, synth, torch, dev, na=4096, m=8, reps=5):
         f"({100 * tf / 78.6:.0f} % of the 78.6 TFLOP/s fp64 matrix peak)")
 
 
+def dense_only(P, synth, torch, dev, n=20_000, m=8, reps=20):
+    """Times Y = A W for the dense Hessian-like operator at its full size."""
+    A = synth.dense_hessian(n, seed=synth.SEEDS["dense_hessian"][0])
+    s = P.Solver(n)
+    s.set_operator_dense(torch.from_numpy(A).to(dev))
+    del A
+    s.ensure_workspace(m)
+    W = torch.from_numpy(synth.start_block(n, m, synth.SEEDS["dense_hessian"][1])).to(dev)
+    Y = torch.empty_like(W)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        P.lobpcg_apply_operator(s.h, W, Y)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        P.lobpcg_apply_operator(s.h, W, Y)
+    ev1.record(stream)
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    nbytes = 8 * n * n + 2 * 8 * n * m
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log(f"dense: n={n} m={m}: {ms * 1e3:.1f} us per apply, {nbytes / 1e9:.3f} GB, {gbs:.0f} GB/s "
+        f"({100 * gbs / 8000:.0f} % of 8 TB/s)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +178,12 @@ def main():
         help="skip the solves: time the Kronecker-sum operator at na = 4096 (n = 16.8M) on 8 "
         "fp64 columns and print its MFMA rate",
     )
+    ap.add_argument(
+        "--dense",
+        action="store_true",
+        help="skip the solves: time the dense operator at n = 20,000 on 8 fp64 columns and print "
+        "its HBM rate",
+    )
     args = ap.parse_args()
     if args.gpus != 1:
         print(
@@ -169,6 +201,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.kron:
         kron_only(P, synth, torch, dev)
+        return
+    if args.dense:
+        dense_only(P, synth, torch, dev)
         return
     n, k = args.n, args.k
     mseed, xseed = synth.SEEDS["csr_banded"]

@@ -128,18 +128,34 @@ def test_apply_csr_strided_and_empty_rows(P):
     assert np.all(out[:, :5] == 0) and np.all(out[:, 12:] == 0)
 
 
-@pytest.mark.parametrize("n,m", [(777, 1), (2000, 4), (1031, 8), (515, 11)])
-def test_apply_dense(P, n, m):
+@pytest.mark.parametrize(
+    "n,m,ldw",
+    [
+        (777, 1, 1),  # odd sizes: value-by-value kernel
+        (2000, 4, 4),  # 16-byte vector kernel, 4 columns, ragged column tail
+        (1031, 8, 8),
+        (515, 11, 11),
+        (1030, 8, 8),  # vector kernel, 8 columns, ragged row group and tail
+        (1030, 6, 10),  # vector kernel on a strided block
+        (2050, 12, 12),  # two launches (8 + 4 columns), both vector
+        (1030, 5, 6),  # even but too narrow for whole-row W vectors
+    ],
+)
+def test_apply_dense(P, n, m, ldw):
+    say("dense", n, m, ldw)
     A = synth.dense_dd(n, seed=n)
-    W = synth.start_block(n, m, 2)
+    W = synth.start_block(n, ldw, 2)
     s = P.Solver(n)
     s.set_operator_dense(cu(A))
     s.ensure_workspace(1)
-    Y = torch.zeros((n, m), dtype=torch.float64, device="cuda")
-    P.lobpcg_apply_operator(s.h, cu(W), Y)
-    ref = A @ W
-    scale = np.abs(A) @ np.abs(W)
-    assert np.all(np.abs(host(Y) - ref) <= 1e-13 * scale)
+    Wd = cu(W)
+    Y = torch.full((n, ldw), 5.0, dtype=torch.float64, device="cuda")
+    P.lobpcg_apply_operator(s.h, Wd[:, :m], Y[:, :m])
+    ref = A @ W[:, :m]
+    scale = np.abs(A) @ np.abs(W[:, :m])
+    Yh = host(Y)
+    assert np.all(np.abs(Yh[:, :m] - ref) <= 1e-13 * scale)
+    assert np.all(Yh[:, m:] == 5.0)
 
 
 @pytest.mark.parametrize("na,m,ldw", [(19, 5, 5), (64, 8, 8), (45, 13, 16), (96, 17, 20)])
