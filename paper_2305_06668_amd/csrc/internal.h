@@ -183,17 +183,17 @@ hipError_t mlp_apply_f32(float* R, int64_t ld, int nact, int64_t n, const double
                          const int* mask, int* flags, hipStream_t st);
 // The same transform with layer 2 on bf16 MFMA (fp32 accumulate): the
 // solver's inference path.
-// tcount, tlist: device scratch for the list of super tiles (kMlpSuper
-// entries) that hold window entries: a counter that must be 0 on entry
-// (zero_count: cleared here) and tiles_cap >= ceil(n nact / kMlpSuper) ints
+// tflags: device scratch of tiles_cap >= ceil(n nact / kMlpSuper) ints,
+// one flag per super tile of kMlpSuper entries (written by the screening
+// pass, read by the MFMA pass)
 hipError_t mlp_apply_bf16_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, int* tcount, int* tlist,
-                              int64_t tiles_cap, bool zero_count, hipStream_t st);
+                              const float* w, const int* mask, int* flags, int* tflags,
+                              int64_t tiles_cap, hipStream_t st);
 hipError_t mlp_apply_bf16_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, int* tcount, int* tlist,
-                              int64_t tiles_cap, bool zero_count, hipStream_t st);
+                              const float* w, const int* mask, int* flags, int* tflags,
+                              int64_t tiles_cap, hipStream_t st);
 // grad (kMlpParams doubles) = d/dweights of sum_e G_e w_e(weights), with w
 // the learned columns of R; part needs kMlpBlocks * kMlpParams doubles.
 hipError_t mlp_grad(const double* R, const double* G, int64_t ld, int nact, int64_t n,

@@ -459,17 +459,16 @@ __device__ __forceinline__ float silu_fast(float z) {
 // Screening pass of the bf16 transform: a wave takes a super tile of
 // kMlpSuper entries (4 per lane, loaded together) and, when none of them is
 // inside the window, takes the Jacobi step for all of them (the formula of
-// the tile epilogue with c = 0); super tiles with an entry inside are
-// appended to tlist (count in *tcount, zero on entry) for the MFMA
-// kernel.  The order of the list depends on timing; every super tile
-// is processed the same way wherever it sits, so results do not.
+// the tile epilogue with c = 0); it records per super tile whether one of
+// its entries is inside (tflags[st] = 1) for the MFMA kernel.  (A list
+// appended with an atomic counter serialised ~2000 same-address atomics
+// per launch in L2.)
 template <typename T>
 __global__ __launch_bounds__(256) void k_mlp_screen(T* __restrict__ R, int64_t ld, int nact, int64_t n,
                                                     const double* __restrict__ theta,
                                                     const double* __restrict__ diag,
                                                     const double* __restrict__ rho,
-                                                    int* __restrict__ tcount,
-                                                    int* __restrict__ tlist) {
+                                                    int* __restrict__ tflags) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t total = n * nact;
   const int64_t nst = (total + kMlpSuper - 1) / kMlpSuper;
@@ -510,10 +509,9 @@ __global__ __launch_bounds__(256) void k_mlp_screen(T* __restrict__ R, int64_t l
       sdm[q] -= sth[q];
       any |= sval[q] && fabs(sdm[q]) <= kMlpWindow * srr[q];
     }
-    if (__ballot(any) != 0) {
-      if (lane == 0) tlist[atomicAdd(tcount, 1)] = (int)st;
-      continue;
-    }
+    const bool listed = __ballot(any) != 0;
+    if (lane == 0) tflags[st] = listed ? 1 : 0;
+    if (listed) continue;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       if (!sval[q]) continue;
@@ -535,8 +533,7 @@ __global__ __launch_bounds__(256, 2) void k_mlp_apply_bf16(T* __restrict__ R, in
                                                         const float* __restrict__ wts,
                                                         const int* __restrict__ mask,
                                                         int* __restrict__ flags,
-                                                        const int* __restrict__ tcount,
-                                                        const int* __restrict__ tlist) {
+                                                        const int* __restrict__ tflags) {
   constexpr int kBS = kH + 8;  // padded row stride of the bf16 W2 copy
   __shared__ float4 w1s[kH];  // (W1[k][0..2], b1[k])
   __shared__ __attribute__((aligned(16))) __bf16 w2s[kH * kBS];
@@ -559,120 +556,131 @@ __global__ __launch_bounds__(256, 2) void k_mlp_apply_bf16(T* __restrict__ R, in
   const int64_t total = n * nact;
   constexpr int E = 16 * MT;  // entries per wave tile
   const int64_t nwt = (total + E - 1) / E;
-  // the super tiles (kSE entries) that k_mlp_screen found to hold entries
-  // inside the window, one per wave iteration, each as kSE / E tiles
+  // the super tiles (kSE entries) that k_mlp_screen flagged as holding
+  // entries inside the window, each taken as kSE / E tiles
   constexpr int kSE = kMlpSuper, kTS = kSE / E;
-  const int nlist = *tcount;
-  for (int li = blockIdx.x * 4 + wave; li < nlist; li += gridDim.x * 4) {
-    const int64_t st = tlist[li];
-    for (int u = 0; u < kTS; ++u) {
-      const int64_t wt = st * kTS + u;
-      if (wt >= nwt) break;
-      // keep the weight reads inside the loop (LDS re-reads are cheap; holding
-      // every fragment in registers for the whole kernel would cap occupancy)
-      asm volatile("" ::: "memory");
-      // lane l < E owns entry l of the tile: its operands are loaded once
-      const int64_t ent = wt * E + lane;
-      const bool valid = lane < E && ent < total;
-      int64_t row = 0;
-      int col = 0;
-      double th = 0.0, dmd = 0.0, rr = 0.0;
-      if (valid) {
-        row = ent / nact;
-        col = (int)(ent - row * nact);
-        th = theta[col];
-        dmd = diag[row] - th;
-        rr = rho[row];
-      }
-      const bool inside = valid && fabs(dmd) <= kMlpWindow * rr;
-      // the net only acts inside the window: a tile without such entries takes
-      // the Jacobi step everywhere and skips it
-      float yv = 0.0f;
-      if (__ballot(inside) != 0) {
-        // features (fp32 logs of the fp64 difference d - theta); the four
-        // lanes that hold an entry's A rows read them with shuffles
-        float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+  // wave w takes super tiles w, w + nw, w + 2 nw, ...: their flags are read
+  // 64 at a time (one per lane) and the flagged ones processed in order
+  const int64_t nst = (total + kSE - 1) / kSE;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave, nw = (int64_t)gridDim.x * 4;
+  for (int64_t jb = 0; gw + jb * nw < nst; jb += 64) {
+    const int64_t mine = gw + (jb + lane) * nw;
+    uint64_t pend = __ballot(mine < nst && tflags[mine] != 0);
+    while (pend != 0) {
+      const int bit = __builtin_ctzll(pend);
+      pend &= pend - 1;
+      const int64_t st = gw + (jb + bit) * nw;
+      for (int u = 0; u < kTS; ++u) {
+        const int64_t wt = st * kTS + u;
+        if (wt >= nwt) break;
+        // keep the weight reads inside the loop (LDS re-reads are cheap; holding
+        // every fragment in registers for the whole kernel would cap occupancy)
+        asm volatile("" ::: "memory");
+        // lane l < E owns entry l of the tile: its operands are loaded once
+        const int64_t ent = wt * E + lane;
+        const bool valid = lane < E && ent < total;
+        int64_t row = 0;
+        int col = 0;
+        double th = 0.0, dmd = 0.0, rr = 0.0;
         if (valid) {
-          f0 = __logf((float)(fabs(dmd) * inv_s) + 1e-6f);
-          f1 = (float)(th * inv_s);
-          f2 = __logf((float)(rr * inv_s) + 1e-6f);
+          row = ent / nact;
+          col = (int)(ent - row * nact);
+          th = theta[col];
+          dmd = diag[row] - th;
+          rr = rho[row];
         }
-        float ph[MT][3];
-  #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-          ph[t][0] = __shfl(f0, 16 * t + r, 64);
-          ph[t][1] = __shfl(f1, 16 * t + r, 64);
-          ph[t][2] = __shfl(f2, 16 * t + r, 64);
-        }
-        f32x4 acc[MT][8];
-  #pragma unroll
-        for (int t = 0; t < MT; ++t)
-  #pragma unroll
-          for (int nt = 0; nt < 8; ++nt) acc[t][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          bf16x8 bq[8];
-  #pragma unroll
-          for (int nt = 0; nt < 8; ++nt)
-            bq[nt] = *reinterpret_cast<const bf16x8*>(w2s + (16 * nt + r) * kBS + 32 * ks + 8 * g);
-  #pragma unroll
+        const bool inside = valid && fabs(dmd) <= kMlpWindow * rr;
+        // the net only acts inside the window: a tile without such entries takes
+        // the Jacobi step everywhere and skips it
+        float yv = 0.0f;
+        if (__ballot(inside) != 0) {
+          // features (fp32 logs of the fp64 difference d - theta); the four
+          // lanes that hold an entry's A rows read them with shuffles
+          float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+          if (valid) {
+            f0 = __logf((float)(fabs(dmd) * inv_s) + 1e-6f);
+            f1 = (float)(th * inv_s);
+            f2 = __logf((float)(rr * inv_s) + 1e-6f);
+          }
+          float ph[MT][3];
+    #pragma unroll
           for (int t = 0; t < MT; ++t) {
-            bf16x8 a;
-  #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const float4 w = w1s[32 * ks + 8 * g + j];
-              const float z = w.w + w.x * ph[t][0] + w.y * ph[t][1] + w.z * ph[t][2];
-              a[j] = (__bf16)silu_fast(z);
-            }
-  #pragma unroll
+            ph[t][0] = __shfl(f0, 16 * t + r, 64);
+            ph[t][1] = __shfl(f1, 16 * t + r, 64);
+            ph[t][2] = __shfl(f2, 16 * t + r, 64);
+          }
+          f32x4 acc[MT][8];
+    #pragma unroll
+          for (int t = 0; t < MT; ++t)
+    #pragma unroll
+            for (int nt = 0; nt < 8; ++nt) acc[t][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    #pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            bf16x8 bq[8];
+    #pragma unroll
             for (int nt = 0; nt < 8; ++nt)
-              acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[nt], acc[t][nt], 0, 0, 0);
+              bq[nt] =
+                  *reinterpret_cast<const bf16x8*>(w2s + (16 * nt + r) * kBS + 32 * ks + 8 * g);
+    #pragma unroll
+            for (int t = 0; t < MT; ++t) {
+              bf16x8 a;
+    #pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                const float4 w = w1s[32 * ks + 8 * g + j];
+                const float z = w.w + w.x * ph[t][0] + w.y * ph[t][1] + w.z * ph[t][2];
+                a[j] = (__bf16)silu_fast(z);
+              }
+    #pragma unroll
+              for (int nt = 0; nt < 8; ++nt)
+                acc[t][nt] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[nt], acc[t][nt], 0, 0, 0);
+            }
           }
-        }
-        // layer 3: y of entry 16 t + 4 g + i, summed over the 16 lanes of segment g
-        float y[MT][4];
-  #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-  #pragma unroll
-          for (int i = 0; i < 4; ++i) y[t][i] = 0.0f;
-  #pragma unroll
-          for (int nt = 0; nt < 8; ++nt)
-  #pragma unroll
+          // layer 3: y of entry 16 t + 4 g + i, summed over the 16 lanes of segment g
+          float y[MT][4];
+    #pragma unroll
+          for (int t = 0; t < MT; ++t) {
+    #pragma unroll
+            for (int i = 0; i < 4; ++i) y[t][i] = 0.0f;
+    #pragma unroll
+            for (int nt = 0; nt < 8; ++nt)
+    #pragma unroll
+              for (int i = 0; i < 4; ++i)
+                y[t][i] = fmaf(w3r[nt], silu_fast(acc[t][nt][i] + b2r[nt]), y[t][i]);
+    #pragma unroll
             for (int i = 0; i < 4; ++i)
-              y[t][i] = fmaf(w3r[nt], silu_fast(acc[t][nt][i] + b2r[nt]), y[t][i]);
-  #pragma unroll
-          for (int i = 0; i < 4; ++i)
-  #pragma unroll
-            for (int off = 8; off >= 1; off >>= 1) y[t][i] += __shfl_xor(y[t][i], off, 16);
-        }
-        // entry L's y sits in segment (L % 16) / 4, slot (t = L / 16, i = L % 4)
-        const int src = 16 * ((lane & 15) >> 2);
-  #pragma unroll
-        for (int t = 0; t < MT; ++t)
-  #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float v = __shfl(y[t][i], src, 64);
-            if ((lane >> 4) == t && (lane & 3) == i) yv = v;
+    #pragma unroll
+              for (int off = 8; off >= 1; off >>= 1) y[t][i] += __shfl_xor(y[t][i], off, 16);
           }
-        yv += b3;
-      }
-      // epilogue: w = r / sqrt((d - theta)^2 + c^2), floored at the guard
-      if (valid) {
-        bool jac = !inside || (mask != nullptr && mask[col] != 0);
-        float c = 0.0f;
-        if (!jac) {
-          // c = s softplus(y), fp32 (the net itself ran in bf16)
-          c = (float)s * (fmaxf(yv, 0.0f) + __logf(1.0f + __expf(-fabsf(yv))));
-          if (!isfinite(c)) {
-            if (flags) flags[col] = 1;
-            c = 0.0f;
-          }
+          // entry L's y sits in segment (L % 16) / 4, slot (t = L / 16, i = L % 4)
+          const int src = 16 * ((lane & 15) >> 2);
+    #pragma unroll
+          for (int t = 0; t < MT; ++t)
+    #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float v = __shfl(y[t][i], src, 64);
+              if ((lane >> 4) == t && (lane & 3) == i) yv = v;
+            }
+          yv += b3;
         }
-        const float dm = (float)dmd;
-        const float delta = (float)(kPrecondGuard * fmax(1.0, fabs(th)));
-        const float q = fmaxf(dm * dm + c * c, delta * delta);
-        T* p = R + row * ld + col;
-        *p = (T)((double)*p * (double)__frsqrt_rn(q));
+        // epilogue: w = r / sqrt((d - theta)^2 + c^2), floored at the guard
+        if (valid) {
+          bool jac = !inside || (mask != nullptr && mask[col] != 0);
+          float c = 0.0f;
+          if (!jac) {
+            // c = s softplus(y), fp32 (the net itself ran in bf16)
+            c = (float)s * (fmaxf(yv, 0.0f) + __logf(1.0f + __expf(-fabsf(yv))));
+            if (!isfinite(c)) {
+              if (flags) flags[col] = 1;
+              c = 0.0f;
+            }
+          }
+          const float dm = (float)dmd;
+          const float delta = (float)(kPrecondGuard * fmax(1.0, fabs(th)));
+          const float q = fmaxf(dm * dm + c * c, delta * delta);
+          T* p = R + row * ld + col;
+          *p = (T)((double)*p * (double)__frsqrt_rn(q));
+        }
       }
     }
   }
@@ -769,43 +777,37 @@ int mlp_grid(int64_t total) {
 template <typename T>
 static hipError_t mlp_apply_bf16_t(T* R, int64_t ld, int nact, int64_t n, const double* theta,
                                    const double* diag, const double* rho, const double* s,
-                                   const float* w, const int* mask, int* flags, int* tcount,
-                                   int* tlist, int64_t tiles_cap, bool zero_count,
-                                   hipStream_t st) {
+                                   const float* w, const int* mask, int* flags, int* tflags,
+                                   int64_t tiles_cap, hipStream_t st) {
   if (n <= 0 || nact <= 0) return hipSuccess;
   constexpr int MT = kMlpTilesPerWave;
   const int64_t nst = (n * nact + kMlpSuper - 1) / kMlpSuper;
-  if (tcount == nullptr || tlist == nullptr || nst > tiles_cap || nst > INT32_MAX)
-    return hipErrorInvalidValue;
+  if (tflags == nullptr || nst > tiles_cap) return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
-  if (zero_count) {
-    e = hipMemsetAsync(tcount, 0, sizeof(int), st);
-    if (e != hipSuccess) return e;
-  }
   const int sgrid = (int)std::min<int64_t>((nst + 3) / 4, 4096);
   hipLaunchKernelGGL((k_mlp_screen<T>), dim3(sgrid), dim3(256), 0, st, R, ld, nact, n, theta, diag,
-                     rho, tcount, tlist);
+                     rho, tflags);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // two waves per SIMD (the MFMA path holds ~240 registers): 2 blocks per CU
   hipLaunchKernelGGL((k_mlp_apply_bf16<T, MT>), dim3(512), dim3(256), 0, st, R, ld, nact, n, theta,
-                     diag, rho, s, w, mask, flags, tcount, tlist);
+                     diag, rho, s, w, mask, flags, tflags);
   return hipGetLastError();
 }
 
 hipError_t mlp_apply_bf16_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, int* tcount, int* tlist,
-                              int64_t tiles_cap, bool zero_count, hipStream_t st) {
-  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tcount, tlist,
-                          tiles_cap, zero_count, st);
+                              const float* w, const int* mask, int* flags, int* tflags,
+                              int64_t tiles_cap, hipStream_t st) {
+  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tflags, tiles_cap,
+                          st);
 }
 hipError_t mlp_apply_bf16_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, int* tcount, int* tlist,
-                              int64_t tiles_cap, bool zero_count, hipStream_t st) {
-  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tcount, tlist,
-                          tiles_cap, zero_count, st);
+                              const float* w, const int* mask, int* flags, int* tflags,
+                              int64_t tiles_cap, hipStream_t st) {
+  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tflags, tiles_cap,
+                          st);
 }
 
 template <typename T>

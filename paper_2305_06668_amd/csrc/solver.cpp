@@ -64,13 +64,12 @@ Layout lobpcg_ctx::plan(int m) const {
   L.a = stake(sizeof(double) * kGramMaxCols * kGramMaxCols);
   // read back once per iteration as one block: residual norms (64),
   // Ritz values (two slots of 64), RR info (64 ints), learned-path flags
-  // (64 ints) and the learned transform's super-tile counter
-  L.rb = stake(kReadbackBytes + 256);
+  // (64 ints)
+  L.rb = stake(kReadbackBytes);
   L.resn2 = L.rb;
   L.theta = L.rb + 512;
   L.info = L.rb + 1536;
   L.lflags = L.rb + 1792;
-  L.ltcount = L.rb + 2048;
   L.U = stake(sizeof(double) * kMaxP * 64);
   L.G = stake(sizeof(double) * kMaxP * kMaxBlock);
   L.coef = stake(sizeof(double) * kMaxP * kMaxBlock);
@@ -223,19 +222,17 @@ static hipError_t gram_t(const float* A, int64_t lda, int p, const float* B, int
 static hipError_t mlp_apply_t(bool bf16, double* R, int64_t ld, int nact, int64_t n,
                               const double* theta, const double* diag, const double* rho,
                               const double* s, const float* w, const int* mask, int* flags,
-                              int* tcount, int* tlist, int64_t tiles_cap, bool zero_count,
-                              hipStream_t st) {
-  return bf16 ? mlp_apply_bf16_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tcount, tlist,
-                                   tiles_cap, zero_count, st)
+                              int* tflags, int64_t tiles_cap, hipStream_t st) {
+  return bf16 ? mlp_apply_bf16_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tflags,
+                                   tiles_cap, st)
               : mlp_apply_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
 }
 static hipError_t mlp_apply_t(bool bf16, float* R, int64_t ld, int nact, int64_t n,
                               const double* theta, const double* diag, const double* rho,
                               const double* s, const float* w, const int* mask, int* flags,
-                              int* tcount, int* tlist, int64_t tiles_cap, bool zero_count,
-                              hipStream_t st) {
-  return bf16 ? mlp_apply_bf16_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tcount, tlist,
-                                   tiles_cap, zero_count, st)
+                              int* tflags, int64_t tiles_cap, hipStream_t st) {
+  return bf16 ? mlp_apply_bf16_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tflags,
+                                   tiles_cap, st)
               : mlp_apply_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
 }
 static hipError_t rotate_t(const double* V, const double* AV, double* Vo, double* AVo,
@@ -392,7 +389,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
   int* lmask = small_ptr<int>(lay.lmask);
   int* lflags = small_ptr<int>(lay.lflags);
   int* hmask = reinterpret_cast<int*>(pinned + kPinnedBytes / 2);
-  if (learned) HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 65, stream));  // flags + tile counter
+  if (learned) HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
   int rc = ortho_run<T>(V[0], m, 0, m, nullptr, true, tau_phase);
   if (rc) return rc;
   rc = apply_op(V[0], m, m, AV[0], m);
@@ -541,11 +538,11 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
         r_before[j] = rnorm[j];
       }
       HIPCHK(hipMemcpyAsync(lmask, hmask, sizeof(int) * nact, hipMemcpyHostToDevice, stream));
-      HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 65, stream));  // flags + tile counter
+      HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
       HIPCHK(mlp_apply_t(learned_bf16 != 0, V[1 - c] + q, ldo, nact, n, theta + a0,
                          dptr(lay.diag), dptr(lay.rho), small_ptr<double>(lay.lscale), lweights,
-                         lmask, lflags, small_ptr<int>(lay.ltcount),
-                         reinterpret_cast<int*>(ws + lay.ltiles), ltiles_cap(), false, stream));
+                         lmask, lflags, reinterpret_cast<int*>(ws + lay.ltiles), ltiles_cap(),
+                         stream));
       prev_a0 = a0;
       prev_nact = nact;
     }
@@ -915,8 +912,7 @@ int lobpcg_learned_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const dou
   hipError_t e = mlp_apply_t(h->learned_bf16 != 0, R, ldr, nact, h->n, theta,
                              h->dptr(h->lay.diag), h->dptr(h->lay.rho),
                              h->small_ptr<double>(h->lay.lscale), h->lweights, mask, nullptr,
-                             h->small_ptr<int>(h->lay.ltcount),
-                             reinterpret_cast<int*>(h->ws + h->lay.ltiles), h->ltiles_cap(), true,
+                             reinterpret_cast<int*>(h->ws + h->lay.ltiles), h->ltiles_cap(),
                              h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "learned apply");
   return LOBPCG_OK;

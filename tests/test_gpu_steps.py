@@ -90,7 +90,7 @@ def test_gram_deterministic(P):
     assert torch.equal(C1, C2)
 
 
-@pytest.mark.parametrize("m", [1, 3, 4, 8, 16, 17, 32, 40])
+@pytest.mark.parametrize("m", [1, 3, 4, 8, 9, 12, 16, 17, 32, 40])
 def test_apply_csr(P, m):
     say("apply_csr", m)
     n = 30011
