@@ -29,7 +29,7 @@ struct Layout {
   size_t V[2], AV[2], diag, rho, ltiles, part, small, total;
   size_t V32[2], AV32[2], op32;  // mixed precision only (0 otherwise)
   // inside small (byte offsets)
-  size_t a, rb, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye, lmask, lflags, lscale;
+  size_t a, rb, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye, lflags, lscale;
 };
 
 }  // namespace lobpcg

@@ -172,15 +172,17 @@ hipError_t ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner,
 // In place: R[:, 0:nact] (n rows, leading dimension ld) <- learned
 // preconditioned columns for Ritz values theta[0:nact]; diag, rho (off-
 // diagonal absolute row sums) and *s (mean |diag|) describe the operator;
-// w holds kMlpParams fp32 weights; mask[j] != 0 (optional) selects the
-// Jacobi step for column j; flags[j] (optional) is set to 1 where a net
-// output was not finite (that entry then takes the Jacobi step).
+// w holds kMlpParams fp32 weights; mask[j] != 0 (optional, device) or bit j
+// of mbits selects the Jacobi step for column j; flags[j] (optional) is set
+// to 1 where a net output was not finite (that entry then takes the Jacobi
+// step).  The bf16 form clears flags[0 .. nact) itself; the fp32 form
+// expects them cleared.
 hipError_t mlp_apply_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
                          const double* diag, const double* rho, const double* s, const float* w,
-                         const int* mask, int* flags, hipStream_t st);
+                         const int* mask, uint64_t mbits, int* flags, hipStream_t st);
 hipError_t mlp_apply_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
                          const double* diag, const double* rho, const double* s, const float* w,
-                         const int* mask, int* flags, hipStream_t st);
+                         const int* mask, uint64_t mbits, int* flags, hipStream_t st);
 // The same transform with layer 2 on bf16 MFMA (fp32 accumulate): the
 // solver's inference path.
 // tflags: device scratch of tiles_cap >= ceil(n nact / kMlpSuper) ints,
@@ -188,12 +190,12 @@ hipError_t mlp_apply_f32(float* R, int64_t ld, int nact, int64_t n, const double
 // pass, read by the MFMA pass)
 hipError_t mlp_apply_bf16_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, int* tflags,
-                              int64_t tiles_cap, hipStream_t st);
+                              const float* w, const int* mask, uint64_t mbits, int* flags,
+                              int* tflags, int64_t tiles_cap, hipStream_t st);
 hipError_t mlp_apply_bf16_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, int* tflags,
-                              int64_t tiles_cap, hipStream_t st);
+                              const float* w, const int* mask, uint64_t mbits, int* flags,
+                              int* tflags, int64_t tiles_cap, hipStream_t st);
 // grad (kMlpParams doubles) = d/dweights of sum_e G_e w_e(weights), with w
 // the learned columns of R; part needs kMlpBlocks * kMlpParams doubles.
 hipError_t mlp_grad(const double* R, const double* G, int64_t ld, int nact, int64_t n,

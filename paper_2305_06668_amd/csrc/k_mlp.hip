@@ -9,7 +9,8 @@
 // window |d_i - theta| <= 16 rho_i, c = 0 by definition (the regulariser
 // only matters where d_i is within a few couplings of theta), and a tile
 // with no entry inside the window skips the net.  A column flagged in
-// `mask`, and any entry whose net output is not finite, takes c = 0: the
+// `mask` or in the bit set `mbits`, and any entry whose net output is not
+// finite, takes c = 0: the
 // guarded absolute Jacobi step (the diagonal fallback).
 //
 // Work layout: a workgroup of 256 threads holds W2^T (128 x 128 fp32, rows
@@ -205,6 +206,7 @@ __global__ __launch_bounds__(256) void k_mlp_apply(T* __restrict__ R, int64_t ld
                                                    const double* __restrict__ sptr,
                                                    const float* __restrict__ wts,
                                                    const int* __restrict__ mask,
+                                                   uint64_t mbits,
                                                    int* __restrict__ flags) {
   extern __shared__ float L[];
   load_weights(wts, L);
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(256) void k_mlp_apply(T* __restrict__ R, int64_t ld
     // the net only matters inside the window: skip it for tiles without such entries
     if (__syncthreads_or(threadIdx.x < kTE && in.valid && in.inside)) forward_tile(L, z2, eg, kg);
     if (threadIdx.x < kTE && in.valid) {
-      const bool jac = mask != nullptr && mask[in.col] != 0;
+      const bool jac = ((mbits >> in.col) & 1) != 0 || (mask != nullptr && mask[in.col] != 0);
       const EntryOut o = regularise(in, L[sY + threadIdx.x], s, jac, flags);
       T* p = R + in.row * ld + in.col;
       *p = (T)((double)*p / sqrt(o.q));
@@ -468,8 +470,11 @@ __global__ __launch_bounds__(256) void k_mlp_screen(T* __restrict__ R, int64_t l
                                                     const double* __restrict__ theta,
                                                     const double* __restrict__ diag,
                                                     const double* __restrict__ rho,
+                                                    int* __restrict__ flags,
                                                     int* __restrict__ tflags) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the MFMA pass (next on the stream) sets flags[j] for non-finite outputs
+  if (flags != nullptr && blockIdx.x == 0 && (int)threadIdx.x < nact) flags[threadIdx.x] = 0;
   const int64_t total = n * nact;
   const int64_t nst = (total + kMlpSuper - 1) / kMlpSuper;
   constexpr int Q = kMlpSuper / 64;
@@ -532,6 +537,7 @@ __global__ __launch_bounds__(256, 2) void k_mlp_apply_bf16(T* __restrict__ R, in
                                                         const double* __restrict__ sptr,
                                                         const float* __restrict__ wts,
                                                         const int* __restrict__ mask,
+                                                        uint64_t mbits,
                                                         int* __restrict__ flags,
                                                         const int* __restrict__ tflags) {
   constexpr int kBS = kH + 8;  // padded row stride of the bf16 W2 copy
@@ -665,7 +671,7 @@ __global__ __launch_bounds__(256, 2) void k_mlp_apply_bf16(T* __restrict__ R, in
         }
         // epilogue: w = r / sqrt((d - theta)^2 + c^2), floored at the guard
         if (valid) {
-          bool jac = !inside || (mask != nullptr && mask[col] != 0);
+          bool jac = !inside || ((mbits >> col) & 1) != 0 || (mask != nullptr && mask[col] != 0);
           float c = 0.0f;
           if (!jac) {
             // c = s softplus(y), fp32 (the net itself ran in bf16)
@@ -777,8 +783,8 @@ int mlp_grid(int64_t total) {
 template <typename T>
 static hipError_t mlp_apply_bf16_t(T* R, int64_t ld, int nact, int64_t n, const double* theta,
                                    const double* diag, const double* rho, const double* s,
-                                   const float* w, const int* mask, int* flags, int* tflags,
-                                   int64_t tiles_cap, hipStream_t st) {
+                                   const float* w, const int* mask, uint64_t mbits, int* flags,
+                                   int* tflags, int64_t tiles_cap, hipStream_t st) {
   if (n <= 0 || nact <= 0) return hipSuccess;
   constexpr int MT = kMlpTilesPerWave;
   const int64_t nst = (n * nact + kMlpSuper - 1) / kMlpSuper;
@@ -786,34 +792,35 @@ static hipError_t mlp_apply_bf16_t(T* R, int64_t ld, int nact, int64_t n, const 
   hipError_t e = hipSuccess;
   const int sgrid = (int)std::min<int64_t>((nst + 3) / 4, 4096);
   hipLaunchKernelGGL((k_mlp_screen<T>), dim3(sgrid), dim3(256), 0, st, R, ld, nact, n, theta, diag,
-                     rho, tflags);
+                     rho, flags, tflags);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // two waves per SIMD (the MFMA path holds ~240 registers): 2 blocks per CU
   hipLaunchKernelGGL((k_mlp_apply_bf16<T, MT>), dim3(512), dim3(256), 0, st, R, ld, nact, n, theta,
-                     diag, rho, s, w, mask, flags, tflags);
+                     diag, rho, s, w, mask, mbits, flags, tflags);
   return hipGetLastError();
 }
 
 hipError_t mlp_apply_bf16_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, int* tflags,
-                              int64_t tiles_cap, hipStream_t st) {
-  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tflags, tiles_cap,
-                          st);
+                              const float* w, const int* mask, uint64_t mbits, int* flags,
+                              int* tflags, int64_t tiles_cap, hipStream_t st) {
+  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, mbits, flags, tflags,
+                          tiles_cap, st);
 }
 hipError_t mlp_apply_bf16_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, int* tflags,
-                              int64_t tiles_cap, hipStream_t st) {
-  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tflags, tiles_cap,
-                          st);
+                              const float* w, const int* mask, uint64_t mbits, int* flags,
+                              int* tflags, int64_t tiles_cap, hipStream_t st) {
+  return mlp_apply_bf16_t(R, ld, nact, n, theta, diag, rho, s, w, mask, mbits, flags, tflags,
+                          tiles_cap, st);
 }
 
 template <typename T>
 static hipError_t mlp_apply_t(T* R, int64_t ld, int nact, int64_t n, const double* theta,
                               const double* diag, const double* rho, const double* s,
-                              const float* w, const int* mask, int* flags, hipStream_t st) {
+                              const float* w, const int* mask, uint64_t mbits, int* flags,
+                              hipStream_t st) {
   if (n <= 0 || nact <= 0) return hipSuccess;
   static bool attr = false;
   if (!attr) {
@@ -823,19 +830,19 @@ static hipError_t mlp_apply_t(T* R, int64_t ld, int nact, int64_t n, const doubl
     attr = true;
   }
   hipLaunchKernelGGL(k_mlp_apply<T>, dim3(mlp_grid(n * nact)), dim3(256), kFwdBytes, st, R, ld,
-                     nact, n, theta, diag, rho, s, w, mask, flags);
+                     nact, n, theta, diag, rho, s, w, mask, mbits, flags);
   return hipGetLastError();
 }
 
 hipError_t mlp_apply_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
                          const double* diag, const double* rho, const double* s, const float* w,
-                         const int* mask, int* flags, hipStream_t st) {
-  return mlp_apply_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+                         const int* mask, uint64_t mbits, int* flags, hipStream_t st) {
+  return mlp_apply_t(R, ld, nact, n, theta, diag, rho, s, w, mask, mbits, flags, st);
 }
 hipError_t mlp_apply_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
                          const double* diag, const double* rho, const double* s, const float* w,
-                         const int* mask, int* flags, hipStream_t st) {
-  return mlp_apply_t(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+                         const int* mask, uint64_t mbits, int* flags, hipStream_t st) {
+  return mlp_apply_t(R, ld, nact, n, theta, diag, rho, s, w, mask, mbits, flags, st);
 }
 
 hipError_t mlp_grad(const double* R, const double* G, int64_t ld, int nact, int64_t n,

@@ -151,7 +151,7 @@ int lobpcg_learner::decrease(Snapshot& S, const double* W0, bool run_mlp, const 
   HIPCHK(hipMemcpyAsync(W, W0, sizeof(double) * n * nc, hipMemcpyDeviceToDevice, st));
   if (run_mlp)
     HIPCHK(mlp_apply_f64(W, nc, nc, n, thc, h->dptr(h->lay.diag), h->dptr(h->lay.rho),
-                         h->small_ptr<double>(h->lay.lscale), w, mask, nullptr, st));
+                         h->small_ptr<double>(h->lay.lscale), w, mask, 0, nullptr, st));
   HIPCHK(gram_f64(S.X, m, m, W, nc, nc, n, gpart, s_C(), nullptr, st));
   HIPCHK(project_block(W, nc, S.X, m, m, s_C(), nc, n, U, nc, st));
   int rc = h->apply_op(U, nc, nc, AU, nc);

@@ -78,7 +78,6 @@ Layout lobpcg_ctx::plan(int m) const {
   L.pidx = stake(sizeof(int64_t) * 256 * 64);
   L.pval = stake(sizeof(double) * 256 * 64);
   L.eye = stake(sizeof(double) * 64 * 64);
-  L.lmask = stake(sizeof(int) * 64);
   L.lscale = stake(sizeof(double) * 4);
   L.small = take(so);
   if (precision == LOBPCG_PREC_FP32) {
@@ -221,19 +220,21 @@ static hipError_t gram_t(const float* A, int64_t lda, int p, const float* B, int
 }
 static hipError_t mlp_apply_t(bool bf16, double* R, int64_t ld, int nact, int64_t n,
                               const double* theta, const double* diag, const double* rho,
-                              const double* s, const float* w, const int* mask, int* flags,
-                              int* tflags, int64_t tiles_cap, hipStream_t st) {
-  return bf16 ? mlp_apply_bf16_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tflags,
-                                   tiles_cap, st)
-              : mlp_apply_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+                              const double* s, const float* w, const int* mask,
+                              uint64_t mbits, int* flags, int* tflags, int64_t tiles_cap,
+                              hipStream_t st) {
+  return bf16 ? mlp_apply_bf16_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, mbits, flags,
+                                   tflags, tiles_cap, st)
+              : mlp_apply_f64(R, ld, nact, n, theta, diag, rho, s, w, mask, mbits, flags, st);
 }
 static hipError_t mlp_apply_t(bool bf16, float* R, int64_t ld, int nact, int64_t n,
                               const double* theta, const double* diag, const double* rho,
-                              const double* s, const float* w, const int* mask, int* flags,
-                              int* tflags, int64_t tiles_cap, hipStream_t st) {
-  return bf16 ? mlp_apply_bf16_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, tflags,
-                                   tiles_cap, st)
-              : mlp_apply_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, flags, st);
+                              const double* s, const float* w, const int* mask,
+                              uint64_t mbits, int* flags, int* tflags, int64_t tiles_cap,
+                              hipStream_t st) {
+  return bf16 ? mlp_apply_bf16_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, mbits, flags,
+                                   tflags, tiles_cap, st)
+              : mlp_apply_f32(R, ld, nact, n, theta, diag, rho, s, w, mask, mbits, flags, st);
 }
 static hipError_t rotate_t(const double* V, const double* AV, double* Vo, double* AVo,
                            const RotateArgs& a, hipStream_t s) {
@@ -386,9 +387,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
   std::vector<char> used_learned(m, 0);
   std::vector<double> r_before(m, 0.0);
   int prev_a0 = 0, prev_nact = 0;
-  int* lmask = small_ptr<int>(lay.lmask);
   int* lflags = small_ptr<int>(lay.lflags);
-  int* hmask = reinterpret_cast<int*>(pinned + kPinnedBytes / 2);
   if (learned) HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
   int rc = ortho_run<T>(V[0], m, 0, m, nullptr, true, tau_phase);
   if (rc) return rc;
@@ -530,19 +529,21 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     ++iter;
     // ---- W = ortho(T R; [X P]) and AW = A W (Alg. 1) ----
     if (learned) {
+      // the fallback columns go to the kernels as a bit set (no copy); the
+      // bf16 transform clears its flags itself
+      uint64_t mbits = 0;
       for (int j = a0; j < m; ++j) {
         const bool jac = fb_left[j] > 0;
         if (jac) --fb_left[j];
-        hmask[j - a0] = jac ? 1 : 0;
+        if (jac) mbits |= uint64_t(1) << (j - a0);
         used_learned[j] = jac ? 0 : 1;
         r_before[j] = rnorm[j];
       }
-      HIPCHK(hipMemcpyAsync(lmask, hmask, sizeof(int) * nact, hipMemcpyHostToDevice, stream));
-      HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
+      if (!learned_bf16) HIPCHK(hipMemsetAsync(lflags, 0, sizeof(int) * 64, stream));
       HIPCHK(mlp_apply_t(learned_bf16 != 0, V[1 - c] + q, ldo, nact, n, theta + a0,
                          dptr(lay.diag), dptr(lay.rho), small_ptr<double>(lay.lscale), lweights,
-                         lmask, lflags, reinterpret_cast<int*>(ws + lay.ltiles), ltiles_cap(),
-                         stream));
+                         nullptr, mbits, lflags, reinterpret_cast<int*>(ws + lay.ltiles),
+                         ltiles_cap(), stream));
       prev_a0 = a0;
       prev_nact = nact;
     }
@@ -911,9 +912,9 @@ int lobpcg_learned_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const dou
   if (rc) return rc;
   hipError_t e = mlp_apply_t(h->learned_bf16 != 0, R, ldr, nact, h->n, theta,
                              h->dptr(h->lay.diag), h->dptr(h->lay.rho),
-                             h->small_ptr<double>(h->lay.lscale), h->lweights, mask, nullptr,
-                             reinterpret_cast<int*>(h->ws + h->lay.ltiles), h->ltiles_cap(),
-                             h->stream);
+                             h->small_ptr<double>(h->lay.lscale), h->lweights, mask, 0,
+                             nullptr, reinterpret_cast<int*>(h->ws + h->lay.ltiles),
+                             h->ltiles_cap(), h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "learned apply");
   return LOBPCG_OK;
 }
