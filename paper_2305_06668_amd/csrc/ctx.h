@@ -18,6 +18,7 @@ constexpr size_t kAlign = 256;
 // ~13 us of launches; a further check costs a ~30 us read-back)
 constexpr int kOrthoRounds = 3;
 constexpr size_t kReadbackBytes = 2048;  // resn2, theta (2 slots), info, learned flags
+constexpr size_t kPostBytes = 4096;      // largest status block posted to the host
 constexpr int kOrthoHardCap = 64;   // rounds before giving up
 constexpr size_t kPinnedBytes = 1 << 16;
 
@@ -89,9 +90,15 @@ struct lobpcg_ctx {
   bool op32_ready = false;
   double norm_bound = -1.0;
 
+  // coherent host memory (kPostBytes of data, then the sequence word) that a
+  // kernel writes status blocks into; post_dev is its device address
+  uint32_t* post = nullptr;
+  uint32_t* post_dev = nullptr;
+  uint32_t post_seq = 0;
+
   // ---- helpers ----
   double* dptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
-  // super-tile list of the bf16 learned transform: up to 64 columns
+  // super-tile flags of the bf16 learned transform: up to 64 columns
   int64_t ltiles_cap() const { return (n * 64 + lobpcg::kMlpSuper - 1) / lobpcg::kMlpSuper; }
   template <typename T> T* small_ptr(size_t off) const {
     return reinterpret_cast<T*>(ws + lay.small + off);
@@ -108,6 +115,10 @@ struct lobpcg_ctx {
   size_t op32_elems() const;
   int ensure_layout(int m);
   int apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy);
+  // brings `bytes` (a multiple of 4, at most kPostBytes) of device memory
+  // at src to the host once the work queued before it has run; *out points
+  // at the host copy until the next read-back
+  int readback(const void* src, size_t bytes, const void** out);
   int apply_op(const float* W, int64_t ldw, int nc, float* Y, int64_t ldy);
   template <typename T>
   int ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info, bool fold = false,

@@ -55,6 +55,11 @@ enum OrthoPhase { kPhStart = 0, kPhBegin = 1, kPhLoop = 2, kPhOuter = 3, kPhDone
 enum { kOrthoErrZero = 1, kOrthoErrNonfinite = 2, kOrthoErrFailed = 3 };
 
 // ---- streaming kernels (k_blas.hip) -------------------------------------
+// Copies nwords 32-bit words from src (device) to dst (coherent host memory
+// mapped for the device), makes them visible to the host, then stores seq
+// to *flag (same memory).  One workgroup; nwords <= 1024.
+hipError_t post_status(const void* src, int nwords, uint32_t* dst, uint32_t* flag, uint32_t seq,
+                       hipStream_t s);
 // C (p x q) = A^T B over n rows, fp64 result; `part` needs kGramBlocks*p*q.
 hipError_t gram_f64(const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
                     int64_t n, double* part, double* C, const int* skip, hipStream_t s);

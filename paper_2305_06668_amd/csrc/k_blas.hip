@@ -1066,4 +1066,25 @@ hipError_t convert_vec_f64_to_f32(const double* in, float* out, int64_t len, hip
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// status post: the block goes to coherent host memory with vector stores,
+// every thread fences its stores at system scope, and after the barrier
+// one thread stores the sequence word the host waits for
+__global__ __launch_bounds__(256) void k_post_status(const uint32_t* __restrict__ src, int nwords,
+                                                     uint32_t* dst, uint32_t* flag, uint32_t seq) {
+  for (int i = threadIdx.x; i < nwords; i += 256) dst[i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) *reinterpret_cast<volatile uint32_t*>(flag) = seq;
+}
+
+hipError_t post_status(const void* src, int nwords, uint32_t* dst, uint32_t* flag, uint32_t seq,
+                       hipStream_t s) {
+  if (nwords < 0 || nwords > 1024 || src == nullptr || dst == nullptr || flag == nullptr)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_post_status, dim3(1), dim3(256), 0, s,
+                     reinterpret_cast<const uint32_t*>(src), nwords, dst, flag, seq);
+  return hipGetLastError();
+}
+
 }  // namespace lobpcg

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -264,6 +265,42 @@ static hipError_t fill_t(float* X, int64_t ld, int col, int id, int64_t n, uint6
 }
 
 // ortho(W; Y) (Alg. 3 around Alg. 2) on base = [Y | W] rows, ld.
+int lobpcg_ctx::readback(const void* src, size_t bytes, const void** out) {
+  if (bytes > kPostBytes || bytes % 4 != 0) return fail(LOBPCG_ERR_INVALID_ARG, "read-back size");
+  if (post == nullptr) {
+    HIPCHK(hipMemcpyAsync(pinned, src, bytes, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    *out = pinned;
+    return LOBPCG_OK;
+  }
+  // a kernel copies the block into coherent host memory and then raises the
+  // sequence word; the host spins on that word instead of synchronising the
+  // stream (which costs a copy-engine transfer and a wake-up per read-back)
+  if (++post_seq == 0) post_seq = 1;
+  const uint32_t seq = post_seq;
+  HIPCHK(post_status(src, (int)(bytes / 4), post_dev, post_dev + kPostBytes / 4, seq, stream));
+  volatile uint32_t* flag = post + kPostBytes / 4;
+  const auto t0 = std::chrono::steady_clock::now();
+  unsigned k = 0;
+  while (*flag != seq) {
+    __builtin_ia32_pause();
+    if ((++k & 255) != 0) continue;
+    // every few microseconds: a failed stream ends the wait, a drained one
+    // must have posted (its kernels have completed)
+    const hipError_t q = hipStreamQuery(stream);
+    if (q == hipSuccess) {
+      if (*flag == seq) break;
+      return fail(LOBPCG_ERR_DEVICE, "status post missing after the stream drained");
+    }
+    if (q != hipErrorNotReady) return hip_fail(q, "stream");
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(300))
+      return fail(LOBPCG_ERR_DEVICE, "status post timed out");
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  *out = post;
+  return LOBPCG_OK;
+}
+
 template <typename T>
 int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info,
                           bool fold, double tau_run) {
@@ -271,7 +308,6 @@ int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info
   double* G = small_ptr<double>(lay.G);
   double* coef = small_ptr<double>(lay.coef);
   double* part = dptr(lay.part);
-  OrthoState* hst = reinterpret_cast<OrthoState*>(pinned);
   const int nr = ny + nw;
   const double t = (tau_run > 0.0) ? tau_run : tau;
   for (int attempt = 0; attempt < 3; ++attempt) {
@@ -283,6 +319,7 @@ int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info
     HIPCHK(gram_t(base, ld, nr, base + ny, ld, nw, n, part, G, nullptr, stream));
     int rounds = 0;
     bool finished = false;
+    OrthoState hs{};
     while (!finished) {
       const int batch = (rounds == 0) ? kOrthoRounds : 2;
       for (int r = 0; r < batch; ++r) {
@@ -290,12 +327,14 @@ int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info
         HIPCHK(ortho_apply_t(base, ld, ny, nw, coef, st, n, part, G, stream));
       }
       rounds += batch;
-      HIPCHK(hipMemcpyAsync(hst, st, sizeof(OrthoState), hipMemcpyDeviceToHost, stream));
-      HIPCHK(hipStreamSynchronize(stream));
-      if (hst->done) finished = true;
+      const void* rbp = nullptr;
+      const int rc = readback(st, sizeof(OrthoState), &rbp);
+      if (rc) return rc;
+      std::memcpy(&hs, rbp, sizeof(OrthoState));
+      if (hs.done) finished = true;
       else if (rounds >= kOrthoHardCap) return fail(LOBPCG_ERR_ORTHO_FAILED, "ortho did not finish");
     }
-    OrthoState s = *hst;
+    const OrthoState s = hs;
     stats.ortho_grams += s.grams;
     stats.ortho_factorizations += s.factorizations;
     stats.ortho_failed += s.failed;
@@ -432,22 +471,25 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     ra.part = part;
     ra.resnorm2 = resn2;
     HIPCHK(rotate_t(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
-    // one read-back: resn2 at h[0], theta at h[64], info at h[192], flags at h[224]
-    HIPCHK(hipMemcpyAsync(h, resn2, kReadbackBytes, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    const int* hinfo = reinterpret_cast<const int*>(h + 192);
+    // one read-back: resn2 at hb[0], theta at hb[64], info at hb[192], flags
+    // at hb[224]
+    const void* rbp = nullptr;
+    rc = readback(resn2, kReadbackBytes, &rbp);
+    if (rc) return rc;
+    const double* hb = static_cast<const double*>(rbp);
+    const int* hinfo = reinterpret_cast<const int*>(hb + 192);
     if (hinfo[1] != 0) return fail(LOBPCG_ERR_ORTHO_FAILED, "R^p orthonormalisation of u_p failed");
     stats.rr_eig_fallbacks += hinfo[11];
     double rmax = 0.0;
     for (int j = 0; j < m; ++j) {
-      rnorm[j] = std::sqrt(h[j]);
-      th_rr[j] = h[64 + j];
+      rnorm[j] = std::sqrt(hb[j]);
+      th_rr[j] = hb[64 + j];
       if (!std::isfinite(rnorm[j]) || !std::isfinite(th_rr[j]))
         return fail(LOBPCG_ERR_NONFINITE, "non-finite Ritz value or residual");
       rmax = std::max(rmax, rnorm[j]);
     }
     if (learned) {
-      const int* hfl = reinterpret_cast<const int*>(h + 224);
+      const int* hfl = reinterpret_cast<const int*>(hb + 224);
       for (int j = 0; j < prev_nact; ++j)
         if (hfl[j]) {
           stats.learned_nonfinite++;
@@ -653,6 +695,21 @@ int lobpcg_create(int64_t n, int device, lobpcg_t* out) {
     delete h;
     return LOBPCG_ERR_DEVICE;
   }
+  // coherent host memory for the status posts; without it the status
+  // read-backs take the copy + stream synchronisation path
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->post), kPostBytes + 256, hipHostMallocCoherent) ==
+      hipSuccess) {
+    if (hipHostGetDevicePointer(reinterpret_cast<void**>(&h->post_dev), h->post, 0) != hipSuccess) {
+      (void)hipHostFree(h->post);
+      h->post = nullptr;
+      h->post_dev = nullptr;
+    } else {
+      h->post[kPostBytes / 4] = 0;
+    }
+  } else {
+    h->post = nullptr;
+    (void)hipGetLastError();
+  }
   *out = h;
   return LOBPCG_OK;
 }
@@ -661,6 +718,7 @@ int lobpcg_destroy(lobpcg_t h) {
   if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
   hipSetDevice(h->device);
   if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->post) (void)hipHostFree(h->post);
   if (h->lweights) (void)hipFree(h->lweights);
   delete h;
   return LOBPCG_OK;
