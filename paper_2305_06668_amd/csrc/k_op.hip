@@ -68,13 +68,15 @@ __global__ __launch_bounds__(256) void k_dense(const T* __restrict__ A, int64_t 
 // and the ncols x R sums are reduced across the wave once at the end, one
 // output value per lane.  Fewer rows per wave re-read W more often (4 rows:
 // half the rate); splitting a row group's columns over 2 or 4 waves, with a
-// reduction through LDS, ran 30-45 % slower.
+// reduction through LDS, ran 30-45 % slower.  Walking A by column strips
+// instead (A symmetric, Y = A^T W, lanes owning output rows, W rows shared
+// through LDS) ran at 0.3 TB/s: every step moves to another row of A.
 template <typename T>
 struct alignas(16) DVec {
   T v[16 / sizeof(T)];
 };
 
-template <typename T, int R, int MC>
+template <typename T, int R, int MC, bool FULLW>
 __global__ __launch_bounds__(256) void k_dense_vec(const T* __restrict__ A, int64_t lda,
                                                    const T* __restrict__ W, int64_t ldw,
                                                    T* __restrict__ Y, int64_t ldy, int ncols,
@@ -103,11 +105,22 @@ __global__ __launch_bounds__(256) void k_dense_vec(const T* __restrict__ A, int6
     V a[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = *reinterpret_cast<const V*>(arow[r] + c);
+    // W rows as 16-byte vectors; a vector that would reach past column
+    // ncols (the block may be a column slice of a wider buffer) is read value
+    // by value
     V w[VE][WV];
 #pragma unroll
     for (int e = 0; e < VE; ++e)
 #pragma unroll
-      for (int q = 0; q < WV; ++q) w[e][q] = *reinterpret_cast<const V*>(W + (c + e) * ldw + q * VE);
+      for (int q = 0; q < WV; ++q) {
+        const T* src = W + (c + e) * ldw + q * VE;
+        if (FULLW || (q + 1) * VE <= ncols) {
+          w[e][q] = *reinterpret_cast<const V*>(src);
+        } else {
+#pragma unroll
+          for (int u = 0; u < VE; ++u) w[e][q].v[u] = (q * VE + u < ncols) ? src[u] : T(0);
+        }
+      }
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -154,16 +167,19 @@ static hipError_t dense_any(const T* A, int64_t lda, const T* W, int64_t ldw, T*
     const int gridv = cdiv(cdiv(n, RV), 4);
     for (int c0 = 0; c0 < ncols; c0 += 8) {
       const int nc = std::min(8, ncols - c0);
-      // W rows are read as whole vectors of MC values: the block must hold
-      // them (ld >= c0 + MC) and stay aligned at the column offset c0
-      if (nc <= 4 && ldw >= c0 + 4)
-        hipLaunchKernelGGL((k_dense_vec<T, RV, 4>), dim3(gridv), dim3(256), 0, s, A, lda,
+      // W + c0 stays 16-byte aligned (c0 is a multiple of 8); only the block's
+      // nc columns of each W row are read
+      if (nc == 8)
+        hipLaunchKernelGGL((k_dense_vec<T, RV, 8, true>), dim3(gridv), dim3(256), 0, s, A, lda,
                            W + c0, ldw, Y + c0, ldy, nc, n);
-      else if (ldw >= c0 + 8)
-        hipLaunchKernelGGL((k_dense_vec<T, RV, 8>), dim3(gridv), dim3(256), 0, s, A, lda,
+      else if (nc == 4)
+        hipLaunchKernelGGL((k_dense_vec<T, RV, 4, true>), dim3(gridv), dim3(256), 0, s, A, lda,
+                           W + c0, ldw, Y + c0, ldy, nc, n);
+      else if (nc < 4)
+        hipLaunchKernelGGL((k_dense_vec<T, RV, 4, false>), dim3(gridv), dim3(256), 0, s, A, lda,
                            W + c0, ldw, Y + c0, ldy, nc, n);
       else
-        hipLaunchKernelGGL((k_dense<T, 4, 8>), dim3(cdiv(cdiv(n, 4), 4)), dim3(256), 0, s, A, lda,
+        hipLaunchKernelGGL((k_dense_vec<T, RV, 8, false>), dim3(gridv), dim3(256), 0, s, A, lda,
                            W + c0, ldw, Y + c0, ldy, nc, n);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;

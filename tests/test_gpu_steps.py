@@ -340,3 +340,21 @@ def test_rotate_definition(P, precond):
     assert np.all(np.abs(avo[:, :q] - AXn) <= 1e-13 * (np.abs(AV) @ np.abs(U)))
     assert np.allclose(vo[:, q:q + m - a0], Wt, rtol=1e-12, atol=1e-12 * np.abs(Wt).max())
     assert np.allclose(host(r2), (R ** 2).sum(0), rtol=1e-12)
+
+
+def test_apply_dense_column_slice_at_buffer_end(P):
+    # W is columns 2..6 of an (n, 8) buffer (16-byte aligned, vector path):
+    # the operator must read no W column past the block's own (those of the
+    # last row would lie past the buffer's end)
+    n, ld, off, m = 1030, 8, 2, 5
+    A = synth.dense_dd(n, seed=11)
+    Wb = synth.start_block(n, ld, 4)
+    s = P.Solver(n)
+    s.set_operator_dense(cu(A))
+    s.ensure_workspace(1)
+    Wd = cu(Wb)
+    Y = torch.zeros((n, m), dtype=torch.float64, device="cuda")
+    P.lobpcg_apply_operator(s.h, Wd[:, off : off + m], Y)
+    ref = A @ Wb[:, off : off + m]
+    scale = np.abs(A) @ np.abs(Wb[:, off : off + m])
+    assert np.all(np.abs(host(Y) - ref) <= 1e-13 * scale)
