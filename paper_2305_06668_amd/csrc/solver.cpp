@@ -401,7 +401,8 @@ static int leading_converged(const std::vector<double>& r, double tol) {
 // (reading of the mixed-precision extension): no locking, ortho threshold
 // 1e-6, and the phase ends when every residual is within 100 fp32 roundoffs
 // of ||A|| or has stalled (no 10% decrease over 3 iterations).  The fp64
-// phase ends on the true-residual check (reading R9) or max_iter.
+// phase ends on the true-residual check (every sought column's ||A x -
+// theta x|| <= tol, recomputed from an explicit product A X) or max_iter.
 template <typename T>
 int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool low, int& iter,
                           PhaseOut& out) {
@@ -516,7 +517,8 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     }
     const int newc = std::max(m_conv, leading_converged(rnorm, lock_tol));
     if (!low && newc >= k) {
-      // reading R9: judge with an explicit product A X
+      // convergence is confirmed on an explicit product A X, not the
+      // recurrence's residuals
       // the implicit-P recurrence lets X's orthonormality drift by rounding
       // (about 1e-12 after hundreds of iterations): re-orthonormalise X
       // (Alg. 2) before the explicit product that judges it
