@@ -71,6 +71,9 @@ __global__ __launch_bounds__(256) void k_dense(const T* __restrict__ A, int64_t 
 // reduction through LDS, ran 30-45 % slower.  Walking A by column strips
 // instead (A symmetric, Y = A^T W, lanes owning output rows, W rows shared
 // through LDS) ran at 0.3 TB/s: every step moves to another row of A.
+// Sharing each chunk of W rows among a workgroup's 4 waves through LDS
+// (double-buffered, one barrier per 512 columns) ran 15 % slower: the W
+// re-reads from L2 are not what bounds this kernel.
 template <typename T>
 struct alignas(16) DVec {
   T v[16 / sizeof(T)];
