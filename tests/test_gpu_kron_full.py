@@ -14,7 +14,8 @@ size, so the check is twofold:
   within 1e-12 of the sum of absolute values, which a missing, repeated or
   misplaced tile breaks (the bound sums |A| |W| over every output).
 Both a compact block (ld = 8) and a strided one (ld = 24, 7 columns, the
-solver's [X P W] buffer after a lock) are checked.
+solver's [X P W] buffer after a lock) are checked, and the same checks run
+at na = 256 (8 x 8 whole tiles of 32) and na = 264 (9 x 9 tiles, ragged).
 """
 import time
 
@@ -37,18 +38,31 @@ def P():
     return P
 
 
-@pytest.fixture(scope="module")
-def problem():
-    na = 4096
+def make_problem(na):
     A, V = synth.kronsum(na=na, seed=synth.SEEDS["kronsum"][0])
     W = synth.start_block(na * na, 8, synth.SEEDS["kronsum"][1])
     return na, A, V, W
 
 
+@pytest.fixture(scope="module")
+def problem():
+    return make_problem(4096)
+
+
 @pytest.mark.parametrize("ldw,off,m", [(8, 0, 8), (24, 16, 7)])
 def test_kronsum_full_size(P, problem, ldw, off, m):
+    check_kronsum(P, problem, ldw, off, m)
+
+
+@pytest.mark.parametrize("na", [256, 264])
+def test_kronsum_tile_orders(P, na):
+    # 8 x 8 whole tiles and 9 x 9 tiles with a ragged edge
+    check_kronsum(P, make_problem(na), 8, 0, 8)
+
+
+def check_kronsum(P, problem, ldw, off, m):
     na, A, V, Wh = problem
-    print(f"kron full na={na} ldw={ldw} off={off} m={m}", flush=True)
+    print(f"kron na={na} ldw={ldw} off={off} m={m}", flush=True)
     n = na * na
     dev = "cuda"
     s = P.Solver(n)
@@ -74,6 +88,8 @@ def test_kronsum_full_size(P, problem, ldw, off, m):
     # edges of the 32 x 32 tiles and of the operator
     ii[:4] = [0, 31, 32, na - 1]
     jj[:4] = [na - 1, 32, 31, 0]
+    ii = np.minimum(ii, na - 1)
+    jj = np.minimum(jj, na - 1)
     rows = torch.from_numpy(ii * na + jj).to(dev)
     Ys = Y.index_select(0, rows).cpu().numpy()
     for t in range(len(ii)):
