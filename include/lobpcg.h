@@ -24,7 +24,8 @@
  *    lobpcg_gram, ...) are asynchronous unless stated otherwise.
  *  - Device scratch comes from a caller-provided workspace
  *    (lobpcg_workspace_size / lobpcg_set_workspace); the library itself only
- *    allocates a few KB of pinned host memory for read-backs.
+ *    allocates a few KB of pinned host memory for read-backs and, once learned
+ *    weights are set, a 68 KB device copy of them.
  *  - A handle is not thread-safe; distinct handles are independent.
  */
 #ifndef LOBPCG_MI355X_H
@@ -48,7 +49,7 @@ typedef struct lobpcg_ctx* lobpcg_t;
 #define LOBPCG_ERR_WORKSPACE -4    /* no workspace, or smaller than lobpcg_workspace_size */
 #define LOBPCG_ERR_ORTHO_FAILED -5 /* shifted Cholesky and SVQB both failed */
 #define LOBPCG_ERR_NONFINITE -6    /* NaN or Inf met in residuals or overlaps */
-#define LOBPCG_ERR_UNSUPPORTED -7  /* size or mode outside what this build implements */
+#define LOBPCG_ERR_UNSUPPORTED -7  /* size or mode outside what the library implements */
 
 /* ---- preconditioners (Sec. 2, T in w = T r) ---------------------------- */
 #define LOBPCG_PRECOND_NONE 0        /* T = I */
@@ -130,7 +131,7 @@ int lobpcg_set_option(lobpcg_t h, int key, double value);
 /* Bytes of device workspace needed for a block of `block` columns under the
  * current options and operator (call after the operator is set).  The block
  * is the RR block m (Sec. 2: m >= number of pairs sought); 1 <= block <= 32
- * and 3 * block <= n in this build. */
+ * and 3 * block <= n. */
 int lobpcg_workspace_size(lobpcg_t h, int block, size_t* bytes);
 /* Hand over a device buffer of `bytes` bytes (256-byte aligned) used for all
  * blocks and partial results.  Borrowed, not freed by the library. */

@@ -553,14 +553,20 @@ class Solver:
     def set_operator_csr(self, row_ptr, col, val):
         self._keep["op"] = (row_ptr, col, val)
         lobpcg_set_operator_csr(self.h, row_ptr, col, val)
+        if self._block is not None:
+            self.ensure_workspace(self._block)  # the workspace depends on the operator
 
     def set_operator_dense(self, A):
         self._keep["op"] = (A,)
         lobpcg_set_operator_dense(self.h, A)
+        if self._block is not None:
+            self.ensure_workspace(self._block)  # the workspace depends on the operator
 
     def set_operator_kronsum(self, A, V):
         self._keep["op"] = (A, V)
         lobpcg_set_operator_kronsum(self.h, A, V)
+        if self._block is not None:
+            self.ensure_workspace(self._block)  # the workspace depends on the operator
 
     def set_preconditioner(self, kind=PRECOND_DIAG, diag=None):
         self._keep["diag"] = diag

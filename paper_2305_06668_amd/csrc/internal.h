@@ -131,10 +131,14 @@ hipError_t dense_apply_f64(const double* A, int64_t lda, const double* W, int64_
                            int64_t ldy, int ncols, int64_t n, hipStream_t s);
 hipError_t dense_apply_f32(const float* A, int64_t lda, const float* W, int64_t ldw, float* Y,
                            int64_t ldy, int ncols, int64_t n, hipStream_t s);
+// pack (optional, na^2 x 8 values): scratch for a compact copy of W when W
+// is not a compact 8-column block
 hipError_t kronsum_apply_f64(const double* A, const double* Vp, int64_t na, const double* W,
-                             int64_t ldw, double* Y, int64_t ldy, int ncols, hipStream_t s);
+                             int64_t ldw, double* Y, int64_t ldy, int ncols, double* pack,
+                             hipStream_t s);
 hipError_t kronsum_apply_f32(const float* A, const float* Vp, int64_t na, const float* W,
-                             int64_t ldw, float* Y, int64_t ldy, int ncols, hipStream_t s);
+                             int64_t ldw, float* Y, int64_t ldy, int ncols, float* pack,
+                             hipStream_t s);
 // Sets bits of *bad (device int, zeroed by the caller) on a malformed CSR.
 hipError_t csr_check(const int32_t* rp, const int32_t* ci, int64_t n, int64_t nnz, int* bad,
                      hipStream_t s);

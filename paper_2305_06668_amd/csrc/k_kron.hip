@@ -97,6 +97,8 @@ template <typename T, bool VEC>
 struct KronStage {
   Pair<T> xk[kPXK], xi[kPXI], ai, aj;
 
+  // nc: the columns of W that may be read (a zero-padded packed block
+  // allows all 8)
   __device__ __forceinline__ void load(const T* __restrict__ A, const T* __restrict__ W,
                                        int64_t na, int64_t ldw, int nc, int64_t i0, int64_t j0,
                                        int b0, int64_t k0, int t) {
@@ -164,7 +166,8 @@ template <typename T, bool VEC>
 __global__ __launch_bounds__(256, 2) void k_kron_mfma(const T* __restrict__ A,
                                                       const T* __restrict__ Vp, int64_t na,
                                                       const T* __restrict__ W, int64_t ldw,
-                                                      T* __restrict__ Y, int64_t ldy, int nc) {
+                                                      T* __restrict__ Y, int64_t ldy, int nc,
+                                                      int ncl) {
   typedef typename KAcc<T>::type AccT;
   __shared__ KronSmem<T> sm;
   const int t = threadIdx.x;
@@ -182,13 +185,13 @@ __global__ __launch_bounds__(256, 2) void k_kron_mfma(const T* __restrict__ A,
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[bw][si][sj][e] = T(0);
   KronStage<T, VEC> st;
-  st.load(A, W, na, ldw, nc, i0, j0, b0, 0, t);
+  st.load(A, W, na, ldw, ncl, i0, j0, b0, 0, t);
   st.store(sm, t);
   __syncthreads();
   for (int64_t k0 = 0; k0 < na; k0 += kKC) {
     // the next chunk's loads are in flight while this chunk's MFMAs run
     const bool more = k0 + kKC < na;
-    if (more) st.load(A, W, na, ldw, nc, i0, j0, b0, k0 + kKC, t);
+    if (more) st.load(A, W, na, ldw, ncl, i0, j0, b0, k0 + kKC, t);
     // k steps not unrolled: 228 registers (all four unrolled hold 256 and
     // spill, two unrolled run 2 % slower)
 #pragma unroll 1
@@ -256,29 +259,71 @@ __global__ __launch_bounds__(256, 2) void k_kron_mfma(const T* __restrict__ A,
 
 }  // namespace
 
+// packs columns [0, nc) of W (n rows, leading dimension ldw) into out
+// (n x 8, zero-padded): the MFMA kernel then reads whole 64-byte rows
 template <typename T>
-static hipError_t kron_any(const T* A, const T* Vp, int64_t na, const T* W, int64_t ldw, T* Y,
-                           int64_t ldy, int nc, hipStream_t s) {
-  if (na < 1 || nc < 1) return hipErrorInvalidValue;
+__global__ __launch_bounds__(256) void k_kron_pack8(const T* __restrict__ W, int64_t ldw, int nc,
+                                                    int64_t n, T* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    Pair<T> v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q].x = (2 * q < nc) ? W[i * ldw + 2 * q] : T(0);
+      v[q].y = (2 * q + 1 < nc) ? W[i * ldw + 2 * q + 1] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) reinterpret_cast<Pair<T>*>(out + i * 8)[q] = v[q];
+  }
+}
+
+template <typename T>
+static hipError_t kron_launch(const T* A, const T* Vp, int64_t na, const T* W, int64_t ldw, T* Y,
+                              int64_t ldy, int nc, int ncl, hipStream_t s) {
   const dim3 grid((unsigned)((na + kTJ - 1) / kTJ), (unsigned)((na + kTI - 1) / kTI),
                   (unsigned)((nc + kBB - 1) / kBB));
   const bool vec = (ldw % 2 == 0) && (na % 2 == 0) &&
                    (reinterpret_cast<uintptr_t>(W) % (2 * sizeof(T)) == 0) &&
                    (reinterpret_cast<uintptr_t>(A) % (2 * sizeof(T)) == 0);
   if (vec)
-    hipLaunchKernelGGL((k_kron_mfma<T, true>), grid, dim3(256), 0, s, A, Vp, na, W, ldw, Y, ldy, nc);
+    hipLaunchKernelGGL((k_kron_mfma<T, true>), grid, dim3(256), 0, s, A, Vp, na, W, ldw, Y, ldy, nc,
+                       ncl);
   else
-    hipLaunchKernelGGL((k_kron_mfma<T, false>), grid, dim3(256), 0, s, A, Vp, na, W, ldw, Y, ldy, nc);
+    hipLaunchKernelGGL((k_kron_mfma<T, false>), grid, dim3(256), 0, s, A, Vp, na, W, ldw, Y, ldy,
+                       nc, ncl);
   return hipGetLastError();
 }
 
+// A block that is not already a compact 8-column one is packed first (per
+// 8 columns) into `pack` (na^2 x 8, optional): strided rows cost the MFMA
+// kernel half again its time (na = 4096: 64 ms at ld 24 against 43 ms).
+template <typename T>
+static hipError_t kron_any(const T* A, const T* Vp, int64_t na, const T* W, int64_t ldw, T* Y,
+                           int64_t ldy, int nc, T* pack, hipStream_t s) {
+  if (na < 1 || nc < 1) return hipErrorInvalidValue;
+  const bool compact = ldw == 8 && nc == 8 && reinterpret_cast<uintptr_t>(W) % 16 == 0;
+  if (pack == nullptr || compact) return kron_launch<T>(A, Vp, na, W, ldw, Y, ldy, nc, nc, s);
+  const int64_t n = na * na;
+  const int pgrid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  for (int c0 = 0; c0 < nc; c0 += 8) {
+    const int m = std::min(8, nc - c0);
+    hipLaunchKernelGGL((k_kron_pack8<T>), dim3(pgrid), dim3(256), 0, s, W + c0, ldw, m, n, pack);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = kron_launch<T>(A, Vp, na, pack, 8, Y + c0, ldy, m, 8, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t kronsum_apply_f64(const double* A, const double* Vp, int64_t na, const double* W,
-                             int64_t ldw, double* Y, int64_t ldy, int ncols, hipStream_t s) {
-  return kron_any<double>(A, Vp, na, W, ldw, Y, ldy, ncols, s);
+                             int64_t ldw, double* Y, int64_t ldy, int ncols, double* pack,
+                             hipStream_t s) {
+  return kron_any<double>(A, Vp, na, W, ldw, Y, ldy, ncols, pack, s);
 }
 hipError_t kronsum_apply_f32(const float* A, const float* Vp, int64_t na, const float* W,
-                             int64_t ldw, float* Y, int64_t ldy, int ncols, hipStream_t s) {
-  return kron_any<float>(A, Vp, na, W, ldw, Y, ldy, ncols, s);
+                             int64_t ldw, float* Y, int64_t ldy, int ncols, float* pack,
+                             hipStream_t s) {
+  return kron_any<float>(A, Vp, na, W, ldw, Y, ldy, ncols, pack, s);
 }
 
 }  // namespace lobpcg

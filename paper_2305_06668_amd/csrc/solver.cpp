@@ -50,6 +50,7 @@ Layout lobpcg_ctx::plan(int m) const {
   L.diag = take((size_t)n * sizeof(double));
   L.rho = take((size_t)n * sizeof(double));
   L.ltiles = take((size_t)ltiles_cap() * sizeof(int));
+  if (op == kOpKron) L.kpack = take((size_t)n * 8 * sizeof(double));
   const size_t gblk = (size_t)std::min<int64_t>(kGramBlocks, (n + 63) / 64) + 1;
   const size_t part =
       std::max({gblk * kGramMaxCols * kGramMaxCols, (size_t)kStreamBlocks * 3 * 64,
@@ -113,7 +114,11 @@ int lobpcg_ctx::apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_
   switch (op) {
     case kOpCsr: e = spmm_csr_f64(rp, ci, val, W, ldw, Y, ldy, nc, n, stream); break;
     case kOpDense: e = dense_apply_f64(A, lda, W, ldw, Y, ldy, nc, n, stream); break;
-    case kOpKron: e = kronsum_apply_f64(A, Vpot, na, W, ldw, Y, ldy, nc, stream); break;
+    case kOpKron:
+      e = kronsum_apply_f64(A, Vpot, na, W, ldw, Y, ldy, nc,
+                            (ws && lay_block > 0 && lay.kpack) ? dptr(lay.kpack) : nullptr,
+                            stream);
+      break;
     default: return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
   }
   if (e != hipSuccess) return hip_fail(e, "operator");
@@ -129,7 +134,9 @@ int lobpcg_ctx::apply_op(const float* W, int64_t ldw, int nc, float* Y, int64_t 
     case kOpCsr: e = spmm_csr_f32(rp, ci, o32, W, ldw, Y, ldy, nc, n, stream); break;
     case kOpDense: e = dense_apply_f32(o32, n, W, ldw, Y, ldy, nc, n, stream); break;
     case kOpKron:
-      e = kronsum_apply_f32(o32, o32 + na * na, na, W, ldw, Y, ldy, nc, stream);
+      e = kronsum_apply_f32(o32, o32 + na * na, na, W, ldw, Y, ldy, nc,
+                            lay.kpack ? reinterpret_cast<float*>(dptr(lay.kpack)) : nullptr,
+                            stream);
       break;
     default: return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
   }
@@ -950,6 +957,13 @@ int lobpcg_apply_operator(lobpcg_t h, const double* W, int64_t ldw, int ncols, d
   GUARD(h);
   if (W == nullptr || Y == nullptr || ncols < 1 || ncols > 64 || ldw < ncols || ldy < ncols)
     return h->fail(LOBPCG_ERR_INVALID_ARG, "bad apply arguments");
+  // with a workspace, plan its layout so that the operator can use its
+  // scratch (the Kronecker operator packs strided blocks there); without
+  // one, or if it is too small, the operator runs without scratch
+  if (h->ws != nullptr) {
+    const int m = h->lay_block > 0 ? h->lay_block : (h->block > 0 ? h->block : 1);
+    if (h->ensure_layout(m) != LOBPCG_OK) h->err.clear();
+  }
   return h->apply_op(W, ldw, ncols, Y, ldy);
 }
 
