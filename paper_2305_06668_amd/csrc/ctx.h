@@ -28,7 +28,7 @@ enum OpKind { kOpNone = 0, kOpCsr = 1, kOpDense = 2, kOpKron = 3 };
 
 struct Layout {
   size_t V[2], AV[2], diag, rho, ltiles, part, small, total;
-  size_t kpack = 0;  // Kronecker operator: n x 8 packed copy of a W block
+  size_t kpack = 0;  // dense / Kronecker operator: n x 8 packed copy of a W block
   size_t V32[2], AV32[2], op32;  // mixed precision only (0 otherwise)
   // inside small (byte offsets)
   size_t a, rb, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye, lflags, lscale;

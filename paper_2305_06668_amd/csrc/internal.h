@@ -127,10 +127,16 @@ hipError_t spmm_csr_f64(const int32_t* rp, const int32_t* ci, const double* val,
                         int64_t ldw, double* Y, int64_t ldy, int ncols, int64_t n, hipStream_t s);
 hipError_t spmm_csr_f32(const int32_t* rp, const int32_t* ci, const float* val, const float* W,
                         int64_t ldw, float* Y, int64_t ldy, int ncols, int64_t n, hipStream_t s);
+// pack (optional, n x 8 values): scratch for a compact copy of W when W is
+// not a compact 8-column block
 hipError_t dense_apply_f64(const double* A, int64_t lda, const double* W, int64_t ldw, double* Y,
-                           int64_t ldy, int ncols, int64_t n, hipStream_t s);
+                           int64_t ldy, int ncols, int64_t n, double* pack, hipStream_t s);
 hipError_t dense_apply_f32(const float* A, int64_t lda, const float* W, int64_t ldw, float* Y,
-                           int64_t ldy, int ncols, int64_t n, hipStream_t s);
+                           int64_t ldy, int ncols, int64_t n, float* pack, hipStream_t s);
+// out (n x 8) = columns [0, nc) of W (n rows, leading dimension ldw), zero
+// padded to 8: the operators' compact copy of a strided or partial block
+hipError_t pack8_f64(const double* W, int64_t ldw, int nc, int64_t n, double* out, hipStream_t s);
+hipError_t pack8_f32(const float* W, int64_t ldw, int nc, int64_t n, float* out, hipStream_t s);
 // pack (optional, na^2 x 8 values): scratch for a compact copy of W when W
 // is not a compact 8-column block
 hipError_t kronsum_apply_f64(const double* A, const double* Vp, int64_t na, const double* W,

@@ -315,6 +315,20 @@ static hipError_t kron_any(const T* A, const T* Vp, int64_t na, const T* W, int6
   return hipSuccess;
 }
 
+template <typename T>
+static hipError_t pack8_any(const T* W, int64_t ldw, int nc, int64_t n, T* out, hipStream_t s) {
+  if (n < 1 || nc < 1 || nc > 8 || W == nullptr || out == nullptr) return hipErrorInvalidValue;
+  const int pgrid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_kron_pack8<T>), dim3(pgrid), dim3(256), 0, s, W, ldw, nc, n, out);
+  return hipGetLastError();
+}
+hipError_t pack8_f64(const double* W, int64_t ldw, int nc, int64_t n, double* out, hipStream_t s) {
+  return pack8_any<double>(W, ldw, nc, n, out, s);
+}
+hipError_t pack8_f32(const float* W, int64_t ldw, int nc, int64_t n, float* out, hipStream_t s) {
+  return pack8_any<float>(W, ldw, nc, n, out, s);
+}
+
 hipError_t kronsum_apply_f64(const double* A, const double* Vp, int64_t na, const double* W,
                              int64_t ldw, double* Y, int64_t ldy, int ncols, double* pack,
                              hipStream_t s) {

@@ -159,9 +159,31 @@ __global__ __launch_bounds__(256) void k_dense_vec(const T* __restrict__ A, int6
 
 template <typename T>
 static hipError_t dense_any(const T* A, int64_t lda, const T* W, int64_t ldw, T* Y, int64_t ldy,
-                            int ncols, int64_t n, hipStream_t s) {
+                            int ncols, int64_t n, T* pack, hipStream_t s) {
   if (n < 1 || ncols < 1) return hipErrorInvalidValue;
   constexpr int VE = 16 / sizeof(T);
+  // a block that is not a compact 8-column one is packed (8 columns at a
+  // time, zero-padded) into `pack` first: strided rows and partial widths
+  // cost the vector kernel 25-70 % (n = 2e4: 904 / 1271 us at ld 24 with 8
+  // and 7 columns, against 737 us compact)
+  if (pack != nullptr && lda % VE == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+      !(ldw == 8 && ncols == 8 && reinterpret_cast<uintptr_t>(W) % 16 == 0)) {
+    const int gridv = cdiv(cdiv(n, 8), 4);
+    for (int c0 = 0; c0 < ncols; c0 += 8) {
+      const int nc = std::min(8, ncols - c0);
+      hipError_t e = (sizeof(T) == 8)
+                         ? pack8_f64(reinterpret_cast<const double*>(W + c0), ldw, nc, n,
+                                     reinterpret_cast<double*>(pack), s)
+                         : pack8_f32(reinterpret_cast<const float*>(W + c0), ldw, nc, n,
+                                     reinterpret_cast<float*>(pack), s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_dense_vec<T, 8, 8, true>), dim3(gridv), dim3(256), 0, s, A, lda, pack,
+                         (int64_t)8, Y + c0, ldy, nc, n);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const bool vec = lda % VE == 0 && ldw % VE == 0 &&
                    reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
                    reinterpret_cast<uintptr_t>(W) % 16 == 0;
@@ -207,12 +229,12 @@ static hipError_t dense_any(const T* A, int64_t lda, const T* W, int64_t ldw, T*
 }
 
 hipError_t dense_apply_f64(const double* A, int64_t lda, const double* W, int64_t ldw, double* Y,
-                           int64_t ldy, int ncols, int64_t n, hipStream_t s) {
-  return dense_any<double>(A, lda, W, ldw, Y, ldy, ncols, n, s);
+                           int64_t ldy, int ncols, int64_t n, double* pack, hipStream_t s) {
+  return dense_any<double>(A, lda, W, ldw, Y, ldy, ncols, n, pack, s);
 }
 hipError_t dense_apply_f32(const float* A, int64_t lda, const float* W, int64_t ldw, float* Y,
-                           int64_t ldy, int ncols, int64_t n, hipStream_t s) {
-  return dense_any<float>(A, lda, W, ldw, Y, ldy, ncols, n, s);
+                           int64_t ldy, int ncols, int64_t n, float* pack, hipStream_t s) {
+  return dense_any<float>(A, lda, W, ldw, Y, ldy, ncols, n, pack, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -50,7 +50,7 @@ Layout lobpcg_ctx::plan(int m) const {
   L.diag = take((size_t)n * sizeof(double));
   L.rho = take((size_t)n * sizeof(double));
   L.ltiles = take((size_t)ltiles_cap() * sizeof(int));
-  if (op == kOpKron) L.kpack = take((size_t)n * 8 * sizeof(double));
+  if (op == kOpKron || op == kOpDense) L.kpack = take((size_t)n * 8 * sizeof(double));
   const size_t gblk = (size_t)std::min<int64_t>(kGramBlocks, (n + 63) / 64) + 1;
   const size_t part =
       std::max({gblk * kGramMaxCols * kGramMaxCols, (size_t)kStreamBlocks * 3 * 64,
@@ -113,7 +113,10 @@ int lobpcg_ctx::apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_
   hipError_t e = hipSuccess;
   switch (op) {
     case kOpCsr: e = spmm_csr_f64(rp, ci, val, W, ldw, Y, ldy, nc, n, stream); break;
-    case kOpDense: e = dense_apply_f64(A, lda, W, ldw, Y, ldy, nc, n, stream); break;
+    case kOpDense:
+      e = dense_apply_f64(A, lda, W, ldw, Y, ldy, nc, n,
+                          (ws && lay_block > 0 && lay.kpack) ? dptr(lay.kpack) : nullptr, stream);
+      break;
     case kOpKron:
       e = kronsum_apply_f64(A, Vpot, na, W, ldw, Y, ldy, nc,
                             (ws && lay_block > 0 && lay.kpack) ? dptr(lay.kpack) : nullptr,
@@ -132,7 +135,10 @@ int lobpcg_ctx::apply_op(const float* W, int64_t ldw, int nc, float* Y, int64_t 
   hipError_t e = hipSuccess;
   switch (op) {
     case kOpCsr: e = spmm_csr_f32(rp, ci, o32, W, ldw, Y, ldy, nc, n, stream); break;
-    case kOpDense: e = dense_apply_f32(o32, n, W, ldw, Y, ldy, nc, n, stream); break;
+    case kOpDense:
+      e = dense_apply_f32(o32, n, W, ldw, Y, ldy, nc, n,
+                          lay.kpack ? reinterpret_cast<float*>(dptr(lay.kpack)) : nullptr, stream);
+      break;
     case kOpKron:
       e = kronsum_apply_f32(o32, o32 + na * na, na, W, ldw, Y, ldy, nc,
                             lay.kpack ? reinterpret_cast<float*>(dptr(lay.kpack)) : nullptr,
