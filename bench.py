@@ -122,6 +122,16 @@ def kron_only(P, synth, torch, dev, na=4096, m=8, reps=5):
     tf = flops / (ms * 1e-3) / 1e12
     log(f"kron: na={na} m={m}: {ms:.2f} ms per apply, {flops / 1e12:.2f} TFLOP, {tf:.1f} TFLOP/s fp64 "
         f"({100 * tf / 78.6:.0f} % of the 78.6 TFLOP/s fp64 matrix peak)")
+    # six iterations of a mixed-precision solve (untimed): its first applies
+    # run the fp32 kernel on the solver's own (packed) blocks, for a kernel
+    # trace of this command to time
+    s.set_preconditioner(P.PRECOND_DIAG)
+    s.set_initial_guess(W)
+    s.set_option(P.OPT_PRECISION, P.PREC_FP32)
+    s.set_option(P.OPT_MAX_ITER, 6)
+    r = s.solve(m, 1e-8, want_vectors=False)
+    torch.cuda.synchronize()
+    log(f"kron: mixed solve, {r.stats['iterations']} iterations (capped; fp32 operator in its trace)")
 
 
 def dense_only(P, synth, torch, dev, n=20_000, m=8, reps=20):
