@@ -95,7 +95,7 @@ def test_dense_dd_full_size(P):
     say("iters gpu", st["iterations"], "oracle", ora.iterations, st)
 
 
-@pytest.mark.parametrize("precond", [1, 2, 0])
+@pytest.mark.parametrize("precond", [1, 2])
 def test_csr_banded_scaled(P, precond):
     say("csr scaled precond", precond)
     n, k = 20000, 8
@@ -106,14 +106,26 @@ def test_csr_banded_scaled(P, precond):
         X0[np.argsort(C.diag)[:k], np.arange(k)] = 1.0
         X0 += 1e-3 * synth.start_block(n, k, 23) / np.sqrt(n)
     op = O.csr_operator(C.row_ptr, C.col, C.val, n)
-    if precond == 0:
-        pytest.skip("unpreconditioned: too many iterations for this spectrum")
     s, res = gpu_solve(P, n, lambda s: s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val)), X0, k, 1e-8, precond=precond)
     pname = {1: "diag", 2: "diag_signed"}[precond]
     ora = O.lobpcg(op, X0, k, 1e-8, diag=C.diag, precond=pname)
-    lam_all = np.sort(np.linalg.eigvalsh(C.to_dense()[:0, :0])) if False else None
     # reference eigenvalues: the oracle (checked against dense eigh in the pins)
     check_pairs(res, op, ora.evals, 1e-8, normA=11.0)
+    assert abs(res.stats["iterations"] - ora.iterations) <= max(3, 0.1 * ora.iterations)
+
+
+def test_unpreconditioned_vs_oracle(P):
+    # T = I (no preconditioner): a prescribed spectrum with the sought four
+    # well separated from the rest, so that plain LOBPCG converges quickly
+    say("unpreconditioned")
+    n, k = 200, 4
+    lam = np.concatenate([[1.0, 2.0, 3.0, 4.0], np.linspace(10.0, 20.0, n - 4)])
+    A, _ = synth.prescribed_spectrum(lam, 31)
+    X0 = synth.start_block(n, k, 32)
+    s, res = gpu_solve(P, n, lambda s: s.set_operator_dense(cu(A)), X0, k, 1e-9, precond=0)
+    op = O.dense_operator(A)
+    check_pairs(res, op, lam[:k], 1e-9, normA=20.0)
+    ora = O.lobpcg(op, X0, k, 1e-9, precond="none")
     assert abs(res.stats["iterations"] - ora.iterations) <= max(3, 0.1 * ora.iterations)
 
 
