@@ -49,10 +49,12 @@ the design notes of the repository):
       2-norm is <= tol, never decreasing; locked columns stay in X and are
       still rotated by the RR; W and P are built for the active columns only.
   R9  Convergence is the per-column residual 2-norm ||A x - theta x|| <= tol
-      with ||x|| = 1.  When the RR residuals say "converged", the residual is
-      recomputed from an explicit product A X (the true residual); if that
-      check fails, AX is replaced by the explicit product, P is dropped and
-      the iteration continues.
+      with ||x|| = 1.  When the RR residuals say "converged", X is passed
+      through ``ortho`` once more and the residual is recomputed from an
+      explicit product A X (the true residual); if that check fails, the
+      iteration restarts as Alg. 1 starts: Rayleigh-Ritz on [X] with the
+      explicit product, P dropped, locking recounted, and the next
+      convergence test only after one more iteration.
   R10 The reduced matrix is symmetrised, a <- (a + a^T) / 2, before eigh.
   R16 Eigenvectors of the reduced matrix are oriented so that the diagonal
       entry u[j, j] is >= 0 (for the X block: the new Ritz vector continues
@@ -166,9 +168,12 @@ def _potrf(M: np.ndarray) -> Optional[np.ndarray]:
     return L
 
 
-def shifted_cholesky(M: np.ndarray, stats: OrthoStats) -> Optional[np.ndarray]:
+def shifted_cholesky(
+    M: np.ndarray, stats: OrthoStats, retries: int = SHIFT_RETRIES
+) -> Optional[np.ndarray]:
     """Cholesky of M; on failure add alpha*eps*||X||_F to the diagonal and
-    increase alpha until it succeeds (Sec. 3.2, Alg. 2; reading R5).
+    increase alpha until it succeeds (Sec. 3.2, Alg. 2; reading R5), at most
+    ``retries`` shifted attempts.
 
     Returns None when every retry failed (the caller then uses SVQB)."""
     stats.factorizations += 1
@@ -179,7 +184,7 @@ def shifted_cholesky(M: np.ndarray, stats: OrthoStats) -> Optional[np.ndarray]:
     norm_x = math.sqrt(max(float(np.trace(M)), 0.0))
     alpha = SHIFT_ALPHA0
     eye = np.eye(M.shape[0])
-    for _ in range(SHIFT_RETRIES):
+    for _ in range(retries):
         sigma = alpha * EPS * norm_x
         stats.factorizations += 1
         L = _potrf(M + sigma * eye)
@@ -207,9 +212,12 @@ def ortho(
     tau: float = TAU_ORTHO,
     stats: Optional[OrthoStats] = None,
     max_passes: int = ORTHO_MAX_PASSES,
+    shift_retries: int = SHIFT_RETRIES,
 ) -> np.ndarray:
     """Alg. 2: while ||X^T X - I|| > tau, factor M = X^T X = L L^T (shifting
-    the diagonal when the factorisation fails) and set X <- X L^-T."""
+    the diagonal when the factorisation fails) and set X <- X L^-T.  When
+    the plain factorisation and all ``shift_retries`` shifted ones fail, the
+    pass uses SVQB instead (reading R5)."""
     st = stats if stats is not None else OrthoStats()
     st.ortho_calls += 1
     X = normalize_columns(X, st)
@@ -225,7 +233,7 @@ def ortho(
         if p == max_passes - 1:
             st.stalled += 1
             return X
-        L = shifted_cholesky(M, st)
+        L = shifted_cholesky(M, st, shift_retries)
         if L is None:
             X = svqb(X, M, st)
         else:
@@ -241,6 +249,7 @@ def ortho_against(
     tau: float = TAU_ORTHO,
     stats: Optional[OrthoStats] = None,
     max_passes: int = ORTHO_Y_MAX_PASSES,
+    shift_retries: int = SHIFT_RETRIES,
 ) -> np.ndarray:
     """Alg. 3 (reading R3): X <- X - Y (Y^T X); X <- ortho(X); repeat until
     ||Y^T X|| <= tau.  Y must have orthonormal columns."""
@@ -248,12 +257,12 @@ def ortho_against(
     st.against_calls += 1
     X = normalize_columns(X, st)
     if Y is None or Y.shape[1] == 0:
-        return ortho(X, tau, st)
+        return ortho(X, tau, st, shift_retries=shift_retries)
     C = Y.T @ X
     for p in range(max_passes):
         st.against_passes += 1
         X = X - Y @ C
-        X = ortho(X, tau, st)
+        X = ortho(X, tau, st, shift_retries=shift_retries)
         C = Y.T @ X
         if max_abs(C) <= tau:
             return X
@@ -397,6 +406,7 @@ class LobpcgResult:
     rms: np.ndarray  # ||r||_2 / sqrt(n), the paper's RMS measure
     maxabs: np.ndarray  # max |r_i|, the paper's second measure
     X_all: np.ndarray = None  # the whole final block
+    restarts: int = 0  # failed true-residual checks (reading R9)
     theta_all: np.ndarray = None
 
 
@@ -410,13 +420,19 @@ def lobpcg(
     tau: float = TAU_ORTHO,
     max_iter: int = 1000,
     callback: Optional[Callable[[dict], None]] = None,
+    shift_retries: int = SHIFT_RETRIES,
+    force_restarts: int = 0,
 ) -> LobpcgResult:
     """Alg. 1: the lowest k eigenpairs of the symmetric operator ``op``.
 
     X0 is the n x m initial block (m >= k, the block may hold extra vectors,
     Sec. 2).  ``precond`` is "diag" (|Jacobi|, needs ``diag``),
     "diag_signed" (the paper's signed Jacobi), "none", or a callable
-    f(R_act, theta_act, X_act) returning the preconditioned columns."""
+    f(R_act, theta_act, X_act) returning the preconditioned columns.
+    ``shift_retries`` caps the shifted Cholesky retries of every ortho call
+    (0 sends a failed factorisation straight to SVQB).  ``force_restarts``
+    is a test hook: the first that many true-residual checks count as
+    failed, which drives the restart branch of reading R9."""
     X0 = np.asarray(X0, dtype=np.float64)
     n, m = X0.shape
     if not (1 <= k <= m):
@@ -440,7 +456,7 @@ def lobpcg(
         raise ValueError(precond)
 
     # Alg. 1 initial Rayleigh-Ritz (reading R2: orthonormalise X0 first)
-    X = ortho(X0, tau, st)
+    X = ortho(X0, tau, st, shift_retries=shift_retries)
     AX = op(X)
     matvecs += m
     theta_all, U = rayleigh_ritz(X, AX)
@@ -455,25 +471,38 @@ def lobpcg(
     P = AP = None
     it = 0
     converged = False
+    restarts = 0
+    just_restarted = False
     while True:
         m_conv = max(m_conv, leading_converged(rnorm, tol))  # reading R8
-        if m_conv >= k:
-            # reading R9: judge with the true residual of an explicit product
+        if m_conv >= k and not just_restarted:
+            # reading R9: re-orthonormalise X (Alg. 2; the implicit-P
+            # recurrence lets X^T X drift from I by rounding), then judge with
+            # the true residual of an explicit product
+            X = ortho(X, tau, st, shift_retries=shift_retries)
             true_checks += 1
             th_t, r_t, AX_t = true_residuals(op, X)
             matvecs += m
-            if float(np.max(r_t[:k])) <= tol:
+            if float(np.max(r_t[:k])) <= tol and restarts >= force_restarts:
                 converged = True
                 break
-            AX = AX_t
-            theta = th_t
+            # restart: Rayleigh-Ritz on [X] with the explicit product (as at
+            # the start of Alg. 1), P dropped, locking recomputed; the next
+            # convergence test waits for one iteration
+            restarts += 1
+            theta_all, U = rayleigh_ritz(X, AX_t)
+            X = X @ U
+            AX = AX_t @ U
+            theta = theta_all[:m]
             R = ritz_residual(AX, X, theta)
             rnorm = np.linalg.norm(R, axis=0)
+            hist_theta.append(theta.copy())
+            hist_resid.append(rnorm.copy())
             m_conv = leading_converged(rnorm, tol)
             P = AP = None
-            if m_conv >= k:
-                converged = True
-                break
+            just_restarted = True
+            continue
+        just_restarted = False
         if it >= max_iter:
             break
         it += 1
@@ -481,7 +510,7 @@ def lobpcg(
         # Alg. 1: preconditioned residuals, orthogonalised against (X, P)
         Wt = tprec(R[:, act], theta[act], X[:, act])
         Y = X if P is None else np.hstack([X, P])
-        W = ortho_against(Wt, Y, tau, st)
+        W = ortho_against(Wt, Y, tau, st, shift_retries=shift_retries)
         AW = op(W)
         matvecs += W.shape[1]
         hist_active.append(W.shape[1])
@@ -513,12 +542,13 @@ def lobpcg(
             p = V.shape[1]
             up_t = ux[:, act].copy()
             up_t[act, np.arange(act.size)] -= 1.0
-            up = ortho_against(up_t, ux, tau, st)
+            up = ortho_against(up_t, ux, tau, st, shift_retries=shift_retries)
             P = V @ up
             AP = AV @ up
         X, AX = Xn, AXn
 
     if not converged:
+        X = ortho(X, tau, st, shift_retries=shift_retries)
         true_checks += 1
         th_t, r_t, AX_t = true_residuals(op, X)
     Rt = AX_t[:, :k] - X[:, :k] * th_t[:k]
@@ -538,5 +568,6 @@ def lobpcg(
         maxabs=np.max(np.abs(Rt), axis=0),
         X_all=X,
         theta_all=th_t,
+        restarts=restarts,
     )
     return res

@@ -477,11 +477,130 @@ def test_planted_unorthogonalised_p(monkeypatch):
     run_invariants(A, 4, 1)
     orig = O.ortho_against
 
-    def skip_small(X, Y, tau=O.TAU_ORTHO, stats=None, max_passes=O.ORTHO_Y_MAX_PASSES):
+    def skip_small(X, Y, tau=O.TAU_ORTHO, stats=None, max_passes=O.ORTHO_Y_MAX_PASSES, **kw):
         if Y is not None and Y.shape[0] < 100:  # the R^p call that builds u_p
             return O.normalize_columns(X)
-        return orig(X, Y, tau, stats, max_passes)
+        return orig(X, Y, tau, stats, max_passes, **kw)
 
     monkeypatch.setattr(O, "ortho_against", skip_small)
     with pytest.raises(AssertionError):
         run_invariants(A, 4, 1)
+
+
+# ---------------------------------------------------------------------------
+# SVQB, the last resort after the shifted retries (reading R5; Stathopoulos
+# and Wu's orthonormalisation from the eigen-decomposition of the overlap)
+
+
+def svqb_pin(svqb_fn):
+    """One SVQB pass on unit columns of condition 1e2 and 1e4: the columns
+    must come out orthonormal to within what a one-pass method built on the
+    overlap allows (about eps cond^2) and span the same space as the input.
+    Returns the worst error relative to that allowance."""
+    worst = 0.0
+    for cond in (1e2, 1e4):
+        Xn = O.normalize_columns(graded(600, 8, cond, 3))
+        Q = svqb_fn(Xn, Xn.T @ Xn, O.OrthoStats())
+        allow = 1e2 * O.EPS * cond**2
+        worst = max(worst, O.max_abs(Q.T @ Q - np.eye(8)) / allow)
+        assert projector_distance(Q, Xn) < 1e-12 * cond
+    return worst
+
+
+def test_svqb_one_pass():
+    assert svqb_pin(O.svqb) <= 1.0
+
+
+def test_planted_svqb_inverse_instead_of_inverse_sqrt():
+    def bad(X, M, stats):
+        s, U = np.linalg.eigh(M)
+        s = np.maximum(s, O.EPS * s.max())
+        return (X @ U) / s  # should be / sqrt(s)
+
+    assert svqb_pin(bad) > 1.0
+
+
+def test_ortho_reaches_svqb_without_shift_retries():
+    # cond ~ 1e10: the plain factorisation fails (Sec. 3.2); with no
+    # shifted retry allowed, that pass of Alg. 2 takes SVQB, and the next
+    # pass's plain Cholesky finishes the job
+    g = synth.rng(5)
+    x, y = g.standard_normal(800), g.standard_normal(800)
+    Z = g.standard_normal((800, 3))
+    st = O.OrthoStats()
+    Q = O.ortho(np.column_stack([x, x + 1e-10 * y, Z]), stats=st, shift_retries=0)
+    assert st.svqb == 1 and st.failed_factorizations == 1 and st.shifted == 0
+    assert O.max_abs(Q.T @ Q - np.eye(5)) <= O.TAU_ORTHO
+    assert projector_distance(Q, np.column_stack([x, y, Z])) < 1e-5
+    # an exactly repeated column: no column is dropped, the output is finite
+    # and orthonormal (the clamped eigenvalue turns the copy into a new
+    # direction)
+    st = O.OrthoStats()
+    Q = O.ortho(np.column_stack([x, x, Z]), stats=st, shift_retries=0)
+    assert st.svqb == 1 and Q.shape == (800, 5) and np.all(np.isfinite(Q))
+    assert O.max_abs(Q.T @ Q - np.eye(5)) <= O.TAU_ORTHO
+    assert projector_distance(np.column_stack([x, Z]), Q @ (Q.T @ np.column_stack([x, Z]))) < 1e-10
+
+
+def test_ortho_against_with_svqb():
+    # Alg. 3 around an Alg. 2 that needs SVQB (an exactly repeated column
+    # makes the overlap singular, so the plain factorisation must fail): the
+    # same span and Y-orthogonality bars as with the shifted Cholesky
+    g = synth.rng(8)
+    Y = np.linalg.qr(g.standard_normal((700, 4)))[0]
+    x = g.standard_normal(700)
+    Z = g.standard_normal((700, 2))
+    st = O.OrthoStats()
+    Q = O.ortho_against(np.column_stack([x, x, Z]), Y, stats=st, shift_retries=0)
+    assert st.svqb >= 1
+    assert O.max_abs(Y.T @ Q) <= O.TAU_ORTHO
+    assert O.max_abs(Q.T @ Q - np.eye(4)) <= O.TAU_ORTHO
+    # x and Z, less their Y parts, lie in span(Q)
+    B = np.column_stack([x, Z])
+    B = B - Y @ (Y.T @ B)
+    assert np.linalg.norm(B - Q @ (Q.T @ B)) <= 1e-12 * np.linalg.norm(B)
+
+
+# ---------------------------------------------------------------------------
+# reading R9: a failed true-residual check restarts the iteration
+
+
+def _drifted_solve(plant, tol=1e-9, force_restarts=0):
+    n, k = 400, 4
+    A = synth.dense_dd(n, seed=7)
+    noise = 1e-6 * synth.start_block(n, k, 99)
+    planted = {}
+
+    def cb(d):
+        # once the recurrence's residuals meet tol, move X away from the
+        # vectors they were measured on (in place: this is the block the
+        # true check will judge)
+        if plant and not planted and np.max(d["rnorm"][:k]) <= tol:
+            d["X"] += noise
+            planted["it"] = d["it"]
+
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(n, k, 8), k, tol, diag=np.diag(A).copy(), callback=cb,
+                   force_restarts=force_restarts)
+    return A, res, planted
+
+
+def test_restart_after_failed_true_check():
+    A, res0, _ = _drifted_solve(False)
+    assert res0.converged and res0.true_checks == 1 and res0.restarts == 0
+    A, res, planted = _drifted_solve(True)
+    assert planted
+    assert res.true_checks >= 2 and res.restarts >= 1
+    assert res.converged and np.max(res.resnorms) <= 1e-9
+    assert_eigs(res, np.linalg.eigvalsh(A)[:4], tol=1e-9)
+    # the restart costs iterations: it drops P and re-enters the loop
+    assert res.iterations > res0.iterations
+    X = res.X_all
+    assert O.max_abs(X.T @ X - np.eye(4)) < 1e-12
+
+
+def test_forced_restart_hook_matches_a_real_one():
+    # the test hook that rejects the first true check takes the same branch
+    A, res, _ = _drifted_solve(False, force_restarts=1)
+    assert res.restarts == 1 and res.true_checks == 2
+    assert res.converged
+    assert_eigs(res, np.linalg.eigvalsh(A)[:4], tol=1e-9)
