@@ -80,6 +80,17 @@ typedef struct lobpcg_ctx* lobpcg_t;
 #define LOBPCG_OPT_LEARNED_BF16 6     /* learned preconditioner inference: 1 (default)
                                          = hidden layer on bf16 MFMA with fp32
                                          accumulation, 0 = fp32 throughout */
+#define LOBPCG_OPT_SHIFT_RETRIES 8    /* shifted Cholesky attempts after a failed plain
+                                         factorisation (Sec. 3.2), default 20, 0..20;
+                                         when they all fail the pass orthonormalises
+                                         by SVQB (Stathopoulos-Wu).  0 sends every
+                                         failed factorisation straight to SVQB */
+#define LOBPCG_OPT_FORCE_RESTARTS 9   /* test hook, default 0: the first N explicit
+                                         true-residual checks of a solve count as
+                                         failed, which drives the restart that a
+                                         failed check triggers (Rayleigh-Ritz on
+                                         [X] with the explicit product A X, P
+                                         dropped) */
 
 /* ---- statistics --------------------------------------------------------- */
 typedef struct lobpcg_stats {
@@ -107,6 +118,8 @@ typedef struct lobpcg_stats {
   int32_t learned_nonfinite;   /* learned applications with a non-finite net output */
   int32_t rr_eig_fallbacks;    /* Rayleigh-Ritz eigensolves that fell back from the
                                   tridiagonal path to Jacobi */
+  int32_t restarts;            /* failed true-residual checks (each restarts the
+                                  iteration from X with the explicit product) */
 } lobpcg_stats;
 
 /* ---- ortho report for the step entry points ---------------------------- */
@@ -128,11 +141,14 @@ int lobpcg_set_stream(lobpcg_t h, void* hip_stream);
 /* Set an option (LOBPCG_OPT_*); integer options take integral values. */
 int lobpcg_set_option(lobpcg_t h, int key, double value);
 
-/* Bytes of device workspace needed for a block of `block` columns under the
- * current options and operator (call after the operator is set).  The block
- * is the RR block m (Sec. 2: m >= number of pairs sought); 1 <= block <= 32
- * and 3 * block <= n. */
-int lobpcg_workspace_size(lobpcg_t h, int block, size_t* bytes);
+/* Bytes of device workspace a solve for k pairs with a block of `block`
+ * columns needs in precision mode `precision` (LOBPCG_PREC_*) with the
+ * operator currently set (the dense and Kronecker operators and the fp32
+ * mode need more, so query again after changing them; Sec. 2: the block m
+ * may exceed the number k of pairs sought, and the solve stops when the
+ * first k have converged).  1 <= k <= block <= 32 and 3 * block <= n.  Also
+ * selects `block` for a later solve when no initial guess is set. */
+int lobpcg_workspace_size(lobpcg_t h, int k, int block, int precision, size_t* bytes);
 /* Hand over a device buffer of `bytes` bytes (256-byte aligned) used for all
  * blocks and partial results.  Borrowed, not freed by the library. */
 int lobpcg_set_workspace(lobpcg_t h, void* dev_ptr, size_t bytes);
@@ -178,9 +194,16 @@ int lobpcg_set_preconditioner(lobpcg_t h, int kind, const double* diag);
 int lobpcg_set_learned_weights(lobpcg_t h, const float* w, int64_t count);
 
 /* Initial block X0 (Alg. 1 input): device, row-major n x block with leading
- * dimension ld.  Copied when lobpcg_solve starts.  Without it the solver
- * fills X0 with SplitMix64 uniforms in [-0.5, 0.5). */
+ * dimension ld >= block; borrowed, read when lobpcg_solve starts.  Without an
+ * initial guess the solver fills X0 with SplitMix64 uniforms in [-0.5, 0.5).
+ * 1 <= block <= 32, 3 * block <= n. */
 int lobpcg_set_initial_guess(lobpcg_t h, const double* X0, int64_t ld, int block);
+/* The same from host memory in column-major order (the layout of the
+ * problem statement: column j is the j-th start vector): entry (i, j) at
+ * X0[j * ld + i], ld >= n.  Copied into a library-owned host buffer at the
+ * call (n * block doubles) and uploaded when lobpcg_solve starts; replaces a
+ * device initial guess and vice versa. */
+int lobpcg_set_initial_guess_host(lobpcg_t h, const double* X0, int64_t ld, int block);
 
 /* ======================================================================== */
 /* Solve and results                                                          */
@@ -199,6 +222,11 @@ int lobpcg_solve(lobpcg_t h, int k, double tol);
  * residual 2-norms from an explicit product A X.  Blocking. */
 int lobpcg_get_eigenpairs(lobpcg_t h, int k, double* evals, double* evecs, int64_t ldv,
                           double* resnorms);
+/* The same with evecs in host memory, column-major: entry (i, j) of the
+ * n x k result at evecs[j * ldv + i], ldv >= n (may be NULL).  Uses the
+ * workspace as staging.  Blocking. */
+int lobpcg_get_eigenpairs_host(lobpcg_t h, int k, double* evals, double* evecs, int64_t ldv,
+                               double* resnorms);
 /* Counters and phase times of the last solve (host struct). */
 int lobpcg_get_stats(lobpcg_t h, lobpcg_stats* out);
 
@@ -240,10 +268,12 @@ int lobpcg_ortho_against(lobpcg_t h, double* X, int64_t ldx, int ncols, const do
                          int64_t ldy, int ycols, lobpcg_ortho_info* info);
 
 /* Small symmetric eigensolve of the RR matrix (Alg. 1, "solve a u = lambda
- * u"): a (device p x p, symmetrised as (a + a^T)/2 first) -> evals (device,
- * p, ascending) and evecs (device p x p row-major, column j pairs with
- * evals[j]).  2 <= p <= 96.  Cyclic parallel-order Jacobi in fp64.
- * Asynchronous. */
+ * u"; Sec. 3.1 uses LAPACK's dsyev there): a (device p x p, symmetrised as
+ * (a + a^T)/2 first) -> evals (device, p, ascending) and evecs (device p x p
+ * row-major, column j pairs with evals[j]).  1 <= p <= 96.  fp64, one
+ * workgroup, the Rayleigh-Ritz kernel's eigensolver: Householder
+ * tridiagonalisation, Sturm multisection and inverse iteration, with cyclic
+ * parallel-order Jacobi sweeps as the fallback.  Asynchronous. */
 int lobpcg_small_eigh(lobpcg_t h, const double* a, int p, double* evals, double* evecs);
 
 /* Shifted Cholesky of a small overlap M (device p x p, p <= 64): L (device,

@@ -54,7 +54,9 @@ the design notes of the repository):
       explicit product A X (the true residual); if that check fails, the
       iteration restarts as Alg. 1 starts: Rayleigh-Ritz on [X] with the
       explicit product, P dropped, locking recounted, and the next
-      convergence test only after one more iteration.
+      convergence test only after one more iteration, which locks at most
+      k - 1 columns (so it has an active column, and a check that fails
+      again cannot repeat without progress).
   R10 The reduced matrix is symmetrised, a <- (a + a^T) / 2, before eigh.
   R16 Eigenvectors of the reduced matrix are oriented so that the diagonal
       entry u[j, j] is >= 0 (for the X block: the new Ritz vector continues
@@ -474,8 +476,14 @@ def lobpcg(
     restarts = 0
     just_restarted = False
     while True:
-        m_conv = max(m_conv, leading_converged(rnorm, tol))  # reading R8
-        if m_conv >= k and not just_restarted:
+        lead = leading_converged(rnorm, tol)
+        if just_restarted:
+            # after a restart the convergence test waits one iteration, and
+            # that iteration keeps at least the k-th column active
+            m_conv = min(max(m_conv, lead), k - 1)
+        else:
+            m_conv = max(m_conv, lead)  # reading R8
+        if m_conv >= k:
             # reading R9: re-orthonormalise X (Alg. 2; the implicit-P
             # recurrence lets X^T X drift from I by rounding), then judge with
             # the true residual of an explicit product

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "liblobpcg.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m paper_2305_06668_amd.build` "
+        f"{LIB_PATH} is missing: build it with `python paper_2305_06668_amd/build.py` "
         "(hipcc, gfx950); there is no CPU fallback"
     )
 _lib = ctypes.CDLL(LIB_PATH)
@@ -55,6 +55,8 @@ OPT_ORTHO_Y_MAX_PASSES = 4
 OPT_TRACE = 5
 OPT_LEARNED_BF16 = 6
 OPT_RR_JACOBI = 7
+OPT_SHIFT_RETRIES = 8
+OPT_FORCE_RESTARTS = 9
 
 _i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -83,6 +85,7 @@ class lobpcg_stats(ctypes.Structure):
         ("learned_fallbacks", _i32),
         ("learned_nonfinite", _i32),
         ("rr_eig_fallbacks", _i32),
+        ("restarts", _i32),
     ]
 
     def as_dict(self) -> dict:
@@ -108,15 +111,19 @@ _c = {
     "destroy": _sig("lobpcg_destroy", [_vp]),
     "set_stream": _sig("lobpcg_set_stream", [_vp, _vp]),
     "set_option": _sig("lobpcg_set_option", [_vp, ctypes.c_int, _dbl]),
-    "workspace_size": _sig("lobpcg_workspace_size", [_vp, ctypes.c_int, ctypes.POINTER(_sz)]),
+    "workspace_size": _sig(
+        "lobpcg_workspace_size", [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_sz)]
+    ),
     "set_workspace": _sig("lobpcg_set_workspace", [_vp, _vp, _sz]),
     "set_operator_csr": _sig("lobpcg_set_operator_csr", [_vp, _vp, _vp, _vp, _i64]),
     "set_operator_dense": _sig("lobpcg_set_operator_dense", [_vp, _vp, _i64]),
     "set_operator_kronsum": _sig("lobpcg_set_operator_kronsum", [_vp, _i64, _vp, _vp]),
     "set_preconditioner": _sig("lobpcg_set_preconditioner", [_vp, ctypes.c_int, _vp]),
     "set_initial_guess": _sig("lobpcg_set_initial_guess", [_vp, _vp, _i64, ctypes.c_int]),
+    "set_initial_guess_host": _sig("lobpcg_set_initial_guess_host", [_vp, _vp, _i64, ctypes.c_int]),
     "solve": _sig("lobpcg_solve", [_vp, ctypes.c_int, _dbl]),
     "get_eigenpairs": _sig("lobpcg_get_eigenpairs", [_vp, ctypes.c_int, _vp, _vp, _i64, _vp]),
+    "get_eigenpairs_host": _sig("lobpcg_get_eigenpairs_host", [_vp, ctypes.c_int, _vp, _vp, _i64, _vp]),
     "get_stats": _sig("lobpcg_get_stats", [_vp, ctypes.POINTER(lobpcg_stats)]),
     "status_string": _sig("lobpcg_status_string", [ctypes.c_int], ctypes.c_char_p),
     "last_error": _sig("lobpcg_last_error", [_vp], ctypes.c_char_p),
@@ -158,7 +165,8 @@ EXPORTED = [
     "lobpcg_create", "lobpcg_destroy", "lobpcg_set_stream", "lobpcg_set_option",
     "lobpcg_workspace_size", "lobpcg_set_workspace", "lobpcg_set_operator_csr",
     "lobpcg_set_operator_dense", "lobpcg_set_operator_kronsum", "lobpcg_set_preconditioner",
-    "lobpcg_set_initial_guess", "lobpcg_solve", "lobpcg_get_eigenpairs", "lobpcg_get_stats",
+    "lobpcg_set_initial_guess", "lobpcg_set_initial_guess_host", "lobpcg_solve",
+    "lobpcg_get_eigenpairs", "lobpcg_get_eigenpairs_host", "lobpcg_get_stats",
     "lobpcg_status_string", "lobpcg_last_error", "lobpcg_apply_operator", "lobpcg_gram",
     "lobpcg_ortho", "lobpcg_ortho_against", "lobpcg_small_eigh", "lobpcg_small_cholesky",
     "lobpcg_rotate", "lobpcg_set_learned_weights", "lobpcg_learned_apply",
@@ -243,9 +251,9 @@ def lobpcg_set_option(h, key: int, value: float) -> None:
     _check(h, _c["set_option"](h, int(key), float(value)))
 
 
-def lobpcg_workspace_size(h, block: int) -> int:
+def lobpcg_workspace_size(h, k: int, block: int, precision: int = PREC_FP64) -> int:
     out = ctypes.c_size_t()
-    _check(h, _c["workspace_size"](h, int(block), ctypes.byref(out)))
+    _check(h, _c["workspace_size"](h, int(k), int(block), int(precision), ctypes.byref(out)))
     return int(out.value)
 
 
@@ -291,6 +299,12 @@ def lobpcg_set_initial_guess(h, X0) -> None:
     _check(h, _c["set_initial_guess"](h, _dev_ptr(X0, torch.float64, "X0"), _ld(X0, "X0"), int(X0.shape[1])))
 
 
+def lobpcg_set_initial_guess_host(h, X0: np.ndarray) -> None:
+    """X0: host n x block array; passed to the library column-major."""
+    Xf = np.asfortranarray(X0, dtype=np.float64)
+    _check(h, _c["set_initial_guess_host"](h, Xf.ctypes.data_as(ctypes.c_void_p), int(Xf.shape[0]), int(Xf.shape[1])))
+
+
 def lobpcg_solve(h, k: int, tol: float) -> int:
     return _check(h, _c["solve"](h, int(k), float(tol)), allow=(OK, NOT_CONVERGED))
 
@@ -308,6 +322,26 @@ def lobpcg_get_eigenpairs(h, k: int, evecs=None):
         ),
     )
     return ev, rn
+
+
+def lobpcg_get_eigenpairs_host(h, k: int, n: int, want_vectors: bool = True):
+    """Eigenvalues, residual norms and (optionally) the n x k eigenvectors as
+    a host array, read back column-major."""
+    ev = np.zeros(k)
+    rn = np.zeros(k)
+    X = np.zeros((n, k), order="F") if want_vectors else None
+    _check(
+        h,
+        _c["get_eigenpairs_host"](
+            h,
+            int(k),
+            ev.ctypes.data_as(ctypes.c_void_p),
+            X.ctypes.data_as(ctypes.c_void_p) if X is not None else None,
+            int(n),
+            rn.ctypes.data_as(ctypes.c_void_p),
+        ),
+    )
+    return ev, rn, X
 
 
 def lobpcg_get_stats(h) -> dict:
@@ -536,6 +570,7 @@ class Solver:
         self._keep = {}
         self._ws = None
         self._block = None
+        self._prec = PREC_FP64
         lobpcg_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
 
     def close(self):
@@ -577,17 +612,24 @@ class Solver:
 
     def set_option(self, key, value):
         lobpcg_set_option(self.h, key, value)
-        if key == OPT_PRECISION and self._block is not None:
-            self.ensure_workspace(self._block)  # the fp32 phase needs more workspace
+        if key == OPT_PRECISION:
+            self._prec = int(value)
+            if self._block is not None:
+                self.ensure_workspace(self._block)  # the fp32 phase needs more workspace
 
     def set_initial_guess(self, X0):
         self._keep["X0"] = X0
         lobpcg_set_initial_guess(self.h, X0)
         self.ensure_workspace(X0.shape[1])
 
+    def set_initial_guess_host(self, X0: np.ndarray):
+        self._keep["X0"] = None
+        lobpcg_set_initial_guess_host(self.h, X0)
+        self.ensure_workspace(X0.shape[1])
+
     def ensure_workspace(self, block: int):
         torch = _torch()
-        need = lobpcg_workspace_size(self.h, block)
+        need = lobpcg_workspace_size(self.h, 1, block, self._prec)
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(need + 256, dtype=torch.uint8, device=f"cuda:{self.device}")
         ptr = self._ws.data_ptr()

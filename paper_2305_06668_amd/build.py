@@ -1,6 +1,7 @@
 """Build the HIP shared library liblobpcg.so for gfx950 (in-tree).
 
-Usage: python -m paper_2305_06668_amd.build   (or build() from Python)
+Usage: python paper_2305_06668_amd/build.py   (or __graft_entry__.build());
+run as a file: importing the package needs the library this script builds.
 """
 from __future__ import annotations
 

@@ -50,6 +50,8 @@ struct lobpcg_ctx {
   int ortho_max_outer = 4;
   int trace = 0;
   int rr_jacobi = 0;     // Rayleigh-Ritz eigensolver: 0 tridiagonal, 1 Jacobi
+  int shift_retries = 20;  // shifted Cholesky retries before SVQB (ortho controller)
+  int force_restarts = 0;  // test hook: true checks that count as failed
   int learned_bf16 = 1;  // learned preconditioner inference: layer 2 on bf16 MFMA
   // operator
   int op = lobpcg::kOpNone;
@@ -68,9 +70,10 @@ struct lobpcg_ctx {
   float* lweights = nullptr;     // learned preconditioner weights (library-owned device copy)
   bool lfeat_ready = false;      // off-diagonal row sums and mean |diag| computed
   double lscale_host = 0.0;
-  // initial guess
+  // initial guess (device, row-major; or a host copy, row-major)
   const double* X0 = nullptr;
   int64_t ldx0 = 0;
+  std::vector<double> X0_host;
   int block = 0;
   // workspace
   char* ws = nullptr;
@@ -112,7 +115,8 @@ struct lobpcg_ctx {
     err = std::string(where) + ": " + hipGetErrorString(e);
     return LOBPCG_ERR_DEVICE;
   }
-  Layout plan(int m) const;
+  Layout plan(int m) const { return plan(m, precision); }
+  Layout plan(int m, int prec) const;
   size_t op32_elems() const;
   int ensure_layout(int m);
   int apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy);

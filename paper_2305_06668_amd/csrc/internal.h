@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 namespace lobpcg {
 
@@ -46,6 +47,7 @@ struct OrthoState {
   int grams, factorizations, failed, shifted, updates, stalled, svqb, passes;
   int ny, nw;   // current shape
   int max_inner, max_outer;
+  int shift_retries;  // shifted Cholesky attempts after a failed plain one, then SVQB
   int fold_scale;     // input: a final diagonal column scaling may be left pending
   int pending_scale;  // output: W must still be scaled by dscale (folded into the next RR)
   double tau;
@@ -181,7 +183,7 @@ hipError_t small_cholesky(const double* M, int p, double* L, int* info, hipStrea
 // updates the state and writes the next coefficient ((ny+nw) x nw).
 hipError_t ortho_ctl(const double* G, OrthoState* st, double* coef, hipStream_t s);
 hipError_t ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner, int max_outer,
-                      int fold_scale, hipStream_t s);
+                      int shift_retries, int fold_scale, hipStream_t s);
 
 // ---- learned preconditioner (k_mlp.hip) ---------------------------------
 // In place: R[:, 0:nact] (n rows, leading dimension ld) <- learned

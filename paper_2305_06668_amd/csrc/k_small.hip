@@ -143,7 +143,7 @@ struct ShiftCount {
 // Sec. 3.2 / Alg. 2: plain Cholesky, then shifts alpha*eps*||X||_F with
 // ||X||_F = sqrt(trace M), alpha = 100, x10 per retry.
 __device__ __forceinline__ bool blk_shifted_chol(const double* M, int ldm, int n, double* L, int ldl, int* flag,
-                                 ShiftCount* c, double* scratch) {
+                                 ShiftCount* c, double* scratch, int retries = kShiftRetries) {
   if (threadIdx.x == 0) c->factorizations++;
   if (blk_chol(M, ldm, n, 0.0, L, ldl, flag)) return true;
   if (threadIdx.x == 0) c->failed++;
@@ -151,7 +151,7 @@ __device__ __forceinline__ bool blk_shifted_chol(const double* M, int ldm, int n
   for (int i = 0; i < n; ++i) tr += M[i * ldm + i];
   const double normx = sqrt(fmax(tr, 0.0));
   double alpha = kShiftAlpha0;
-  for (int t = 0; t < kShiftRetries; ++t) {
+  for (int t = 0; t < retries; ++t) {
     if (threadIdx.x == 0) c->factorizations++;
     if (blk_chol(M, ldm, n, alpha * kEps * normx, L, ldl, flag)) {
       if (threadIdx.x == 0) c->shifted++;
@@ -1395,7 +1395,7 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
     have_scale = (phase == kPhBegin);
   } else {
     // shifted Cholesky of M (= M' in BEGIN)
-    const bool ok = blk_shifted_chol(Ms, ldm, nw, Ls, ldm, &flag, &cnt, scratch);
+    const bool ok = blk_shifted_chol(Ms, ldm, nw, Ls, ldm, &flag, &cnt, scratch, st.shift_retries);
     if (ok) {
       blk_tri_inv(Ls, ldm, nw, Li, ldm);
       // coef W part: D L^-T, i.e. coef[ny+i][j] = D_i Linv[j][i]
@@ -1486,7 +1486,7 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
 }
 
 __global__ void k_ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner,
-                             int max_outer, int fold_scale) {
+                             int max_outer, int shift_retries, int fold_scale) {
   OrthoState s;
   s.state = kPhStart;
   s.done = 0;
@@ -1500,6 +1500,7 @@ __global__ void k_ortho_init(OrthoState* st, int ny, int nw, double tau, int max
   s.nw = nw;
   s.max_inner = max_inner;
   s.max_outer = max_outer;
+  s.shift_retries = shift_retries;
   s.fold_scale = fold_scale;
   s.pending_scale = 0;
   s.tau = tau;
@@ -1508,10 +1509,11 @@ __global__ void k_ortho_init(OrthoState* st, int ny, int nw, double tau, int max
 }
 
 hipError_t ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner, int max_outer,
-                      int fold_scale, hipStream_t s) {
-  if (nw < 1 || nw > kMaxBlock || ny < 0 || ny + nw > kMaxP) return hipErrorInvalidValue;
+                      int shift_retries, int fold_scale, hipStream_t s) {
+  if (nw < 1 || nw > kMaxBlock || ny < 0 || ny + nw > kMaxP || shift_retries < 0)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ortho_init, dim3(1), dim3(1), 0, s, st, ny, nw, tau, max_inner, max_outer,
-                     fold_scale);
+                     shift_retries, fold_scale);
   return hipGetLastError();
 }
 

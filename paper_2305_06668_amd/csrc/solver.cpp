@@ -34,7 +34,7 @@ size_t lobpcg_ctx::op32_elems() const {
   }
 }
 
-Layout lobpcg_ctx::plan(int m) const {
+Layout lobpcg_ctx::plan(int m, int prec) const {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -82,7 +82,7 @@ Layout lobpcg_ctx::plan(int m) const {
   L.eye = stake(sizeof(double) * 64 * 64);
   L.lscale = stake(sizeof(double) * 4);
   L.small = take(so);
-  if (precision == LOBPCG_PREC_FP32) {
+  if (prec == LOBPCG_PREC_FP32) {
     const size_t blk32 = (size_t)n * 3 * m * sizeof(float);
     L.V32[0] = take(blk32);
     L.V32[1] = take(blk32);
@@ -277,7 +277,7 @@ static hipError_t fill_t(float* X, int64_t ld, int col, int id, int64_t n, uint6
   return fill_splitmix_f32(X, ld, col, id, n, seed, s);
 }
 
-// ortho(W; Y) (Alg. 3 around Alg. 2) on base = [Y | W] rows, ld.
+// Status read-back of `bytes` of device memory once the queued work ran.
 int lobpcg_ctx::readback(const void* src, size_t bytes, const void** out) {
   if (bytes > kPostBytes || bytes % 4 != 0) return fail(LOBPCG_ERR_INVALID_ARG, "read-back size");
   if (post == nullptr) {
@@ -314,6 +314,9 @@ int lobpcg_ctx::readback(const void* src, size_t bytes, const void** out) {
   return LOBPCG_OK;
 }
 
+// ortho(W; Y) (Alg. 3 around Alg. 2) on base = [Y | W] rows, ld: rounds of
+// (controller kernel, block update with the next overlap) driven by the
+// device-side state, read back every few rounds.
 template <typename T>
 int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info* info,
                           bool fold, double tau_run) {
@@ -324,7 +327,8 @@ int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info
   const int nr = ny + nw;
   const double t = (tau_run > 0.0) ? tau_run : tau;
   for (int attempt = 0; attempt < 3; ++attempt) {
-    HIPCHK(ortho_init(st, ny, nw, t, ortho_max_inner, ortho_max_outer, fold ? 1 : 0, stream));
+    HIPCHK(ortho_init(st, ny, nw, t, ortho_max_inner, ortho_max_outer, shift_retries, fold ? 1 : 0,
+                      stream));
     // the overlap [Y W~]^T W~ of the raw W~, by its own kernel: fused into
     // the rotation it held the rotation at two waves per SIMD (fp64), which
     // cost more than the separate pass (434 us against 328 + 91 us per
@@ -455,6 +459,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
   int c = 0;           // current buffer
   int L = m;           // its leading dimension (= number of columns in V)
   bool first = true;   // V = [X] only (initial RR, or restart after a true check)
+  bool just_restarted = false;  // the convergence test waits one iteration after a restart
   int m_conv = 0;
   double prev_max = INFINITY;
   int stall = 0;
@@ -528,7 +533,11 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
         return LOBPCG_OK;
       }
     }
-    const int newc = std::max(m_conv, leading_converged(rnorm, lock_tol));
+    int newc = std::max(m_conv, leading_converged(rnorm, lock_tol));
+    // after a restart the convergence test waits one iteration, and that
+    // iteration keeps at least the k-th column active
+    if (just_restarted) newc = std::min(newc, k - 1);
+    just_restarted = false;
     if (!low && newc >= k) {
       // convergence is confirmed on an explicit product A X, not the
       // recurrence's residuals
@@ -543,19 +552,25 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       if (rc) return rc;
       double worst = 0.0;
       for (int j = 0; j < k; ++j) worst = std::max(worst, rn_t[j]);
-      if (worst <= tol) {
+      if (worst <= tol && stats.restarts >= force_restarts) {
         out.converged = true;
         out.X = V[1 - c];
         out.ld = ldo;
         break;
       }
-      // restart from X with the explicit product: V = [X], AV = [A X]
+      // restart as Alg. 1 starts: Rayleigh-Ritz on V = [X] with the explicit
+      // product AV = [A X] (true_residuals left it in AV[c] at leading
+      // dimension m), P dropped, locking recounted; the next convergence
+      // test comes one iteration later, an iteration with at most k - 1
+      // locked columns
+      stats.restarts++;
       HIPCHK(hipMemcpy2DAsync(V[c], sizeof(T) * m, V[1 - c], sizeof(T) * ldo, sizeof(T) * m, n,
                               hipMemcpyDeviceToDevice, stream));
       L = m;
       first = true;
       m_conv = 0;
       pend_valid = false;  // the copied X is fully scaled
+      just_restarted = true;
       continue;
     }
     if (newc != m_conv) {
@@ -651,6 +666,10 @@ int lobpcg_ctx::solve(int k, double tol) {
   if (X0 != nullptr) {
     HIPCHK(hipMemcpy2DAsync(V[0], sizeof(double) * m, X0, sizeof(double) * ldx0,
                             sizeof(double) * m, n, hipMemcpyDeviceToDevice, stream));
+  } else if (!X0_host.empty()) {
+    HIPCHK(hipMemcpyAsync(V[0], X0_host.data(), sizeof(double) * m * n, hipMemcpyHostToDevice,
+                          stream));
+    HIPCHK(hipStreamSynchronize(stream));
   } else {
     for (int j = 0; j < m; ++j) HIPCHK(fill_splitmix(V[0], m, j, j, n, kDefaultX0Seed, stream));
   }
@@ -778,16 +797,29 @@ int lobpcg_set_option(lobpcg_t h, int key, double v) {
     case LOBPCG_OPT_RR_JACOBI:
       h->rr_jacobi = (v != 0.0);
       return LOBPCG_OK;
+    case LOBPCG_OPT_SHIFT_RETRIES:
+      if (v < 0 || v > 20 || v != (int)v)
+        return h->fail(LOBPCG_ERR_INVALID_ARG, "shift retries must be an integer in [0, 20]");
+      h->shift_retries = (int)v;
+      return LOBPCG_OK;
+    case LOBPCG_OPT_FORCE_RESTARTS:
+      if (v < 0 || v > 100 || v != (int)v)
+        return h->fail(LOBPCG_ERR_INVALID_ARG, "forced restarts must be an integer in [0, 100]");
+      h->force_restarts = (int)v;
+      return LOBPCG_OK;
     default: return h->fail(LOBPCG_ERR_INVALID_ARG, "unknown option");
   }
 }
 
-int lobpcg_workspace_size(lobpcg_t h, int block, size_t* bytes) {
+int lobpcg_workspace_size(lobpcg_t h, int k, int block, int precision, size_t* bytes) {
   if (h == nullptr || bytes == nullptr) return LOBPCG_ERR_INVALID_ARG;
   if (block < 1 || block > kMaxBlock || 3 * (int64_t)block > h->n)
     return h->fail(LOBPCG_ERR_INVALID_ARG, "need 1 <= block <= 32 and 3*block <= n");
-  *bytes = h->plan(block).total;
-  if (h->X0 == nullptr) h->block = block;
+  if (k < 1 || k > block) return h->fail(LOBPCG_ERR_INVALID_ARG, "need 1 <= k <= block");
+  if (precision != LOBPCG_PREC_FP64 && precision != LOBPCG_PREC_FP32)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad precision");
+  *bytes = h->plan(block, precision).total;
+  if (h->X0 == nullptr && h->X0_host.empty()) h->block = block;
   return LOBPCG_OK;
 }
 
@@ -901,6 +933,27 @@ int lobpcg_set_initial_guess(lobpcg_t h, const double* X0, int64_t ld, int block
   h->X0 = X0;
   h->ldx0 = ld;
   h->block = block;
+  h->X0_host.clear();
+  h->X0_host.shrink_to_fit();
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_initial_guess_host(lobpcg_t h, const double* X0, int64_t ld, int block) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  if (X0 == nullptr || block < 1 || block > kMaxBlock || ld < h->n || 3 * (int64_t)block > h->n)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad initial guess (block <= 32, 3*block <= n, ld >= n)");
+  try {
+    h->X0_host.assign((size_t)h->n * block, 0.0);
+  } catch (...) {
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "initial guess: host allocation failed");
+  }
+  // column-major in, row-major (the device layout) kept
+  const int64_t n = h->n;
+  for (int64_t i = 0; i < n; ++i)
+    for (int j = 0; j < block; ++j) h->X0_host[(size_t)i * block + j] = X0[(size_t)j * ld + i];
+  h->X0 = nullptr;
+  h->ldx0 = 0;
+  h->block = block;
   return LOBPCG_OK;
 }
 
@@ -927,6 +980,39 @@ int lobpcg_get_eigenpairs(lobpcg_t h, int k, double* evals, double* evecs, int64
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return h->hip_fail(e, "sync");
   }
+  return LOBPCG_OK;
+}
+
+int lobpcg_get_eigenpairs_host(lobpcg_t h, int k, double* evals, double* evecs, int64_t ldv,
+                               double* resnorms) {
+  GUARD(h);
+  if (!h->have_result) return h->fail(LOBPCG_ERR_BAD_STATE, "no solve result");
+  if (k < 1 || k > (int)h->res_evals.size()) return h->fail(LOBPCG_ERR_INVALID_ARG, "bad k");
+  if (evecs != nullptr && ldv < h->n) return h->fail(LOBPCG_ERR_INVALID_ARG, "ldv < n");
+  for (int j = 0; j < k; ++j) {
+    if (evals) evals[j] = h->res_evals[j];
+    if (resnorms) resnorms[j] = h->res_resn[j];
+  }
+  if (evecs == nullptr) return LOBPCG_OK;
+  // sign-fixed row-major copy staged in the AV area of the workspace (the
+  // result itself lives in a V buffer), then transposed on the host
+  double* stage = h->dptr(h->lay.AV[0]);
+  hipError_t e = copy_signfix(h->res_X, h->res_ld, k, h->n, stage, k,
+                              h->small_ptr<int64_t>(h->lay.pidx), h->small_ptr<double>(h->lay.pval),
+                              h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "copy_signfix");
+  std::vector<double> tmp;
+  try {
+    tmp.resize((size_t)h->n * k);
+  } catch (...) {
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "get_eigenpairs_host: host allocation failed");
+  }
+  e = hipMemcpyAsync(tmp.data(), stage, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost,
+                     h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "eigenvector read-back");
+  for (int64_t i = 0; i < h->n; ++i)
+    for (int j = 0; j < k; ++j) evecs[(size_t)j * ldv + i] = tmp[(size_t)i * k + j];
   return LOBPCG_OK;
 }
 

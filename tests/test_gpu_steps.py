@@ -273,6 +273,75 @@ def test_ortho_forced_shift(P):
     assert np.abs(Q.T @ Q - np.eye(5)).max() <= 1e-14
 
 
+def test_ortho_svqb_without_shift_retries(P):
+    """Sec. 3.2's fallback chain with the shifted retries switched off: the
+    failed plain factorisation of a cond ~ 1e10 block goes straight to SVQB
+    (Stathopoulos-Wu), as in the oracle with shift_retries=0, and the next
+    pass finishes with a plain Cholesky."""
+    say("ortho svqb")
+    g = synth.rng(5)
+    n = 800
+    x, y = g.standard_normal(n), g.standard_normal(n)
+    Z = g.standard_normal((n, 3))
+    X = np.column_stack([x, x + 1e-10 * y, Z])
+    s = make_solver(P, n)
+    P.lobpcg_set_option(s.h, P.OPT_SHIFT_RETRIES, 0)
+    Xd = cu(X)
+    info = P.lobpcg_ortho(s.h, Xd)
+    Q = host(Xd)
+    st = O.OrthoStats()
+    Qo = O.ortho(X, stats=st, shift_retries=0)
+    say(info, st)
+    assert st.svqb == 1 and st.failed_factorizations == 1
+    assert info["svqb"] == st.svqb and info["failed"] == st.failed_factorizations
+    assert info["shifted"] == 0 and info["stalled"] == 0
+    assert np.abs(Q.T @ Q - np.eye(5)).max() <= 1e-14
+    # the span is fixed to ~ eps cond: x, y and Z as the oracle keeps them
+    dist = lambda A, B: np.linalg.norm(np.linalg.qr(A)[0] @ np.linalg.qr(A)[0].T - np.linalg.qr(B)[0] @ np.linalg.qr(B)[0].T, 2)
+    assert dist(Q, Qo) < 1e-5 and dist(Q, np.column_stack([x, y, Z])) < 1e-5
+    # an exactly repeated column: every column kept, finite and orthonormal
+    s2 = make_solver(P, n)
+    P.lobpcg_set_option(s2.h, P.OPT_SHIFT_RETRIES, 0)
+    Xd = cu(np.column_stack([x, x, Z]))
+    info = P.lobpcg_ortho(s2.h, Xd)
+    Q = host(Xd)
+    assert np.all(np.isfinite(Q)) and np.abs(Q.T @ Q - np.eye(5)).max() <= 1e-14
+    B = np.column_stack([x, Z])
+    assert np.linalg.norm(B - Q @ (Q.T @ B)) <= 1e-12 * np.linalg.norm(B)
+    # the default (20 shifted retries) never needs SVQB here
+    s3 = make_solver(P, n)
+    Xd = cu(X)
+    info = P.lobpcg_ortho(s3.h, Xd)
+    assert info["svqb"] == 0 and info["shifted"] == 1
+
+
+def test_ortho_against_svqb(P):
+    """Alg. 3 around an Alg. 2 whose first factorisation fails, with SVQB as
+    the only fallback: the oracle's bars (Y-orthogonality, orthonormality,
+    span) hold."""
+    g = synth.rng(8)
+    n, ny = 7000, 4
+    Y = np.linalg.qr(g.standard_normal((n, ny)))[0]
+    x, y = g.standard_normal(n), g.standard_normal(n)
+    Xt = np.column_stack([x, x + 1e-10 * y, g.standard_normal((n, 2))])
+    buf = cu(np.hstack([Y, Xt]))
+    s = make_solver(P, n)
+    P.lobpcg_set_option(s.h, P.OPT_SHIFT_RETRIES, 0)
+    info = P.lobpcg_ortho_against(s.h, buf[:, ny:], buf[:, :ny])
+    out = host(buf)
+    Q = out[:, ny:]
+    st = O.OrthoStats()
+    Qo = O.ortho_against(Xt, Y, stats=st, shift_retries=0)
+    say(info, st)
+    assert info["svqb"] >= 1 and st.svqb >= 1
+    assert np.array_equal(out[:, :ny], Y)
+    assert np.abs(Y.T @ Q).max() <= 1e-14
+    assert np.abs(Q.T @ Q - np.eye(4)).max() <= 1e-14
+    PQ = Q @ Q.T
+    PO = Qo @ Qo.T
+    assert np.linalg.norm(PQ - PO, 2) < 1e-5
+
+
 def test_ortho_against_vs_oracle(P):
     g = synth.rng(11)
     n = 6000
