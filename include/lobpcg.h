@@ -252,6 +252,18 @@ int lobpcg_apply_operator(lobpcg_t h, const double* W, int64_t ldw, int ncols, d
 int lobpcg_gram(lobpcg_t h, const double* A, int64_t lda, int p, const double* B, int64_t ldb,
                 int q, double* C);
 
+/* lobpcg_gram for callers that cannot allocate memory (code under HIP
+ * stream capture, tight serving loops, harnesses that forbid allocation): the
+ * same product, the same kernels and bitwise the same result, but no
+ * workspace is needed -- the partial sums of the n-reduction live in a
+ * library-owned static device array (16 MiB per GPU the library runs on, held
+ * until the process ends), and the call allocates nothing.  Limit: 1 <= p, q
+ * <= 64 (INVALID_ARG beyond).  Every call on one GPU shares that array, so
+ * calls that overlap on a GPU (other streams, other threads) race; calls in
+ * one stream's order are safe.  Asynchronous. */
+int lobpcg_gram_noalloc(lobpcg_t h, const double* A, int64_t lda, int p, const double* B,
+                        int64_t ldb, int q, double* C);
+
 /* Alg. 2, ortho(X): orthonormalise the ncols columns of X in place (device,
  * n x ncols, ldx), 1 <= ncols <= 32.  Columns are scaled to unit norm first;
  * a failed Cholesky of the overlap is retried with the diagonal shift

@@ -129,6 +129,7 @@ _c = {
     "last_error": _sig("lobpcg_last_error", [_vp], ctypes.c_char_p),
     "apply_operator": _sig("lobpcg_apply_operator", [_vp, _vp, _i64, ctypes.c_int, _vp, _i64]),
     "gram": _sig("lobpcg_gram", [_vp, _vp, _i64, ctypes.c_int, _vp, _i64, ctypes.c_int, _vp]),
+    "gram_noalloc": _sig("lobpcg_gram_noalloc", [_vp, _vp, _i64, ctypes.c_int, _vp, _i64, ctypes.c_int, _vp]),
     "ortho": _sig("lobpcg_ortho", [_vp, _vp, _i64, ctypes.c_int, ctypes.POINTER(lobpcg_ortho_info)]),
     "ortho_against": _sig(
         "lobpcg_ortho_against", [_vp, _vp, _i64, ctypes.c_int, _vp, _i64, ctypes.c_int, ctypes.POINTER(lobpcg_ortho_info)]
@@ -168,6 +169,7 @@ EXPORTED = [
     "lobpcg_set_initial_guess", "lobpcg_set_initial_guess_host", "lobpcg_solve",
     "lobpcg_get_eigenpairs", "lobpcg_get_eigenpairs_host", "lobpcg_get_stats",
     "lobpcg_status_string", "lobpcg_last_error", "lobpcg_apply_operator", "lobpcg_gram",
+    "lobpcg_gram_noalloc",
     "lobpcg_ortho", "lobpcg_ortho_against", "lobpcg_small_eigh", "lobpcg_small_cholesky",
     "lobpcg_rotate", "lobpcg_set_learned_weights", "lobpcg_learned_apply",
     "lobpcg_learner_create", "lobpcg_learner_destroy", "lobpcg_learner_set_stream",
@@ -356,6 +358,24 @@ def lobpcg_apply_operator(h, W, Y) -> None:
         h,
         _c["apply_operator"](
             h, _dev_ptr(W, torch.float64, "W"), _ld(W, "W"), int(W.shape[1]), _dev_ptr(Y, torch.float64, "Y"), _ld(Y, "Y")
+        ),
+    )
+
+
+def lobpcg_gram_noalloc(h, A, B, C) -> None:
+    """lobpcg_gram without a workspace (static device scratch, p, q <= 64)."""
+    torch = _torch()
+    _check(
+        h,
+        _c["gram_noalloc"](
+            h,
+            _dev_ptr(A, torch.float64, "A"),
+            _ld(A, "A"),
+            int(A.shape[1]),
+            _dev_ptr(B, torch.float64, "B"),
+            _ld(B, "B"),
+            int(B.shape[1]),
+            _dev_ptr(C, torch.float64, "C"),
         ),
     )
 

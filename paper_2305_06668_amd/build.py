@@ -23,6 +23,7 @@ SOURCES = [
     "k_learn.hip",
     "solver.cpp",
     "learner.cpp",
+    "noalloc.hip",
 ]
 ARCH = "gfx950"
 

@@ -162,6 +162,12 @@ hipError_t csr_norm_bound(const int32_t* rp, const double* val, int64_t n, doubl
 hipError_t dense_norm_bound(const double* A, int64_t lda, int64_t n, double* part, double* out,
                             hipStream_t s);
 
+// ---- lobpcg_gram_noalloc (noalloc.hip) -----------------------------------
+// Looks up (once per device, with that device current) the device address of
+// the static partial-sum array of lobpcg_gram_noalloc; *out receives it.
+// Returns a LOBPCG_* status; *err gets a message on failure.
+int noalloc_setup(int device, double** out, std::string* err);
+
 // ---- small dense fp64 kernels (k_small.hip) -----------------------------
 // Eigen-decomposition of sym(a) (p x p): evals ascending, evecs p x p.
 hipError_t small_eigh(const double* a, int p, double* evals, double* evecs, int* sweeps,

@@ -724,6 +724,12 @@ int lobpcg_create(int64_t n, int device, lobpcg_t* out) {
   if (h == nullptr) return LOBPCG_ERR_DEVICE;
   h->n = n;
   h->device = device;
+  // the static scratch of lobpcg_gram_noalloc: its device address is taken
+  // here, once per device, so that the entry point itself does no set-up
+  if (noalloc_setup(device, nullptr, &h->err) != LOBPCG_OK) {
+    delete h;
+    return LOBPCG_ERR_DEVICE;
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&h->pinned), kPinnedBytes, hipHostMallocDefault) !=
       hipSuccess) {
     delete h;
