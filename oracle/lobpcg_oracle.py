@@ -58,6 +58,13 @@ the design notes of the repository):
       k - 1 columns (so it has an active column, and a check that fails
       again cannot repeat without progress).
   R10 The reduced matrix is symmetrised, a <- (a + a^T) / 2, before eigh.
+  R17 Cheap exits (optional; Sec. 3.2 proposes them after Alg. 2 and Alg. 3
+      without fixing a rule): Alg. 2 stops without a new overlap after an
+      unshifted factor whose e = ||I - L||_F < 1/2 gives c(n) eps kappa^2 <=
+      tau, kappa = (1 + e) / (1 - e); Alg. 3 stops without Y^T X when
+      c(n) eps g <= tau, g the growth of the ortho call (normalisation scale
+      times a bound on ||L^-1|| per factor).  c(n) = max(4, 0.02 sqrt(n)) is
+      twice the loss measured on this oracle.
   R16 Eigenvectors of the reduced matrix are oriented so that the diagonal
       entry u[j, j] is >= 0 (for the X block: the new Ritz vector continues
       the old one).  The "Basis selection" paragraph forms P from the
@@ -84,6 +91,15 @@ SHIFT_RETRIES = 20  # R5
 ORTHO_MAX_PASSES = 6  # R4 (Alg. 2)
 ORTHO_Y_MAX_PASSES = 4  # R4 (Alg. 3)
 PRECOND_GUARD = 1e-8  # R7
+# Cheap exits of Alg. 2 / Alg. 3 (the estimates Sec. 3.2 proposes after each
+# algorithm; reading R17): one Cholesky-QR pass leaves X^T X - I at about
+# c eps kappa^2, and one project + ortho pass leaves Y^T X at about c eps g,
+# with c measured on this oracle at up to 1.5 (n = 1e4) .. 8.5 (n = 1e6),
+# ~0.0085 sqrt(n); the exits use twice that.
+
+
+def cheap_exit_factor(n: int) -> float:
+    return max(4.0, 0.02 * math.sqrt(n))
 ZERO_COLUMN_SEED = 0x2305066680000000  # R6
 
 Operator = Callable[[np.ndarray], np.ndarray]
@@ -106,6 +122,7 @@ class OrthoStats:
     stalled: int = 0
     svqb: int = 0
     zero_columns: int = 0
+    cheap_exits: int = 0  # overlaps not formed thanks to a cheap exit (R17)
 
     def merge(self, o: "OrthoStats") -> None:
         for f in dataclasses.fields(self):
@@ -209,20 +226,48 @@ def svqb(X: np.ndarray, M: np.ndarray, stats: OrthoStats) -> np.ndarray:
     return (X @ U) / np.sqrt(s)
 
 
+def inverse_factor_bound(L: np.ndarray):
+    """Upper bound b >= ||L^-1||_2 for a lower-triangular factor, and
+    e = ||I - L||_F: b = 1 / (1 - e) when e < 1/2 (Neumann series), else
+    ||L^-1||_F."""
+    m = L.shape[0]
+    e = float(np.linalg.norm(np.eye(m) - L))
+    if e < 0.5:
+        return 1.0 / (1.0 - e), e
+    Li = sla.solve_triangular(L, np.eye(m), lower=True, check_finite=False)
+    return float(np.linalg.norm(Li)), e
+
+
 def ortho(
     X: np.ndarray,
     tau: float = TAU_ORTHO,
     stats: Optional[OrthoStats] = None,
     max_passes: int = ORTHO_MAX_PASSES,
     shift_retries: int = SHIFT_RETRIES,
+    cheap_exit: bool = False,
+    growth: Optional[dict] = None,
 ) -> np.ndarray:
     """Alg. 2: while ||X^T X - I|| > tau, factor M = X^T X = L L^T (shifting
     the diagonal when the factorisation fails) and set X <- X L^-T.  When
     the plain factorisation and all ``shift_retries`` shifted ones fail, the
-    pass uses SVQB instead (reading R5)."""
+    pass uses SVQB instead (reading R5).
+
+    ``cheap_exit`` (reading R17): after an unshifted factor with
+    e = ||I - L||_F < 1/2, kappa(L) <= (1 + e) / (1 - e) bounds the
+    conditioning the pass removed; when c(n) eps kappa^2 <= tau the new X is
+    taken as orthonormal without forming its overlap.  ``growth`` (a dict,
+    optional) receives "g": the amplification this call can apply to errors
+    in its input, 1 / (smallest input column norm) times the bound on
+    ||L^-1|| of every factor (infinite after an SVQB pass)."""
     st = stats if stats is not None else OrthoStats()
     st.ortho_calls += 1
+    n = X.shape[0]
+    cn = cheap_exit_factor(n)
+    norms0 = np.sqrt(np.einsum("ij,ij->j", X, X)) if X.shape[1] else np.ones(0)
+    g = (1.0 / float(norms0.min())) if X.shape[1] and norms0.min() > 0 else math.inf
     X = normalize_columns(X, st)
+    if growth is not None:
+        growth["g"] = g
     if X.shape[1] == 0:
         return X
     eye = np.eye(X.shape[1])
@@ -231,17 +276,29 @@ def ortho(
         M = 0.5 * (M + M.T)
         st.grams += 1
         if max_abs(M - eye) <= tau:
-            return X
+            break
         if p == max_passes - 1:
             st.stalled += 1
-            return X
+            break
+        shifted_before = st.shifted
         L = shifted_cholesky(M, st, shift_retries)
         if L is None:
             X = svqb(X, M, st)
-        else:
-            # X L^-T  ==  (L^-1 X^T)^T
-            X = sla.solve_triangular(L, X.T, lower=True, check_finite=False).T
+            g = math.inf
+            st.updates += 1
+            continue
+        # X L^-T  ==  (L^-1 X^T)^T
+        X = sla.solve_triangular(L, X.T, lower=True, check_finite=False).T
         st.updates += 1
+        b, e = inverse_factor_bound(L)
+        g *= b
+        if cheap_exit and st.shifted == shifted_before and e < 0.5:
+            kappa = (1.0 + e) / (1.0 - e)
+            if cn * EPS * kappa * kappa <= tau:
+                st.cheap_exits += 1
+                break
+    if growth is not None:
+        growth["g"] = g
     return X
 
 
@@ -252,19 +309,30 @@ def ortho_against(
     stats: Optional[OrthoStats] = None,
     max_passes: int = ORTHO_Y_MAX_PASSES,
     shift_retries: int = SHIFT_RETRIES,
+    cheap_exit: bool = False,
 ) -> np.ndarray:
     """Alg. 3 (reading R3): X <- X - Y (Y^T X); X <- ortho(X); repeat until
-    ||Y^T X|| <= tau.  Y must have orthonormal columns."""
+    ||Y^T X|| <= tau.  Y must have orthonormal columns.
+
+    ``cheap_exit`` (reading R17): the projection leaves a Y-component of
+    rounding size, which ortho(X) amplifies by at most its growth g; when
+    c(n) eps g <= tau the loop ends without forming Y^T X (and the Alg. 2
+    exits inside ortho apply)."""
     st = stats if stats is not None else OrthoStats()
     st.against_calls += 1
     X = normalize_columns(X, st)
     if Y is None or Y.shape[1] == 0:
-        return ortho(X, tau, st, shift_retries=shift_retries)
+        return ortho(X, tau, st, shift_retries=shift_retries, cheap_exit=cheap_exit)
+    cn = cheap_exit_factor(X.shape[0])
     C = Y.T @ X
     for p in range(max_passes):
         st.against_passes += 1
         X = X - Y @ C
-        X = ortho(X, tau, st, shift_retries=shift_retries)
+        gr = {}
+        X = ortho(X, tau, st, shift_retries=shift_retries, cheap_exit=cheap_exit, growth=gr)
+        if cheap_exit and cn * EPS * gr["g"] <= tau:
+            st.cheap_exits += 1
+            return X
         C = Y.T @ X
         if max_abs(C) <= tau:
             return X
@@ -334,6 +402,15 @@ def true_residuals(op: Operator, X: np.ndarray):
     theta = np.einsum("ij,ij->j", X, AX) / xx
     R = AX - X * theta
     return theta, np.linalg.norm(R, axis=0), AX
+
+
+def lowest_eigenpairs_dense(A: np.ndarray, k: int):
+    """The result the method approximates, by its plain definition (Sec. 2:
+    the k lowest eigenpairs of a symmetric matrix): LAPACK's dense symmetric
+    eigensolver restricted to eigenvalue indices 0..k-1 (syevr).  Returns
+    the ascending eigenvalues and orthonormal eigenvectors (n x k)."""
+    w, V = sla.eigh(A, subset_by_index=[0, k - 1], driver="evr", check_finite=False)
+    return w, V
 
 
 def normalize_signs(X: np.ndarray) -> np.ndarray:
@@ -424,6 +501,7 @@ def lobpcg(
     callback: Optional[Callable[[dict], None]] = None,
     shift_retries: int = SHIFT_RETRIES,
     force_restarts: int = 0,
+    cheap_exit: bool = False,
 ) -> LobpcgResult:
     """Alg. 1: the lowest k eigenpairs of the symmetric operator ``op``.
 
@@ -434,7 +512,9 @@ def lobpcg(
     ``shift_retries`` caps the shifted Cholesky retries of every ortho call
     (0 sends a failed factorisation straight to SVQB).  ``force_restarts``
     is a test hook: the first that many true-residual checks count as
-    failed, which drives the restart branch of reading R9."""
+    failed, which drives the restart branch of reading R9.  ``cheap_exit``
+    turns on reading R17's exits in the orthonormalisations of n-vectors
+    (X0, W, the re-orthonormalisation before a true check)."""
     X0 = np.asarray(X0, dtype=np.float64)
     n, m = X0.shape
     if not (1 <= k <= m):
@@ -458,7 +538,7 @@ def lobpcg(
         raise ValueError(precond)
 
     # Alg. 1 initial Rayleigh-Ritz (reading R2: orthonormalise X0 first)
-    X = ortho(X0, tau, st, shift_retries=shift_retries)
+    X = ortho(X0, tau, st, shift_retries=shift_retries, cheap_exit=cheap_exit)
     AX = op(X)
     matvecs += m
     theta_all, U = rayleigh_ritz(X, AX)
@@ -487,7 +567,7 @@ def lobpcg(
             # reading R9: re-orthonormalise X (Alg. 2; the implicit-P
             # recurrence lets X^T X drift from I by rounding), then judge with
             # the true residual of an explicit product
-            X = ortho(X, tau, st, shift_retries=shift_retries)
+            X = ortho(X, tau, st, shift_retries=shift_retries, cheap_exit=cheap_exit)
             true_checks += 1
             th_t, r_t, AX_t = true_residuals(op, X)
             matvecs += m
@@ -518,7 +598,7 @@ def lobpcg(
         # Alg. 1: preconditioned residuals, orthogonalised against (X, P)
         Wt = tprec(R[:, act], theta[act], X[:, act])
         Y = X if P is None else np.hstack([X, P])
-        W = ortho_against(Wt, Y, tau, st, shift_retries=shift_retries)
+        W = ortho_against(Wt, Y, tau, st, shift_retries=shift_retries, cheap_exit=cheap_exit)
         AW = op(W)
         matvecs += W.shape[1]
         hist_active.append(W.shape[1])
@@ -556,7 +636,7 @@ def lobpcg(
         X, AX = Xn, AXn
 
     if not converged:
-        X = ortho(X, tau, st, shift_retries=shift_retries)
+        X = ortho(X, tau, st, shift_retries=shift_retries, cheap_exit=cheap_exit)
         true_checks += 1
         th_t, r_t, AX_t = true_residuals(op, X)
     Rt = AX_t[:, :k] - X[:, :k] * th_t[:k]

@@ -604,3 +604,101 @@ def test_forced_restart_hook_matches_a_real_one():
     assert res.restarts == 1 and res.true_checks == 2
     assert res.converged
     assert_eigs(res, np.linalg.eigvalsh(A)[:4], tol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# the exact dense eigensolve that the full-size dense goldens come from
+
+
+def test_lowest_eigenpairs_dense_closed_forms():
+    # 1-D Laplacian: lambda_j = 2 - 2 cos(j pi / (n + 1)), j = 1..k
+    n, k = 300, 9
+    L = synth.laplacian_1d(n).to_dense()
+    w, V = O.lowest_eigenpairs_dense(L, k)
+    j = np.arange(1, k + 1)
+    assert np.allclose(w, 2 - 2 * np.cos(j * np.pi / (n + 1)), rtol=0, atol=1e-13)
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-13
+    # prescribed spectrum Q diag(lam) Q^T, with a cluster and a negative end
+    lam = np.concatenate([[-3.0, -1.0, -1.0 + 1e-9, 0.5], np.linspace(2.0, 9.0, 196)])
+    A, Q = synth.prescribed_spectrum(lam, 12)
+    w, V = O.lowest_eigenpairs_dense(A, 5)
+    assert np.allclose(w, lam[:5], rtol=0, atol=1e-13)
+    assert np.linalg.norm(A @ V - V * w, axis=0).max() < 1e-13
+
+
+def test_planted_eigh_off_by_one_index():
+    lam = np.linspace(1.0, 2.0, 50)
+    A, _ = synth.prescribed_spectrum(lam, 3)
+    w = sla.eigh(A, subset_by_index=[1, 4], eigvals_only=True)  # skips the lowest
+    with pytest.raises(AssertionError):
+        assert np.allclose(w, lam[:4], atol=1e-13)
+
+
+def subspace_sine(A, B):
+    """Sine of the largest principal angle between the column spaces of A
+    and B (equal dimensions), ||Q_B - Q_A Q_A^T Q_B||_2, for tall blocks."""
+    QA = np.linalg.qr(A)[0]
+    QB = np.linalg.qr(B)[0]
+    return float(np.linalg.norm(QB - QA @ (QA.T @ QB), 2))
+
+
+# ---------------------------------------------------------------------------
+# reading R17: cheap exits of Alg. 2 and Alg. 3 (Sec. 3.2 proposes a norm
+# estimate of L^-T and the growth factor of ortho(X); the exit rules are
+# this oracle's reading)
+
+
+@pytest.mark.parametrize("n", [20000, 200000])
+def test_cheap_exit_alg2(n):
+    I = np.eye(16)
+    for cond in (1.0 + 1e-3, 3.0, 1e3, 1e7):
+        X = graded(n, 16, cond, 3) * synth.rng(5).uniform(0.5, 2.0, 16)
+        st0, st1 = O.OrthoStats(), O.OrthoStats()
+        Q0 = O.ortho(X, stats=st0)
+        Q1 = O.ortho(X, stats=st1, cheap_exit=True)
+        assert O.max_abs(Q1.T @ Q1 - I) <= O.TAU_ORTHO, cond
+        assert subspace_sine(Q1, Q0) < 1e-13 * cond
+        assert st1.grams <= st0.grams and st1.updates == st0.updates
+        if cond == 1e3:
+            # Cholesky-QR twice, then the exit replaces the third overlap
+            assert st0.updates == 2 and st1.cheap_exits == 1 and st1.grams == st0.grams - 1
+
+
+def test_cheap_exit_alg3():
+    n = 100000
+    g = synth.rng(14)
+    Y = np.linalg.qr(g.standard_normal((n, 16)))[0]
+    exits = 0
+    for delta in (1e-1, 1e-4, 1e-10):
+        Xt = Y @ g.standard_normal((16, 8)) + delta * g.standard_normal((n, 8))
+        st0, st1 = O.OrthoStats(), O.OrthoStats()
+        Q0 = O.ortho_against(Xt, Y, stats=st0)
+        Q1 = O.ortho_against(Xt, Y, stats=st1, cheap_exit=True)
+        assert O.max_abs(Y.T @ Q1) <= O.TAU_ORTHO, delta
+        assert O.max_abs(Q1.T @ Q1 - np.eye(8)) <= O.TAU_ORTHO, delta
+        assert subspace_sine(np.hstack([Y, Q1]), np.hstack([Y, Q0])) < 1e-12 / delta
+        assert st1.against_passes <= st0.against_passes
+        exits += st1.cheap_exits
+    assert exits >= 3
+
+
+def test_planted_cheap_exit_ignoring_kappa(monkeypatch):
+    # an exit that trusts any unshifted pass (the bound on ||L^-1|| taken as
+    # 1 and ||I - L|| as 0) stops after one Cholesky-QR of a cond 1e3 block,
+    # whose orthogonality is only ~eps cond^2
+    monkeypatch.setattr(O, "inverse_factor_bound", lambda L: (1.0, 0.0))
+    Q = O.ortho(graded(20000, 16, 1e3, 3), cheap_exit=True)
+    assert O.max_abs(Q.T @ Q - np.eye(16)) > O.TAU_ORTHO
+
+
+def test_cheap_exit_solve_matches_eigh():
+    n, k = 600, 6
+    A = synth.dense_dd(n, seed=17)
+    lam = np.linalg.eigvalsh(A)[:k]
+    X0 = synth.start_block(n, k, 3)
+    r0 = O.lobpcg(O.dense_operator(A), X0, k, 1e-9, diag=np.diag(A).copy())
+    r1 = O.lobpcg(O.dense_operator(A), X0, k, 1e-9, diag=np.diag(A).copy(), cheap_exit=True)
+    assert_eigs(r1, lam, tol=1e-9)
+    assert O.max_abs(r1.X_all.T @ r1.X_all - np.eye(k)) < 1e-12
+    assert r1.ortho.cheap_exits > 0 and r1.ortho.grams < r0.ortho.grams
+    assert abs(r1.iterations - r0.iterations) <= 2
