@@ -85,6 +85,16 @@ typedef struct lobpcg_ctx* lobpcg_t;
                                          when they all fail the pass orthonormalises
                                          by SVQB (Stathopoulos-Wu).  0 sends every
                                          failed factorisation straight to SVQB */
+#define LOBPCG_OPT_CHEAP_EXIT 10      /* 1: cheap exits of the ortho loops (Sec. 3.2
+                                         proposes them after Alg. 2 and Alg. 3): an
+                                         unshifted factor L with e = ||I - L||_F < 1/2
+                                         and c(n) u ((1+e)/(1-e))^2 <= tau ends Alg. 2
+                                         without the overlap of the new block, and a
+                                         growth g of the Alg. 2 call (normalisation
+                                         scale times a bound on ||L^-1|| per factor)
+                                         with c(n) u g <= tau ends Alg. 3 without
+                                         Y^T X; c(n) = max(4, 0.02 sqrt(n)), u the
+                                         blocks' unit roundoff.  Default 0 */
 #define LOBPCG_OPT_FORCE_RESTARTS 9   /* test hook, default 0: the first N explicit
                                          true-residual checks of a solve count as
                                          failed, which drives the restart that a
@@ -120,11 +130,13 @@ typedef struct lobpcg_stats {
                                   tridiagonal path to Jacobi */
   int32_t restarts;            /* failed true-residual checks (each restarts the
                                   iteration from X with the explicit product) */
+  int32_t ortho_cheap_exits;   /* overlaps the cheap exits skipped */
 } lobpcg_stats;
 
 /* ---- ortho report for the step entry points ---------------------------- */
 typedef struct lobpcg_ortho_info {
   int32_t grams, factorizations, failed, shifted, updates, passes, stalled, svqb;
+  int32_t cheap_exits;  /* overlaps skipped by LOBPCG_OPT_CHEAP_EXIT */
 } lobpcg_ortho_info;
 
 /* ======================================================================== */

@@ -279,6 +279,7 @@ def ortho(
             break
         if p == max_passes - 1:
             st.stalled += 1
+            g = math.inf  # a stalled call gives no bound
             break
         shifted_before = st.shifted
         L = shifted_cholesky(M, st, shift_retries)

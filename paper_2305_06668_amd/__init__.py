@@ -57,6 +57,7 @@ OPT_LEARNED_BF16 = 6
 OPT_RR_JACOBI = 7
 OPT_SHIFT_RETRIES = 8
 OPT_FORCE_RESTARTS = 9
+OPT_CHEAP_EXIT = 10
 
 _i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -86,6 +87,7 @@ class lobpcg_stats(ctypes.Structure):
         ("learned_nonfinite", _i32),
         ("rr_eig_fallbacks", _i32),
         ("restarts", _i32),
+        ("ortho_cheap_exits", _i32),
     ]
 
     def as_dict(self) -> dict:
@@ -93,7 +95,10 @@ class lobpcg_stats(ctypes.Structure):
 
 
 class lobpcg_ortho_info(ctypes.Structure):
-    _fields_ = [(f, _i32) for f in ("grams", "factorizations", "failed", "shifted", "updates", "passes", "stalled", "svqb")]
+    _fields_ = [
+        (f, _i32)
+        for f in ("grams", "factorizations", "failed", "shifted", "updates", "passes", "stalled", "svqb", "cheap_exits")
+    ]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

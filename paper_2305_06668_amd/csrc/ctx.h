@@ -52,6 +52,7 @@ struct lobpcg_ctx {
   int rr_jacobi = 0;     // Rayleigh-Ritz eigensolver: 0 tridiagonal, 1 Jacobi
   int shift_retries = 20;  // shifted Cholesky retries before SVQB (ortho controller)
   int force_restarts = 0;  // test hook: true checks that count as failed
+  int cheap_exit = 0;      // cheap exits of the ortho loops
   int learned_bf16 = 1;  // learned preconditioner inference: layer 2 on bf16 MFMA
   // operator
   int op = lobpcg::kOpNone;

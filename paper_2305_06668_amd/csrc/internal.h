@@ -50,6 +50,15 @@ struct OrthoState {
   int shift_retries;  // shifted Cholesky attempts after a failed plain one, then SVQB
   int fold_scale;     // input: a final diagonal column scaling may be left pending
   int pending_scale;  // output: W must still be scaled by dscale (folded into the next RR)
+  // cheap exits (Sec. 3.2's estimates after Alg. 2 and Alg. 3): when set,
+  // a factor whose conditioning bound shows the pass already reached tau
+  // skips the overlap that would only confirm it
+  int cheap_exit;     // input: 0/1
+  int cheap_exits;    // overlaps skipped
+  int no_gram;        // the pending apply need not form the overlap
+  int skip_sum;       // done || no_gram: the overlap's second stage skips itself
+  double cexit;       // input: c(n) * unit roundoff of the block precision
+  double growth;      // amplification of errors by the current Alg. 2 call
   double tau;
   double dscale[kMaxBlock];
 };
@@ -188,8 +197,10 @@ hipError_t small_cholesky(const double* M, int p, double* L, int* info, hipStrea
 // One controller step of ortho(W; Y): reads G = [Y W]^T W ((ny+nw) x nw),
 // updates the state and writes the next coefficient ((ny+nw) x nw).
 hipError_t ortho_ctl(const double* G, OrthoState* st, double* coef, hipStream_t s);
+// cexit > 0 turns the cheap exits on (cexit = c(n) times the unit roundoff
+// of the blocks' precision).
 hipError_t ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner, int max_outer,
-                      int shift_retries, int fold_scale, hipStream_t s);
+                      int shift_retries, int fold_scale, double cexit, hipStream_t s);
 
 // ---- learned preconditioner (k_mlp.hip) ---------------------------------
 // In place: R[:, 0:nact] (n rows, leading dimension ld) <- learned

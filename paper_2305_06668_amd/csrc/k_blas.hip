@@ -409,7 +409,9 @@ __device__ __forceinline__ void stage_rows(const T* __restrict__ In, int64_t ld,
 //   part[block] = [Y W]^T W        (of the NEW W, per-block partial)
 // The new W rows are written back into the LDS tile so that the overlap is
 // accumulated with MFMA straight from LDS (K = 4 rows per MFMA).  Skips
-// itself when the controller has finished (st->done).
+// itself when the controller has finished (st->done), and the overlap when
+// the controller does not need it (st->no_gram: a cheap exit, or a final
+// diagonal scaling).
 
 template <typename T, int MTI, int MTJ>
 // 4 waves per SIMD for one column tile and up to 5 row tiles (fp64 136 -> 108
@@ -421,6 +423,7 @@ __global__ __launch_bounds__(256, (MTJ == 1 && MTI <= 5) ? 4 : 1) void k_ortho_a
   typedef typename AccOf<T>::type AccT;
   if (st->done) return;
   const int w_only = st->w_only;
+  const bool gram = st->no_gram == 0;  // the controller may not need the overlap
   const int nr = ny + nw;
   extern __shared__ double smem_d[];
   double* red = smem_d;                          // MTI * MTJ * 256 doubles
@@ -472,6 +475,7 @@ __global__ __launch_bounds__(256, (MTJ == 1 && MTI <= 5) ? 4 : 1) void k_ortho_a
         }
       }
     }
+    if (!gram) continue;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -491,6 +495,7 @@ __global__ __launch_bounds__(256, (MTJ == 1 && MTI <= 5) ? 4 : 1) void k_ortho_a
       }
     }
   }
+  if (!gram) return;
   // fixed-order reduction over the waves, then the block partial
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
@@ -534,7 +539,7 @@ static hipError_t ortho_apply_launch(T* base, int64_t ld, int ny, int nw, const 
                      coef, st, n, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return sum_parts(part, grid, nr * nw, G, &st->done, s);
+  return sum_parts(part, grid, nr * nw, G, &st->skip_sum, s);
 }
 
 template <typename T>

@@ -1273,7 +1273,28 @@ hipError_t small_cholesky(const double* M, int p, double* L, int* info, hipStrea
 //          coef = [-C; I] (scaled by the pending D) -> BEGIN
 //   FINAL  a pending diagonal scaling was applied: finished.
 
-enum { kPhFinal = 5 };
+enum { kPhFinal = 5, kPhYCheck = 6 };
+
+// Bound on ||L^-1||_2 for the n x n lower factor L (stride ldl) with its
+// inverse Li (stride ldi): 1 / (1 - e) when e = ||I - L||_F < 1/2 (Neumann
+// series), else ||Li||_F.  *e_out receives e.  Every thread gets the result.
+__device__ double blk_inv_bound(const double* L, int ldl, const double* Li, int ldi, int n,
+                                double* e_out, double* scratch) {
+  double se = 0.0, si = 0.0;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx - i * n;
+    if (j > i) continue;
+    const double d = (i == j ? 1.0 : 0.0) - L[i * ldl + j];
+    se += d * d;
+    const double v = Li[i * ldi + j];
+    si += v * v;
+  }
+  se = blk_reduce_sum_ordered(se, scratch);
+  si = blk_reduce_sum_ordered(si, scratch);
+  const double e = sqrt(se);
+  *e_out = e;
+  return (e < 0.5) ? 1.0 / (1.0 - e) : sqrt(si);
+}
 
 __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G,
                                                    OrthoState* __restrict__ gst,
@@ -1307,19 +1328,21 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
     if (!isfinite(v)) nonfinite = 1;
   }
   __syncthreads();
-  if (threadIdx.x == 0) st.grams++;
   if (st.state == kPhFinal) {
     if (threadIdx.x == 0) {
       st.done = 1;
+      st.skip_sum = 1;
       st.state = kPhDone;
       *gst = st;
     }
     return;
   }
+  if (threadIdx.x == 0) st.grams++;  // (a no-overlap apply only precedes kPhFinal)
   if (nonfinite) {
     if (threadIdx.x == 0) {
       st.error = kOrthoErrNonfinite;
       st.done = 1;
+      st.skip_sum = 1;
       *gst = st;
     }
     return;
@@ -1336,6 +1359,8 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
   // helper lambdas are avoided: explicit code per phase
   bool check_outer = false;
   bool have_scale = false;  // D pending (BEGIN passed its check)
+  bool capped = false;
+  double growth = st.growth;  // amplification of errors by the current Alg. 2 call
   if (phase == kPhStart || phase == kPhBegin) {
     for (int j = threadIdx.x; j < nw; j += blockDim.x) {
       const double d = Ms[j * ldm + j];
@@ -1348,6 +1373,7 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
         st.error = kOrthoErrZero;
         st.zero_mask = zero_mask;
         st.done = 1;
+        st.skip_sum = 1;
         *gst = st;
       }
       return;
@@ -1363,24 +1389,35 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
       st.passes++;
       st.outer = 1;
       st.w_only = 0;
+      st.no_gram = 0;
+      st.skip_sum = 0;
       st.state = kPhBegin;
       *gst = st;
     }
     return;
   }
   if (phase == kPhBegin) {
-    // M' = D M D, Alg. 2 check on the normalised X
+    // M' = D M D, Alg. 2 check on the normalised X; the normalisation is
+    // the first factor of this Alg. 2 call's growth
+    double dmax = 0.0;
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) dmax = fmax(dmax, D[j]);
+    growth = blk_reduce_max(dmax, scratch);
     for (int idx = threadIdx.x; idx < nw * nw; idx += blockDim.x) {
       const int i = idx / nw, j = idx - i * nw;
       Ms[i * ldm + j] *= D[i] * D[j];
     }
     if (threadIdx.x == 0) st.inner = 1;
     __syncthreads();
-  } else if (phase == kPhLoop) {
-    if (threadIdx.x == 0) st.inner++;
+  } else if (phase == kPhLoop || phase == kPhYCheck) {
+    if (threadIdx.x == 0 && phase == kPhLoop) st.inner++;
     for (int j = threadIdx.x; j < nw; j += blockDim.x) D[j] = 1.0;
     __syncthreads();
   }
+  if (phase == kPhYCheck) {
+    // a cheap exit ended Alg. 2 with the last update; only the Alg. 3
+    // check of Y^T W (in the overlap that update formed) remains
+    check_outer = true;
+  } else {
   double dev = 0.0;
   for (int idx = threadIdx.x; idx < nw * nw; idx += blockDim.x) {
     const int i = idx / nw, j = idx - i * nw;
@@ -1388,7 +1425,7 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
   }
   dev = blk_reduce_max(dev, scratch);
   const bool ortho_ok = dev <= st.tau;
-  const bool capped = !ortho_ok && st.inner >= st.max_inner;
+  capped = !ortho_ok && st.inner >= st.max_inner;
   if (ortho_ok || capped) {
     if (capped && threadIdx.x == 0) st.stalled++;
     check_outer = true;
@@ -1403,6 +1440,32 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
         const int i = idx / nw, j = idx - i * nw;
         coef[idx] = (i < ny) ? 0.0 : D[i - ny] * Li[j * ldm + (i - ny)];
       }
+      // cheap exits: e = ||I - L||_F bounds kappa(L) <= (1 + e) / (1 - e)
+      // and ||L^-1||; when the pass provably reached tau the overlap of the
+      // new W is not formed (Alg. 2), and when the growth of the whole
+      // Alg. 2 call also keeps Y^T W below tau, neither is Y^T W (Alg. 3)
+      double e = 1.0;
+      const double b = blk_inv_bound(Ls, ldm, Li, ldm, nw, &e, scratch);
+      growth *= b;
+      const double kap = (1.0 + e) / (1.0 - e);
+      const bool exit2 = st.cheap_exit && cnt.shifted == 0 && e < 0.5 &&
+                         st.cexit * kap * kap <= st.tau;
+      const bool exit3 = exit2 && (ny == 0 || st.cexit * growth <= st.tau);
+      if (threadIdx.x == 0) {
+        st.factorizations += cnt.factorizations;
+        st.failed += cnt.failed;
+        st.shifted += cnt.shifted;
+        st.svqb += cnt.svqb;
+        st.updates++;
+        st.w_only = 1;
+        st.growth = growth;
+        if (exit2) st.cheap_exits += (exit3 && ny > 0) ? 2 : 1;
+        st.no_gram = exit3 ? 1 : 0;
+        st.skip_sum = st.no_gram;
+        st.state = exit3 ? kPhFinal : (exit2 ? kPhYCheck : kPhLoop);
+        *gst = st;
+      }
+      return;
     } else {
       if (threadIdx.x == 0) cnt.svqb++;
       const bool sv = blk_svqb_coef(Ms, ldm, nw, Li, ldm, Ws, cs, pr, &flag, perm, scratch);
@@ -1410,6 +1473,7 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
         if (threadIdx.x == 0) {
           st.error = kOrthoErrFailed;
           st.done = 1;
+          st.skip_sum = 1;
           st.factorizations += cnt.factorizations;
           st.failed += cnt.failed;
           *gst = st;
@@ -1428,19 +1492,28 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
       st.svqb += cnt.svqb;
       st.updates++;
       st.w_only = 1;
+      st.growth = INFINITY;  // SVQB: no growth bound, no cheap exit
+      st.no_gram = 0;
+      st.skip_sum = 0;
       st.state = kPhLoop;
       *gst = st;
     }
     return;
   }
-  // Alg. 3 check on C D (D = 1 unless BEGIN's normalisation is pending)
+  }
+  // Alg. 3: the growth of the finished Alg. 2 call may already bound Y^T W
+  // below tau (cheap exit); else check C D (D = 1 unless BEGIN's
+  // normalisation is pending)
+  const bool grow_ok = st.cheap_exit && ny > 0 && !capped && phase != kPhYCheck &&
+                       st.cexit * growth <= st.tau;
   double cm = 0.0;
   for (int idx = threadIdx.x; idx < ny * nw; idx += blockDim.x) {
     const int j = idx % nw;
     cm = fmax(cm, fabs(Gs[idx] * D[j]));
   }
   cm = blk_reduce_max(cm, scratch);
-  const bool y_ok = (ny == 0) || (cm <= st.tau);
+  if (grow_ok && threadIdx.x == 0) st.cheap_exits++;
+  const bool y_ok = (ny == 0) || grow_ok || (cm <= st.tau);
   if (y_ok || st.outer >= st.max_outer) {
     if (!y_ok && threadIdx.x == 0) st.stalled++;
     if (have_scale && st.fold_scale) {
@@ -1450,6 +1523,7 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
         for (int j = 0; j < nw; ++j) st.dscale[j] = D[j];
         st.pending_scale = 1;
         st.done = 1;
+        st.skip_sum = 1;
         st.state = kPhDone;
         *gst = st;
       }
@@ -1461,11 +1535,14 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
       }
       if (threadIdx.x == 0) {
         st.w_only = 1;
+        st.no_gram = 1;  // the next round only finishes
+        st.skip_sum = 1;
         st.state = kPhFinal;
         *gst = st;
       }
     } else if (threadIdx.x == 0) {
       st.done = 1;
+      st.skip_sum = 1;
       st.state = kPhDone;
       *gst = st;
     }
@@ -1480,13 +1557,15 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
     st.passes++;
     st.outer++;
     st.w_only = 0;
+    st.no_gram = 0;
+    st.skip_sum = 0;
     st.state = kPhBegin;
     *gst = st;
   }
 }
 
 __global__ void k_ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner,
-                             int max_outer, int shift_retries, int fold_scale) {
+                             int max_outer, int shift_retries, int fold_scale, double cexit) {
   OrthoState s;
   s.state = kPhStart;
   s.done = 0;
@@ -1503,17 +1582,23 @@ __global__ void k_ortho_init(OrthoState* st, int ny, int nw, double tau, int max
   s.shift_retries = shift_retries;
   s.fold_scale = fold_scale;
   s.pending_scale = 0;
+  s.cheap_exit = cexit > 0.0 ? 1 : 0;
+  s.cheap_exits = 0;
+  s.no_gram = 0;
+  s.skip_sum = 0;
+  s.cexit = cexit;
+  s.growth = INFINITY;
   s.tau = tau;
   for (int j = 0; j < kMaxBlock; ++j) s.dscale[j] = 1.0;
   *st = s;
 }
 
 hipError_t ortho_init(OrthoState* st, int ny, int nw, double tau, int max_inner, int max_outer,
-                      int shift_retries, int fold_scale, hipStream_t s) {
+                      int shift_retries, int fold_scale, double cexit, hipStream_t s) {
   if (nw < 1 || nw > kMaxBlock || ny < 0 || ny + nw > kMaxP || shift_retries < 0)
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ortho_init, dim3(1), dim3(1), 0, s, st, ny, nw, tau, max_inner, max_outer,
-                     shift_retries, fold_scale);
+                     shift_retries, fold_scale, cexit);
   return hipGetLastError();
 }
 

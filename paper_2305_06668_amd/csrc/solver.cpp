@@ -327,8 +327,12 @@ int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info
   const int nr = ny + nw;
   const double t = (tau_run > 0.0) ? tau_run : tau;
   for (int attempt = 0; attempt < 3; ++attempt) {
+    // cheap exits: c(n) times the unit roundoff of the blocks' precision
+    const double unit = (sizeof(T) == sizeof(float)) ? 0x1.0p-23 : 0x1.0p-52;
+    const double cexit =
+        cheap_exit ? std::max(4.0, 0.02 * std::sqrt((double)n)) * unit : 0.0;
     HIPCHK(ortho_init(st, ny, nw, t, ortho_max_inner, ortho_max_outer, shift_retries, fold ? 1 : 0,
-                      stream));
+                      cexit, stream));
     // the overlap [Y W~]^T W~ of the raw W~, by its own kernel: fused into
     // the rotation it held the rotation at two waves per SIMD (fp64), which
     // cost more than the separate pass (434 us against 328 + 91 us per
@@ -359,7 +363,9 @@ int lobpcg_ctx::ortho_run(T* base, int64_t ld, int ny, int nw, lobpcg_ortho_info
     stats.ortho_stalled += s.stalled;
     stats.ortho_svqb += s.svqb;
     stats.against_passes += s.passes;
+    stats.ortho_cheap_exits += s.cheap_exits;
     if (info != nullptr) {
+      info->cheap_exits += s.cheap_exits;
       info->grams += s.grams;
       info->factorizations += s.factorizations;
       info->failed += s.failed;
@@ -807,6 +813,9 @@ int lobpcg_set_option(lobpcg_t h, int key, double v) {
       if (v < 0 || v > 20 || v != (int)v)
         return h->fail(LOBPCG_ERR_INVALID_ARG, "shift retries must be an integer in [0, 20]");
       h->shift_retries = (int)v;
+      return LOBPCG_OK;
+    case LOBPCG_OPT_CHEAP_EXIT:
+      h->cheap_exit = (v != 0.0);
       return LOBPCG_OK;
     case LOBPCG_OPT_FORCE_RESTARTS:
       if (v < 0 || v > 100 || v != (int)v)

@@ -390,3 +390,46 @@ def test_host_column_major_abi(P):
     assert np.array_equal(X0h, r0.evecs.cpu().numpy()) and np.array_equal(X0h, X1h)
     lam = np.linalg.eigvalsh(A)[:k]
     assert np.all(np.abs(ev0 - lam) <= 1e-9 * np.abs(lam))
+
+
+@pytest.mark.parametrize("case", ["dense", "csr"])
+def test_cheap_exit_solve_vs_oracle(P, case):
+    """Full solves with the cheap exits of the ortho loops: the eigenpair
+    bar against the oracle (which takes the same exits), fewer overlaps
+    than without them."""
+    say("cheap exit solve", case)
+    if case == "dense":
+        n, k = 2000, 4
+        A = synth.dense_dd(n)
+        op = O.dense_operator(A)
+        diag = np.diag(A).copy()
+        setop = lambda s: s.set_operator_dense(cu(A))
+        lam = np.linalg.eigvalsh(A)[:k]
+        normA = abs(lam).max() + 100
+    else:
+        n, k = 20000, 8
+        C = synth.csr_banded(n=n, seed=21, band=600, diag_slope=10.0 / n)
+        op = O.csr_operator(C.row_ptr, C.col, C.val, n)
+        diag = C.diag
+        setop = lambda s: s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val))
+        lam = None
+        normA = 11.0
+    X0 = synth.start_block(n, k, 5)
+    out = {}
+    for ce in (0, 1):
+        s = P.Solver(n)
+        setop(s)
+        s.set_preconditioner(P.PRECOND_DIAG)
+        s.set_option(P.OPT_CHEAP_EXIT, ce)
+        s.set_initial_guess(cu(X0))
+        res = s.solve(k, 1e-9)
+        res.evecs_np = res.evecs.cpu().numpy()
+        out[ce] = res
+    ora = O.lobpcg(op, X0, k, 1e-9, diag=diag, cheap_exit=True)
+    r0, r1 = out[0], out[1]
+    say(r0.stats["ortho_grams"], r1.stats["ortho_grams"], r1.stats["ortho_cheap_exits"], "iters", r0.stats["iterations"],
+        r1.stats["iterations"], "oracle", ora.iterations, ora.ortho.cheap_exits)
+    check_pairs(r1, op, lam if lam is not None else ora.evals, 1e-9, normA=normA)
+    assert r1.stats["ortho_cheap_exits"] > 0 and ora.ortho.cheap_exits > 0
+    assert r1.stats["ortho_grams"] < r0.stats["ortho_grams"]
+    assert abs(r1.stats["iterations"] - ora.iterations) <= max(3, 0.1 * ora.iterations)

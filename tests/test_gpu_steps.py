@@ -259,6 +259,58 @@ def test_ortho_vs_oracle(P, n, m, cond):
     assert info["stalled"] == 0
 
 
+@pytest.mark.parametrize("n,m,cond", [(20011, 16, 1e3), (200003, 16, 1.001), (5000, 8, 1e5), (3001, 32, 10.0)])
+def test_ortho_cheap_exit_vs_oracle(P, n, m, cond):
+    """Cheap exit of Alg. 2 (the ||L^-T|| estimate Sec. 3.2 proposes): the
+    GPU takes the oracle's decisions (same overlaps formed, same exits) and
+    gives its Q; the overlap it skips would only have confirmed tau."""
+    say("ortho cheap exit", n, m, cond)
+    X = graded(n, m, cond, 3) * synth.rng(4).uniform(0.5, 10, m)
+    s = make_solver(P, n)
+    P.lobpcg_set_option(s.h, P.OPT_CHEAP_EXIT, 1)
+    Xd = cu(X)
+    info = P.lobpcg_ortho(s.h, Xd)
+    Q = host(Xd)
+    st = O.OrthoStats()
+    Qo = O.ortho(X, stats=st, cheap_exit=True)
+    say(info, st)
+    assert np.abs(Q.T @ Q - np.eye(m)).max() <= 1e-14
+    assert np.abs(Q - Qo).max() <= 1e-15 * cond * 50
+    assert info["cheap_exits"] == st.cheap_exits and info["grams"] == st.grams
+    assert info["updates"] == st.updates and info["stalled"] == 0
+    # the same call without the exit forms one overlap more when it exits
+    s2 = make_solver(P, n)
+    Xd = cu(X)
+    info0 = P.lobpcg_ortho(s2.h, Xd)
+    assert info0["cheap_exits"] == 0 and info0["grams"] == info["grams"] + info["cheap_exits"]
+
+
+@pytest.mark.parametrize("delta", [1e-1, 1e-4, 1e-9])
+def test_ortho_against_cheap_exit_vs_oracle(P, delta):
+    """Cheap exit of Alg. 3 (the growth factor of ortho(X)): Y^T W is not
+    formed once the growth of the last Alg. 2 call bounds it below tau."""
+    g = synth.rng(21)
+    n, ny, nw = 100003, 16, 8
+    Y = np.linalg.qr(g.standard_normal((n, ny)))[0]
+    Xt = Y @ g.standard_normal((ny, nw)) + delta * g.standard_normal((n, nw))
+    buf = cu(np.hstack([Y, Xt]))
+    s = make_solver(P, n)
+    P.lobpcg_set_option(s.h, P.OPT_CHEAP_EXIT, 1)
+    info = P.lobpcg_ortho_against(s.h, buf[:, ny:], buf[:, :ny])
+    out = host(buf)
+    Q = out[:, ny:]
+    st = O.OrthoStats()
+    Qo = O.ortho_against(Xt, Y, stats=st, cheap_exit=True)
+    say(delta, info, st)
+    assert np.abs(Y.T @ Q).max() <= 1e-14
+    assert np.abs(Q.T @ Q - np.eye(nw)).max() <= 1e-14
+    assert info["cheap_exits"] >= 1 and st.cheap_exits >= 1
+    assert info["passes"] == st.against_passes
+    Qa = np.linalg.qr(np.hstack([Y, Q]))[0]
+    Qb = np.linalg.qr(np.hstack([Y, Qo]))[0]
+    assert np.linalg.norm(Qb - Qa @ (Qa.T @ Qb), 2) < 1e-12 / delta
+
+
 def test_ortho_forced_shift(P):
     g = synth.rng(5)
     n = 800
