@@ -660,3 +660,132 @@ def lobpcg(
         restarts=restarts,
     )
     return res
+
+
+# ---------------------------------------------------------------------------
+# Block Davidson with a history (Sec. 2, the recurrence X^{k+1} = RR(X^1,
+# T^1 R^1, ..., T^k R^k); Sec. 4 runs it with 25 vectors per root and
+# locking).  Reading R18: the history is truncated by a restart from the
+# current Ritz vectors when adding the next block would exceed
+# ``max_dim`` columns; every block is made orthonormal to the basis with
+# Alg. 3; convergence, locking and the true-residual judgement are those of
+# the LOBPCG above (R8, R9).
+
+
+@dataclasses.dataclass
+class DavidsonResult:
+    evals: np.ndarray
+    evecs: np.ndarray
+    resnorms: np.ndarray
+    converged: bool
+    iterations: int
+    matvec_columns: int
+    restarts: int  # history truncations
+    max_basis: int  # largest basis size reached
+    true_checks: int
+    ortho: OrthoStats
+    history_theta: list
+    X_all: np.ndarray = None
+
+
+def davidson(
+    op: Operator,
+    X0: np.ndarray,
+    k: int,
+    tol: float = 1e-8,
+    diag: Optional[np.ndarray] = None,
+    precond="diag",
+    max_dim: Optional[int] = None,
+    tau: float = TAU_ORTHO,
+    max_iter: int = 1000,
+) -> DavidsonResult:
+    """Block Davidson for the lowest k eigenpairs of ``op`` (Sec. 2): the
+    basis holds X^{[1]} and every preconditioned residual block since the
+    last restart.  ``max_dim`` defaults to 25 m (Sec. 4's subspace of 25 per
+    root).  The preconditioners are those of ``lobpcg``."""
+    X0 = np.asarray(X0, dtype=np.float64)
+    n, m = X0.shape
+    if not (1 <= k <= m):
+        raise ValueError("need 1 <= k <= block size")
+    if max_dim is None:
+        max_dim = 25 * m
+    if max_dim < 2 * m:
+        raise ValueError("max_dim must hold the Ritz block and one new block")
+    st = OrthoStats()
+    hist_theta = []
+    V = ortho(X0, tau, st)
+    AV = op(V)
+    matvecs = m
+    true_checks = 0
+    restarts = 0
+    max_basis = m
+    m_conv = 0
+    it = 0
+    converged = False
+
+    def tprec(R, theta):
+        if precond == "diag":
+            return precondition_diag(R, diag, theta)
+        if precond == "diag_signed":
+            return precondition_diag(R, diag, theta, signed=True)
+        if precond == "none":
+            return R.copy()
+        return np.asarray(precond(R, theta, None), dtype=np.float64)
+
+    while True:
+        # Rayleigh-Ritz on the whole basis (R10, R16)
+        theta_all, U = rayleigh_ritz(V, AV)
+        ux = U[:, :m]
+        theta = theta_all[:m]
+        X = V @ ux
+        AX = AV @ ux
+        R = ritz_residual(AX, X, theta)
+        rnorm = np.linalg.norm(R, axis=0)
+        hist_theta.append(theta.copy())
+        m_conv = max(m_conv, leading_converged(rnorm, tol))
+        if m_conv >= k:
+            X = ortho(X, tau, st)
+            true_checks += 1
+            th_t, r_t, AX_t = true_residuals(op, X)
+            matvecs += m
+            if float(np.max(r_t[:k])) <= tol:
+                converged = True
+                break
+            # restart from X with the explicit product (as in R9)
+            V, AV = X, AX_t
+            m_conv = 0
+            restarts += 1
+            continue
+        if it >= max_iter:
+            break
+        it += 1
+        act = np.arange(m_conv, m)
+        Wt = tprec(R[:, act], theta[act])
+        if V.shape[1] + act.size > max_dim:
+            # history truncation: restart from the current Ritz vectors
+            V, AV = X, AX
+            restarts += 1
+        W = ortho_against(Wt, V, tau, st)
+        AW = op(W)
+        matvecs += W.shape[1]
+        V = np.hstack([V, W])
+        AV = np.hstack([AV, AW])
+        max_basis = max(max_basis, V.shape[1])
+    if not converged:
+        X = ortho(X, tau, st)
+        true_checks += 1
+        th_t, r_t, AX_t = true_residuals(op, X)
+    return DavidsonResult(
+        evals=th_t[:k].copy(),
+        evecs=normalize_signs(X[:, :k]),
+        resnorms=r_t[:k].copy(),
+        converged=converged,
+        iterations=it,
+        matvec_columns=matvecs,
+        restarts=restarts,
+        max_basis=max_basis,
+        true_checks=true_checks,
+        ortho=st,
+        history_theta=hist_theta,
+        X_all=X,
+    )

@@ -702,3 +702,81 @@ def test_cheap_exit_solve_matches_eigh():
     assert O.max_abs(r1.X_all.T @ r1.X_all - np.eye(k)) < 1e-12
     assert r1.ortho.cheap_exits > 0 and r1.ortho.grams < r0.ortho.grams
     assert abs(r1.iterations - r0.iterations) <= 2
+
+
+# ---------------------------------------------------------------------------
+# block Davidson (Sec. 2's recurrence, Sec. 4's history; reading R18)
+
+
+def _davidson_by_definition(A, X0, steps, diag):
+    """X^{j+1} = RR(X^1, T^1 R^1, ..., T^j R^j) written out directly: the
+    span of the blocks by Householder QR, the RR by eigh, no locking."""
+    m = X0.shape[1]
+    Q = np.linalg.qr(X0)[0]
+    th, U = np.linalg.eigh(Q.T @ A @ Q)
+    X = Q @ U[:, :m]
+    blocks = [X]
+    out = [th[:m]]
+    for _ in range(steps):
+        th_x = out[-1]
+        R = A @ X - X * th_x
+        den = np.abs(diag[:, None] - th_x[None, :])
+        den = np.maximum(den, O.PRECOND_GUARD * np.maximum(1.0, np.abs(th_x)))
+        blocks.append(R / den)
+        Q = np.linalg.qr(np.hstack(blocks))[0]
+        th, U = np.linalg.eigh(Q.T @ A @ Q)
+        X = Q @ U[:, :m]
+        out.append(th[:m])
+    return out
+
+
+def test_davidson_is_rr_on_the_history():
+    n, m = 300, 3
+    A = synth.dense_dd(n, seed=41)
+    X0 = synth.start_block(n, m, 5)
+    d = np.diag(A).copy()
+    res = O.davidson(O.dense_operator(A), X0, m, 1e-30, diag=d, max_iter=4)
+    ref = _davidson_by_definition(A, X0, 4, d)
+    assert res.restarts == 0 and res.max_basis == 5 * m
+    # the two roundings (Cholesky-QR of the growing basis vs Householder QR
+    # of the stacked blocks) separate to ~1e-12 relative over the steps,
+    # since each step's residuals carry the previous step's rounding
+    for j in range(5):
+        assert np.allclose(res.history_theta[j], ref[j], rtol=1e-10, atol=0), j
+    # the subspace only grows between restarts: Ritz values never increase
+    H = np.array(res.history_theta)
+    assert np.all(np.diff(H, axis=0) <= 1e-13)
+
+
+@pytest.mark.parametrize("max_dim", [8, 24, None])
+def test_davidson_vs_eigh(max_dim):
+    n, k = 600, 4
+    A = synth.dense_dd(n, seed=2)
+    lam = np.linalg.eigvalsh(A)[:k]
+    res = O.davidson(O.dense_operator(A), synth.start_block(n, k, 3), k, 1e-9, diag=np.diag(A).copy(), max_dim=max_dim)
+    assert_eigs(res, lam, tol=1e-9)
+    assert O.max_abs(res.X_all.T @ res.X_all - np.eye(k)) < 1e-12
+    if max_dim == 8:
+        assert res.restarts > 0 and res.max_basis <= 8
+
+
+def test_davidson_closed_form_laplacian():
+    n, k = 150, 3
+    L = synth.laplacian_1d(n)
+    op = O.csr_operator(L.row_ptr, L.col, L.val, n)
+    res = O.davidson(op, synth.start_block(n, 5, 1), k, 1e-9, diag=L.diag, max_dim=40, max_iter=3000)
+    j = np.arange(1, k + 1)
+    assert_eigs(res, 2 - 2 * np.cos(j * np.pi / (n + 1)), tol=1e-9)
+
+
+def test_planted_davidson_without_projection(monkeypatch):
+    # each new block orthonormalised only among itself (no Alg. 3 against
+    # the basis): the basis stops being orthonormal and the standard RR on it
+    # goes wrong
+    monkeypatch.setattr(O, "ortho_against", lambda X, Y, tau=O.TAU_ORTHO, stats=None, **kw: O.ortho(X, tau, stats))
+    n, m = 300, 3
+    A = synth.dense_dd(n, seed=41)
+    X0 = synth.start_block(n, m, 5)
+    res = O.davidson(O.dense_operator(A), X0, m, 1e-30, diag=np.diag(A).copy(), max_iter=4)
+    ref = _davidson_by_definition(A, X0, 4, np.diag(A).copy())
+    assert not all(np.allclose(res.history_theta[j], ref[j], rtol=1e-10, atol=0) for j in range(5))
