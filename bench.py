@@ -340,7 +340,8 @@ def main():
 
     def timed(variant, cheap_exit=0):
         """Warm-up solves, then `steps` timed solves between synchronisations."""
-        s.set_option(P.OPT_PRECISION, P.PREC_FP64 if variant == "plain" else P.PREC_FP32)
+        s.set_option(P.OPT_METHOD, P.METHOD_DAVIDSON if variant == "davidson" else P.METHOD_LOBPCG)
+        s.set_option(P.OPT_PRECISION, P.PREC_FP64 if variant in ("plain", "davidson") else P.PREC_FP32)
         s.set_preconditioner(P.PRECOND_LEARNED if variant == "learned+mixed" else P.PRECOND_DIAG)
         s.set_option(P.OPT_CHEAP_EXIT, cheap_exit)
         for w in range(args.warmup):
@@ -361,6 +362,7 @@ def main():
 
     t_plain, res_plain = timed("plain")
     t_plain_ce, res_plain_ce = timed("plain", cheap_exit=1)
+    t_dav, res_dav = timed("davidson")
     t_mixed, res_mixed = timed("mixed")
     t_lm, res_lm = timed("learned+mixed")
     # headline: learned preconditioner + mixed precision
@@ -441,6 +443,18 @@ def main():
             "dtype_note": "learned+mixed runs phase 1 in fp32 (operator, Grams, blocks) and phase 2 in "
             "fp64 to tolerance; every small dense kernel is fp64; the plain line is fp64 throughout",
             "eigenvalue_error_vs_oracle": eig_err,
+            "davidson": {
+                "note": "block Davidson (fp64, Jacobi) on the same matrix and start block; history of "
+                f"{res_dav.stats['max_basis']} columns (the Rayleigh-Ritz kernels' limit), truncated by "
+                "restarts from the Ritz vectors",
+                **per_iter(res_dav, t_dav),
+                "matvec_columns": res_dav.stats["matvec_columns"],
+                "history_restarts": res_dav.stats["history_restarts"],
+                "basis_columns": res_dav.stats["max_basis"],
+                "lobpcg_basis_columns": 3 * k,
+                "lobpcg_matvec_columns": res_plain.stats["matvec_columns"],
+                "eigenvalue_error_vs_oracle": golden_errors(res_dav.evals, golden) if golden else None,
+            },
             "cheap_exit": {
                 "note": "plain fp64 solve with and without the cheap exits of the ortho loops",
                 "off": per_iter(res_plain, t_plain),

@@ -66,6 +66,16 @@ typedef struct lobpcg_ctx* lobpcg_t;
 #define LOBPCG_PREC_FP32 1 /* operator, Grams and blocks in fp32 until the
                               residual nears the fp32 floor, then fp64 */
 
+/* ---- methods ------------------------------------------------------------ */
+#define LOBPCG_METHOD_LOBPCG 0   /* Alg. 1 (default) */
+#define LOBPCG_METHOD_DAVIDSON 1 /* block Davidson with a history (Sec. 2: X^{k+1} =
+                                    RR(X^1, T^1 R^1, ..., T^k R^k); Sec. 4 compares it
+                                    with LOBPCG): each active preconditioned residual
+                                    block is made orthonormal to the basis by Alg. 3 and
+                                    appended; Rayleigh-Ritz runs on the whole basis;
+                                    locking and the true-residual test as for LOBPCG.
+                                    fp64 with the Jacobi preconditioners only. */
+
 /* ---- option keys for lobpcg_set_option --------------------------------- */
 #define LOBPCG_OPT_TAU_ORTHO 0        /* ortho threshold, default 1e-14 (Sec. 4) */
 #define LOBPCG_OPT_MAX_ITER 1         /* default 1000 */
@@ -95,6 +105,12 @@ typedef struct lobpcg_ctx* lobpcg_t;
                                          with c(n) u g <= tau ends Alg. 3 without
                                          Y^T X; c(n) = max(4, 0.02 sqrt(n)), u the
                                          blocks' unit roundoff.  Default 0 */
+#define LOBPCG_OPT_METHOD 11          /* LOBPCG_METHOD_*, default LOBPCG */
+#define LOBPCG_OPT_DAVIDSON_MAX_DIM 12 /* block Davidson: largest basis (columns) before
+                                          its history is truncated by a restart from the
+                                          current Ritz vectors; 0 (default) = min(25 m,
+                                          96) (Sec. 4 keeps 25 vectors per root; 96 is the
+                                          library's Rayleigh-Ritz limit); 2 m .. 96 */
 #define LOBPCG_OPT_FORCE_RESTARTS 9   /* test hook, default 0: the first N explicit
                                          true-residual checks of a solve count as
                                          failed, which drives the restart that a
@@ -131,6 +147,8 @@ typedef struct lobpcg_stats {
   int32_t restarts;            /* failed true-residual checks (each restarts the
                                   iteration from X with the explicit product) */
   int32_t ortho_cheap_exits;   /* overlaps the cheap exits skipped */
+  int32_t history_restarts;    /* block Davidson: history truncations */
+  int32_t max_basis;           /* block Davidson: largest basis reached (columns) */
 } lobpcg_stats;
 
 /* ---- ortho report for the step entry points ---------------------------- */

@@ -683,6 +683,7 @@ class DavidsonResult:
     restarts: int  # history truncations
     max_basis: int  # largest basis size reached
     true_checks: int
+    check_restarts: int  # failed true-residual checks (R9)
     ortho: OrthoStats
     history_theta: list
     X_all: np.ndarray = None
@@ -722,6 +723,8 @@ def davidson(
     m_conv = 0
     it = 0
     converged = False
+    just_restarted = False
+    check_restarts = 0
 
     def tprec(R, theta):
         if precond == "diag":
@@ -742,7 +745,10 @@ def davidson(
         R = ritz_residual(AX, X, theta)
         rnorm = np.linalg.norm(R, axis=0)
         hist_theta.append(theta.copy())
-        m_conv = max(m_conv, leading_converged(rnorm, tol))
+        lead = leading_converged(rnorm, tol)
+        # R9's rule after a restart: one iteration with at most k - 1 locked
+        m_conv = min(max(m_conv, lead), k - 1) if just_restarted else max(m_conv, lead)
+        just_restarted = False
         if m_conv >= k:
             X = ortho(X, tau, st)
             true_checks += 1
@@ -754,7 +760,8 @@ def davidson(
             # restart from X with the explicit product (as in R9)
             V, AV = X, AX_t
             m_conv = 0
-            restarts += 1
+            check_restarts += 1
+            just_restarted = True
             continue
         if it >= max_iter:
             break
@@ -785,6 +792,7 @@ def davidson(
         restarts=restarts,
         max_basis=max_basis,
         true_checks=true_checks,
+        check_restarts=check_restarts,
         ortho=st,
         history_theta=hist_theta,
         X_all=X,

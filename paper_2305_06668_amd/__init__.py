@@ -58,6 +58,11 @@ OPT_RR_JACOBI = 7
 OPT_SHIFT_RETRIES = 8
 OPT_FORCE_RESTARTS = 9
 OPT_CHEAP_EXIT = 10
+OPT_METHOD = 11
+OPT_DAVIDSON_MAX_DIM = 12
+
+METHOD_LOBPCG = 0
+METHOD_DAVIDSON = 1
 
 _i32, _i64, _dbl, _vp, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -88,6 +93,8 @@ class lobpcg_stats(ctypes.Structure):
         ("rr_eig_fallbacks", _i32),
         ("restarts", _i32),
         ("ortho_cheap_exits", _i32),
+        ("history_restarts", _i32),
+        ("max_basis", _i32),
     ]
 
     def as_dict(self) -> dict:
@@ -639,8 +646,9 @@ class Solver:
         lobpcg_set_option(self.h, key, value)
         if key == OPT_PRECISION:
             self._prec = int(value)
-            if self._block is not None:
-                self.ensure_workspace(self._block)  # the fp32 phase needs more workspace
+        if key in (OPT_PRECISION, OPT_METHOD, OPT_DAVIDSON_MAX_DIM) and self._block is not None:
+            # the fp32 phase and the Davidson basis need other workspace sizes
+            self.ensure_workspace(self._block)
 
     def set_initial_guess(self, X0):
         self._keep["X0"] = X0

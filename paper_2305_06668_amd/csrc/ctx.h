@@ -29,6 +29,7 @@ enum OpKind { kOpNone = 0, kOpCsr = 1, kOpDense = 2, kOpKron = 3 };
 struct Layout {
   size_t V[2], AV[2], diag, rho, ltiles, part, small, total;
   size_t kpack = 0;  // dense / Kronecker operator: n x 8 packed copy of a W block
+  size_t dscr = 0;   // block Davidson: n x m scratch for the explicit product A X
   size_t V32[2], AV32[2], op32;  // mixed precision only (0 otherwise)
   // inside small (byte offsets)
   size_t a, rb, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye, lflags, lscale;
@@ -53,6 +54,8 @@ struct lobpcg_ctx {
   int shift_retries = 20;  // shifted Cholesky retries before SVQB (ortho controller)
   int force_restarts = 0;  // test hook: true checks that count as failed
   int cheap_exit = 0;      // cheap exits of the ortho loops
+  int method = LOBPCG_METHOD_LOBPCG;
+  int dav_max_dim = 0;     // 0: min(25 m, kMaxP)
   int learned_bf16 = 1;  // learned preconditioner inference: layer 2 on bf16 MFMA
   // operator
   int op = lobpcg::kOpNone;
@@ -143,6 +146,11 @@ struct lobpcg_ctx {
   int run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool low, int& iter,
                 PhaseOut& out);
   int solve(int k, double tol);
+  int dav_dim(int m) const {
+    const int d = dav_max_dim > 0 ? dav_max_dim : 25 * m;
+    return d < lobpcg::kMaxP ? d : lobpcg::kMaxP;
+  }
+  int run_davidson(int k, double tol, int& iter, PhaseOut& out);
 };
 
 #define HIPCHK(expr)                                  \

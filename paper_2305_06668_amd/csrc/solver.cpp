@@ -42,11 +42,23 @@ Layout lobpcg_ctx::plan(int m, int prec) const {
     off = align_up(off + bytes);
     return o;
   };
-  const size_t blk = (size_t)n * 3 * m * sizeof(double);
-  L.V[0] = take(blk);
-  L.V[1] = take(blk);
-  L.AV[0] = take(blk);
-  L.AV[1] = take(blk);
+  if (method == LOBPCG_METHOD_DAVIDSON) {
+    // basis and its products (n x max_dim), the rotation's [X | W~] and A X
+    // (n x 2m), the explicit product of a true-residual check (n x m)
+    const size_t basis = (size_t)n * dav_dim(m) * sizeof(double);
+    const size_t side = (size_t)n * 2 * m * sizeof(double);
+    L.V[0] = take(basis);
+    L.AV[0] = take(basis);
+    L.V[1] = take(side);
+    L.AV[1] = take(side);
+    L.dscr = take((size_t)n * m * sizeof(double));
+  } else {
+    const size_t blk = (size_t)n * 3 * m * sizeof(double);
+    L.V[0] = take(blk);
+    L.V[1] = take(blk);
+    L.AV[0] = take(blk);
+    L.AV[1] = take(blk);
+  }
   L.diag = take((size_t)n * sizeof(double));
   L.rho = take((size_t)n * sizeof(double));
   L.ltiles = take((size_t)ltiles_cap() * sizeof(int));
@@ -82,7 +94,7 @@ Layout lobpcg_ctx::plan(int m, int prec) const {
   L.eye = stake(sizeof(double) * 64 * 64);
   L.lscale = stake(sizeof(double) * 4);
   L.small = take(so);
-  if (prec == LOBPCG_PREC_FP32) {
+  if (prec == LOBPCG_PREC_FP32 && method != LOBPCG_METHOD_DAVIDSON) {
     const size_t blk32 = (size_t)n * 3 * m * sizeof(float);
     L.V32[0] = take(blk32);
     L.V32[1] = take(blk32);
@@ -643,6 +655,144 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
   return LOBPCG_OK;
 }
 
+// Block Davidson (Sec. 2, X^{k+1} = RR(X^1, T^1 R^1, ..., T^k R^k); Sec. 4
+// keeps 25 vectors per root): the basis V (n x max_dim, leading dimension
+// max_dim) starts as ortho(X0) and grows by each active preconditioned
+// residual block, made orthonormal to it by Alg. 3 (the ortho controller
+// on [V | W]).  Per iteration: Gram a = V^T AV over the p basis columns,
+// the RR eigensolve, the rotation into the side buffer ([X | W~], A X),
+// locking and the true-residual test as in run_phase (readings R8, R9),
+// then W~ is copied behind the basis, orthonormalised and multiplied by A.
+// When the next block would exceed max_dim the history is truncated: the
+// basis restarts from the current Ritz vectors X (and A X).
+int lobpcg_ctx::run_davidson(int k, double tol, int& iter, PhaseOut& out) {
+  const int m = block;
+  const int md = dav_dim(m);
+  double* V = dptr(lay.V[0]);
+  double* AV = dptr(lay.AV[0]);
+  double* V1 = dptr(lay.V[1]);
+  double* AV1 = dptr(lay.AV[1]);
+  double* scr = dptr(lay.dscr);
+  double* a = small_ptr<double>(lay.a);
+  double* theta = small_ptr<double>(lay.theta);
+  double* U = small_ptr<double>(lay.U);
+  double* resn2 = small_ptr<double>(lay.resn2);
+  int* info = small_ptr<int>(lay.info);
+  double* part = dptr(lay.part);
+  const size_t sd = sizeof(double);
+
+  int rc = ortho_run<double>(V, md, 0, m, nullptr, false, tau);
+  if (rc) return rc;
+  rc = apply_op(V, md, m, AV, md);
+  if (rc) return rc;
+  int p = m;  // basis columns
+  int m_conv = 0;
+  bool just_restarted = false;
+  stats.max_basis = p;
+  std::vector<double> rnorm(m), th_t, rn_t;
+  out.converged = false;
+  for (;;) {
+    HIPCHK(gram_f64(V, md, p, AV, md, p, n, part, a, nullptr, stream));
+    int a0 = m_conv;
+    int nact = m - a0;
+    HIPCHK(small_rr(a, p, m, a0, 0, tau, nullptr, 0, theta, U, info, rr_jacobi, stream));
+    int ldo = m + nact;
+    RotateArgs ra{};
+    ra.n = n;
+    ra.ldv = md;
+    ra.ldo = ldo;
+    ra.p = p;
+    ra.m = m;
+    ra.q = m;
+    ra.a0 = a0;
+    ra.precond = pkind;
+    ra.U = U;
+    ra.theta = theta;
+    ra.diag = dptr(lay.diag);
+    ra.part = part;
+    ra.resnorm2 = resn2;
+    HIPCHK(rotate_f64(V, AV, V1, AV1, ra, stream));
+    const void* rbp = nullptr;
+    rc = readback(resn2, kReadbackBytes, &rbp);
+    if (rc) return rc;
+    const double* hb = static_cast<const double*>(rbp);
+    const int* hinfo = reinterpret_cast<const int*>(hb + 192);
+    if (hinfo[1] != 0) return fail(LOBPCG_ERR_ORTHO_FAILED, "Rayleigh-Ritz eigensolve failed");
+    stats.rr_eig_fallbacks += hinfo[11];
+    for (int j = 0; j < m; ++j) {
+      rnorm[j] = std::sqrt(hb[j]);
+      if (!std::isfinite(rnorm[j]) || !std::isfinite(hb[64 + j]))
+        return fail(LOBPCG_ERR_NONFINITE, "non-finite Ritz value or residual");
+    }
+    int newc = std::max(m_conv, leading_converged(rnorm, tol));
+    if (just_restarted) newc = std::min(newc, k - 1);
+    just_restarted = false;
+    if (newc >= k) {
+      rc = ortho_run<double>(V1, ldo, 0, m, nullptr, false, tau);
+      if (rc) return rc;
+      rc = true_residuals(V1, ldo, m, scr, theta, th_t, rn_t);
+      if (rc) return rc;
+      double worst = 0.0;
+      for (int j = 0; j < k; ++j) worst = std::max(worst, rn_t[j]);
+      if (worst <= tol && stats.restarts >= force_restarts) {
+        out.converged = true;
+        out.X = V1;
+        out.ld = ldo;
+        break;
+      }
+      // restart from X with the explicit product (reading R9)
+      stats.restarts++;
+      HIPCHK(hipMemcpy2DAsync(V, sd * md, V1, sd * ldo, sd * m, n, hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipMemcpy2DAsync(AV, sd * md, scr, sd * m, sd * m, n, hipMemcpyDeviceToDevice, stream));
+      p = m;
+      m_conv = 0;
+      just_restarted = true;
+      continue;
+    }
+    if (newc != m_conv) {
+      // locking changed the active set: W~ for the new one
+      stats.relocks++;
+      m_conv = newc;
+      a0 = m_conv;
+      nact = m - a0;
+      HIPCHK(small_rr(a, p, m, a0, 0, tau, nullptr, 0, theta, U, info, rr_jacobi, stream));
+      ldo = m + nact;
+      ra.ldo = ldo;
+      ra.a0 = a0;
+      HIPCHK(rotate_f64(V, AV, V1, AV1, ra, stream));
+    }
+    if (iter >= max_iter) {
+      rc = ortho_run<double>(V1, ldo, 0, m, nullptr, false, tau);
+      if (rc) return rc;
+      rc = true_residuals(V1, ldo, m, scr, theta, th_t, rn_t);
+      if (rc) return rc;
+      out.X = V1;
+      out.ld = ldo;
+      break;
+    }
+    ++iter;
+    if (p + nact > md) {
+      // history truncation: restart the basis from the Ritz vectors
+      stats.history_restarts++;
+      HIPCHK(hipMemcpy2DAsync(V, sd * md, V1, sd * ldo, sd * m, n, hipMemcpyDeviceToDevice, stream));
+      HIPCHK(hipMemcpy2DAsync(AV, sd * md, AV1, sd * ldo, sd * m, n, hipMemcpyDeviceToDevice, stream));
+      p = m;
+    }
+    HIPCHK(hipMemcpy2DAsync(V + p, sd * md, V1 + m, sd * ldo, sd * nact, n, hipMemcpyDeviceToDevice,
+                            stream));
+    rc = ortho_run<double>(V, md, p, nact, nullptr, false, tau);
+    if (rc) return rc;
+    rc = apply_op(V + p, md, nact, AV + p, md);
+    if (rc) return rc;
+    p += nact;
+    stats.max_basis = std::max(stats.max_basis, p);
+  }
+  res_evals.assign(th_t.begin(), th_t.begin() + m);
+  res_resn.assign(rn_t.begin(), rn_t.begin() + m);
+  stats.m_conv = m_conv;
+  return LOBPCG_OK;
+}
+
 int lobpcg_ctx::solve(int k, double tol) {
   const auto t0 = std::chrono::steady_clock::now();
   if (op == kOpNone) return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
@@ -667,20 +817,39 @@ int lobpcg_ctx::solve(int k, double tol) {
   }
   double* V[2] = {dptr(lay.V[0]), dptr(lay.V[1])};
   double* AV[2] = {dptr(lay.AV[0]), dptr(lay.AV[1])};
+  const bool dav = (method == LOBPCG_METHOD_DAVIDSON);
+  if (dav && (precision != LOBPCG_PREC_FP64 || pkind == LOBPCG_PRECOND_LEARNED))
+    return fail(LOBPCG_ERR_UNSUPPORTED, "block Davidson runs in fp64 with the Jacobi preconditioners");
+  if (dav && dav_dim(m) < 2 * m)
+    return fail(LOBPCG_ERR_INVALID_ARG, "Davidson basis limit below 2 * block");
+  const int ld0 = dav ? dav_dim(m) : m;  // the basis of block Davidson is n x max_dim
 
   // ---- initial block (Alg. 1 input) ----
   if (X0 != nullptr) {
-    HIPCHK(hipMemcpy2DAsync(V[0], sizeof(double) * m, X0, sizeof(double) * ldx0,
+    HIPCHK(hipMemcpy2DAsync(V[0], sizeof(double) * ld0, X0, sizeof(double) * ldx0,
                             sizeof(double) * m, n, hipMemcpyDeviceToDevice, stream));
   } else if (!X0_host.empty()) {
-    HIPCHK(hipMemcpyAsync(V[0], X0_host.data(), sizeof(double) * m * n, hipMemcpyHostToDevice,
-                          stream));
+    HIPCHK(hipMemcpy2DAsync(V[0], sizeof(double) * ld0, X0_host.data(), sizeof(double) * m,
+                            sizeof(double) * m, n, hipMemcpyHostToDevice, stream));
     HIPCHK(hipStreamSynchronize(stream));
   } else {
-    for (int j = 0; j < m; ++j) HIPCHK(fill_splitmix(V[0], m, j, j, n, kDefaultX0Seed, stream));
+    for (int j = 0; j < m; ++j) HIPCHK(fill_splitmix(V[0], ld0, j, j, n, kDefaultX0Seed, stream));
   }
   int iter = 0;
   PhaseOut po{};
+  if (dav) {
+    rc = run_davidson(k, tol, iter, po);
+    if (rc) return rc;
+    res_k = k;
+    res_X = reinterpret_cast<const double*>(po.X);
+    res_ld = po.ld;
+    have_result = true;
+    stats.iterations = iter;
+    stats.converged = po.converged ? 1 : 0;
+    stats.ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return po.converged ? LOBPCG_OK : LOBPCG_NOT_CONVERGED;
+  }
   if (precision == LOBPCG_PREC_FP32) {
     rc = ensure_op32();
     if (rc) return rc;
@@ -813,6 +982,18 @@ int lobpcg_set_option(lobpcg_t h, int key, double v) {
       if (v < 0 || v > 20 || v != (int)v)
         return h->fail(LOBPCG_ERR_INVALID_ARG, "shift retries must be an integer in [0, 20]");
       h->shift_retries = (int)v;
+      return LOBPCG_OK;
+    case LOBPCG_OPT_METHOD:
+      if (v != LOBPCG_METHOD_LOBPCG && v != LOBPCG_METHOD_DAVIDSON)
+        return h->fail(LOBPCG_ERR_INVALID_ARG, "bad method");
+      h->method = (int)v;
+      h->lay_block = -1;  // the workspace layout depends on the method
+      return LOBPCG_OK;
+    case LOBPCG_OPT_DAVIDSON_MAX_DIM:
+      if (v < 0 || v > kMaxP || v != (int)v)
+        return h->fail(LOBPCG_ERR_INVALID_ARG, "Davidson basis limit must be an integer in [0, 96]");
+      h->dav_max_dim = (int)v;
+      h->lay_block = -1;
       return LOBPCG_OK;
     case LOBPCG_OPT_CHEAP_EXIT:
       h->cheap_exit = (v != 0.0);

@@ -1,7 +1,7 @@
 """Writes the full-size expected values under tests/golden/ from the CPU
 oracle alone (no GPU code is imported).  Run once on a CPU host:
 
-    python tests/golden/make_full_size.py [c2] [c3]
+    python tests/golden/make_full_size.py [c2] [c3] [c3_inputs]
 
 Outputs (JSON, one per workload; each records the input digests):
   csr_banded_n1e6_k16.json    the sparse banded workload (n = 1e6, k = block =
@@ -13,7 +13,9 @@ Outputs (JSON, one per workload; each records the input digests):
   dense_hessian_n20000_k8.json  the dense Hessian-like workload (n = 2e4,
                               k = 8): the lowest 8 eigenvalues from the exact
                               dense eigensolve (LAPACK syevr), plus the 9th
-                              for the gap.
+                              for the gap; its input is fingerprinted by
+                              sampled entries (c3_inputs adds them to a stored
+                              file), since BLAS threading changes its last bits.
 """
 import json
 import os
@@ -76,6 +78,31 @@ def c2():
         json.dump(out, f, indent=1)
 
 
+def dense_input_check(A):
+    """Fingerprint of a dense input that survives rounding-level differences:
+    the generator's QR and low-rank product run through multithreaded BLAS,
+    whose summation order (hence the last bits of A) depends on the host."""
+    n = A.shape[0]
+    idx = [(i * 7919) % n for i in range(64)]
+    jdx = [(j * 104729 + 13) % n for j in range(64)]
+    return {
+        "frobenius": float(np.linalg.norm(A)),
+        "positions": [[int(i), int(j)] for i, j in zip(idx, jdx)],
+        "values": [float(A[i, j]) for i, j in zip(idx, jdx)],
+        "rtol": 1e-12,
+    }
+
+
+def c3_inputs():
+    """Adds the rounding-tolerant input fingerprint to the stored C3 file."""
+    path = os.path.join(HERE, "dense_hessian_n20000_k8.json")
+    out = json.load(open(path))
+    A = synth.dense_hessian(20_000, seed=synth.SEEDS["dense_hessian"][0])
+    out["inputs_check"] = dense_input_check(A)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+
+
 def c3():
     n, k = 20_000, 8
     mseed, xseed = synth.SEEDS["dense_hessian"]
@@ -90,6 +117,7 @@ def c3():
         "workload": "dense_hessian n=20000 k=8 block=8 (seed %d)" % mseed,
         "source": "oracle/lobpcg_oracle.py lowest_eigenpairs_dense (LAPACK syevr, indices 0..8)",
         "inputs_sha256": {"A": dig},
+        "inputs_check": dense_input_check(A),
         "evals": w[:k].tolist(),
         "next_eval": float(w[k]),
         "residuals": np.linalg.norm(R, axis=0).tolist(),
@@ -106,3 +134,5 @@ if __name__ == "__main__":
         c2()
     if "c3" in which:
         c3()
+    if "c3_inputs" in which:
+        c3_inputs()

@@ -1,0 +1,138 @@
+"""Block Davidson with a history (Sec. 2's recurrence X^{k+1} = RR(X^1,
+T^1 R^1, ..., T^k R^k), Sec. 4's history of up to 25 vectors per root and
+its comparison with LOBPCG) on the GPU through the C ABI, against the CPU
+oracle's Davidson with the same history limit: the eigenpair bar of the
+problem (true residual <= tol recomputed on the CPU, eigenvalues within
+1e-9 max(|lambda|, 1e-3 ||A||) of the exact or the oracle's), the history
+truncations, and iteration counts within max(3, 10 %) (rounding-sensitive,
+so a soft check)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import lobpcg_oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_06668_amd as P
+
+    return P
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dav_solve(P, n, setop, X0, k, tol, max_dim=0, force_restarts=0):
+    s = P.Solver(n)
+    setop(s)
+    s.set_preconditioner(P.PRECOND_DIAG)
+    s.set_option(P.OPT_METHOD, P.METHOD_DAVIDSON)
+    s.set_option(P.OPT_DAVIDSON_MAX_DIM, max_dim)
+    s.set_option(P.OPT_FORCE_RESTARTS, force_restarts)
+    s.set_initial_guess(cu(X0))
+    res = s.solve(k, tol)
+    res.evecs_np = res.evecs.cpu().numpy()
+    return s, res
+
+
+def check(res, op, lam, tol, normA):
+    assert res.status == 0, res.stats
+    X = res.evecs_np
+    AX = op(X)
+    th = np.einsum("ij,ij->j", X, AX)
+    r = np.linalg.norm(AX - X * th, axis=0)
+    assert np.all(r <= tol * 1.0001), r
+    assert np.abs(X.T @ X - np.eye(X.shape[1])).max() < 1e-12
+    scale = np.maximum(np.abs(lam), 1e-3 * normA)
+    assert np.all(np.abs(res.evals - lam) <= 1e-9 * scale), (res.evals, lam)
+
+
+@pytest.mark.parametrize("max_dim", [8, 24, 0])
+def test_davidson_dense_dd(P, max_dim):
+    n, k = 2000, 4
+    A = synth.dense_dd(n)
+    X0 = synth.start_block(n, k, synth.SEEDS["dense_dd"][1])
+    d = np.diag(A).copy()
+    s, res = dav_solve(P, n, lambda s: s.set_operator_dense(cu(A)), X0, k, 1e-8, max_dim=max_dim)
+    md = max_dim or min(25 * k, 96)
+    ora = O.davidson(O.dense_operator(A), X0, k, 1e-8, diag=d, max_dim=md)
+    st = res.stats
+    say(max_dim, "gpu", st["iterations"], st["history_restarts"], st["max_basis"], "oracle", ora.iterations, ora.restarts,
+        ora.max_basis)
+    lam = np.linalg.eigvalsh(A)[:k]
+    check(res, O.dense_operator(A), lam, 1e-8, normA=101.0)
+    assert abs(st["iterations"] - ora.iterations) <= max(3, 0.1 * ora.iterations)
+    assert st["max_basis"] <= md and st["max_basis"] == ora.max_basis
+    if max_dim == 8:
+        assert st["history_restarts"] > 0
+
+
+@pytest.mark.parametrize("max_dim", [24, 96])
+def test_davidson_csr(P, max_dim):
+    n, k = 20000, 8
+    C = synth.csr_banded(n=n, seed=21, band=600, diag_slope=10.0 / n)
+    X0 = synth.start_block(n, k, 22)
+    op = O.csr_operator(C.row_ptr, C.col, C.val, n)
+    s, res = dav_solve(P, n, lambda s: s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val)), X0, k, 1e-8,
+                       max_dim=max_dim)
+    ora = O.davidson(op, X0, k, 1e-8, diag=C.diag, max_dim=max_dim)
+    st = res.stats
+    say(max_dim, "gpu", st["iterations"], st["history_restarts"], "oracle", ora.iterations, ora.restarts)
+    check(res, op, ora.evals, 1e-8, normA=11.0)
+    assert abs(st["iterations"] - ora.iterations) <= max(3, 0.1 * ora.iterations)
+
+
+def test_davidson_forced_restart(P):
+    n, k = 400, 4
+    A = synth.dense_dd(n, seed=7)
+    X0 = synth.start_block(n, k, 8)
+    s, res = dav_solve(P, n, lambda s: s.set_operator_dense(cu(A)), X0, k, 1e-9, max_dim=16, force_restarts=1)
+    assert res.stats["restarts"] == 1 and res.stats["true_checks"] == 2
+    check(res, O.dense_operator(A), np.linalg.eigvalsh(A)[:k], 1e-9, normA=40.0)
+
+
+def test_davidson_unsupported_modes(P):
+    n = 300
+    A = synth.dense_dd(n, seed=1)
+    s = P.Solver(n)
+    s.set_operator_dense(cu(A))
+    s.set_option(P.OPT_METHOD, P.METHOD_DAVIDSON)
+    s.set_option(P.OPT_PRECISION, P.PREC_FP32)
+    s.set_initial_guess(cu(synth.start_block(n, 3, 1)))
+    with pytest.raises(P.LobpcgError) as e:
+        s.solve(3, 1e-8)
+    assert e.value.status == P.ERR_UNSUPPORTED
+    with pytest.raises(P.LobpcgError):
+        P.lobpcg_set_option(s.h, P.OPT_DAVIDSON_MAX_DIM, 97)
+
+
+def test_davidson_full_size_csr(P):
+    """The n = 1e6 banded workload (k = 16; 96 basis columns = 6 per root)
+    against the oracle's converged LOBPCG eigenvalues of the same inputs."""
+    import scipy.sparse as sp
+
+    n, k = 1_000_000, 16
+    mseed, xseed = synth.SEEDS["csr_banded"]
+    C = synth.csr_banded(n=n, seed=mseed)
+    X0 = synth.start_block(n, k, xseed)
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "csr_banded_n1e6_k16.json")))
+    A = sp.csr_matrix((C.val, C.col, C.row_ptr), shape=(n, n))
+    s, res = dav_solve(P, n, lambda s: s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val)), X0, k, 1e-8)
+    st = res.stats
+    say("davidson n=1e6:", st["iterations"], "iterations", st["history_restarts"], "truncations",
+        f"{st['ms_total']:.1f} ms", st["matvec_columns"], "matvec columns")
+    check(res, lambda X: A @ X, np.asarray(gold["evals"]), 1e-8, normA=11.2)

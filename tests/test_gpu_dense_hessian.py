@@ -40,7 +40,13 @@ def test_dense_hessian_full_size(P):
     mseed, xseed = synth.SEEDS["dense_hessian"]
     A = synth.dense_hessian(N, seed=mseed)
     gold = json.load(open(GOLDEN))
-    assert synth.array_digest(A) == gold["inputs_sha256"]["A"]
+    # same input up to the last bits (its generator's BLAS calls round
+    # differently with the host's thread count); the eigenvalues move by at
+    # most ||dA||_2 (Weyl), ~1e-13 here, far inside the bar
+    chk = gold["inputs_check"]
+    assert abs(np.linalg.norm(A) - chk["frobenius"]) <= chk["rtol"] * chk["frobenius"]
+    vals = np.array([A[i, j] for i, j in chk["positions"]])
+    assert np.allclose(vals, chk["values"], rtol=chk["rtol"], atol=1e-15)
     lam = np.asarray(gold["evals"])
     X0 = synth.start_block(N, K, xseed)
     s = P.Solver(N)
