@@ -65,6 +65,10 @@ the design notes of the repository):
       c(n) eps g <= tau, g the growth of the ortho call (normalisation scale
       times a bound on ||L^-1|| per factor).  c(n) = max(4, 0.02 sqrt(n)) is
       twice the loss measured on this oracle.
+  R19 Tridiagonal preconditioner (Sec. 4.4): T_j = tridiag(e, t, e) with
+      t_i = max(|d_i - theta_j|, |e_{i-1}| + |e_i| + delta_j), the positive
+      definite counterpart of R7 (strictly diagonally dominant), solved by
+      LAPACK's Gaussian elimination with partial pivoting (dgtsv).
   R16 Eigenvectors of the reduced matrix are oriented so that the diagonal
       entry u[j, j] is >= 0 (for the X block: the new Ritz vector continues
       the old one).  The "Basis selection" paragraph forms P from the
@@ -381,6 +385,42 @@ def precondition_diag(
     return out
 
 
+def tridiagonal_part(A) -> np.ndarray:
+    """The off-diagonal of tridiag(A): e[i] = a_{i, i+1} (n - 1 values) of a
+    dense array or a scipy sparse matrix."""
+    if hasattr(A, "tocsr"):
+        return np.asarray(A.tocsr().diagonal(1), dtype=np.float64)
+    return np.asarray(np.diagonal(A, 1), dtype=np.float64).copy()
+
+
+def precondition_tridiag(R: np.ndarray, diag: np.ndarray, off: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    """Tridiagonal preconditioner (Sec. 4.4, Table 1: the diagonal plus the
+    upper and lower diagonal elements, solved by LAPACK's Gaussian
+    elimination with partial pivoting), reading R19: column j solves
+    T_j w = r with T_j = tridiag(e, t, e), e the off-diagonal of A and
+    t_i = max(|d_i - theta_j|, |e_{i-1}| + |e_i| + delta_j), delta_j the
+    Jacobi guard of R7.  T_j is symmetric and strictly diagonally dominant
+    with a positive diagonal (so positive definite, like R7's absolute
+    Jacobi step, to which it reduces where e = 0)."""
+    from scipy.linalg import lapack
+
+    n = R.shape[0]
+    e = np.asarray(off, dtype=np.float64)
+    ae = np.abs(e)
+    rowoff = np.zeros(n)
+    rowoff[:-1] += ae
+    rowoff[1:] += ae
+    out = np.empty_like(R)
+    for j in range(R.shape[1]):
+        delta = PRECOND_GUARD * max(1.0, abs(float(theta[j])))
+        t = np.maximum(np.abs(diag - theta[j]), rowoff + delta)
+        _, _, _, x, info = lapack.dgtsv(e.copy(), t, e.copy(), R[:, j].copy())
+        if info != 0:
+            raise np.linalg.LinAlgError(f"dgtsv failed (info {info})")
+        out[:, j] = x
+    return out
+
+
 def ritz_residual(AX: np.ndarray, X: np.ndarray, theta: np.ndarray) -> np.ndarray:
     """R = A X - X diag(theta) for Ritz pairs (Sec. 2, reading R1)."""
     return AX - X * theta
@@ -500,6 +540,7 @@ def lobpcg(
     tau: float = TAU_ORTHO,
     max_iter: int = 1000,
     callback: Optional[Callable[[dict], None]] = None,
+    off: Optional[np.ndarray] = None,
     shift_retries: int = SHIFT_RETRIES,
     force_restarts: int = 0,
     cheap_exit: bool = False,
@@ -508,7 +549,8 @@ def lobpcg(
 
     X0 is the n x m initial block (m >= k, the block may hold extra vectors,
     Sec. 2).  ``precond`` is "diag" (|Jacobi|, needs ``diag``),
-    "diag_signed" (the paper's signed Jacobi), "none", or a callable
+    "diag_signed" (the paper's signed Jacobi), "tridiag" (reading R19,
+    needs ``diag`` and the off-diagonal ``off``), "none", or a callable
     f(R_act, theta_act, X_act) returning the preconditioned columns.
     ``shift_retries`` caps the shifted Cholesky retries of every ortho call
     (0 sends a failed factorisation straight to SVQB).  ``force_restarts``
@@ -520,8 +562,10 @@ def lobpcg(
     n, m = X0.shape
     if not (1 <= k <= m):
         raise ValueError("need 1 <= k <= block size")
-    if isinstance(precond, str) and precond.startswith("diag") and diag is None:
-        raise ValueError("the Jacobi preconditioner needs diag(A)")
+    if isinstance(precond, str) and precond in ("diag", "diag_signed", "tridiag") and diag is None:
+        raise ValueError("the Jacobi and tridiagonal preconditioners need diag(A)")
+    if precond == "tridiag" and off is None:
+        raise ValueError("the tridiagonal preconditioner needs the off-diagonal of A (off=)")
     st = OrthoStats()
     hist_theta, hist_resid, hist_active = [], [], []
     matvecs = 0
@@ -534,6 +578,8 @@ def lobpcg(
             return precondition_diag(R, diag, theta)
         if precond == "diag_signed":
             return precondition_diag(R, diag, theta, signed=True)
+        if precond == "tridiag":
+            return precondition_tridiag(R, diag, off, theta)
         if precond == "none":
             return R.copy()
         raise ValueError(precond)
@@ -699,6 +745,7 @@ def davidson(
     max_dim: Optional[int] = None,
     tau: float = TAU_ORTHO,
     max_iter: int = 1000,
+    off: Optional[np.ndarray] = None,
 ) -> DavidsonResult:
     """Block Davidson for the lowest k eigenpairs of ``op`` (Sec. 2): the
     basis holds X^{[1]} and every preconditioned residual block since the
@@ -731,6 +778,8 @@ def davidson(
             return precondition_diag(R, diag, theta)
         if precond == "diag_signed":
             return precondition_diag(R, diag, theta, signed=True)
+        if precond == "tridiag":
+            return precondition_tridiag(R, diag, off, theta)
         if precond == "none":
             return R.copy()
         return np.asarray(precond(R, theta, None), dtype=np.float64)

@@ -780,3 +780,79 @@ def test_planted_davidson_without_projection(monkeypatch):
     res = O.davidson(O.dense_operator(A), X0, m, 1e-30, diag=np.diag(A).copy(), max_iter=4)
     ref = _davidson_by_definition(A, X0, 4, np.diag(A).copy())
     assert not all(np.allclose(res.history_theta[j], ref[j], rtol=1e-10, atol=0) for j in range(5))
+
+
+# ---------------------------------------------------------------------------
+# tridiagonal preconditioner (Sec. 4.4, Table 1; reading R19)
+
+
+def _tri_dense(d, e, theta):
+    ae = np.abs(e)
+    rowoff = np.zeros(d.size)
+    rowoff[:-1] += ae
+    rowoff[1:] += ae
+    delta = O.PRECOND_GUARD * max(1.0, abs(theta))
+    t = np.maximum(np.abs(d - theta), rowoff + delta)
+    return np.diag(t) + np.diag(e, 1) + np.diag(e, -1)
+
+
+def test_tridiag_preconditioner_definition():
+    n = 400
+    A = synth.dense_dd(n, seed=9) + np.diag(np.full(n - 1, 0.3), 1) + np.diag(np.full(n - 1, 0.3), -1)
+    d, e = np.diag(A).copy(), O.tridiagonal_part(A)
+    assert np.array_equal(e, np.diagonal(A, 1))
+    R = synth.start_block(n, 3, 1)
+    theta = np.array([1.2, 3.01, 11.0])  # below, inside and far inside the diagonal's range
+    W = O.precondition_tridiag(R, d, e, theta)
+    for j in range(3):
+        T = _tri_dense(d, e, theta[j])
+        assert np.all(np.linalg.eigvalsh(T) > 0)  # positive definite
+        assert np.allclose(W[:, j], np.linalg.solve(T, R[:, j]), rtol=0, atol=1e-12 * np.abs(W[:, j]).max())
+    # sparse and dense inputs give the same off-diagonal
+    Cs = synth.csr_from_dense(A).to_scipy()
+    assert np.array_equal(O.tridiagonal_part(Cs), e)
+
+
+def test_tridiag_reduces_to_jacobi_without_offdiagonal():
+    n = 300
+    d = synth.rng(3).uniform(0.5, 5.0, n)
+    d[7] = 2.0  # an entry right at theta: the guard decides
+    R = synth.start_block(n, 2, 4)
+    theta = np.array([2.0, 0.1])
+    W = O.precondition_tridiag(R, d, np.zeros(n - 1), theta)
+    assert np.array_equal(W, O.precondition_diag(R, d, theta))
+
+
+def test_planted_tridiag_subdiagonal_shift():
+    # the sub-diagonal taken one row off (e shifted by one) is caught by the
+    # dense solve of the definition
+    n = 200
+    g = synth.rng(8)
+    d, e = g.uniform(2.0, 4.0, n), g.uniform(-0.5, 0.5, n - 1)
+    R = g.standard_normal((n, 1))
+    from scipy.linalg import lapack
+
+    ae = np.abs(e)
+    rowoff = np.zeros(n)
+    rowoff[:-1] += ae
+    rowoff[1:] += ae
+    t = np.maximum(np.abs(d - 1.0), rowoff + 1e-8)
+    _, _, _, bad, _ = lapack.dgtsv(np.roll(e, 1), t, e.copy(), R[:, 0].copy())
+    good = np.linalg.solve(_tri_dense(d, e, 1.0), R[:, 0])
+    assert np.allclose(O.precondition_tridiag(R, d, e, np.array([1.0]))[:, 0], good, atol=1e-13)
+    assert not np.allclose(bad, good, atol=1e-8)
+
+
+def test_tridiag_solve_matches_eigh():
+    n, k = 600, 4
+    A = synth.dense_dd(n, seed=4) + np.diag(np.full(n - 1, 0.02), 1) + np.diag(np.full(n - 1, 0.02), -1)
+    lam = np.linalg.eigvalsh(A)[:k]
+    X0 = synth.start_block(n, k, 2)
+    d, e = np.diag(A).copy(), O.tridiagonal_part(A)
+    r0 = O.lobpcg(O.dense_operator(A), X0, k, 1e-9, diag=d)
+    r1 = O.lobpcg(O.dense_operator(A), X0, k, 1e-9, diag=d, precond="tridiag", off=e)
+    assert_eigs(r1, lam, tol=1e-9)
+    # the tridiagonal part is a better model of A here than its diagonal
+    assert r1.iterations < r0.iterations
+    rd = O.davidson(O.dense_operator(A), X0, k, 1e-9, diag=d, precond="tridiag", off=e)
+    assert_eigs(rd, lam, tol=1e-9)
