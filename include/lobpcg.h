@@ -57,6 +57,12 @@ typedef struct lobpcg_ctx* lobpcg_t;
 #define LOBPCG_PRECOND_DIAG_SIGNED 2 /* T_j = (diag(A) - theta_j I)^-1, Sec. 2's example */
 #define LOBPCG_PRECOND_LEARNED 3     /* learned regularised Jacobi step (see
                                         lobpcg_set_learned_weights); Jacobi fallback */
+#define LOBPCG_PRECOND_TRIDIAG 4     /* tridiagonal (Sec. 4.4, Table 1): T_j w = r with
+                                        T_j = tridiag(e, t, e), e_i = a_{i,i+1},
+                                        t_i = max(|d_i - theta_j|, |e_{i-1}| + |e_i| +
+                                        delta_j): the positive definite counterpart of
+                                        LOBPCG_PRECOND_DIAG (equal to it where e = 0),
+                                        solved exactly on the device */
 
 /* Parameters of the learned preconditioner's MLP (3 -> 128 -> 128 -> 1). */
 #define LOBPCG_LEARNED_NPARAMS 17153
@@ -348,6 +354,15 @@ int lobpcg_rotate(lobpcg_t h, const double* V, const double* AV, int64_t ldv, in
  * Needs weights and the operator.  1 <= nact <= 64.  Asynchronous. */
 int lobpcg_learned_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const double* theta,
                          const int* mask);
+
+/* The tridiagonal preconditioner (LOBPCG_PRECOND_TRIDIAG) on caller
+ * buffers: column j of R (device n x nact, ldr, in place) becomes the
+ * solution w of T_j w = r_j for theta_j (device, nact).  diag(A) and the
+ * off-diagonal come from the operator (or the diag given to
+ * lobpcg_set_preconditioner).  Needs the operator and a workspace sized with
+ * the tridiagonal preconditioner selected.  1 <= nact <= block.
+ * Asynchronous. */
+int lobpcg_tridiag_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const double* theta);
 
 /* ======================================================================== */
 /* Training the learned preconditioner                                        */

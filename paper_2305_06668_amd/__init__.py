@@ -42,6 +42,7 @@ PRECOND_NONE = 0
 PRECOND_DIAG = 1
 PRECOND_DIAG_SIGNED = 2
 PRECOND_LEARNED = 3
+PRECOND_TRIDIAG = 4
 LEARNED_NPARAMS = 17153
 
 PREC_FP64 = 0
@@ -154,6 +155,7 @@ _c = {
     ),
     "set_learned_weights": _sig("lobpcg_set_learned_weights", [_vp, _vp, _i64]),
     "learned_apply": _sig("lobpcg_learned_apply", [_vp, _vp, _i64, ctypes.c_int, _vp, _vp]),
+    "tridiag_apply": _sig("lobpcg_tridiag_apply", [_vp, _vp, _i64, ctypes.c_int, _vp]),
     "learner_create": _sig("lobpcg_learner_create", [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "learner_destroy": _sig("lobpcg_learner_destroy", [_vp]),
     "learner_set_stream": _sig("lobpcg_learner_set_stream", [_vp, _vp]),
@@ -183,7 +185,7 @@ EXPORTED = [
     "lobpcg_status_string", "lobpcg_last_error", "lobpcg_apply_operator", "lobpcg_gram",
     "lobpcg_gram_noalloc",
     "lobpcg_ortho", "lobpcg_ortho_against", "lobpcg_small_eigh", "lobpcg_small_cholesky",
-    "lobpcg_rotate", "lobpcg_set_learned_weights", "lobpcg_learned_apply",
+    "lobpcg_rotate", "lobpcg_set_learned_weights", "lobpcg_learned_apply", "lobpcg_tridiag_apply",
     "lobpcg_learner_create", "lobpcg_learner_destroy", "lobpcg_learner_set_stream",
     "lobpcg_learner_set_weights", "lobpcg_learner_get_weights", "lobpcg_learner_add_snapshot",
     "lobpcg_learner_snapshot_info", "lobpcg_learner_objective", "lobpcg_learner_train",
@@ -501,6 +503,15 @@ def lobpcg_learned_apply(h, R, theta, mask=None) -> None:
     _check(h, _c["learned_apply"](h, _dev_ptr(R, torch.float64, "R"), _ld(R, "R"), nact, _dev_ptr(theta, torch.float64, "theta"), mp))
 
 
+def lobpcg_tridiag_apply(h, R, theta) -> None:
+    """In place: column j of R (cuda, n x nact) <- T_j^-1 R[:, j]."""
+    torch = _torch()
+    nact = R.shape[1]
+    if theta.numel() != nact:
+        raise ValueError("theta: one value per column")
+    _check(h, _c["tridiag_apply"](h, _dev_ptr(R, torch.float64, "R"), _ld(R, "R"), nact, _dev_ptr(theta, torch.float64, "theta")))
+
+
 def lobpcg_learner_last_error(L) -> str:
     return (_c["learner_last_error"](L) or b"").decode()
 
@@ -638,6 +649,8 @@ class Solver:
     def set_preconditioner(self, kind=PRECOND_DIAG, diag=None):
         self._keep["diag"] = diag
         lobpcg_set_preconditioner(self.h, kind, diag)
+        if self._block is not None:
+            self.ensure_workspace(self._block)  # the tridiagonal solve needs more workspace
 
     def set_learned_weights(self, w):
         lobpcg_set_learned_weights(self.h, w)

@@ -17,6 +17,7 @@ SOURCES = [
     "k_blas.hip",
     "k_op.hip",
     "k_spmm.hip",
+    "k_tri.hip",
     "k_kron.hip",
     "k_small.hip",
     "k_mlp.hip",

@@ -30,6 +30,9 @@ struct Layout {
   size_t V[2], AV[2], diag, rho, ltiles, part, small, total;
   size_t kpack = 0;  // dense / Kronecker operator: n x 8 packed copy of a W block
   size_t dscr = 0;   // block Davidson: n x m scratch for the explicit product A X
+  // tridiagonal preconditioner: off-diagonal, row off-sums, forward factors,
+  // chunk boundary data
+  size_t tri_e = 0, tri_off = 0, tri_scr = 0, tri_bnd = 0, tri_xb = 0;
   size_t V32[2], AV32[2], op32;  // mixed precision only (0 otherwise)
   // inside small (byte offsets)
   size_t a, rb, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye, lflags, lscale;
@@ -73,6 +76,7 @@ struct lobpcg_ctx {
   bool diag_ready = false;
   float* lweights = nullptr;     // learned preconditioner weights (library-owned device copy)
   bool lfeat_ready = false;      // off-diagonal row sums and mean |diag| computed
+  bool tri_ready = false;        // tridiagonal off-diagonal extracted
   double lscale_host = 0.0;
   // initial guess (device, row-major; or a host copy, row-major)
   const double* X0 = nullptr;
@@ -134,6 +138,9 @@ struct lobpcg_ctx {
                 double tau_run = -1.0);
   int ensure_diag();
   int ensure_learned_features();
+  int ensure_tri();
+  template <typename T>
+  int tri_apply(T* R, int64_t ld, int nact, const double* theta);
   int ensure_op32();
   int true_residuals(const double* X, int64_t ldx, int m, double* scratch, const double* theta_rr,
                      std::vector<double>& th, std::vector<double>& rn);

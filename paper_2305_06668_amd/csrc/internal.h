@@ -22,7 +22,7 @@ constexpr double kPrecondGuard = 1e-8;   // |d - theta| floor, relative to max(1
 constexpr uint64_t kZeroColumnSeed = 0x2305066680000000ull;
 constexpr uint64_t kDefaultX0Seed = 0x2305066600000001ull;
 
-enum PrecondKind { kPrecNone = 0, kPrecDiag = 1, kPrecDiagSigned = 2, kPrecLearned = 3 };
+enum PrecondKind { kPrecNone = 0, kPrecDiag = 1, kPrecDiagSigned = 2, kPrecLearned = 3, kPrecTridiag = 4 };
 
 // learned preconditioner: per-entry MLP 3 -> 128 -> 128 -> 1
 constexpr int kMlpHidden = 128;
@@ -176,6 +176,26 @@ hipError_t dense_norm_bound(const double* A, int64_t lda, int64_t n, double* par
 // the static partial-sum array of lobpcg_gram_noalloc; *out receives it.
 // Returns a LOBPCG_* status; *err gets a message on failure.
 int noalloc_setup(int device, double** out, std::string* err);
+
+// ---- tridiagonal preconditioner (k_tri.hip) ------------------------------
+constexpr int kTriMaxChunks = 1024;
+// Chunks of the partition method for order n (balanced, >= 64 rows each).
+int tri_chunks(int64_t n);
+// In place: R[:, 0:nact] (ld) <- T_j^-1 R[:, j], T_j = tridiag(e, t, e) with
+// t_i = max(|d_i - theta_j|, off_i + delta_j).  e: n values (e[n-1] = 0),
+// off_i = |e_{i-1}| + |e_i|; bnd: 6 kTriMaxChunks nact doubles, xb: 2
+// kTriMaxChunks nact doubles; scr: n nact doubles.
+hipError_t tri_apply_f64(double* R, int64_t ld, int nact, int64_t n, const double* theta,
+                         const double* d, const double* e, const double* off, double* bnd,
+                         double* xb, double* scr, hipStream_t s);
+hipError_t tri_apply_f32(float* R, int64_t ld, int nact, int64_t n, const double* theta,
+                         const double* d, const double* e, const double* off, double* bnd,
+                         double* xb, double* scr, hipStream_t s);
+hipError_t tri_offdiag_csr(const int32_t* rp, const int32_t* ci, const double* val, int64_t n,
+                           double* e, double* off, hipStream_t s);
+hipError_t tri_offdiag_dense(const double* A, int64_t lda, int64_t n, double* e, double* off,
+                             hipStream_t s);
+hipError_t tri_offdiag_kron(const double* A, int64_t na, double* e, double* off, hipStream_t s);
 
 // ---- small dense fp64 kernels (k_small.hip) -----------------------------
 // Eigen-decomposition of sym(a) (p x p): evals ascending, evecs p x p.

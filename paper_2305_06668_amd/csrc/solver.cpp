@@ -61,6 +61,13 @@ Layout lobpcg_ctx::plan(int m, int prec) const {
   }
   L.diag = take((size_t)n * sizeof(double));
   L.rho = take((size_t)n * sizeof(double));
+  if (pkind == LOBPCG_PRECOND_TRIDIAG) {
+    L.tri_e = take((size_t)n * sizeof(double));
+    L.tri_off = take((size_t)n * sizeof(double));
+    L.tri_scr = take((size_t)n * std::max(m, 1) * sizeof(double));
+    L.tri_bnd = take((size_t)kTriMaxChunks * kMaxBlock * 6 * sizeof(double));
+    L.tri_xb = take((size_t)kTriMaxChunks * kMaxBlock * 6 * sizeof(double));
+  }
   L.ltiles = take((size_t)ltiles_cap() * sizeof(int));
   if (op == kOpKron || op == kOpDense) L.kpack = take((size_t)n * 8 * sizeof(double));
   const size_t gblk = (size_t)std::min<int64_t>(kGramBlocks, (n + 63) / 64) + 1;
@@ -116,6 +123,7 @@ int lobpcg_ctx::ensure_layout(int m) {
     lay_block = m;
     diag_ready = false;
     lfeat_ready = false;
+    tri_ready = false;
     op32_ready = false;
   }
   return LOBPCG_OK;
@@ -207,6 +215,45 @@ int lobpcg_ctx::ensure_diag() {
     }
   }
   diag_ready = true;
+  return LOBPCG_OK;
+}
+
+// The tridiagonal preconditioner's off-diagonal e_i = a_{i,i+1} and the row
+// off-sums |e_{i-1}| + |e_i|, from the operator.
+int lobpcg_ctx::ensure_tri() {
+  if (tri_ready) return LOBPCG_OK;
+  if (lay.tri_e == 0) return fail(LOBPCG_ERR_WORKSPACE, "workspace not sized for the tridiagonal preconditioner");
+  int rc = ensure_diag();
+  if (rc) return rc;
+  double* e = dptr(lay.tri_e);
+  double* off = dptr(lay.tri_off);
+  switch (op) {
+    case kOpCsr: HIPCHK(tri_offdiag_csr(rp, ci, val, n, e, off, stream)); break;
+    case kOpDense: HIPCHK(tri_offdiag_dense(A, lda, n, e, off, stream)); break;
+    case kOpKron: HIPCHK(tri_offdiag_kron(A, na, e, off, stream)); break;
+    default: return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+  }
+  tri_ready = true;
+  return LOBPCG_OK;
+}
+
+static hipError_t tri_apply_t(double* R, int64_t ld, int nact, int64_t n, const double* th,
+                              const double* d, const double* e, const double* off, double* bnd,
+                              double* xb, double* scr, hipStream_t s) {
+  return tri_apply_f64(R, ld, nact, n, th, d, e, off, bnd, xb, scr, s);
+}
+static hipError_t tri_apply_t(float* R, int64_t ld, int nact, int64_t n, const double* th,
+                              const double* d, const double* e, const double* off, double* bnd,
+                              double* xb, double* scr, hipStream_t s) {
+  return tri_apply_f32(R, ld, nact, n, th, d, e, off, bnd, xb, scr, s);
+}
+
+template <typename T>
+int lobpcg_ctx::tri_apply(T* R, int64_t ld, int nact, const double* th) {
+  if (nact > lay_block || nact > kMaxBlock)
+    return fail(LOBPCG_ERR_INVALID_ARG, "tridiagonal preconditioner: nact exceeds the block");
+  HIPCHK(tri_apply_t(R, ld, nact, n, th, dptr(lay.diag), dptr(lay.tri_e), dptr(lay.tri_off),
+                     dptr(lay.tri_bnd), dptr(lay.tri_xb), dptr(lay.tri_scr), stream));
   return LOBPCG_OK;
 }
 
@@ -458,6 +505,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
   // the step that used its learned W takes the Jacobi step for the next 3
   // iterations (so does a column where the net produced a non-finite value)
   const bool learned = (pkind == LOBPCG_PRECOND_LEARNED);
+  const bool tri = (pkind == LOBPCG_PRECOND_TRIDIAG);
   std::vector<int> fb_left(m, 0);
   std::vector<char> used_learned(m, 0);
   std::vector<double> r_before(m, 0.0);
@@ -501,7 +549,8 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     ra.m = m;
     ra.q = q;
     ra.a0 = a0;
-    ra.precond = learned ? kPrecNone : pkind;  // learned: W~ = R, transformed below
+    // learned and tridiagonal: W~ = R here, transformed below
+    ra.precond = (learned || tri) ? kPrecNone : pkind;
     ra.U = U;
     ra.theta = theta;
     ra.diag = dptr(lay.diag);
@@ -637,6 +686,10 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       prev_a0 = a0;
       prev_nact = nact;
     }
+    if (tri) {
+      rc = tri_apply<T>(V[1 - c] + q, ldo, nact, theta + a0);
+      if (rc) return rc;
+    }
     rc = ortho_run<T>(V[1 - c], ldo, q, nact, nullptr, true, tau_phase);
     if (rc) return rc;
     pend_valid = true;
@@ -705,7 +758,7 @@ int lobpcg_ctx::run_davidson(int k, double tol, int& iter, PhaseOut& out) {
     ra.m = m;
     ra.q = m;
     ra.a0 = a0;
-    ra.precond = pkind;
+    ra.precond = (pkind == LOBPCG_PRECOND_TRIDIAG) ? kPrecNone : pkind;
     ra.U = U;
     ra.theta = theta;
     ra.diag = dptr(lay.diag);
@@ -778,6 +831,10 @@ int lobpcg_ctx::run_davidson(int k, double tol, int& iter, PhaseOut& out) {
       HIPCHK(hipMemcpy2DAsync(AV, sd * md, AV1, sd * ldo, sd * m, n, hipMemcpyDeviceToDevice, stream));
       p = m;
     }
+    if (pkind == LOBPCG_PRECOND_TRIDIAG) {
+      rc = tri_apply<double>(V1 + m, ldo, nact, theta + a0);
+      if (rc) return rc;
+    }
     HIPCHK(hipMemcpy2DAsync(V + p, sd * md, V1 + m, sd * ldo, sd * nact, n, hipMemcpyDeviceToDevice,
                             stream));
     rc = ortho_run<double>(V, md, p, nact, nullptr, false, tau);
@@ -807,6 +864,10 @@ int lobpcg_ctx::solve(int k, double tol) {
   have_result = false;
   if (pkind != LOBPCG_PRECOND_NONE) {
     rc = ensure_diag();
+    if (rc) return rc;
+  }
+  if (pkind == LOBPCG_PRECOND_TRIDIAG) {
+    rc = ensure_tri();
     if (rc) return rc;
   }
   if (pkind == LOBPCG_PRECOND_LEARNED) {
@@ -1061,6 +1122,7 @@ int lobpcg_set_operator_csr(lobpcg_t h, const int32_t* row_ptr, const int32_t* c
   h->nnz = nnz;
   h->diag_ready = false;
   h->lfeat_ready = false;
+  h->tri_ready = false;
   h->op32_ready = false;
   h->have_result = false;
   return LOBPCG_OK;
@@ -1074,6 +1136,7 @@ int lobpcg_set_operator_dense(lobpcg_t h, const double* A, int64_t lda) {
   h->lda = lda;
   h->diag_ready = false;
   h->lfeat_ready = false;
+  h->tri_ready = false;
   h->op32_ready = false;
   h->have_result = false;
   return LOBPCG_OK;
@@ -1089,6 +1152,7 @@ int lobpcg_set_operator_kronsum(lobpcg_t h, int64_t na, const double* A, const d
   h->Vpot = V;
   h->diag_ready = false;
   h->lfeat_ready = false;
+  h->tri_ready = false;
   h->op32_ready = false;
   h->have_result = false;
   return LOBPCG_OK;
@@ -1097,12 +1161,14 @@ int lobpcg_set_operator_kronsum(lobpcg_t h, int64_t na, const double* A, const d
 int lobpcg_set_preconditioner(lobpcg_t h, int kind, const double* diag) {
   if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
   if (kind != LOBPCG_PRECOND_NONE && kind != LOBPCG_PRECOND_DIAG &&
-      kind != LOBPCG_PRECOND_DIAG_SIGNED && kind != LOBPCG_PRECOND_LEARNED)
+      kind != LOBPCG_PRECOND_DIAG_SIGNED && kind != LOBPCG_PRECOND_LEARNED &&
+      kind != LOBPCG_PRECOND_TRIDIAG)
     return h->fail(LOBPCG_ERR_UNSUPPORTED, "preconditioner kind not available");
   h->pkind = kind;
   h->user_diag = diag;
   h->diag_ready = false;
   h->lfeat_ready = false;
+  h->tri_ready = false;
   return LOBPCG_OK;
 }
 
@@ -1279,6 +1345,20 @@ int lobpcg_learned_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const dou
                              h->ltiles_cap(), h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "learned apply");
   return LOBPCG_OK;
+}
+
+int lobpcg_tridiag_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const double* theta) {
+  GUARD(h);
+  if (R == nullptr || theta == nullptr || nact < 1 || nact > kMaxBlock || ldr < nact)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad tridiag_apply arguments");
+  if (h->op == kOpNone) return h->fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+  if (h->pkind != LOBPCG_PRECOND_TRIDIAG)
+    return h->fail(LOBPCG_ERR_BAD_STATE, "select LOBPCG_PRECOND_TRIDIAG first");
+  int rc = need_ws(h);
+  if (rc) return rc;
+  rc = h->ensure_tri();
+  if (rc) return rc;
+  return h->tri_apply<double>(R, ldr, nact, theta);
 }
 
 int lobpcg_gram(lobpcg_t h, const double* A, int64_t lda, int p, const double* B, int64_t ldb,
