@@ -170,6 +170,32 @@ def kron_only(P, synth, torch, dev, na=4096, m=8, reps=5):
     log(f"kron: mixed solve, {r.stats['iterations']} iterations (capped; fp32 operator in its trace)")
 
 
+def tridiag_only(P, synth, torch, dev, n=1_000_000, m=16, reps=10):
+    """Times the tridiagonal preconditioner's solve (lobpcg_tridiag_apply)
+    on a 16-column block of the banded workload."""
+    mseed, _ = synth.SEEDS["csr_banded"]
+    C = synth.csr_banded(n=n, seed=mseed)
+    s = P.Solver(n)
+    s.set_operator_csr(*(torch.from_numpy(a).to(dev) for a in (C.row_ptr, C.col, C.val)))
+    s.ensure_workspace(m)
+    s.set_preconditioner(P.PRECOND_TRIDIAG)
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    R = torch.randn((n, m), dtype=torch.float64, device=dev, generator=g)
+    th = torch.from_numpy(np.sort(C.diag)[:m] + 1e-4).to(dev)
+    for _ in range(3):
+        P.lobpcg_tridiag_apply(s.h, R, th)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        P.lobpcg_tridiag_apply(s.h, R, th)
+    ev1.record(stream)
+    ev1.synchronize()
+    log(f"tridiag: n={n} m={m}: {ev0.elapsed_time(ev1) / reps * 1e3:.1f} us per application")
+
+
 def dense_only(P, synth, torch, dev, n=20_000, m=8, reps=20):
     """Times Y = A W for the dense Hessian-like operator at its full size."""
     A = synth.dense_hessian(n, seed=synth.SEEDS["dense_hessian"][0])
@@ -225,6 +251,12 @@ def main():
         "fp64 columns and print its MFMA rate",
     )
     ap.add_argument(
+        "--tridiag",
+        action="store_true",
+        help="skip the solves: time the tridiagonal preconditioner's solve on 16 columns of the "
+        "n = 1e6 banded matrix",
+    )
+    ap.add_argument(
         "--dense",
         action="store_true",
         help="skip the solves: time the dense operator at n = 20,000 on 8 fp64 columns and print "
@@ -250,6 +282,9 @@ def main():
         return
     if args.dense:
         dense_only(P, synth, torch, dev)
+        return
+    if args.tridiag:
+        tridiag_only(P, synth, torch, dev)
         return
     n, k = args.n, args.k
     mseed, xseed = synth.SEEDS["csr_banded"]
