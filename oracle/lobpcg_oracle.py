@@ -846,3 +846,199 @@ def davidson(
         history_theta=hist_theta,
         X_all=X,
     )
+
+
+# ---------------------------------------------------------------------------
+# The generalized problem A x = lambda B x, B symmetric positive definite
+# (Sec. 3.3).  Reading R21: the basis V = [X, W, P] is kept B-orthonormal
+# with B V carried along.  W~ = T R (R = A X - B X Theta, the Jacobi
+# preconditioner (diag A - theta diag B)^-1 with the guard of R7) goes through
+# W^ = ortho(W~, (BX, BP)): Alg. 3 with the projection W <- W - [X P]
+# ([BX BP]^T W) (the B-orthogonal projector, since [X P] is B-orthonormal)
+# and Euclidean Alg. 2 passes, until ||[BX BP]^T W||_max <= tau; then one
+# B-Cholesky with the reused application: B W^ once, M = W^T B W^ = L L^T
+# (shifted if it fails, as in Alg. 2), W = W^ L^-T, BW = (B W^) L^-T.  X0
+# is B-orthonormalised the same way.  The Rayleigh-Ritz matrix V^T A V is a
+# standard symmetric eigenproblem on a B-orthonormal V.  Convergence:
+# ||A x - theta B x||_2 <= tol for x with x^T B x = 1 (theta = x^T A x),
+# judged on explicit products after one more B-orthonormalisation (R9).
+
+
+def b_orthonormalize(X: np.ndarray, BX: np.ndarray, st: OrthoStats):
+    """One Cholesky B-orthonormalisation reusing B X: X L^-T, BX L^-T."""
+    M = symmetrize(X.T @ BX)
+    st.grams += 1
+    L = shifted_cholesky(M, st)
+    if L is None:
+        raise OrthoFailed("B-overlap not positive definite")
+    X = sla.solve_triangular(L, X.T, lower=True, check_finite=False).T
+    BX = sla.solve_triangular(L, BX.T, lower=True, check_finite=False).T
+    st.updates += 1
+    return X, BX
+
+
+def b_ortho_against(Wt: np.ndarray, Y: np.ndarray, BY: np.ndarray, tau: float, st: OrthoStats,
+                    max_passes: int = ORTHO_Y_MAX_PASSES) -> np.ndarray:
+    """W^ = ortho(W~, (BX, BP)) of Sec. 3.3 (reading R21)."""
+    W = normalize_columns(Wt, st)
+    if Y is None or Y.shape[1] == 0:
+        return ortho(W, tau, st)
+    C = BY.T @ W
+    for _ in range(max_passes):
+        st.against_passes += 1
+        W = W - Y @ C
+        W = ortho(W, tau, st)
+        C = BY.T @ W
+        if max_abs(C) <= tau:
+            return W
+    st.stalled += 1
+    return W
+
+
+def precondition_diag_gen(R: np.ndarray, dA: np.ndarray, dB: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    """W~[:, j] = R[:, j] / g(|dA - theta_j dB|) (reading R21, R7's guard)."""
+    out = np.empty_like(R)
+    for j in range(R.shape[1]):
+        delta = PRECOND_GUARD * max(1.0, abs(float(theta[j])))
+        den = np.abs(dA - theta[j] * dB)
+        out[:, j] = R[:, j] / np.maximum(den, delta)
+    return out
+
+
+def lobpcg_generalized(
+    opA: Operator,
+    opB: Operator,
+    X0: np.ndarray,
+    k: int,
+    tol: float = 1e-8,
+    dA: Optional[np.ndarray] = None,
+    dB: Optional[np.ndarray] = None,
+    precond="diag",
+    tau: float = TAU_ORTHO,
+    max_iter: int = 1000,
+) -> LobpcgResult:
+    """Alg. 1 for A x = lambda B x (Sec. 3.3, reading R21).  ``precond``:
+    "diag" (needs dA, dB) or "none".  The returned vectors satisfy
+    X^T B X = I."""
+    X0 = np.asarray(X0, dtype=np.float64)
+    n, m = X0.shape
+    if not (1 <= k <= m):
+        raise ValueError("need 1 <= k <= block size")
+    st = OrthoStats()
+    hist_theta, hist_resid, hist_active = [], [], []
+    matvecs = bmatvecs = 0
+    true_checks = 0
+
+    def tprec(R, theta):
+        if precond == "diag":
+            return precondition_diag_gen(R, dA, dB, theta)
+        if precond == "none":
+            return R.copy()
+        raise ValueError(precond)
+
+    X = ortho(X0, tau, st)
+    BX = opB(X)
+    bmatvecs += m
+    X, BX = b_orthonormalize(X, BX, st)
+    AX = opA(X)
+    matvecs += m
+    theta_all, U = rayleigh_ritz(X, AX)
+    X, AX, BX = X @ U, AX @ U, BX @ U
+    theta = theta_all[:m]
+    R = AX - BX * theta
+    rnorm = np.linalg.norm(R, axis=0)
+    hist_theta.append(theta.copy())
+    hist_resid.append(rnorm.copy())
+    m_conv = 0
+    P = AP = BP = None
+    it = 0
+    converged = False
+    restarts = 0
+    just_restarted = False
+    while True:
+        lead = leading_converged(rnorm, tol)
+        m_conv = min(max(m_conv, lead), k - 1) if just_restarted else max(m_conv, lead)
+        just_restarted = False
+        if m_conv >= k:
+            # R9 for the generalized problem: B-orthonormalise X once more
+            # (explicit B X), then judge with explicit products
+            BXt = opB(X)
+            bmatvecs += m
+            X, BXt = b_orthonormalize(X, BXt, st)
+            AXt = opA(X)
+            matvecs += m
+            true_checks += 1
+            th_t = np.einsum("ij,ij->j", X, AXt) / np.einsum("ij,ij->j", X, BXt)
+            r_t = np.linalg.norm(AXt - BXt * th_t, axis=0)
+            if float(np.max(r_t[:k])) <= tol:
+                converged = True
+                break
+            restarts += 1
+            theta_all, U = rayleigh_ritz(X, AXt)
+            X, AX, BX = X @ U, AXt @ U, BXt @ U
+            theta = theta_all[:m]
+            R = AX - BX * theta
+            rnorm = np.linalg.norm(R, axis=0)
+            m_conv = 0
+            P = AP = BP = None
+            just_restarted = True
+            continue
+        if it >= max_iter:
+            break
+        it += 1
+        act = np.arange(m_conv, m)
+        Wt = tprec(R[:, act], theta[act])
+        Y = X if P is None else np.hstack([X, P])
+        BY = BX if P is None else np.hstack([BX, BP])
+        W = b_ortho_against(Wt, Y, BY, tau, st)
+        BW = opB(W)
+        bmatvecs += W.shape[1]
+        W, BW = b_orthonormalize(W, BW, st)
+        AW = opA(W)
+        matvecs += W.shape[1]
+        hist_active.append(W.shape[1])
+        if P is None:
+            V, AV, BV = np.hstack([X, W]), np.hstack([AX, AW]), np.hstack([BX, BW])
+        else:
+            V, AV, BV = np.hstack([X, W, P]), np.hstack([AX, AW, AP]), np.hstack([BX, BW, BP])
+        theta_all, U = rayleigh_ritz(V, AV)
+        ux = U[:, :m]
+        theta = theta_all[:m]
+        Xn, AXn, BXn = V @ ux, AV @ ux, BV @ ux
+        R = AXn - BXn * theta
+        rnorm = np.linalg.norm(R, axis=0)
+        hist_theta.append(theta.copy())
+        hist_resid.append(rnorm.copy())
+        m_conv = max(m_conv, leading_converged(rnorm, tol))
+        act = np.arange(m_conv, m)
+        if m_conv < k:
+            up_t = ux[:, act].copy()
+            up_t[act, np.arange(act.size)] -= 1.0
+            up = ortho_against(up_t, ux, tau, st)
+            P, AP, BP = V @ up, AV @ up, BV @ up
+        X, AX, BX = Xn, AXn, BXn
+    if not converged:
+        BXt = opB(X)
+        X, BXt = b_orthonormalize(X, BXt, st)
+        AXt = opA(X)
+        true_checks += 1
+        th_t = np.einsum("ij,ij->j", X, AXt) / np.einsum("ij,ij->j", X, BXt)
+        r_t = np.linalg.norm(AXt - BXt * th_t, axis=0)
+    return LobpcgResult(
+        evals=th_t[:k].copy(),
+        evecs=normalize_signs(X[:, :k]),
+        resnorms=r_t[:k].copy(),
+        converged=converged,
+        iterations=it,
+        matvec_columns=matvecs,
+        ortho=st,
+        history_theta=hist_theta,
+        history_resid=hist_resid,
+        history_active=hist_active,
+        true_checks=true_checks,
+        rms=r_t[:k] / math.sqrt(n),
+        maxabs=np.max(np.abs(AXt[:, :k] - BXt[:, :k] * th_t[:k]), axis=0),
+        X_all=X,
+        theta_all=th_t,
+        restarts=restarts,
+    )

@@ -856,3 +856,63 @@ def test_tridiag_solve_matches_eigh():
     assert r1.iterations < r0.iterations
     rd = O.davidson(O.dense_operator(A), X0, k, 1e-9, diag=d, precond="tridiag", off=e)
     assert_eigs(rd, lam, tol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# the generalized problem A x = lambda B x (Sec. 3.3; reading R21)
+
+
+def _gen_problem(n=400, seed=5):
+    A = synth.dense_dd(n, seed=seed)
+    g = synth.rng(seed + 4)
+    B = np.diag(g.uniform(1.0, 2.0, n)) + synth.random_symmetric(n, seed + 1, 1e-3)
+    return A, B
+
+
+def test_generalized_vs_scipy_eigh():
+    n, k = 400, 4
+    A, B = _gen_problem(n)
+    lam = sla.eigh(A, B, eigvals_only=True)[:k]
+    res = O.lobpcg_generalized(O.dense_operator(A), O.dense_operator(B), synth.start_block(n, k, 2), k, 1e-9,
+                               dA=np.diag(A).copy(), dB=np.diag(B).copy())
+    assert_eigs(res, lam, tol=1e-9)
+    X = res.X_all
+    assert O.max_abs(X.T @ B @ X - np.eye(k)) < 1e-12  # B-orthonormal output
+    r = np.linalg.norm(A @ X - (B @ X) * res.theta_all, axis=0)
+    assert np.all(r[:k] <= 1e-9)
+    # Courant-Fischer for the pencil: Ritz values never below the eigenvalues
+    assert np.all(np.array(res.history_theta) >= lam - 1e-12)
+
+
+def test_generalized_with_identity_is_the_standard_method():
+    n, k = 400, 4
+    A = synth.dense_dd(n, seed=5)
+    X0 = synth.start_block(n, k, 2)
+    rI = O.lobpcg_generalized(O.dense_operator(A), lambda X: X.copy(), X0, k, 1e-9, dA=np.diag(A).copy(), dB=np.ones(n))
+    rs = O.lobpcg(O.dense_operator(A), X0, k, 1e-9, diag=np.diag(A).copy())
+    assert rI.iterations == rs.iterations
+    assert np.allclose(rI.evals, rs.evals, rtol=0, atol=1e-13)
+
+
+def test_generalized_closed_form_diagonal():
+    n, k = 300, 5
+    g = synth.rng(12)
+    a = g.uniform(1.0, 50.0, n)
+    b = g.uniform(0.5, 3.0, n)
+    res = O.lobpcg_generalized(lambda X: a[:, None] * X, lambda X: b[:, None] * X, synth.start_block(n, 8, 1), k, 1e-10,
+                               dA=a, dB=b)
+    assert_eigs(res, np.sort(a / b)[:k], tol=1e-10)
+
+
+def test_planted_euclidean_projection_in_generalized(monkeypatch):
+    # projecting W against [X P] with Y^T W instead of (B Y)^T W leaves W
+    # B-nonorthogonal to X: the standard RR on V is then invalid
+    n, k = 400, 4
+    A, B = _gen_problem(n)
+    lam = sla.eigh(A, B, eigvals_only=True)[:k]
+    orig = O.b_ortho_against
+    monkeypatch.setattr(O, "b_ortho_against", lambda Wt, Y, BY, tau, st, max_passes=4: orig(Wt, Y, Y, tau, st, max_passes))
+    res = O.lobpcg_generalized(O.dense_operator(A), O.dense_operator(B), synth.start_block(n, k, 2), k, 1e-9,
+                               dA=np.diag(A).copy(), dB=np.diag(B).copy(), max_iter=200)
+    with pytest.raises(AssertionError):
+        assert_eigs(res, lam, tol=1e-9)
