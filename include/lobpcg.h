@@ -155,6 +155,7 @@ typedef struct lobpcg_stats {
   int32_t ortho_cheap_exits;   /* overlaps the cheap exits skipped */
   int32_t history_restarts;    /* block Davidson: history truncations */
   int32_t max_basis;           /* block Davidson: largest basis reached (columns) */
+  int64_t b_matvec_columns;    /* generalized problem: columns B was applied to */
 } lobpcg_stats;
 
 /* ---- ortho report for the step entry points ---------------------------- */
@@ -205,6 +206,20 @@ int lobpcg_set_operator_dense(lobpcg_t h, const double* A, int64_t lda);
  * (na x na, symmetric, row-major) and V (na x na, row-major); vector entry
  * i * na + j pairs with V[i][j].  Device, borrowed. */
 int lobpcg_set_operator_kronsum(lobpcg_t h, int64_t na, const double* A, const double* V);
+
+/* The second operator B of the generalized problem A x = lambda B x (Sec.
+ * 3.3), B symmetric positive definite: CSR (device arrays, both triangles,
+ * borrowed) or dense (device, row-major, ldb >= n, borrowed).  A NULL
+ * row_ptr / B returns to the standard problem.  With B set, lobpcg_solve
+ * keeps the basis B-orthonormal (Sec. 3.3: W^ = ortho(W~, (BX, BP)) by the
+ * B-orthogonal projection and Euclidean Alg. 2 passes, one application B W^,
+ * one B-Cholesky reusing it), the residuals are A x - theta B x, the Jacobi
+ * step uses |diag A - theta diag B|, returned vectors satisfy X^T B X = I
+ * and resnorms are ||A x - theta B x||.  fp64 LOBPCG with the NONE / DIAG /
+ * DIAG_SIGNED preconditioners only (else LOBPCG_ERR_UNSUPPORTED). */
+int lobpcg_set_operator_b_csr(lobpcg_t h, const int32_t* row_ptr, const int32_t* col,
+                              const double* val, int64_t nnz);
+int lobpcg_set_operator_b_dense(lobpcg_t h, const double* B, int64_t ldb);
 
 /* Preconditioner T (Sec. 2).  kind: LOBPCG_PRECOND_*.  diag: device array of
  * n values of diag(A), or NULL to take it from the operator (CSR: the stored

@@ -96,6 +96,7 @@ class lobpcg_stats(ctypes.Structure):
         ("ortho_cheap_exits", _i32),
         ("history_restarts", _i32),
         ("max_basis", _i32),
+        ("b_matvec_columns", _i64),
     ]
 
     def as_dict(self) -> dict:
@@ -131,6 +132,8 @@ _c = {
     "set_operator_csr": _sig("lobpcg_set_operator_csr", [_vp, _vp, _vp, _vp, _i64]),
     "set_operator_dense": _sig("lobpcg_set_operator_dense", [_vp, _vp, _i64]),
     "set_operator_kronsum": _sig("lobpcg_set_operator_kronsum", [_vp, _i64, _vp, _vp]),
+    "set_operator_b_csr": _sig("lobpcg_set_operator_b_csr", [_vp, _vp, _vp, _vp, _i64]),
+    "set_operator_b_dense": _sig("lobpcg_set_operator_b_dense", [_vp, _vp, _i64]),
     "set_preconditioner": _sig("lobpcg_set_preconditioner", [_vp, ctypes.c_int, _vp]),
     "set_initial_guess": _sig("lobpcg_set_initial_guess", [_vp, _vp, _i64, ctypes.c_int]),
     "set_initial_guess_host": _sig("lobpcg_set_initial_guess_host", [_vp, _vp, _i64, ctypes.c_int]),
@@ -179,7 +182,8 @@ _c = {
 EXPORTED = [
     "lobpcg_create", "lobpcg_destroy", "lobpcg_set_stream", "lobpcg_set_option",
     "lobpcg_workspace_size", "lobpcg_set_workspace", "lobpcg_set_operator_csr",
-    "lobpcg_set_operator_dense", "lobpcg_set_operator_kronsum", "lobpcg_set_preconditioner",
+    "lobpcg_set_operator_dense", "lobpcg_set_operator_kronsum", "lobpcg_set_operator_b_csr",
+    "lobpcg_set_operator_b_dense", "lobpcg_set_preconditioner",
     "lobpcg_set_initial_guess", "lobpcg_set_initial_guess_host", "lobpcg_solve",
     "lobpcg_get_eigenpairs", "lobpcg_get_eigenpairs_host", "lobpcg_get_stats",
     "lobpcg_status_string", "lobpcg_last_error", "lobpcg_apply_operator", "lobpcg_gram",
@@ -302,6 +306,33 @@ def lobpcg_set_operator_kronsum(h, A, V) -> None:
         h,
         _c["set_operator_kronsum"](h, int(A.shape[0]), _dev_ptr(A, torch.float64, "A"), _dev_ptr(V, torch.float64, "V")),
     )
+
+
+def lobpcg_set_operator_b_csr(h, row_ptr, col, val) -> None:
+    """B of A x = lambda B x as CSR (cuda tensors); row_ptr None: standard problem."""
+    torch = _torch()
+    if row_ptr is None:
+        _check(h, _c["set_operator_b_csr"](h, None, None, None, 0))
+        return
+    _check(
+        h,
+        _c["set_operator_b_csr"](
+            h,
+            _dev_ptr(row_ptr, torch.int32, "row_ptr"),
+            _dev_ptr(col, torch.int32, "col"),
+            _dev_ptr(val, torch.float64, "val"),
+            int(col.numel()),
+        ),
+    )
+
+
+def lobpcg_set_operator_b_dense(h, B) -> None:
+    """B of A x = lambda B x, dense row-major (cuda); None: standard problem."""
+    torch = _torch()
+    if B is None:
+        _check(h, _c["set_operator_b_dense"](h, None, 0))
+        return
+    _check(h, _c["set_operator_b_dense"](h, _dev_ptr(B, torch.float64, "B"), _ld(B, "B")))
 
 
 def lobpcg_set_preconditioner(h, kind: int, diag=None) -> None:
@@ -645,6 +676,18 @@ class Solver:
         lobpcg_set_operator_kronsum(self.h, A, V)
         if self._block is not None:
             self.ensure_workspace(self._block)  # the workspace depends on the operator
+
+    def set_operator_b_csr(self, row_ptr, col, val):
+        self._keep["opb"] = (row_ptr, col, val)
+        lobpcg_set_operator_b_csr(self.h, row_ptr, col, val)
+        if self._block is not None:
+            self.ensure_workspace(self._block)  # B V needs its own buffers
+
+    def set_operator_b_dense(self, B):
+        self._keep["opb"] = (B,)
+        lobpcg_set_operator_b_dense(self.h, B)
+        if self._block is not None:
+            self.ensure_workspace(self._block)
 
     def set_preconditioner(self, kind=PRECOND_DIAG, diag=None):
         self._keep["diag"] = diag

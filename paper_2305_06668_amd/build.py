@@ -18,6 +18,7 @@ SOURCES = [
     "k_op.hip",
     "k_spmm.hip",
     "k_tri.hip",
+    "k_gen.hip",
     "k_kron.hip",
     "k_small.hip",
     "k_mlp.hip",

@@ -33,6 +33,8 @@ struct Layout {
   // tridiagonal preconditioner: off-diagonal, row off-sums, forward factors,
   // chunk boundary data
   size_t tri_e = 0, tri_off = 0, tri_scr = 0, tri_bnd = 0, tri_xb = 0;
+  // generalized problem: B V (double-buffered like V) and diag(B)
+  size_t BV[2] = {0, 0}, bdiag = 0;
   size_t V32[2], AV32[2], op32;  // mixed precision only (0 otherwise)
   // inside small (byte offsets)
   size_t a, rb, theta, U, G, coef, resn2, cols, info, ost, pidx, pval, eye, lflags, lscale;
@@ -70,6 +72,15 @@ struct lobpcg_ctx {
   int64_t lda = 0;
   int64_t na = 0;
   const double* Vpot = nullptr;
+  // the second operator B of A x = lambda B x (Sec. 3.3); kOpNone: standard
+  int bop = lobpcg::kOpNone;
+  const int32_t* brp = nullptr;
+  const int32_t* bci = nullptr;
+  const double* bval = nullptr;
+  int64_t bnnz = 0;
+  const double* Bd = nullptr;
+  int64_t ldb = 0;
+  bool bdiag_ready = false;
   // preconditioner
   int pkind = LOBPCG_PRECOND_DIAG;
   const double* user_diag = nullptr;
@@ -158,6 +169,10 @@ struct lobpcg_ctx {
     return d < lobpcg::kMaxP ? d : lobpcg::kMaxP;
   }
   int run_davidson(int k, double tol, int& iter, PhaseOut& out);
+  int apply_b(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy);
+  int ensure_bdiag();
+  int b_orthonormalize(double* X, double* BX, int64_t ld, int nc);
+  int run_generalized(int k, double tol, int& iter, PhaseOut& out);
 };
 
 #define HIPCHK(expr)                                  \

@@ -177,6 +177,23 @@ hipError_t dense_norm_bound(const double* A, int64_t lda, int64_t n, double* par
 // Returns a LOBPCG_* status; *err gets a message on failure.
 int noalloc_setup(int device, double** out, std::string* err);
 
+// ---- generalized problem (k_gen.hip) -------------------------------------
+// resn2[j] = ||A X - B X theta||^2 per column (AX, BX: n x m, ld); columns
+// j >= a0 of R, preconditioned (0 none, 1 |dA - theta dB|, 2 signed, with
+// the Jacobi guard), go to Wout[:, j - a0] (ldw).  part: 1024 m doubles.
+hipError_t gen_residual(const double* AX, const double* BX, int64_t ld, int m, const double* theta,
+                        int a0, int precond, const double* dA, const double* dB, double* Wout,
+                        int64_t ldw, int64_t n, double* part, double* resn2, hipStream_t s);
+// out[0:m] = x^T B x, out[m:2m] = x^T A x, out[2m:3m] = ||A x - theta B x||^2
+// (X: ldx; AX, BX: ldm).  part: 3072 m doubles.
+hipError_t gen_colstats(const double* X, int64_t ldx, const double* AX, const double* BX, int64_t ldm,
+                        int m, const double* theta, int64_t n, double* part, double* out,
+                        hipStream_t s);
+// coef = [-C; I] ((ny + nw) x nw) and *cmax = max |C| (C: ny x nw)
+hipError_t gen_proj_coef(const double* C, int ny, int nw, double* coef, double* cmax, hipStream_t s);
+// out = L^-T (p x p, p <= kMaxBlock)
+hipError_t gen_lt_inv(const double* L, int p, double* out, hipStream_t s);
+
 // ---- tridiagonal preconditioner (k_tri.hip) ------------------------------
 constexpr int kTriMaxChunks = 1024;
 // Chunks of the partition method for order n (balanced, >= 64 rows each).

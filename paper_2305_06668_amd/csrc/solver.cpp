@@ -59,6 +59,12 @@ Layout lobpcg_ctx::plan(int m, int prec) const {
     L.AV[0] = take(blk);
     L.AV[1] = take(blk);
   }
+  if (bop != kOpNone) {
+    const size_t blk = (size_t)n * 3 * m * sizeof(double);
+    L.BV[0] = take(blk);
+    L.BV[1] = take(blk);
+    L.bdiag = take((size_t)n * sizeof(double));
+  }
   L.diag = take((size_t)n * sizeof(double));
   L.rho = take((size_t)n * sizeof(double));
   if (pkind == LOBPCG_PRECOND_TRIDIAG) {
@@ -124,6 +130,7 @@ int lobpcg_ctx::ensure_layout(int m) {
     diag_ready = false;
     lfeat_ready = false;
     tri_ready = false;
+    bdiag_ready = false;
     op32_ready = false;
   }
   return LOBPCG_OK;
@@ -850,6 +857,252 @@ int lobpcg_ctx::run_davidson(int k, double tol, int& iter, PhaseOut& out) {
   return LOBPCG_OK;
 }
 
+// ---- the generalized problem A x = lambda B x (Sec. 3.3) ----------------
+
+int lobpcg_ctx::apply_b(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy) {
+  hipError_t e = hipSuccess;
+  switch (bop) {
+    case kOpCsr: e = spmm_csr_f64(brp, bci, bval, W, ldw, Y, ldy, nc, n, stream); break;
+    case kOpDense:
+      e = dense_apply_f64(Bd, ldb, W, ldw, Y, ldy, nc, n,
+                          (ws && lay_block > 0 && lay.kpack) ? dptr(lay.kpack) : nullptr, stream);
+      break;
+    default: return fail(LOBPCG_ERR_BAD_STATE, "no B operator set");
+  }
+  if (e != hipSuccess) return hip_fail(e, "B operator");
+  stats.b_matvec_columns += nc;
+  return LOBPCG_OK;
+}
+
+int lobpcg_ctx::ensure_bdiag() {
+  if (bdiag_ready) return LOBPCG_OK;
+  double* d = dptr(lay.bdiag);
+  switch (bop) {
+    case kOpCsr: HIPCHK(csr_diag(brp, bci, bval, n, d, stream)); break;
+    case kOpDense: HIPCHK(dense_diag(Bd, ldb, n, d, stream)); break;
+    default: return fail(LOBPCG_ERR_BAD_STATE, "no B operator set");
+  }
+  bdiag_ready = true;
+  return LOBPCG_OK;
+}
+
+// One B-Cholesky pass with the application reused (Sec. 3.3): M = X^T (BX),
+// M = L L^T (shifted on failure, Sec. 3.2), X <- X L^-T, BX <- BX L^-T; X
+// and BX are n x nc with leading dimension ld.
+int lobpcg_ctx::b_orthonormalize(double* X, double* BX, int64_t ld, int nc) {
+  double* M = small_ptr<double>(lay.a);
+  double* Lf = small_ptr<double>(lay.G);
+  double* coef = small_ptr<double>(lay.coef);
+  int* info = small_ptr<int>(lay.info);
+  HIPCHK(gram_f64(X, ld, nc, BX, ld, nc, n, dptr(lay.part), M, nullptr, stream));
+  HIPCHK(small_cholesky(M, nc, Lf, info, stream));
+  HIPCHK(gen_lt_inv(Lf, nc, coef, stream));
+  HIPCHK(tsmm_f64(X, ld, nc, coef, nc, X, ld, n, nullptr, stream));
+  HIPCHK(tsmm_f64(BX, ld, nc, coef, nc, BX, ld, n, nullptr, stream));
+  const void* rbp = nullptr;
+  int rc = readback(info, 16, &rbp);
+  if (rc) return rc;
+  const int* hi = static_cast<const int*>(rbp);
+  stats.ortho_factorizations += hi[1];
+  stats.ortho_failed += hi[2];
+  if (hi[0] != 0) return fail(LOBPCG_ERR_ORTHO_FAILED, "B-overlap not positive definite");
+  return LOBPCG_OK;
+}
+
+// Alg. 1 for the generalized problem (reading of Sec. 3.3): the basis
+// V = [X | P | W] is B-orthonormal and B V is carried in its own buffers.
+// Per iteration: Gram a = V^T AV, the RR kernel, the rotation of V and AV
+// (its residual is replaced), B V U for [BX BP], the generalized residual
+// R = A X - B X Theta with the preconditioned W~, then
+// W^ = ortho(W~, (BX, BP)) (the B-orthogonal projection W - [X P]([BX BP]^T
+// W) and Euclidean Alg. 2 passes until ||[BX BP]^T W|| <= tau), one
+// application B W^, one B-Cholesky reusing it, and A W.
+int lobpcg_ctx::run_generalized(int k, double tol, int& iter, PhaseOut& out) {
+  const int m = block;
+  double* V[2] = {dptr(lay.V[0]), dptr(lay.V[1])};
+  double* AV[2] = {dptr(lay.AV[0]), dptr(lay.AV[1])};
+  double* BV[2] = {dptr(lay.BV[0]), dptr(lay.BV[1])};
+  double* a = small_ptr<double>(lay.a);
+  double* theta = small_ptr<double>(lay.theta);
+  double* U = small_ptr<double>(lay.U);
+  double* resn2 = small_ptr<double>(lay.resn2);
+  int* info = small_ptr<int>(lay.info);
+  double* part = dptr(lay.part);
+  double* C = small_ptr<double>(lay.G);
+  double* coef = small_ptr<double>(lay.coef);
+  double* cols = small_ptr<double>(lay.cols);
+  const size_t sd = sizeof(double);
+  const int gp = (pkind == LOBPCG_PRECOND_NONE) ? 0 : (pkind == LOBPCG_PRECOND_DIAG_SIGNED ? 2 : 1);
+
+  // X0: Euclidean Alg. 2, then B-orthonormalised with one B application
+  int rc = ortho_run<double>(V[0], m, 0, m, nullptr, false, tau);
+  if (rc) return rc;
+  rc = apply_b(V[0], m, m, BV[0], m);
+  if (rc) return rc;
+  rc = b_orthonormalize(V[0], BV[0], m, m);
+  if (rc) return rc;
+  rc = apply_op(V[0], m, m, AV[0], m);
+  if (rc) return rc;
+
+  int c = 0, L = m, m_conv = 0;
+  bool first = true, just_restarted = false;
+  std::vector<double> rnorm(m);
+  std::vector<double> th_t(m), rn_t(m);
+  out.converged = false;
+  // the explicit products of a true check: X (B-orthonormalised again), A X
+  // and B X land in V[c], AV[c] and BV[c] (leading dimension m), which the
+  // restart then uses as its basis
+  auto true_check = [&](double* X, int64_t ldx) -> int {
+    int r = apply_b(X, ldx, m, BV[c], m);
+    if (r) return r;
+    HIPCHK(hipMemcpy2DAsync(V[c], sd * m, X, sd * ldx, sd * m, n, hipMemcpyDeviceToDevice, stream));
+    r = b_orthonormalize(V[c], BV[c], m, m);
+    if (r) return r;
+    r = apply_op(V[c], m, m, AV[c], m);
+    if (r) return r;
+    // Rayleigh quotients, then the residuals with them
+    double* thd = small_ptr<double>(lay.theta) + 64;
+    HIPCHK(gen_colstats(V[c], m, AV[c], BV[c], m, m, theta, n, part, cols, stream));
+    const void* rbp = nullptr;
+    r = readback(cols, sd * 3 * m, &rbp);
+    if (r) return r;
+    const double* h = static_cast<const double*>(rbp);
+    for (int j = 0; j < m; ++j) th_t[j] = h[m + j] / h[j];
+    HIPCHK(hipMemcpyAsync(thd, th_t.data(), sd * m, hipMemcpyHostToDevice, stream));
+    HIPCHK(gen_colstats(V[c], m, AV[c], BV[c], m, m, thd, n, part, cols, stream));
+    r = readback(cols, sd * 3 * m, &rbp);
+    if (r) return r;
+    h = static_cast<const double*>(rbp);
+    for (int j = 0; j < m; ++j) rn_t[j] = std::sqrt(std::max(h[2 * m + j], 0.0));
+    stats.true_checks++;
+    return LOBPCG_OK;
+  };
+
+  for (;;) {
+    HIPCHK(gram_f64(V[c], L, L, AV[c], L, L, n, part, a, nullptr, stream));
+    const int want_up = first ? 0 : 1;
+    int a0 = m_conv;
+    int nact = m - a0;
+    HIPCHK(small_rr(a, L, m, a0, want_up, tau, nullptr, 0, theta, U, info, rr_jacobi, stream));
+    int q = m + (want_up ? nact : 0);
+    int ldo = q + nact;
+    RotateArgs ra{};
+    ra.n = n;
+    ra.ldv = L;
+    ra.ldo = ldo;
+    ra.p = L;
+    ra.m = m;
+    ra.q = q;
+    ra.a0 = a0;
+    ra.precond = kPrecNone;
+    ra.U = U;
+    ra.theta = theta;
+    ra.diag = dptr(lay.diag);
+    ra.part = part;
+    ra.resnorm2 = resn2;
+    auto rotate_all = [&]() -> int {
+      HIPCHK(rotate_f64(V[c], AV[c], V[1 - c], AV[1 - c], ra, stream));
+      HIPCHK(tsmm_f64(BV[c], L, L, U, q, BV[1 - c], ldo, n, nullptr, stream));
+      HIPCHK(gen_residual(AV[1 - c], BV[1 - c], ldo, m, theta, a0, gp, dptr(lay.diag),
+                          dptr(lay.bdiag), V[1 - c] + q, ldo, n, part, resn2, stream));
+      return LOBPCG_OK;
+    };
+    rc = rotate_all();
+    if (rc) return rc;
+    const void* rbp = nullptr;
+    rc = readback(resn2, kReadbackBytes, &rbp);
+    if (rc) return rc;
+    const double* hb = static_cast<const double*>(rbp);
+    const int* hinfo = reinterpret_cast<const int*>(hb + 192);
+    if (hinfo[1] != 0) return fail(LOBPCG_ERR_ORTHO_FAILED, "R^p orthonormalisation of u_p failed");
+    stats.rr_eig_fallbacks += hinfo[11];
+    for (int j = 0; j < m; ++j) {
+      rnorm[j] = std::sqrt(hb[j]);
+      if (!std::isfinite(rnorm[j]) || !std::isfinite(hb[64 + j]))
+        return fail(LOBPCG_ERR_NONFINITE, "non-finite Ritz value or residual");
+    }
+    int newc = std::max(m_conv, leading_converged(rnorm, tol));
+    if (just_restarted) newc = std::min(newc, k - 1);
+    just_restarted = false;
+    if (newc >= k) {
+      rc = true_check(V[1 - c], ldo);
+      if (rc) return rc;
+      double worst = 0.0;
+      for (int j = 0; j < k; ++j) worst = std::max(worst, rn_t[j]);
+      if (worst <= tol && stats.restarts >= force_restarts) {
+        out.converged = true;
+        out.X = V[c];
+        out.ld = m;
+        break;
+      }
+      // restart from the checked X, A X, B X (now in V[c], AV[c], BV[c])
+      stats.restarts++;
+      L = m;
+      first = true;
+      m_conv = 0;
+      just_restarted = true;
+      continue;
+    }
+    if (newc != m_conv) {
+      stats.relocks++;
+      m_conv = newc;
+      a0 = m_conv;
+      nact = m - a0;
+      HIPCHK(small_rr(a, L, m, a0, want_up, tau, nullptr, 0, theta, U, info, rr_jacobi, stream));
+      q = m + (want_up ? nact : 0);
+      ldo = q + nact;
+      ra.ldo = ldo;
+      ra.q = q;
+      ra.a0 = a0;
+      rc = rotate_all();
+      if (rc) return rc;
+    }
+    if (iter >= max_iter) {
+      rc = true_check(V[1 - c], ldo);
+      if (rc) return rc;
+      out.X = V[c];
+      out.ld = m;
+      break;
+    }
+    ++iter;
+    // W^ = ortho(W~, (BX, BP)) with Y = [X P] = columns [0, q) of V[1-c]
+    double* Vn = V[1 - c];
+    double* BVn = BV[1 - c];
+    double* W = Vn + q;
+    HIPCHK(gram_f64(BVn, ldo, q, W, ldo, nact, n, part, C, nullptr, stream));
+    double cmax = INFINITY;
+    for (int pass = 0; pass < ortho_max_outer; ++pass) {
+      HIPCHK(gen_proj_coef(C, q, nact, coef, cols, stream));
+      HIPCHK(tsmm_f64(Vn, ldo, q + nact, coef, nact, W, ldo, n, nullptr, stream));
+      stats.against_passes++;
+      rc = ortho_run<double>(W, ldo, 0, nact, nullptr, false, tau);
+      if (rc) return rc;
+      HIPCHK(gram_f64(BVn, ldo, q, W, ldo, nact, n, part, C, nullptr, stream));
+      HIPCHK(gen_proj_coef(C, q, nact, coef, cols, stream));
+      const void* cp = nullptr;
+      rc = readback(cols, sizeof(double), &cp);
+      if (rc) return rc;
+      cmax = *static_cast<const double*>(cp);
+      if (cmax <= tau) break;
+    }
+    if (!(cmax <= tau)) stats.ortho_stalled++;
+    // one application of B, one B-Cholesky reusing it, then A W
+    rc = apply_b(W, ldo, nact, BVn + q, ldo);
+    if (rc) return rc;
+    rc = b_orthonormalize(W, BVn + q, ldo, nact);
+    if (rc) return rc;
+    rc = apply_op(W, ldo, nact, AV[1 - c] + q, ldo);
+    if (rc) return rc;
+    c = 1 - c;
+    L = ldo;
+    first = false;
+  }
+  res_evals.assign(th_t.begin(), th_t.begin() + m);
+  res_resn.assign(rn_t.begin(), rn_t.begin() + m);
+  stats.m_conv = m_conv;
+  return LOBPCG_OK;
+}
+
 int lobpcg_ctx::solve(int k, double tol) {
   const auto t0 = std::chrono::steady_clock::now();
   if (op == kOpNone) return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
@@ -898,6 +1151,28 @@ int lobpcg_ctx::solve(int k, double tol) {
   }
   int iter = 0;
   PhaseOut po{};
+  if (bop != kOpNone) {
+    if (dav || precision != LOBPCG_PREC_FP64 ||
+        (pkind != LOBPCG_PRECOND_NONE && pkind != LOBPCG_PRECOND_DIAG &&
+         pkind != LOBPCG_PRECOND_DIAG_SIGNED))
+      return fail(LOBPCG_ERR_UNSUPPORTED,
+                  "the generalized problem runs LOBPCG in fp64 with the Jacobi preconditioners");
+    if (pkind != LOBPCG_PRECOND_NONE) {
+      rc = ensure_bdiag();
+      if (rc) return rc;
+    }
+    rc = run_generalized(k, tol, iter, po);
+    if (rc) return rc;
+    res_k = k;
+    res_X = reinterpret_cast<const double*>(po.X);
+    res_ld = po.ld;
+    have_result = true;
+    stats.iterations = iter;
+    stats.converged = po.converged ? 1 : 0;
+    stats.ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return po.converged ? LOBPCG_OK : LOBPCG_NOT_CONVERGED;
+  }
   if (dav) {
     rc = run_davidson(k, tol, iter, po);
     if (rc) return rc;
@@ -1155,6 +1430,53 @@ int lobpcg_set_operator_kronsum(lobpcg_t h, int64_t na, const double* A, const d
   h->tri_ready = false;
   h->op32_ready = false;
   h->have_result = false;
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_operator_b_csr(lobpcg_t h, const int32_t* row_ptr, const int32_t* col,
+                              const double* val, int64_t nnz) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  h->have_result = false;
+  h->bdiag_ready = false;
+  if (row_ptr == nullptr) {  // back to the standard problem
+    h->bop = kOpNone;
+    return LOBPCG_OK;
+  }
+  if (nnz < 1 || nnz > INT32_MAX || col == nullptr || val == nullptr)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad CSR arrays for B");
+  {
+    hipError_t e = hipSetDevice(h->device);
+    int* bad = nullptr;
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&bad), sizeof(int));
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), h->stream);
+    if (e == hipSuccess) e = csr_check(row_ptr, col, h->n, nnz, bad, h->stream);
+    int hb = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (bad != nullptr) (void)hipFree(bad);
+    if (e != hipSuccess) return h->hip_fail(e, "CSR check (B)");
+    if (hb != 0) return h->fail(LOBPCG_ERR_INVALID_ARG, "malformed CSR for B");
+  }
+  h->bop = kOpCsr;
+  h->brp = row_ptr;
+  h->bci = col;
+  h->bval = val;
+  h->bnnz = nnz;
+  return LOBPCG_OK;
+}
+
+int lobpcg_set_operator_b_dense(lobpcg_t h, const double* B, int64_t ldb) {
+  if (h == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  h->have_result = false;
+  h->bdiag_ready = false;
+  if (B == nullptr) {
+    h->bop = kOpNone;
+    return LOBPCG_OK;
+  }
+  if (ldb < h->n) return h->fail(LOBPCG_ERR_INVALID_ARG, "bad dense B");
+  h->bop = kOpDense;
+  h->Bd = B;
+  h->ldb = ldb;
   return LOBPCG_OK;
 }
 

@@ -1,0 +1,142 @@
+"""The generalized problem A x = lambda B x (Sec. 3.3) on the GPU through
+the C ABI: against scipy's dense eigh(A, B) (the definition), the oracle's
+generalized LOBPCG, the B = I reduction to the standard solve and the
+diagonal closed form.  Bar: ||A x - theta B x|| <= tol recomputed on the
+CPU from the returned vectors, X^T B X = I to 1e-12, eigenvalues within
+1e-9 max(|lambda|, 1e-3 ||A||); iteration counts within max(3, 10 %) of the
+oracle's (rounding-sensitive, a soft check)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import synth
+from oracle import lobpcg_oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_06668_amd as P
+
+    return P
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def check(res, A, B, lam, tol, normA):
+    assert res.status == 0, res.stats
+    X = res.evecs.cpu().numpy()
+    AX, BX = A @ X, B @ X
+    th = np.einsum("ij,ij->j", X, AX) / np.einsum("ij,ij->j", X, BX)
+    r = np.linalg.norm(AX - BX * th, axis=0)
+    assert np.all(r <= tol * 1.0001), r
+    G = X.T @ BX
+    assert np.abs(G - np.eye(X.shape[1])).max() < 1e-12
+    assert np.all(np.abs(res.evals - lam) <= 1e-9 * np.maximum(np.abs(lam), 1e-3 * normA)), (res.evals, lam)
+    assert np.allclose(res.resnorms, r, rtol=1e-3, atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [400, 2000])
+def test_generalized_dense_vs_eigh(P, n):
+    k = 4
+    A = synth.dense_dd(n, seed=5)
+    g = synth.rng(9)
+    B = np.diag(g.uniform(1.0, 2.0, n)) + synth.random_symmetric(n, 6, 1e-3)
+    lam = sla.eigh(A, B, eigvals_only=True, subset_by_index=[0, k - 1])
+    X0 = synth.start_block(n, k, 2)
+    s = P.Solver(n)
+    s.set_operator_dense(cu(A))
+    s.set_operator_b_dense(cu(B))
+    s.set_preconditioner(P.PRECOND_DIAG)
+    s.set_initial_guess(cu(X0))
+    res = s.solve(k, 1e-9)
+    ora = O.lobpcg_generalized(O.dense_operator(A), O.dense_operator(B), X0, k, 1e-9, dA=np.diag(A).copy(),
+                               dB=np.diag(B).copy())
+    say(n, "gpu", res.stats["iterations"], res.stats["b_matvec_columns"], "oracle", ora.iterations)
+    check(res, A, B, lam, 1e-9, normA=abs(lam).max() + 100)
+    assert abs(res.stats["iterations"] - ora.iterations) <= max(3, 0.1 * ora.iterations)
+
+
+def test_generalized_csr_vs_oracle(P):
+    n, k = 20000, 8
+    C = synth.csr_banded(n=n, seed=21, band=600, diag_slope=10.0 / n)
+    Asp = C.to_scipy()
+    bd = synth.rng(3).uniform(1.0, 2.0, n)
+    off = 0.1 * np.minimum(bd[:-1], bd[1:])
+    Bsp = sp.diags([off, bd, off], [-1, 0, 1]).tocsr()
+    Bsp.sort_indices()
+    X0 = synth.start_block(n, k, 22)
+    s = P.Solver(n)
+    s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val))
+    s.set_operator_b_csr(cu(Bsp.indptr.astype(np.int32)), cu(Bsp.indices.astype(np.int32)), cu(Bsp.data))
+    s.set_preconditioner(P.PRECOND_DIAG)
+    s.set_initial_guess(cu(X0))
+    res = s.solve(k, 1e-8)
+    ora = O.lobpcg_generalized(lambda X: Asp @ X, lambda X: Bsp @ X, X0, k, 1e-8, dA=C.diag, dB=bd)
+    say("csr gpu", res.stats["iterations"], "oracle", ora.iterations, ora.converged)
+    assert ora.converged
+    check(res, Asp, Bsp, ora.evals, 1e-8, normA=11.0)
+    assert abs(res.stats["iterations"] - ora.iterations) <= max(3, 0.1 * ora.iterations)
+
+
+def test_generalized_identity_b_is_standard(P):
+    n, k = 2000, 4
+    A = synth.dense_dd(n, seed=5)
+    X0 = synth.start_block(n, k, 2)
+    I = sp.identity(n, format="csr")
+    out = []
+    for with_b in (False, True):
+        s = P.Solver(n)
+        s.set_operator_dense(cu(A))
+        if with_b:
+            s.set_operator_b_csr(cu(I.indptr.astype(np.int32)), cu(I.indices.astype(np.int32)), cu(I.data))
+        s.set_preconditioner(P.PRECOND_DIAG)
+        s.set_initial_guess(cu(X0))
+        out.append(s.solve(k, 1e-9))
+    r0, r1 = out
+    say("B=I", r0.stats["iterations"], r1.stats["iterations"])
+    assert r0.status == 0 and r1.status == 0
+    assert abs(r0.stats["iterations"] - r1.stats["iterations"]) <= 2
+    assert np.all(np.abs(r0.evals - r1.evals) <= 1e-12 * np.abs(r0.evals))
+
+
+def test_generalized_diagonal_closed_form(P):
+    n, k = 3000, 5
+    g = synth.rng(12)
+    a, b = g.uniform(1.0, 50.0, n), g.uniform(0.5, 3.0, n)
+    idx = np.arange(n, dtype=np.int32)
+    rp = np.arange(n + 1, dtype=np.int32)
+    s = P.Solver(n)
+    s.set_operator_csr(cu(rp), cu(idx), cu(a))
+    s.set_operator_b_csr(cu(rp), cu(idx), cu(b))
+    s.set_preconditioner(P.PRECOND_DIAG)
+    s.set_initial_guess(cu(synth.start_block(n, 8, 1)))
+    res = s.solve(k, 1e-10)
+    A, B = sp.diags(a).tocsr(), sp.diags(b).tocsr()
+    check(res, A, B, np.sort(a / b)[:k], 1e-10, normA=50.0)
+
+
+def test_generalized_unsupported_modes(P):
+    n = 300
+    A = synth.dense_dd(n, seed=1)
+    s = P.Solver(n)
+    s.set_operator_dense(cu(A))
+    s.set_operator_b_dense(cu(np.eye(n)))
+    s.set_initial_guess(cu(synth.start_block(n, 3, 1)))
+    for key, val in ((P.OPT_PRECISION, P.PREC_FP32), (P.OPT_METHOD, P.METHOD_DAVIDSON)):
+        s.set_option(key, val)
+        with pytest.raises(P.LobpcgError) as e:
+            s.solve(3, 1e-8)
+        assert e.value.status == P.ERR_UNSUPPORTED
+        s.set_option(key, 0)
