@@ -193,6 +193,8 @@ hipError_t gen_colstats(const double* X, int64_t ldx, const double* AX, const do
 hipError_t gen_proj_coef(const double* C, int ny, int nw, double* coef, double* cmax, hipStream_t s);
 // out = L^-T (p x p, p <= kMaxBlock)
 hipError_t gen_lt_inv(const double* L, int p, double* out, hipStream_t s);
+// *out = max |x_i| (part: 1024 doubles; out must not lie in part)
+hipError_t vec_max_abs(const double* x, int64_t len, double* part, double* out, hipStream_t s);
 
 // ---- tridiagonal preconditioner (k_tri.hip) ------------------------------
 constexpr int kTriMaxChunks = 1024;

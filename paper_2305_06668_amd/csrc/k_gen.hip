@@ -192,4 +192,31 @@ hipError_t gen_lt_inv(const double* L, int p, double* out, hipStream_t s) {
   return hipGetLastError();
 }
 
+// *out = max_i |x_i| over len values: per-block maxima, then one block
+__global__ __launch_bounds__(256) void k_max_abs_part(const double* __restrict__ x, int64_t len,
+                                                      double* __restrict__ part) {
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    mx = fmax(mx, fabs(x[i]));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+hipError_t vec_max_abs(const double* x, int64_t len, double* part, double* out, hipStream_t s) {
+  if (len < 1) return hipErrorInvalidValue;
+  const int nb = (int)std::min<int64_t>(1024, (len + 255) / 256);
+  hipLaunchKernelGGL(k_max_abs_part, dim3(nb), dim3(256), 0, s, x, len, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_max_abs_part, dim3(1), dim3(256), 0, s, part, (int64_t)nb, out);
+  return hipGetLastError();
+}
+
 }  // namespace lobpcg

@@ -196,8 +196,10 @@ int lobpcg_ctx::ensure_op32() {
     case kOpKron:
       HIPCHK(convert_vec_f64_to_f32(A, o32, na * na, stream));
       HIPCHK(convert_vec_f64_to_f32(Vpot, o32 + na * na, na * na, stream));
+      // ||H|| <= 2 max_i sum_j |A_ij| + max |V_ij| (the diag(vec V) term
+      // contributes its largest entry, not a row sum of V)
       HIPCHK(dense_norm_bound(A, na, na, part, nb, stream));
-      HIPCHK(dense_norm_bound(Vpot, na, na, part, nb + 1, stream));
+      HIPCHK(vec_max_abs(Vpot, na * na, part, nb + 1, stream));
       break;
     default: return fail(LOBPCG_ERR_BAD_STATE, "no operator set");
   }
