@@ -239,6 +239,182 @@ def generalized_line(P, synth, torch, dev, C, X0, k, tol, steps, warmup):
     }
 
 
+def family_bench(P, synth, torch, dev, args):
+    """The preconditioner-study configuration (stand-in for Sec. 4.4): the
+    csr_family matrices (n = 2e5, ~31 stored entries per row, dominance ratio
+    rho ~ U(0.3, 3) per matrix), k = block = 32, tol 1e-8.  The learned
+    preconditioner trains on indices [0, train) of the 192 training indices
+    (a labelled subset), validated on index 191; every variant is then
+    solved on held-out indices [192, 192 + held_out) (a labelled subset of
+    the 64).  Prints one JSON line with per-variant medians, IQRs and
+    converged counts of iterations and time."""
+    from paper_2305_06668_amd import learn
+
+    n, k, tol = args.family_n, 32, args.tol
+
+    def solver_for(idx):
+        C, rho = synth.csr_family(idx, n=n)
+        st = P.Solver(n)
+        st.set_operator_csr(*(torch.from_numpy(a).to(dev) for a in (C.row_ptr, C.col, C.val)))
+        st.set_preconditioner(P.PRECOND_DIAG)
+        st.set_initial_guess(torch.from_numpy(synth.start_block(n, k, 2305600 + idx)).to(dev))
+        return st, rho
+
+    t0 = time.perf_counter()
+    trainers = [solver_for(i)[0] for i in range(args.family_train)]
+    val, _ = solver_for(191)
+
+    def validate(w):
+        val.set_learned_weights(w)
+        val.set_preconditioner(P.PRECOND_LEARNED)
+        val.set_option(P.OPT_PRECISION, P.PREC_FP32)
+        r = val.solve(k, tol, want_vectors=False)
+        return r.stats["iterations"] if r.status == P.OK else 10**6
+
+    rep = learn.train(trainers, k, steps=args.family_steps, cols_per_step=k, lr=1e-3,
+                      chunks=args.family_chunks, validate=validate)
+    for st in trainers + [val]:
+        st.close()
+    setup = time.perf_counter() - t0
+    log(f"family: trained on {args.family_train} matrices in {setup:.1f} s, validation "
+        f"{[c['score'] for c in rep.log]} (kept {rep.best_chunk})")
+    variants = {
+        "jacobi": dict(prec=P.PREC_FP64, pc=P.PRECOND_DIAG, method=P.METHOD_LOBPCG),
+        "tridiag": dict(prec=P.PREC_FP64, pc=P.PRECOND_TRIDIAG, method=P.METHOD_LOBPCG),
+        "davidson_jacobi": dict(prec=P.PREC_FP64, pc=P.PRECOND_DIAG, method=P.METHOD_DAVIDSON),
+        "mixed_jacobi": dict(prec=P.PREC_FP32, pc=P.PRECOND_DIAG, method=P.METHOD_LOBPCG),
+        "learned+mixed": dict(prec=P.PREC_FP32, pc=P.PRECOND_LEARNED, method=P.METHOD_LOBPCG),
+    }
+    rows = {v: [] for v in variants}
+    for idx in range(192, 192 + args.family_held_out):
+        st, rho = solver_for(idx)
+        st.set_learned_weights(rep.weights)
+        line = [f"matrix {idx} rho {rho:.2f}:"]
+        for name, cfg in variants.items():
+            st.set_option(P.OPT_METHOD, cfg["method"])
+            st.set_option(P.OPT_PRECISION, cfg["prec"])
+            st.set_preconditioner(cfg["pc"])
+            st.set_option(P.OPT_MAX_ITER, 5000)
+            st.solve(k, tol, want_vectors=False)  # warm-up (workspace, features)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = st.solve(k, tol, want_vectors=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            rows[name].append(dict(idx=idx, rho=rho, iterations=r.stats["iterations"], seconds=dt,
+                                   converged=r.status == P.OK, max_resid=float(r.resnorms.max())))
+            line.append(f"{name} {r.stats['iterations']} it {dt*1e3:.0f} ms")
+        st.close()
+        log(" ".join(line))
+
+    def summary(v):
+        it = np.array([r["iterations"] for r in v], dtype=float)
+        tt = np.array([r["seconds"] for r in v])
+        return {
+            "iterations_median": float(np.median(it)),
+            "iterations_iqr": [float(np.percentile(it, 25)), float(np.percentile(it, 75))],
+            "seconds_median": float(np.median(tt)),
+            "seconds_iqr": [float(np.percentile(tt, 25)), float(np.percentile(tt, 75))],
+            "converged": int(sum(r["converged"] for r in v)),
+            "solves": len(v),
+        }
+
+    out = {
+        "mode": "preconditioner study (csr_family)",
+        "workload": f"csr_family n={n} k=block={k} tol={tol:g}; held-out indices 192..{191 + args.family_held_out} "
+        f"(subset of the 64), training indices 0..{args.family_train - 1} (subset of the 192)",
+        "learned_training": {"setup_s": setup, "steps": args.family_steps, "chunks": args.family_chunks,
+                             "validation_iterations": [c["score"] for c in rep.log], "kept_chunk": rep.best_chunk,
+                             "loss_first": rep.loss_first, "loss_last": rep.loss_last},
+        "variants": {v: summary(r) for v, r in rows.items()},
+        "per_matrix": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def kron_solve(P, synth, torch, dev, args):
+    """The matrix-free Kronecker-sum workload (stand-in for the paper's Full
+    CI sigma, Sec. 4.1): H = A (x) I + I (x) A + diag(vec V), na = 4096
+    (n = 16.8M), k = 8, tol 1e-8.  Variants: plain fp64 with block k and
+    block k + 5 (Sec. 4.1 adds 5 vectors), mixed (fp32 MFMA operator, then
+    fp64), and learned + mixed with block k + 5, the net trained on smaller
+    members of the same generator (na = 256, other seeds).  Each solve is
+    reported as time to tolerance, or NOT_CONVERGED with its residuals at
+    max_iter."""
+    from paper_2305_06668_amd import learn
+
+    na, k, tol = args.kron_na, 8, args.tol
+    n = na * na
+    mseed, xseed = synth.SEEDS["kronsum"]
+    A, V = synth.kronsum(na=na, seed=mseed)
+    s = P.Solver(n)
+    s.set_operator_kronsum(torch.from_numpy(A).to(dev), torch.from_numpy(V).to(dev))
+    s.set_preconditioner(P.PRECOND_DIAG)
+    s.set_option(P.OPT_MAX_ITER, args.kron_max_iter)
+    X0 = torch.from_numpy(synth.start_block(n, k + 5, xseed)).to(dev)
+    # learned preconditioner: trained on na = 256 members of the generator
+    t0 = time.perf_counter()
+    trainers = []
+    for i in range(3):
+        At, Vt = synth.kronsum(na=256, seed=mseed + 1000 + i)
+        st = P.Solver(256 * 256)
+        st.set_operator_kronsum(torch.from_numpy(At).to(dev), torch.from_numpy(Vt).to(dev))
+        st.set_preconditioner(P.PRECOND_DIAG)
+        st.set_initial_guess(torch.from_numpy(synth.start_block(256 * 256, k + 5, xseed + 1000 + i)).to(dev))
+        trainers.append(st)
+    Av, Vv = synth.kronsum(na=256, seed=mseed + 2000)
+    val = P.Solver(256 * 256)
+    val.set_operator_kronsum(torch.from_numpy(Av).to(dev), torch.from_numpy(Vv).to(dev))
+    val.set_initial_guess(torch.from_numpy(synth.start_block(256 * 256, k + 5, xseed + 2000)).to(dev))
+
+    def validate(w):
+        val.set_learned_weights(w)
+        val.set_preconditioner(P.PRECOND_LEARNED)
+        val.set_option(P.OPT_PRECISION, P.PREC_FP32)
+        r = val.solve(k, tol, want_vectors=False)
+        return r.stats["iterations"] if r.status == P.OK else 10**6
+
+    rep = learn.train(trainers, k + 5, steps=300, cols_per_step=k + 5, lr=1e-3, chunks=6, validate=validate)
+    for st in trainers + [val]:
+        st.close()
+    setup = time.perf_counter() - t0
+    log(f"kron-solve: learned preconditioner trained in {setup:.1f} s, validation {[c['score'] for c in rep.log]}")
+    s.set_learned_weights(rep.weights)
+    variants = [
+        ("plain_block8", k, P.PREC_FP64, P.PRECOND_DIAG),
+        ("plain_block13", k + 5, P.PREC_FP64, P.PRECOND_DIAG),
+        ("mixed_block13", k + 5, P.PREC_FP32, P.PRECOND_DIAG),
+        ("learned+mixed_block13", k + 5, P.PREC_FP32, P.PRECOND_LEARNED),
+    ]
+    out = {"mode": "kron-solve", "workload": f"kronsum na={na} n={n} k={k} tol={tol:g}",
+           "max_iter": args.kron_max_iter, "learned_training_s": setup,
+           "validation_iterations": [c["score"] for c in rep.log], "variants": {}}
+    evals = {}
+    for name, m, prec, pc in variants:
+        s.set_initial_guess(X0[:, :m])
+        s.set_option(P.OPT_PRECISION, prec)
+        s.set_preconditioner(pc)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = s.solve(k, tol, want_vectors=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        st = r.stats
+        status = "ok" if r.status == P.OK else "NOT_CONVERGED"
+        log(f"[{name}] {status} {st['iterations']} iterations, {dt:.2f} s, switch {st['precision_switch_iter']}, "
+            f"max resid {r.resnorms.max():.2e}, evals {np.round(r.evals, 6).tolist()}")
+        evals[name] = r.evals
+        out["variants"][name] = {"status": status, "iterations": st["iterations"], "seconds": dt,
+                                 "precision_switch_iter": st["precision_switch_iter"],
+                                 "resnorms": r.resnorms.tolist(), "evals": r.evals.tolist(),
+                                 "matvec_columns": st["matvec_columns"]}
+    conv = [v for v in evals if out["variants"][v]["status"] == "ok"]
+    if len(conv) > 1:
+        ref = evals[conv[0]]
+        out["max_eval_spread_between_converged"] = float(max(np.abs(evals[v] - ref).max() for v in conv))
+    print(json.dumps(out), flush=True)
+
+
 def dense_only(P, synth, torch, dev, n=20_000, m=8, reps=20):
     """Times Y = A W for the dense Hessian-like operator at its full size."""
     A = synth.dense_hessian(n, seed=synth.SEEDS["dense_hessian"][0])
@@ -293,6 +469,20 @@ def main():
         help="skip the solves: time the Kronecker-sum operator at na = 4096 (n = 16.8M) on 8 "
         "fp64 columns and print its MFMA rate",
     )
+    ap.add_argument("--kron-solve", action="store_true",
+                    help="time-to-tolerance of the Kronecker-sum workload (na = 4096, k = 8): plain fp64 with "
+                    "block 8 and 13, mixed and learned + mixed with block 13")
+    ap.add_argument("--kron-na", type=int, default=4096)
+    ap.add_argument("--kron-max-iter", type=int, default=1500)
+    ap.add_argument("--family", action="store_true",
+                    help="the preconditioner-study configuration (csr_family, n = 2e5, k = 32): train the learned "
+                    "preconditioner on a subset of the training indices, solve held-out matrices with every "
+                    "variant, print per-variant distributions")
+    ap.add_argument("--family-n", type=int, default=200_000)
+    ap.add_argument("--family-train", type=int, default=16)
+    ap.add_argument("--family-held-out", type=int, default=16)
+    ap.add_argument("--family-steps", type=int, default=600)
+    ap.add_argument("--family-chunks", type=int, default=6)
     ap.add_argument(
         "--tridiag",
         action="store_true",
@@ -328,6 +518,12 @@ def main():
         return
     if args.tridiag:
         tridiag_only(P, synth, torch, dev)
+        return
+    if args.family:
+        family_bench(P, synth, torch, dev, args)
+        return
+    if args.kron_solve:
+        kron_solve(P, synth, torch, dev, args)
         return
     n, k = args.n, args.k
     mseed, xseed = synth.SEEDS["csr_banded"]
