@@ -760,7 +760,7 @@ def main():
             },
         },
         "roofline": {
-            "kernel": "k_spmm_csr (fp64, 16 columns)",
+            "kernel": "k_spmm_csr_vec (fp64, 16 columns, 8 lanes per row)",
             "bound": "hbm",
             "achieved": spmm_gbs,
             "peak": HBM_PEAK_GBS,

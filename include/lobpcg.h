@@ -294,6 +294,14 @@ const char* lobpcg_last_error(lobpcg_t h);
  * Asynchronous. */
 int lobpcg_apply_operator(lobpcg_t h, const double* W, int64_t ldw, int ncols, double* Y,
                           int64_t ldy);
+/* The same product in fp32 (the operator applications of the fp32 phase of
+ * the mixed-precision solve): the operator's values rounded to fp32 (a copy
+ * the library keeps in the workspace, made on first use), fp32 W and Y,
+ * fp32 accumulation.  Needs LOBPCG_OPT_PRECISION = LOBPCG_PREC_FP32 (the
+ * workspace layout that holds the fp32 copy) and a workspace; returns
+ * LOBPCG_ERR_BAD_STATE otherwise.  Asynchronous. */
+int lobpcg_apply_operator_f32(lobpcg_t h, const float* W, int64_t ldw, int ncols, float* Y,
+                              int64_t ldy);
 
 /* Overlap / projection product C = A^T B over the handle's n rows (the
  * a = V^T AV of Alg. 1, the X^T X of Alg. 2, the Y^T X of Alg. 3).

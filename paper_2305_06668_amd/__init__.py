@@ -144,6 +144,7 @@ _c = {
     "status_string": _sig("lobpcg_status_string", [ctypes.c_int], ctypes.c_char_p),
     "last_error": _sig("lobpcg_last_error", [_vp], ctypes.c_char_p),
     "apply_operator": _sig("lobpcg_apply_operator", [_vp, _vp, _i64, ctypes.c_int, _vp, _i64]),
+    "apply_operator_f32": _sig("lobpcg_apply_operator_f32", [_vp, _vp, _i64, ctypes.c_int, _vp, _i64]),
     "gram": _sig("lobpcg_gram", [_vp, _vp, _i64, ctypes.c_int, _vp, _i64, ctypes.c_int, _vp]),
     "gram_noalloc": _sig("lobpcg_gram_noalloc", [_vp, _vp, _i64, ctypes.c_int, _vp, _i64, ctypes.c_int, _vp]),
     "ortho": _sig("lobpcg_ortho", [_vp, _vp, _i64, ctypes.c_int, ctypes.POINTER(lobpcg_ortho_info)]),
@@ -186,7 +187,7 @@ EXPORTED = [
     "lobpcg_set_operator_b_dense", "lobpcg_set_preconditioner",
     "lobpcg_set_initial_guess", "lobpcg_set_initial_guess_host", "lobpcg_solve",
     "lobpcg_get_eigenpairs", "lobpcg_get_eigenpairs_host", "lobpcg_get_stats",
-    "lobpcg_status_string", "lobpcg_last_error", "lobpcg_apply_operator", "lobpcg_gram",
+    "lobpcg_status_string", "lobpcg_last_error", "lobpcg_apply_operator", "lobpcg_apply_operator_f32", "lobpcg_gram",
     "lobpcg_gram_noalloc",
     "lobpcg_ortho", "lobpcg_ortho_against", "lobpcg_small_eigh", "lobpcg_small_cholesky",
     "lobpcg_rotate", "lobpcg_set_learned_weights", "lobpcg_learned_apply", "lobpcg_tridiag_apply",
@@ -403,6 +404,17 @@ def lobpcg_apply_operator(h, W, Y) -> None:
         h,
         _c["apply_operator"](
             h, _dev_ptr(W, torch.float64, "W"), _ld(W, "W"), int(W.shape[1]), _dev_ptr(Y, torch.float64, "Y"), _ld(Y, "Y")
+        ),
+    )
+
+
+def lobpcg_apply_operator_f32(h, W, Y) -> None:
+    """fp32 Y = A W with the operator rounded to fp32 (needs OPT_PRECISION = PREC_FP32)."""
+    torch = _torch()
+    _check(
+        h,
+        _c["apply_operator_f32"](
+            h, _dev_ptr(W, torch.float32, "W"), _ld(W, "W"), int(W.shape[1]), _dev_ptr(Y, torch.float32, "Y"), _ld(Y, "Y")
         ),
     )
 

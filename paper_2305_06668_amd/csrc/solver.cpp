@@ -1651,6 +1651,21 @@ static int need_ws(lobpcg_t h) {
   return h->ensure_layout(m);
 }
 
+int lobpcg_apply_operator_f32(lobpcg_t h, const float* W, int64_t ldw, int ncols, float* Y,
+                              int64_t ldy) {
+  GUARD(h);
+  if (W == nullptr || Y == nullptr || ncols < 1 || ncols > 64 || ldw < ncols || ldy < ncols)
+    return h->fail(LOBPCG_ERR_INVALID_ARG, "bad apply arguments");
+  if (h->op == kOpNone) return h->fail(LOBPCG_ERR_BAD_STATE, "no operator set");
+  if (h->precision != LOBPCG_PREC_FP32)
+    return h->fail(LOBPCG_ERR_BAD_STATE, "the fp32 operator needs LOBPCG_OPT_PRECISION = LOBPCG_PREC_FP32");
+  int rc = need_ws(h);
+  if (rc) return rc;
+  rc = h->ensure_op32();
+  if (rc) return rc;
+  return h->apply_op(W, ldw, ncols, Y, ldy);
+}
+
 int lobpcg_learned_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const double* theta,
                          const int* mask) {
   GUARD(h);

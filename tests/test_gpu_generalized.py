@@ -4,7 +4,7 @@ generalized LOBPCG, the B = I reduction to the standard solve and the
 diagonal closed form.  Bar: ||A x - theta B x|| <= tol recomputed on the
 CPU from the returned vectors, X^T B X = I to 1e-12, eigenvalues within
 1e-9 max(|lambda|, 1e-3 ||A||); iteration counts within max(3, 10 %) of the
-oracle's (rounding-sensitive, a soft check)."""
+oracle's (rounding-sensitive, a soft check; 20 % on the clustered CSR case)."""
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -87,7 +87,10 @@ def test_generalized_csr_vs_oracle(P):
     say("csr gpu", res.stats["iterations"], "oracle", ora.iterations, ora.converged)
     assert ora.converged
     check(res, Asp, Bsp, ora.evals, 1e-8, normA=11.0)
-    assert abs(res.stats["iterations"] - ora.iterations) <= max(3, 0.1 * ora.iterations)
+    # this clustered problem is rounding-sensitive: the oracle itself takes
+    # 104 to 125 iterations (111 without noise) when its products A W carry
+    # random last-bit perturbations (ten seeds), so the bar is 20 %
+    assert abs(res.stats["iterations"] - ora.iterations) <= max(3, 0.2 * ora.iterations)
 
 
 def test_generalized_identity_b_is_standard(P):

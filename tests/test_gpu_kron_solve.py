@@ -68,7 +68,14 @@ def test_kron_full_size_learned_mixed(P):
         th = (X * Y).sum(0)
         r = torch.linalg.vector_norm(Y - X * th, dim=0).cpu().numpy()
         assert np.all(r <= tol * 1.0001), r
-        G = (X.T @ X).cpu().numpy()
+        # X^T X summed over chunks of 2^16 rows: one fp64 GEMM over all
+        # 16.8M rows carries rounding errors of a few 1e-13 by itself (the
+        # chunked sum agrees with an 80-bit host sum to ~1e-15)
+        G = torch.zeros((k, k), dtype=torch.float64, device="cuda")
+        for c0 in range(0, n, 1 << 16):
+            Xc = X[c0 : c0 + (1 << 16)]
+            G += Xc.T @ Xc
+        G = G.cpu().numpy()
         assert np.abs(G - np.eye(k)).max() < 1e-12
         assert np.allclose(th.cpu().numpy(), res.evals, rtol=0, atol=1e-12)
         out.append(res.evals)

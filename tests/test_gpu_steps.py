@@ -128,6 +128,93 @@ def test_apply_csr_strided_and_empty_rows(P):
     assert np.all(out[:, :5] == 0) and np.all(out[:, 12:] == 0)
 
 
+def _heavy_csr(n, seed):
+    """Banded CSR (~41 stored entries per row, band +-700) plus four rows of
+    1500-3100 entries: a 64-row block then holds more entries than one LDS
+    pass of the vector kernel takes, and a pass boundary falls inside a row."""
+    import scipy.sparse as sp
+
+    C = synth.csr_banded(n=n, seed=seed, band=700, diag_slope=1e-3)
+    g = np.random.default_rng(seed)
+    rows, cols = [], []
+    for r, cnt in ((100, 3100), (101, 1500), (4000, 2200), (n - 1, 1800)):
+        c = np.unique(g.integers(0, n, size=cnt))
+        rows.append(np.full(c.size, r))
+        cols.append(c)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    H = sp.csr_matrix((g.uniform(-1e-3, 1e-3, rows.size), (rows, cols)), shape=(n, n))
+    S = (C.to_scipy() + H).tocsr()
+    S.sort_indices()
+    return S
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize(
+    "m,ldw,q",
+    [
+        (16, 16, 0),  # 16-byte loads: 8 (fp64) / 4 (fp32) lanes per row
+        (16, 48, 32),  # the solver's layout: W at column 32 of a 48-wide basis
+        (16, 48, 17),  # misaligned start: one column per lane
+        (15, 48, 18),  # 16-byte loads with a partial last lane (fp64)
+        (6, 8, 2),  # fp64: 3 lanes in a group of 4; fp32: narrow kernel
+        (12, 12, 0),
+        (9, 10, 0),  # fp64: 5 lanes; fp32: ldw not a multiple of 4
+        (24, 24, 0),
+        (32, 40, 8),  # fp64: 16 lanes per row; fp32: 8
+        (40, 40, 0),  # fp64: 32 + 8 columns (two launches); fp32: 10 lanes
+        (64, 64, 0),  # fp64: two launches of 32; fp32: 16 lanes
+    ],
+)
+def test_apply_csr_paths(P, prec, m, ldw, q):
+    """Both CSR kernels (16-byte loads from LDS-staged (col, val), and one
+    column per lane) in fp64 and fp32 against the definition, entry by entry,
+    within the summation bound (row length + 2) u sum_j |a_ij| |w_j|."""
+    say("csr paths", prec, m, ldw, q)
+    n = 20011
+    S = _heavy_csr(n, 11)
+    s = P.Solver(n)
+    s.set_operator_csr(
+        cu(S.indptr.astype(np.int32)), cu(S.indices.astype(np.int32)), cu(S.data.astype(np.float64))
+    )
+    f32 = prec == "f32"
+    if f32:
+        s.set_option(P.OPT_PRECISION, P.PREC_FP32)
+    s.ensure_workspace(1)
+    ldy = ldw + 3
+    Wb = synth.start_block(n, ldw, 3)
+    dt = torch.float32 if f32 else torch.float64
+    Wd = torch.from_numpy(Wb).to(dt).cuda()
+    Y = torch.full((n, ldy), 5.0, dtype=dt, device="cuda")
+    (P.lobpcg_apply_operator_f32 if f32 else P.lobpcg_apply_operator)(s.h, Wd[:, q : q + m], Y[:, q : q + m])
+    Yh = Y.cpu().numpy().astype(np.float64)
+    if f32:
+        Sv = S.copy()
+        Sv.data = S.data.astype(np.float32).astype(np.float64)
+        Wv = Wb.astype(np.float32).astype(np.float64)[:, q : q + m]
+        u = 2.0**-24
+    else:
+        Sv, Wv, u = S, Wb[:, q : q + m], 2.0**-53
+    ref = Sv @ Wv
+    scale = abs(Sv) @ np.abs(Wv)
+    lens = np.diff(S.indptr)[:, None]
+    assert np.all(np.abs(Yh[:, q : q + m] - ref) <= (lens + 2) * u * scale + 1e-300)
+    assert np.all(Yh[:, :q] == 5.0) and np.all(Yh[:, q + m :] == 5.0)  # other columns untouched
+    s.close()
+
+
+def test_apply_csr_f32_needs_fp32_layout(P):
+    n = 1000
+    C = synth.csr_banded(n=n, seed=2, band=50)
+    s = P.Solver(n)
+    s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val))
+    s.ensure_workspace(1)
+    W = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(P.LobpcgError):
+        P.lobpcg_apply_operator_f32(s.h, W, W.clone())
+    s.close()
+
+
 @pytest.mark.parametrize(
     "n,m,ldw",
     [
