@@ -708,9 +708,50 @@ __host__ __device__ inline int rotate_ldc(int p, int q, size_t tsize) {
   return rotate_smem_bytes(p, q, padded, tsize) <= 150 * 1024 ? padded : q;
 }
 
-// 4 waves per SIMD for every instance (fp64 MTJ = 4: 3), without spills
-template <typename T, int MTJ>
-__global__ __launch_bounds__(256, (MTJ <= 3 ? 4 : 3)) void k_rotate(const T* __restrict__ V,
+// Register prefetch of the next chunk's rows (PF): thread t holds vectors
+// t, t + 256, ... of the 64 x p tile read as 16-byte vectors, at most
+// kPfVec of them per tile (p <= 64); they are loaded while the current
+// chunk is multiplied and written, and stored to LDS at the next chunk.
+template <typename T>
+struct PfTile {
+  static constexpr int VE = 16 / (int)sizeof(T);
+  static constexpr int kPfVec = 64 * 64 / VE / 256;
+  typename Vec16<T>::type v[kPfVec];
+};
+template <typename T>
+__device__ __forceinline__ void pf_load(const T* __restrict__ In, int64_t ld, int p, int64_t row0,
+                                        int rows, PfTile<T>& t) {
+  constexpr int VE = PfTile<T>::VE;
+  const int pv = p / VE, total = 64 * pv;
+#pragma unroll
+  for (int i = 0; i < PfTile<T>::kPfVec; ++i) {
+    const int idx = threadIdx.x + 256 * i;
+    const int r = idx / pv, cv = idx - r * pv;
+    if (idx < total && r < rows)
+      t.v[i] = *reinterpret_cast<const typename Vec16<T>::type*>(In + (row0 + r) * ld + cv * VE);
+    else
+      for (int e = 0; e < VE; ++e) t.v[i][e] = T(0);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void pf_store(const PfTile<T>& t, int p, T* __restrict__ tile) {
+  constexpr int VE = PfTile<T>::VE;
+  const int pv = p / VE, total = 64 * pv, ldt = p + 1;
+#pragma unroll
+  for (int i = 0; i < PfTile<T>::kPfVec; ++i) {
+    const int idx = threadIdx.x + 256 * i;
+    if (idx < total) {
+      const int r = idx / pv, cv = idx - r * pv;
+#pragma unroll
+      for (int e = 0; e < VE; ++e) tile[r * ldt + cv * VE + e] = t.v[i][e];
+    }
+  }
+}
+
+// 4 waves per SIMD for every instance (fp64 MTJ = 4: 3), without spills; the
+// prefetching instances are bound to 2 blocks per CU by their LDS anyway
+template <typename T, int MTJ, bool PF>
+__global__ __launch_bounds__(256, (PF ? 2 : (MTJ <= 3 ? 4 : 3))) void k_rotate(const T* __restrict__ V,
                                                                    const T* __restrict__ AV,
                                                                    T* __restrict__ Vout,
                                                                    T* __restrict__ AVout,
@@ -742,12 +783,32 @@ __global__ __launch_bounds__(256, (MTJ <= 3 ? 4 : 3)) void k_rotate(const T* __r
   }
   const int64_t n = a.n;
   const int64_t nchunks = (n + 63) / 64;
+  PfTile<T> pfv, pfa;
+  if (PF && blockIdx.x < nchunks) {
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int rws = (int)min<int64_t>(64, n - r0);
+    pf_load<T>(V, a.ldv, p, r0, rws, pfv);
+    pf_load<T>(AV, a.ldv, p, r0, rws, pfa);
+  }
   for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
     __syncthreads();
     const int64_t row0 = chunk * 64;
     const int rows = (int)min<int64_t>(64, n - row0);
-    stage_rows<T>(V, a.ldv, p, row0, rows, tV);
-    stage_rows<T>(AV, a.ldv, p, row0, rows, tA);
+    if (PF) {
+      pf_store<T>(pfv, p, tV);
+      pf_store<T>(pfa, p, tA);
+      const int64_t nx = chunk + gridDim.x;
+      if (nx < nchunks) {
+        // the next chunk's loads are in flight during this chunk's work
+        const int64_t r0 = nx * 64;
+        const int rws = (int)min<int64_t>(64, n - r0);
+        pf_load<T>(V, a.ldv, p, r0, rws, pfv);
+        pf_load<T>(AV, a.ldv, p, r0, rws, pfa);
+      }
+    } else {
+      stage_rows<T>(V, a.ldv, p, row0, rows, tV);
+      stage_rows<T>(AV, a.ldv, p, row0, rows, tA);
+    }
     __syncthreads();
     AccT ax[MTJ], aa[MTJ];
 #pragma unroll
@@ -840,20 +901,37 @@ static size_t rotate_smem(int p, int q) {
   return rotate_smem_bytes(p, q, rotate_ldc(p, q, sizeof(T)), sizeof(T));
 }
 
-template <typename T, int MTJ>
-static hipError_t rotate_launch(const T* V, const T* AV, T* Vout, T* AVout, const RotateArgs& a,
-                                hipStream_t s) {
+template <typename T, int MTJ, bool PF>
+static void rotate_kernel_launch(const T* V, const T* AV, T* Vout, T* AVout, const RotateArgs& a,
+                                 int grid, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_rotate<T, MTJ>,
+    (void)hipFuncSetAttribute((const void*)k_rotate<T, MTJ, PF>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     (void)hipGetLastError();
     attr = true;
   }
+  hipLaunchKernelGGL((k_rotate<T, MTJ, PF>), dim3(grid), dim3(256), rotate_smem<T>(a.p, a.q), s, V,
+                     AV, Vout, AVout, a);
+}
+
+template <typename T, int MTJ>
+static hipError_t rotate_launch(const T* V, const T* AV, T* Vout, T* AVout, const RotateArgs& a,
+                                hipStream_t s) {
   const int64_t nchunks = (a.n + 63) / 64;
   const int grid = (int)std::min<int64_t>(nchunks, kStreamBlocks);
-  hipLaunchKernelGGL((k_rotate<T, MTJ>), dim3(grid), dim3(256), rotate_smem<T>(a.p, a.q), s, V, AV,
-                     Vout, AVout, a);
+  // register prefetch: 16-byte rows (p, ld and both bases aligned), p <= 64
+  constexpr int VE = 16 / (int)sizeof(T);
+  const bool pf = a.p <= 64 && a.p % VE == 0 && a.ldv % VE == 0 &&
+                  (reinterpret_cast<uintptr_t>(V) & 15) == 0 &&
+                  (reinterpret_cast<uintptr_t>(AV) & 15) == 0;
+  // (fp64 with four column tiles would spill: it keeps the staged path)
+  if constexpr (sizeof(T) == 8 && MTJ == 4) {
+    rotate_kernel_launch<T, MTJ, false>(V, AV, Vout, AVout, a, grid, s);
+  } else {
+    if (pf) rotate_kernel_launch<T, MTJ, true>(V, AV, Vout, AVout, a, grid, s);
+    else rotate_kernel_launch<T, MTJ, false>(V, AV, Vout, AVout, a, grid, s);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return sum_parts(a.part, grid, a.m, a.resnorm2, nullptr, s);

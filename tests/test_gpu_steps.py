@@ -550,6 +550,46 @@ def test_rotate_definition(P, precond):
     assert np.allclose(host(r2), (R ** 2).sum(0), rtol=1e-12)
 
 
+@pytest.mark.parametrize(
+    "n,m,a0,npw,off",
+    [
+        (200003, 16, 0, 16, 0),  # the benchmark's shape: p = 48, q = 32; ~3 chunks per block, ragged tail
+        (200003, 16, 5, 11, 2),  # p = 38 at a 16-byte aligned column offset
+        (70001, 7, 1, 3, 0),  # odd p: staged path, 1-2 chunks per block
+        (70001, 16, 3, 13, 1),  # misaligned base: staged path
+    ],
+)
+def test_rotate_chunks(P, n, m, a0, npw, off):
+    """The rotation over many 64-row chunks per workgroup (the register
+    prefetch of the next chunk, and the staged path) against V U and AV U."""
+    say("rotate chunks", n, m, a0, npw, off)
+    p = m + 2 * npw
+    q = m + (m - a0)
+    g = synth.rng(n + off)
+    Vf = g.standard_normal((n, p + off))
+    AVf = g.standard_normal((n, p + off))
+    U = g.standard_normal((p, q))
+    theta = np.sort(g.uniform(0.5, 2.0, m))
+    s = P.Solver(n)
+    s.ensure_workspace(m)
+    s.set_preconditioner(0)
+    ldo = q + (m - a0)
+    Vo = torch.zeros((n, ldo), dtype=torch.float64, device="cuda")
+    AVo = torch.zeros((n, ldo), dtype=torch.float64, device="cuda")
+    r2 = torch.zeros(m, dtype=torch.float64, device="cuda")
+    P.lobpcg_rotate(s.h, cu(Vf)[:, off:], cu(AVf)[:, off:], p, cu(U), m, q, cu(theta), a0, Vo, AVo, r2)
+    V, AV = Vf[:, off:], AVf[:, off:]
+    Xn = V @ U
+    AXn = AV @ U
+    R = AXn[:, :m] - Xn[:, :m] * theta
+    vo, avo = host(Vo), host(AVo)
+    assert np.all(np.abs(vo[:, :q] - Xn) <= 1e-13 * (np.abs(V) @ np.abs(U)))
+    assert np.all(np.abs(avo[:, :q] - AXn) <= 1e-13 * (np.abs(AV) @ np.abs(U)))
+    assert np.allclose(vo[:, q:], R[:, a0:], rtol=1e-12, atol=1e-12 * np.abs(R).max())
+    assert np.allclose(host(r2), (R ** 2).sum(0), rtol=1e-12)
+    s.close()
+
+
 def test_apply_dense_column_slice_at_buffer_end(P):
     # W is columns 2..6 of an (n, 8) buffer (16-byte aligned, vector path):
     # the operator must read no W column past the block's own (those of the
