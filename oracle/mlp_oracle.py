@@ -36,12 +36,18 @@ S = sqrt(h^2 + b^2) when h > 0, where the difference form cancels.
 The loss is the mean over columns of log(Delta(t) / Delta(w)), where t is
 the near-exact Jacobi-Davidson correction of the same column (``jd_targets``):
 it is the log of the factor by which the learned step falls short of the
-near-exact solve's step, and its gradient does not depend on t.
+near-exact solve's step.  Its gradient does not depend on t, so a second,
+supervised term ties the learned step to the near-exact one itself: with
+tau = (I - X X^T) t, the column adds mu (1 - cos^2 angle(u, tau)) (``alignment``),
+zero when the learned direction is the near-exact one, one when it is
+orthogonal to it, blind to the scale of w (which the Rayleigh-Ritz step
+ignores too).  mu = 0 leaves the first term alone.
 
 Functions: ``features``, ``forward``, ``backward_dy`` (generic MLP backward
 for an output gradient), ``precondition``, ``decrease`` (Delta),
-``objective`` (loss and analytic gradient with respect to the flat
-parameters), ``adam_step``, ``init_params``, ``jd_targets``.  Everything in
+``alignment`` (the supervised term and its gradient), ``objective`` (loss and
+analytic gradient with respect to the flat parameters), ``adam_step``,
+``init_params``, ``jd_targets``.  Everything in
 float64.
 """
 from __future__ import annotations
@@ -176,9 +182,24 @@ def decrease(A, X: np.ndarray, x: np.ndarray, r: np.ndarray, theta: float, w: np
     return _delta(h, b)[0]
 
 
-def objective(p: Params, A, X: np.ndarray, R: np.ndarray, theta: np.ndarray, cols, d, rho, s, ref=None):
-    """Mean over the columns `cols` of log(ref_j / Delta_j(w_j)) and its
-    gradient with respect to the flat parameters (ref_j = 1 when None)."""
+def alignment(u: np.ndarray, tau: np.ndarray):
+    """1 - cos^2 of the angle between u and tau, and its gradient in u:
+    with c = u.tau, a = u.u, e = tau.tau the value is 1 - c^2 / (a e) and
+    d/du = -2 c / (a e) tau + 2 c^2 / (a^2 e) u.  (0, 0) when tau = 0."""
+    a = float(u @ u)
+    e = float(tau @ tau)
+    if e == 0.0 or a == 0.0:
+        return 0.0, np.zeros_like(u)
+    c = float(u @ tau)
+    return 1.0 - c * c / (a * e), -2.0 * c / (a * e) * tau + 2.0 * c * c / (a * a * e) * u
+
+
+def objective(p: Params, A, X: np.ndarray, R: np.ndarray, theta: np.ndarray, cols, d, rho, s, ref=None,
+              T=None, mu=0.0):
+    """Mean over the columns `cols` of log(ref_j / Delta_j(w_j)) (ref_j = 1
+    when None), plus mu (1 - cos^2 angle(u_j, (I - X X^T) T[:, j])) when the
+    near-exact corrections T (n x m, all columns of the block) are given, and
+    its gradient with respect to the flat parameters."""
     g = np.zeros(n_params(p.W2.shape[0], p.W1.shape[1]))
     L = 0.0
     nc = len(cols)
@@ -200,6 +221,11 @@ def objective(p: Params, A, X: np.ndarray, R: np.ndarray, theta: np.ndarray, col
         cb = -b / (S * D * nc)
         cc = 1.0 / (2.0 * S * nc)
         gu = cb * (r / nu - b * u / nu2) + cc * 2.0 * (Au - cq * u) / nu2
+        if T is not None and mu != 0.0:
+            tau = T[:, j] - X @ (X.T @ T[:, j])
+            la, ga = alignment(u, tau)
+            L += mu * la / nc
+            gu = gu + (mu / nc) * ga
         gw = gu - X @ (X.T @ gu)
         # w = r q^-1/2, q = dm^2 + c^2 (not floored), c = s softplus(y)
         dq = gw * r * (-0.5) * aux["q"] ** -1.5

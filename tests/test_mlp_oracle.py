@@ -66,6 +66,76 @@ def test_objective_gradient_matches_central_differences():
     assert checked > 20
 
 
+def test_alignment_closed_forms():
+    g = np.random.default_rng(5)
+    tau = g.standard_normal(40)
+    assert abs(M.alignment(3.0 * tau, tau)[0]) <= 1e-15  # same direction: 0
+    assert abs(M.alignment(-0.5 * tau, tau)[0]) <= 1e-15  # sign does not matter
+    e1, e2 = np.eye(40)[0], np.eye(40)[1]
+    assert M.alignment(e2, e1)[0] == 1.0  # orthogonal: 1
+    assert abs(M.alignment(e1 + e2, e1)[0] - 0.5) <= 1e-15  # 45 degrees: sin^2 = 1/2
+    u = g.standard_normal(40)
+    v0 = M.alignment(u, tau)[0]
+    assert abs(M.alignment(7.0 * u, 0.01 * tau)[0] - v0) <= 1e-14  # scale-free in both
+    v, gz = M.alignment(u, np.zeros(40))  # no target: no term
+    assert v == 0.0 and not gz.any()
+
+
+def test_alignment_gradient_matches_central_differences():
+    g = np.random.default_rng(6)
+    u, tau = g.standard_normal(30), g.standard_normal(30)
+    _, gr = M.alignment(u, tau)
+    h = 1e-6
+    for i in range(30):
+        up, um = u.copy(), u.copy()
+        up[i] += h
+        um[i] -= h
+        fd = (M.alignment(up, tau)[0] - M.alignment(um, tau)[0]) / (2 * h)
+        assert abs(fd - gr[i]) <= 1e-7 * max(1.0, abs(fd)), (i, fd, gr[i])
+
+
+def test_objective_with_supervision_gradient_matches_central_differences():
+    H = 16
+    A, X, th, R, d, rho, s = block_problem()
+    p = small_net(H=H)
+    cols = [0, 2]
+    T = M.jd_targets(A, X, th, R, rtol=1e-10, maxiter=400)
+    L, gr = M.objective(p, A, X, R, th, cols, d, rho, s, T=T, mu=0.7)
+    L0, _ = M.objective(p, A, X, R, th, cols, d, rho, s)
+    assert L > L0  # the term is >= 0 and the learned step is not the near-exact one
+    v = p.flat()
+    h = 1e-6
+    checked = 0
+    for i in np.linspace(0, v.size - 1, 50).astype(int):
+        vp, vm = v.copy(), v.copy()
+        vp[i] += h
+        vm[i] -= h
+        lp = M.objective(M.Params.from_flat(vp, H=H), A, X, R, th, cols, d, rho, s, T=T, mu=0.7)[0]
+        lm = M.objective(M.Params.from_flat(vm, H=H), A, X, R, th, cols, d, rho, s, T=T, mu=0.7)[0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - gr[i]) <= 1e-6 * max(1e-3, abs(fd)), (i, fd, gr[i])
+        checked += abs(fd) > 1e-6
+    assert checked > 20
+
+
+def test_supervision_sees_only_the_complement_of_the_block():
+    # the target enters through (I - X X^T) t: parts of t inside span(X)
+    # change nothing; mu = 0 is the unsupervised objective exactly
+    H = 16
+    A, X, th, R, d, rho, s = block_problem()
+    p = small_net(H=H)
+    cols = [1, 2]
+    T = M.jd_targets(A, X, th, R, rtol=1e-10, maxiter=400)
+    Tx = T + X @ np.random.default_rng(8).standard_normal((X.shape[1], T.shape[1]))
+    La, ga = M.objective(p, A, X, R, th, cols, d, rho, s, T=T, mu=1.3)
+    Lb, gb = M.objective(p, A, X, R, th, cols, d, rho, s, T=Tx, mu=1.3)
+    assert abs(La - Lb) <= 1e-12 * abs(La)
+    assert np.linalg.norm(ga - gb) <= 1e-10 * np.linalg.norm(ga)
+    L0, g0 = M.objective(p, A, X, R, th, cols, d, rho, s)
+    Lz, gz = M.objective(p, A, X, R, th, cols, d, rho, s, T=T, mu=0.0)
+    assert Lz == L0 and np.array_equal(gz, g0)
+
+
 def test_decrease_is_two_dimensional_rayleigh_ritz():
     # independent: Rayleigh-Ritz on an orthonormal basis of span{x_j, (I - X X^T) w}
     A, X, th, R, d, rho, s = block_problem(n=50, m=4, seed=9)
