@@ -272,7 +272,7 @@ def family_bench(P, synth, torch, dev, args):
         return r.stats["iterations"] if r.status == P.OK else 10**6
 
     rep = learn.train(trainers, k, steps=args.family_steps, cols_per_step=k, lr=1e-3,
-                      chunks=args.family_chunks, validate=validate)
+                      chunks=args.family_chunks, validate=validate, supervision=args.supervision)
     for st in trainers + [val]:
         st.close()
     setup = time.perf_counter() - t0
@@ -325,7 +325,8 @@ def family_bench(P, synth, torch, dev, args):
         f"(subset of the 64), training indices 0..{args.family_train - 1} (subset of the 192)",
         "learned_training": {"setup_s": setup, "steps": args.family_steps, "chunks": args.family_chunks,
                              "validation_iterations": [c["score"] for c in rep.log], "kept_chunk": rep.best_chunk,
-                             "loss_first": rep.loss_first, "loss_last": rep.loss_last},
+                             "loss_first": rep.loss_first, "loss_last": rep.loss_last,
+                             "supervision": args.supervision},
         "variants": {v: summary(r) for v, r in rows.items()},
         "per_matrix": rows,
     }
@@ -456,6 +457,9 @@ def main():
     ap.add_argument("--train-n", type=int, default=200_000)
     ap.add_argument("--train-steps", type=int, default=600)
     ap.add_argument("--train-chunks", type=int, default=24)
+    ap.add_argument("--train-lr", type=float, default=1e-3)
+    ap.add_argument("--supervision", type=float, default=1.0,
+                    help="weight of the training term aligning the learned step with the MINRES correction")
     ap.add_argument("--rr-jacobi", action="store_true", help="Rayleigh-Ritz eigensolves by Jacobi")
     ap.add_argument(
         "--kernels-only",
@@ -600,8 +604,8 @@ def main():
         return total / len(vals)
 
     log(f"training matrices generated ({time.perf_counter() - t_tr:.1f} s)")
-    rep = learn.train(trainers, k, steps=args.train_steps, cols_per_step=k, lr=1e-3, minres_maxiter=100,
-                      chunks=args.train_chunks, validate=validate)
+    rep = learn.train(trainers, k, steps=args.train_steps, cols_per_step=k, lr=args.train_lr, minres_maxiter=100,
+                      chunks=args.train_chunks, validate=validate, supervision=args.supervision)
     log(f"learned preconditioner: {rep.snapshots} snapshots, loss {rep.loss_first:.3f} -> {rep.loss_last:.3f}, "
         f"collect {rep.seconds_collect:.1f} s, train {rep.seconds_train:.1f} s, validation iterations "
         f"{[c['score'] for c in rep.log]} (kept chunk {rep.best_chunk})")
@@ -755,6 +759,8 @@ def main():
                 "kept_chunk": rep.best_chunk,
                 "loss_first": rep.loss_first,
                 "loss_last": rep.loss_last,
+                "supervision": args.supervision,
+                "lr": args.train_lr,
                 "setup_s": train_s,
                 "note": "untimed; same generator, other seeds, n scaled with the diagonal slope",
             },

@@ -398,8 +398,11 @@ int lobpcg_tridiag_apply(lobpcg_t h, double* R, int64_t ldr, int nact, const dou
  *   (I - x_j x_j^T)(A - theta_j I)(I - x_j x_j^T) t = -r_j,  t orthogonal to x_j
  * by MINRES.  The training loss of a column is log(Delta(t_j) / Delta(w_j)),
  * Delta(v) being the decrease of theta_j achieved by the Rayleigh-Ritz step on
- * span{x_j, (I - X X^T) v}, and w_j the learned column; the loss of a step is
- * its mean over the step's columns.  Device buffers are library-owned. */
+ * span{x_j, (I - X X^T) v}, and w_j the learned column, plus (weight mu, 0 by
+ * default) the supervised term mu (1 - cos^2 of the angle between
+ * (I - X X^T) w_j and (I - X X^T) t_j), which ties the learned step to the
+ * near-exact one; the loss of a step is its mean over the step's columns.
+ * Device buffers are library-owned. */
 typedef struct lobpcg_learner* lobpcg_learner_t;
 
 /* Create a learner on `device` with weights drawn from `seed` (layer l
@@ -408,6 +411,10 @@ typedef struct lobpcg_learner* lobpcg_learner_t;
 int lobpcg_learner_create(int device, uint64_t seed, lobpcg_learner_t* out);
 int lobpcg_learner_destroy(lobpcg_learner_t L);
 int lobpcg_learner_set_stream(lobpcg_learner_t L, void* hip_stream);
+/* Weight mu >= 0 (finite) of the supervised term of the loss; 0 turns it
+ * off.  Applies to later lobpcg_learner_objective / lobpcg_learner_train
+ * calls; LOBPCG_ERR_INVALID_ARG for a negative or non-finite mu. */
+int lobpcg_learner_set_supervision(lobpcg_learner_t L, double mu);
 /* Host fp32 weights in, out (LOBPCG_LEARNED_NPARAMS); set resets Adam. */
 int lobpcg_learner_set_weights(lobpcg_learner_t L, const float* w, int64_t count);
 int lobpcg_learner_get_weights(lobpcg_learner_t L, float* w, int64_t count);

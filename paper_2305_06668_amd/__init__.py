@@ -177,6 +177,7 @@ _c = {
         "lobpcg_learner_train",
         [_vp, ctypes.c_int, ctypes.c_int, _dbl, ctypes.c_uint64, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)],
     ),
+    "learner_set_supervision": _sig("lobpcg_learner_set_supervision", [_vp, ctypes.c_double]),
     "learner_last_error": _sig("lobpcg_learner_last_error", [_vp], ctypes.c_char_p),
 }
 
@@ -194,7 +195,7 @@ EXPORTED = [
     "lobpcg_learner_create", "lobpcg_learner_destroy", "lobpcg_learner_set_stream",
     "lobpcg_learner_set_weights", "lobpcg_learner_get_weights", "lobpcg_learner_add_snapshot",
     "lobpcg_learner_snapshot_info", "lobpcg_learner_objective", "lobpcg_learner_train",
-    "lobpcg_learner_last_error",
+    "lobpcg_learner_last_error", "lobpcg_learner_set_supervision",
 ]
 
 
@@ -584,6 +585,11 @@ def lobpcg_learner_set_stream(L, stream_ptr=None) -> None:
 def lobpcg_learner_set_weights(L, w) -> None:
     a = _host_f32(w)
     _lcheck(L, _c["learner_set_weights"](L, a.ctypes.data_as(_vp), a.size))
+
+
+def lobpcg_learner_set_supervision(L, mu: float) -> None:
+    """Weight of the supervised term (alignment with the MINRES corrections)."""
+    _lcheck(L, _c["learner_set_supervision"](L, float(mu)))
 
 
 def lobpcg_learner_get_weights(L) -> np.ndarray:

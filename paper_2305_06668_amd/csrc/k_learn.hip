@@ -76,10 +76,15 @@ __global__ void k_coldots_final(const double* __restrict__ part, int nblk, int c
   out[idx] = s;
 }
 
-// Training objective per column (see mlp_objective_scalars).
+// Training objective per column (see mlp_objective_scalars).  With sdots
+// (u.tau, tau.tau per column) and mu > 0 the supervised term
+// mu (1 - (u.tau)^2 / (u.u tau.tau)) joins the loss, and its gradient in u,
+// -2 mu c / (a e) tau + 2 mu c^2 / (a^2 e) u (c = u.tau, a = u.u, e =
+// tau.tau; divided by nc like the rest), the coefficients of tau (coef4) and u.
 __global__ void k_obj_scalars(const double* __restrict__ dots, const double* __restrict__ theta,
                               const double* __restrict__ ref, int nc, double* __restrict__ coef,
-                              double* __restrict__ out) {
+                              double* __restrict__ out, const double* __restrict__ sdots,
+                              double mu, double* __restrict__ coef4) {
   const int j = threadIdx.x;
   if (j >= nc) return;
   const double uu = dots[j], ru = dots[nc + j], uau = dots[2 * nc + j];
@@ -93,22 +98,37 @@ __global__ void k_obj_scalars(const double* __restrict__ dots, const double* __r
   // dL/db = -(b / S) / (D nc); dL/dcq = (D / (2 S)) / (D nc) = 1 / (2 S nc)
   const double cb = -b / (S * D * nc);
   const double cc = 1.0 / (2.0 * S * nc);
-  coef[j] = cb / nu;                                    // r
-  coef[nc + j] = -cb * b / nu2 - cc * 2.0 * cq / nu2;   // u
-  coef[2 * nc + j] = cc * 2.0 / nu2;                    // P A u
+  double cu = -cb * b / nu2 - cc * 2.0 * cq / nu2;
+  double ct = 0.0, lsup = 0.0;
+  if (sdots != nullptr && mu != 0.0) {
+    const double c = sdots[j], e = sdots[nc + j];
+    if (e > 0.0 && uu > 0.0) {
+      lsup = mu * (1.0 - c * c / (uu * e));
+      ct = -2.0 * mu * c / (uu * e * nc);
+      cu += 2.0 * mu * c * c / (uu * uu * e * nc);
+    }
+  }
+  coef[j] = cb / nu;           // r
+  coef[nc + j] = cu;           // u
+  coef[2 * nc + j] = cc * 2.0 / nu2;  // P A u
+  if (coef4 != nullptr) coef4[j] = ct;  // tau
   out[j] = D;
-  out[nc + j] = (ref ? log(ref[j]) : 0.0) - log(D);
+  out[nc + j] = (ref ? log(ref[j]) : 0.0) - log(D) + lsup;
 }
 
-// Out = a R + b U + c Z  (per-column coefficients)
+// Out = a R + b U + c Z (+ d Tau)  (per-column coefficients)
 __global__ void k_combine3(const double* __restrict__ R, const double* __restrict__ U,
-                           const double* __restrict__ Z, const double* __restrict__ coef, int nc,
-                           int64_t n, double* __restrict__ Out) {
+                           const double* __restrict__ Z, const double* __restrict__ Tau,
+                           const double* __restrict__ coef, const double* __restrict__ coef4,
+                           int nc, int64_t n, double* __restrict__ Out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  for (int j = 0; j < nc; ++j)
-    Out[i * nc + j] = coef[j] * R[i * nc + j] + coef[nc + j] * U[i * nc + j] +
-                      coef[2 * nc + j] * Z[i * nc + j];
+  for (int j = 0; j < nc; ++j) {
+    double o = coef[j] * R[i * nc + j] + coef[nc + j] * U[i * nc + j] +
+               coef[2 * nc + j] * Z[i * nc + j];
+    if (Tau != nullptr) o += coef4[j] * Tau[i * nc + j];
+    Out[i * nc + j] = o;
+  }
 }
 
 // R = AX - X diag(theta)
@@ -267,13 +287,17 @@ hipError_t coldots(int npairs, const double* const* P, const int64_t* ldp, const
   return hipGetLastError();
 }
 hipError_t objective_scalars(const double* dots, const double* theta, const double* ref, int nc,
-                             double* coef, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_obj_scalars, dim3(1), dim3(64), 0, s, dots, theta, ref, nc, coef, out);
+                             double* coef, double* out, const double* sdots, double mu,
+                             double* coef4, hipStream_t s) {
+  hipLaunchKernelGGL(k_obj_scalars, dim3(1), dim3(64), 0, s, dots, theta, ref, nc, coef, out, sdots,
+                     mu, coef4);
   return hipGetLastError();
 }
-hipError_t combine3(const double* R, const double* U, const double* Z, const double* coef, int nc,
-                    int64_t n, double* Out, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine3, dim3(cdiv64(n, 256)), dim3(256), 0, s, R, U, Z, coef, nc, n, Out);
+hipError_t combine3(const double* R, const double* U, const double* Z, const double* Tau,
+                    const double* coef, const double* coef4, int nc, int64_t n, double* Out,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_combine3, dim3(cdiv64(n, 256)), dim3(256), 0, s, R, U, Z, Tau, coef, coef4,
+                     nc, n, Out);
   return hipGetLastError();
 }
 hipError_t residual_block(const double* X, const double* AX, const double* theta, int m,

@@ -26,9 +26,11 @@ hipError_t coldots(int npairs, const double* const* P, const int64_t* ldp, const
                    const int64_t* ldq, int nc, int64_t n, double* part, double* out,
                    hipStream_t s);
 hipError_t objective_scalars(const double* dots, const double* theta, const double* ref, int nc,
-                             double* coef, double* out, hipStream_t s);
-hipError_t combine3(const double* R, const double* U, const double* Z, const double* coef, int nc,
-                    int64_t n, double* Out, hipStream_t s);
+                             double* coef, double* out, const double* sdots, double mu,
+                             double* coef4, hipStream_t s);
+hipError_t combine3(const double* R, const double* U, const double* Z, const double* Tau,
+                    const double* coef, const double* coef4, int nc, int64_t n, double* Out,
+                    hipStream_t s);
 hipError_t residual_block(const double* X, const double* AX, const double* theta, int m,
                           int64_t n, double* R, hipStream_t s);
 hipError_t mr_init(const double* bnorm2, int nc, void* st, hipStream_t s);
@@ -72,6 +74,7 @@ struct Snapshot {
   double* R = nullptr;      // n x m
   double* theta = nullptr;  // m
   double* ref = nullptr;    // m: Delta of the MINRES corrections
+  double* Tp = nullptr;     // n x m: (I - X X^T) times the MINRES corrections
   std::vector<double> th_h, rn_h, ref_h, relres_h;
 };
 
@@ -91,6 +94,7 @@ struct lobpcg_learner {
   void* mrst = nullptr;
   double* pinned = nullptr;
   int adam_t = 0;
+  double mu = 0.0;  // weight of the supervised term (alignment with the corrections)
   std::vector<Snapshot> snaps;
   size_t work_elems = 0;
   double* work[kNumWork] = {};
@@ -106,8 +110,8 @@ struct lobpcg_learner {
   }
   int ensure_work(size_t elems);
   int decrease(Snapshot& S, const double* W0, bool run_mlp, const int* mask, int nc,
-               const double* Rc, const double* thc, const double* refc, bool want_grad,
-               hipStream_t st);
+               const double* Rc, const double* thc, const double* refc, const double* Tc,
+               bool want_grad, hipStream_t st);
   int objective(Snapshot& S, const int* cols, int nc, double* loss, double* grad_host,
                 double* dl, double* dj, bool dev_grad = false);
   int minres(Snapshot& S, int maxit, double rtol);
@@ -118,6 +122,8 @@ struct lobpcg_learner {
   double* s_C() { return small + 512; }                   // 32 * 64
   double* s_thc() { return small + 512 + 2048; }          // 64
   double* s_refc() { return small + 512 + 2048 + 64; }    // 64
+  double* s_sdots() { return small + 2688; }              // 2 * 64: u.tau, tau.tau
+  double* s_coef4() { return small + 2816; }              // 64: coefficient of tau
   double* s_dpart() { return small + 4096; }              // kDotPart
 };
 
@@ -135,11 +141,12 @@ int lobpcg_learner::ensure_work(size_t elems) {
 
 // Delta (and the loss terms) of the columns W (n x nc): W0 is copied into
 // work[1] and, when run_mlp, transformed by the learned preconditioner from
-// the residual columns Rc.  Leaves U = work[2], AU = work[3] and, with
-// want_grad, the gradient of the loss in `grad`.
+// the residual columns Rc.  With Tc (the columns' projected corrections) and
+// mu != 0 the supervised term joins the loss.  Leaves U = work[2],
+// AU = work[3] and, with want_grad, the gradient of the loss in `grad`.
 int lobpcg_learner::decrease(Snapshot& S, const double* W0, bool run_mlp, const int* mask, int nc,
                              const double* Rc, const double* thc, const double* refc,
-                             bool want_grad, hipStream_t st) {
+                             const double* Tc, bool want_grad, hipStream_t st) {
   const int64_t n = S.n;
   const int m = S.m;
   lobpcg_ctx* h = S.h;
@@ -160,11 +167,18 @@ int lobpcg_learner::decrease(Snapshot& S, const double* W0, bool run_mlp, const 
   const double* Q[3] = {U, U, AU};
   const int64_t ld[3] = {nc, nc, nc};
   HIPCHK(coldots(3, P, ld, Q, ld, nc, n, s_dpart(), s_dots(), st));
-  HIPCHK(objective_scalars(s_dots(), thc, refc, nc, s_coef(), s_out(), st));
+  const bool sup = Tc != nullptr && mu != 0.0;
+  if (sup) {
+    const double* Ps[2] = {U, Tc};
+    const double* Qs[2] = {Tc, Tc};
+    HIPCHK(coldots(2, Ps, ld, Qs, ld, nc, n, s_dpart(), s_sdots(), st));
+  }
+  HIPCHK(objective_scalars(s_dots(), thc, refc, nc, s_coef(), s_out(), sup ? s_sdots() : nullptr,
+                           mu, s_coef4(), st));
   if (!want_grad) return LOBPCG_OK;
   HIPCHK(gram_f64(S.X, m, m, AU, nc, nc, n, gpart, s_C(), nullptr, st));
   HIPCHK(project_block(AU, nc, S.X, m, m, s_C(), nc, n, Z, nc, st));
-  HIPCHK(combine3(Rc, U, Z, s_coef(), nc, n, G, st));
+  HIPCHK(combine3(Rc, U, Z, sup ? Tc : nullptr, s_coef(), s_coef4(), nc, n, G, st));
   HIPCHK(mlp_grad(Rc, G, nc, nc, n, thc, h->dptr(h->lay.diag), h->dptr(h->lay.rho),
                   h->small_ptr<double>(h->lay.lscale), w, gpart, grad, st));
   return LOBPCG_OK;
@@ -181,7 +195,12 @@ int lobpcg_learner::objective(Snapshot& S, const int* cols, int nc, double* loss
   HIPCHK(gather_cols(S.R, S.m, dcols, nc, n, Rc, nc, st));
   HIPCHK(gather_cols(S.theta, S.m, dcols, nc, 1, s_thc(), nc, st));
   HIPCHK(gather_cols(S.ref, S.m, dcols, nc, 1, s_refc(), nc, st));
-  int rc = decrease(S, Rc, true, nullptr, nc, Rc, s_thc(), s_refc(),
+  double* Tc = nullptr;
+  if (mu != 0.0) {
+    Tc = work[6];
+    HIPCHK(gather_cols(S.Tp, S.m, dcols, nc, n, Tc, nc, st));
+  }
+  int rc = decrease(S, Rc, true, nullptr, nc, Rc, s_thc(), s_refc(), Tc,
                     dev_grad || grad_host != nullptr, st);
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(pinned, s_out(), sizeof(double) * 2 * 64, hipMemcpyDeviceToHost, st));
@@ -195,7 +214,7 @@ int lobpcg_learner::objective(Snapshot& S, const int* cols, int nc, double* loss
   if (dl) std::memcpy(dl, pinned, sizeof(double) * nc);
   if (grad_host) std::memcpy(grad_host, pinned + 256, sizeof(double) * kMlpParams);
   if (dj) {
-    rc = decrease(S, Rc, true, dones, nc, Rc, s_thc(), nullptr, false, st);
+    rc = decrease(S, Rc, true, dones, nc, Rc, s_thc(), nullptr, nullptr, false, st);
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(pinned, s_out(), sizeof(double) * nc, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -288,8 +307,11 @@ int lobpcg_learner::minres(Snapshot& S, int maxit, double rtol) {
     read_state(j, &b1, &pb);
     S.relres_h[j] = b1 > 0.0 ? pb / b1 : 0.0;
   }
+  // the corrections' components outside span(X), kept for the supervised term
+  HIPCHK(gram_f64(S.X, nc, nc, T, nc, nc, n, gpart, s_C(), nullptr, st));
+  HIPCHK(project_block(T, nc, S.X, nc, nc, s_C(), nc, n, S.Tp, nc, st));
   // Delta of the corrections (no net); T lives in work[7], untouched by decrease
-  int rc = decrease(S, T, false, nullptr, nc, S.R, S.theta, nullptr, false, st);
+  int rc = decrease(S, T, false, nullptr, nc, S.R, S.theta, nullptr, nullptr, false, st);
   if (rc) return rc;
   HIPCHK(hipMemcpyAsync(S.ref, s_out(), sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(pinned, s_out(), sizeof(double) * nc, hipMemcpyDeviceToHost, st));
@@ -360,6 +382,7 @@ int lobpcg_learner_destroy(lobpcg_learner_t L) {
     (void)hipFree(S.R);
     (void)hipFree(S.theta);
     (void)hipFree(S.ref);
+    (void)hipFree(S.Tp);
   }
   for (auto p : L->work)
     if (p) (void)hipFree(p);
@@ -368,6 +391,13 @@ int lobpcg_learner_destroy(lobpcg_learner_t L) {
     if (p) (void)hipFree(p);
   if (L->pinned) (void)hipHostFree(L->pinned);
   delete L;
+  return LOBPCG_OK;
+}
+
+int lobpcg_learner_set_supervision(lobpcg_learner_t L, double mu) {
+  if (L == nullptr) return LOBPCG_ERR_INVALID_ARG;
+  if (!(mu >= 0.0) || !(mu < INFINITY)) return L->fail(LOBPCG_ERR_INVALID_ARG, "mu must be finite and >= 0");
+  L->mu = mu;
   return LOBPCG_OK;
 }
 
@@ -424,11 +454,13 @@ int lobpcg_learner_add_snapshot(lobpcg_learner_t L, lobpcg_t h, const double* X,
     (void)hipFree(S.R);
     (void)hipFree(S.theta);
     (void)hipFree(S.ref);
+    (void)hipFree(S.Tp);
   };
   hipError_t e = hipMalloc(&S.X, sizeof(double) * n * m);
   if (e == hipSuccess) e = hipMalloc(&S.R, sizeof(double) * n * m);
   if (e == hipSuccess) e = hipMalloc(&S.theta, sizeof(double) * m);
   if (e == hipSuccess) e = hipMalloc(&S.ref, sizeof(double) * m);
+  if (e == hipSuccess) e = hipMalloc(&S.Tp, sizeof(double) * n * m);
   if (e == hipSuccess)
     e = hipMemcpy2DAsync(S.X, sizeof(double) * m, X, sizeof(double) * ldx, sizeof(double) * m, n,
                          hipMemcpyDeviceToDevice, st);

@@ -23,6 +23,7 @@ from . import (
     lobpcg_learner_get_weights,
     lobpcg_learner_set_stream,
     lobpcg_learner_snapshot_info,
+    lobpcg_learner_set_supervision,
     lobpcg_learner_train,
 )
 
@@ -54,6 +55,7 @@ def train(
     device: int = 0,
     chunks: int = 1,
     validate=None,
+    supervision: float = 1.0,
 ) -> TrainReport:
     """Train on the operators held by `solvers` (paper_2305_06668_amd.Solver
     objects with an operator, a preconditioner and an initial block of
@@ -62,9 +64,11 @@ def train(
 
     The `steps` Adam steps run in `chunks` equal parts; with `validate`
     (weights -> score, lower is better) the weights after each part are
-    scored and the best are returned."""
+    scored and the best are returned.  `supervision` is the weight of the
+    loss term that aligns the learned step with the MINRES correction."""
     L = lobpcg_learner_create(device, seed)
     lobpcg_learner_set_stream(L)
+    lobpcg_learner_set_supervision(L, supervision)
     log = []
     relres = 0.0
     try:

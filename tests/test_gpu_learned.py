@@ -181,6 +181,56 @@ def test_learner_objective_and_gradient_match_oracle(P):
         P.lobpcg_learner_destroy(L)
 
 
+def test_learner_supervised_objective_matches_oracle(P):
+    """The loss with the supervised term mu (1 - cos^2 angle(u, (I - X X^T) t))
+    and its gradient against the oracle, the corrections t solved tightly on
+    both sides (GPU block MINRES to 1e-10, scipy's MINRES to 1e-12) on a
+    block near the lowest eigenvectors, where the projected systems are well
+    enough conditioned for that."""
+    n, m = 500, 4
+    A = synth.dense_dd(n, seed=12)
+    V = np.linalg.eigh(A)[1]
+    Xb = np.linalg.qr(V[:, :m] + 1e-2 * synth.rng(13).standard_normal((n, m)))[0]
+    X = Xb @ np.linalg.eigh(Xb.T @ A @ Xb)[1]
+    d = np.diag(A).copy()
+    rho = np.abs(A).sum(1) - np.abs(d)
+    s = P.Solver(n)
+    s.set_operator_dense(cu(A))
+    s.ensure_workspace(m)
+    L = P.lobpcg_learner_create(0, 3)
+    try:
+        w32, p = f32_params(9)
+        P.lobpcg_learner_set_weights(L, w32)
+        snap = P.lobpcg_learner_add_snapshot(L, s.h, cu(X), minres_maxiter=600, minres_rtol=1e-10)
+        info = P.lobpcg_learner_snapshot_info(L, snap, m)
+        assert np.all(info["minres_relres"] <= 1e-10)
+        th = np.einsum("ij,ij->j", X, A @ X)
+        R = A @ X - X * th
+        T = M.jd_targets(A, X, th, R, rtol=1e-12, maxiter=2000)
+        cols = [0, 1, 3]
+        ref = info["ref_decrease"][cols]
+        base = P.lobpcg_learner_objective(L, snap, cols, want_grad=True)
+        Lb, _ = M.objective(p, A, X, R, th, cols, d, rho, M.scale_of(d), ref=ref)
+        assert abs(base["loss"] - Lb) <= 1e-5 * abs(Lb)
+        for mu in (0.8, 3.0):
+            P.lobpcg_learner_set_supervision(L, mu)
+            out = P.lobpcg_learner_objective(L, snap, cols, want_grad=True)
+            Lo, go = M.objective(p, A, X, R, th, cols, d, rho, M.scale_of(d), ref=ref, T=T, mu=mu)
+            rel_l = abs(out["loss"] - Lo) / abs(Lo)
+            rel_g = np.linalg.norm(out["grad"] - go) / np.linalg.norm(go)
+            say(f"mu {mu}: loss gpu {out['loss']:.10f} oracle {Lo:.10f} rel {rel_l:.2e}; grad rel {rel_g:.2e}")
+            assert rel_l <= 1e-5
+            assert rel_g <= 1e-4
+            assert out["loss"] > base["loss"]  # the term is positive here
+        P.lobpcg_learner_set_supervision(L, 0.0)
+        off = P.lobpcg_learner_objective(L, snap, cols, want_grad=True)
+        assert off["loss"] == base["loss"] and np.array_equal(off["grad"], base["grad"])
+        with pytest.raises(P.LobpcgError):
+            P.lobpcg_learner_set_supervision(L, -1.0)
+    finally:
+        P.lobpcg_learner_destroy(L)
+
+
 def test_minres_corrections_match_oracle(P):
     # a Ritz block near the lowest eigenvectors: the projected systems are
     # then well enough conditioned for MINRES to reach 1e-10 in a few hundred
@@ -221,6 +271,12 @@ def test_training_lowers_loss(P):
             P.lobpcg_learner_add_snapshot(L, s.h, cu(Xs), minres_maxiter=60)
         first, last = P.lobpcg_learner_train(L, 120, 4, 3e-3, seed=2)
         say(f"training loss {first:.4f} -> {last:.4f}")
+        assert np.isfinite(first) and np.isfinite(last)
+        assert last < first
+        # with the supervised term as well
+        P.lobpcg_learner_set_supervision(L, 1.0)
+        first, last = P.lobpcg_learner_train(L, 120, 4, 3e-3, seed=3)
+        say(f"supervised training loss {first:.4f} -> {last:.4f}")
         assert np.isfinite(first) and np.isfinite(last)
         assert last < first
     finally:
