@@ -375,7 +375,8 @@ def kron_solve(P, synth, torch, dev, args):
         r = val.solve(k, tol, want_vectors=False)
         return r.stats["iterations"] if r.status == P.OK else 10**6
 
-    rep = learn.train(trainers, k + 5, steps=300, cols_per_step=k + 5, lr=1e-3, chunks=6, validate=validate)
+    rep = learn.train(trainers, k + 5, steps=300, cols_per_step=k + 5, lr=1e-3, chunks=6, validate=validate,
+                      supervision=args.supervision)
     for st in trainers + [val]:
         st.close()
     setup = time.perf_counter() - t0
@@ -388,7 +389,7 @@ def kron_solve(P, synth, torch, dev, args):
         ("learned+mixed_block13", k + 5, P.PREC_FP32, P.PRECOND_LEARNED),
     ]
     out = {"mode": "kron-solve", "workload": f"kronsum na={na} n={n} k={k} tol={tol:g}",
-           "max_iter": args.kron_max_iter, "learned_training_s": setup,
+           "max_iter": args.kron_max_iter, "learned_training_s": setup, "supervision": args.supervision,
            "validation_iterations": [c["score"] for c in rep.log], "variants": {}}
     evals = {}
     for name, m, prec, pc in variants:

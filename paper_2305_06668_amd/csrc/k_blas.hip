@@ -920,13 +920,15 @@ static hipError_t rotate_launch(const T* V, const T* AV, T* Vout, T* AVout, cons
                                 hipStream_t s) {
   const int64_t nchunks = (a.n + 63) / 64;
   const int grid = (int)std::min<int64_t>(nchunks, kStreamBlocks);
-  // register prefetch: 16-byte rows (p, ld and both bases aligned), p <= 64
+  // register prefetch (fp64): 16-byte rows (p, ld and both bases aligned),
+  // p <= 64.  The fp32 instances keep the staged path: their prefetch
+  // registers would cost a block per CU (4 fit by LDS without them, 3 with)
   constexpr int VE = 16 / (int)sizeof(T);
-  const bool pf = a.p <= 64 && a.p % VE == 0 && a.ldv % VE == 0 &&
+  const bool pf = sizeof(T) == 8 && a.p <= 64 && a.p % VE == 0 && a.ldv % VE == 0 &&
                   (reinterpret_cast<uintptr_t>(V) & 15) == 0 &&
                   (reinterpret_cast<uintptr_t>(AV) & 15) == 0;
   // (fp64 with four column tiles would spill: it keeps the staged path)
-  if constexpr (sizeof(T) == 8 && MTJ == 4) {
+  if constexpr (sizeof(T) != 8 || MTJ == 4) {
     rotate_kernel_launch<T, MTJ, false>(V, AV, Vout, AVout, a, grid, s);
   } else {
     if (pf) rotate_kernel_launch<T, MTJ, true>(V, AV, Vout, AVout, a, grid, s);
