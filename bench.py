@@ -239,6 +239,15 @@ def generalized_line(P, synth, torch, dev, C, X0, k, tol, steps, warmup):
     }
 
 
+def initial_learned_weights(P, seed=1):
+    """The weights a learner starts from (learn.train's default seed)."""
+    L = P.lobpcg_learner_create(0, seed)
+    try:
+        return P.lobpcg_learner_get_weights(L)
+    finally:
+        P.lobpcg_learner_destroy(L)
+
+
 def family_bench(P, synth, torch, dev, args):
     """The preconditioner-study configuration (stand-in for Sec. 4.4): the
     csr_family matrices (n = 2e5, ~31 stored entries per row, dominance ratio
@@ -251,6 +260,11 @@ def family_bench(P, synth, torch, dev, args):
     from paper_2305_06668_amd import learn
 
     n, k, tol = args.family_n, 32, args.tol
+    snap_iters = (1, 3, 8, 20, 50)
+    if args.family_full:
+        # 192 resident trainers: two snapshots each keep the snapshots at
+        # ~60 GB next to ~135 GB of solver workspaces
+        args.family_train, args.family_held_out, snap_iters = 192, 64, (3, 20)
 
     def solver_for(idx):
         C, rho = synth.csr_family(idx, n=n)
@@ -261,7 +275,11 @@ def family_bench(P, synth, torch, dev, args):
         return st, rho
 
     t0 = time.perf_counter()
-    trainers = [solver_for(i)[0] for i in range(args.family_train)]
+    trainers = []
+    for i in range(args.family_train):
+        trainers.append(solver_for(i)[0])
+        if (i + 1) % 16 == 0:
+            log(f"family: {i + 1} training matrices generated ({time.perf_counter() - t0:.0f} s)")
     val, _ = solver_for(191)
 
     def validate(w):
@@ -271,8 +289,13 @@ def family_bench(P, synth, torch, dev, args):
         r = val.solve(k, tol, want_vectors=False)
         return r.stats["iterations"] if r.status == P.OK else 10**6
 
-    rep = learn.train(trainers, k, steps=args.family_steps, cols_per_step=k, lr=1e-3,
-                      chunks=args.family_chunks, validate=validate, supervision=args.supervision)
+    def progress(i, nsnap):
+        if (i + 1) % 16 == 0:
+            log(f"family: snapshots of {i + 1} matrices taken ({nsnap}, {time.perf_counter() - t0:.0f} s)")
+
+    rep = learn.train(trainers, k, snapshot_iters=snap_iters, steps=args.family_steps, cols_per_step=k, lr=1e-3,
+                      chunks=args.family_chunks, validate=validate, supervision=args.supervision,
+                      progress=progress)
     for st in trainers + [val]:
         st.close()
     setup = time.perf_counter() - t0
@@ -283,14 +306,19 @@ def family_bench(P, synth, torch, dev, args):
         "tridiag": dict(prec=P.PREC_FP64, pc=P.PRECOND_TRIDIAG, method=P.METHOD_LOBPCG),
         "davidson_jacobi": dict(prec=P.PREC_FP64, pc=P.PRECOND_DIAG, method=P.METHOD_DAVIDSON),
         "mixed_jacobi": dict(prec=P.PREC_FP32, pc=P.PRECOND_DIAG, method=P.METHOD_LOBPCG),
-        "learned+mixed": dict(prec=P.PREC_FP32, pc=P.PRECOND_LEARNED, method=P.METHOD_LOBPCG),
+        "learned+mixed": dict(prec=P.PREC_FP32, pc=P.PRECOND_LEARNED, method=P.METHOD_LOBPCG, w=rep.weights),
+        # the weights training starts from (learn.train's learner seed): the
+        # regularised Jacobi step c = s softplus(-3) where the net acts
+        "untrained+mixed": dict(prec=P.PREC_FP32, pc=P.PRECOND_LEARNED, method=P.METHOD_LOBPCG,
+                                w=initial_learned_weights(P)),
     }
     rows = {v: [] for v in variants}
     for idx in range(192, 192 + args.family_held_out):
         st, rho = solver_for(idx)
-        st.set_learned_weights(rep.weights)
         line = [f"matrix {idx} rho {rho:.2f}:"]
         for name, cfg in variants.items():
+            if "w" in cfg:
+                st.set_learned_weights(cfg["w"])
             st.set_option(P.OPT_METHOD, cfg["method"])
             st.set_option(P.OPT_PRECISION, cfg["prec"])
             st.set_preconditioner(cfg["pc"])
@@ -302,7 +330,8 @@ def family_bench(P, synth, torch, dev, args):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
             rows[name].append(dict(idx=idx, rho=rho, iterations=r.stats["iterations"], seconds=dt,
-                                   converged=r.status == P.OK, max_resid=float(r.resnorms.max())))
+                                   converged=r.status == P.OK, max_resid=float(r.resnorms.max()),
+                                   learned_budget_iter=r.stats["learned_budget_iter"]))
             line.append(f"{name} {r.stats['iterations']} it {dt*1e3:.0f} ms")
         st.close()
         log(" ".join(line))
@@ -322,7 +351,9 @@ def family_bench(P, synth, torch, dev, args):
     out = {
         "mode": "preconditioner study (csr_family)",
         "workload": f"csr_family n={n} k=block={k} tol={tol:g}; held-out indices 192..{191 + args.family_held_out} "
-        f"(subset of the 64), training indices 0..{args.family_train - 1} (subset of the 192)",
+        f"({'all' if args.family_held_out == 64 else 'subset'} of the 64), training indices "
+        f"0..{args.family_train - 1} ({'all' if args.family_train == 192 else 'subset'} of the 192; "
+        f"snapshots after {list(snap_iters)} iterations; weights chosen on index 191)",
         "learned_training": {"setup_s": setup, "steps": args.family_steps, "chunks": args.family_chunks,
                              "validation_iterations": [c["score"] for c in rep.log], "kept_chunk": rep.best_chunk,
                              "loss_first": rep.loss_first, "loss_last": rep.loss_last,
@@ -488,6 +519,9 @@ def main():
     ap.add_argument("--family-held-out", type=int, default=16)
     ap.add_argument("--family-steps", type=int, default=600)
     ap.add_argument("--family-chunks", type=int, default=6)
+    ap.add_argument("--family-full", action="store_true",
+                    help="the whole configuration: train on all 192 training indices (two snapshots each), "
+                    "solve all 64 held-out ones")
     ap.add_argument(
         "--tridiag",
         action="store_true",
@@ -621,7 +655,8 @@ def main():
         """Warm-up solves, then `steps` timed solves between synchronisations."""
         s.set_option(P.OPT_METHOD, P.METHOD_DAVIDSON if variant == "davidson" else P.METHOD_LOBPCG)
         s.set_option(P.OPT_PRECISION, P.PREC_FP64 if variant in ("plain", "davidson", "tridiag") else P.PREC_FP32)
-        s.set_preconditioner({"learned+mixed": P.PRECOND_LEARNED, "tridiag": P.PRECOND_TRIDIAG}.get(variant, P.PRECOND_DIAG))
+        s.set_preconditioner({"learned+mixed": P.PRECOND_LEARNED, "untrained+mixed": P.PRECOND_LEARNED,
+                              "tridiag": P.PRECOND_TRIDIAG}.get(variant, P.PRECOND_DIAG))
         s.set_option(P.OPT_CHEAP_EXIT, cheap_exit)
         for w in range(args.warmup):
             r = s.solve(k, args.tol, want_vectors=False)
@@ -645,6 +680,11 @@ def main():
     t_tri, res_tri = timed("tridiag")
     gen_line = generalized_line(P, synth, torch, dev, C, X0, k, args.tol, args.steps, args.warmup)
     t_mixed, res_mixed = timed("mixed")
+    # the learned path with the weights training starts from: the regularised
+    # Jacobi step alone, to show what the training itself adds
+    s.set_learned_weights(initial_learned_weights(P))
+    t_um, res_um = timed("untrained+mixed")
+    s.set_learned_weights(rep.weights)
     t_lm, res_lm = timed("learned+mixed")
     # headline: learned preconditioner + mixed precision
     tt, res = t_lm, res_lm
@@ -721,6 +761,10 @@ def main():
             "learned_fallbacks": stats["learned_fallbacks"],
             "mixed_jacobi_time_to_tol_s": t_mixed,
             "mixed_jacobi_iterations": res_mixed.stats["iterations"],
+            "untrained_mixed_time_to_tol_s": t_um,
+            "untrained_mixed_iterations": res_um.stats["iterations"],
+            "untrained_note": "the learned path with the untrained initial weights (regularised Jacobi, "
+            "c = s softplus(-3) where the net acts): the share of the gain that is the form, not the training",
             "dtype_note": "learned+mixed runs phase 1 in fp32 (operator, Grams, blocks) and phase 2 in "
             "fp64 to tolerance; every small dense kernel is fp64; the plain line is fp64 throughout",
             "eigenvalue_error_vs_oracle": eig_err,

@@ -117,6 +117,14 @@ typedef struct lobpcg_ctx* lobpcg_t;
                                           current Ritz vectors; 0 (default) = min(25 m,
                                           96) (Sec. 4 keeps 25 vectors per root; 96 is the
                                           library's Rayleigh-Ritz limit); 2 m .. 96 */
+#define LOBPCG_OPT_LEARNED_BUDGET 13  /* learned preconditioner: the iterations of a
+                                         solve that use the learned step; from
+                                         the next one on every column takes the
+                                         (absolute) Jacobi step, its fallback.
+                                         Default 200, 0 = no limit.  Bounds the
+                                         cost of a net that slows a solve down
+                                         without ever failing the per-column
+                                         residual test */
 #define LOBPCG_OPT_FORCE_RESTARTS 9   /* test hook, default 0: the first N explicit
                                          true-residual checks of a solve count as
                                          failed, which drives the restart that a
@@ -156,6 +164,8 @@ typedef struct lobpcg_stats {
   int32_t history_restarts;    /* block Davidson: history truncations */
   int32_t max_basis;           /* block Davidson: largest basis reached (columns) */
   int64_t b_matvec_columns;    /* generalized problem: columns B was applied to */
+  int32_t learned_budget_iter; /* first iteration that took the Jacobi step because
+                                  LOBPCG_OPT_LEARNED_BUDGET was spent, -1 if none */
 } lobpcg_stats;
 
 /* ---- ortho report for the step entry points ---------------------------- */

@@ -61,6 +61,7 @@ OPT_FORCE_RESTARTS = 9
 OPT_CHEAP_EXIT = 10
 OPT_METHOD = 11
 OPT_DAVIDSON_MAX_DIM = 12
+OPT_LEARNED_BUDGET = 13
 
 METHOD_LOBPCG = 0
 METHOD_DAVIDSON = 1
@@ -97,6 +98,7 @@ class lobpcg_stats(ctypes.Structure):
         ("history_restarts", _i32),
         ("max_basis", _i32),
         ("b_matvec_columns", _i64),
+        ("learned_budget_iter", _i32),
     ]
 
     def as_dict(self) -> dict:

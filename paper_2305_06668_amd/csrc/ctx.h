@@ -61,6 +61,7 @@ struct lobpcg_ctx {
   int cheap_exit = 0;      // cheap exits of the ortho loops
   int method = LOBPCG_METHOD_LOBPCG;
   int dav_max_dim = 0;     // 0: min(25 m, kMaxP)
+  int learned_budget = 200;  // iterations that use the learned step (0: no limit)
   int learned_bf16 = 1;  // learned preconditioner inference: layer 2 on bf16 MFMA
   // operator
   int op = lobpcg::kOpNone;

@@ -558,8 +558,10 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     ra.m = m;
     ra.q = q;
     ra.a0 = a0;
-    // learned and tridiagonal: W~ = R here, transformed below
-    ra.precond = (learned || tri) ? kPrecNone : pkind;
+    // learned and tridiagonal: W~ = R here, transformed below; once the
+    // learned budget is spent the next iteration takes the fused Jacobi step
+    const bool learned_now = learned && !(learned_budget > 0 && iter + 1 > learned_budget);
+    ra.precond = (learned_now || tri) ? kPrecNone : (learned ? kPrecDiag : pkind);
     ra.U = U;
     ra.theta = theta;
     ra.diag = dptr(lay.diag);
@@ -676,7 +678,8 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     }
     ++iter;
     // ---- W = ortho(T R; [X P]) and AW = A W (Alg. 1) ----
-    if (learned) {
+    if (learned && !learned_now && stats.learned_budget_iter < 0) stats.learned_budget_iter = iter;
+    if (learned_now) {
       // the fallback columns go to the kernels as a bit set (no copy); the
       // bf16 transform clears its flags itself
       uint64_t mbits = 0;
@@ -1116,6 +1119,7 @@ int lobpcg_ctx::solve(int k, double tol) {
   if (rc) return rc;
   std::memset(&stats, 0, sizeof(stats));
   stats.precision_switch_iter = -1;
+  stats.learned_budget_iter = -1;
   have_result = false;
   if (pkind != LOBPCG_PRECOND_NONE) {
     rc = ensure_diag();
@@ -1335,6 +1339,11 @@ int lobpcg_set_option(lobpcg_t h, int key, double v) {
       return LOBPCG_OK;
     case LOBPCG_OPT_CHEAP_EXIT:
       h->cheap_exit = (v != 0.0);
+      return LOBPCG_OK;
+    case LOBPCG_OPT_LEARNED_BUDGET:
+      if (v < 0 || v > 1e9 || v != (int)v)
+        return h->fail(LOBPCG_ERR_INVALID_ARG, "learned budget must be a non-negative integer");
+      h->learned_budget = (int)v;
       return LOBPCG_OK;
     case LOBPCG_OPT_FORCE_RESTARTS:
       if (v < 0 || v > 100 || v != (int)v)

@@ -56,6 +56,7 @@ def train(
     chunks: int = 1,
     validate=None,
     supervision: float = 1.0,
+    progress=None,
 ) -> TrainReport:
     """Train on the operators held by `solvers` (paper_2305_06668_amd.Solver
     objects with an operator, a preconditioner and an initial block of
@@ -65,7 +66,9 @@ def train(
     The `steps` Adam steps run in `chunks` equal parts; with `validate`
     (weights -> score, lower is better) the weights after each part are
     scored and the best are returned.  `supervision` is the weight of the
-    loss term that aligns the learned step with the MINRES correction."""
+    loss term that aligns the learned step with the MINRES correction;
+    `progress(i, snapshots)`, when given, is called after solver i's
+    snapshots are taken."""
     L = lobpcg_learner_create(device, seed)
     lobpcg_learner_set_stream(L)
     lobpcg_learner_set_supervision(L, supervision)
@@ -74,7 +77,7 @@ def train(
     try:
         t0 = time.perf_counter()
         nsnap = 0
-        for s in solvers:
+        for si, s in enumerate(solvers):
             for it in snapshot_iters:
                 s.set_option(OPT_MAX_ITER, it)
                 res = s.solve(block, 1e-300)
@@ -83,6 +86,8 @@ def train(
                 relres = max(relres, float(info["minres_relres"].max()))
                 nsnap += 1
             s.set_option(OPT_MAX_ITER, 1000)
+            if progress is not None:
+                progress(si, nsnap)
         t1 = time.perf_counter()
         per = max(1, steps // max(1, chunks))
         best_w, best_score, best_chunk = None, float("inf"), -1

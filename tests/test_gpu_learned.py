@@ -313,6 +313,44 @@ def test_learned_solve_eigenpairs(P, precision):
     assert np.abs(X.T @ X - np.eye(k)).max() < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_learned_budget_switches_to_jacobi(P, precision):
+    """LOBPCG_OPT_LEARNED_BUDGET: after that many iterations every column
+    takes the Jacobi step; the solve still meets the eigenpair bar, and with
+    the budget at 0 (no limit) or above the iteration count nothing switches."""
+    n, k = 1500, 6
+    A = synth.dense_dd(n, seed=21)
+    w_all, _ = _eig_ref(A, k)
+    X0 = synth.start_block(n, k, 22)
+    w32, _ = f32_params(3, out_bias=-2.0, w3_scale=1.0)
+    s = P.Solver(n)
+    s.set_operator_dense(cu(A))
+    s.set_learned_weights(w32)
+    s.set_preconditioner(P.PRECOND_LEARNED)
+    if precision == "mixed":
+        s.set_option(P.OPT_PRECISION, P.PREC_FP32)
+    out = {}
+    for budget in (0, 3, 10000):
+        s.set_option(P.OPT_LEARNED_BUDGET, budget)
+        s.set_initial_guess(cu(X0))
+        res = s.solve(k, 1e-8)
+        say(precision, "budget", budget, res.stats["iterations"], "switch", res.stats["learned_budget_iter"])
+        assert res.status == 0
+        X = res.evecs.cpu().numpy()
+        AX = A @ X
+        th = np.einsum("ij,ij->j", X, AX)
+        assert np.all(np.linalg.norm(AX - X * th, axis=0) <= 1e-8 * 1.0001)
+        assert np.all(np.abs(res.evals - w_all[:k]) <= 1e-9 * np.maximum(np.abs(w_all[:k]), 1e-3 * 101))
+        out[budget] = res.stats
+    assert out[0]["learned_budget_iter"] == -1
+    assert out[10000]["learned_budget_iter"] == -1
+    assert out[3]["learned_budget_iter"] == 4
+    # budget 0 and a budget above the iteration count are the same solve
+    assert out[0]["iterations"] == out[10000]["iterations"]
+    with pytest.raises(P.LobpcgError):
+        s.set_option(P.OPT_LEARNED_BUDGET, -1)
+
+
 def test_learned_solve_with_nan_weights_still_converges(P):
     # diagonal slope 1e-3: gaps wide enough that the Jacobi-preconditioned
     # solve converges in tens of iterations (with the default slope at this n
