@@ -73,10 +73,24 @@ __global__ __launch_bounds__(256) void k_dense(const T* __restrict__ A, int64_t 
 // through LDS) ran at 0.3 TB/s: every step moves to another row of A.
 // Sharing each chunk of W rows among a workgroup's 4 waves through LDS
 // (double-buffered, one barrier per 512 columns) ran 15 % slower: the W
-// re-reads from L2 are not what bounds this kernel.
+// re-reads from L2 are not what bounds this kernel.  With 8 fp64 columns
+// the 64 accumulators leave room for one wave per SIMD, so A is prefetched
+// a step ahead and read with the non-temporal hint (737 -> 661 us at
+// n = 2e4 in isolation).
 template <typename T>
 struct alignas(16) DVec {
   T v[16 / sizeof(T)];
+};
+// the same 16 bytes as a vector type (what the non-temporal load takes)
+template <typename T>
+struct NtVec;
+template <>
+struct NtVec<double> {
+  typedef double __attribute__((ext_vector_type(2))) type;
+};
+template <>
+struct NtVec<float> {
+  typedef float __attribute__((ext_vector_type(4))) type;
 };
 
 template <typename T, int R, int MC, bool FULLW>
@@ -101,13 +115,34 @@ __global__ __launch_bounds__(256) void k_dense_vec(const T* __restrict__ A, int6
   for (int r = 0; r < R; ++r) arow[r] = A + min(r0 + r, n - 1) * lda;
   constexpr int64_t kStep = 64 * VE;
   const int64_t nfull = (n / kStep) * kStep;
-  // not unrolled: 3 % faster than two steps in flight (256 registers)
+  // A is read once: non-temporal loads keep it from evicting W from L2, and
+  // the next step's A vectors are loaded before this step's products (one
+  // step in flight ahead; fully unrolled steps ran 3 % slower)
+  typedef typename NtVec<T>::type VN;
+  auto load_a = [&](int64_t c, V* dst) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const VN t = __builtin_nontemporal_load(reinterpret_cast<const VN*>(arow[r] + c));
+#pragma unroll
+      for (int u = 0; u < VE; ++u) dst[r].v[u] = t[u];
+    }
+  };
+  // (prefetch only where occupancy is one wave per SIMD anyway: fp64 with 8
+  // columns; elsewhere its registers would cost a wave)
+  constexpr bool PF = sizeof(T) == 8 && MC == 8;
+  V anext[PF ? R : 1];
+  if (PF && nfull > 0) load_a(lane * VE, anext);
 #pragma unroll 1
   for (int64_t c0 = 0; c0 < nfull; c0 += kStep) {
     const int64_t c = c0 + lane * VE;
     V a[R];
+    if constexpr (PF) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) a[r] = *reinterpret_cast<const V*>(arow[r] + c);
+      for (int r = 0; r < R; ++r) a[r] = anext[r];
+      if (c0 + kStep < nfull) load_a(c + kStep, anext);
+    } else {
+      load_a(c, a);
+    }
     // W rows as 16-byte vectors; a vector that would reach past column
     // ncols (the block may be a column slice of a wider buffer) is read value
     // by value
