@@ -490,6 +490,10 @@ def main():
     ap.add_argument("--train-steps", type=int, default=600)
     ap.add_argument("--train-chunks", type=int, default=24)
     ap.add_argument("--train-lr", type=float, default=1e-3)
+    ap.add_argument("--train-val", type=int, default=2, help="held-out matrices that choose the weights")
+    ap.add_argument("--train-val-n", type=int, default=0,
+                    help="size of those matrices (0: the benchmark's size)")
+    ap.add_argument("--train-seed", type=int, default=1, help="learner seed (initial weights, column draws)")
     ap.add_argument("--supervision", type=float, default=1.0,
                     help="weight of the training term aligning the learned step with the MINRES correction")
     ap.add_argument("--rr-jacobi", action="store_true", help="Rayleigh-Ritz eigensolves by Jacobi")
@@ -602,26 +606,31 @@ def main():
     # ---- learned preconditioner: trained on other matrices of the family ----
     # smaller members of the same generator (n = 2e5 with the diagonal slope
     # scaled by 5 so that mean |d| and the coupling match), other seeds; the
-    # weights kept are those with the fewest iterations on a held-out member
+    # weights kept are those with the fewest iterations on held-out members of
+    # the benchmark's size (the n = 2e5 ones predicted the full-size count
+    # poorly: kept weights 26 iterations there, 37 here)
     from paper_2305_06668_amd import learn
 
     t_tr = time.perf_counter()
     ntr = args.train_n
     slope = 1e-5 * n / ntr
 
-    def family_solver(seed_m, seed_x):
-        Ct = synth.csr_banded(n=ntr, seed=seed_m, diag_slope=slope)
-        st = P.Solver(ntr)
+    def family_solver(seed_m, seed_x, nn=ntr):
+        Ct = synth.csr_banded(n=nn, seed=seed_m, diag_slope=1e-5 * n / nn)
+        st = P.Solver(nn)
         st.set_option(P.OPT_RR_JACOBI, 1 if args.rr_jacobi else 0)
         st.set_operator_csr(
             torch.from_numpy(Ct.row_ptr).to(dev), torch.from_numpy(Ct.col).to(dev), torch.from_numpy(Ct.val).to(dev)
         )
         st.set_preconditioner(P.PRECOND_DIAG)
-        st.set_initial_guess(torch.from_numpy(synth.start_block(ntr, k, seed_x)).to(dev))
+        st.set_initial_guess(torch.from_numpy(synth.start_block(nn, k, seed_x)).to(dev))
         return st
 
     trainers = [family_solver(mseed + 1000 + i, xseed + 1000 + i) for i in range(args.train_matrices)]
-    vals = [family_solver(mseed + 2000 + i, xseed + 2000 + i) for i in range(2)]
+    # the weights are chosen on other members of the generator at the size
+    # they will be used at (never the benchmark's own matrix)
+    nval = args.train_val_n if args.train_val_n > 0 else n
+    vals = [family_solver(mseed + 2000 + i, xseed + 2000 + i, nval) for i in range(args.train_val)]
 
     def validate(w):
         # mean iterations over two held-out members: single solves carry
@@ -640,7 +649,8 @@ def main():
 
     log(f"training matrices generated ({time.perf_counter() - t_tr:.1f} s)")
     rep = learn.train(trainers, k, steps=args.train_steps, cols_per_step=k, lr=args.train_lr, minres_maxiter=100,
-                      chunks=args.train_chunks, validate=validate, supervision=args.supervision)
+                      chunks=args.train_chunks, validate=validate, supervision=args.supervision,
+                      seed=args.train_seed)
     log(f"learned preconditioner: {rep.snapshots} snapshots, loss {rep.loss_first:.3f} -> {rep.loss_last:.3f}, "
         f"collect {rep.seconds_collect:.1f} s, train {rep.seconds_train:.1f} s, validation iterations "
         f"{[c['score'] for c in rep.log]} (kept chunk {rep.best_chunk})")
@@ -682,7 +692,7 @@ def main():
     t_mixed, res_mixed = timed("mixed")
     # the learned path with the weights training starts from: the regularised
     # Jacobi step alone, to show what the training itself adds
-    s.set_learned_weights(initial_learned_weights(P))
+    s.set_learned_weights(initial_learned_weights(P, args.train_seed))
     t_um, res_um = timed("untrained+mixed")
     s.set_learned_weights(rep.weights)
     t_lm, res_lm = timed("learned+mixed")
@@ -799,7 +809,9 @@ def main():
                 "snapshots": rep.snapshots,
                 "steps": args.train_steps,
                 "chunks": args.train_chunks,
-                "validation_matrices": 2,
+                "validation_matrices": args.train_val,
+                "validation_n": args.train_val_n if args.train_val_n > 0 else n,
+                "learner_seed": args.train_seed,
                 "validation_iterations": [c["score"] for c in rep.log],
                 "kept_chunk": rep.best_chunk,
                 "loss_first": rep.loss_first,
@@ -807,7 +819,8 @@ def main():
                 "supervision": args.supervision,
                 "lr": args.train_lr,
                 "setup_s": train_s,
-                "note": "untimed; same generator, other seeds, n scaled with the diagonal slope",
+                "note": "untimed; training matrices: same generator, other seeds, smaller n with the diagonal "
+                "slope scaled; validation matrices: same generator and size, other seeds",
             },
         },
         "roofline": {

@@ -533,8 +533,11 @@ static hipError_t ortho_apply_launch(T* base, int64_t ld, int ny, int nw, const 
     (void)hipGetLastError();
     attr = true;
   }
+  // up to 4 workgroups per CU (the partials, grid x nr x nw doubles, fit
+  // the workspace's kStreamBlocks x kMaxP x kMaxBlock for every nr <= kMaxP,
+  // nw <= kMaxBlock); 512 left registers and LDS for 4 - 5 per CU unused
   const int64_t nchunks = (n + 63) / 64;
-  const int grid = (int)std::min<int64_t>(nchunks, kGramBlocks);
+  const int grid = (int)std::min<int64_t>(nchunks, kStreamBlocks);
   hipLaunchKernelGGL((k_ortho_apply<T, MTI, MTJ>), dim3(grid), dim3(256), sm, s, base, ld, ny, nw,
                      coef, st, n, part);
   hipError_t e = hipGetLastError();
