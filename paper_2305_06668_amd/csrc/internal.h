@@ -16,7 +16,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kMaxBlock = 32;            // RR block m
 constexpr int kMaxP = 3 * kMaxBlock;     // RR subspace m + 2 m_act
 constexpr int kGramMaxCols = 128;        // p, q limit of the Gram kernel
-constexpr int kGramBlocks = 512;         // stage-1 workgroups of the Gram
+constexpr int kGramBlocks = 512;         // stage-1 workgroups of the Gram (768, 3 per CU, ran 4-8 % slower)
 constexpr int kStreamBlocks = 1024;      // persistent grid of streaming kernels
 constexpr double kPrecondGuard = 1e-8;   // |d - theta| floor, relative to max(1, |theta|)
 constexpr uint64_t kZeroColumnSeed = 0x2305066680000000ull;
