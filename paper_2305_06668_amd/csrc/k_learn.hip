@@ -1,8 +1,10 @@
 // Streaming kernels of the learned preconditioner's training driver: column
 // gathers, block projections, column dot products, the per-column scalars of
 // the training objective, and the vector updates of the block MINRES that
-// produces the near-exact Jacobi-Davidson corrections.  All fp64, one row
-// per thread; the column dots reduce in two fixed-order stages.
+// produces the near-exact Jacobi-Davidson corrections.  All fp64.  The
+// blocks are row-major n x nc (nc <= 64); the elementwise kernels give a
+// workgroup 256 / nc whole rows, one element per thread, so a wave's loads
+// are one contiguous run; the column dots reduce in two fixed-order stages.
 #include <algorithm>
 
 #include "internal.h"
@@ -15,13 +17,27 @@ constexpr int kDotBlocks = 1024;
 
 inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Element (i, j) of this thread in an n x nc block: a workgroup covers
+// 256 / nc whole rows (grid rows_grid(n, nc)).
+struct Elem {
+  int64_t i;
+  int j;
+  bool ok;
+};
+__device__ __forceinline__ Elem elem_of(int nc, int64_t n) {
+  const int rpb = 256 / nc;
+  const int r = (int)threadIdx.x / nc;
+  const int64_t i = (int64_t)blockIdx.x * rpb + r;
+  return {i, (int)threadIdx.x - r * nc, r < rpb && i < n};
+}
+inline int rows_grid(int64_t n, int nc) { return std::max(1, cdiv64(n, 256 / nc)); }
+
 // Out[:, j] = In[:, cols[j]]
 __global__ void k_gather_cols(const double* __restrict__ In, int64_t ldi,
                               const int* __restrict__ cols, int nc, int64_t n,
                               double* __restrict__ Out, int64_t ldo) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  for (int j = 0; j < nc; ++j) Out[i * ldo + j] = In[i * ldi + cols[j]];
+  const Elem x = elem_of(nc, n);
+  if (x.ok) Out[x.i * ldo + x.j] = In[x.i * ldi + cols[x.j]];
 }
 
 // Out = In - X C  (X: n x m, C: m x nc row-major)
@@ -47,33 +63,50 @@ struct DotArgs {
   int64_t n;
 };
 
-// part[b][pair][col] = sum over this block's rows of P[i][col] Q[i][col]
+// part[(pair nc + col) nblk + b] = sum over block b's rows of P[i][col] Q[i][col].
+// Lane = (row offset rr < 64 / nc, column j): a wave reads 64 / nc whole
+// rows per step; the partials of a column are added over (wave, rr) in a
+// fixed order.
 __global__ __launch_bounds__(256) void k_coldots_part(DotArgs a, double* __restrict__ part) {
-  __shared__ double red[256];
-  for (int pr = 0; pr < a.npairs; ++pr) {
-    for (int j = 0; j < a.nc; ++j) {
-      double s = 0.0;
-      for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n;
-           i += (int64_t)gridDim.x * 256)
-        s += a.P[pr][i * a.ldp[pr] + j] * a.Q[pr][i * a.ldq[pr] + j];
-      red[threadIdx.x] = s;
-      __syncthreads();
-      for (int w = 128; w >= 1; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) part[((size_t)blockIdx.x * a.npairs + pr) * a.nc + j] = red[0];
-      __syncthreads();
+  __shared__ double red[3][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nc = a.nc, rpw = 64 / nc;
+  const int rr = lane / nc, j = lane - rr * nc;
+  double s[3] = {0.0, 0.0, 0.0};
+  if (rr < rpw) {
+    const int64_t step = (int64_t)gridDim.x * 4 * rpw;
+    for (int64_t i = ((int64_t)blockIdx.x * 4 + wave) * rpw + rr; i < a.n; i += step) {
+#pragma unroll
+      for (int pr = 0; pr < 3; ++pr)
+        if (pr < a.npairs) s[pr] += a.P[pr][i * a.ldp[pr] + j] * a.Q[pr][i * a.ldq[pr] + j];
     }
   }
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr) red[pr][threadIdx.x] = s[pr];
+  __syncthreads();
+  if ((int)threadIdx.x < a.npairs * nc) {
+    const int pr = (int)threadIdx.x / nc, jj = (int)threadIdx.x - pr * nc;
+    double t = 0.0;
+    for (int w = 0; w < 4; ++w)
+      for (int r = 0; r < rpw; ++r) t += red[pr][64 * w + r * nc + jj];
+    part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
 }
-__global__ void k_coldots_final(const double* __restrict__ part, int nblk, int count,
-                                double* __restrict__ out) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
+// out[idx] = sum over the nblk partials of output idx (one workgroup each,
+// fixed-order tree)
+__global__ __launch_bounds__(256) void k_coldots_final(const double* __restrict__ part, int nblk,
+                                                       double* __restrict__ out) {
+  __shared__ double red[256];
+  const double* p = part + (size_t)blockIdx.x * nblk;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * count + idx];
-  out[idx] = s;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += p[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // Training objective per column (see mlp_objective_scalars).  With sdots
@@ -121,23 +154,22 @@ __global__ void k_combine3(const double* __restrict__ R, const double* __restric
                            const double* __restrict__ Z, const double* __restrict__ Tau,
                            const double* __restrict__ coef, const double* __restrict__ coef4,
                            int nc, int64_t n, double* __restrict__ Out) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  for (int j = 0; j < nc; ++j) {
-    double o = coef[j] * R[i * nc + j] + coef[nc + j] * U[i * nc + j] +
-               coef[2 * nc + j] * Z[i * nc + j];
-    if (Tau != nullptr) o += coef4[j] * Tau[i * nc + j];
-    Out[i * nc + j] = o;
-  }
+  const Elem x = elem_of(nc, n);
+  if (!x.ok) return;
+  const int64_t e = x.i * nc + x.j;
+  double o = coef[x.j] * R[e] + coef[nc + x.j] * U[e] + coef[2 * nc + x.j] * Z[e];
+  if (Tau != nullptr) o += coef4[x.j] * Tau[e];
+  Out[e] = o;
 }
 
 // R = AX - X diag(theta)
 __global__ void k_residual(const double* __restrict__ X, const double* __restrict__ AX,
                            const double* __restrict__ theta, int m, int64_t n,
                            double* __restrict__ R) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  for (int j = 0; j < m; ++j) R[i * m + j] = AX[i * m + j] - theta[j] * X[i * m + j];
+  const Elem x = elem_of(m, n);
+  if (!x.ok) return;
+  const int64_t e = x.i * m + x.j;
+  R[e] = AX[e] - theta[x.j] * X[e];
 }
 
 // ---- block MINRES (Paige-Saunders recurrence, one system per column) ----
@@ -150,9 +182,10 @@ struct MrState {
 // V = Y / beta
 __global__ void k_mr_scale(const double* __restrict__ Y, const MrState* __restrict__ st, int nc,
                            int64_t n, double* __restrict__ V) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  for (int j = 0; j < nc; ++j) V[i * nc + j] = st[j].done ? 0.0 : Y[i * nc + j] / st[j].beta;
+  const Elem x = elem_of(nc, n);
+  if (!x.ok) return;
+  const int64_t e = x.i * nc + x.j;
+  V[e] = st[x.j].done ? 0.0 : Y[e] / st[x.j].beta;
 }
 
 // Y = (AV - theta V) - x (x^T (AV - theta V)) - (beta / oldb) R1 [itn > 1]
@@ -161,23 +194,23 @@ __global__ void k_mr_y(const double* __restrict__ AV, const double* __restrict__
                        const double* __restrict__ dots, const double* __restrict__ R1,
                        const MrState* __restrict__ st, int first, int nc, int64_t n,
                        double* __restrict__ Y) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  for (int j = 0; j < nc; ++j) {
-    const double xd = dots[j] - theta[j] * dots[nc + j];  // x^T (A v - theta v)
-    double y = AV[i * nc + j] - theta[j] * V[i * nc + j] - xd * Xc[i * nc + j];
-    if (!first && !st[j].done) y -= (st[j].beta / st[j].oldb) * R1[i * nc + j];
-    Y[i * nc + j] = y;
-  }
+  const Elem x = elem_of(nc, n);
+  if (!x.ok) return;
+  const int j = x.j;
+  const int64_t e = x.i * nc + j;
+  const double xd = dots[j] - theta[j] * dots[nc + j];  // x^T (A v - theta v)
+  double y = AV[e] - theta[j] * V[e] - xd * Xc[e];
+  if (!first && !st[j].done) y -= (st[j].beta / st[j].oldb) * R1[e];
+  Y[e] = y;
 }
 
 // Y -= (alfa / beta) R2   (alfa = dots[j] stored into the state)
 __global__ void k_mr_y2(const double* __restrict__ dots, const double* __restrict__ R2,
                         MrState* __restrict__ st, int nc, int64_t n, double* __restrict__ Y) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  for (int j = 0; j < nc; ++j)
-    if (!st[j].done) Y[i * nc + j] -= (dots[j] / st[j].beta) * R2[i * nc + j];
+  const Elem x = elem_of(nc, n);
+  if (!x.ok || st[x.j].done) return;
+  const int64_t e = x.i * nc + x.j;
+  Y[e] -= (dots[x.j] / st[x.j].beta) * R2[e];
 }
 
 __global__ void k_mr_init(const double* __restrict__ bnorm2, int nc, MrState* __restrict__ st) {
@@ -229,23 +262,23 @@ __global__ void k_mr_scalars(const double* __restrict__ alfa, const double* __re
 __global__ void k_mr_update(const double* __restrict__ V, const double* __restrict__ W1,
                             const double* __restrict__ W2, const MrState* __restrict__ st, int nc,
                             int64_t n, double* __restrict__ Wn, double* __restrict__ T) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  for (int j = 0; j < nc; ++j) {
-    const MrState& s = st[j];
-    const double w = (V[i * nc + j] - s.oldeps * W1[i * nc + j] - s.delta * W2[i * nc + j]) * s.denom;
-    Wn[i * nc + j] = w;
-    T[i * nc + j] += s.phi * w;
-  }
+  const Elem x = elem_of(nc, n);
+  if (!x.ok) return;
+  const MrState& s = st[x.j];
+  const int64_t e = x.i * nc + x.j;
+  const double w = (V[e] - s.oldeps * W1[e] - s.delta * W2[e]) * s.denom;
+  Wn[e] = w;
+  T[e] += s.phi * w;
 }
 
 // Y = -(r - x (x^T r)) given dots = x^T r
 __global__ void k_mr_rhs(const double* __restrict__ Rc, const double* __restrict__ Xc,
                          const double* __restrict__ dots, int nc, int64_t n,
                          double* __restrict__ Y) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  for (int j = 0; j < nc; ++j) Y[i * nc + j] = -(Rc[i * nc + j] - dots[j] * Xc[i * nc + j]);
+  const Elem x = elem_of(nc, n);
+  if (!x.ok) return;
+  const int64_t e = x.i * nc + x.j;
+  Y[e] = -(Rc[e] - dots[x.j] * Xc[e]);
 }
 
 }  // namespace
@@ -254,7 +287,8 @@ size_t mr_state_bytes() { return sizeof(MrState); }
 
 hipError_t gather_cols(const double* In, int64_t ldi, const int* cols, int nc, int64_t n,
                        double* Out, int64_t ldo, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_cols, dim3(cdiv64(n, 256)), dim3(256), 0, s, In, ldi, cols, nc, n,
+  if (nc <= 0 || nc > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gather_cols, dim3(rows_grid(n, nc)), dim3(256), 0, s, In, ldi, cols, nc, n,
                      Out, ldo);
   return hipGetLastError();
 }
@@ -276,14 +310,13 @@ hipError_t coldots(int npairs, const double* const* P, const int64_t* ldp, const
     a.ldp[k] = ldp[k];
     a.ldq[k] = ldq[k];
   }
+  if (npairs < 1 || npairs > 3 || nc <= 0 || nc > 64) return hipErrorInvalidValue;
   a.npairs = npairs;
   a.nc = nc;
   a.n = n;
   const int grid = std::max(1, std::min(kDotBlocks, cdiv64(n, 256)));
   hipLaunchKernelGGL(k_coldots_part, dim3(grid), dim3(256), 0, s, a, part);
-  const int count = npairs * nc;
-  hipLaunchKernelGGL(k_coldots_final, dim3(cdiv64(count, 64)), dim3(64), 0, s, part, grid, count,
-                     out);
+  hipLaunchKernelGGL(k_coldots_final, dim3(npairs * nc), dim3(256), 0, s, part, grid, out);
   return hipGetLastError();
 }
 hipError_t objective_scalars(const double* dots, const double* theta, const double* ref, int nc,
@@ -296,13 +329,15 @@ hipError_t objective_scalars(const double* dots, const double* theta, const doub
 hipError_t combine3(const double* R, const double* U, const double* Z, const double* Tau,
                     const double* coef, const double* coef4, int nc, int64_t n, double* Out,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_combine3, dim3(cdiv64(n, 256)), dim3(256), 0, s, R, U, Z, Tau, coef, coef4,
+  if (nc <= 0 || nc > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_combine3, dim3(rows_grid(n, nc)), dim3(256), 0, s, R, U, Z, Tau, coef, coef4,
                      nc, n, Out);
   return hipGetLastError();
 }
 hipError_t residual_block(const double* X, const double* AX, const double* theta, int m,
                           int64_t n, double* R, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(cdiv64(n, 256)), dim3(256), 0, s, X, AX, theta, m, n, R);
+  if (m <= 0 || m > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_residual, dim3(rows_grid(n, m)), dim3(256), 0, s, X, AX, theta, m, n, R);
   return hipGetLastError();
 }
 hipError_t mr_init(const double* bnorm2, int nc, void* st, hipStream_t s) {
@@ -311,24 +346,28 @@ hipError_t mr_init(const double* bnorm2, int nc, void* st, hipStream_t s) {
 }
 hipError_t mr_rhs(const double* Rc, const double* Xc, const double* dots, int nc, int64_t n,
                   double* Y, hipStream_t s) {
-  hipLaunchKernelGGL(k_mr_rhs, dim3(cdiv64(n, 256)), dim3(256), 0, s, Rc, Xc, dots, nc, n, Y);
+  if (nc <= 0 || nc > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mr_rhs, dim3(rows_grid(n, nc)), dim3(256), 0, s, Rc, Xc, dots, nc, n, Y);
   return hipGetLastError();
 }
 hipError_t mr_scale(const double* Y, const void* st, int nc, int64_t n, double* V, hipStream_t s) {
-  hipLaunchKernelGGL(k_mr_scale, dim3(cdiv64(n, 256)), dim3(256), 0, s, Y,
+  if (nc <= 0 || nc > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mr_scale, dim3(rows_grid(n, nc)), dim3(256), 0, s, Y,
                      static_cast<const MrState*>(st), nc, n, V);
   return hipGetLastError();
 }
 hipError_t mr_y(const double* AV, const double* V, const double* Xc, const double* theta,
                 const double* dots, const double* R1, const void* st, int first, int nc, int64_t n,
                 double* Y, hipStream_t s) {
-  hipLaunchKernelGGL(k_mr_y, dim3(cdiv64(n, 256)), dim3(256), 0, s, AV, V, Xc, theta, dots, R1,
+  if (nc <= 0 || nc > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mr_y, dim3(rows_grid(n, nc)), dim3(256), 0, s, AV, V, Xc, theta, dots, R1,
                      static_cast<const MrState*>(st), first, nc, n, Y);
   return hipGetLastError();
 }
 hipError_t mr_y2(const double* dots, const double* R2, void* st, int nc, int64_t n, double* Y,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_mr_y2, dim3(cdiv64(n, 256)), dim3(256), 0, s, dots, R2,
+  if (nc <= 0 || nc > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mr_y2, dim3(rows_grid(n, nc)), dim3(256), 0, s, dots, R2,
                      static_cast<MrState*>(st), nc, n, Y);
   return hipGetLastError();
 }
@@ -339,7 +378,8 @@ hipError_t mr_scalars(const double* alfa, const double* beta2, int nc, void* st,
 }
 hipError_t mr_update(const double* V, const double* W1, const double* W2, const void* st, int nc,
                      int64_t n, double* Wn, double* T, hipStream_t s) {
-  hipLaunchKernelGGL(k_mr_update, dim3(cdiv64(n, 256)), dim3(256), 0, s, V, W1, W2,
+  if (nc <= 0 || nc > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mr_update, dim3(rows_grid(n, nc)), dim3(256), 0, s, V, W1, W2,
                      static_cast<const MrState*>(st), nc, n, Wn, T);
   return hipGetLastError();
 }

@@ -23,11 +23,12 @@
 // W2^T chunks per wave).  The layer-3 dot is reduced over the 16 neuron
 // groups through LDS in a fixed order.
 //
-// Training (k_mlp_grad): the same forward pass per tile, then the analytic
-// backward pass for an output gradient dL/dw given per entry; per-tile sums
-// are formed in fp32 and accumulated across tiles in fp64 per workgroup;
-// k_grad_reduce adds the workgroup partials in a fixed order, k_adam updates
-// the fp32 master weights.
+// Training (k_mlp_grad): the forward pass and the analytic backward pass
+// for an output gradient dL/dw given per entry, with the tile's three
+// 64 x 128 x 128 contractions (layer 2 forward, dW2, dH1) on fp32 MFMA;
+// per-tile sums are formed in fp32 and accumulated across tiles in fp64 per
+// workgroup; k_grad_reduce adds the workgroup partials in a fixed order,
+// k_adam updates the fp32 master weights.
 #include <algorithm>
 #include <cmath>
 
@@ -57,14 +58,7 @@ constexpr int sH1 = sPhi + kTE * 4;      // [j][kHS]
 constexpr int sYP = sH1 + kH * kHS;      // [kg][kTE] layer-3 partials
 constexpr int sY = sYP + 16 * kTE;       // [e]
 constexpr int kFwdFloats = sY + kTE;
-// training extras
-constexpr int sDZ2 = kFwdFloats;         // [k][kHS]
-constexpr int sDY = sDZ2 + kH * kHS;     // [e]
-constexpr int sGA = sDY + kTE;           // [j][8]: dW1 (3), db1, db2, dW3
-constexpr int sDEnd = sGA + kH * 8;      // then 2 kTE doubles (r, dL/dw)
 constexpr size_t kFwdBytes = sizeof(float) * kFwdFloats;
-constexpr size_t kGradBytes = sizeof(float) * sDEnd + sizeof(double) * 2 * kTE;
-static_assert(kGradBytes <= 152 * 1024, "LDS budget");
 
 __device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu(float z) { return z * sigm(z); }
@@ -234,8 +228,97 @@ __global__ __launch_bounds__(256) void k_mlp_apply(T* __restrict__ R, int64_t ld
 
 // Training: per-workgroup partial gradients (kMlpParams doubles each) of
 // sum_e G_e w_e, where w is the learned column of R and G = dL/dw is given
-// (same layout as R).
-__global__ __launch_bounds__(256) void k_mlp_grad(const double* __restrict__ R,
+// (same layout as R).  512 threads (eight waves, two per SIMD) per tile of
+// kTE entries; the tile's three 64 x 128 x 128 contractions run on
+// v_mfma_f32_16x16x4f32 (fp32 in, fp32 accumulate):
+//   forward  Z2  = H1 W2^T   wave w: entry tile w & 3, neuron tiles 4 (w >> 2) + [0, 4)
+//   dW2      dW2 = dZ2^T H1  wave w: neuron tile w (rows k), all eight column tiles j
+//   dH1      dH1 = dZ2 W2    wave w: entry tile w & 3, column tiles 4 (w >> 2) + [0, 4)
+// The activations, layers 1 and 3 and the regulariser's derivative stay on
+// the vector units.  Per-tile sums are fp32 (the MFMA accumulators, xor
+// shuffles, and LDS partials added in a fixed order); they are accumulated
+// across tiles in fp64 per workgroup.
+constexpr int kGT = 512;
+constexpr int gW2 = 0;                // W2 [k][j]
+constexpr int gH1 = gW2 + kH * kH;    // H1 [e][j]
+constexpr int gDZ = gH1 + kTE * kH;   // dZ2 [e][k]
+constexpr int gW1 = gDZ + kTE * kH;   // [j][4]
+constexpr int gB1 = gW1 + kH * 4;
+constexpr int gB2 = gB1 + kH;
+constexpr int gW3 = gB2 + kH;
+constexpr int gB3 = gW3 + kH;         // 4 floats
+constexpr int gPhi = gB3 + 4;         // [e][4]
+constexpr int gYP = gPhi + kTE * 4;   // [2][e] layer-3 partials of the two neuron halves
+constexpr int gDY = gYP + 2 * kTE;    // [e]
+constexpr int gP1 = gDY + kTE;        // [4][j][4] dW1 (3), db1 per entry tile
+constexpr int gP2 = gP1 + 4 * kH * 4; // [4][k][2] dW3, db2 per entry tile
+constexpr int gEnd = gP2 + 4 * kH * 2;
+// then doubles: per entry r, dL/dw, d - theta, theta; per neuron the fp64
+// sums dW1 (3), db1, db2, dW3; dB3
+constexpr int dR = 0, dG = kTE, dDM = 2 * kTE, dTH = 3 * kTE, dRow = 4 * kTE,
+              dB3 = dRow + 6 * kH, dEnd = dB3 + 2;
+constexpr size_t kGradBytes = sizeof(float) * gEnd + sizeof(double) * dEnd;
+static_assert(gEnd % 2 == 0 && kGradBytes <= 160 * 1024, "LDS budget");
+
+// Rows of 128 floats with the column bits 2..5 xor-ed by the row's low four
+// bits: a wave's operand reads of 16 rows x 4 columns and of 4 rows x 16
+// columns both land on 64 distinct banks.
+__device__ __forceinline__ int swz(int row, int col) {
+  return row * kH + (col ^ (((row & 3) << 4) | (((row >> 2) & 3) << 2)));
+}
+
+// Features of tile entry e into LDS, with the entry's r, dL/dw, d - theta
+// and theta; returns whether the entry is inside the window.  Not inlined:
+// the constants of the fp64 log stay out of the caller's tile loop.
+__device__ __noinline__ bool grad_entry(float* L, double* Ld, int e, int64_t ent, int64_t total,
+                                        int nact, const double* __restrict__ R,
+                                        const double* __restrict__ G, int64_t ld,
+                                        const double* __restrict__ diag,
+                                        const double* __restrict__ rho,
+                                        const double* __restrict__ theta, double s) {
+  float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+  double r = 0.0, gg = 0.0, dm = 0.0, th = 0.0;
+  bool inside = false;
+  if (ent < total) {
+    const int64_t row = ent / nact;
+    const int col = (int)(ent - row * nact);
+    th = theta[col];
+    dm = diag[row] - th;
+    const double rr = rho[row];
+    inside = fabs(dm) <= kMlpWindow * rr;
+    f0 = (float)log(fabs(dm) / s + 1e-6);
+    f1 = (float)(th / s);
+    f2 = (float)log(rr / s + 1e-6);
+    r = R[row * ld + col];
+    gg = G[row * ld + col];
+  }
+  L[gPhi + e * 4 + 0] = f0;
+  L[gPhi + e * 4 + 1] = f1;
+  L[gPhi + e * 4 + 2] = f2;
+  Ld[dR + e] = r;
+  Ld[dG + e] = gg;
+  Ld[dDM + e] = dm;
+  Ld[dTH + e] = th;
+  return inside;
+}
+
+// dL/dy of tile entry e (0 outside the window or where the floor or the
+// fallback holds): w = r q^-1/2, q = dm^2 + c^2, c = s softplus(y).
+__device__ __noinline__ float grad_entry_dy(const double* Ld, int e, bool inside, float y,
+                                            double s) {
+  if (!inside) return 0.0f;
+  EntryIn in{};
+  in.valid = true;
+  in.inside = true;
+  in.dm = Ld[dDM + e];
+  in.theta = Ld[dTH + e];
+  const EntryOut o = regularise(in, y, s, false, nullptr);
+  if (o.floored || !(o.c > 0.0)) return 0.0f;
+  const double sg = 1.0 / (1.0 + exp(-(double)y));
+  return (float)(-Ld[dG + e] * Ld[dR + e] * o.c * s * sg / (o.q * sqrt(o.q)));
+}
+
+__global__ __launch_bounds__(kGT) void k_mlp_grad(const double* __restrict__ R,
                                                   const double* __restrict__ G, int64_t ld,
                                                   int nact, int64_t n,
                                                   const double* __restrict__ theta,
@@ -245,198 +328,219 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const double* __restrict__ R,
                                                   const float* __restrict__ wts,
                                                   double* __restrict__ part) {
   extern __shared__ float L[];
-  double* Ld = reinterpret_cast<double*>(L + sDEnd);  // [r(kTE) | g(kTE)]
-  load_weights(wts, L);
-  const double s = *sptr;
+  double* Ld = reinterpret_cast<double*>(L + gEnd);
   const int tid = threadIdx.x;
-  const int eg = tid & 15, kg = tid >> 4;
+  for (int idx = tid; idx < kH * kH; idx += kGT) L[gW2 + swz(idx >> 7, idx & 127)] = wts[oW2 + idx];
+  for (int idx = tid; idx < kH; idx += kGT) {
+    L[gW1 + idx * 4 + 0] = wts[oW1 + idx * 3 + 0];
+    L[gW1 + idx * 4 + 1] = wts[oW1 + idx * 3 + 1];
+    L[gW1 + idx * 4 + 2] = wts[oW1 + idx * 3 + 2];
+    L[gW1 + idx * 4 + 3] = 0.0f;
+    L[gB1 + idx] = wts[oB1 + idx];
+    L[gB2 + idx] = wts[oB2 + idx];
+    L[gW3 + idx] = wts[oW3 + idx];
+  }
+  for (int idx = tid; idx < 6 * kH + 2; idx += kGT) Ld[dRow + idx] = 0.0;
+  if (tid == 0) L[gB3] = wts[oB3];
+  const double s = *sptr;
   const int64_t total = n * nact;
   const int64_t ntiles = (total + kTE - 1) / kTE;
-  // fp64 accumulators: dW2 block (8 k x 8 j) of this thread, per-neuron rows
-  double aW2[8][8];
+  double aW2[8][4];  // dW2[k = 16 w + 4 g + r][j = 16 t + c]
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int t = 0; t < 8; ++t)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) aW2[a][b] = 0.0;
-  double aRow[6] = {0, 0, 0, 0, 0, 0};  // neuron tid (< 128): dW1[0..2], db1, db2, dW3
-  double aB3 = 0.0;
-  float z2[4][8];
+    for (int r = 0; r < 4; ++r) aW2[t][r] = 0.0;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    EntryIn in{};
-    __syncthreads();
-    if (tid < kTE) {
-      in = entry_features(L, tid, tile * kTE + tid, total, nact, diag, rho, theta, s);
-      Ld[tid] = in.valid ? R[in.row * ld + in.col] : 0.0;
-      Ld[kTE + tid] = in.valid ? G[in.row * ld + in.col] : 0.0;
-    }
-    for (int idx = tid; idx < kH * 8; idx += blockDim.x) L[sGA + idx] = 0.0f;
+    // the lane indices are re-derived per tile, opaque to the compiler: the
+    // swizzled LDS addresses built from them are recomputed inside the loop
+    // instead of being hoisted into (and spilled from) registers
+    int lid = tid;
+    asm volatile("" : "+v"(lid));
+    const int w = lid >> 6, c = lid & 15, g = (lid >> 4) & 3;
+    const int mt = w & 3, n0 = 4 * (w >> 2);
+    bool inside = false;
+    __syncthreads();  // previous tile's LDS reads done
+    if (tid < kTE)
+      inside = grad_entry(L, Ld, tid, tile * kTE + tid, total, nact, R, G, ld, diag, rho, theta, s);
     // entries outside the window have dL/dy = 0: skip tiles without any inside
-    if (!__syncthreads_or(tid < kTE && in.valid && in.inside)) continue;
-    forward_tile(L, z2, eg, kg);
-    // dL/dy per entry: w = r q^-1/2, q = dm^2 + c^2, c = s softplus(y)
-    if (tid < kTE) {
-      float dy = 0.0f;
-      if (in.valid) {
-        const float y = L[sY + tid];
-        const EntryOut o = regularise(in, y, s, false, nullptr);
-        if (!o.floored && o.c > 0.0) {
-          const double sg = 1.0 / (1.0 + exp(-(double)y));
-          dy = (float)(-Ld[kTE + tid] * Ld[tid] * o.c * s * sg / (o.q * sqrt(o.q)));
-        }
-      }
-      L[sDY + tid] = dy;
+    if (!__syncthreads_or(inside)) continue;
+    // layer 1: H1[e][j] = silu(b1[j] + W1[j] . phi[e])
+    for (int idx = tid; idx < kTE * kH; idx += kGT) {
+      const int e = idx >> 7, j = idx & 127;
+      const float* w1 = L + gW1 + j * 4;
+      const float* ph = L + gPhi + e * 4;
+      L[gH1 + swz(e, j)] = silu(L[gB1 + j] + w1[0] * ph[0] + w1[1] * ph[1] + w1[2] * ph[2]);
     }
+    __syncthreads();
+    // layer 2: z[tt][r] = Z2[e = 16 mt + 4 g + r][k = 16 (n0 + tt) + c]
+    f4 z[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      const float b = L[gB2 + 16 * (n0 + tt) + c];
+      z[tt] = f4{b, b, b, b};
+    }
+#pragma unroll 4
+    for (int j4 = 0; j4 < kH; j4 += 4) {
+      const float a = L[gH1 + swz(16 * mt + c, j4 + g)];
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt)
+        z[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L[gW2 + swz(16 * (n0 + tt) + c, j4 + g)],
+                                                     z[tt], 0, 0, 0);
+    }
+    // layer 3 over this wave's 64 neurons, reduced over the 16 lanes of a row
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float p = 0.0f;
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) p = fmaf(L[gW3 + 16 * (n0 + tt) + c], silu(z[tt][r]), p);
+#pragma unroll
+      for (int off = 8; off >= 1; off >>= 1) p += __shfl_xor(p, off, 16);
+      if (c == 0) L[gYP + (w >> 2) * kTE + 16 * mt + 4 * g + r] = p;
+    }
+    __syncthreads();
+    if (tid < kTE)
+      L[gDY + tid] =
+          grad_entry_dy(Ld, tid, inside, L[gB3] + L[gYP + tid] + L[gYP + kTE + tid], s);
     __syncthreads();
     if (tid == 0) {
       float t = 0.0f;
-      for (int e = 0; e < kTE; ++e) t += L[sDY + e];
-      aB3 += (double)t;
+      for (int e = 0; e < kTE; ++e) t += L[gDY + e];
+      Ld[dB3] += (double)t;
     }
-    // dz2 = dy w3 silu'(z2); dW3 += dy h2; db2 += dz2
+    // dz2 = dy w3 silu'(z2) into LDS; dW3 += dy h2, db2 += dz2 (this entry tile)
     {
-      float pW3[8], pB2[8];
+      float pW3[4], pB2[4];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) pW3[k] = pB2[k] = 0.0f;
+      for (int tt = 0; tt < 4; ++tt) pW3[tt] = pB2[tt] = 0.0f;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float dy = L[sDY + 4 * eg + e];
+      for (int r = 0; r < 4; ++r) {
+        const int e = 16 * mt + 4 * g + r;
+        const float dy = L[gDY + e];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const float z = z2[e][k];
-          const float dz = dy * L[sW3 + 8 * kg + k] * dsilu(z);
-          L[sDZ2 + (8 * kg + k) * kHS + 4 * eg + e] = dz;
-          pW3[k] = fmaf(dy, silu(z), pW3[k]);
-          pB2[k] += dz;
+        for (int tt = 0; tt < 4; ++tt) {
+          const int k = 16 * (n0 + tt) + c;
+          const float zz = z[tt][r], sg = sigm(zz);
+          const float dz = dy * L[gW3 + k] * (sg * (1.0f + zz * (1.0f - sg)));
+          L[gDZ + swz(e, k)] = dz;
+          pW3[tt] = fmaf(dy, zz * sg, pW3[tt]);
+          pB2[tt] += dz;
         }
       }
-      // reduce over the 16 entry groups (lanes with equal kg are one
-      // 16-lane segment of a wave)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-#pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) {
-          pW3[k] += __shfl_xor(pW3[k], off, 16);
-          pB2[k] += __shfl_xor(pB2[k], off, 16);
-        }
-      }
-      if (eg == 0) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          L[sGA + (8 * kg + k) * 8 + 4] = pB2[k];
-          L[sGA + (8 * kg + k) * 8 + 5] = pW3[k];
+      for (int tt = 0; tt < 4; ++tt) {
+        pW3[tt] += __shfl_xor(pW3[tt], 16);
+        pB2[tt] += __shfl_xor(pB2[tt], 16);
+        pW3[tt] += __shfl_xor(pW3[tt], 32);
+        pB2[tt] += __shfl_xor(pB2[tt], 32);
+        if (g == 0) {
+          float* q = L + gP2 + (mt * kH + 16 * (n0 + tt) + c) * 2;
+          q[0] = pW3[tt];
+          q[1] = pB2[tt];
         }
       }
     }
     __syncthreads();
-    // dW2[k][j] += sum_e dz2[k][e] h1[j][e]; thread: k = 8 kg .., j = 8 eg ..
+    // dW2 = dZ2^T H1 for neuron tile w (fp32 per tile, fp64 across tiles)
     {
-      float t[8][8];
+      f4 acc[8];
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+      for (int t = 0; t < 8; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 2
+      for (int e4 = 0; e4 < kTE; e4 += 4) {
+        const float a = L[gDZ + swz(e4 + g, 16 * w + c)];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) t[a][b] = 0.0f;
-      for (int e = 0; e < kTE; e += 4) {
-        float4 dz[8], hv[8];
-#pragma unroll
-        for (int a = 0; a < 8; ++a)
-          dz[a] = *reinterpret_cast<const float4*>(L + sDZ2 + (8 * kg + a) * kHS + e);
-#pragma unroll
-        for (int b = 0; b < 8; ++b)
-          hv[b] = *reinterpret_cast<const float4*>(L + sH1 + (8 * eg + b) * kHS + e);
-#pragma unroll
-        for (int a = 0; a < 8; ++a)
-#pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            float v = t[a][b];
-            v = fmaf(dz[a].x, hv[b].x, v);
-            v = fmaf(dz[a].y, hv[b].y, v);
-            v = fmaf(dz[a].z, hv[b].z, v);
-            v = fmaf(dz[a].w, hv[b].w, v);
-            t[a][b] = v;
-          }
+        for (int t = 0; t < 8; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L[gH1 + swz(e4 + g, 16 * t + c)],
+                                                        acc[t], 0, 0, 0);
       }
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+      for (int t = 0; t < 8; ++t)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) aW2[a][b] += (double)t[a][b];
+        for (int r = 0; r < 4; ++r) aW2[t][r] += (double)acc[t][r];
     }
-    // dh1[e][j] = sum_k dz2[k][e] W2[k][j]; thread: e = 4 eg .., j = 8 kg ..
+    // dH1 = dZ2 W2, then dz1 = dh1 silu'(z1); dW1 += dz1 phi, db1 += dz1
     {
-      float dh[4][8];
+      f4 dh[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int tt = 0; tt < 4; ++tt) dh[tt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+      for (int k4 = 0; k4 < kH; k4 += 4) {
+        const float a = L[gDZ + swz(16 * mt + c, k4 + g)];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) dh[e][b] = 0.0f;
-      for (int k = 0; k < kH; ++k) {
-        const float4 dz = *reinterpret_cast<const float4*>(L + sDZ2 + k * kHS + 4 * eg);
-        const float dd[4] = {dz.x, dz.y, dz.z, dz.w};
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const float w = L[sW2T + (8 * kg + b) * kW2S + k];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) dh[e][b] = fmaf(dd[e], w, dh[e][b]);
-        }
+        for (int tt = 0; tt < 4; ++tt)
+          dh[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L[gW2 + swz(k4 + g, 16 * (n0 + tt) + c)],
+                                                        dh[tt], 0, 0, 0);
       }
-      // dz1 = dh1 silu'(z1); dW1 += dz1 phi; db1 += dz1
-      float p0[8], p1[8], p2[8], pb[8];
+      float p0[4], p1[4], p2[4], pb[4];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) p0[b] = p1[b] = p2[b] = pb[b] = 0.0f;
+      for (int tt = 0; tt < 4; ++tt) p0[tt] = p1[tt] = p2[tt] = pb[tt] = 0.0f;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float* ph = L + sPhi + (4 * eg + e) * 4;
+      for (int r = 0; r < 4; ++r) {
+        const float* ph = L + gPhi + (16 * mt + 4 * g + r) * 4;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int j = 8 * kg + b;
-          const float* w1 = L + sW1 + j * 4;
-          const float z1 = L[sB1 + j] + w1[0] * ph[0] + w1[1] * ph[1] + w1[2] * ph[2];
-          const float dz1 = dh[e][b] * dsilu(z1);
-          p0[b] = fmaf(dz1, ph[0], p0[b]);
-          p1[b] = fmaf(dz1, ph[1], p1[b]);
-          p2[b] = fmaf(dz1, ph[2], p2[b]);
-          pb[b] += dz1;
+        for (int tt = 0; tt < 4; ++tt) {
+          const int j = 16 * (n0 + tt) + c;
+          const float* w1 = L + gW1 + j * 4;
+          const float z1 = L[gB1 + j] + w1[0] * ph[0] + w1[1] * ph[1] + w1[2] * ph[2];
+          const float dz1 = dh[tt][r] * dsilu(z1);
+          p0[tt] = fmaf(dz1, ph[0], p0[tt]);
+          p1[tt] = fmaf(dz1, ph[1], p1[tt]);
+          p2[tt] = fmaf(dz1, ph[2], p2[tt]);
+          pb[tt] += dz1;
         }
       }
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
+      for (int tt = 0; tt < 4; ++tt) {
 #pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) {
-          p0[b] += __shfl_xor(p0[b], off, 16);
-          p1[b] += __shfl_xor(p1[b], off, 16);
-          p2[b] += __shfl_xor(p2[b], off, 16);
-          pb[b] += __shfl_xor(pb[b], off, 16);
+        for (int off = 16; off <= 32; off <<= 1) {
+          p0[tt] += __shfl_xor(p0[tt], off);
+          p1[tt] += __shfl_xor(p1[tt], off);
+          p2[tt] += __shfl_xor(p2[tt], off);
+          pb[tt] += __shfl_xor(pb[tt], off);
         }
-      }
-      if (eg == 0) {
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          float* g = L + sGA + (8 * kg + b) * 8;
-          g[0] = p0[b];
-          g[1] = p1[b];
-          g[2] = p2[b];
-          g[3] = pb[b];
+        if (g == 0) {
+          float* q = L + gP1 + (mt * kH + 16 * (n0 + tt) + c) * 4;
+          q[0] = p0[tt];
+          q[1] = p1[tt];
+          q[2] = p2[tt];
+          q[3] = pb[tt];
         }
       }
     }
     __syncthreads();
     if (tid < kH) {
+      float q[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-      for (int c = 0; c < 6; ++c) aRow[c] += (double)L[sGA + tid * 8 + c];
+      for (int m = 0; m < 4; ++m) {
+        const float* p1 = L + gP1 + (m * kH + tid) * 4;
+        const float* p2 = L + gP2 + (m * kH + tid) * 2;
+        q[0] += p1[0];
+        q[1] += p1[1];
+        q[2] += p1[2];
+        q[3] += p1[3];
+        q[4] += p2[1];
+        q[5] += p2[0];
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) Ld[dRow + k * kH + tid] += (double)q[k];
     }
   }
+  __syncthreads();
   double* out = part + (size_t)blockIdx.x * kMlpParams;
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int t = 0; t < 8; ++t)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) out[oW2 + (8 * kg + a) * kH + 8 * eg + b] = aW2[a][b];
+    for (int r = 0; r < 4; ++r)
+      out[oW2 + (16 * (tid >> 6) + 4 * ((tid >> 4) & 3) + r) * kH + 16 * t + (tid & 15)] = aW2[t][r];
   if (tid < kH) {
-    out[oW1 + tid * 3 + 0] = aRow[0];
-    out[oW1 + tid * 3 + 1] = aRow[1];
-    out[oW1 + tid * 3 + 2] = aRow[2];
-    out[oB1 + tid] = aRow[3];
-    out[oB2 + tid] = aRow[4];
-    out[oW3 + tid] = aRow[5];
+    out[oW1 + tid * 3 + 0] = Ld[dRow + 0 * kH + tid];
+    out[oW1 + tid * 3 + 1] = Ld[dRow + 1 * kH + tid];
+    out[oW1 + tid * 3 + 2] = Ld[dRow + 2 * kH + tid];
+    out[oB1 + tid] = Ld[dRow + 3 * kH + tid];
+    out[oB2 + tid] = Ld[dRow + 4 * kH + tid];
+    out[oW3 + tid] = Ld[dRow + 5 * kH + tid];
   }
-  if (tid == 0) out[oB3] = aB3;
+  if (tid == 0) out[oB3] = Ld[dB3];
 }
 
 // Inference with layer 2 on bf16 MFMA (v_mfma_f32_16x16x32_bf16, fp32
@@ -857,7 +961,7 @@ hipError_t mlp_grad(const double* R, const double* G, int64_t ld, int nact, int6
   }
   const int grid = (n > 0 && nact > 0) ? mlp_grid(n * nact) : 0;
   if (grid > 0)
-    hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(256), kGradBytes, st, R, G, ld, nact, n,
+    hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(kGT), kGradBytes, st, R, G, ld, nact, n,
                        theta, diag, rho, s, w, part);
   hipLaunchKernelGGL(k_grad_reduce, dim3(cdiv64(kMlpParams, 256)), dim3(256), 0, st, part, grid,
                      grad);

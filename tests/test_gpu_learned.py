@@ -140,8 +140,12 @@ def test_learned_apply_nonfinite_weights_fall_back(P, bf16):
     assert np.allclose(Rd.cpu().numpy(), ref, rtol=1e-14 if bf16 == 0 else 1e-6, atol=0)
 
 
-def test_learner_objective_and_gradient_match_oracle(P):
-    C, As, X, rho = family_problem()
+@pytest.mark.parametrize("n", [3000, 20011])
+def test_learner_objective_and_gradient_match_oracle(P, n):
+    """n = 3000: one 64-entry tile per workgroup; n = 20011: 938 tiles over
+    the 256 workgroups (several per workgroup, fp64 sums across them) and a
+    ragged last tile of one entry."""
+    C, As, X, rho = family_problem(n=n)
     n, m = X.shape
     s = solver_for(P, C, m)
     L = P.lobpcg_learner_create(0, 3)
@@ -152,6 +156,11 @@ def test_learner_objective_and_gradient_match_oracle(P):
         info = P.lobpcg_learner_snapshot_info(L, snap, m)
         th = np.einsum("ij,ij->j", X, As @ X)
         assert np.allclose(info["theta"], th, rtol=1e-13)
+        # the oracle takes the snapshot's own theta (a sum over n terms whose
+        # order differs from numpy's by ~1e-14 relative): the Jacobi step
+        # r / (d - theta) amplifies that ~1e5-fold in Delta where some
+        # |d_i - theta| ~ 1e-5
+        th = np.asarray(info["theta"], dtype=np.float64)
         R = As @ X - X * th
         assert np.allclose(info["resnorm"], np.linalg.norm(R, axis=0), rtol=1e-10)
         cols = [0, 2, 5]
