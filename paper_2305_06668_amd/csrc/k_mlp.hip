@@ -13,22 +13,22 @@
 // finite, takes c = 0: the
 // guarded absolute Jacobi step (the diagonal fallback).
 //
-// Work layout: a workgroup of 256 threads holds W2^T (128 x 128 fp32, rows
-// padded to 132 floats) and the small layers in LDS and walks tiles of 64
-// entries (entry e = row * nact + column, contiguous in the row-major
-// block).  Layer 2 is a 64 x 128 x 128 product per tile: thread (eg, kg)
-// owns entries 4eg..4eg+3 and neurons 8kg..8kg+7 in 32 fp32 accumulators,
-// reading one float4 of h1 and two float4 of W2^T per step of the inner
-// dimension; LDS reads are broadcasts (16 distinct h1 chunks and 4 distinct
-// W2^T chunks per wave).  The layer-3 dot is reduced over the 16 neuron
-// groups through LDS in a fixed order.
+// fp32 path (k_mlp_apply, and the forward inside training): a workgroup of
+// 512 threads (eight waves, two per SIMD) holds W2 (128 x 128 fp32) and the
+// small layers in LDS and walks tiles of 64 entries (entry e = row * nact +
+// column, contiguous in the row-major block).  Layer 2 is a 64 x 128 x 128
+// product per tile on v_mfma_f32_16x16x4f32: wave w computes entries
+// 16 (w & 3) + [0, 16) against neurons 64 (w >> 2) + [0, 64); layer 3 is
+// reduced over a wave's 16 neuron lanes with xor shuffles and over the two
+// neuron halves through LDS.  Tiles are screened eight at a time (one entry
+// per thread, a ballot per wave); only tiles with an entry inside the window
+// run the net, the others take the Jacobi step in the screening pass.
 //
-// Training (k_mlp_grad): the forward pass and the analytic backward pass
-// for an output gradient dL/dw given per entry, with the tile's three
-// 64 x 128 x 128 contractions (layer 2 forward, dW2, dH1) on fp32 MFMA;
-// per-tile sums are formed in fp32 and accumulated across tiles in fp64 per
-// workgroup; k_grad_reduce adds the workgroup partials in a fixed order,
-// k_adam updates the fp32 master weights.
+// Training (k_mlp_grad): that forward pass, then the analytic backward pass
+// for an output gradient dL/dw given per entry, its two contractions (dW2,
+// dH1) on the same MFMA; per-tile sums are formed in fp32 and accumulated
+// across tiles in fp64 per workgroup; k_grad_reduce adds the workgroup
+// partials in a fixed order, k_adam updates the fp32 master weights.
 #include <algorithm>
 #include <cmath>
 
@@ -40,27 +40,13 @@ namespace {
 
 constexpr int kH = kMlpHidden;
 constexpr int kTE = 64;          // entries per tile
-constexpr int kW2S = 132;        // padded row stride of W2^T
-constexpr int kHS = kTE + 4;     // padded row stride of h1 / dz2 ([neuron][entry])
 constexpr int oW1 = 0, oB1 = kH * kMlpFeat, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH,
               oB3 = oW3 + kH;
 static_assert(oB3 + 1 == kMlpParams, "parameter layout");
 
-// LDS layout (floats)
-constexpr int sW2T = 0;
-constexpr int sW1 = sW2T + kH * kW2S;
-constexpr int sB1 = sW1 + kH * 4;  // W1 rows padded to 4
-constexpr int sB2 = sB1 + kH;
-constexpr int sW3 = sB2 + kH;
-constexpr int sB3 = sW3 + kH;
-constexpr int sPhi = sB3 + 4;            // [e][4]
-constexpr int sH1 = sPhi + kTE * 4;      // [j][kHS]
-constexpr int sYP = sH1 + kH * kHS;      // [kg][kTE] layer-3 partials
-constexpr int sY = sYP + 16 * kTE;       // [e]
-constexpr int kFwdFloats = sY + kTE;
-constexpr size_t kFwdBytes = sizeof(float) * kFwdFloats;
-
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// fp32 activations; the reciprocal is v_rcp_f32 (1 ulp) rather than a
+// full division
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float dsilu(float z) {
   const float s = sigm(z);
@@ -68,23 +54,6 @@ __device__ __forceinline__ float dsilu(float z) {
 }
 __device__ __forceinline__ double softplus_d(double y) {
   return fmax(y, 0.0) + log1p(exp(-fabs(y)));
-}
-
-__device__ __forceinline__ void load_weights(const float* __restrict__ wts, float* L) {
-  for (int idx = threadIdx.x; idx < kH * kH; idx += blockDim.x) {
-    const int k = idx / kH, j = idx - k * kH;  // W2[k][j]
-    L[sW2T + j * kW2S + k] = wts[oW2 + idx];
-  }
-  for (int idx = threadIdx.x; idx < kH; idx += blockDim.x) {
-    L[sW1 + idx * 4 + 0] = wts[oW1 + idx * 3 + 0];
-    L[sW1 + idx * 4 + 1] = wts[oW1 + idx * 3 + 1];
-    L[sW1 + idx * 4 + 2] = wts[oW1 + idx * 3 + 2];
-    L[sW1 + idx * 4 + 3] = 0.0f;
-    L[sB1 + idx] = wts[oB1 + idx];
-    L[sB2 + idx] = wts[oB2 + idx];
-    L[sW3 + idx] = wts[oW3 + idx];
-  }
-  if (threadIdx.x == 0) L[sB3] = wts[oB3];
 }
 
 // Per-entry inputs of one tile entry.
@@ -96,75 +65,6 @@ struct EntryIn {
   double dm;     // d_i - theta_j
   double theta;
 };
-
-// Features of tile entry e into LDS (threads 0..kTE-1).
-__device__ __forceinline__ EntryIn entry_features(float* L, int e, int64_t ent, int64_t total,
-                                                  int nact, const double* __restrict__ diag,
-                                                  const double* __restrict__ rho,
-                                                  const double* __restrict__ theta, double s) {
-  EntryIn in{};
-  in.valid = ent < total;
-  float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
-  if (in.valid) {
-    in.row = ent / nact;
-    in.col = (int)(ent - in.row * nact);
-    in.theta = theta[in.col];
-    in.dm = diag[in.row] - in.theta;
-    const double rr = rho[in.row];
-    in.inside = fabs(in.dm) <= kMlpWindow * rr;
-    f0 = (float)log(fabs(in.dm) / s + 1e-6);
-    f1 = (float)(in.theta / s);
-    f2 = (float)log(rr / s + 1e-6);
-  }
-  L[sPhi + e * 4 + 0] = f0;
-  L[sPhi + e * 4 + 1] = f1;
-  L[sPhi + e * 4 + 2] = f2;
-  return in;
-}
-
-// Layer 1 into h1 (all threads), then layer 2 into z2 registers and the
-// layer-3 partials; y of each tile entry lands in L[sY + e].  Two barriers.
-__device__ __forceinline__ void forward_tile(float* L, float (&z2)[4][8], int eg, int kg) {
-  for (int idx = threadIdx.x; idx < kH * kTE; idx += blockDim.x) {
-    const int j = idx / kTE, e = idx - j * kTE;
-    const float* w1 = L + sW1 + j * 4;
-    const float* ph = L + sPhi + e * 4;
-    const float z = L[sB1 + j] + w1[0] * ph[0] + w1[1] * ph[1] + w1[2] * ph[2];
-    L[sH1 + j * kHS + e] = silu(z);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-#pragma unroll
-    for (int k = 0; k < 8; ++k) z2[e][k] = L[sB2 + 8 * kg + k];
-  const float* h1 = L + sH1 + 4 * eg;
-  const float* w2 = L + sW2T + 8 * kg;
-#pragma unroll 4
-  for (int j = 0; j < kH; ++j) {
-    const float4 hv = *reinterpret_cast<const float4*>(h1 + j * kHS);
-    const float4 wa = *reinterpret_cast<const float4*>(w2 + j * kW2S);
-    const float4 wb = *reinterpret_cast<const float4*>(w2 + j * kW2S + 4);
-    const float hh[4] = {hv.x, hv.y, hv.z, hv.w};
-    const float ww[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int k = 0; k < 8; ++k) z2[e][k] = fmaf(hh[e], ww[k], z2[e][k]);
-  }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    float acc = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) acc = fmaf(L[sW3 + 8 * kg + k], silu(z2[e][k]), acc);
-    L[sYP + kg * kTE + 4 * eg + e] = acc;
-  }
-  __syncthreads();
-  if (threadIdx.x < kTE) {
-    float y = L[sB3];
-    for (int g = 0; g < 16; ++g) y += L[sYP + g * kTE + threadIdx.x];
-    L[sY + threadIdx.x] = y;
-  }
-}
 
 struct EntryOut {
   double c;      // regulariser (0 on fallback)
@@ -190,58 +90,11 @@ __device__ __forceinline__ EntryOut regularise(const EntryIn& in, float y, doubl
   return o;
 }
 
-// Inference: R (n x nact, leading dimension ld) is replaced by the learned
-// preconditioned columns.
-template <typename T>
-__global__ __launch_bounds__(256) void k_mlp_apply(T* __restrict__ R, int64_t ld, int nact,
-                                                   int64_t n, const double* __restrict__ theta,
-                                                   const double* __restrict__ diag,
-                                                   const double* __restrict__ rho,
-                                                   const double* __restrict__ sptr,
-                                                   const float* __restrict__ wts,
-                                                   const int* __restrict__ mask,
-                                                   uint64_t mbits,
-                                                   int* __restrict__ flags) {
-  extern __shared__ float L[];
-  load_weights(wts, L);
-  const double s = *sptr;
-  const int eg = threadIdx.x & 15, kg = threadIdx.x >> 4;
-  const int64_t total = n * nact;
-  const int64_t ntiles = (total + kTE - 1) / kTE;
-  float z2[4][8];
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    EntryIn in{};
-    __syncthreads();  // weights loaded / previous tile's LDS reads done
-    if (threadIdx.x < kTE)
-      in = entry_features(L, threadIdx.x, tile * kTE + threadIdx.x, total, nact, diag, rho, theta,
-                          s);
-    // the net only matters inside the window: skip it for tiles without such entries
-    if (__syncthreads_or(threadIdx.x < kTE && in.valid && in.inside)) forward_tile(L, z2, eg, kg);
-    if (threadIdx.x < kTE && in.valid) {
-      const bool jac = ((mbits >> in.col) & 1) != 0 || (mask != nullptr && mask[in.col] != 0);
-      const EntryOut o = regularise(in, L[sY + threadIdx.x], s, jac, flags);
-      T* p = R + in.row * ld + in.col;
-      *p = (T)((double)*p / sqrt(o.q));
-    }
-  }
-}
-
-// Training: per-workgroup partial gradients (kMlpParams doubles each) of
-// sum_e G_e w_e, where w is the learned column of R and G = dL/dw is given
-// (same layout as R).  512 threads (eight waves, two per SIMD) per tile of
-// kTE entries; the tile's three 64 x 128 x 128 contractions run on
-// v_mfma_f32_16x16x4f32 (fp32 in, fp32 accumulate):
-//   forward  Z2  = H1 W2^T   wave w: entry tile w & 3, neuron tiles 4 (w >> 2) + [0, 4)
-//   dW2      dW2 = dZ2^T H1  wave w: neuron tile w (rows k), all eight column tiles j
-//   dH1      dH1 = dZ2 W2    wave w: entry tile w & 3, column tiles 4 (w >> 2) + [0, 4)
-// The activations, layers 1 and 3 and the regulariser's derivative stay on
-// the vector units.  Per-tile sums are fp32 (the MFMA accumulators, xor
-// shuffles, and LDS partials added in a fixed order); they are accumulated
-// across tiles in fp64 per workgroup.
+// ---- fp32 MFMA tile kernels (512 threads) ----
 constexpr int kGT = 512;
 constexpr int gW2 = 0;                // W2 [k][j]
 constexpr int gH1 = gW2 + kH * kH;    // H1 [e][j]
-constexpr int gDZ = gH1 + kTE * kH;   // dZ2 [e][k]
+constexpr int gDZ = gH1 + kTE * kH;   // dZ2 [e][k] (training)
 constexpr int gW1 = gDZ + kTE * kH;   // [j][4]
 constexpr int gB1 = gW1 + kH * 4;
 constexpr int gB2 = gB1 + kH;
@@ -252,13 +105,15 @@ constexpr int gYP = gPhi + kTE * 4;   // [2][e] layer-3 partials of the two neur
 constexpr int gDY = gYP + 2 * kTE;    // [e]
 constexpr int gP1 = gDY + kTE;        // [4][j][4] dW1 (3), db1 per entry tile
 constexpr int gP2 = gP1 + 4 * kH * 4; // [4][k][2] dW3, db2 per entry tile
-constexpr int gEnd = gP2 + 4 * kH * 2;
+constexpr int gAct = gP2 + 4 * kH * 2;  // [8] ints: tile of the screened group has an entry inside
+constexpr int gEnd = gAct + 8;
+constexpr int kGroup = kGT / kTE;     // tiles screened together, one per wave
 // then doubles: per entry r, dL/dw, d - theta, theta; per neuron the fp64
 // sums dW1 (3), db1, db2, dW3; dB3
 constexpr int dR = 0, dG = kTE, dDM = 2 * kTE, dTH = 3 * kTE, dRow = 4 * kTE,
               dB3 = dRow + 6 * kH, dEnd = dB3 + 2;
-constexpr size_t kGradBytes = sizeof(float) * gEnd + sizeof(double) * dEnd;
-static_assert(gEnd % 2 == 0 && kGradBytes <= 160 * 1024, "LDS budget");
+constexpr size_t kTileBytes = sizeof(float) * gEnd + sizeof(double) * dEnd;
+static_assert(gEnd % 2 == 0 && kTileBytes <= 160 * 1024, "LDS budget");
 
 // Rows of 128 floats with the column bits 2..5 xor-ed by the row's low four
 // bits: a wave's operand reads of 16 rows x 4 columns and of 4 rows x 16
@@ -267,10 +122,26 @@ __device__ __forceinline__ int swz(int row, int col) {
   return row * kH + (col ^ (((row & 3) << 4) | (((row >> 2) & 3) << 2)));
 }
 
-// Features of tile entry e into LDS, with the entry's r, dL/dw, d - theta
-// and theta; returns whether the entry is inside the window.  Not inlined:
-// the constants of the fp64 log stay out of the caller's tile loop.
-__device__ __noinline__ bool grad_entry(float* L, double* Ld, int e, int64_t ent, int64_t total,
+__device__ __forceinline__ void load_weights(const float* __restrict__ wts, float* L) {
+  for (int idx = threadIdx.x; idx < kH * kH; idx += kGT)
+    L[gW2 + swz(idx >> 7, idx & 127)] = wts[oW2 + idx];
+  for (int idx = threadIdx.x; idx < kH; idx += kGT) {
+    L[gW1 + idx * 4 + 0] = wts[oW1 + idx * 3 + 0];
+    L[gW1 + idx * 4 + 1] = wts[oW1 + idx * 3 + 1];
+    L[gW1 + idx * 4 + 2] = wts[oW1 + idx * 3 + 2];
+    L[gW1 + idx * 4 + 3] = 0.0f;
+    L[gB1 + idx] = wts[oB1 + idx];
+    L[gB2 + idx] = wts[oB2 + idx];
+    L[gW3 + idx] = wts[oW3 + idx];
+  }
+  if (threadIdx.x == 0) L[gB3] = wts[oB3];
+}
+
+// Features of tile entry e into LDS, with the entry's d - theta and theta
+// and (R, G given) its r and dL/dw; returns whether the entry is inside the
+// window.  Not inlined: the constants of the fp64 log stay out of the
+// callers' tile loops.
+__device__ __noinline__ bool tile_entry(float* L, double* Ld, int e, int64_t ent, int64_t total,
                                         int nact, const double* __restrict__ R,
                                         const double* __restrict__ G, int64_t ld,
                                         const double* __restrict__ diag,
@@ -289,8 +160,10 @@ __device__ __noinline__ bool grad_entry(float* L, double* Ld, int e, int64_t ent
     f0 = (float)log(fabs(dm) / s + 1e-6);
     f1 = (float)(th / s);
     f2 = (float)log(rr / s + 1e-6);
-    r = R[row * ld + col];
-    gg = G[row * ld + col];
+    if (R != nullptr) {
+      r = R[row * ld + col];
+      gg = G[row * ld + col];
+    }
   }
   L[gPhi + e * 4 + 0] = f0;
   L[gPhi + e * 4 + 1] = f1;
@@ -302,10 +175,158 @@ __device__ __noinline__ bool grad_entry(float* L, double* Ld, int e, int64_t ent
   return inside;
 }
 
+// Screening of the group of kGroup tiles from tile t0: thread tid takes
+// entry t0 kTE + tid (wave w = tile t0 + w) and the wave's ballot records
+// whether its tile has an entry inside the window.  Without a Jacobi target
+// (J == nullptr) that is all; with one, the entries of tiles with none
+// inside take the guarded Jacobi step there (the learned step with c = 0).
+// The caller syncs before reading the flags.
+template <typename T>
+__device__ __forceinline__ void screen_group(float* L, int64_t t0, int64_t total, int nact,
+                                             const double* __restrict__ diag,
+                                             const double* __restrict__ rho,
+                                             const double* __restrict__ theta, T* __restrict__ J,
+                                             int64_t ld) {
+  const int64_t ent = t0 * kTE + threadIdx.x;
+  const bool valid = ent < total;
+  int64_t row = 0;
+  int col = 0;
+  double dm = 0.0, th = 0.0;
+  bool ins = false;
+  if (valid) {
+    row = ent / nact;
+    col = (int)(ent - row * nact);
+    th = theta[col];
+    dm = diag[row] - th;
+    ins = fabs(dm) <= kMlpWindow * rho[row];
+  }
+  const bool act = __ballot(ins) != 0;
+  if ((threadIdx.x & 63) == 0) reinterpret_cast<int*>(L + gAct)[threadIdx.x >> 6] = act ? 1 : 0;
+  if (J != nullptr && valid && !act) {
+    const double delta = kPrecondGuard * fmax(1.0, fabs(th));
+    T* p = J + row * ld + col;
+    *p = (T)((double)*p / sqrt(fmax(dm * dm, delta * delta)));
+  }
+}
+
+// Layer 1 into H1 (all threads), then layer 2 on MFMA: wave w's
+// z[tt][r] = Z2[e = 16 (w & 3) + 4 g + r][k = 16 (4 (w >> 2) + tt) + c],
+// and the layer-3 partial of each entry over the wave's 64 neurons into
+// L[gYP + (w >> 2) kTE + e].  One barrier inside; the caller syncs before
+// reading the partials.
+__device__ __forceinline__ void mfma_forward(float* L, f4 (&z)[4], int w, int c, int g) {
+  const int mt = w & 3, n0 = 4 * (w >> 2);
+  for (int idx = threadIdx.x; idx < kTE * kH; idx += kGT) {
+    const int e = idx >> 7, j = idx & 127;
+    const float* w1 = L + gW1 + j * 4;
+    const float* ph = L + gPhi + e * 4;
+    L[gH1 + swz(e, j)] = silu(L[gB1 + j] + w1[0] * ph[0] + w1[1] * ph[1] + w1[2] * ph[2]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) {
+    const float b = L[gB2 + 16 * (n0 + tt) + c];
+    z[tt] = f4{b, b, b, b};
+  }
+#pragma unroll 4
+  for (int j4 = 0; j4 < kH; j4 += 4) {
+    const float a = L[gH1 + swz(16 * mt + c, j4 + g)];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt)
+      z[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L[gW2 + swz(16 * (n0 + tt) + c, j4 + g)],
+                                                   z[tt], 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float p = 0.0f;
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) p = fmaf(L[gW3 + 16 * (n0 + tt) + c], silu(z[tt][r]), p);
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) p += __shfl_xor(p, off, 16);
+    if (c == 0) L[gYP + (w >> 2) * kTE + 16 * mt + 4 * g + r] = p;
+  }
+}
+
+// The learned step of tile entry e (valid), written over R.
+template <typename T>
+__device__ __noinline__ void apply_entry(const double* Ld, int e, int64_t ent, int nact,
+                                         T* __restrict__ R, int64_t ld, float y, double s,
+                                         bool inside, const int* __restrict__ mask,
+                                         uint64_t mbits, int* __restrict__ flags) {
+  EntryIn in{};
+  in.valid = true;
+  in.inside = inside;
+  in.row = ent / nact;
+  in.col = (int)(ent - in.row * nact);
+  in.dm = Ld[dDM + e];
+  in.theta = Ld[dTH + e];
+  const bool jac = ((mbits >> in.col) & 1) != 0 || (mask != nullptr && mask[in.col] != 0);
+  const EntryOut o = regularise(in, y, s, jac, flags);
+  T* p = R + in.row * ld + in.col;
+  *p = (T)((double)*p / sqrt(o.q));
+}
+
+// Inference: R (n x nact, leading dimension ld) is replaced by the learned
+// preconditioned columns.
+template <typename T>
+__global__ __launch_bounds__(kGT) void k_mlp_apply(T* __restrict__ R, int64_t ld, int nact,
+                                                   int64_t n, const double* __restrict__ theta,
+                                                   const double* __restrict__ diag,
+                                                   const double* __restrict__ rho,
+                                                   const double* __restrict__ sptr,
+                                                   const float* __restrict__ wts,
+                                                   const int* __restrict__ mask, uint64_t mbits,
+                                                   int* __restrict__ flags) {
+  extern __shared__ float L[];
+  double* Ld = reinterpret_cast<double*>(L + gEnd);
+  load_weights(wts, L);
+  const double s = *sptr;
+  const int tid = threadIdx.x;
+  const int64_t total = n * nact;
+  const int64_t ntiles = (total + kTE - 1) / kTE;
+  for (int64_t t0 = (int64_t)blockIdx.x * kGroup; t0 < ntiles; t0 += (int64_t)gridDim.x * kGroup) {
+    __syncthreads();  // previous group's flag reads done
+    // the net only matters inside the window: tiles without such entries
+    // take the Jacobi step here and skip it
+    screen_group(L, t0, total, nact, diag, rho, theta, R, ld);
+    __syncthreads();
+    for (int u = 0; u < kGroup; ++u) {
+      if (reinterpret_cast<const int*>(L + gAct)[u] == 0) continue;  // uniform in the workgroup
+      // lane indices opaque to the compiler (see k_mlp_grad)
+      int lid = tid;
+      asm volatile("" : "+v"(lid));
+      const int w = lid >> 6, c = lid & 15, g = (lid >> 4) & 3;
+      const int64_t ent = (t0 + u) * kTE + tid;
+      bool inside = false;
+      __syncthreads();  // weights loaded / previous tile's LDS reads done
+      if (tid < kTE)
+        inside = tile_entry(L, Ld, tid, ent, total, nact, nullptr, nullptr, 0, diag, rho, theta, s);
+      __syncthreads();
+      f4 z[4];
+      mfma_forward(L, z, w, c, g);
+      __syncthreads();
+      if (tid < kTE && ent < total)
+        apply_entry(Ld, tid, ent, nact, R, ld, L[gB3] + L[gYP + tid] + L[gYP + kTE + tid], s,
+                    inside, mask, mbits, flags);
+    }
+  }
+}
+
+// Training: per-workgroup partial gradients (kMlpParams doubles each) of
+// sum_e G_e w_e, where w is the learned column of R and G = dL/dw is given
+// (same layout as R).  The tile's three 64 x 128 x 128 contractions on
+// v_mfma_f32_16x16x4f32 (fp32 in, fp32 accumulate):
+//   forward  Z2  = H1 W2^T   wave w: entry tile w & 3, neuron tiles 4 (w >> 2) + [0, 4)
+//   dW2      dW2 = dZ2^T H1  wave w: neuron tile w (rows k), all eight column tiles j
+//   dH1      dH1 = dZ2 W2    wave w: entry tile w & 3, column tiles 4 (w >> 2) + [0, 4)
+// The activations, layers 1 and 3 and the regulariser's derivative stay on
+// the vector units.  Per-tile sums are fp32 (the MFMA accumulators, xor
+// shuffles, and LDS partials added in a fixed order); they are accumulated
+// across tiles in fp64 per workgroup (registers for dW2, LDS for the rest).
+
 // dL/dy of tile entry e (0 outside the window or where the floor or the
 // fallback holds): w = r q^-1/2, q = dm^2 + c^2, c = s softplus(y).
-__device__ __noinline__ float grad_entry_dy(const double* Ld, int e, bool inside, float y,
-                                            double s) {
+__device__ __noinline__ float entry_dy(const double* Ld, int e, bool inside, float y, double s) {
   if (!inside) return 0.0f;
   EntryIn in{};
   in.valid = true;
@@ -330,18 +351,8 @@ __global__ __launch_bounds__(kGT) void k_mlp_grad(const double* __restrict__ R,
   extern __shared__ float L[];
   double* Ld = reinterpret_cast<double*>(L + gEnd);
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < kH * kH; idx += kGT) L[gW2 + swz(idx >> 7, idx & 127)] = wts[oW2 + idx];
-  for (int idx = tid; idx < kH; idx += kGT) {
-    L[gW1 + idx * 4 + 0] = wts[oW1 + idx * 3 + 0];
-    L[gW1 + idx * 4 + 1] = wts[oW1 + idx * 3 + 1];
-    L[gW1 + idx * 4 + 2] = wts[oW1 + idx * 3 + 2];
-    L[gW1 + idx * 4 + 3] = 0.0f;
-    L[gB1 + idx] = wts[oB1 + idx];
-    L[gB2 + idx] = wts[oB2 + idx];
-    L[gW3 + idx] = wts[oW3 + idx];
-  }
+  load_weights(wts, L);
   for (int idx = tid; idx < 6 * kH + 2; idx += kGT) Ld[dRow + idx] = 0.0;
-  if (tid == 0) L[gB3] = wts[oB3];
   const double s = *sptr;
   const int64_t total = n * nact;
   const int64_t ntiles = (total + kTE - 1) / kTE;
@@ -350,179 +361,155 @@ __global__ __launch_bounds__(kGT) void k_mlp_grad(const double* __restrict__ R,
   for (int t = 0; t < 8; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) aW2[t][r] = 0.0;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    // the lane indices are re-derived per tile, opaque to the compiler: the
-    // swizzled LDS addresses built from them are recomputed inside the loop
-    // instead of being hoisted into (and spilled from) registers
-    int lid = tid;
-    asm volatile("" : "+v"(lid));
-    const int w = lid >> 6, c = lid & 15, g = (lid >> 4) & 3;
-    const int mt = w & 3, n0 = 4 * (w >> 2);
-    bool inside = false;
-    __syncthreads();  // previous tile's LDS reads done
-    if (tid < kTE)
-      inside = grad_entry(L, Ld, tid, tile * kTE + tid, total, nact, R, G, ld, diag, rho, theta, s);
-    // entries outside the window have dL/dy = 0: skip tiles without any inside
-    if (!__syncthreads_or(inside)) continue;
-    // layer 1: H1[e][j] = silu(b1[j] + W1[j] . phi[e])
-    for (int idx = tid; idx < kTE * kH; idx += kGT) {
-      const int e = idx >> 7, j = idx & 127;
-      const float* w1 = L + gW1 + j * 4;
-      const float* ph = L + gPhi + e * 4;
-      L[gH1 + swz(e, j)] = silu(L[gB1 + j] + w1[0] * ph[0] + w1[1] * ph[1] + w1[2] * ph[2]);
-    }
+  for (int64_t t0 = (int64_t)blockIdx.x * kGroup; t0 < ntiles; t0 += (int64_t)gridDim.x * kGroup) {
+    __syncthreads();  // previous group's flag reads done
+    // entries outside the window have dL/dy = 0: tiles without any inside are skipped
+    screen_group<double>(L, t0, total, nact, diag, rho, theta, nullptr, 0);
     __syncthreads();
-    // layer 2: z[tt][r] = Z2[e = 16 mt + 4 g + r][k = 16 (n0 + tt) + c]
-    f4 z[4];
+    for (int u = 0; u < kGroup; ++u) {
+      if (reinterpret_cast<const int*>(L + gAct)[u] == 0) continue;  // uniform in the workgroup
+      const int64_t tile = t0 + u;
+      // the lane indices are re-derived per tile, opaque to the compiler: the
+      // swizzled LDS addresses built from them are recomputed inside the loop
+      // instead of being hoisted into (and spilled from) registers
+      int lid = tid;
+      asm volatile("" : "+v"(lid));
+      const int w = lid >> 6, c = lid & 15, g = (lid >> 4) & 3;
+      const int mt = w & 3, n0 = 4 * (w >> 2);
+      bool inside = false;
+      __syncthreads();  // previous tile's LDS reads done
+      if (tid < kTE)
+        inside = tile_entry(L, Ld, tid, tile * kTE + tid, total, nact, R, G, ld, diag, rho, theta, s);
+      __syncthreads();
+      f4 z[4];  // Z2[e = 16 (w & 3) + 4 g + r][k = 16 (4 (w >> 2) + tt) + c]
+      mfma_forward(L, z, w, c, g);
+      __syncthreads();
+      if (tid < kTE)
+        L[gDY + tid] =
+            entry_dy(Ld, tid, inside, L[gB3] + L[gYP + tid] + L[gYP + kTE + tid], s);
+      __syncthreads();
+      if (tid == 0) {
+        float t = 0.0f;
+        for (int e = 0; e < kTE; ++e) t += L[gDY + e];
+        Ld[dB3] += (double)t;
+      }
+      // dz2 = dy w3 silu'(z2) into LDS; dW3 += dy h2, db2 += dz2 (this entry tile)
+      {
+        float pW3[4], pB2[4];
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      const float b = L[gB2 + 16 * (n0 + tt) + c];
-      z[tt] = f4{b, b, b, b};
-    }
-#pragma unroll 4
-    for (int j4 = 0; j4 < kH; j4 += 4) {
-      const float a = L[gH1 + swz(16 * mt + c, j4 + g)];
+        for (int tt = 0; tt < 4; ++tt) pW3[tt] = pB2[tt] = 0.0f;
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt)
-        z[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L[gW2 + swz(16 * (n0 + tt) + c, j4 + g)],
-                                                     z[tt], 0, 0, 0);
-    }
-    // layer 3 over this wave's 64 neurons, reduced over the 16 lanes of a row
+        for (int r = 0; r < 4; ++r) {
+          const int e = 16 * mt + 4 * g + r;
+          const float dy = L[gDY + e];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      float p = 0.0f;
-#pragma unroll
-      for (int tt = 0; tt < 4; ++tt) p = fmaf(L[gW3 + 16 * (n0 + tt) + c], silu(z[tt][r]), p);
-#pragma unroll
-      for (int off = 8; off >= 1; off >>= 1) p += __shfl_xor(p, off, 16);
-      if (c == 0) L[gYP + (w >> 2) * kTE + 16 * mt + 4 * g + r] = p;
-    }
-    __syncthreads();
-    if (tid < kTE)
-      L[gDY + tid] =
-          grad_entry_dy(Ld, tid, inside, L[gB3] + L[gYP + tid] + L[gYP + kTE + tid], s);
-    __syncthreads();
-    if (tid == 0) {
-      float t = 0.0f;
-      for (int e = 0; e < kTE; ++e) t += L[gDY + e];
-      Ld[dB3] += (double)t;
-    }
-    // dz2 = dy w3 silu'(z2) into LDS; dW3 += dy h2, db2 += dz2 (this entry tile)
-    {
-      float pW3[4], pB2[4];
-#pragma unroll
-      for (int tt = 0; tt < 4; ++tt) pW3[tt] = pB2[tt] = 0.0f;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int e = 16 * mt + 4 * g + r;
-        const float dy = L[gDY + e];
+          for (int tt = 0; tt < 4; ++tt) {
+            const int k = 16 * (n0 + tt) + c;
+            const float zz = z[tt][r], sg = sigm(zz);
+            const float dz = dy * L[gW3 + k] * (sg * (1.0f + zz * (1.0f - sg)));
+            L[gDZ + swz(e, k)] = dz;
+            pW3[tt] = fmaf(dy, zz * sg, pW3[tt]);
+            pB2[tt] += dz;
+          }
+        }
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-          const int k = 16 * (n0 + tt) + c;
-          const float zz = z[tt][r], sg = sigm(zz);
-          const float dz = dy * L[gW3 + k] * (sg * (1.0f + zz * (1.0f - sg)));
-          L[gDZ + swz(e, k)] = dz;
-          pW3[tt] = fmaf(dy, zz * sg, pW3[tt]);
-          pB2[tt] += dz;
+          pW3[tt] += __shfl_xor(pW3[tt], 16);
+          pB2[tt] += __shfl_xor(pB2[tt], 16);
+          pW3[tt] += __shfl_xor(pW3[tt], 32);
+          pB2[tt] += __shfl_xor(pB2[tt], 32);
+          if (g == 0) {
+            float* q = L + gP2 + (mt * kH + 16 * (n0 + tt) + c) * 2;
+            q[0] = pW3[tt];
+            q[1] = pB2[tt];
+          }
         }
       }
+      __syncthreads();
+      // dW2 = dZ2^T H1 for neuron tile w (fp32 per tile, fp64 across tiles)
+      {
+        f4 acc[8];
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
-        pW3[tt] += __shfl_xor(pW3[tt], 16);
-        pB2[tt] += __shfl_xor(pB2[tt], 16);
-        pW3[tt] += __shfl_xor(pW3[tt], 32);
-        pB2[tt] += __shfl_xor(pB2[tt], 32);
-        if (g == 0) {
-          float* q = L + gP2 + (mt * kH + 16 * (n0 + tt) + c) * 2;
-          q[0] = pW3[tt];
-          q[1] = pB2[tt];
-        }
-      }
-    }
-    __syncthreads();
-    // dW2 = dZ2^T H1 for neuron tile w (fp32 per tile, fp64 across tiles)
-    {
-      f4 acc[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int t = 0; t < 8; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 2
-      for (int e4 = 0; e4 < kTE; e4 += 4) {
-        const float a = L[gDZ + swz(e4 + g, 16 * w + c)];
+        for (int e4 = 0; e4 < kTE; e4 += 4) {
+          const float a = L[gDZ + swz(e4 + g, 16 * w + c)];
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L[gH1 + swz(e4 + g, 16 * t + c)],
+                                                          acc[t], 0, 0, 0);
+        }
 #pragma unroll
         for (int t = 0; t < 8; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L[gH1 + swz(e4 + g, 16 * t + c)],
-                                                        acc[t], 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) aW2[t][r] += (double)acc[t][r];
       }
+      // dH1 = dZ2 W2, then dz1 = dh1 silu'(z1); dW1 += dz1 phi, db1 += dz1
+      {
+        f4 dh[4];
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) aW2[t][r] += (double)acc[t][r];
-    }
-    // dH1 = dZ2 W2, then dz1 = dh1 silu'(z1); dW1 += dz1 phi, db1 += dz1
-    {
-      f4 dh[4];
-#pragma unroll
-      for (int tt = 0; tt < 4; ++tt) dh[tt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int tt = 0; tt < 4; ++tt) dh[tt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 4
-      for (int k4 = 0; k4 < kH; k4 += 4) {
-        const float a = L[gDZ + swz(16 * mt + c, k4 + g)];
+        for (int k4 = 0; k4 < kH; k4 += 4) {
+          const float a = L[gDZ + swz(16 * mt + c, k4 + g)];
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt)
-          dh[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L[gW2 + swz(k4 + g, 16 * (n0 + tt) + c)],
-                                                        dh[tt], 0, 0, 0);
-      }
-      float p0[4], p1[4], p2[4], pb[4];
+          for (int tt = 0; tt < 4; ++tt)
+            dh[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L[gW2 + swz(k4 + g, 16 * (n0 + tt) + c)],
+                                                          dh[tt], 0, 0, 0);
+        }
+        float p0[4], p1[4], p2[4], pb[4];
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) p0[tt] = p1[tt] = p2[tt] = pb[tt] = 0.0f;
+        for (int tt = 0; tt < 4; ++tt) p0[tt] = p1[tt] = p2[tt] = pb[tt] = 0.0f;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float* ph = L + gPhi + (16 * mt + 4 * g + r) * 4;
+        for (int r = 0; r < 4; ++r) {
+          const float* ph = L + gPhi + (16 * mt + 4 * g + r) * 4;
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            const int j = 16 * (n0 + tt) + c;
+            const float* w1 = L + gW1 + j * 4;
+            const float z1 = L[gB1 + j] + w1[0] * ph[0] + w1[1] * ph[1] + w1[2] * ph[2];
+            const float dz1 = dh[tt][r] * dsilu(z1);
+            p0[tt] = fmaf(dz1, ph[0], p0[tt]);
+            p1[tt] = fmaf(dz1, ph[1], p1[tt]);
+            p2[tt] = fmaf(dz1, ph[2], p2[tt]);
+            pb[tt] += dz1;
+          }
+        }
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-          const int j = 16 * (n0 + tt) + c;
-          const float* w1 = L + gW1 + j * 4;
-          const float z1 = L[gB1 + j] + w1[0] * ph[0] + w1[1] * ph[1] + w1[2] * ph[2];
-          const float dz1 = dh[tt][r] * dsilu(z1);
-          p0[tt] = fmaf(dz1, ph[0], p0[tt]);
-          p1[tt] = fmaf(dz1, ph[1], p1[tt]);
-          p2[tt] = fmaf(dz1, ph[2], p2[tt]);
-          pb[tt] += dz1;
+#pragma unroll
+          for (int off = 16; off <= 32; off <<= 1) {
+            p0[tt] += __shfl_xor(p0[tt], off);
+            p1[tt] += __shfl_xor(p1[tt], off);
+            p2[tt] += __shfl_xor(p2[tt], off);
+            pb[tt] += __shfl_xor(pb[tt], off);
+          }
+          if (g == 0) {
+            float* q = L + gP1 + (mt * kH + 16 * (n0 + tt) + c) * 4;
+            q[0] = p0[tt];
+            q[1] = p1[tt];
+            q[2] = p2[tt];
+            q[3] = pb[tt];
+          }
         }
       }
+      __syncthreads();
+      if (tid < kH) {
+        float q[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
-#pragma unroll
-        for (int off = 16; off <= 32; off <<= 1) {
-          p0[tt] += __shfl_xor(p0[tt], off);
-          p1[tt] += __shfl_xor(p1[tt], off);
-          p2[tt] += __shfl_xor(p2[tt], off);
-          pb[tt] += __shfl_xor(pb[tt], off);
+        for (int m = 0; m < 4; ++m) {
+          const float* p1 = L + gP1 + (m * kH + tid) * 4;
+          const float* p2 = L + gP2 + (m * kH + tid) * 2;
+          q[0] += p1[0];
+          q[1] += p1[1];
+          q[2] += p1[2];
+          q[3] += p1[3];
+          q[4] += p2[1];
+          q[5] += p2[0];
         }
-        if (g == 0) {
-          float* q = L + gP1 + (mt * kH + 16 * (n0 + tt) + c) * 4;
-          q[0] = p0[tt];
-          q[1] = p1[tt];
-          q[2] = p2[tt];
-          q[3] = pb[tt];
-        }
-      }
-    }
-    __syncthreads();
-    if (tid < kH) {
-      float q[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const float* p1 = L + gP1 + (m * kH + tid) * 4;
-        const float* p2 = L + gP2 + (m * kH + tid) * 2;
-        q[0] += p1[0];
-        q[1] += p1[1];
-        q[2] += p1[2];
-        q[3] += p1[3];
-        q[4] += p2[1];
-        q[5] += p2[0];
+        for (int k = 0; k < 6; ++k) Ld[dRow + k * kH + tid] += (double)q[k];
       }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) Ld[dRow + k * kH + tid] += (double)q[k];
     }
   }
   __syncthreads();
@@ -877,9 +864,10 @@ __global__ void k_absmean_final(const double* __restrict__ part, int nblk, int64
 
 inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// workgroups of the fp32 tile kernels: one per group of kGroup tiles, at most kMlpBlocks
 int mlp_grid(int64_t total) {
-  const int64_t tiles = (total + kTE - 1) / kTE;
-  return (int)std::min<int64_t>(tiles, kMlpBlocks);
+  const int64_t groups = (total + kTE * kGroup - 1) / (kTE * kGroup);
+  return (int)std::min<int64_t>(groups, kMlpBlocks);
 }
 
 }  // namespace
@@ -929,11 +917,11 @@ static hipError_t mlp_apply_t(T* R, int64_t ld, int nact, int64_t n, const doubl
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_apply<T>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdBytes);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileBytes);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k_mlp_apply<T>, dim3(mlp_grid(n * nact)), dim3(256), kFwdBytes, st, R, ld,
+  hipLaunchKernelGGL(k_mlp_apply<T>, dim3(mlp_grid(n * nact)), dim3(kGT), kTileBytes, st, R, ld,
                      nact, n, theta, diag, rho, s, w, mask, mbits, flags);
   return hipGetLastError();
 }
@@ -955,13 +943,13 @@ hipError_t mlp_grad(const double* R, const double* G, int64_t ld, int nact, int6
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_grad),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGradBytes);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileBytes);
     if (e != hipSuccess) return e;
     attr = true;
   }
   const int grid = (n > 0 && nact > 0) ? mlp_grid(n * nact) : 0;
   if (grid > 0)
-    hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(kGT), kGradBytes, st, R, G, ld, nact, n,
+    hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(kGT), kTileBytes, st, R, G, ld, nact, n,
                        theta, diag, rho, s, w, part);
   hipLaunchKernelGGL(k_grad_reduce, dim3(cdiv64(kMlpParams, 256)), dim3(256), 0, st, part, grid,
                      grad);

@@ -95,6 +95,43 @@ def test_learned_apply_matches_oracle(P):
             assert err.max() <= 1e-4, j
 
 
+def test_learned_apply_screened_tiles_match_oracle(P):
+    """fp32 net where most 64-entry tiles have no entry inside the window
+    |d - theta| <= 16 rho (d_i = i + 1, couplings 0.5, so rho <= 1): those
+    tiles take the guarded Jacobi step in the kernel's screening pass, the
+    others run the net; every column against the oracle's definition,
+    n = 3001 (ragged last tile), one theta hitting a diagonal entry."""
+    import scipy.sparse as sp
+
+    n, m = 3001, 6
+    d = np.arange(n, dtype=np.float64) + 1.0
+    off = np.full(n - 1, 0.5)
+    As = sp.diags([off, d, off], [-1, 0, 1], format="csr")
+    rho = np.asarray(abs(As).sum(1)).ravel() - np.abs(d)
+    C = synth.CSR(n=n, row_ptr=As.indptr.astype(np.int32), col=As.indices.astype(np.int32),
+                  val=As.data.astype(np.float64), diag=d)
+    theta = np.array([5.5, 100.0, 1500.25, 2990.0, 17.0, 700.0])  # 17.0 = d[16]
+    inside = (np.abs(d[:, None] - theta[None, :]) <= 16 * rho[:, None]).ravel()
+    act = [inside[t : t + 64].any() for t in range(0, inside.size, 64)]
+    assert 0 < sum(act) < len(act) // 4  # both kinds of tiles, mostly screened out
+    s_ = M.scale_of(d)
+    w32, p = f32_params(5)
+    s = solver_for(P, C, m)
+    s.set_learned_weights(w32)
+    s.set_option(P.OPT_LEARNED_BF16, 0)
+    R = synth.rng(8).standard_normal((n, m))
+    Rd = cu(R)
+    P.lobpcg_learned_apply(s.h, Rd, cu(theta), cu(np.zeros(m, dtype=np.int32)))
+    Wg = Rd.cpu().numpy()
+    for j in range(m):
+        ref, _ = M.precondition(p, R[:, j], d, theta[j], rho, s_)
+        err = np.abs(Wg[:, j] - ref) / np.abs(ref)
+        out = ~inside.reshape(n, m)[:, j]
+        say(f"col {j}: max rel err {err.max():.2e}, outside the window {err[out].max():.2e}")
+        assert err.max() <= 1e-4, j
+        assert err[out].max() <= 1e-14, j  # the Jacobi step: fp64 on both sides
+
+
 @pytest.mark.parametrize("n", [3000, 1777])
 def test_learned_apply_bf16_matches_oracle(P, n):
     # the solver's inference path: layer 2 on bf16 MFMA.  bf16 rounding of
