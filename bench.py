@@ -448,6 +448,41 @@ def kron_solve(P, synth, torch, dev, args):
     print(json.dumps(out), flush=True)
 
 
+def mlp_only(P, torch, dev, n=16384, m=16, reps=20):
+    """The learned preconditioner's fp32 MFMA kernels with every tile inside
+    the net's window: the training objective with its gradient on a dense
+    operator (diagonal 1 + 10 i / n, symmetric uniform(-0.05, 0.05)
+    couplings, so rho ~ 400 >> |d - theta|), 16 columns, n = 16384 (4096
+    tiles of 64 entries, 16 per workgroup).  Kernel durations come from a
+    kernel trace of this mode."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    B = (torch.rand((n, n), dtype=torch.float64, device=dev, generator=g) - 0.5) * 0.1
+    A = (B + B.T) * 0.5
+    del B
+    A.diagonal().copy_(1.0 + 10.0 * torch.arange(n, dtype=torch.float64, device=dev) / n)
+    d = A.diagonal()
+    rho = A.abs().sum(1) - d.abs()
+    X = torch.linalg.qr(torch.randn((n, m), dtype=torch.float64, device=dev, generator=g))[0].contiguous()
+    th = (X * (A @ X)).sum(0)
+    inside = ((d[:, None] - th[None, :]).abs() <= 16 * rho[:, None]).double().mean().item()
+    s = P.Solver(n)
+    s.set_operator_dense(A)
+    s.ensure_workspace(m)
+    L = P.lobpcg_learner_create(0, 3)
+    try:
+        snap = P.lobpcg_learner_add_snapshot(L, s.h, X, minres_maxiter=1, minres_rtol=1e-6)
+        for _ in range(reps):
+            out = P.lobpcg_learner_objective(L, snap, list(range(m)), want_grad=True)
+        torch.cuda.synchronize()
+    finally:
+        P.lobpcg_learner_destroy(L)
+    tiles = n * m // 64
+    log(f"mlp kernels: n={n} columns={m}: {tiles} tiles, entries inside the window {inside:.3f}, "
+        f"{reps} objective+gradient calls (loss {out['loss']:.6f}); per tile 6.29 MFLOP in the gradient "
+        f"(three 64x128x128 products), 2.10 MFLOP in the forward")
+
+
 def dense_only(P, synth, torch, dev, n=20_000, m=8, reps=20):
     """Times Y = A W for the dense Hessian-like operator at its full size."""
     A = synth.dense_hessian(n, seed=synth.SEEDS["dense_hessian"][0])
@@ -490,6 +525,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=600)
     ap.add_argument("--train-chunks", type=int, default=24)
     ap.add_argument("--train-lr", type=float, default=1e-3)
+    ap.add_argument("--train-lr-schedule", choices=("constant", "cosine"), default="constant",
+                    help="learning rate over the chunks (cosine: decays to ~0 by the last chunk)")
     ap.add_argument("--train-val", type=int, default=2, help="held-out matrices that choose the weights")
     ap.add_argument("--train-val-n", type=int, default=0,
                     help="size of those matrices (0: the benchmark's size)")
@@ -533,6 +570,12 @@ def main():
         "n = 1e6 banded matrix",
     )
     ap.add_argument(
+        "--mlp-kernels",
+        action="store_true",
+        help="skip the solves: the learned preconditioner's fp32 MFMA forward and gradient with every "
+        "tile inside the net's window (n = 16384, 16 columns), for a kernel trace",
+    )
+    ap.add_argument(
         "--dense",
         action="store_true",
         help="skip the solves: time the dense operator at n = 20,000 on 8 fp64 columns and print "
@@ -555,6 +598,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.kron:
         kron_only(P, synth, torch, dev)
+        return
+    if args.mlp_kernels:
+        mlp_only(P, torch, dev)
         return
     if args.dense:
         dense_only(P, synth, torch, dev)
@@ -650,7 +696,7 @@ def main():
     log(f"training matrices generated ({time.perf_counter() - t_tr:.1f} s)")
     rep = learn.train(trainers, k, steps=args.train_steps, cols_per_step=k, lr=args.train_lr, minres_maxiter=100,
                       chunks=args.train_chunks, validate=validate, supervision=args.supervision,
-                      seed=args.train_seed)
+                      seed=args.train_seed, lr_schedule=args.train_lr_schedule)
     log(f"learned preconditioner: {rep.snapshots} snapshots, loss {rep.loss_first:.3f} -> {rep.loss_last:.3f}, "
         f"collect {rep.seconds_collect:.1f} s, train {rep.seconds_train:.1f} s, validation iterations "
         f"{[c['score'] for c in rep.log]} (kept chunk {rep.best_chunk})")
@@ -818,6 +864,7 @@ def main():
                 "loss_last": rep.loss_last,
                 "supervision": args.supervision,
                 "lr": args.train_lr,
+                "lr_schedule": args.train_lr_schedule,
                 "setup_s": train_s,
                 "note": "untimed; training matrices: same generator, other seeds, smaller n with the diagonal "
                 "slope scaled; validation matrices: same generator and size, other seeds",

@@ -365,7 +365,7 @@ int lobpcg_small_eigh(lobpcg_t h, const double* a, int p, double* evals, double*
  * all retries fail. */
 int lobpcg_small_cholesky(lobpcg_t h, const double* M, int p, double* L, int* shifts);
 
-/* Block rotation with residual and preconditioner (Alg. 1 lines forming
+/* Block rotation with residual and preconditioner (the steps of Alg. 1 forming
  * X^[k+1], AX^[k+1], P^[k+1], AP^[k+1], R and W~ = T R; eq. neweigv and the
  * "Reuse of applications" paragraph, Sec. 3.1):
  *   [X' P'] = V U,  [AX' AP'] = AV U    with U = [u_x u_p] (device p x q,

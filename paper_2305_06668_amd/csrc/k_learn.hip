@@ -40,19 +40,21 @@ __global__ void k_gather_cols(const double* __restrict__ In, int64_t ldi,
   if (x.ok) Out[x.i * ldo + x.j] = In[x.i * ldi + cols[x.j]];
 }
 
-// Out = In - X C  (X: n x m, C: m x nc row-major)
-__global__ void k_project(const double* __restrict__ In, int64_t ldi, const double* __restrict__ X,
-                          int64_t ldx, int m, const double* __restrict__ C, int nc, int64_t n,
-                          double* __restrict__ Out, int64_t ldo) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  double x[kMaxBlock];
-  for (int t = 0; t < m; ++t) x[t] = X[i * ldx + t];
-  for (int j = 0; j < nc; ++j) {
-    double s = In[i * ldi + j];
-    for (int t = 0; t < m; ++t) s -= x[t] * C[t * nc + j];
-    Out[i * ldo + j] = s;
-  }
+// Out = In - X C  (X: n x m, C: m x nc row-major, staged in LDS); the
+// lanes of one row read the same X entries together
+__global__ __launch_bounds__(256) void k_project(const double* __restrict__ In, int64_t ldi,
+                                                 const double* __restrict__ X, int64_t ldx, int m,
+                                                 const double* __restrict__ C, int nc, int64_t n,
+                                                 double* __restrict__ Out, int64_t ldo) {
+  __shared__ double Cs[kMaxBlock * 64];
+  for (int q = threadIdx.x; q < m * nc; q += 256) Cs[q] = C[q];
+  __syncthreads();
+  const Elem x = elem_of(nc, n);
+  if (!x.ok) return;
+  const double* xr = X + x.i * ldx;
+  double s = In[x.i * ldi + x.j];
+  for (int t = 0; t < m; ++t) s -= xr[t] * Cs[t * nc + x.j];
+  Out[x.i * ldo + x.j] = s;
 }
 
 struct DotArgs {
@@ -295,8 +297,8 @@ hipError_t gather_cols(const double* In, int64_t ldi, const int* cols, int nc, i
 hipError_t project_block(const double* In, int64_t ldi, const double* X, int64_t ldx, int m,
                          const double* C, int nc, int64_t n, double* Out, int64_t ldo,
                          hipStream_t s) {
-  if (m > kMaxBlock) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_project, dim3(cdiv64(n, 256)), dim3(256), 0, s, In, ldi, X, ldx, m, C, nc,
+  if (m > kMaxBlock || nc <= 0 || nc > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_project, dim3(rows_grid(n, nc)), dim3(256), 0, s, In, ldi, X, ldx, m, C, nc,
                      n, Out, ldo);
   return hipGetLastError();
 }

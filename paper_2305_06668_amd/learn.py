@@ -10,6 +10,7 @@ so its value is a noisy guide to the iteration count of whole solves).
 """
 from __future__ import annotations
 
+import math
 import time
 from dataclasses import dataclass, field
 
@@ -57,6 +58,7 @@ def train(
     validate=None,
     supervision: float = 1.0,
     progress=None,
+    lr_schedule: str = "constant",
 ) -> TrainReport:
     """Train on the operators held by `solvers` (paper_2305_06668_amd.Solver
     objects with an operator, a preconditioner and an initial block of
@@ -68,7 +70,11 @@ def train(
     scored and the best are returned.  `supervision` is the weight of the
     loss term that aligns the learned step with the MINRES correction;
     `progress(i, snapshots)`, when given, is called after solver i's
-    snapshots are taken."""
+    snapshots are taken.  `lr_schedule` "cosine" runs chunk c at
+    lr (1 + cos(pi c / chunks)) / 2 (the late chunks settle instead of
+    moving at the full rate); "constant" keeps lr."""
+    if lr_schedule not in ("constant", "cosine"):
+        raise ValueError(f"lr_schedule: {lr_schedule!r}")
     L = lobpcg_learner_create(device, seed)
     lobpcg_learner_set_stream(L)
     lobpcg_learner_set_supervision(L, supervision)
@@ -92,8 +98,10 @@ def train(
         per = max(1, steps // max(1, chunks))
         best_w, best_score, best_chunk = None, float("inf"), -1
         first = last = float("nan")
-        for c in range(max(1, chunks)):
-            a, b = lobpcg_learner_train(L, per, cols_per_step, lr, seed * 1000003 + c)
+        nch = max(1, chunks)
+        for c in range(nch):
+            lr_c = lr if lr_schedule == "constant" else lr * 0.5 * (1.0 + math.cos(math.pi * c / nch))
+            a, b = lobpcg_learner_train(L, per, cols_per_step, lr_c, seed * 1000003 + c)
             if c == 0:
                 first = a
             last = b
