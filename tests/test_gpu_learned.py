@@ -227,6 +227,53 @@ def test_learner_objective_and_gradient_match_oracle(P, n):
         P.lobpcg_learner_destroy(L)
 
 
+def test_learner_gradient_screened_tiles_match_oracle(P):
+    """Loss and gradient where 139 of 141 tiles have no entry inside the
+    net's window (tridiagonal, d_i = i + 1, couplings 0.5, a block near the
+    lowest eigenvectors): the gradient kernel skips those tiles, whose dL/dy
+    is zero by definition; every layer against the oracle."""
+    import scipy.linalg as sl
+    import scipy.sparse as sp
+
+    n, m = 3001, 4
+    d = np.arange(n, dtype=np.float64) + 1.0
+    off = np.full(n - 1, 0.5)
+    As = sp.diags([off, d, off], [-1, 0, 1], format="csr")
+    rho = np.asarray(abs(As).sum(1)).ravel() - np.abs(d)
+    C = synth.CSR(n=n, row_ptr=As.indptr.astype(np.int32), col=As.indices.astype(np.int32),
+                  val=As.data.astype(np.float64), diag=d)
+    V = sl.eigh_tridiagonal(d, off, select="i", select_range=(0, m - 1))[1]
+    Xb = np.linalg.qr(V + 1e-3 * synth.rng(13).standard_normal((n, m)))[0]
+    X = Xb @ np.linalg.eigh(Xb.T @ (As @ Xb))[1]
+    s = solver_for(P, C, m)
+    L = P.lobpcg_learner_create(0, 3)
+    try:
+        w32, p = f32_params(9)
+        P.lobpcg_learner_set_weights(L, w32)
+        snap = P.lobpcg_learner_add_snapshot(L, s.h, cu(X), minres_maxiter=50, minres_rtol=1e-6)
+        info = P.lobpcg_learner_snapshot_info(L, snap, m)
+        th = np.asarray(info["theta"], dtype=np.float64)
+        R = As @ X - X * th
+        cols = [0, 1, 3]
+        inside = (np.abs(d[:, None] - th[None, cols]) <= 16 * rho[:, None]).ravel()
+        act = [inside[t : t + 64].any() for t in range(0, inside.size, 64)]
+        assert 0 < sum(act) <= 4 and len(act) == 141
+        out = P.lobpcg_learner_objective(L, snap, cols, want_grad=True)
+        Lo, go = M.objective(p, As, X, R, th, cols, d, rho, M.scale_of(d), ref=info["ref_decrease"][cols])
+        rel_l = abs(out["loss"] - Lo) / abs(Lo)
+        rel_g = np.linalg.norm(out["grad"] - go) / np.linalg.norm(go)
+        say(f"active tiles {sum(act)} of {len(act)}: loss rel {rel_l:.2e}, grad rel {rel_g:.2e}")
+        assert rel_l <= 1e-5
+        assert rel_g <= 1e-4
+        gp, op = M.Params.from_flat(out["grad"]), M.Params.from_flat(go)
+        for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            a, b = getattr(gp, name), getattr(op, name)
+            assert np.linalg.norm(b) > 0, name
+            assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), name
+    finally:
+        P.lobpcg_learner_destroy(L)
+
+
 def test_learner_supervised_objective_matches_oracle(P):
     """The loss with the supervised term mu (1 - cos^2 angle(u, (I - X X^T) t))
     and its gradient against the oracle, the corrections t solved tightly on
