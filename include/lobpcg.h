@@ -125,6 +125,19 @@ typedef struct lobpcg_ctx* lobpcg_t;
                                          cost of a net that slows a solve down
                                          without ever failing the per-column
                                          residual test */
+#define LOBPCG_OPT_STALL_WINDOW 14    /* fp64 phase: when the largest residual of
+                                         the sought active columns has not fallen
+                                         by 1 % over this many iterations, the
+                                         explicit true-residual check runs
+                                         although the recurrence has not
+                                         converged: it ends the solve if A X
+                                         meets the tolerance, else restarts from
+                                         A X.  The recurrence's residuals can
+                                         settle on a floor left by rounding in
+                                         its implicit products (Sec. 3.1, "Reuse
+                                         of applications") just above the
+                                         tolerance, which no other test would
+                                         leave.  Default 20, 0 = off */
 #define LOBPCG_OPT_FORCE_RESTARTS 9   /* test hook, default 0: the first N explicit
                                          true-residual checks of a solve count as
                                          failed, which drives the restart that a
@@ -166,6 +179,8 @@ typedef struct lobpcg_stats {
   int64_t b_matvec_columns;    /* generalized problem: columns B was applied to */
   int32_t learned_budget_iter; /* first iteration that took the Jacobi step because
                                   LOBPCG_OPT_LEARNED_BUDGET was spent, -1 if none */
+  int32_t stall_checks;        /* true-residual checks started by
+                                  LOBPCG_OPT_STALL_WINDOW */
 } lobpcg_stats;
 
 /* ---- ortho report for the step entry points ---------------------------- */

@@ -69,6 +69,16 @@ the design notes of the repository):
       t_i = max(|d_i - theta_j|, |e_{i-1}| + |e_i| + delta_j), the positive
       definite counterpart of R7 (strictly diagonally dominant), solved by
       LAPACK's Gaussian elimination with partial pivoting (dgtsv).
+  R22 Stalled recurrence: the residuals of Alg. 1's recurrence come from
+      X and A X carried through the Rayleigh-Ritz coefficients ("Reuse of
+      applications", Sec. 3.1), and rounding in those implicit products can
+      leave them on a floor above tol while the true residuals are below
+      it (or the reverse for a locked column), so that R9's check is never
+      reached.  When the largest residual of the sought active columns
+      (m_conv <= j < k) has not fallen below 0.99 times its smallest value
+      since the last check for ``stall_window`` consecutive
+      Rayleigh-Ritz steps, R9's check runs although m_conv < k: it ends the
+      solve if the true residuals meet tol, else restarts as R9 does.
   R16 Eigenvectors of the reduced matrix are oriented so that the diagonal
       entry u[j, j] is >= 0 (for the X block: the new Ritz vector continues
       the old one).  The "Basis selection" paragraph forms P from the
@@ -528,6 +538,7 @@ class LobpcgResult:
     X_all: np.ndarray = None  # the whole final block
     restarts: int = 0  # failed true-residual checks (reading R9)
     theta_all: np.ndarray = None
+    stall_checks: int = 0  # true-residual checks started by reading R22
 
 
 def lobpcg(
@@ -544,6 +555,7 @@ def lobpcg(
     shift_retries: int = SHIFT_RETRIES,
     force_restarts: int = 0,
     cheap_exit: bool = False,
+    stall_window: int = 20,
 ) -> LobpcgResult:
     """Alg. 1: the lowest k eigenpairs of the symmetric operator ``op``.
 
@@ -557,7 +569,8 @@ def lobpcg(
     is a test hook: the first that many true-residual checks count as
     failed, which drives the restart branch of reading R9.  ``cheap_exit``
     turns on reading R17's exits in the orthonormalisations of n-vectors
-    (X0, W, the re-orthonormalisation before a true check)."""
+    (X0, W, the re-orthonormalisation before a true check).
+    ``stall_window`` is reading R22's window (0 turns the rule off)."""
     X0 = np.asarray(X0, dtype=np.float64)
     n, m = X0.shape
     if not (1 <= k <= m):
@@ -602,6 +615,7 @@ def lobpcg(
     converged = False
     restarts = 0
     just_restarted = False
+    best_act, since_best, stall_checks = np.inf, 0, 0  # reading R22
     while True:
         lead = leading_converged(rnorm, tol)
         if just_restarted:
@@ -610,7 +624,18 @@ def lobpcg(
             m_conv = min(max(m_conv, lead), k - 1)
         else:
             m_conv = max(m_conv, lead)  # reading R8
-        if m_conv >= k:
+        stalled = False
+        if stall_window > 0:
+            ract = float(np.max(rnorm[m_conv:k])) if m_conv < k else 0.0
+            if ract < 0.99 * best_act:
+                best_act, since_best = ract, 0
+            else:
+                since_best += 1
+            stalled = since_best >= stall_window
+        if m_conv >= k or stalled:
+            if m_conv < k:
+                stall_checks += 1
+            best_act, since_best = np.inf, 0
             # reading R9: re-orthonormalise X (Alg. 2; the implicit-P
             # recurrence lets X^T X drift from I by rounding), then judge with
             # the true residual of an explicit product
@@ -704,6 +729,7 @@ def lobpcg(
         X_all=X,
         theta_all=th_t,
         restarts=restarts,
+        stall_checks=stall_checks,
     )
     return res
 

@@ -62,6 +62,7 @@ OPT_CHEAP_EXIT = 10
 OPT_METHOD = 11
 OPT_DAVIDSON_MAX_DIM = 12
 OPT_LEARNED_BUDGET = 13
+OPT_STALL_WINDOW = 14
 
 METHOD_LOBPCG = 0
 METHOD_DAVIDSON = 1
@@ -99,6 +100,7 @@ class lobpcg_stats(ctypes.Structure):
         ("max_basis", _i32),
         ("b_matvec_columns", _i64),
         ("learned_budget_iter", _i32),
+        ("stall_checks", _i32),
     ]
 
     def as_dict(self) -> dict:

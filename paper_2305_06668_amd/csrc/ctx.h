@@ -62,6 +62,7 @@ struct lobpcg_ctx {
   int method = LOBPCG_METHOD_LOBPCG;
   int dav_max_dim = 0;     // 0: min(25 m, kMaxP)
   int learned_budget = 200;  // iterations that use the learned step (0: no limit)
+  int stall_window = 20;     // fp64 phase: iterations without 1 % progress before a true check (0: off)
   int learned_bf16 = 1;  // learned preconditioner inference: layer 2 on bf16 MFMA
   // operator
   int op = lobpcg::kOpNone;

@@ -538,6 +538,12 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
   int m_conv = 0;
   double prev_max = INFINITY;
   int stall = 0;
+  // fp64 phase: the recurrence's residuals (A X carried as [AX AW AP] U)
+  // can settle on a floor left by its rounding rather than by convergence;
+  // without 1 % progress of the largest sought active one over
+  // stall_window iterations the explicit check runs anyway
+  double best_act = INFINITY;
+  int since_best = 0;
   std::vector<double> rnorm(m), th_rr(m), th_t, rn_t;
   out.converged = false;
   for (;;) {
@@ -616,7 +622,22 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     // iteration keeps at least the k-th column active
     if (just_restarted) newc = std::min(newc, k - 1);
     just_restarted = false;
-    if (!low && newc >= k) {
+    bool stalled = false;
+    if (!low && stall_window > 0) {
+      double ract = 0.0;
+      for (int j = m_conv; j < k; ++j) ract = std::max(ract, rnorm[j]);
+      if (ract < 0.99 * best_act) {
+        best_act = ract;
+        since_best = 0;
+      } else {
+        ++since_best;
+      }
+      stalled = since_best >= stall_window;
+    }
+    if (!low && (newc >= k || stalled)) {
+      if (stalled && newc < k) stats.stall_checks++;
+      best_act = INFINITY;
+      since_best = 0;
       // convergence is confirmed on an explicit product A X, not the
       // recurrence's residuals
       // the implicit-P recurrence lets X's orthonormality drift by rounding
@@ -1120,6 +1141,7 @@ int lobpcg_ctx::solve(int k, double tol) {
   std::memset(&stats, 0, sizeof(stats));
   stats.precision_switch_iter = -1;
   stats.learned_budget_iter = -1;
+  stats.stall_checks = 0;
   have_result = false;
   if (pkind != LOBPCG_PRECOND_NONE) {
     rc = ensure_diag();
@@ -1344,6 +1366,11 @@ int lobpcg_set_option(lobpcg_t h, int key, double v) {
       if (v < 0 || v > 1e9 || v != (int)v)
         return h->fail(LOBPCG_ERR_INVALID_ARG, "learned budget must be a non-negative integer");
       h->learned_budget = (int)v;
+      return LOBPCG_OK;
+    case LOBPCG_OPT_STALL_WINDOW:
+      if (v < 0 || v > 1e9 || v != (int)v)
+        return h->fail(LOBPCG_ERR_INVALID_ARG, "stall window must be a non-negative integer");
+      h->stall_window = (int)v;
       return LOBPCG_OK;
     case LOBPCG_OPT_FORCE_RESTARTS:
       if (v < 0 || v > 100 || v != (int)v)

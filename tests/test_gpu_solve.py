@@ -364,6 +364,42 @@ def test_forced_restart_vs_oracle(P, case):
         assert abs(res.stats["iterations"] - ora.iterations) <= max(3, 0.1 * ora.iterations)
 
 
+def test_stall_rule_reaches_the_true_check(P):
+    """Reading R22 on the GPU: with the tolerance (1e-14, ||A|| ~ 21) below
+    the floor that the recurrence's residuals reach, the window of 5
+    iterations starts true-residual checks; each either ends the solve or
+    restarts from an explicit A X.  The solve ends within max_iter either
+    way with eigenvalues at fp64 accuracy, and with the rule off it never
+    runs one (the oracle: off stalls at 5.8e-14 and runs out of
+    iterations, on converges to 6.9e-15 after one restart)."""
+    n, k, tol = 400, 4, 1e-14
+    A = synth.dense_dd(n, seed=7)
+    lam = np.linalg.eigvalsh(A)[:k]
+    X0 = synth.start_block(n, k, 8)
+    ora = O.lobpcg(O.dense_operator(A), X0, k, tol, diag=np.diag(A).copy(), max_iter=80, stall_window=5)
+    assert ora.converged and ora.stall_checks >= 1
+    out = {}
+    for window in (0, 5):
+        s = P.Solver(n)
+        s.set_operator_dense(cu(A))
+        s.set_preconditioner(P.PRECOND_DIAG)
+        s.set_option(P.OPT_MAX_ITER, 80)
+        s.set_option(P.OPT_STALL_WINDOW, window)
+        s.set_initial_guess(cu(X0))
+        res = s.solve(k, tol)
+        st = res.stats
+        say(f"window {window}: status {res.status}, {st['iterations']} iterations, stall checks "
+            f"{st['stall_checks']}, restarts {st['restarts']}, max resid {res.resnorms.max():.2e}")
+        assert np.all(np.abs(res.evals - lam) <= 1e-12 * np.abs(lam))
+        if res.status == P.OK:
+            assert res.resnorms.max() <= tol
+        out[window] = st
+    assert out[0]["stall_checks"] == 0
+    assert out[5]["stall_checks"] >= 1 and out[5]["true_checks"] >= 2
+    with pytest.raises(P.LobpcgError):
+        P.Solver(n).set_option(P.OPT_STALL_WINDOW, -1)
+
+
 def test_host_column_major_abi(P):
     """lobpcg_set_initial_guess_host / lobpcg_get_eigenpairs_host take and
     return column-major host blocks (the problem statement's layout) and

@@ -607,6 +607,49 @@ def test_forced_restart_hook_matches_a_real_one():
 
 
 # ---------------------------------------------------------------------------
+# reading R22: a stalled recurrence still reaches the true-residual check
+
+
+def _floor_solve(window, plant):
+    n, k = 400, 4
+    A = synth.dense_dd(n, seed=7)
+    e = synth.start_block(n, 1, 98)[:, 0]
+    E = 1e-7 * e / np.linalg.norm(e)
+    planted = {}
+
+    def cb(d):
+        # once the last sought column is on its way, add a fixed error to its
+        # A x: the recurrence carries it on (A X from [AX AW AP] U), so the
+        # residuals it reports for that column stay near 1e-7
+        if plant and not planted and d["rnorm"][k - 1] < 1e-4:
+            d["AX"][:, k - 1] += E
+            planted["it"] = d["it"]
+
+    res = O.lobpcg(O.dense_operator(A), synth.start_block(n, k, 8), k, 1e-9, diag=np.diag(A).copy(), callback=cb,
+                   max_iter=300, stall_window=window)
+    return A, res, planted
+
+
+def test_stalled_recurrence_reaches_the_true_check():
+    A, res0, planted = _floor_solve(0, True)
+    assert planted
+    # without the rule R9's check is never reached: the iterations run out
+    assert not res0.converged and res0.iterations == 300
+    assert res0.stall_checks == 0 and res0.true_checks == 1
+    A, res, _ = _floor_solve(20, True)
+    assert res.converged and res.stall_checks >= 1 and res.restarts >= 1
+    assert np.max(res.resnorms) <= 1e-9
+    assert_eigs(res, np.linalg.eigvalsh(A)[:4], tol=1e-9)
+    X = res.X_all
+    assert O.max_abs(X.T @ X - np.eye(4)) < 1e-12
+
+
+def test_stall_rule_silent_on_a_converging_solve():
+    A, res, _ = _floor_solve(20, False)
+    assert res.converged and res.stall_checks == 0 and res.restarts == 0 and res.true_checks == 1
+
+
+# ---------------------------------------------------------------------------
 # the exact dense eigensolve that the full-size dense goldens come from
 
 
