@@ -423,7 +423,7 @@ def kron_solve(P, synth, torch, dev, args):
 
     rep = learn.train(trainers, k + 5, steps=300, cols_per_step=k + 5, lr=1e-3, chunks=6, validate=validate,
                       supervision=args.supervision)
-    for st in trainers + vals:
+    for st in trainers + [val]:
         st.close()
     setup = time.perf_counter() - t0
     log(f"kron-solve: learned preconditioner trained in {setup:.1f} s, validation {[c['score'] for c in rep.log]}")
