@@ -126,8 +126,9 @@ typedef struct lobpcg_ctx* lobpcg_t;
                                          without ever failing the per-column
                                          residual test */
 #define LOBPCG_OPT_STALL_WINDOW 14    /* fp64 phase: when the largest residual of
-                                         the sought active columns has not fallen
-                                         by 1 % over this many iterations, the
+                                         the sought active columns is within 100
+                                         tol and has not fallen by 1 % over this
+                                         many iterations, the
                                          explicit true-residual check runs
                                          although the recurrence has not
                                          converged: it ends the solve if A X
@@ -138,6 +139,14 @@ typedef struct lobpcg_ctx* lobpcg_t;
                                          of applications") just above the
                                          tolerance, which no other test would
                                          leave.  Default 20, 0 = off */
+#define LOBPCG_OPT_SPMM_SLAB 15      /* CSR products: 0 (default) the gather
+                                         kernels; 1 the banded path (W staged in
+                                         LDS in slabs over each 2048-row block's
+                                         column window) where the columns are
+                                         sorted within rows, else the gather
+                                         kernels.  Measured slower on the
+                                         benchmark's banded matrix (1.4 ms
+                                         against 0.38 ms at 16 fp64 columns) */
 #define LOBPCG_OPT_FORCE_RESTARTS 9   /* test hook, default 0: the first N explicit
                                          true-residual checks of a solve count as
                                          failed, which drives the restart that a

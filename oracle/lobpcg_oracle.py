@@ -75,10 +75,12 @@ the design notes of the repository):
       leave them on a floor above tol while the true residuals are below
       it (or the reverse for a locked column), so that R9's check is never
       reached.  When the largest residual of the sought active columns
-      (m_conv <= j < k) has not fallen below 0.99 times its smallest value
-      since the last check for ``stall_window`` consecutive
-      Rayleigh-Ritz steps, R9's check runs although m_conv < k: it ends the
-      solve if the true residuals meet tol, else restarts as R9 does.
+      (m_conv <= j < k) is within 100 tol and has not fallen below 0.99
+      times its smallest value since the last check for ``stall_window``
+      consecutive Rayleigh-Ritz steps, R9's check runs although m_conv < k:
+      it ends the solve if the true residuals meet tol, else restarts as R9
+      does.  (A plateau far above tol is slow convergence, which a restart,
+      dropping P, would only slow down.)
   R16 Eigenvectors of the reduced matrix are oriented so that the diagonal
       entry u[j, j] is >= 0 (for the X block: the new Ritz vector continues
       the old one).  The "Basis selection" paragraph forms P from the
@@ -631,7 +633,7 @@ def lobpcg(
                 best_act, since_best = ract, 0
             else:
                 since_best += 1
-            stalled = since_best >= stall_window
+            stalled = since_best >= stall_window and ract <= 100.0 * tol
         if m_conv >= k or stalled:
             if m_conv < k:
                 stall_checks += 1

@@ -63,6 +63,7 @@ OPT_METHOD = 11
 OPT_DAVIDSON_MAX_DIM = 12
 OPT_LEARNED_BUDGET = 13
 OPT_STALL_WINDOW = 14
+OPT_SPMM_SLAB = 15
 
 METHOD_LOBPCG = 0
 METHOD_DAVIDSON = 1
@@ -724,7 +725,7 @@ class Solver:
         lobpcg_set_option(self.h, key, value)
         if key == OPT_PRECISION:
             self._prec = int(value)
-        if key in (OPT_PRECISION, OPT_METHOD, OPT_DAVIDSON_MAX_DIM) and self._block is not None:
+        if key in (OPT_PRECISION, OPT_METHOD, OPT_DAVIDSON_MAX_DIM, OPT_SPMM_SLAB) and self._block is not None:
             # the fp32 phase and the Davidson basis need other workspace sizes
             self.ensure_workspace(self._block)
 

@@ -29,6 +29,7 @@ enum OpKind { kOpNone = 0, kOpCsr = 1, kOpDense = 2, kOpKron = 3 };
 struct Layout {
   size_t V[2], AV[2], diag, rho, ltiles, part, small, total;
   size_t kpack = 0;  // dense / Kronecker operator: n x 8 packed copy of a W block
+  size_t cwin = 0;   // CSR operator: column window per block of the banded path (+ a flag)
   size_t dscr = 0;   // block Davidson: n x m scratch for the explicit product A X
   // tridiagonal preconditioner: off-diagonal, row off-sums, forward factors,
   // chunk boundary data
@@ -63,6 +64,9 @@ struct lobpcg_ctx {
   int dav_max_dim = 0;     // 0: min(25 m, kMaxP)
   int learned_budget = 200;  // iterations that use the learned step (0: no limit)
   int stall_window = 20;     // fp64 phase: iterations without 1 % progress before a true check (0: off)
+  int slab_mode = 0;         // CSR products: 0 gather kernels, 1 banded path (columns sorted)
+  bool cwin_ready = false;   // the column windows of the current CSR operator are computed
+  bool slab_ok = false;      // ... and the columns are sorted within rows
   int learned_bf16 = 1;  // learned preconditioner inference: layer 2 on bf16 MFMA
   // operator
   int op = lobpcg::kOpNone;
@@ -155,6 +159,7 @@ struct lobpcg_ctx {
   template <typename T>
   int tri_apply(T* R, int64_t ld, int nact, const double* theta);
   int ensure_op32();
+  const int2* csr_slab_windows();
   int true_residuals(const double* X, int64_t ldx, int m, double* scratch, const double* theta_rr,
                      std::vector<double>& th, std::vector<double>& rn);
   struct PhaseOut {

@@ -134,10 +134,20 @@ hipError_t convert_f32_to_f64(const float* in, int64_t ldi, double* out, int64_t
 hipError_t convert_vec_f64_to_f32(const double* in, float* out, int64_t len, hipStream_t s);
 
 // ---- operators (k_op.hip) -----------------------------------------------
+// kSlabBlockRows-row blocks of the banded CSR path (win: one int2 per block,
+// from csr_windows; nullptr selects the gather kernels)
+constexpr int kSlabBlockRows = 2048;
+constexpr int kSlabThreads = 1024;
+constexpr int kSlabUnits = kSlabBlockRows * 4 / kSlabThreads;  // rows per thread
+constexpr int kSlabLds = 128 * 1024;                            // bytes of W per slab
 hipError_t spmm_csr_f64(const int32_t* rp, const int32_t* ci, const double* val, const double* W,
-                        int64_t ldw, double* Y, int64_t ldy, int ncols, int64_t n, hipStream_t s);
+                        int64_t ldw, double* Y, int64_t ldy, int ncols, int64_t n, const int2* win,
+                        hipStream_t s);
 hipError_t spmm_csr_f32(const int32_t* rp, const int32_t* ci, const float* val, const float* W,
-                        int64_t ldw, float* Y, int64_t ldy, int ncols, int64_t n, hipStream_t s);
+                        int64_t ldw, float* Y, int64_t ldy, int ncols, int64_t n, const int2* win,
+                        hipStream_t s);
+hipError_t csr_windows(const int32_t* rp, const int32_t* ci, int64_t n, int2* win, int* unsorted,
+                       hipStream_t s);
 // pack (optional, n x 8 values): scratch for a compact copy of W when W is
 // not a compact 8-column block
 hipError_t dense_apply_f64(const double* A, int64_t lda, const double* W, int64_t ldw, double* Y,

@@ -76,6 +76,8 @@ Layout lobpcg_ctx::plan(int m, int prec) const {
   }
   L.ltiles = take((size_t)ltiles_cap() * sizeof(int));
   if (op == kOpKron || op == kOpDense) L.kpack = take((size_t)n * 8 * sizeof(double));
+  if (op == kOpCsr && slab_mode == 1)
+    L.cwin = take(((size_t)(n + kSlabBlockRows - 1) / kSlabBlockRows + 1) * 8);
   const size_t gblk = (size_t)std::min<int64_t>(kGramBlocks, (n + 63) / 64) + 1;
   const size_t part =
       std::max({gblk * kGramMaxCols * kGramMaxCols, (size_t)kStreamBlocks * 3 * 64,
@@ -132,14 +134,39 @@ int lobpcg_ctx::ensure_layout(int m) {
     tri_ready = false;
     bdiag_ready = false;
     op32_ready = false;
+    cwin_ready = false;
   }
   return LOBPCG_OK;
+}
+
+// The banded CSR path's column windows when LOBPCG_OPT_SPMM_SLAB selects
+// it, computed once per operator and workspace layout (one read-back);
+// nullptr for the gather kernels, also when some row's columns are not
+// sorted.
+const int2* lobpcg_ctx::csr_slab_windows() {
+  if (op != kOpCsr || slab_mode != 1 || ws == nullptr || lay_block <= 0 || lay.cwin == 0)
+    return nullptr;
+  int2* win = reinterpret_cast<int2*>(ws + lay.cwin);
+  const int64_t nb = (n + kSlabBlockRows - 1) / kSlabBlockRows;
+  if (!cwin_ready) {
+    int* flag = reinterpret_cast<int*>(win + nb);
+    std::vector<int2> hw(nb + 1);
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), stream);
+    if (e == hipSuccess) e = csr_windows(rp, ci, n, win, flag, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hw.data(), win, sizeof(int2) * (nb + 1), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return nullptr;
+    slab_ok = hw[nb].x == 0;  // sorted columns
+    cwin_ready = true;
+  }
+  return slab_ok ? win : nullptr;
 }
 
 int lobpcg_ctx::apply_op(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy) {
   hipError_t e = hipSuccess;
   switch (op) {
-    case kOpCsr: e = spmm_csr_f64(rp, ci, val, W, ldw, Y, ldy, nc, n, stream); break;
+    case kOpCsr: e = spmm_csr_f64(rp, ci, val, W, ldw, Y, ldy, nc, n, csr_slab_windows(), stream); break;
     case kOpDense:
       e = dense_apply_f64(A, lda, W, ldw, Y, ldy, nc, n,
                           (ws && lay_block > 0 && lay.kpack) ? dptr(lay.kpack) : nullptr, stream);
@@ -161,7 +188,7 @@ int lobpcg_ctx::apply_op(const float* W, int64_t ldw, int nc, float* Y, int64_t 
   const float* o32 = reinterpret_cast<const float*>(ws + lay.op32);
   hipError_t e = hipSuccess;
   switch (op) {
-    case kOpCsr: e = spmm_csr_f32(rp, ci, o32, W, ldw, Y, ldy, nc, n, stream); break;
+    case kOpCsr: e = spmm_csr_f32(rp, ci, o32, W, ldw, Y, ldy, nc, n, csr_slab_windows(), stream); break;
     case kOpDense:
       e = dense_apply_f32(o32, n, W, ldw, Y, ldy, nc, n,
                           lay.kpack ? reinterpret_cast<float*>(dptr(lay.kpack)) : nullptr, stream);
@@ -541,7 +568,7 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
   // fp64 phase: the recurrence's residuals (A X carried as [AX AW AP] U)
   // can settle on a floor left by its rounding rather than by convergence;
   // without 1 % progress of the largest sought active one over
-  // stall_window iterations the explicit check runs anyway
+  // stall_window iterations, within 100 tol, the explicit check runs anyway
   double best_act = INFINITY;
   int since_best = 0;
   std::vector<double> rnorm(m), th_rr(m), th_t, rn_t;
@@ -632,7 +659,9 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
       } else {
         ++since_best;
       }
-      stalled = since_best >= stall_window;
+      // only near the tolerance: a plateau far above it is slow
+      // convergence, which a restart (P dropped) would only slow down
+      stalled = since_best >= stall_window && ract <= 100.0 * tol;
     }
     if (!low && (newc >= k || stalled)) {
       if (stalled && newc < k) stats.stall_checks++;
@@ -888,7 +917,7 @@ int lobpcg_ctx::run_davidson(int k, double tol, int& iter, PhaseOut& out) {
 int lobpcg_ctx::apply_b(const double* W, int64_t ldw, int nc, double* Y, int64_t ldy) {
   hipError_t e = hipSuccess;
   switch (bop) {
-    case kOpCsr: e = spmm_csr_f64(brp, bci, bval, W, ldw, Y, ldy, nc, n, stream); break;
+    case kOpCsr: e = spmm_csr_f64(brp, bci, bval, W, ldw, Y, ldy, nc, n, nullptr, stream); break;
     case kOpDense:
       e = dense_apply_f64(Bd, ldb, W, ldw, Y, ldy, nc, n,
                           (ws && lay_block > 0 && lay.kpack) ? dptr(lay.kpack) : nullptr, stream);
@@ -1367,6 +1396,13 @@ int lobpcg_set_option(lobpcg_t h, int key, double v) {
         return h->fail(LOBPCG_ERR_INVALID_ARG, "learned budget must be a non-negative integer");
       h->learned_budget = (int)v;
       return LOBPCG_OK;
+    case LOBPCG_OPT_SPMM_SLAB:
+      if (v != 0 && v != 1)
+        return h->fail(LOBPCG_ERR_INVALID_ARG, "CSR product path must be 0 or 1");
+      h->slab_mode = (int)v;
+      h->cwin_ready = false;
+      h->lay_block = -1;  // the workspace layout holds the column windows in mode 1
+      return LOBPCG_OK;
     case LOBPCG_OPT_STALL_WINDOW:
       if (v < 0 || v > 1e9 || v != (int)v)
         return h->fail(LOBPCG_ERR_INVALID_ARG, "stall window must be a non-negative integer");
@@ -1433,6 +1469,8 @@ int lobpcg_set_operator_csr(lobpcg_t h, const int32_t* row_ptr, const int32_t* c
   h->ci = col;
   h->val = val;
   h->nnz = nnz;
+  h->cwin_ready = false;
+  if (h->slab_mode == 1) h->lay_block = -1;  // the layout holds its column windows
   h->diag_ready = false;
   h->lfeat_ready = false;
   h->tri_ready = false;

@@ -203,6 +203,57 @@ def test_apply_csr_paths(P, prec, m, ldw, q):
     s.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("m,ldw,q", [(16, 16, 0), (12, 40, 5), (3, 3, 0), (20, 24, 2)])
+def test_apply_csr_banded_path(P, prec, m, ldw, q):
+    """The opt-in banded path (LOBPCG_OPT_SPMM_SLAB = 1: W staged in LDS in
+    slabs over each 2048-row block's column window) against the definition
+    within the summation bound, on the heavy-row banded matrix: 20011 rows
+    (ten blocks, a ragged last one), rows whose columns span the whole
+    matrix (every slab), widths below 16, a 16-column slice plus a 4-column
+    one, strided W and Y.  A matrix with unsorted columns takes the gather
+    kernels under the same option, with the same result."""
+    say("csr banded path", prec, m, ldw, q)
+    n = 20011
+    S = _heavy_csr(n, 11)
+    f32 = prec == "f32"
+    dt = torch.float32 if f32 else torch.float64
+    Wb = synth.start_block(n, ldw, 3)
+    if f32:
+        Sv = S.copy()
+        Sv.data = S.data.astype(np.float32).astype(np.float64)
+        Wv = Wb.astype(np.float32).astype(np.float64)[:, q : q + m]
+        u = 2.0**-24
+    else:
+        Sv, Wv, u = S, Wb[:, q : q + m], 2.0**-53
+    ref = Sv @ Wv
+    bound = (np.diff(S.indptr)[:, None] + 2) * u * (abs(Sv) @ np.abs(Wv)) + 1e-300
+    # the same matrix with each row's columns reversed: not sorted
+    Su = S.copy()
+    for r in range(n):
+        a, z = Su.indptr[r], Su.indptr[r + 1]
+        Su.indices[a:z] = Su.indices[a:z][::-1].copy()
+        Su.data[a:z] = Su.data[a:z][::-1].copy()
+    for M in (S, Su):
+        s = P.Solver(n)
+        s.set_operator_csr(
+            cu(M.indptr.astype(np.int32)), cu(M.indices.astype(np.int32)), cu(M.data.astype(np.float64))
+        )
+        if f32:
+            s.set_option(P.OPT_PRECISION, P.PREC_FP32)
+        s.ensure_workspace(1)
+        s.set_option(P.OPT_SPMM_SLAB, 1)
+        Wd = torch.from_numpy(Wb).to(dt).cuda()
+        Y = torch.full((n, ldw + 3), 5.0, dtype=dt, device="cuda")
+        (P.lobpcg_apply_operator_f32 if f32 else P.lobpcg_apply_operator)(s.h, Wd[:, q : q + m], Y[:, q : q + m])
+        Yh = Y.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(Yh[:, q : q + m] - ref) <= bound)
+        assert np.all(Yh[:, :q] == 5.0) and np.all(Yh[:, q + m :] == 5.0)
+        s.close()
+    with pytest.raises(P.LobpcgError):
+        P.Solver(n).set_option(P.OPT_SPMM_SLAB, 2)
+
+
 def test_apply_csr_f32_needs_fp32_layout(P):
     n = 1000
     C = synth.csr_banded(n=n, seed=2, band=50)
