@@ -125,7 +125,8 @@ typedef struct lobpcg_ctx* lobpcg_t;
                                          cost of a net that slows a solve down
                                          without ever failing the per-column
                                          residual test */
-#define LOBPCG_OPT_STALL_WINDOW 14    /* fp64 phase: when the largest residual of
+#define LOBPCG_OPT_STALL_WINDOW 14    /* LOBPCG's fp64 phase, block Davidson and the
+                                         generalized driver: when the largest residual of
                                          the sought active columns is within 100
                                          tol and has not fallen by 1 % over this
                                          many iterations, the

@@ -438,6 +438,19 @@ def ritz_residual(AX: np.ndarray, X: np.ndarray, theta: np.ndarray) -> np.ndarra
     return AX - X * theta
 
 
+def _stall_step(rnorm, m_conv, k, tol, best_act, since_best, window):
+    """Reading R22's bookkeeping for one Rayleigh-Ritz step: (stalled,
+    best_act, since_best)."""
+    if window <= 0:
+        return False, best_act, since_best
+    ract = float(np.max(rnorm[m_conv:k])) if m_conv < k else 0.0
+    if ract < 0.99 * best_act:
+        best_act, since_best = ract, 0
+    else:
+        since_best += 1
+    return since_best >= window and ract <= 100.0 * tol, best_act, since_best
+
+
 def leading_converged(rnorm: np.ndarray, tol: float) -> int:
     c = 0
     for r in rnorm:
@@ -774,11 +787,13 @@ def davidson(
     tau: float = TAU_ORTHO,
     max_iter: int = 1000,
     off: Optional[np.ndarray] = None,
+    stall_window: int = 20,
 ) -> DavidsonResult:
     """Block Davidson for the lowest k eigenpairs of ``op`` (Sec. 2): the
     basis holds X^{[1]} and every preconditioned residual block since the
     last restart.  ``max_dim`` defaults to 25 m (Sec. 4's subspace of 25 per
-    root).  The preconditioners are those of ``lobpcg``."""
+    root).  The preconditioners are those of ``lobpcg``; R9's check also
+    runs on reading R22's stall rule (``stall_window``, 0 = off)."""
     X0 = np.asarray(X0, dtype=np.float64)
     n, m = X0.shape
     if not (1 <= k <= m):
@@ -799,6 +814,7 @@ def davidson(
     it = 0
     converged = False
     just_restarted = False
+    best_act, since_best = np.inf, 0  # reading R22
     check_restarts = 0
 
     def tprec(R, theta):
@@ -826,7 +842,9 @@ def davidson(
         # R9's rule after a restart: one iteration with at most k - 1 locked
         m_conv = min(max(m_conv, lead), k - 1) if just_restarted else max(m_conv, lead)
         just_restarted = False
-        if m_conv >= k:
+        stalled, best_act, since_best = _stall_step(rnorm, m_conv, k, tol, best_act, since_best, stall_window)
+        if m_conv >= k or stalled:
+            best_act, since_best = np.inf, 0
             X = ortho(X, tau, st)
             true_checks += 1
             th_t, r_t, AX_t = true_residuals(op, X)
@@ -944,10 +962,12 @@ def lobpcg_generalized(
     precond="diag",
     tau: float = TAU_ORTHO,
     max_iter: int = 1000,
+    stall_window: int = 20,
 ) -> LobpcgResult:
     """Alg. 1 for A x = lambda B x (Sec. 3.3, reading R21).  ``precond``:
     "diag" (needs dA, dB) or "none".  The returned vectors satisfy
-    X^T B X = I."""
+    X^T B X = I.  R9's check also runs on reading R22's stall rule
+    (``stall_window``, 0 = off)."""
     X0 = np.asarray(X0, dtype=np.float64)
     n, m = X0.shape
     if not (1 <= k <= m):
@@ -983,11 +1003,14 @@ def lobpcg_generalized(
     converged = False
     restarts = 0
     just_restarted = False
+    best_act, since_best = np.inf, 0  # reading R22
     while True:
         lead = leading_converged(rnorm, tol)
         m_conv = min(max(m_conv, lead), k - 1) if just_restarted else max(m_conv, lead)
         just_restarted = False
-        if m_conv >= k:
+        stalled, best_act, since_best = _stall_step(rnorm, m_conv, k, tol, best_act, since_best, stall_window)
+        if m_conv >= k or stalled:
+            best_act, since_best = np.inf, 0
             # R9 for the generalized problem: B-orthonormalise X once more
             # (explicit B X), then judge with explicit products
             BXt = opB(X)

@@ -514,6 +514,26 @@ static int leading_converged(const std::vector<double>& r, double tol) {
   return c;
 }
 
+// Reading R22's bookkeeping for one Rayleigh-Ritz step: true when R9's
+// check is to run although the recurrence has not converged (the largest
+// residual of the sought active columns, within 100 tol, has not fallen by
+// 1 % over `window` steps)
+static bool stall_step(const std::vector<double>& rnorm, int m_conv, int k, double tol,
+                       int window, double& best, int& since) {
+  if (window <= 0) return false;
+  double ract = 0.0;
+  for (int j = m_conv; j < k; ++j) ract = std::max(ract, rnorm[j]);
+  if (ract < 0.99 * best) {
+    best = ract;
+    since = 0;
+  } else {
+    ++since;
+  }
+  // only near the tolerance: a plateau far above it is slow convergence,
+  // which a restart (P dropped) would only slow down
+  return since >= window && ract <= 100.0 * tol;
+}
+
 // One precision phase of Alg. 1, starting from the block X stored in V0
 // (leading dimension m, not yet orthonormal).  `low` selects the fp32 phase
 // (reading of the mixed-precision extension): no locking, ortho threshold
@@ -649,20 +669,8 @@ int lobpcg_ctx::run_phase(T* V0, T* V1, T* AV0, T* AV1, int k, double tol, bool 
     // iteration keeps at least the k-th column active
     if (just_restarted) newc = std::min(newc, k - 1);
     just_restarted = false;
-    bool stalled = false;
-    if (!low && stall_window > 0) {
-      double ract = 0.0;
-      for (int j = m_conv; j < k; ++j) ract = std::max(ract, rnorm[j]);
-      if (ract < 0.99 * best_act) {
-        best_act = ract;
-        since_best = 0;
-      } else {
-        ++since_best;
-      }
-      // only near the tolerance: a plateau far above it is slow
-      // convergence, which a restart (P dropped) would only slow down
-      stalled = since_best >= stall_window && ract <= 100.0 * tol;
-    }
+    const bool stalled =
+        !low && stall_step(rnorm, m_conv, k, tol, stall_window, best_act, since_best);
     if (!low && (newc >= k || stalled)) {
       if (stalled && newc < k) stats.stall_checks++;
       best_act = INFINITY;
@@ -803,6 +811,8 @@ int lobpcg_ctx::run_davidson(int k, double tol, int& iter, PhaseOut& out) {
   int p = m;  // basis columns
   int m_conv = 0;
   bool just_restarted = false;
+  double best_act = INFINITY;  // reading R22
+  int since_best = 0;
   stats.max_basis = p;
   std::vector<double> rnorm(m), th_t, rn_t;
   out.converged = false;
@@ -842,7 +852,11 @@ int lobpcg_ctx::run_davidson(int k, double tol, int& iter, PhaseOut& out) {
     int newc = std::max(m_conv, leading_converged(rnorm, tol));
     if (just_restarted) newc = std::min(newc, k - 1);
     just_restarted = false;
-    if (newc >= k) {
+    const bool stalled = stall_step(rnorm, m_conv, k, tol, stall_window, best_act, since_best);
+    if (newc >= k || stalled) {
+      if (stalled && newc < k) stats.stall_checks++;
+      best_act = INFINITY;
+      since_best = 0;
       rc = ortho_run<double>(V1, ldo, 0, m, nullptr, false, tau);
       if (rc) return rc;
       rc = true_residuals(V1, ldo, m, scr, theta, th_t, rn_t);
@@ -1001,6 +1015,8 @@ int lobpcg_ctx::run_generalized(int k, double tol, int& iter, PhaseOut& out) {
 
   int c = 0, L = m, m_conv = 0;
   bool first = true, just_restarted = false;
+  double best_act = INFINITY;  // reading R22
+  int since_best = 0;
   std::vector<double> rnorm(m);
   std::vector<double> th_t(m), rn_t(m);
   out.converged = false;
@@ -1079,7 +1095,11 @@ int lobpcg_ctx::run_generalized(int k, double tol, int& iter, PhaseOut& out) {
     int newc = std::max(m_conv, leading_converged(rnorm, tol));
     if (just_restarted) newc = std::min(newc, k - 1);
     just_restarted = false;
-    if (newc >= k) {
+    const bool stalled = stall_step(rnorm, m_conv, k, tol, stall_window, best_act, since_best);
+    if (newc >= k || stalled) {
+      if (stalled && newc < k) stats.stall_checks++;
+      best_act = INFINITY;
+      since_best = 0;
       rc = true_check(V[1 - c], ldo);
       if (rc) return rc;
       double worst = 0.0;
