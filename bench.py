@@ -309,14 +309,22 @@ def family_bench(P, synth, torch, dev, args):
         if (i + 1) % 16 == 0:
             log(f"family: snapshots of {i + 1} matrices taken ({nsnap}, {time.perf_counter() - t0:.0f} s)")
 
-    rep = learn.train(trainers, k, snapshot_iters=snap_iters, steps=args.family_steps, cols_per_step=k, lr=1e-3,
-                      chunks=args.family_chunks, validate=validate, supervision=args.supervision,
-                      progress=progress)
-    for st in trainers + vals:
-        st.close()
+    rep = learn.train(trainers, k, snapshot_iters=snap_iters, steps=args.family_steps, cols_per_step=k,
+                      lr=args.family_lr, chunks=args.family_chunks, validate=validate,
+                      supervision=args.supervision, progress=progress)
     setup = time.perf_counter() - t0
     log(f"family: trained on {args.family_train} matrices in {setup:.1f} s, validation "
         f"{[c['score'] for c in rep.log]} (kept {rep.best_chunk})")
+    if args.family_no_eval:
+        print(json.dumps({"mode": "preconditioner study, training only", "lr": args.family_lr,
+                          "supervision": args.supervision, "validation_indices": val_idx,
+                          "validation_iterations": [c["score"] for c in rep.log],
+                          "untrained_validation": validate(initial_learned_weights(P)),
+                          "kept_chunk": rep.best_chunk}), flush=True)
+    for st in trainers + vals:
+        st.close()
+    if args.family_no_eval:
+        return
     variants = {
         "jacobi": dict(prec=P.PREC_FP64, pc=P.PRECOND_DIAG, method=P.METHOD_LOBPCG),
         "tridiag": dict(prec=P.PREC_FP64, pc=P.PRECOND_TRIDIAG, method=P.METHOD_LOBPCG),
@@ -376,7 +384,7 @@ def family_bench(P, synth, torch, dev, args):
                              "validation_rho": [float(rhos[i]) for i in val_idx],
                              "validation_iterations": [c["score"] for c in rep.log], "kept_chunk": rep.best_chunk,
                              "loss_first": rep.loss_first, "loss_last": rep.loss_last,
-                             "supervision": args.supervision},
+                             "supervision": args.supervision, "lr": args.family_lr},
         "variants": {v: summary(r) for v, r in rows.items()},
         "per_matrix": rows,
     }
@@ -579,6 +587,9 @@ def main():
     ap.add_argument("--family-held-out", type=int, default=16)
     ap.add_argument("--family-steps", type=int, default=600)
     ap.add_argument("--family-chunks", type=int, default=6)
+    ap.add_argument("--family-lr", type=float, default=1e-3)
+    ap.add_argument("--family-no-eval", action="store_true",
+                    help="stop after training and print the validation iterations per chunk")
     ap.add_argument("--family-full", action="store_true",
                     help="the whole configuration: train on all 192 training indices (two snapshots each), "
                     "solve all 64 held-out ones")
