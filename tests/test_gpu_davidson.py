@@ -136,3 +136,32 @@ def test_davidson_full_size_csr(P):
     say("davidson n=1e6:", st["iterations"], "iterations", st["history_restarts"], "truncations",
         f"{st['ms_total']:.1f} ms", st["matvec_columns"], "matvec columns")
     check(res, lambda X: A @ X, np.asarray(gold["evals"]), 1e-8, normA=11.2)
+
+
+def test_davidson_stall_rule(P):
+    """Reading R22 in the block Davidson driver: at a tolerance below what
+    fp64 residuals reach (1e-15 with ||A|| ~ 21; the GPU's got to 2.8e-15,
+    the oracle's to 2.6e-15) the solve plateaus, and with a window of 5 the
+    true-residual check runs on the stall (the oracle: 9 restarts in 80
+    iterations, none without the rule); every solve ends at max_iter with
+    fp64-accurate eigenvalues."""
+    n, k, tol = 400, 4, 1e-15
+    A = synth.dense_dd(n, seed=7)
+    lam = np.linalg.eigvalsh(A)[:k]
+    X0 = synth.start_block(n, k, 8)
+    stalls = {}
+    for window in (0, 5):
+        s = P.Solver(n)
+        s.set_operator_dense(cu(A))
+        s.set_preconditioner(P.PRECOND_DIAG)
+        s.set_option(P.OPT_METHOD, P.METHOD_DAVIDSON)
+        s.set_option(P.OPT_MAX_ITER, 80)
+        s.set_option(P.OPT_STALL_WINDOW, window)
+        s.set_initial_guess(cu(X0))
+        res = s.solve(k, tol)
+        st = res.stats
+        say(f"davidson window {window}: status {res.status}, {st['iterations']} iterations, "
+            f"stall checks {st['stall_checks']}, restarts {st['restarts']}, max resid {res.resnorms.max():.2e}")
+        assert np.all(np.abs(res.evals - lam) <= 1e-12 * np.abs(lam))
+        stalls[window] = st["stall_checks"]
+    assert stalls[0] == 0 and stalls[5] >= 1

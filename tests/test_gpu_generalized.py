@@ -143,3 +143,36 @@ def test_generalized_unsupported_modes(P):
             s.solve(3, 1e-8)
         assert e.value.status == P.ERR_UNSUPPORTED
         s.set_option(key, 0)
+
+
+def test_generalized_stall_rule(P):
+    """Reading R22 in the generalized driver: below what fp64 residuals
+    reach (tol 1e-15) the window of 5 starts true-residual checks on the
+    plateau (the oracle: 5 restarts in 80 iterations, none without the
+    rule); eigenvalues against eigh(A, B)."""
+    n, k, tol = 400, 4, 1e-15
+    A = synth.dense_dd(n, seed=5)
+    g = synth.rng(6)
+    B = np.diag(g.uniform(1.0, 2.0, n))
+    off = 0.1 * np.minimum(np.diag(B)[:-1], np.diag(B)[1:])
+    B = B + np.diag(off, 1) + np.diag(off, -1)
+    lam = sla.eigh(A, B, eigvals_only=True, subset_by_index=[0, k - 1])
+    X0 = synth.start_block(n, k, 8)
+    stalls = {}
+    for window in (0, 5):
+        s = P.Solver(n)
+        s.set_operator_dense(cu(A))
+        s.set_operator_b_dense(cu(B))
+        s.set_preconditioner(P.PRECOND_DIAG)
+        s.set_option(P.OPT_MAX_ITER, 80)
+        s.set_option(P.OPT_STALL_WINDOW, window)
+        s.set_initial_guess(cu(X0))
+        res = s.solve(k, tol)
+        st = res.stats
+        say(f"generalized window {window}: status {res.status}, {st['iterations']} iterations, "
+            f"stall checks {st['stall_checks']}, restarts {st['restarts']}, max resid {res.resnorms.max():.2e}")
+        assert np.all(np.abs(res.evals - lam) <= 1e-12 * np.abs(lam))
+        if res.status == P.OK:
+            assert res.resnorms.max() <= tol
+        stalls[window] = st["stall_checks"]
+    assert stalls[0] == 0 and stalls[5] >= 1
