@@ -34,6 +34,93 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Cholesky of an n x n symmetric matrix (n <= 16) held by one wave in
+// registers: lane l keeps column c = l & 15, rows r = (l >> 4) + 4 t
+// (t = 0..3), in g[t]; only r >= c is read, and rows or columns from n to 15
+// are those of the identity.  Right-looking, column by column: the pivot is
+// read from its lane, column k of L is formed in its four lanes and handed
+// to the others by lane shuffles, then the trailing entries are updated.
+// Every entry takes the same operations in the same order as the LDS
+// factorizations: G[r][k] / l_kk (KDIV) or G[r][k] * (1 / l_kk), and
+// G[r][c] - L[r][k] L[c][k] as one fused multiply-add.  On return g holds L
+// (diagonal included).  False, uniform over the wave, when a pivot is not
+// > 0 (or, with CHECKINF, not finite); linv (LDS, may be null) receives
+// 1 / l_kk when !KDIV.
+template <bool KDIV, bool CHECKINF>
+__device__ __forceinline__ bool reg_chol16(double (&g)[4], int n, double* linv) {
+  const int l = threadIdx.x & 63, c = l & 15, rb = l >> 4;
+  for (int k = 0; k < n; ++k) {
+    // register k >> 2 of lane k + 16 (k & 3) (a select: no indexed registers)
+    const int tk = k >> 2;
+    const double gk = (tk == 0) ? g[0] : (tk == 1) ? g[1] : (tk == 2) ? g[2] : g[3];
+    const double gkk = readlane_f64(gk, k + 16 * (k & 3));
+    if (!(gkk > 0.0)) return false;
+    if (CHECKINF && !(gkk < INFINITY)) return false;
+    const double lkk = sqrt(gkk);
+    const double inv = KDIV ? 0.0 : 1.0 / lkk;
+    if (c == k) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = rb + 4 * t;
+        if (r > k) g[t] = KDIV ? g[t] / lkk : g[t] * inv;
+        else if (r == k) g[t] = lkk;
+      }
+    }
+    if (!KDIV && linv != nullptr && l == 0) linv[k] = inv;
+    // lr[t] = L[rb + 4t][k] (lane k + 16 rb, register t); lc[t] from lane
+    // k + 16 (c & 3): L[c][k] is its register c >> 2
+    double lr[4], lc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      lr[t] = __shfl(g[t], k + 16 * rb);
+      lc[t] = __shfl(g[t], k + 16 * (c & 3));
+    }
+    const int tc = c >> 2;
+    const double lck = (tc == 0) ? lc[0] : (tc == 1) ? lc[1] : (tc == 2) ? lc[2] : lc[3];
+    if (c > k) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (rb + 4 * t >= c) g[t] = fma(-lr[t], lck, g[t]);
+    }
+  }
+  return true;
+}
+
+// One wave (all 64 lanes): L = chol(S + shift I) for the n x n (n <= 16)
+// matrix S in LDS (lower triangle read), written to L in LDS (lower
+// triangle; the strict upper one zeroed when ZUP).  Out of line, so that the
+// large single-workgroup kernels keep their own register budgets.  Returns
+// false (uniform) on a pivot that is not > 0 (or, CHECKINF, not finite).
+template <bool KDIV, bool CHECKINF, bool ZUP>
+__device__ __noinline__ bool wave_chol16_lds(const double* S, int lds_, int n, double shift, double* L,
+                                             int ldl, double* linv) {
+  const int l = threadIdx.x & 63, c = l & 15, rb = l >> 4;
+  double g[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int r = rb + 4 * t;
+    g[t] = (r < n && c < n) ? ((r >= c) ? S[r * lds_ + c] + (r == c ? shift : 0.0) : 0.0)
+                            : (r == c ? 1.0 : 0.0);
+  }
+  const bool ok = reg_chol16<KDIV, CHECKINF>(g, n, linv);
+  if (ok || ZUP) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int r = rb + 4 * t;
+      if (r < n && c < n) {
+        if (r >= c) L[r * ldl + c] = g[t];
+        else if (ZUP) L[r * ldl + c] = 0.0;
+      }
+    }
+  }
+  return ok;
+}
+
 // ---------------------------------------------------------------------------
 // block-wide helpers (every thread of the block calls them)
 
@@ -115,13 +202,19 @@ __device__ __forceinline__ void blk_normalize(double* X, int ldx, int n, int q, 
 // Cholesky L L^T = M + shift I (lower, n x n); returns true on success.
 // Breaks down when a pivot is not > 0 (NaN included), like LAPACK potrf.
 // Every thread calls it and M must be complete on entry.  Wave 0 alone
-// factors, column by column with wave-level syncs, while the other waves
-// wait at the closing barriers: two workgroup barriers per factorization
-// instead of three per column.  Each entry takes the same operations in the
-// same order as a column-parallel factorization by the whole workgroup.
+// factors (REG and n <= 16: in registers by an out-of-line call, which pays
+// off in the Rayleigh-Ritz kernel but not in the short controller kernels;
+// otherwise column by column in LDS with wave-level syncs) while the other
+// waves wait at the closing barriers: two workgroup barriers per
+// factorization.  Each entry takes the same operations in the same order as
+// a column-parallel factorization by the whole workgroup.
+template <bool REG = true>
 __device__ __forceinline__ bool blk_chol(const double* M, int ldm, int n, double shift, double* L, int ldl,
                          int* flag) {
-  if (threadIdx.x < 64) {
+  if (REG && threadIdx.x < 64 && n <= 16) {
+    const bool ok = wave_chol16_lds<true, false, true>(M, ldm, n, shift, L, ldl, nullptr);
+    if (threadIdx.x == 0) *flag = ok ? 0 : 1;
+  } else if (threadIdx.x < 64) {
     const int l = threadIdx.x;
     for (int idx = l; idx < n * n; idx += 64) {
       const int i = idx / n, j = idx - i * n;
@@ -160,10 +253,11 @@ struct ShiftCount {
 
 // Sec. 3.2 / Alg. 2: plain Cholesky, then shifts alpha*eps*||X||_F with
 // ||X||_F = sqrt(trace M), alpha = 100, x10 per retry.
+template <bool REG = true>
 __device__ __forceinline__ bool blk_shifted_chol(const double* M, int ldm, int n, double* L, int ldl, int* flag,
                                  ShiftCount* c, double* scratch, int retries = kShiftRetries) {
   if (threadIdx.x == 0) c->factorizations++;
-  if (blk_chol(M, ldm, n, 0.0, L, ldl, flag)) return true;
+  if (blk_chol<REG>(M, ldm, n, 0.0, L, ldl, flag)) return true;
   if (threadIdx.x == 0) c->failed++;
   double tr = 0.0;
   for (int i = 0; i < n; ++i) tr += M[i * ldm + i];
@@ -171,7 +265,7 @@ __device__ __forceinline__ bool blk_shifted_chol(const double* M, int ldm, int n
   double alpha = kShiftAlpha0;
   for (int t = 0; t < retries; ++t) {
     if (threadIdx.x == 0) c->factorizations++;
-    if (blk_chol(M, ldm, n, alpha * kEps * normx, L, ldl, flag)) {
+    if (blk_chol<REG>(M, ldm, n, alpha * kEps * normx, L, ldl, flag)) {
       if (threadIdx.x == 0) c->shifted++;
       return true;
     }
@@ -476,10 +570,6 @@ __device__ __forceinline__ double dpp_f64(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
 // Sum over the 64 lanes (all active), the same bits in every lane: within
 // each row of 16 by DPP (swap neighbours, swap pairs, mirror 8, mirror 16;
 // each step adds the same two operands on both partners), then the four row
@@ -782,12 +872,17 @@ __device__ void blk_gram_lower(const double* Z, int ldz, int p, int n, double* G
 }
 
 // Z <- Z L^-T with L L^T = G (the Gram Z^T Z from blk_gram_lower), by one
-// wave; G is overwritten by L.  False when a pivot is not > 0.
+// wave; G is overwritten by L (n <= 16: factored in registers by
+// reg_chol16).  False when a pivot is not > 0.
 template <int NR>
 __device__ bool wave_cholqr(double* Z, int ldz, int p, int n, double* G, int ldg, double* linv) {
   const int l = threadIdx.x & 63;
   wave_sync();
-  for (int k = 0; k < n; ++k) {
+  if (n <= 16) {
+    if (!wave_chol16_lds<false, true, false>(G, ldg, n, 0.0, G, ldg, linv)) return false;
+    wave_sync();
+  }
+  for (int k = 0; k < n && n > 16; ++k) {
     const double gkk = G[k * ldg + k];
     if (!(gkk > 0.0) || !(gkk < INFINITY)) return false;
     const double lkk = sqrt(gkk), inv = 1.0 / lkk;
@@ -1253,7 +1348,7 @@ __global__ __launch_bounds__(256) void k_small_chol(const double* __restrict__ M
     Ms[i * 65 + j] = 0.5 * (M[i * p + j] + M[j * p + i]);
   }
   __syncthreads();
-  const bool ok = blk_shifted_chol(Ms, 65, p, Ls, 65, &flag, &cnt, scratch);
+  const bool ok = blk_shifted_chol<false>(Ms, 65, p, Ls, 65, &flag, &cnt, scratch);
   for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
     const int i = idx / p, j = idx - i * p;
     Lout[idx] = ok ? Ls[i * 65 + j] : 0.0;
@@ -1450,7 +1545,7 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
     have_scale = (phase == kPhBegin);
   } else {
     // shifted Cholesky of M (= M' in BEGIN)
-    const bool ok = blk_shifted_chol(Ms, ldm, nw, Ls, ldm, &flag, &cnt, scratch, st.shift_retries);
+    const bool ok = blk_shifted_chol<false>(Ms, ldm, nw, Ls, ldm, &flag, &cnt, scratch, st.shift_retries);
     if (ok) {
       blk_tri_inv(Ls, ldm, nw, Li, ldm);
       // coef W part: D L^-T, i.e. coef[ny+i][j] = D_i Linv[j][i]
