@@ -93,12 +93,13 @@ __device__ __forceinline__ bool reg_chol16(double (&g)[4], int n, double* linv) 
 
 // One wave (all 64 lanes): L = chol(S + shift I) for the n x n (n <= 16)
 // matrix S in LDS (lower triangle read), written to L in LDS (lower
-// triangle; the strict upper one zeroed when ZUP).  Out of line, so that the
-// large single-workgroup kernels keep their own register budgets.  Returns
+// triangle; the strict upper one zeroed when ZUP).  wave_chol16_lds is the
+// out-of-line form, so that the large single-workgroup kernels keep their
+// own register budgets.  Returns
 // false (uniform) on a pivot that is not > 0 (or, CHECKINF, not finite).
 template <bool KDIV, bool CHECKINF, bool ZUP>
-__device__ __noinline__ bool wave_chol16_lds(const double* S, int lds_, int n, double shift, double* L,
-                                             int ldl, double* linv) {
+__device__ __forceinline__ bool wave_chol16_body(const double* S, int lds_, int n, double shift,
+                                                 double* L, int ldl, double* linv) {
   const int l = threadIdx.x & 63, c = l & 15, rb = l >> 4;
   double g[4];
 #pragma unroll
@@ -119,6 +120,11 @@ __device__ __noinline__ bool wave_chol16_lds(const double* S, int lds_, int n, d
     }
   }
   return ok;
+}
+template <bool KDIV, bool CHECKINF, bool ZUP>
+__device__ __noinline__ bool wave_chol16_lds(const double* S, int lds_, int n, double shift, double* L,
+                                             int ldl, double* linv) {
+  return wave_chol16_body<KDIV, CHECKINF, ZUP>(S, lds_, n, shift, L, ldl, linv);
 }
 
 // ---------------------------------------------------------------------------
@@ -202,17 +208,20 @@ __device__ __forceinline__ void blk_normalize(double* X, int ldx, int n, int q, 
 // Cholesky L L^T = M + shift I (lower, n x n); returns true on success.
 // Breaks down when a pivot is not > 0 (NaN included), like LAPACK potrf.
 // Every thread calls it and M must be complete on entry.  Wave 0 alone
-// factors (REG and n <= 16: in registers by an out-of-line call, which pays
-// off in the Rayleigh-Ritz kernel but not in the short controller kernels;
-// otherwise column by column in LDS with wave-level syncs) while the other
+// factors (REG != 0 and n <= 16: in registers, by an out-of-line call in
+// the Rayleigh-Ritz kernel, whose register budget is full, inline in the
+// ortho controller; otherwise column by column in LDS with wave-level
+// syncs) while the other
 // waves wait at the closing barriers: two workgroup barriers per
 // factorization.  Each entry takes the same operations in the same order as
 // a column-parallel factorization by the whole workgroup.
-template <bool REG = true>
+// REG: 0 column by column in LDS, 1 registers (out of line), 2 registers (inline)
+template <int REG = 1>
 __device__ __forceinline__ bool blk_chol(const double* M, int ldm, int n, double shift, double* L, int ldl,
                          int* flag) {
-  if (REG && threadIdx.x < 64 && n <= 16) {
-    const bool ok = wave_chol16_lds<true, false, true>(M, ldm, n, shift, L, ldl, nullptr);
+  if (REG != 0 && threadIdx.x < 64 && n <= 16) {
+    const bool ok = (REG == 1) ? wave_chol16_lds<true, false, true>(M, ldm, n, shift, L, ldl, nullptr)
+                               : wave_chol16_body<true, false, true>(M, ldm, n, shift, L, ldl, nullptr);
     if (threadIdx.x == 0) *flag = ok ? 0 : 1;
   } else if (threadIdx.x < 64) {
     const int l = threadIdx.x;
@@ -253,7 +262,7 @@ struct ShiftCount {
 
 // Sec. 3.2 / Alg. 2: plain Cholesky, then shifts alpha*eps*||X||_F with
 // ||X||_F = sqrt(trace M), alpha = 100, x10 per retry.
-template <bool REG = true>
+template <int REG = 1>
 __device__ __forceinline__ bool blk_shifted_chol(const double* M, int ldm, int n, double* L, int ldl, int* flag,
                                  ShiftCount* c, double* scratch, int retries = kShiftRetries) {
   if (threadIdx.x == 0) c->factorizations++;
@@ -1348,7 +1357,7 @@ __global__ __launch_bounds__(256) void k_small_chol(const double* __restrict__ M
     Ms[i * 65 + j] = 0.5 * (M[i * p + j] + M[j * p + i]);
   }
   __syncthreads();
-  const bool ok = blk_shifted_chol<false>(Ms, 65, p, Ls, 65, &flag, &cnt, scratch);
+  const bool ok = blk_shifted_chol<0>(Ms, 65, p, Ls, 65, &flag, &cnt, scratch);
   for (int idx = threadIdx.x; idx < p * p; idx += blockDim.x) {
     const int i = idx / p, j = idx - i * p;
     Lout[idx] = ok ? Ls[i * 65 + j] : 0.0;
@@ -1545,7 +1554,7 @@ __global__ __launch_bounds__(1024) void k_ortho_ctl(const double* __restrict__ G
     have_scale = (phase == kPhBegin);
   } else {
     // shifted Cholesky of M (= M' in BEGIN)
-    const bool ok = blk_shifted_chol<false>(Ms, ldm, nw, Ls, ldm, &flag, &cnt, scratch, st.shift_retries);
+    const bool ok = blk_shifted_chol<2>(Ms, ldm, nw, Ls, ldm, &flag, &cnt, scratch, st.shift_retries);
     if (ok) {
       blk_tri_inv(Ls, ldm, nw, Li, ldm);
       // coef W part: D L^-T, i.e. coef[ny+i][j] = D_i Linv[j][i]
