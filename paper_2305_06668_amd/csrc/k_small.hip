@@ -890,42 +890,43 @@ __device__ bool wave_cholqr(double* Z, int ldz, int p, int n, double* G, int ldg
   if (n <= 16) {
     if (!wave_chol16_lds<false, true, false>(G, ldg, n, 0.0, G, ldg, linv)) return false;
     wave_sync();
-  }
-  for (int k = 0; k < n && n > 16; ++k) {
-    const double gkk = G[k * ldg + k];
-    if (!(gkk > 0.0) || !(gkk < INFINITY)) return false;
-    const double lkk = sqrt(gkk), inv = 1.0 / lkk;
+  } else {
+    for (int k = 0; k < n; ++k) {
+      const double gkk = G[k * ldg + k];
+      if (!(gkk > 0.0) || !(gkk < INFINITY)) return false;
+      const double lkk = sqrt(gkk), inv = 1.0 / lkk;
 #pragma unroll
-    for (int h = 0; h < NR; ++h) {
-      const int r = l + 64 * h;
-      if (r > k && r < n) G[r * ldg + k] *= inv;
-    }
-    if (l == 0) {
-      G[k * ldg + k] = lkk;
-      linv[k] = inv;
-    }
-    wave_sync();
-    // trailing update, lane c owning column c: G[r][c] -= L[r][k] L[c][k], r >= c > k
+      for (int h = 0; h < NR; ++h) {
+        const int r = l + 64 * h;
+        if (r > k && r < n) G[r * ldg + k] *= inv;
+      }
+      if (l == 0) {
+        G[k * ldg + k] = lkk;
+        linv[k] = inv;
+      }
+      wave_sync();
+      // trailing update, lane c owning column c: G[r][c] -= L[r][k] L[c][k], r >= c > k
 #pragma unroll
-    for (int h = 0; h < NR; ++h) {
-      const int c = l + 64 * h;
-      if (c > k && c < n) {
-        const double lck = G[c * ldg + k];
-        for (int r0 = c; r0 < n; r0 += 4) {
-          double lk[4], gc[4];
+      for (int h = 0; h < NR; ++h) {
+        const int c = l + 64 * h;
+        if (c > k && c < n) {
+          const double lck = G[c * ldg + k];
+          for (int r0 = c; r0 < n; r0 += 4) {
+            double lk[4], gc[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int r = min(r0 + u, n - 1);
-            lk[u] = G[r * ldg + k];
-            gc[u] = G[r * ldg + c];
+            for (int u = 0; u < 4; ++u) {
+              const int r = min(r0 + u, n - 1);
+              lk[u] = G[r * ldg + k];
+              gc[u] = G[r * ldg + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (r0 + u < n) G[(r0 + u) * ldg + c] = gc[u] - lk[u] * lck;
           }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (r0 + u < n) G[(r0 + u) * ldg + c] = gc[u] - lk[u] * lck;
         }
       }
+      wave_sync();
     }
-    wave_sync();
   }
 #pragma unroll
   for (int h = 0; h < NR; ++h) {
