@@ -95,8 +95,8 @@ __device__ __forceinline__ bool reg_chol16(double (&g)[4], int n, double* linv) 
 // matrix S in LDS (lower triangle read), written to L in LDS (lower
 // triangle; the strict upper one zeroed when ZUP).  wave_chol16_lds is the
 // out-of-line form, so that the large single-workgroup kernels keep their
-// own register budgets.  Returns
-// false (uniform) on a pivot that is not > 0 (or, CHECKINF, not finite).
+// own register budgets.  Returns false (uniform) on a pivot that is not > 0
+// (or, CHECKINF, not finite).
 template <bool KDIV, bool CHECKINF, bool ZUP>
 __device__ __forceinline__ bool wave_chol16_body(const double* S, int lds_, int n, double shift,
                                                  double* L, int ldl, double* linv) {
