@@ -55,3 +55,42 @@ def test_status_strings_and_null_handle():
     lib.lobpcg_create.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
     h = ctypes.c_void_p()
     assert lib.lobpcg_create(0, 0, ctypes.byref(h)) == P.ERR_INVALID_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_constants_equal_header_defines():
+    """Every integer #define LOBPCG_X of the header is the binding's X."""
+    import paper_2305_06668_amd as P
+
+    defs = {m.group(1): int(m.group(2))
+            for m in re.finditer(r"#define LOBPCG_([A-Z0-9_]+)\s+(-?\d+)\b", open(HEADER).read())}
+    assert len(defs) >= 30
+    for name, value in defs.items():
+        assert getattr(P, name) == value, name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+@pytest.mark.parametrize("struct", ["lobpcg_stats", "lobpcg_ortho_info"])
+def test_struct_layouts_match_the_c_compiler(tmp_path, struct):
+    """Field offsets and sizes of the ctypes mirrors equal what a C compiler
+    lays out from the header (a reordered or resized field would otherwise
+    shift every later statistic silently)."""
+    import paper_2305_06668_amd as P
+
+    cls = getattr(P, struct)
+    fields = [f for f, _ in cls._fields_]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lobpcg.h"', "int main(void) {",
+             f'  printf("sizeof %zu\\n", sizeof({struct}));']
+    lines += [f'  printf("{f} %zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    assert int(out["sizeof"]) == ctypes.sizeof(cls)
+    for f in fields:
+        assert int(out[f]) == getattr(cls, f).offset, f
