@@ -257,6 +257,39 @@ def test_deterministic(P):
     assert np.array_equal(r1.evecs_np, r2.evecs_np)
 
 
+@pytest.mark.parametrize("mode", ["fp64_dense", "mixed_csr"])
+def test_caller_stream_matches_default_stream(P, mode):
+    """A solver created under a caller's stream (default priority) launches
+    its kernels, copies and status posts there: the same bits and counts as
+    the same solve on the default stream."""
+    if mode == "fp64_dense":
+        n, k = 3000, 4
+        A = synth.dense_dd(n, seed=8)
+        X0 = synth.start_block(n, k, 8)
+
+        def run():
+            return gpu_solve(P, n, lambda s: s.set_operator_dense(cu(A)), X0, k, 1e-9)
+    else:
+        n, k = 20000, 8
+        C = synth.csr_banded(n=n, seed=21, band=600, diag_slope=10.0 / n)
+        X0 = synth.start_block(n, k, 22)
+
+        def run():
+            return mixed_solve(P, n, lambda s: s.set_operator_csr(cu(C.row_ptr), cu(C.col), cu(C.val)),
+                               X0, k, 1e-8)
+    say("caller stream", mode)
+    _, r0 = run()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        _, r1 = run()
+    torch.cuda.synchronize()
+    assert r0.status == 0 and r1.status == 0
+    assert np.array_equal(r0.evals, r1.evals)
+    assert np.array_equal(r0.evecs_np, r1.evecs_np)
+    for key in ("iterations", "matvec_columns", "ortho_grams", "true_checks"):
+        assert r0.stats[key] == r1.stats[key], key
+
+
 def test_invalid_calls(P):
     s = P.Solver(100)
     with pytest.raises(P.LobpcgError) as e:
