@@ -445,12 +445,15 @@ typedef struct lobpcg_learner* lobpcg_learner_t;
  * 0.1, biases 0 except b3 = -3). */
 int lobpcg_learner_create(int device, uint64_t seed, lobpcg_learner_t* out);
 int lobpcg_learner_destroy(lobpcg_learner_t L);
-int lobpcg_learner_set_stream(lobpcg_learner_t L, void* hip_stream);
+/* The learner has no stream of its own: snapshot collection, the objective
+ * and training run on the stream of the solver handle of each snapshot
+ * (lobpcg_set_stream), and each call returns once that work is done. */
 /* Weight mu >= 0 (finite) of the supervised term of the loss; 0 turns it
  * off.  Applies to later lobpcg_learner_objective / lobpcg_learner_train
  * calls; LOBPCG_ERR_INVALID_ARG for a negative or non-finite mu. */
 int lobpcg_learner_set_supervision(lobpcg_learner_t L, double mu);
-/* Host fp32 weights in, out (LOBPCG_LEARNED_NPARAMS); set resets Adam. */
+/* Host fp32 weights in, out (LOBPCG_LEARNED_NPARAMS); set resets Adam and
+ * returns once the device copy is complete. */
 int lobpcg_learner_set_weights(lobpcg_learner_t L, const float* w, int64_t count);
 int lobpcg_learner_get_weights(lobpcg_learner_t L, float* w, int64_t count);
 /* Add a snapshot: X device n x m (ldx), orthonormal columns, of the operator

@@ -167,7 +167,6 @@ _c = {
     "tridiag_apply": _sig("lobpcg_tridiag_apply", [_vp, _vp, _i64, ctypes.c_int, _vp]),
     "learner_create": _sig("lobpcg_learner_create", [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "learner_destroy": _sig("lobpcg_learner_destroy", [_vp]),
-    "learner_set_stream": _sig("lobpcg_learner_set_stream", [_vp, _vp]),
     "learner_set_weights": _sig("lobpcg_learner_set_weights", [_vp, _vp, _i64]),
     "learner_get_weights": _sig("lobpcg_learner_get_weights", [_vp, _vp, _i64]),
     "learner_add_snapshot": _sig(
@@ -197,7 +196,7 @@ EXPORTED = [
     "lobpcg_gram_noalloc",
     "lobpcg_ortho", "lobpcg_ortho_against", "lobpcg_small_eigh", "lobpcg_small_cholesky",
     "lobpcg_rotate", "lobpcg_set_learned_weights", "lobpcg_learned_apply", "lobpcg_tridiag_apply",
-    "lobpcg_learner_create", "lobpcg_learner_destroy", "lobpcg_learner_set_stream",
+    "lobpcg_learner_create", "lobpcg_learner_destroy",
     "lobpcg_learner_set_weights", "lobpcg_learner_get_weights", "lobpcg_learner_add_snapshot",
     "lobpcg_learner_snapshot_info", "lobpcg_learner_objective", "lobpcg_learner_train",
     "lobpcg_learner_last_error", "lobpcg_learner_set_supervision",
@@ -581,10 +580,6 @@ def lobpcg_learner_create(device: int = 0, seed: int = 1):
 
 def lobpcg_learner_destroy(L) -> None:
     _c["learner_destroy"](L)
-
-
-def lobpcg_learner_set_stream(L, stream_ptr=None) -> None:
-    _lcheck(L, _c["learner_set_stream"](L, stream_ptr if stream_ptr is not None else _stream_ptr()))
 
 
 def lobpcg_learner_set_weights(L, w) -> None:

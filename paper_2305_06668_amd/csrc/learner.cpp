@@ -82,7 +82,6 @@ struct Snapshot {
 
 struct lobpcg_learner {
   int device = 0;
-  hipStream_t stream = nullptr;
   float* w = nullptr;
   float* mo = nullptr;
   float* vo = nullptr;
@@ -401,12 +400,6 @@ int lobpcg_learner_set_supervision(lobpcg_learner_t L, double mu) {
   return LOBPCG_OK;
 }
 
-int lobpcg_learner_set_stream(lobpcg_learner_t L, void* s) {
-  if (L == nullptr) return LOBPCG_ERR_INVALID_ARG;
-  L->stream = reinterpret_cast<hipStream_t>(s);
-  return LOBPCG_OK;
-}
-
 int lobpcg_learner_set_weights(lobpcg_learner_t L, const float* w, int64_t count) {
   LGUARD(L);
   if (w == nullptr || count != kMlpParams)
@@ -414,6 +407,9 @@ int lobpcg_learner_set_weights(lobpcg_learner_t L, const float* w, int64_t count
   hipError_t e = hipMemcpy(L->w, w, sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(L->mo, 0, sizeof(float) * kMlpParams);
   if (e == hipSuccess) e = hipMemset(L->vo, 0, sizeof(float) * kMlpParams);
+  // the fills run on the null stream, which does not order work on
+  // non-blocking streams: finish them before training can start elsewhere
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) return L->hip_fail(e, "set_weights");
   L->adam_t = 0;
   return LOBPCG_OK;

@@ -22,7 +22,6 @@ from . import (
     lobpcg_learner_create,
     lobpcg_learner_destroy,
     lobpcg_learner_get_weights,
-    lobpcg_learner_set_stream,
     lobpcg_learner_snapshot_info,
     lobpcg_learner_set_supervision,
     lobpcg_learner_train,
@@ -76,7 +75,6 @@ def train(
     if lr_schedule not in ("constant", "cosine"):
         raise ValueError(f"lr_schedule: {lr_schedule!r}")
     L = lobpcg_learner_create(device, seed)
-    lobpcg_learner_set_stream(L)
     lobpcg_learner_set_supervision(L, supervision)
     log = []
     relres = 0.0

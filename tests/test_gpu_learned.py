@@ -376,6 +376,45 @@ def test_training_lowers_loss(P):
         P.lobpcg_learner_destroy(L)
 
 
+def test_training_and_learned_solve_on_a_caller_stream(P):
+    """Snapshot collection, training and a learned mixed-precision solve
+    whose solver handles were created under a caller's stream (default
+    priority) give the default stream's weights and bits."""
+    C, As, X, rho = family_problem(n=4000, m=8)
+    op = O.csr_operator(C.row_ptr, C.col, C.val, C.n)
+    Xs = O.lobpcg(op, synth.start_block(C.n, 8, 2), 8, 1e-8, diag=C.diag, max_iter=2).X_all
+    X0 = synth.start_block(C.n, 8, 5)
+
+    def run():
+        s = solver_for(P, C, 8)
+        L = P.lobpcg_learner_create(0, 4)
+        try:
+            P.lobpcg_learner_add_snapshot(L, s.h, cu(Xs), minres_maxiter=60)
+            first, last = P.lobpcg_learner_train(L, 40, 4, 3e-3, seed=2)
+            w = P.lobpcg_learner_get_weights(L)
+        finally:
+            P.lobpcg_learner_destroy(L)
+        s.set_learned_weights(w)
+        s.set_preconditioner(P.PRECOND_LEARNED)
+        s.set_option(P.OPT_PRECISION, P.PREC_FP32)
+        s.set_initial_guess(cu(X0))
+        res = s.solve(8, 1e-8)
+        return first, last, w, res.status, res.evals, res.evecs.cpu().numpy(), res.stats["iterations"]
+
+    a = run()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        b = run()
+    torch.cuda.synchronize()
+    say("caller stream: loss", a[0], "->", a[1], "status", a[3], "iterations", a[6])
+    assert np.isfinite(a[0]) and np.isfinite(a[1])
+    assert a[0] == b[0] and a[1] == b[1]
+    assert np.array_equal(a[2], b[2])
+    assert a[3] == b[3] and a[6] == b[6]
+    assert np.array_equal(a[4], b[4])
+    assert np.array_equal(a[5], b[5])
+
+
 def _eig_ref(A, k):
     w, V = np.linalg.eigh(A)
     return w, V[:, :k]
