@@ -1601,8 +1601,12 @@ int lobpcg_set_learned_weights(lobpcg_t h, const float* w, int64_t count) {
       return h->hip_fail(e, "hipMalloc(weights)");
     }
   }
-  hipError_t e = hipMemcpy(h->lweights, w, sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return h->hip_fail(e, "hipMemcpy(weights)");
+  // on the handle's stream (after any solve still reading the old weights),
+  // complete before the host buffer is handed back
+  hipError_t e = hipMemcpyAsync(h->lweights, w, sizeof(float) * kMlpParams, hipMemcpyHostToDevice,
+                                h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "hipMemcpyAsync(weights)");
   return LOBPCG_OK;
 }
 
